@@ -1,0 +1,715 @@
+/*
+ * fps_oracle.c -- plain, slow, FP64 CPU oracle of the coupled flood-pedestrian
+ * step of Shirvani, Kesserwani & Richmond, "Agent-based simulator of dynamic
+ * flood-people interactions" (arXiv 1908.05232).
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by the tests, the smoke check and the
+ * benchmark's CPU-baseline leg, never by the product path.  It shares no code
+ * with the GPU library.
+ *
+ * What the paper fixes, and where:
+ *   - state U = [h, hu, hv], fluxes F, G, bed-slope and Manning sources: Eq. (1), sec. 2.2
+ *   - explicit update from east/west/north/south fluxes: Eq. (2), sec. 2.2
+ *   - Godunov-type, first-order, 4-neighbour stencil with wetting/drying and
+ *     terrain treatment: sec. 2.2 (deferring to Wang et al. 2011)
+ *   - CFL-adaptive step when wet, 1.0 s pedestrian step when dry: sec. 3
+ *   - HR = (V + 0.5) h with V = max(|u|, |v|); classes and walking speeds: Table 1, sec. 2.4
+ *   - roughness rule n = n0 + Np n0 with at most 20 counted evacuees: sec. 2.4
+ *   - responder cycle storage -> 30 s pick -> barrier -> 30 s drop; layer fill
+ *     along the barrier line, N_L layers: sec. 2.4, sec. 3.3
+ *   - triangular inflow hydrograph: sec. 3.1
+ * Readings where the paper is silent (each also listed in the design notes):
+ *   R1 Riemann solver: HLLC (Toro) with dry-bed wave speeds.  HLL part written
+ *      anchored at the left state, which is the same formula rearranged so that
+ *      two identical states return F(U) exactly.
+ *   R2 wetting/drying + terrain: non-negative hydrostatic reconstruction
+ *      (Audusse et al. 2004), z_f = max(zL, zR), h* = h - (z_f - z); a face side
+ *      with h* <= h_dry counts as dry and h* := 0.  Velocities come from the
+ *      unreconstructed cell (0 if h <= h_dry).  The bed slope enters as the
+ *      one-sided pressure correction 1/2 g h*^2 of the same reconstruction.
+ *   R3 Eq. (2) prints "+ S" without a time factor; read as + dt S.
+ *   R4 Manning friction: splitting point-implicit (Liang & Marche 2009) with a
+ *      no-reversal limiter, applied after the flux update where h > h_dry.
+ *   R5 dt = min(CFL * min_wet min(dx/(|u|+c), dy/(|v|+c)), dt_max), dt_max = 1 s;
+ *      dt_max when nothing is wet.
+ *   R6 boundaries by ghost cells: wall = mirror (normal discharge negated; the
+ *      wall face carries zero mass and tangential flux exactly); transmissive
+ *      = copy.  The "slip" north side of sec. 3.1 is read as transmissive.
+ *   R7 inflow: a line mass source on the cells along the inflow segment,
+ *      depth += (1/dn) * integral of q over the step; piecewise-linear q
+ *      integrated exactly; no momentum added.
+ *   R8 cleanup: h := max(h, 0) (clipped volume recorded), q := 0 where h <= h_dry.
+ *   R9 coupled order per step: flood update with n and z of the previous step,
+ *      then pedestrians with the new flood state, then write-back of n and z.
+ *   R10 hazard: a dry cell (h <= h_dry) is class DRY at the agent's own base
+ *      speed; class intervals are half-open [from, to); above 20 stays HIGHEST.
+ *   R11 roughness: n_eff = n0 (1 + min(Np, cap)), recomputed every step from
+ *      the active evacuees whose containing cell it is (not cumulative).
+ *   R12 navigation: per-destination distance field (input); step toward the
+ *      centre of the 8-neighbour with the smallest distance, ties in the order
+ *      E, N, W, S, NE, NW, SW, SE; inside a destination cell toward its centre.
+ *   R13 movement: social force of Helbing, Farkas & Vicsek (2000): exact
+ *      relaxation to v0 e over tau, exponential repulsion from neighbours in
+ *      the 3x3 bins and from obstacle cells within r_cut, |v| <= v0, explicit
+ *      position update with an axis-wise rejection of moves into obstacles or
+ *      out of the domain.
+ *   R14 arrival when the distance field at the new cell is <= r_arrive.
+ *   R15 evacuees stay put until any cell is wet (evacuation trigger, sec. 2.4).
+ *   R16 barrier: completed drops of a step are summed, then applied in order;
+ *      one bag per drop; a cell-layer takes bags_per bags; z += layer thickness.
+ *   R17 cell / bin indices are decided in FP32 (the GPU kernel's precision):
+ *      i = floor((float)x / (float)dx).
+ */
+#include "fps_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* Riemann flux (R1).  F = (mass, normal momentum, tangential momentum).     */
+/* ------------------------------------------------------------------------ */
+void or_hllc(double g, double hL, double uL, double vL, double hR, double uR, double vR,
+             double F[3])
+{
+    if (hL == 0.0 && hR == 0.0) {
+        F[0] = F[1] = F[2] = 0.0;
+        return;
+    }
+    double cL = sqrt(g * hL), cR = sqrt(g * hR);
+    double sL, sR;
+    if (hL == 0.0) {                     /* dry left bed */
+        sL = uR - 2.0 * cR;
+        sR = uR + cR;
+    } else if (hR == 0.0) {              /* dry right bed */
+        sL = uL - cL;
+        sR = uL + 2.0 * cL;
+    } else {
+        double us = 0.5 * (uL + uR) + cL - cR;
+        double cs = 0.5 * (cL + cR) + 0.25 * (uL - uR);
+        sL = fmin(uL - cL, us - cs);
+        sR = fmax(uR + cR, us + cs);
+    }
+    /* physical fluxes of the two states */
+    double qL = hL * uL, qR = hR * uR;
+    double FL0 = qL, FL1 = qL * uL + 0.5 * g * hL * hL, FL2 = qL * vL;
+    double FR0 = qR, FR1 = qR * uR + 0.5 * g * hR * hR, FR2 = qR * vR;
+    if (sL >= 0.0) {
+        F[0] = FL0; F[1] = FL1; F[2] = FL2;
+        return;
+    }
+    if (sR <= 0.0) {
+        F[0] = FR0; F[1] = FR1; F[2] = FR2;
+        return;
+    }
+    /* HLL star flux (sR FL - sL FR + sL sR (UR - UL)) / (sR - sL), anchored at FL */
+    double inv = 1.0 / (sR - sL);
+    F[0] = FL0 + sL * ((FL0 - FR0) + sR * (hR - hL)) * inv;
+    F[1] = FL1 + sL * ((FL1 - FR1) + sR * (qR - qL)) * inv;
+    /* contact speed; the tangential velocity is carried across it */
+    double sM = (sL * hR * (uR - sR) - sR * hL * (uL - sL)) /
+                (hR * (uR - sR) - hL * (uL - sL));
+    F[2] = F[0] * (sM >= 0.0 ? vL : vR);
+}
+
+/* one face: hydrostatic reconstruction (R2) then the flux.  hsL/hsR return the
+   reconstructed depths each side sees, used by the bed-slope correction. */
+void or_face(const or_params *P, double hL, double qnL, double qtL, double zL,
+             double hR, double qnR, double qtR, double zR, int wall, double F[3],
+             double *hsL, double *hsR)
+{
+    double eps = P->h_dry;
+    double zf = fmax(zL, zR);
+    double hl = hL - (zf - zL);
+    double hr = hR - (zf - zR);
+    if (!(hl > eps)) hl = 0.0;
+    if (!(hr > eps)) hr = 0.0;
+    double unL = 0.0, utL = 0.0, unR = 0.0, utR = 0.0;
+    if (hL > eps) { unL = qnL / hL; utL = qtL / hL; }
+    if (hR > eps) { unR = qnR / hR; utR = qtR / hR; }
+    or_hllc(P->g, hl, unL, utL, hr, unR, utR, F);
+    if (wall) {                          /* R6: a wall passes no mass */
+        F[0] = 0.0;
+        F[2] = 0.0;
+    }
+    *hsL = hl;
+    *hsR = hr;
+}
+
+/* exact integral of the piecewise-linear hydrograph over [a, b] (R7) */
+static double hydro_q(int32_t nh, const double *ht, const double *hq, double t)
+{
+    if (nh <= 0) return 0.0;
+    if (t <= ht[0]) return hq[0];
+    if (t >= ht[nh - 1]) return hq[nh - 1];
+    for (int32_t k = 0; k + 1 < nh; ++k) {
+        if (t >= ht[k] && t <= ht[k + 1]) {
+            double w = (t - ht[k]) / (ht[k + 1] - ht[k]);
+            return hq[k] + w * (hq[k + 1] - hq[k]);
+        }
+    }
+    return hq[nh - 1];
+}
+
+double or_hydro_integral(int32_t nh, const double *ht, const double *hq, double a, double b)
+{
+    if (nh <= 0 || !(b > a)) return 0.0;
+    /* split [a, b] at the breakpoints inside it; trapezoids are exact on lines */
+    double total = 0.0, lo = a;
+    for (int32_t k = 0; k < nh; ++k) {
+        if (ht[k] > lo && ht[k] < b) {
+            total += 0.5 * (hydro_q(nh, ht, hq, lo) + hydro_q(nh, ht, hq, ht[k])) * (ht[k] - lo);
+            lo = ht[k];
+        }
+    }
+    total += 0.5 * (hydro_q(nh, ht, hq, lo) + hydro_q(nh, ht, hq, b)) * (b - lo);
+    return total;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Hazard rate and class (Table 1, sec. 2.4; R10)                             */
+/* ------------------------------------------------------------------------ */
+int32_t or_hr_class(const or_params *P, double h, double qx, double qy, double *hr_out)
+{
+    if (!(h > P->h_dry)) {
+        if (hr_out) *hr_out = 0.0;
+        return OR_CLS_DRY;
+    }
+    double u = qx / h, v = qy / h;
+    double V = fmax(fabs(u), fabs(v));
+    double hr = (V + 0.5) * h;
+    if (hr_out) *hr_out = hr;
+    if (hr < P->hr_t[0]) return OR_CLS_LOW;
+    if (hr < P->hr_t[1]) return OR_CLS_MEDIUM;
+    if (hr < P->hr_t[2]) return OR_CLS_HIGH;
+    return OR_CLS_HIGHEST;
+}
+
+/* roughness write-back (sec. 2.4; R11) */
+double or_n_eff(const or_params *P, int32_t np)
+{
+    int32_t k = np < P->np_cap ? np : P->np_cap;
+    return P->n_base + (double)k * P->n_base;
+}
+
+/* Manning friction, splitting point-implicit (R4) */
+void or_friction(const or_params *P, double dt, double h, double n, double *qx, double *qy)
+{
+    if (!(h > P->h_dry)) return;
+    double u = *qx / h, v = *qy / h;
+    double V2 = u * u + v * v;
+    if (!(V2 > 0.0)) return;
+    double speed = sqrt(V2);
+    double Cf = P->g * n * n / cbrt(h);
+    double Sx = -Cf * u * speed;
+    double Sy = -Cf * v * speed;
+    double Dx = 1.0 + dt * (Cf / h) * (2.0 * u * u + v * v) / speed;
+    double Dy = 1.0 + dt * (Cf / h) * (2.0 * v * v + u * u) / speed;
+    double dqx = dt * Sx / Dx;
+    double dqy = dt * Sy / Dy;
+    if (fabs(dqx) > fabs(*qx)) dqx = -*qx;
+    if (fabs(dqy) > fabs(*qy)) dqy = -*qy;
+    *qx += dqx;
+    *qy += dqy;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Time step (sec. 3; R5)                                                     */
+/* ------------------------------------------------------------------------ */
+double or_compute_dt(const or_sim *S)
+{
+    const or_params *P = &S->P;
+    int64_t nc = (int64_t)P->nx * P->ny;
+    double lam = INFINITY;
+    int any = 0;
+    for (int64_t c = 0; c < nc; ++c) {
+        double h = S->h[c];
+        if (!(h > P->h_dry)) continue;
+        double u = S->qx[c] / h, v = S->qy[c] / h;
+        double cel = sqrt(P->g * h);
+        double lx = P->dx / (fabs(u) + cel);
+        double ly = P->dy / (fabs(v) + cel);
+        lam = fmin(lam, fmin(lx, ly));
+        any = 1;
+    }
+    if (!any) return P->dt_max;
+    return fmin(P->cfl * lam, P->dt_max);
+}
+
+double or_mass(const or_sim *S)
+{
+    int64_t nc = (int64_t)S->P.nx * S->P.ny;
+    double m = 0.0;
+    for (int64_t c = 0; c < nc; ++c) m += S->h[c];
+    return m * S->P.dx * S->P.dy;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Finite-volume update, Eq. (2) with R1-R8                                   */
+/* ------------------------------------------------------------------------ */
+/* the ghost of interior cell c across side s (R6) */
+static void ghost(const or_sim *S, int32_t side, int64_t c, double *h, double *qx, double *qy,
+                  double *z, int *wall)
+{
+    *h = S->h[c];
+    *qx = S->qx[c];
+    *qy = S->qy[c];
+    *z = S->z[c];
+    *wall = S->P.bc[side] == OR_WALL;
+    if (*wall) {
+        if (side <= 1) *qx = -*qx;       /* west / east: x is normal */
+        else *qy = -*qy;                 /* south / north: y is normal */
+    }
+}
+
+void or_fv_step(or_sim *S, double dt)
+{
+    const or_params *P = &S->P;
+    const int32_t nx = P->nx, ny = P->ny;
+    const double g = P->g, eps = P->h_dry;
+    const int64_t nfx = (int64_t)(nx + 1) * ny, nfy = (int64_t)nx * (ny + 1);
+    /* x faces: face f in row j lies between cells f-1 and f */
+    double *FX = malloc(sizeof(double) * 3 * nfx), *HXL = malloc(sizeof(double) * nfx),
+           *HXR = malloc(sizeof(double) * nfx);
+    double *FY = malloc(sizeof(double) * 3 * nfy), *HYL = malloc(sizeof(double) * nfy),
+           *HYR = malloc(sizeof(double) * nfy);
+    double vout = 0.0;
+
+    for (int32_t j = 0; j < ny; ++j) {
+        for (int32_t f = 0; f <= nx; ++f) {
+            double hL, qxL, qyL, zL, hR, qxR, qyR, zR;
+            int wall = 0;
+            if (f == 0) {
+                int64_t c = (int64_t)j * nx;
+                ghost(S, 0, c, &hL, &qxL, &qyL, &zL, &wall);
+                hR = S->h[c]; qxR = S->qx[c]; qyR = S->qy[c]; zR = S->z[c];
+            } else if (f == nx) {
+                int64_t c = (int64_t)j * nx + nx - 1;
+                hL = S->h[c]; qxL = S->qx[c]; qyL = S->qy[c]; zL = S->z[c];
+                ghost(S, 1, c, &hR, &qxR, &qyR, &zR, &wall);
+            } else {
+                int64_t cl = (int64_t)j * nx + f - 1, cr = cl + 1;
+                hL = S->h[cl]; qxL = S->qx[cl]; qyL = S->qy[cl]; zL = S->z[cl];
+                hR = S->h[cr]; qxR = S->qx[cr]; qyR = S->qy[cr]; zR = S->z[cr];
+            }
+            int64_t k = (int64_t)j * (nx + 1) + f;
+            or_face(P, hL, qxL, qyL, zL, hR, qxR, qyR, zR, wall, &FX[3 * k], &HXL[k], &HXR[k]);
+        }
+    }
+    for (int32_t j = 0; j <= ny; ++j) {
+        for (int32_t i = 0; i < nx; ++i) {
+            double hL, qxL, qyL, zL, hR, qxR, qyR, zR;
+            int wall = 0;
+            if (j == 0) {
+                int64_t c = i;
+                ghost(S, 2, c, &hL, &qxL, &qyL, &zL, &wall);
+                hR = S->h[c]; qxR = S->qx[c]; qyR = S->qy[c]; zR = S->z[c];
+            } else if (j == ny) {
+                int64_t c = (int64_t)(ny - 1) * nx + i;
+                hL = S->h[c]; qxL = S->qx[c]; qyL = S->qy[c]; zL = S->z[c];
+                ghost(S, 3, c, &hR, &qxR, &qyR, &zR, &wall);
+            } else {
+                int64_t cl = (int64_t)(j - 1) * nx + i, cr = cl + nx;
+                hL = S->h[cl]; qxL = S->qx[cl]; qyL = S->qy[cl]; zL = S->z[cl];
+                hR = S->h[cr]; qxR = S->qx[cr]; qyR = S->qy[cr]; zR = S->z[cr];
+            }
+            int64_t k = (int64_t)j * nx + i;
+            /* y is normal: pass (qy, qx) as (normal, tangential) */
+            or_face(P, hL, qyL, qxL, zL, hR, qyR, qxR, zR, wall, &FY[3 * k], &HYL[k], &HYR[k]);
+        }
+    }
+    /* outflow through transmissive sides (outward positive) */
+    if (P->bc[0] == OR_TRANSMISSIVE)
+        for (int32_t j = 0; j < ny; ++j) vout -= FX[3 * ((int64_t)j * (nx + 1))] * P->dy;
+    if (P->bc[1] == OR_TRANSMISSIVE)
+        for (int32_t j = 0; j < ny; ++j) vout += FX[3 * ((int64_t)j * (nx + 1) + nx)] * P->dy;
+    if (P->bc[2] == OR_TRANSMISSIVE)
+        for (int32_t i = 0; i < nx; ++i) vout -= FY[3 * (int64_t)i] * P->dx;
+    if (P->bc[3] == OR_TRANSMISSIVE)
+        for (int32_t i = 0; i < nx; ++i) vout += FY[3 * ((int64_t)ny * nx + i)] * P->dx;
+    S->v_out += vout * dt;
+
+    /* inflow depth for this step (R7) */
+    double inc = 0.0;
+    if (P->inflow_side >= 0) {
+        double dn = P->inflow_side <= 1 ? P->dx : P->dy;
+        inc = or_hydro_integral(S->nh, S->ht, S->hq, S->t, S->t + dt) / dn;
+    }
+
+    const double lx = dt / P->dx, ly = dt / P->dy;
+    for (int32_t j = 0; j < ny; ++j) {
+        for (int32_t i = 0; i < nx; ++i) {
+            int64_t c = (int64_t)j * nx + i;
+            int64_t kW = (int64_t)j * (nx + 1) + i, kE = kW + 1;
+            int64_t kS = c, kN = c + nx;
+            const double *fW = &FX[3 * kW], *fE = &FX[3 * kE];
+            const double *fS = &FY[3 * kS], *fN = &FY[3 * kN];
+            /* this cell's own reconstructed depths at its four faces */
+            double hsW = HXR[kW], hsE = HXL[kE], hsS = HYR[kS], hsN = HYL[kN];
+            double pW = 0.5 * g * hsW * hsW, pE = 0.5 * g * hsE * hsE;
+            double pS = 0.5 * g * hsS * hsS, pN = 0.5 * g * hsN * hsN;
+            /* Eq. (2): mass */
+            double ax_h = lx * (fE[0] - fW[0]);
+            double ay_h = ly * (fN[0] - fS[0]);
+            double hn = S->h[c] - (ax_h + ay_h);
+            /* x momentum: normal on x faces (with bed-slope correction), tangential on y faces */
+            double ax_qx = lx * ((fE[1] - pE) - (fW[1] - pW));
+            double ay_qx = ly * (fN[2] - fS[2]);
+            double qxn = S->qx[c] - (ax_qx + ay_qx);
+            /* y momentum */
+            double ay_qy = ly * ((fN[1] - pN) - (fS[1] - pS));
+            double ax_qy = lx * (fE[2] - fW[2]);
+            double qyn = S->qy[c] - (ay_qy + ax_qy);
+            /* inflow line source */
+            if (P->inflow_side >= 0) {
+                int32_t along = -1;
+                if (P->inflow_side == 0 && i == 0) along = j;
+                if (P->inflow_side == 1 && i == nx - 1) along = j;
+                if (P->inflow_side == 2 && j == 0) along = i;
+                if (P->inflow_side == 3 && j == ny - 1) along = i;
+                if (along >= P->inflow_c0 && along < P->inflow_c1) {
+                    hn += inc;
+                    S->v_in += inc * P->dx * P->dy;
+                }
+            }
+            /* cleanup (R8) */
+            if (hn < 0.0) {
+                S->v_clip += -hn * P->dx * P->dy;
+                hn = 0.0;
+            }
+            if (!(hn > eps)) {
+                qxn = 0.0;
+                qyn = 0.0;
+            }
+            /* friction with the effective roughness (R4, R11) */
+            or_friction(P, dt, hn, or_n_eff(P, S->np[c]), &qxn, &qyn);
+            /* in place is safe: every face was computed before this loop */
+            S->h[c] = hn;
+            S->qx[c] = qxn;
+            S->qy[c] = qyn;
+        }
+    }
+    int wet = 0;
+    int64_t nc = (int64_t)nx * ny;
+    for (int64_t c = 0; c < nc; ++c)
+        if (S->h[c] > eps) { wet = 1; break; }
+    S->any_wet = wet;
+    free(FX); free(HXL); free(HXR);
+    free(FY); free(HYL); free(HYR);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Pedestrians                                                                */
+/* ------------------------------------------------------------------------ */
+int32_t or_cell_index(double x, double d, int32_t n)
+{
+    /* R17: decided in FP32; the result may lie outside [0, n) */
+    float q = (float)x / (float)d;
+    float f = floorf(q);
+    if (f < -1.0f) return -1;
+    if (f > (float)n) return n;
+    return (int32_t)f;
+}
+
+static int32_t clampi(int32_t v, int32_t lo, int32_t hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+void or_bins_dims(const or_params *P, int32_t *bsx, int32_t *bsy, int32_t *nbx, int32_t *nby)
+{
+    /* bin side: whole cells, at least r_cut long */
+    int32_t bx = (int32_t)ceil(P->r_cut / P->dx - 1e-9), by = (int32_t)ceil(P->r_cut / P->dy - 1e-9);
+    if (bx < 1) bx = 1;
+    if (by < 1) by = 1;
+    *bsx = bx;
+    *bsy = by;
+    *nbx = (P->nx + bx - 1) / bx;
+    *nby = (P->ny + by - 1) / by;
+}
+
+/* stable counting sort of the non-exited agents by bin (ascending agent id inside a bin) */
+void or_build_bins(const or_params *P, int32_t na, const float *x, const float *y,
+                   const uint8_t *state, int32_t *bin_start, int32_t *perm)
+{
+    int32_t bsx, bsy, nbx, nby;
+    or_bins_dims(P, &bsx, &bsy, &nbx, &nby);
+    int32_t nb = nbx * nby;
+    for (int32_t b = 0; b <= nb; ++b) bin_start[b] = 0;
+    int32_t *key = malloc(sizeof(int32_t) * (na > 0 ? na : 1));
+    for (int32_t a = 0; a < na; ++a) {
+        key[a] = -1;
+        if (state[a] == OR_ST_EXITED) continue;
+        int32_t ci = clampi(or_cell_index(x[a], P->dx, P->nx), 0, P->nx - 1);
+        int32_t cj = clampi(or_cell_index(y[a], P->dy, P->ny), 0, P->ny - 1);
+        key[a] = (cj / bsy) * nbx + ci / bsx;
+        bin_start[key[a] + 1] += 1;
+    }
+    for (int32_t b = 0; b < nb; ++b) bin_start[b + 1] += bin_start[b];
+    int32_t *cur = malloc(sizeof(int32_t) * (nb > 0 ? nb : 1));
+    for (int32_t b = 0; b < nb; ++b) cur[b] = bin_start[b];
+    for (int32_t a = 0; a < na; ++a)      /* ascending id keeps the sort stable */
+        if (key[a] >= 0) perm[cur[key[a]]++] = a;
+    free(cur);
+    free(key);
+}
+
+void or_count_evacuees(or_sim *S)
+{
+    const or_params *P = &S->P;
+    int64_t nc = (int64_t)P->nx * P->ny;
+    for (int64_t c = 0; c < nc; ++c) S->np[c] = 0;
+    for (int32_t a = 0; a < S->na; ++a) {
+        if (S->role[a] != OR_ROLE_EVACUEE || S->state[a] != OR_ST_EVAC) continue;
+        int32_t ci = clampi(or_cell_index(S->x[a], P->dx, P->nx), 0, P->nx - 1);
+        int32_t cj = clampi(or_cell_index(S->y[a], P->dy, P->ny), 0, P->ny - 1);
+        S->np[(int64_t)cj * P->nx + ci] += 1;
+    }
+}
+
+static float dist_at(const or_sim *S, int32_t d, int32_t i, int32_t j)
+{
+    return S->dist[((int64_t)d * S->P.ny + j) * S->P.nx + i];
+}
+
+static int32_t nearest_exit(const or_sim *S, int32_t ci, int32_t cj)
+{
+    int32_t best = 0;
+    for (int32_t e = 1; e < S->n_exit; ++e)
+        if (dist_at(S, e, ci, cj) < dist_at(S, best, ci, cj)) best = e;
+    return best;
+}
+
+/* desired direction (R12) */
+static void direction(const or_sim *S, int32_t d, int32_t ci, int32_t cj, double x, double y,
+                      double *ex, double *ey)
+{
+    static const int32_t off[8][2] = {{1, 0}, {0, 1}, {-1, 0}, {0, -1},
+                                      {1, 1}, {-1, 1}, {-1, -1}, {1, -1}};
+    const or_params *P = &S->P;
+    *ex = 0.0;
+    *ey = 0.0;
+    float here = dist_at(S, d, ci, cj);
+    int32_t ti = ci, tj = cj;
+    if (!(here == 0.0f)) {
+        float best = here;
+        int32_t k_best = -1;
+        for (int32_t k = 0; k < 8; ++k) {
+            int32_t ni = ci + off[k][0], nj = cj + off[k][1];
+            if (ni < 0 || nj < 0 || ni >= P->nx || nj >= P->ny) continue;
+            float dk = dist_at(S, d, ni, nj);
+            if (dk < best) {
+                best = dk;
+                k_best = k;
+            }
+        }
+        if (k_best < 0) return;
+        ti = ci + off[k_best][0];
+        tj = cj + off[k_best][1];
+    }
+    double tx = (ti + 0.5) * P->dx - x, ty = (tj + 0.5) * P->dy - y;
+    double len = sqrt(tx * tx + ty * ty);
+    if (len > 0.0) {
+        *ex = tx / len;
+        *ey = ty / len;
+    }
+}
+
+void or_ped_step(or_sim *S, double dt)
+{
+    const or_params *P = &S->P;
+    const int32_t na = S->na, nx = P->nx, ny = P->ny;
+    if (na <= 0) return;
+    int32_t bsx, bsy, nbx, nby;
+    or_bins_dims(P, &bsx, &bsy, &nbx, &nby);
+    /* cell lists of the positions at the start of the step */
+    float *xf = malloc(sizeof(float) * na), *yf = malloc(sizeof(float) * na);
+    for (int32_t a = 0; a < na; ++a) {
+        xf[a] = (float)S->x[a];
+        yf[a] = (float)S->y[a];
+    }
+    or_build_bins(P, na, xf, yf, S->state, S->bin_start, S->perm);
+    double *x1 = malloc(sizeof(double) * na), *y1 = malloc(sizeof(double) * na);
+    double *vx1 = malloc(sizeof(double) * na), *vy1 = malloc(sizeof(double) * na);
+    const int32_t Rx = (int32_t)ceil(P->r_cut / P->dx - 1e-9), Ry = (int32_t)ceil(P->r_cut / P->dy - 1e-9);
+    int32_t drops = 0;
+
+    for (int32_t a = 0; a < na; ++a) {
+        double x = S->x[a], y = S->y[a];
+        x1[a] = x; y1[a] = y; vx1[a] = S->vx[a]; vy1[a] = S->vy[a];
+        int32_t st = S->state[a];
+        if (st == OR_ST_EXITED) continue;
+        int32_t ci = clampi(or_cell_index(x, P->dx, nx), 0, nx - 1);
+        int32_t cj = clampi(or_cell_index(y, P->dy, ny), 0, ny - 1);
+        int64_t c = (int64_t)cj * nx + ci;
+        /* hazard from the containing cell (Table 1) */
+        int32_t cls = or_hr_class(P, S->h[c], S->qx[c], S->qy[c], NULL);
+        S->cls[a] = (uint8_t)cls;
+        double v0 = cls == OR_CLS_DRY ? S->vbase[a] : P->v_class[cls];
+        /* destinations */
+        if (S->dest[a] < 0) {
+            if (S->role[a] == OR_ROLE_EVACUEE) {
+                S->dest[a] = nearest_exit(S, ci, cj);
+                st = OR_ST_EVAC;
+            } else {
+                S->dest[a] = S->storage_dest;
+                st = OR_ST_TO_STORAGE;
+            }
+        }
+        if (S->role[a] == OR_ROLE_RESPONDER && S->done && st != OR_ST_EVAC) {
+            st = OR_ST_EVAC;
+            S->dest[a] = nearest_exit(S, ci, cj);
+        }
+        /* responder waits (sec. 2.4) */
+        if (st == OR_ST_PICKING || st == OR_ST_DROPPING) {
+            S->timer[a] -= dt;
+            if (S->timer[a] > 0.0) {
+                vx1[a] = 0.0; vy1[a] = 0.0;
+                S->state[a] = (uint8_t)st;
+                continue;
+            }
+            if (st == OR_ST_PICKING) {
+                st = OR_ST_TO_BARRIER;
+                S->dest[a] = S->barrier_dest;
+            } else {
+                drops += 1;
+                st = OR_ST_TO_STORAGE;
+                S->dest[a] = S->storage_dest;
+            }
+        }
+        /* evacuation trigger (R15) */
+        if (S->role[a] == OR_ROLE_EVACUEE && !S->any_wet) {
+            vx1[a] = 0.0; vy1[a] = 0.0;
+            S->state[a] = (uint8_t)st;
+            continue;
+        }
+        /* social force (R13) */
+        double ex, ey;
+        direction(S, S->dest[a], ci, cj, x, y, &ex, &ey);
+        double k = exp(-dt / P->tau);
+        double vx = v0 * ex + (S->vx[a] - v0 * ex) * k;
+        double vy = v0 * ey + (S->vy[a] - v0 * ey) * k;
+        double fx = 0.0, fy = 0.0;
+        int32_t bi = ci / bsx, bj = cj / bsy;
+        for (int32_t qj = bj - 1; qj <= bj + 1; ++qj) {
+            if (qj < 0 || qj >= nby) continue;
+            for (int32_t qi = bi - 1; qi <= bi + 1; ++qi) {
+                if (qi < 0 || qi >= nbx) continue;
+                int32_t b = qj * nbx + qi;
+                for (int32_t s = S->bin_start[b]; s < S->bin_start[b + 1]; ++s) {
+                    int32_t o = S->perm[s];
+                    if (o == a) continue;
+                    double rx = x - S->x[o], ry = y - S->y[o];
+                    double d = sqrt(rx * rx + ry * ry);
+                    if (!(d > 0.0) || !(d < P->r_cut)) continue;
+                    double w = P->a_over_m * exp((2.0 * P->radius - d) / P->b_range);
+                    fx += w * rx / d;
+                    fy += w * ry / d;
+                }
+            }
+        }
+        for (int32_t dj = -Ry; dj <= Ry; ++dj) {
+            int32_t wj = cj + dj;
+            if (wj < 0 || wj >= ny) continue;
+            for (int32_t di = -Rx; di <= Rx; ++di) {
+                int32_t wi = ci + di;
+                if (wi < 0 || wi >= nx) continue;
+                if (S->walk[(int64_t)wj * nx + wi]) continue;
+                double px = fmin(fmax(x, wi * P->dx), (wi + 1) * P->dx);
+                double py = fmin(fmax(y, wj * P->dy), (wj + 1) * P->dy);
+                double rx = x - px, ry = y - py;
+                double d = sqrt(rx * rx + ry * ry);
+                if (!(d > 0.0) || !(d < P->r_cut)) continue;
+                double w = P->a_over_m * exp((P->radius - d) / P->b_range);
+                fx += w * rx / d;
+                fy += w * ry / d;
+            }
+        }
+        vx += dt * fx;
+        vy += dt * fy;
+        double sp = sqrt(vx * vx + vy * vy);
+        if (sp > v0) {
+            if (v0 > 0.0) {
+                vx *= v0 / sp;
+                vy *= v0 / sp;
+            } else {
+                vx = 0.0;
+                vy = 0.0;
+            }
+        }
+        /* move with axis-wise rejection (R13) */
+        double xn = x + dt * vx;
+        int32_t ni = or_cell_index(xn, P->dx, nx);
+        if (ni < 0 || ni >= nx || !S->walk[(int64_t)cj * nx + ni]) {
+            xn = x;
+            vx = 0.0;
+            ni = ci;
+        }
+        double yn = y + dt * vy;
+        int32_t nj = or_cell_index(yn, P->dy, ny);
+        if (nj < 0 || nj >= ny || !S->walk[(int64_t)nj * nx + ni]) {
+            yn = y;
+            vy = 0.0;
+            nj = cj;
+        }
+        /* arrival (R14) */
+        if (dist_at(S, S->dest[a], ni, nj) <= (float)P->r_arrive) {
+            if (st == OR_ST_EVAC) {
+                st = OR_ST_EXITED;
+            } else if (st == OR_ST_TO_STORAGE) {
+                st = OR_ST_PICKING;
+                S->timer[a] = P->pick_s;
+                vx = 0.0; vy = 0.0;
+            } else if (st == OR_ST_TO_BARRIER) {
+                st = OR_ST_DROPPING;
+                S->timer[a] = P->drop_s;
+                vx = 0.0; vy = 0.0;
+            }
+        }
+        x1[a] = xn; y1[a] = yn; vx1[a] = vx; vy1[a] = vy;
+        S->state[a] = (uint8_t)st;
+    }
+    for (int32_t a = 0; a < na; ++a) {
+        S->x[a] = x1[a]; S->y[a] = y1[a]; S->vx[a] = vx1[a]; S->vy[a] = vy1[a];
+    }
+    /* barrier fill (R16) */
+    S->drops_total += drops;
+    if (!S->done && S->nline > 0) {
+        S->bags += drops;
+        while (!S->done && S->bags >= S->bags_per) {
+            S->bags -= S->bags_per;
+            double th = S->layers_done == S->n_layers - 1 ? S->t_last : S->t_bag;
+            S->z[S->line[S->active]] += th;
+            S->active += 1;
+            if (S->active == S->nline) {
+                S->active = 0;
+                S->layers_done += 1;
+                if (S->layers_done >= S->n_layers) S->done = 1;
+            }
+        }
+    }
+    free(xf); free(yf); free(x1); free(y1); free(vx1); free(vy1);
+}
+
+double or_coupled_step(or_sim *S, double dt)
+{
+    if (!(dt > 0.0)) dt = or_compute_dt(S);
+    or_fv_step(S, dt);
+    or_ped_step(S, dt);
+    or_count_evacuees(S);
+    S->t += dt;
+    S->step += 1;
+    return dt;
+}
+
+void or_run(or_sim *S, int32_t n, const double *dts, double *dt_used, int32_t with_peds)
+{
+    for (int32_t k = 0; k < n; ++k) {
+        double dt = dts ? dts[k] : or_compute_dt(S);
+        if (dt_used) dt_used[k] = dt;
+        or_fv_step(S, dt);
+        if (with_peds) {
+            or_ped_step(S, dt);
+            or_count_evacuees(S);
+        }
+        S->t += dt;
+        S->step += 1;
+    }
+}
