@@ -1,0 +1,199 @@
+/*
+ * fps.h -- C-ABI of libfps.so, the MI355X (gfx950) hot path of the coupled
+ * flood-pedestrian simulator of Shirvani, Kesserwani & Richmond,
+ * "Agent-based simulator of dynamic flood-people interactions" (arXiv 1908.05232).
+ *
+ * The calls follow the paper's problem statement: a grid of flood cells and an
+ * aligned grid of navigation cells of the same size (sec. 2.1), initial
+ * topography/water and boundary inflow hydrograph (sec. 3.1), pedestrian agents
+ * whose roles are assigned at input (sec. 2.4), stepping, and read-out of the
+ * flood fields and agent states (sec. 3.2 records coordinates, depth,
+ * velocity and HR of the flood cells, coordinates and HR state of pedestrians).
+ *
+ * Conventions
+ *  - Grids are row-major [ny][nx], index j*nx + i; x runs east with i, y north
+ *    with j; the centre of cell (i, j) is ((i + 1/2) dx, (j + 1/2) dy).
+ *  - The flood state is the conserved vector U = [h, hu, hv] of Eq. (1): depth
+ *    h (m) and unit discharges hu, hv (m^2/s), FP32.  z is bed elevation (m).
+ *  - Pointers documented "device" are HIP device pointers owned by the caller;
+ *    they must stay valid until rebinding or fps_destroy.  The library never
+ *    allocates or frees device memory: all scratch lives in the caller's
+ *    workspace (fps_workspace_bytes).  "host" pointers are read during the
+ *    call only.
+ *  - Every call returns an fps_status.  An invalid argument returns
+ *    FPS_E_INVALID and changes nothing.  No C++ exception crosses this ABI.
+ *  - Stepping is asynchronous on the stream given to fps_create; numeric faults
+ *    detected on the device are latched and reported by the next synchronising
+ *    call (fps_get_diag) as FPS_E_NUMERIC, after which fps_step returns
+ *    FPS_E_STATE until fields are bound again.  Reads stay available.
+ *  - Handles are not thread-safe; distinct handles are independent.
+ */
+#ifndef FPS_H
+#define FPS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FPS_OK = 0,
+    FPS_E_INVALID = -1,   /* bad argument: nothing changed */
+    FPS_E_DEVICE = -2,    /* a HIP call failed */
+    FPS_E_STATE = -3,     /* call out of order (e.g. step before binding fields) */
+    FPS_E_CAPACITY = -4,  /* workspace or a fixed capacity too small */
+    FPS_E_NUMERIC = -5    /* latched non-finite state or time step */
+} fps_status;
+
+/* boundary kinds, sides */
+enum { FPS_BC_WALL = 0, FPS_BC_TRANSMISSIVE = 1 };
+enum { FPS_SIDE_W = 0, FPS_SIDE_E = 1, FPS_SIDE_S = 2, FPS_SIDE_N = 3 };
+/* agent roles (sec. 2.4), states, hazard classes (Table 1, plus DRY) */
+enum { FPS_ROLE_EVACUEE = 0, FPS_ROLE_RESPONDER = 1 };
+enum {
+    FPS_ST_EVAC = 0,        /* heading for an exit (evacuees wait until any cell is wet) */
+    FPS_ST_EXITED = 1,
+    FPS_ST_TO_STORAGE = 2,  /* responder walking to the sandbag storage */
+    FPS_ST_PICKING = 3,     /* responder picking up a bag (timer running) */
+    FPS_ST_TO_BARRIER = 4,  /* responder carrying a bag to the barrier */
+    FPS_ST_DROPPING = 5     /* responder dropping the bag (timer running) */
+};
+enum { FPS_CLS_DRY = 0, FPS_CLS_LOW = 1, FPS_CLS_MEDIUM = 2, FPS_CLS_HIGH = 3, FPS_CLS_HIGHEST = 4 };
+
+/* Grid and flood constants.  Eq. (1)-(2), sec. 2.2; time step rule, sec. 3. */
+typedef struct {
+    int32_t nx, ny;          /* cells, >= 1 each */
+    double dx, dy;           /* cell size (m), > 0 */
+    double g;                /* gravity (m/s^2), e.g. 9.81 */
+    double cfl;              /* Courant number in (0, 1], e.g. 0.5 */
+    double h_dry;            /* dry threshold (m), e.g. 1e-5 */
+    double dt_max;           /* step cap and the dry-domain step (s): 1.0 in the paper */
+    int32_t bc[4];           /* W, E, S, N: FPS_BC_WALL or FPS_BC_TRANSMISSIVE */
+    int32_t inflow_side;     /* side carrying the hydrograph, or -1 for none */
+    int32_t inflow_c0, inflow_c1;  /* cells [c0, c1) along that side */
+    double n_base;           /* Manning n of a cell with no evacuees, e.g. 0.01 */
+    int32_t np_cap;          /* evacuees counted per cell, at most (20 in sec. 2.4) */
+} fps_grid_desc;
+
+/* Pedestrian constants (sec. 2.3-2.4, Table 1).  fps_ped_params_default fills
+   the values used throughout: Table 1 speeds and thresholds, 30 s waits, and
+   social-force constants tau 0.5 s, A/m 25 m/s^2, B 0.08 m, radius 0.25 m,
+   interaction cut-off 1 m, arrival radius 1 m. */
+typedef struct {
+    double tau, a_over_m, b_range, radius, r_cut, r_arrive;
+    double v_class[5];       /* walking speed per class; [0] unused (dry: agent's base speed) */
+    double hr_t[3];          /* class thresholds (0.75, 1.5, 2.5) */
+    double pick_s, drop_s;   /* responder waits (s) */
+} fps_ped_params;
+
+typedef struct {
+    double t;                /* simulated time (s) */
+    int64_t step;            /* steps taken */
+    int64_t ped_steps;       /* agent-steps taken by non-exited agents */
+    double dt_last;          /* step length of the last step (s) */
+    double dt_next;          /* step length the next step will use (s) */
+    double mass;             /* sum of h dx dy after the last step (m^3), FP64 on device */
+    double v_in, v_out, v_clip;  /* accumulated inflow, transmissive outflow, clipped volume (m^3) */
+    int32_t any_wet;         /* some cell has h > h_dry */
+    int32_t n_agents;
+    int32_t class_count[5];  /* non-exited agents per hazard class */
+    int32_t state_count[6];  /* agents per state */
+    int32_t barrier_layers_done, barrier_active_cell, barrier_bags, barrier_done;
+    int32_t drops_total;     /* sandbags delivered */
+    int32_t status;          /* FPS_OK or the latched fault */
+} fps_diag;
+
+typedef struct fps_sim fps_sim;
+
+/* Default pedestrian constants (see fps_ped_params). */
+void fps_ped_params_default(fps_ped_params* out);
+
+/* Bytes of device workspace one simulation of this grid with up to max_agents
+   agents needs.  0 on invalid input. */
+size_t fps_workspace_bytes(const fps_grid_desc* desc, int32_t max_agents);
+
+/* Create a simulation.  ws: device workspace of ws_bytes (>= fps_workspace_bytes),
+   256-byte aligned, caller-owned.  stream: hipStream_t all work is queued on
+   (NULL = default stream).  ped may be NULL (defaults).  The handle is written
+   to *out.  FPS_E_CAPACITY if ws_bytes is too small. */
+int fps_create(const fps_grid_desc* desc, const fps_ped_params* ped, int32_t max_agents,
+               void* ws, size_t ws_bytes, void* stream, fps_sim** out);
+void fps_destroy(fps_sim* sim);
+
+/* Bind the flood state and bed (device, float32 [ny][nx] each).  h >= 0.  The
+   state is read and written in place by fps_step; z is read by every step and
+   raised at barrier cells by the sandbag write-back (sec. 2.4).  Computes the
+   first time step from the bound state.  Clears a latched numeric fault. */
+int fps_bind_fields(fps_sim* sim, float* h, float* hu, float* hv, float* z);
+
+/* Inflow hydrograph (sec. 3.1): piecewise-linear unit discharge q_k (m^2/s)
+   at times t_k (s, increasing), constant beyond the ends; host arrays, copied;
+   at most 64 points.  The inflow enters the cells along the inflow segment
+   as a depth source of (1/dn) * integral of q over each step. */
+int fps_set_hydrograph(fps_sim* sim, const double* t, const double* q, int32_t npts);
+
+/* Navigation map (sec. 2.1): n_dest distance fields (device, float32
+   [n_dest][ny][nx], metres to the nearest cell of that destination, +inf where
+   unreachable); destinations [0, n_exit) are exits.  walkable: device uint8
+   [ny][nx], 1 where pedestrians may stand.  Caller-owned, read-only. */
+int fps_set_navigation(fps_sim* sim, int32_t n_dest, int32_t n_exit, const float* dist,
+                       const uint8_t* walkable);
+
+/* Agents (sec. 2.1, 2.4): structure of arrays of length n <= max_agents, all
+   device, caller-owned, updated in place by fps_step.  Positions in metres
+   inside the domain on walkable cells; role FPS_ROLE_*; state FPS_ST_*;
+   dest: destination index, or -1 to let the first step choose (evacuee:
+   nearest exit, responder: storage); timer: seconds left of a wait.
+   Recomputes the per-cell evacuee counts and the neighbour bins.
+   FPS_E_INVALID if an agent lies outside the domain. */
+int fps_bind_agents(fps_sim* sim, int32_t n, float* x, float* y, float* vx, float* vy,
+                    float* v_base, uint8_t* role, uint8_t* state, uint8_t* hr_class,
+                    int32_t* dest, float* timer);
+
+/* Sandbag barrier (sec. 2.4, sec. 3.3): cells (host, copied) in fill order
+   starting at the first barrier cell; responders shuttle between destination
+   storage_dest and destination barrier_dest; a cell takes bags_per bags per
+   layer; layers 1..n_layers-1 raise z by layer_thickness, the last by
+   last_thickness.  At most 2 (nx + ny) cells. */
+int fps_set_barrier(fps_sim* sim, const int32_t* cells, int32_t ncells, int32_t storage_dest,
+                    int32_t barrier_dest, int32_t n_layers, float layer_thickness,
+                    float last_thickness, int32_t bags_per);
+
+/* Set the simulated time and step counter (resume). */
+int fps_set_time(fps_sim* sim, double t, int64_t step);
+
+/* Advance n_steps coupled steps (sec. 2.4 order: flood update Eq. (2), then
+   pedestrians read the new flood state and move, then roughness and bed
+   write-back).  Asynchronous; no host synchronisation inside. */
+int fps_step(fps_sim* sim, int32_t n_steps);
+
+/* Synchronise the stream and report diagnostics (sec. 3.2 statistics). */
+int fps_get_diag(fps_sim* sim, fps_diag* out);
+
+/* Hazard rate HR = (max(|u|,|v|) + 0.5) h per cell (sec. 2.4), 0 where dry;
+   device float32 [ny][nx] output, caller-owned.  Asynchronous. */
+int fps_hazard_field(fps_sim* sim, float* hr_out);
+
+/* Copies of internal state for verification, asynchronous, device outputs:
+   counts: int32 [ny][nx] active evacuees per cell (the N_p of sec. 2.4);
+   bin_start: int32 [nbins + 1]; perm: int32 [n_agents] agent ids sorted by
+   (bin, id) for non-exited agents (bin_start[nbins] entries used). */
+int fps_get_counts(fps_sim* sim, int32_t* counts);
+int fps_get_bins(fps_sim* sim, int32_t* bin_start, int32_t* perm, int32_t* nbins_out);
+
+/* Run n_steps with HIP events around every launch and return mean device
+   milliseconds per launch of each kernel kind, in the order
+   {flood update, pedestrian step, end-of-step finalize (reductions, barrier, bin scan), bin place, bin sort}; ms_out[5]
+   (host).  Synchronises. */
+int fps_step_profiled(fps_sim* sim, int32_t n_steps, double* ms_out);
+
+const char* fps_status_string(int status);
+/* Last error message of this handle (or of the last failed fps_create when sim is NULL). */
+const char* fps_last_error(const fps_sim* sim);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FPS_H */

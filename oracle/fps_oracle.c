@@ -574,8 +574,9 @@ void or_ped_step(or_sim *S, double dt)
                 S->dest[a] = S->storage_dest;
             }
         }
-        /* evacuation trigger (R15) */
-        if (S->role[a] == OR_ROLE_EVACUEE && !S->any_wet) {
+        /* evacuation trigger (R15); an agent without a destination stands */
+        if ((S->role[a] == OR_ROLE_EVACUEE && !S->any_wet) || S->dest[a] < 0 ||
+            S->dest[a] >= S->n_dest) {
             vx1[a] = 0.0; vy1[a] = 0.0;
             S->state[a] = (uint8_t)st;
             continue;

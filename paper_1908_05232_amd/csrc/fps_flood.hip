@@ -1,0 +1,458 @@
+// Flood update of one time step on gfx950: the explicit first-order
+// Godunov-type finite-volume scheme of Eq. (2) (sec. 2.2) for the shallow-water
+// equations of Eq. (1), with wetting/drying and terrain treatment at every
+// face, Manning friction, the inflow hydrograph of sec. 3.1, and the CFL time
+// step of sec. 3 reduced on the device for the next step.
+//
+// Readings of the paper used here (the scheme is deferred to Wang et al. 2011):
+//   HLLC face flux (Toro) with dry-bed wave speeds; non-negative hydrostatic
+//   reconstruction z_f = max(zL, zR), h* = h - (z_f - z), h* <= h_dry counts
+//   as dry; bed slope as the one-sided pressure correction 1/2 g h*^2; walls by
+//   mirrored ghost cells passing no mass; transmissive sides by copied ghosts;
+//   splitting point-implicit Manning friction with a no-reversal limiter and
+//   roughness n0 (1 + min(Np, cap)) from the evacuee counts (sec. 2.4).
+//
+// Design: one wave marches up a strip of 64 columns (62 outputs plus a halo
+// column each side).  At every row each lane loads one cell (coalesced SoA
+// rows), computes the y face above it in registers (the face below is carried
+// from the previous row), and the x face to its east from its neighbour lane's
+// state (cross-lane shuffle); the west face arrives from the neighbour lane.
+// Every face is evaluated once; no LDS staging is needed.  Each block writes
+// partials (FP64 mass / volumes, FP32 max wave speed); a one-block finalize
+// kernel at the end of the step reduces them in a fixed order, advances time
+// and sets the next time step (no cross-block fences inside the update).
+#include "fps_device.h"
+
+namespace fps {
+namespace {
+
+struct Cell {
+    float h, qx, qy, z, u, v;
+};
+
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float sqrt_fast(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+// Whole-wave DPP shifts (a VALU move, no LDS traffic): lane i receives lane
+// i + 1 (wave_shl:1) or lane i - 1 (wave_shr:1); the lane without a source
+// receives 0 (never used: lanes 0 and 63 are halo lanes).
+__device__ __forceinline__ float lane_from_above(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
+                                                                 0x130, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float lane_from_below(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
+                                                                 0x138, 0xF, 0xF, false));
+}
+
+// Cell (i, j) with i in [-1, nx], j in [-1, ny]; a ghost mirrors the adjacent
+// interior cell (normal discharge negated at a wall).  Indices beyond the
+// ghost layer clamp into the grid (their values are never used).  The raw
+// load and the derived velocities are split so loads can be issued rows ahead.
+__device__ __forceinline__ Cell load_raw(const FvParams& p, int ii, int j)
+{
+    int jj = min(max(j, 0), p.ny - 1);
+    size_t k = (size_t)jj * p.nx + ii;
+    Cell c;
+    c.h = p.h[k];
+    c.qx = p.qx[k];
+    c.qy = p.qy[k];
+    c.z = p.z[k];
+    return c;
+}
+
+__device__ __forceinline__ void derive(const FvParams& p, Cell& c, bool mirror_x, int j)
+{
+    if (mirror_x) c.qx = -c.qx;
+    if ((j < 0 && p.bc[2] == FPS_BC_WALL) || (j >= p.ny && p.bc[3] == FPS_BC_WALL)) c.qy = -c.qy;
+    float r = c.h > p.eps ? rcp(c.h) : 0.0f;
+    c.u = c.qx * r;
+    c.v = c.qy * r;
+}
+
+// Hydrostatic pressure 1/2 g h^2 of a reconstructed depth.  Never contracted
+// into a neighbouring add: the flux and the bed-slope correction must use the
+// identical rounded value for still water to stay exactly at rest.
+__device__ __forceinline__ float pressure(float half_g, float h)
+{
+#pragma clang fp contract(off)
+    return half_g * h * h;
+}
+
+// One face: reconstruction, then the HLLC flux.  (un, ut) are the normal and
+// tangential velocities of each side; F0 mass, F1 normal momentum, F2
+// tangential momentum; pL / pR the pressures 1/2 g h*^2 of the reconstructed
+// depth each side sees (the bed-slope correction of the two cells).
+// Written without divergent branches: every case is evaluated and selected.
+__device__ __forceinline__ void face_flux(const FvParams& p, float hL, float unL, float utL,
+                                          float zL, float hR, float unR, float utR, float zR,
+                                          bool wall, float& F0, float& F1, float& F2,
+                                          float& pL, float& pR)
+{
+    float zf = fmaxf(zL, zR);
+    float hl = hL - (zf - zL);
+    float hr = hR - (zf - zR);
+    hl = hl > p.eps ? hl : 0.0f;
+    hr = hr > p.eps ? hr : 0.0f;
+    pL = pressure(p.half_g, hl);
+    pR = pressure(p.half_g, hr);
+    const bool wetL = hl > 0.0f, wetR = hr > 0.0f;
+    float cL = sqrt_fast(p.g * hl), cR = sqrt_fast(p.g * hr);
+    float us = 0.5f * (unL + unR) + cL - cR;
+    float cs = 0.5f * (cL + cR) + 0.25f * (unL - unR);
+    float sL = fminf(unL - cL, us - cs);
+    float sR = fmaxf(unR + cR, us + cs);
+    // dry-bed wave speeds
+    sL = wetL ? (wetR ? sL : unL - cL) : unR - 2.0f * cR;
+    sR = wetL ? (wetR ? sR : unL + 2.0f * cL) : unR + cR;
+    float qL = hl * unL, qR = hr * unR;
+    float FL0 = qL, FL1 = qL * unL + pL, FL2 = qL * utL;
+    float FR0 = qR, FR1 = qR * unR + pR, FR2 = qR * utR;
+    // HLL written from the left flux: identical states give F exactly
+    float inv = rcp(sR - sL);
+    float H0 = FL0 + sL * ((FL0 - FR0) + sR * (hr - hl)) * inv;
+    float H1 = FL1 + sL * ((FL1 - FR1) + sR * (qR - qL)) * inv;
+    // contact speed s_M = num / den with den < 0 here, so s_M >= 0 iff num <= 0
+    float num = sL * hr * (unR - sR) - sR * hl * (unL - sL);
+    float H2 = H0 * (num <= 0.0f ? utL : utR);
+    const bool left = sL >= 0.0f, right = sR <= 0.0f;
+    F0 = left ? FL0 : (right ? FR0 : H0);
+    F1 = left ? FL1 : (right ? FR1 : H1);
+    F2 = left ? FL2 : (right ? FR2 : H2);
+    const bool none = !(wetL || wetR);
+    F0 = (none || wall) ? 0.0f : F0;
+    F1 = none ? 0.0f : F1;
+    F2 = (none || wall) ? 0.0f : F2;
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+__device__ __forceinline__ float wave_max(float v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+// Blocks are handed to the 8 XCDs round-robin by block id; this mapping gives
+// each XCD a contiguous run of tiles (a band of rows), so the halo columns and
+// rows shared by neighbouring tiles are reused in that XCD's L2.
+__device__ __forceinline__ int xcd_tile_block(int b, int nblocks)
+{
+    const int per = nblocks >> 3;          // nblocks is a multiple of 8
+    return (b & 7) * per + (b >> 3);
+}
+
+__global__ __launch_bounds__(kFvBlock) void fv_step_kernel(FvParams p)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int tile = xcd_tile_block(blockIdx.x, p.nblocks) * (kFvBlock / kWave) + (threadIdx.x >> 6);
+    double m_acc = 0.0, vout_acc = 0.0, vclip_acc = 0.0;
+    float smax = 0.0f;
+    const float dt = p.st->dt;
+    const float inc = p.st->inc;
+    const float lx = dt * p.inv_dx, ly = dt * p.inv_dy;
+
+    if (tile < p.ntiles) {
+        const int sx = tile % p.nsx, sy = tile / p.nsx;
+        const int i = sx * kStrip - 1 + lane;
+        const int ii = min(max(i, 0), p.nx - 1);
+        const int j0 = sy * p.H, j1 = min(j0 + p.H, p.ny);
+        const bool out_lane = lane >= 1 && lane <= kStrip && i < p.nx;
+        const bool mirror_x = (i < 0 && p.bc[0] == FPS_BC_WALL) || (i >= p.nx && p.bc[1] == FPS_BC_WALL);
+        const bool xwall = (i == -1 && p.bc[0] == FPS_BC_WALL) ||
+                           (i + 1 == p.nx && p.bc[1] == FPS_BC_WALL);
+        bool inflow_col = false;
+        if (p.inflow_side == FPS_SIDE_S || p.inflow_side == FPS_SIDE_N)
+            inflow_col = i >= p.c0 && i < p.c1;
+
+        // rows j0-1 and j0 now, rows j0+1 and j0+2 in flight
+        Cell c = load_raw(p, ii, j0 - 1);
+        Cell cn = load_raw(p, ii, j0);
+        Cell pf1 = load_raw(p, ii, j0 + 1);
+        Cell pf2 = load_raw(p, ii, j0 + 2);
+        derive(p, c, mirror_x, j0 - 1);
+        derive(p, cn, mirror_x, j0);
+        float Fs0, Fs1, Fs2, p_dummy, pS;
+        face_flux(p, c.h, c.v, c.u, c.z, cn.h, cn.v, cn.u, cn.z,
+                  j0 == 0 && p.bc[2] == FPS_BC_WALL, Fs0, Fs1, Fs2, p_dummy, pS);
+        c = cn;
+        for (int j = j0; j < j1; ++j) {
+            Cell nb = pf1;
+            pf1 = pf2;
+            pf2 = load_raw(p, ii, j + 3);
+            derive(p, nb, mirror_x, j + 1);
+            const size_t k = (size_t)j * p.nx + i;
+            int npc = 0;
+            if (out_lane) npc = p.np[k];
+            // north face (y normal: pass v as normal, u as tangential)
+            float Fn0, Fn1, Fn2, pN, pS_next;
+            face_flux(p, c.h, c.v, c.u, c.z, nb.h, nb.v, nb.u, nb.z,
+                      j + 1 == p.ny && p.bc[3] == FPS_BC_WALL, Fn0, Fn1, Fn2, pN, pS_next);
+            // east face with the neighbour lane's cell
+            float eh = lane_from_above(c.h), eu = lane_from_above(c.u);
+            float ev = lane_from_above(c.v), ez = lane_from_above(c.z);
+            float Fe0, Fe1, Fe2, pE, pW_east;
+            face_flux(p, c.h, c.u, c.v, c.z, eh, eu, ev, ez, xwall, Fe0, Fe1, Fe2, pE, pW_east);
+            // west face = east face of the lane below
+            float Fw0 = lane_from_below(Fe0), Fw1 = lane_from_below(Fe1);
+            float Fw2 = lane_from_below(Fe2), pW = lane_from_below(pW_east);
+            if (out_lane) {
+                float hn = c.h - (lx * (Fe0 - Fw0) + ly * (Fn0 - Fs0));
+                float qxn = c.qx - (lx * ((Fe1 - pE) - (Fw1 - pW)) + ly * (Fn2 - Fs2));
+                float qyn = c.qy - (ly * ((Fn1 - pN) - (Fs1 - pS)) + lx * (Fe2 - Fw2));
+                // inflow line source (sec. 3.1)
+                bool inflow = false;
+                if (p.inflow_side == FPS_SIDE_S) inflow = inflow_col && j == 0;
+                else if (p.inflow_side == FPS_SIDE_N) inflow = inflow_col && j == p.ny - 1;
+                else if (p.inflow_side == FPS_SIDE_W) inflow = i == 0 && j >= p.c0 && j < p.c1;
+                else if (p.inflow_side == FPS_SIDE_E) inflow = i == p.nx - 1 && j >= p.c0 && j < p.c1;
+                if (inflow) hn += inc;
+                // non-negative depth, no discharge on dry cells
+                if (hn < 0.0f) {
+                    vclip_acc += (double)(-hn);
+                    hn = 0.0f;
+                }
+                if (!(hn > p.eps)) {
+                    qxn = 0.0f;
+                    qyn = 0.0f;
+                }
+                if (hn > p.eps) {
+                    float r = rcp(hn);
+                    float u = qxn * r, v = qyn * r;
+                    float V2 = u * u + v * v;
+                    if (V2 > 0.0f) {
+                        // Manning friction, splitting point-implicit
+                        float n = p.n_base + (float)min(npc, p.np_cap) * p.n_base;
+                        float speed = sqrt_fast(V2);
+                        float hm13 = __builtin_amdgcn_exp2f(-__builtin_amdgcn_logf(hn) * (1.0f / 3.0f));
+                        float Cf = p.g * n * n * hm13;
+                        float Sx = -Cf * u * speed, Sy = -Cf * v * speed;
+                        float a = dt * Cf * r * rcp(speed);
+                        float Dx = 1.0f + a * (2.0f * u * u + v * v);
+                        float Dy = 1.0f + a * (2.0f * v * v + u * u);
+                        float dqx = dt * Sx * rcp(Dx), dqy = dt * Sy * rcp(Dy);
+                        if (fabsf(dqx) > fabsf(qxn)) dqx = -qxn;
+                        if (fabsf(dqy) > fabsf(qyn)) dqy = -qyn;
+                        qxn += dqx;
+                        qyn += dqy;
+                        u = qxn * r;
+                        v = qyn * r;
+                    }
+                    float cel = sqrt_fast(p.g * hn);
+                    smax = fmaxf(smax, fmaxf((fabsf(u) + cel) * p.inv_dx, (fabsf(v) + cel) * p.inv_dy));
+                }
+                m_acc += (double)hn;
+                // outflow through transmissive sides
+                if (i == 0 && p.bc[0] == FPS_BC_TRANSMISSIVE) vout_acc -= (double)Fw0 * dt * p.dy;
+                if (i == p.nx - 1 && p.bc[1] == FPS_BC_TRANSMISSIVE) vout_acc += (double)Fe0 * dt * p.dy;
+                if (j == 0 && p.bc[2] == FPS_BC_TRANSMISSIVE) vout_acc -= (double)Fs0 * dt * p.dx;
+                if (j == p.ny - 1 && p.bc[3] == FPS_BC_TRANSMISSIVE) vout_acc += (double)Fn0 * dt * p.dx;
+                p.ho[k] = hn;
+                p.qxo[k] = qxn;
+                p.qyo[k] = qyn;
+            }
+            Fs0 = Fn0;
+            Fs1 = Fn1;
+            Fs2 = Fn2;
+            pS = pS_next;
+            c = nb;
+        }
+    }
+    // block partials, fixed reduction order; reduced by the finalize kernel
+    __shared__ double wred[kFvBlock / kWave][4];
+    m_acc = wave_sum(m_acc);
+    vout_acc = wave_sum(vout_acc);
+    vclip_acc = wave_sum(vclip_acc);
+    smax = wave_max(smax);
+    if (lane == 0) {
+        int w = threadIdx.x >> 6;
+        wred[w][0] = m_acc;
+        wred[w][1] = vout_acc;
+        wred[w][2] = vclip_acc;
+        wred[w][3] = (double)smax;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+        for (int w = 0; w < kFvBlock / kWave; ++w) {
+            s0 += wred[w][0];
+            s1 += wred[w][1];
+            s2 += wred[w][2];
+            s3 = fmax(s3, wred[w][3]);
+        }
+        double* dst = &p.partials[4 * blockIdx.x];
+        dst[0] = s0;
+        dst[1] = s1;
+        dst[2] = s2;
+        dst[3] = s3;
+    }
+}
+
+// Scan of the current state only: mass, wetness and the time step that the
+// next update will use (no time advance).  Same reduction as the step.
+__global__ __launch_bounds__(kFvBlock) void fv_scan_kernel(FvParams p)
+{
+    double m_acc = 0.0;
+    float smax = 0.0f;
+    const int64_t nc = (int64_t)p.nx * p.ny;
+    for (int64_t k = (int64_t)blockIdx.x * kFvBlock + threadIdx.x; k < nc;
+         k += (int64_t)p.nblocks * kFvBlock) {
+        float h = p.h[k];
+        m_acc += (double)h;
+        if (h > p.eps) {
+            float r = rcp(h);
+            float u = p.qx[k] * r, v = p.qy[k] * r;
+            float cel = sqrt_fast(p.g * h);
+            smax = fmaxf(smax, fmaxf((fabsf(u) + cel) * p.inv_dx, (fabsf(v) + cel) * p.inv_dy));
+        }
+    }
+    __shared__ double wred[kFvBlock / kWave][2];
+    m_acc = wave_sum(m_acc);
+    smax = wave_max(smax);
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        wred[threadIdx.x >> 6][0] = m_acc;
+        wred[threadIdx.x >> 6][1] = (double)smax;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s0 = 0, s3 = 0;
+        for (int w = 0; w < kFvBlock / kWave; ++w) {
+            s0 += wred[w][0];
+            s3 = fmax(s3, wred[w][1]);
+        }
+        double* dst = &p.partials[4 * blockIdx.x];
+        dst[0] = s0;
+        dst[1] = 0.0;
+        dst[2] = 0.0;
+        dst[3] = s3;
+    }
+}
+
+// End of a step (one block of kScanThreads): reduce the flood partials in a
+// fixed order, advance time, set the next CFL time step (sec. 3) and inflow
+// depth; apply the sandbag drops of the step to the barrier line (sec. 2.4);
+// scan the histogram of the new agent bins.
+__global__ __launch_bounds__(kScanThreads) void finalize_kernel(FinParams f)
+{
+    const FvParams& p = f.fv;
+    __shared__ double red[kScanThreads][4];
+    double m = 0.0, vo = 0.0, vc = 0.0, sm = 0.0;
+    for (int b = threadIdx.x; b < p.nblocks; b += kScanThreads) {
+        m += p.partials[4 * b + 0];
+        vo += p.partials[4 * b + 1];
+        vc += p.partials[4 * b + 2];
+        sm = fmax(sm, p.partials[4 * b + 3]);
+    }
+    red[threadIdx.x][0] = m;
+    red[threadIdx.x][1] = vo;
+    red[threadIdx.x][2] = vc;
+    red[threadIdx.x][3] = sm;
+    __syncthreads();
+    for (int s = kScanThreads / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            red[threadIdx.x][0] += red[threadIdx.x + s][0];
+            red[threadIdx.x][1] += red[threadIdx.x + s][1];
+            red[threadIdx.x][2] += red[threadIdx.x + s][2];
+            red[threadIdx.x][3] = fmax(red[threadIdx.x][3], red[threadIdx.x + s][3]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        DevState* st = p.st;
+        float smax = (float)red[0][3];
+        int wet = smax > 0.0f;
+        double mass = red[0][0] * p.dxdy;
+        if (p.mode == 0) {
+            float dt_used = st->dt;
+            st->v_out += red[0][1];
+            st->v_clip += red[0][2] * p.dxdy;
+            st->v_in += (double)st->inc * (double)p.n_inflow * p.dxdy;
+            st->t += (double)dt_used;
+            st->step += 1;
+            st->dt_prev = dt_used;
+        }
+        st->mass = mass;
+        st->any_wet = wet;
+        float dtn = wet ? fminf(p.cfl / smax, p.dt_max) : p.dt_max;
+        st->dt = dtn;
+        float inc = 0.0f;
+        if (p.inflow_side >= 0) {
+            double dn = p.inflow_side <= 1 ? (double)p.dx : (double)p.dy;
+            inc = (float)(hydro_integral(st, st->t, st->t + (double)dtn) / dn);
+        }
+        st->inc = inc;
+        if (!isfinite(mass) || !(dtn > 0.0f) || !isfinite(dtn)) st->status = FPS_E_NUMERIC;
+        // sandbag write-back: drops of this step applied to the barrier line in order
+        if (f.do_barrier) {
+            const BarrierParams& B = f.bar;
+            int D = st->drops;
+            st->drops = 0;
+            st->drops_total += D;
+            if (!st->done && B.nline > 0) {
+                int bags = st->bags + D;
+                int active = st->active, layers = st->layers_done, fin = 0;
+                while (!fin && bags >= B.bags_per) {
+                    bags -= B.bags_per;
+                    float th = layers == B.n_layers - 1 ? B.t_last : B.t_bag;
+                    B.z[B.line[active]] += th;
+                    active += 1;
+                    if (active == B.nline) {
+                        active = 0;
+                        layers += 1;
+                        if (layers >= B.n_layers) fin = 1;
+                    }
+                }
+                st->bags = bags;
+                st->active = active;
+                st->layers_done = layers;
+                st->done = fin;
+            }
+        }
+    }
+    if (f.do_scan) {
+        __syncthreads();
+        block_scan_bins(f.bins);
+    }
+}
+
+}  // namespace
+
+int fv_rows_per_wave(int nx, int ny)
+{
+    // long marches on large grids (halo rows amortised), short ones on small
+    // grids so that there are enough waves to spread over the 1024 SIMDs
+    const int64_t nsx = (nx + kStrip - 1) / kStrip;
+    int H = 64;
+    while (H > 4 && nsx * ((ny + H - 1) / H) < 4096) H >>= 1;
+    return H;
+}
+
+int fv_blocks(int nx, int ny, int H)
+{
+    const int64_t nsx = (nx + kStrip - 1) / kStrip;
+    const int64_t tiles = nsx * ((ny + H - 1) / H);
+    const int64_t blocks = (tiles + kFvBlock / kWave - 1) / (kFvBlock / kWave);
+    return (int)((blocks + 7) / 8 * 8);    // a multiple of the 8 XCDs
+}
+
+hipError_t launch_finalize(const FinParams& f, hipStream_t s)
+{
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kScanThreads), 0, s, f);
+    return hipGetLastError();
+}
+
+hipError_t launch_fv(const FvParams& p, hipStream_t s)
+{
+    if (p.mode == 0)
+        hipLaunchKernelGGL(fv_step_kernel, dim3(p.nblocks), dim3(kFvBlock), 0, s, p);
+    else
+        hipLaunchKernelGGL(fv_scan_kernel, dim3(p.nblocks), dim3(kFvBlock), 0, s, p);
+    return hipGetLastError();
+}
+
+}  // namespace fps

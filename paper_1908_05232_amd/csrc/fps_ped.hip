@@ -1,0 +1,504 @@
+// Pedestrian step and neighbour binning on gfx950 (sec. 2.3-2.4, Table 1).
+//
+// One lane per agent.  Each agent reads the flood state of the navigation
+// cell that contains it, takes its hazard class and walking speed (Table 1,
+// HR = (max(|u|,|v|) + 0.5) h), follows its destination's distance field, is
+// repelled by neighbours found in the 3x3 bins around it and by obstacle
+// cells, and moves.  Evacuee counts per cell (the N_p of the roughness rule)
+// are kept by integer atomics on the old and new cells; responders deliver
+// sandbags that the last block applies to the barrier line in order.
+//
+// Readings (the paper defers the pedestrian model to Karmakharm et al. 2010
+// and Helbing's social force): exact relaxation v <- v0 e + (v - v0 e)
+// exp(-dt/tau); repulsion A/m exp((2r - d)/B) from agents and A/m exp((r -
+// d)/B) from the nearest point of obstacle cells within r_cut; |v| <= v0;
+// axis-wise rejection of moves into obstacles or out of the domain; arrival
+// when the destination distance at the new cell is <= r_arrive; evacuees stand
+// until some cell is wet; dry cells: hazard class DRY at the agent's own speed.
+//
+// Binning is a stable counting sort by (bin, agent id): integer histogram with
+// atomic ranks, one-block exclusive scan, placement by rank, then each agent
+// finds its final slot by counting the smaller ids of its own bin, so the
+// result is deterministic and equal to a stable sort.
+#include "fps_device.h"
+
+namespace fps {
+namespace {
+
+__device__ __forceinline__ int cell_of(float x, float d, int n)
+{
+    // IEEE division and floor in FP32; may return -1 or n (outside)
+    float f = floorf(x / d);
+    if (f < -1.0f) return -1;
+    if (f > (float)n) return n;
+    return (int)f;
+}
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+__device__ __forceinline__ float dist_at(const PedParams& p, int d, int i, int j)
+{
+    return p.dist[((size_t)d * p.ny + j) * p.nx + i];
+}
+
+__device__ __forceinline__ int nearest_exit(const PedParams& p, int ci, int cj)
+{
+    int best = 0;
+    float bd = dist_at(p, 0, ci, cj);
+    for (int e = 1; e < p.n_exit; ++e) {
+        float de = dist_at(p, e, ci, cj);
+        if (de < bd) {
+            bd = de;
+            best = e;
+        }
+    }
+    return best;
+}
+
+__device__ void agent_step(const PedParams& p, int a, float dt, int any_wet, int done,
+                           int& drop)
+{
+    const int st0 = p.state[a];
+    if (st0 == FPS_ST_EXITED) {
+        p.key[a] = -1;
+        return;
+    }
+    const float x = p.x[a], y = p.y[a];
+    const int ci = clampi(cell_of(x, p.dx, p.nx), 0, p.nx - 1);
+    const int cj = clampi(cell_of(y, p.dy, p.ny), 0, p.ny - 1);
+    const size_t c = (size_t)cj * p.nx + ci;
+    const int role = p.role[a];
+    // hazard of the containing cell
+    int cls;
+    float v0;
+    const float h = p.h[c];
+    if (!(h > p.eps)) {
+        cls = FPS_CLS_DRY;
+        v0 = p.vbase[a];
+    } else {
+        float u = p.qx[c] / h, v = p.qy[c] / h;
+        float hr = (fmaxf(fabsf(u), fabsf(v)) + 0.5f) * h;
+        cls = hr < p.hr_t[0] ? FPS_CLS_LOW
+            : hr < p.hr_t[1] ? FPS_CLS_MEDIUM
+            : hr < p.hr_t[2] ? FPS_CLS_HIGH : FPS_CLS_HIGHEST;
+        v0 = p.v_class[cls];
+    }
+    p.cls[a] = (uint8_t)cls;
+    int st = st0;
+    int dest = p.dest[a];
+    if (dest < 0) {
+        if (role == FPS_ROLE_EVACUEE) {
+            dest = nearest_exit(p, ci, cj);
+            st = FPS_ST_EVAC;
+        } else {
+            dest = p.storage_dest;
+            st = FPS_ST_TO_STORAGE;
+        }
+    }
+    if (role == FPS_ROLE_RESPONDER && done && st != FPS_ST_EVAC) {
+        st = FPS_ST_EVAC;
+        dest = nearest_exit(p, ci, cj);
+    }
+    float vx = p.vx[a], vy = p.vy[a];
+    float xn = x, yn = y;
+    bool moving = true;
+    if (st == FPS_ST_PICKING || st == FPS_ST_DROPPING) {
+        float tm = p.timer[a] - dt;
+        p.timer[a] = tm;
+        if (tm > 0.0f) {
+            moving = false;
+        } else if (st == FPS_ST_PICKING) {
+            st = FPS_ST_TO_BARRIER;
+            dest = p.barrier_dest;
+        } else {
+            drop = 1;
+            st = FPS_ST_TO_STORAGE;
+            dest = p.storage_dest;
+        }
+    }
+    if (moving && role == FPS_ROLE_EVACUEE && !any_wet) moving = false;
+    // an agent without a valid destination (e.g. a responder with no barrier set) stands
+    if (dest < 0 || dest >= p.n_dest) moving = false;
+    int ni = ci, nj = cj;
+    if (!moving) {
+        vx = 0.0f;
+        vy = 0.0f;
+    } else {
+        // desired direction from the distance field
+        float ex = 0.0f, ey = 0.0f;
+        float here = dist_at(p, dest, ci, cj);
+        int ti = ci, tj = cj;
+        bool has_target = true;
+        if (!(here == 0.0f)) {
+            const int offx[8] = {1, 0, -1, 0, 1, -1, -1, 1};
+            const int offy[8] = {0, 1, 0, -1, 1, 1, -1, -1};
+            float best = here;
+            int kb = -1;
+            for (int k = 0; k < 8; ++k) {
+                int qi = ci + offx[k], qj = cj + offy[k];
+                if (qi < 0 || qj < 0 || qi >= p.nx || qj >= p.ny) continue;
+                float dk = dist_at(p, dest, qi, qj);
+                if (dk < best) {
+                    best = dk;
+                    kb = k;
+                }
+            }
+            if (kb < 0) has_target = false;
+            else {
+                ti = ci + offx[kb];
+                tj = cj + offy[kb];
+            }
+        }
+        if (has_target) {
+            float tx = ((float)ti + 0.5f) * p.dx - x, ty = ((float)tj + 0.5f) * p.dy - y;
+            float len = sqrtf(tx * tx + ty * ty);
+            if (len > 0.0f) {
+                ex = tx / len;
+                ey = ty / len;
+            }
+        }
+        // relaxation toward the desired velocity
+        float k = expf(-dt / p.tau);
+        vx = v0 * ex + (vx - v0 * ex) * k;
+        vy = v0 * ey + (vy - v0 * ey) * k;
+        // repulsion: neighbours in the 3x3 bins, in (bin, id) order; the three
+        // bins of one bin row are one contiguous run of the sorted positions
+        float fx = 0.0f, fy = 0.0f;
+        const int bi = ci / p.bsx, bj = cj / p.bsy;
+        const int qi0 = max(bi - 1, 0), qi1 = min(bi + 1, p.nbx - 1);
+        const int self = p.slot[a];
+        for (int qj = max(bj - 1, 0); qj <= min(bj + 1, p.nby - 1); ++qj) {
+            const int s0 = p.bin_start[qj * p.nbx + qi0];
+            const int s1 = p.bin_start[qj * p.nbx + qi1 + 1];
+            for (int s = s0; s < s1; ++s) {
+                if (s == self) continue;
+                float2 o = p.xy[s];
+                float rx = x - o.x, ry = y - o.y;
+                float d = sqrtf(rx * rx + ry * ry);
+                if (!(d > 0.0f) || !(d < p.r_cut)) continue;
+                float w = p.a_over_m * expf((p.two_r - d) * p.inv_b) / d;
+                fx += w * rx;
+                fy += w * ry;
+            }
+        }
+        // obstacle cells within r_cut, in row-major offset order
+        if (p.use_wmask) {
+            const uint4 m4 = p.wmask[c];
+            const uint32_t mw[4] = {m4.x, m4.y, m4.z, m4.w};
+            const int wdth = 2 * p.Rx + 1;
+            for (int w = 0; w < 4; ++w) {
+                uint32_t m = mw[w];
+                while (m) {
+                    const int bit = 32 * w + __builtin_ctz(m);
+                    m &= m - 1;
+                    const int wi = ci + bit % wdth - p.Rx, wj = cj + bit / wdth - p.Ry;
+                    float px = fminf(fmaxf(x, (float)wi * p.dx), (float)(wi + 1) * p.dx);
+                    float py = fminf(fmaxf(y, (float)wj * p.dy), (float)(wj + 1) * p.dy);
+                    float rx = x - px, ry = y - py;
+                    float d = sqrtf(rx * rx + ry * ry);
+                    if (!(d > 0.0f) || !(d < p.r_cut)) continue;
+                    float wt = p.a_over_m * expf((p.radius - d) * p.inv_b) / d;
+                    fx += wt * rx;
+                    fy += wt * ry;
+                }
+            }
+        } else {
+            for (int dj = -p.Ry; dj <= p.Ry; ++dj) {
+                int wj = cj + dj;
+                if (wj < 0 || wj >= p.ny) continue;
+                for (int di = -p.Rx; di <= p.Rx; ++di) {
+                    int wi = ci + di;
+                    if (wi < 0 || wi >= p.nx) continue;
+                    if (p.walk[(size_t)wj * p.nx + wi]) continue;
+                    float px = fminf(fmaxf(x, (float)wi * p.dx), (float)(wi + 1) * p.dx);
+                    float py = fminf(fmaxf(y, (float)wj * p.dy), (float)(wj + 1) * p.dy);
+                    float rx = x - px, ry = y - py;
+                    float d = sqrtf(rx * rx + ry * ry);
+                    if (!(d > 0.0f) || !(d < p.r_cut)) continue;
+                    float wt = p.a_over_m * expf((p.radius - d) * p.inv_b) / d;
+                    fx += wt * rx;
+                    fy += wt * ry;
+                }
+            }
+        }
+        vx += dt * fx;
+        vy += dt * fy;
+        float sp = sqrtf(vx * vx + vy * vy);
+        if (sp > v0) {
+            if (v0 > 0.0f) {
+                float s = v0 / sp;
+                vx *= s;
+                vy *= s;
+            } else {
+                vx = 0.0f;
+                vy = 0.0f;
+            }
+        }
+        // move, rejecting an axis that lands in an obstacle or outside
+        xn = x + dt * vx;
+        ni = cell_of(xn, p.dx, p.nx);
+        if (ni < 0 || ni >= p.nx || !p.walk[(size_t)cj * p.nx + ni]) {
+            xn = x;
+            vx = 0.0f;
+            ni = ci;
+        }
+        yn = y + dt * vy;
+        nj = cell_of(yn, p.dy, p.ny);
+        if (nj < 0 || nj >= p.ny || !p.walk[(size_t)nj * p.nx + ni]) {
+            yn = y;
+            vy = 0.0f;
+            nj = cj;
+        }
+        if (dist_at(p, dest, ni, nj) <= p.r_arrive) {
+            if (st == FPS_ST_EVAC) {
+                st = FPS_ST_EXITED;
+            } else if (st == FPS_ST_TO_STORAGE) {
+                st = FPS_ST_PICKING;
+                p.timer[a] = p.pick_s;
+                vx = 0.0f;
+                vy = 0.0f;
+            } else if (st == FPS_ST_TO_BARRIER) {
+                st = FPS_ST_DROPPING;
+                p.timer[a] = p.drop_s;
+                vx = 0.0f;
+                vy = 0.0f;
+            }
+        }
+    }
+    p.x[a] = xn;
+    p.y[a] = yn;
+    p.vx[a] = vx;
+    p.vy[a] = vy;
+    p.state[a] = (uint8_t)st;
+    p.dest[a] = dest;
+    // evacuee counts per cell (roughness write-back)
+    const size_t cn = (size_t)nj * p.nx + ni;
+    const bool was = role == FPS_ROLE_EVACUEE && st0 == FPS_ST_EVAC;
+    const bool now = role == FPS_ROLE_EVACUEE && st == FPS_ST_EVAC;
+    if (was && !(now && cn == c)) atomicSub(&p.np[c], 1);
+    if (now && !(was && cn == c)) atomicAdd(&p.np[cn], 1);
+    // histogram of the new positions
+    if (st != FPS_ST_EXITED) {
+        int b = (nj / p.bsy) * p.nbx + ni / p.bsx;
+        p.key[a] = b;
+        p.rank[a] = atomicAdd(&p.bin_count[b], 1);
+    } else {
+        p.key[a] = -1;
+    }
+}
+
+__global__ __launch_bounds__(kPedBlock) void ped_step_kernel(PedParams p)
+{
+    __shared__ int drops, active, wet;
+    if (threadIdx.x == 0) {
+        drops = 0;
+        active = 0;
+        wet = 0;
+    }
+    __syncthreads();
+    // evacuation trigger: some cell wet after this step's flood update (any
+    // block of the flood kernel saw a positive wave speed)
+    for (int b = threadIdx.x; b < p.fv_blocks; b += kPedBlock)
+        if (p.fv_partials[4 * b + 3] > 0.0) wet = 1;
+    __syncthreads();
+    const DevState* st = p.st;
+    const float dt = st->dt;            // the step length of this step
+    const int done = st->done;
+    const int a = blockIdx.x * kPedBlock + threadIdx.x;
+    if (a < p.na) {
+        int drop = 0;
+        if (p.state[a] != FPS_ST_EXITED) atomicAdd(&active, 1);
+        agent_step(p, a, dt, wet, done, drop);
+        if (drop) atomicAdd(&drops, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (drops) atomicAdd(&p.st->drops, drops);
+        if (active) atomicAdd(&p.st->ped_steps, (unsigned long long)active);
+    }
+}
+
+// --- binning ---------------------------------------------------------------
+__global__ void bin_keys_kernel(BinParams b)
+{
+    int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= b.na) return;
+    if (b.state[a] == FPS_ST_EXITED) {
+        b.key[a] = -1;
+        return;
+    }
+    int ci = clampi(cell_of(b.x[a], b.dx, b.nx), 0, b.nx - 1);
+    int cj = clampi(cell_of(b.y[a], b.dy, b.ny), 0, b.ny - 1);
+    int k = (cj / b.bsy) * b.nbx + ci / b.bsx;
+    b.key[a] = k;
+    b.rank[a] = atomicAdd(&b.bin_count[k], 1);
+}
+
+__global__ __launch_bounds__(kScanThreads) void bin_scan_kernel(BinParams b) { block_scan_bins(b); }
+
+__global__ void bin_place_kernel(BinParams b)
+{
+    int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= b.na) return;
+    int k = b.key[a];
+    if (k >= 0) b.perm_u[b.bin_start[k] + b.rank[a]] = a;
+}
+
+__global__ void bin_sort_kernel(BinParams b)
+{
+    int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= b.na) return;
+    int k = b.key[a];
+    if (k < 0) return;
+    int s0 = b.bin_start[k], s1 = b.bin_start[k + 1];
+    int below = 0;
+    for (int s = s0; s < s1; ++s) below += b.perm_u[s] < a;
+    int f = s0 + below;
+    b.perm[f] = a;
+    b.slot[a] = f;
+    b.xy[f] = make_float2(b.x[a], b.y[a]);
+}
+
+__global__ void count_kernel(BinParams b)
+{
+    int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= b.na) return;
+    if (b.role[a] != FPS_ROLE_EVACUEE || b.state[a] != FPS_ST_EVAC) return;
+    int ci = clampi(cell_of(b.x[a], b.dx, b.nx), 0, b.nx - 1);
+    int cj = clampi(cell_of(b.y[a], b.dy, b.ny), 0, b.ny - 1);
+    atomicAdd(&b.np[(size_t)cj * b.nx + ci], 1);
+}
+
+__global__ void fill_i32_kernel(int32_t* p, int32_t v, int64_t n)
+{
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; k < n; k += (int64_t)gridDim.x * blockDim.x) p[k] = v;
+}
+
+__global__ void hazard_kernel(const float* h, const float* qx, const float* qy, float* hr,
+                              int64_t n, float eps)
+{
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        float d = h[k];
+        float r = 0.0f;
+        if (d > eps) r = (fmaxf(fabsf(qx[k] / d), fabsf(qy[k] / d)) + 0.5f) * d;
+        hr[k] = r;
+    }
+}
+
+__global__ void agent_stats_kernel(const uint8_t* state, const uint8_t* cls, int na, int32_t* out)
+{
+    int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= na) return;
+    int s = state[a];
+    atomicAdd(&out[5 + min(s, 5)], 1);
+    if (s != FPS_ST_EXITED) atomicAdd(&out[min((int)cls[a], 4)], 1);
+}
+
+// Per cell, one bit per offset (di, dj) in [-Rx, Rx] x [-Ry, Ry], row-major
+// from (-Rx, -Ry): set where that cell lies in the grid and is not walkable.
+__global__ void wall_mask_kernel(const uint8_t* walk, uint4* mask, int nx, int ny, int Rx, int Ry)
+{
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= (int64_t)nx * ny) return;
+    int i = (int)(c % nx), j = (int)(c / nx);
+    uint32_t m[4] = {0, 0, 0, 0};
+    int bit = 0;
+    for (int dj = -Ry; dj <= Ry; ++dj)
+        for (int di = -Rx; di <= Rx; ++di, ++bit) {
+            int wi = i + di, wj = j + dj;
+            if (wi < 0 || wj < 0 || wi >= nx || wj >= ny) continue;
+            if (!walk[(size_t)wj * nx + wi]) m[bit >> 5] |= 1u << (bit & 31);
+        }
+    mask[c] = make_uint4(m[0], m[1], m[2], m[3]);
+}
+
+__global__ void check_agents_kernel(const float* x, const float* y, const uint8_t* role,
+                                    const uint8_t* state, const int32_t* dest, int na, float lx,
+                                    float ly, int n_dest, int32_t* bad)
+{
+    int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= na) return;
+    float xa = x[a], ya = y[a];
+    if (!(xa >= 0.0f && xa < lx && ya >= 0.0f && ya < ly)) atomicAdd(&bad[0], 1);
+    if (role[a] > FPS_ROLE_RESPONDER || state[a] > FPS_ST_DROPPING || dest[a] < -1 || dest[a] >= n_dest)
+        atomicAdd(&bad[1], 1);
+}
+
+inline int blocks_for(int64_t n, int t) { return (int)((n + t - 1) / t); }
+
+}  // namespace
+
+hipError_t launch_ped(const PedParams& p, hipStream_t s)
+{
+    hipLaunchKernelGGL(ped_step_kernel, dim3(p.nblocks), dim3(kPedBlock), 0, s, p);
+    return hipGetLastError();
+}
+hipError_t launch_bin_keys(const BinParams& b, hipStream_t s)
+{
+    if (b.na > 0) hipLaunchKernelGGL(bin_keys_kernel, dim3(blocks_for(b.na, 256)), dim3(256), 0, s, b);
+    return hipGetLastError();
+}
+hipError_t launch_bin_scan(const BinParams& b, hipStream_t s)
+{
+    hipLaunchKernelGGL(bin_scan_kernel, dim3(1), dim3(kScanThreads), 0, s, b);
+    return hipGetLastError();
+}
+hipError_t launch_bin_place(const BinParams& b, hipStream_t s)
+{
+    if (b.na > 0) hipLaunchKernelGGL(bin_place_kernel, dim3(blocks_for(b.na, 256)), dim3(256), 0, s, b);
+    return hipGetLastError();
+}
+hipError_t launch_bin_sort(const BinParams& b, hipStream_t s)
+{
+    if (b.na > 0) hipLaunchKernelGGL(bin_sort_kernel, dim3(blocks_for(b.na, 256)), dim3(256), 0, s, b);
+    return hipGetLastError();
+}
+hipError_t launch_count(const BinParams& b, hipStream_t s)
+{
+    if (b.na > 0) hipLaunchKernelGGL(count_kernel, dim3(blocks_for(b.na, 256)), dim3(256), 0, s, b);
+    return hipGetLastError();
+}
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s)
+{
+    if (n > 0) {
+        int g = (int)std::min<int64_t>(blocks_for(n, 256), 4096);
+        hipLaunchKernelGGL(fill_i32_kernel, dim3(g), dim3(256), 0, s, p, v, n);
+    }
+    return hipGetLastError();
+}
+hipError_t launch_hazard(const float* h, const float* qx, const float* qy, float* hr, int64_t n,
+                         float eps, hipStream_t s)
+{
+    int g = (int)std::min<int64_t>(blocks_for(n, 256), 8192);
+    hipLaunchKernelGGL(hazard_kernel, dim3(g), dim3(256), 0, s, h, qx, qy, hr, n, eps);
+    return hipGetLastError();
+}
+hipError_t launch_agent_stats(const uint8_t* state, const uint8_t* cls, int na, int32_t* out11,
+                              hipStream_t s)
+{
+    if (na > 0)
+        hipLaunchKernelGGL(agent_stats_kernel, dim3(blocks_for(na, 256)), dim3(256), 0, s, state,
+                           cls, na, out11);
+    return hipGetLastError();
+}
+hipError_t launch_wall_mask(const uint8_t* walk, uint4* mask, int nx, int ny, int Rx, int Ry,
+                            hipStream_t s)
+{
+    int64_t n = (int64_t)nx * ny;
+    hipLaunchKernelGGL(wall_mask_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, walk, mask, nx, ny,
+                       Rx, Ry);
+    return hipGetLastError();
+}
+hipError_t launch_check_agents(const float* x, const float* y, const uint8_t* role,
+                               const uint8_t* state, const int32_t* dest, int na, float lx,
+                               float ly, int n_dest, int32_t* bad2, hipStream_t s)
+{
+    if (na > 0)
+        hipLaunchKernelGGL(check_agents_kernel, dim3(blocks_for(na, 256)), dim3(256), 0, s, x, y,
+                           role, state, dest, na, lx, ly, n_dest, bad2);
+    return hipGetLastError();
+}
+
+}  // namespace fps

@@ -1,0 +1,260 @@
+"""ctypes binding of libfps.so (C-ABI in include/fps.h).
+
+Argument marshalling only: every step of the simulation runs in the HIP
+kernels of libfps.  PyTorch provides device memory and the stream.  Importing
+this module fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libfps.so")
+
+FPS_OK, FPS_E_INVALID, FPS_E_DEVICE, FPS_E_STATE, FPS_E_CAPACITY, FPS_E_NUMERIC = 0, -1, -2, -3, -4, -5
+
+_vp = C.c_void_p
+
+
+class GridDescC(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32),
+        ("dx", C.c_double), ("dy", C.c_double),
+        ("g", C.c_double), ("cfl", C.c_double), ("h_dry", C.c_double), ("dt_max", C.c_double),
+        ("bc", C.c_int32 * 4),
+        ("inflow_side", C.c_int32), ("inflow_c0", C.c_int32), ("inflow_c1", C.c_int32),
+        ("n_base", C.c_double), ("np_cap", C.c_int32),
+    ]
+
+
+class PedParamsC(C.Structure):
+    _fields_ = [
+        ("tau", C.c_double), ("a_over_m", C.c_double), ("b_range", C.c_double),
+        ("radius", C.c_double), ("r_cut", C.c_double), ("r_arrive", C.c_double),
+        ("v_class", C.c_double * 5), ("hr_t", C.c_double * 3),
+        ("pick_s", C.c_double), ("drop_s", C.c_double),
+    ]
+
+
+class DiagC(C.Structure):
+    _fields_ = [
+        ("t", C.c_double), ("step", C.c_int64), ("ped_steps", C.c_int64),
+        ("dt_last", C.c_double), ("dt_next", C.c_double),
+        ("mass", C.c_double), ("v_in", C.c_double), ("v_out", C.c_double), ("v_clip", C.c_double),
+        ("any_wet", C.c_int32), ("n_agents", C.c_int32),
+        ("class_count", C.c_int32 * 5), ("state_count", C.c_int32 * 6),
+        ("barrier_layers_done", C.c_int32), ("barrier_active_cell", C.c_int32),
+        ("barrier_bags", C.c_int32), ("barrier_done", C.c_int32),
+        ("drops_total", C.c_int32), ("status", C.c_int32),
+    ]
+
+
+EXPORTS = {
+    "fps_ped_params_default": (None, [C.POINTER(PedParamsC)]),
+    "fps_workspace_bytes": (C.c_size_t, [C.POINTER(GridDescC), C.c_int32]),
+    "fps_create": (C.c_int, [C.POINTER(GridDescC), C.POINTER(PedParamsC), C.c_int32, _vp, C.c_size_t,
+                             _vp, C.POINTER(_vp)]),
+    "fps_destroy": (None, [_vp]),
+    "fps_bind_fields": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "fps_set_hydrograph": (C.c_int, [_vp, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int32]),
+    "fps_set_navigation": (C.c_int, [_vp, C.c_int32, C.c_int32, _vp, _vp]),
+    "fps_bind_agents": (C.c_int, [_vp, C.c_int32] + [_vp] * 10),
+    "fps_set_barrier": (C.c_int, [_vp, C.POINTER(C.c_int32), C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                  C.c_float, C.c_float, C.c_int32]),
+    "fps_set_time": (C.c_int, [_vp, C.c_double, C.c_int64]),
+    "fps_step": (C.c_int, [_vp, C.c_int32]),
+    "fps_get_diag": (C.c_int, [_vp, C.POINTER(DiagC)]),
+    "fps_hazard_field": (C.c_int, [_vp, _vp]),
+    "fps_get_counts": (C.c_int, [_vp, _vp]),
+    "fps_get_bins": (C.c_int, [_vp, _vp, _vp, C.POINTER(C.c_int32)]),
+    "fps_step_profiled": (C.c_int, [_vp, C.c_int32, C.POINTER(C.c_double)]),
+    "fps_status_string": (C.c_char_p, [C.c_int]),
+    "fps_last_error": (C.c_char_p, [_vp]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libfps.so; raise if it is missing (there is no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} not built: run python -m paper_1908_05232_amd.build")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+class FpsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+def grid_desc_c(d) -> GridDescC:
+    g = GridDescC()
+    g.nx, g.ny, g.dx, g.dy = d.nx, d.ny, d.dx, d.dy
+    g.g, g.cfl, g.h_dry, g.dt_max = d.g, d.cfl, d.h_dry, d.dt_max
+    for k in range(4):
+        g.bc[k] = d.bc[k]
+    g.inflow_side, g.inflow_c0, g.inflow_c1 = d.inflow_side, d.inflow_c0, d.inflow_c1
+    g.n_base, g.np_cap = d.n_base, d.np_cap
+    return g
+
+
+def ped_params_c(p) -> PedParamsC:
+    c = PedParamsC()
+    c.tau, c.a_over_m, c.b_range, c.radius, c.r_cut, c.r_arrive = (
+        p.tau, p.a_over_m, p.b_range, p.radius, p.r_cut, p.r_arrive)
+    for k in range(5):
+        c.v_class[k] = p.v_class[k]
+    for k in range(3):
+        c.hr_t[k] = p.hr_t[k]
+    c.pick_s, c.drop_s = p.pick_s, p.drop_s
+    return c
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+class Sim:
+    """One scenario on one GPU: device tensors + a libfps handle."""
+
+    def __init__(self, sc, device="cuda", stream=None, max_agents=None):
+        import torch
+        self.torch = torch
+        self.sc = sc
+        self.device = torch.device(device)
+        L = lib()
+        self._lib = L
+        d = sc.desc
+        self.desc_c = grid_desc_c(d)
+        self.ped_c = ped_params_c(sc.ped)
+        na = 0 if sc.agents is None else len(sc.agents["x"])
+        self.max_agents = na if max_agents is None else max_agents
+        nbytes = L.fps_workspace_bytes(C.byref(self.desc_c), self.max_agents)
+        if nbytes == 0:
+            raise FpsError(FPS_E_INVALID, "fps_workspace_bytes rejected the grid description")
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.ws.data_ptr()) % 256
+        self.ws_ptr = C.c_void_p(self.ws.data_ptr() + off)
+        self.ws_bytes = nbytes
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.h_ = C.c_void_p()
+        self._check(L.fps_create(C.byref(self.desc_c), C.byref(self.ped_c), self.max_agents, self.ws_ptr,
+                                 nbytes, C.c_void_p(self.stream.cuda_stream), C.byref(self.h_)), None)
+        f32 = dict(dtype=torch.float32, device=self.device)
+        self.h = torch.tensor(np.asarray(sc.h, np.float32), **f32).contiguous()
+        self.qx = torch.tensor(np.asarray(sc.qx, np.float32), **f32).contiguous()
+        self.qy = torch.tensor(np.asarray(sc.qy, np.float32), **f32).contiguous()
+        self.z = torch.tensor(np.asarray(sc.z, np.float32), **f32).contiguous()
+        self._check(L.fps_bind_fields(self.h_, _ptr(self.h), _ptr(self.qx), _ptr(self.qy), _ptr(self.z)))
+        if sc.hydro_t is not None and len(sc.hydro_t):
+            t = np.ascontiguousarray(sc.hydro_t, np.float64)
+            q = np.ascontiguousarray(sc.hydro_q, np.float64)
+            self._check(L.fps_set_hydrograph(self.h_, t.ctypes.data_as(C.POINTER(C.c_double)),
+                                             q.ctypes.data_as(C.POINTER(C.c_double)), len(t)))
+        if sc.dist is not None:
+            self.dist = torch.tensor(np.asarray(sc.dist, np.float32), **f32).contiguous()
+            self.walk = torch.tensor(np.asarray(sc.walk, np.uint8), dtype=torch.uint8,
+                                     device=self.device).contiguous()
+            self._check(L.fps_set_navigation(self.h_, self.dist.shape[0], sc.n_exit, _ptr(self.dist),
+                                             _ptr(self.walk)))
+        if sc.barrier is not None:
+            b = sc.barrier
+            cells = np.ascontiguousarray(b["cells"], np.int32)
+            self._check(L.fps_set_barrier(self.h_, cells.ctypes.data_as(C.POINTER(C.c_int32)), len(cells),
+                                          b["storage_dest"], b["barrier_dest"], b["n_layers"],
+                                          float(b["t_bag"]), float(b["t_last"]), b["bags_per"]))
+        self.na = na
+        if na:
+            A = sc.agents
+            self.agents_t = {
+                k: torch.tensor(np.asarray(A[k]), device=self.device).contiguous()
+                for k in ("x", "y", "vx", "vy", "v_base", "role", "state", "hr_class", "dest", "timer")}
+            a = self.agents_t
+            self._check(L.fps_bind_agents(self.h_, na, *[_ptr(a[k]) for k in (
+                "x", "y", "vx", "vy", "v_base", "role", "state", "hr_class", "dest", "timer")]))
+        if sc.t0:
+            self.set_time(sc.t0, 0)
+
+    # ------------------------------------------------------------------
+    def _check(self, rc, h=0):
+        if rc != FPS_OK:
+            msg = self._lib.fps_last_error(self.h_ if h == 0 else h)
+            raise FpsError(rc, (msg or b"").decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "h_", None) and self.h_.value:
+            self._lib.fps_destroy(self.h_)
+            self.h_ = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n=1):
+        return self._check(self._lib.fps_step(self.h_, int(n)))
+
+    def step_profiled(self, n):
+        ms = (C.c_double * 5)()
+        self._check(self._lib.fps_step_profiled(self.h_, int(n), ms))
+        return list(ms)
+
+    def set_time(self, t, step=0):
+        return self._check(self._lib.fps_set_time(self.h_, float(t), int(step)))
+
+    def rebind_fields(self):
+        return self._check(self._lib.fps_bind_fields(self.h_, _ptr(self.h), _ptr(self.qx), _ptr(self.qy),
+                                                     _ptr(self.z)))
+
+    def diag(self, check=True):
+        d = DiagC()
+        rc = self._lib.fps_get_diag(self.h_, C.byref(d))
+        if check:
+            self._check(rc)
+        out = {k: getattr(d, k) for k, _ in DiagC._fields_}
+        out["class_count"] = list(d.class_count)
+        out["state_count"] = list(d.state_count)
+        out["rc"] = rc
+        return out
+
+    def fields(self):
+        self.torch.cuda.synchronize(self.device)
+        return tuple(t.cpu().numpy() for t in (self.h, self.qx, self.qy, self.z))
+
+    def agents(self):
+        self.torch.cuda.synchronize(self.device)
+        return {k: v.cpu().numpy() for k, v in self.agents_t.items()}
+
+    def hazard(self):
+        out = self.torch.empty_like(self.h)
+        self._check(self._lib.fps_hazard_field(self.h_, _ptr(out)))
+        return out
+
+    def counts(self):
+        out = self.torch.empty(self.h.shape, dtype=self.torch.int32, device=self.device)
+        self._check(self._lib.fps_get_counts(self.h_, _ptr(out)))
+        return out
+
+    def bins(self):
+        nb = C.c_int32()
+        self._check(self._lib.fps_get_bins(self.h_, None, None, C.byref(nb)))
+        bs = self.torch.empty(nb.value + 1, dtype=self.torch.int32, device=self.device)
+        perm = self.torch.empty(max(self.na, 1), dtype=self.torch.int32, device=self.device)
+        self._check(self._lib.fps_get_bins(self.h_, _ptr(bs), _ptr(perm), C.byref(nb)))
+        self.torch.cuda.synchronize(self.device)
+        bs = bs.cpu().numpy()
+        return bs, perm.cpu().numpy()[: bs[-1]]

@@ -347,3 +347,18 @@ def add_barrier(sc: Scenario, seed: int, n_resp: int, height: float, t_bag: floa
     R["role"][:] = ROLE_RESPONDER
     sc.agents = concat_agents(sc.agents, R) if sc.agents is not None else R
     return sc
+
+
+def wet_probe(n: int = 8192, dx: float = 0.25, seed: int = 8192) -> Scenario:
+    """A large, fully wet grid for bandwidth measurements: a 1 m / 0.5 m dam
+    break along x over a gently varying bed, walls all round, no agents.
+    Every cell does the full flux, friction and time-step work."""
+    rng = rng_of(seed)
+    x = (np.arange(n, dtype=np.float32) + 0.5) * dx
+    z = (0.05 * np.sin(x / 7.0)).astype(np.float32)
+    z = np.broadcast_to(z[None, :], (n, n)) + (0.02 * rng.random((n, 1))).astype(np.float32)
+    h = np.where(x[None, :] < 0.5 * n * dx, 1.0, 0.5).astype(np.float32) - z
+    desc = GridDesc(nx=n, ny=n, dx=dx, dy=dx, n_base=0.02)
+    zeros = np.zeros((n, n), np.float32)
+    return Scenario(desc=desc, h=h.astype(np.float32), qx=zeros, qy=zeros.copy(),
+                    z=np.ascontiguousarray(z, np.float32), name=f"wet_probe_{n}")
