@@ -1,0 +1,120 @@
+"""Plain FP64 oracle of the convolutional flood surrogate (numpy).
+
+TEST INFRASTRUCTURE ONLY: used by the tests (and the benchmark's checks),
+never by the product path; it shares no code with the GPU kernels.
+
+The surrogate is not part of the paper: it is a learned shortcut that advances
+the flood state k finite-volume steps at once.  Network (channels-last, 3x3
+kernels, zero padding, stride 1): input planes (h, hu, hv, z, occupancy)
+scaled by fixed constants and padded with zeros to 8 channels -> 64 -> 64 ->
+64 -> 64 -> 3, ReLU after the first four layers; the three outputs are the
+scaled change of (h, hu, hv) over the k steps.  Loss: mean squared error over
+all outputs.  Optimiser: Adam (Kingma & Ba 2015) on FP32 master weights.
+
+Everything here is the definition written out with plain loops over the nine
+kernel taps and one matrix product per tap (a library primitive as a step).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+CIN0 = 8                       # first layer input channels (5 used + 3 zero)
+WIDTH = 64
+LAYERS = [(CIN0, WIDTH), (WIDTH, WIDTH), (WIDTH, WIDTH), (WIDTH, WIDTH), (WIDTH, 3)]
+# fixed input / output scales: h, hu, hv, z, occupancy  ->  O(1) values
+IN_SCALE = np.array([1.0, 1.0, 1.0, 1.0 / 3.0, 0.25, 0.0, 0.0, 0.0])
+OUT_SCALE = np.array([0.05, 0.05, 0.05])     # scaled change of (h, hu, hv) over k steps
+
+
+def init_params(seed: int = 0):
+    """He-normal weights [cout][3][3][cin] and zero biases, FP64."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    params = []
+    for cin, cout in LAYERS:
+        std = np.sqrt(2.0 / (9 * cin))
+        w = rng.normal(0.0, std, size=(cout, 3, 3, cin))
+        if cin == CIN0:
+            w[..., 5:] = 0.0
+        params.append((w, np.zeros(cout)))
+    return params
+
+
+def conv3x3(x, w, b):
+    """y[n, i, j, o] = b[o] + sum_{dy, dx, c} w[o, dy, dx, c] x[n, i+dy-1, j+dx-1, c],
+    zero outside the image.  x: [N, H, W, Cin], w: [Cout, 3, 3, Cin]."""
+    N, H, W, Ci = x.shape
+    xp = np.zeros((N, H + 2, W + 2, Ci))
+    xp[:, 1:-1, 1:-1, :] = x
+    y = np.zeros((N, H, W, w.shape[0])) + b
+    for dy in range(3):
+        for dx in range(3):
+            y += xp[:, dy:dy + H, dx:dx + W, :] @ w[:, dy, dx, :].T
+    return y
+
+
+def conv3x3_backward(x, w, dy):
+    """Gradients of conv3x3 with respect to x, w and b for upstream dy."""
+    N, H, W, Ci = x.shape
+    xp = np.zeros((N, H + 2, W + 2, Ci))
+    xp[:, 1:-1, 1:-1, :] = x
+    dxp = np.zeros_like(xp)
+    dw = np.zeros_like(w)
+    for ky in range(3):
+        for kx in range(3):
+            patch = xp[:, ky:ky + H, kx:kx + W, :]
+            dw[:, ky, kx, :] = np.einsum("nhwo,nhwc->oc", dy, patch)
+            dxp[:, ky:ky + H, kx:kx + W, :] += dy @ w[:, ky, kx, :]
+    db = dy.sum(axis=(0, 1, 2))
+    return dxp[:, 1:-1, 1:-1, :], dw, db
+
+
+def forward(params, x):
+    """Returns the output and the per-layer inputs / pre-activations."""
+    acts, pres = [], []
+    a = x
+    for li, (w, b) in enumerate(params):
+        acts.append(a)
+        z = conv3x3(a, w, b)
+        pres.append(z)
+        a = np.maximum(z, 0.0) if li < len(params) - 1 else z
+    return a, acts, pres
+
+
+def loss_and_grads(params, x, target):
+    """MSE loss over all outputs and its gradients (list of (dw, db))."""
+    y, acts, pres = forward(params, x)
+    diff = y - target
+    loss = float(np.mean(diff * diff))
+    g = 2.0 * diff / diff.size
+    grads = [None] * len(params)
+    for li in range(len(params) - 1, -1, -1):
+        w, _ = params[li]
+        if li < len(params) - 1:
+            g = g * (pres[li] > 0.0)
+        dxl, dw, db = conv3x3_backward(acts[li], w, g)
+        grads[li] = (dw, db)
+        g = dxl
+    return loss, grads
+
+
+def adam_update(param, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam step (bias-corrected), returns (param, m, v)."""
+    m = beta1 * m + (1.0 - beta1) * grad
+    v = beta2 * v + (1.0 - beta2) * grad * grad
+    mhat = m / (1.0 - beta1 ** step)
+    vhat = v / (1.0 - beta2 ** step)
+    return param - lr * mhat / (np.sqrt(vhat) + eps), m, v
+
+
+def pack_input(h, hu, hv, z, occ):
+    """Scaled channels-last input [H, W, 8] from the state planes."""
+    x = np.zeros(h.shape + (CIN0,))
+    for c, plane in enumerate((h, hu, hv, z, occ)):
+        x[..., c] = plane * IN_SCALE[c]
+    return x
+
+
+def apply_output(h, hu, hv, y):
+    """State after the surrogate call: U + OUT_SCALE * y, depth kept >= 0."""
+    hn = np.maximum(h + OUT_SCALE[0] * y[..., 0], 0.0)
+    return hn, hu + OUT_SCALE[1] * y[..., 1], hv + OUT_SCALE[2] * y[..., 2]
