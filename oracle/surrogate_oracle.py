@@ -6,7 +6,7 @@ never by the product path; it shares no code with the GPU kernels.
 The surrogate is not part of the paper: it is a learned shortcut that advances
 the flood state k finite-volume steps at once.  Network (channels-last, 3x3
 kernels, zero padding, stride 1): input planes (h, hu, hv, z, occupancy)
-scaled by fixed constants and padded with zeros to 8 channels -> 64 -> 64 ->
+scaled by fixed constants and padded with zeros to 16 channels -> 64 -> 64 ->
 64 -> 64 -> 3, ReLU after the first four layers; the three outputs are the
 scaled change of (h, hu, hv) over the k steps.  Loss: mean squared error over
 all outputs.  Optimiser: Adam (Kingma & Ba 2015) on FP32 master weights.
@@ -18,11 +18,11 @@ from __future__ import annotations
 
 import numpy as np
 
-CIN0 = 8                       # first layer input channels (5 used + 3 zero)
+CIN0 = 16                      # first layer input channels (5 used + 11 zero)
 WIDTH = 64
 LAYERS = [(CIN0, WIDTH), (WIDTH, WIDTH), (WIDTH, WIDTH), (WIDTH, WIDTH), (WIDTH, 3)]
 # fixed input / output scales: h, hu, hv, z, occupancy  ->  O(1) values
-IN_SCALE = np.array([1.0, 1.0, 1.0, 1.0 / 3.0, 0.25, 0.0, 0.0, 0.0])
+IN_SCALE = np.array([1.0, 1.0, 1.0, 1.0 / 3.0, 0.25] + [0.0] * 11)
 OUT_SCALE = np.array([0.05, 0.05, 0.05])     # scaled change of (h, hu, hv) over k steps
 
 
@@ -107,14 +107,59 @@ def adam_update(param, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
 
 
 def pack_input(h, hu, hv, z, occ):
-    """Scaled channels-last input [H, W, 8] from the state planes."""
+    """Scaled channels-last input [H, W, 16] from the state planes."""
     x = np.zeros(h.shape + (CIN0,))
     for c, plane in enumerate((h, hu, hv, z, occ)):
         x[..., c] = plane * IN_SCALE[c]
     return x
 
 
-def apply_output(h, hu, hv, y):
-    """State after the surrogate call: U + OUT_SCALE * y, depth kept >= 0."""
+def make_target(h0, hu0, hv0, h1, hu1, hv1):
+    """Training target [H, W, 3]: the change of (h, hu, hv) over the k steps
+    divided by OUT_SCALE."""
+    return np.stack([(h1 - h0) / OUT_SCALE[0], (hu1 - hu0) / OUT_SCALE[1],
+                     (hv1 - hv0) / OUT_SCALE[2]], axis=-1)
+
+
+def apply_output(h, hu, hv, y, h_dry=1e-5):
+    """State after the surrogate call: U + OUT_SCALE * y, depth kept >= 0 and
+    no discharge in cells left dry (h <= h_dry), as in the flood update."""
     hn = np.maximum(h + OUT_SCALE[0] * y[..., 0], 0.0)
-    return hn, hu + OUT_SCALE[1] * y[..., 1], hv + OUT_SCALE[2] * y[..., 2]
+    wet = hn > h_dry
+    qx = np.where(wet, hu + OUT_SCALE[1] * y[..., 1], 0.0)
+    qy = np.where(wet, hv + OUT_SCALE[2] * y[..., 2], 0.0)
+    return hn, qx, qy
+
+
+def hazard_class32(h, qx, qy, h_dry, thr):
+    """Hazard class of Table 1 (0 dry, 1 low .. 4 highest) from float32 states,
+    decided in float32: HR = (max(|u|, |v|) + 0.5) h against the thresholds."""
+    h = np.asarray(h, np.float32)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        u = np.asarray(qx, np.float32) / h
+        v = np.asarray(qy, np.float32) / h
+        hr = (np.maximum(np.abs(u), np.abs(v)) + np.float32(0.5)) * h
+    t = [np.float32(x) for x in thr]
+    cls = np.where(hr < t[0], 1, np.where(hr < t[1], 2, np.where(hr < t[2], 3, 4)))
+    return np.where(h > np.float32(h_dry), cls, 0)
+
+
+def judge(x, y, state, nx, ny, dx, dy, a, b, tol, h_dry, thr, exited=1):
+    """Judge of a surrogate flood state a = (h, qx, qy) against a
+    finite-volume state b at the cells of the agents still in the domain:
+    returns (agents whose depth differs by more than tol or whose hazard
+    class differs, largest depth difference).  Cells: floor(x / dx) in
+    float32, clamped to the grid."""
+    x = np.asarray(x, np.float32)
+    y = np.asarray(y, np.float32)
+    keep = np.asarray(state) != exited
+    i = np.clip(np.floor(x / np.float32(dx)), 0, nx - 1).astype(np.int64)[keep]
+    j = np.clip(np.floor(y / np.float32(dy)), 0, ny - 1).astype(np.int64)[keep]
+    if i.size == 0:
+        return 0, 0.0
+    ha, qxa, qya = (np.asarray(f, np.float32)[j, i] for f in a)
+    hb, qxb, qyb = (np.asarray(f, np.float32)[j, i] for f in b)
+    d = np.abs(ha - hb)
+    bad = (d > np.float32(tol)) | (hazard_class32(ha, qxa, qya, h_dry, thr)
+                                    != hazard_class32(hb, qxb, qyb, h_dry, thr))
+    return int(bad.sum()), float(d.max())

@@ -71,3 +71,56 @@ def test_pack_and_apply():
     assert np.allclose(x[..., 3], z / 3.0) and np.all(x[..., 5:] == 0)
     hn, qun, qvn = S.apply_output(h, hu, hv, np.zeros((3, 4, 3)))
     assert np.array_equal(hn, h) and np.array_equal(qun, hu) and np.array_equal(qvn, hv)
+
+
+def test_apply_output_zeroes_discharge_where_dry():
+    h = np.array([[0.5, 0.02]])
+    hu = np.array([[0.1, 0.3]])
+    hv = np.array([[-0.2, 0.1]])
+    y = np.zeros((1, 2, 3))
+    y[0, 1, 0] = -1.0                      # 0.02 - 0.05 -> dry
+    hn, qx, qy = S.apply_output(h, hu, hv, y)
+    assert hn[0, 1] == 0.0 and qx[0, 1] == 0.0 and qy[0, 1] == 0.0
+    assert hn[0, 0] == 0.5 and qx[0, 0] == 0.1 and qy[0, 0] == -0.2
+
+
+def test_make_target_inverts_apply_output():
+    rng = np.random.default_rng(4)
+    h0, hu0, hv0 = (rng.uniform(0.1, 1, (5, 6)) for _ in range(3))
+    h1, hu1, hv1 = (a + rng.uniform(-0.05, 0.05, a.shape) for a in (h0, hu0, hv0))
+    t = S.make_target(h0, hu0, hv0, h1, hu1, hv1)
+    for got, want in zip(S.apply_output(h0, hu0, hv0, t), (h1, hu1, hv1)):
+        assert np.allclose(got, want, rtol=0, atol=1e-14)
+
+
+def test_hazard_class_thresholds_table1():
+    thr = (0.75, 1.5, 2.5)
+    # HR = (|u| + 0.5) h: h = 1 m still water -> 0.5 (low); u = 0.5 -> 1.0 (medium);
+    # u = 1.5 -> 2.0 (high); u = 2.0 -> 2.5 (highest: the bound is exclusive)
+    h = np.ones(5, np.float32)
+    q = np.array([0.0, 0.5, 1.5, 2.0, -2.0], np.float32)
+    assert list(S.hazard_class32(h, q, 0 * q, 1e-5, thr)) == [1, 2, 3, 4, 4]
+    assert list(S.hazard_class32(h, 0 * q, q, 1e-5, thr)) == [1, 2, 3, 4, 4]
+    assert S.hazard_class32(np.float32(1e-6), np.float32(5.0), np.float32(0), 1e-5, thr) == 0
+
+
+def test_judge_counts_by_hand():
+    thr = (0.75, 1.5, 2.5)
+    nx, ny, dx, dy = 4, 3, 2.0, 2.0
+    hb = np.full((ny, nx), 0.5, np.float32)
+    qb = np.zeros((ny, nx), np.float32)
+    ha = hb.copy()
+    ha[0, 0] = 0.505                       # within 1 cm, same class: fine
+    ha[1, 2] = 0.52                        # 2 cm off: bad
+    qa = qb.copy()
+    qa[2, 3] = 0.6                         # same depth, HR 0.25 -> 0.85: class changes
+    # agents: one per altered cell, one exited on the bad cell, one outside (clamped)
+    x = np.array([1.0, 5.0, 7.9, 5.5, -3.0, 100.0], np.float32)
+    y = np.array([1.0, 3.0, 5.0, 3.5, 1.0, 100.0], np.float32)
+    st = np.array([0, 0, 0, 1, 0, 0], np.uint8)
+    n, dmax = S.judge(x, y, st, nx, ny, dx, dy, (ha, qa, qb), (hb, qb, qb), 0.01, 1e-5, thr)
+    # bad: agent 1 (cell (2,1)), agent 2 (cell (3,2)), agent 5 (clamped to (3,2))
+    assert n == 3
+    assert dmax == np.float32(0.52) - np.float32(0.5)
+    same = S.judge(x, y, st, nx, ny, dx, dy, (hb, qb, qb), (hb, qb, qb), 0.01, 1e-5, thr)
+    assert same == (0, 0.0)
