@@ -95,6 +95,7 @@ def main():
     cells = sc.desc.nx * sc.desc.ny
     stream = torch.cuda.current_stream()
     sim = fps.Sim(sc, stream=stream)
+    rows, _ = sim.autotune()          # flood-update tile shape for this grid
 
     sim.step(args.warmup)
     torch.cuda.synchronize()
@@ -122,11 +123,13 @@ def main():
         big = I.wet_probe(args.probe_n)
         bsim = fps.Sim(big, stream=stream)
         del big
+        brows, _ = bsim.autotune()
         bsim.step(4)
         bk = bsim.step_profiled(args.probe_steps)
         bcells = args.probe_n * args.probe_n
         bach = FV_BYTES_PER_CELL * bcells / (bk[0] * 1e-3) / 1e9
         probe = {"workload": f"wet_probe_{args.probe_n} (fully wet dam break, {bcells} cells)",
+                 "rows_per_wave": brows,
                  "ms_per_launch": bk[0], "cell_updates_per_s": bcells / (bk[0] * 1e-3),
                  "achieved_GBs": bach, "frac": bach / HBM_PEAK_GBS,
                  "working_set_MB": (FV_BYTES_PER_CELL + 12) * bcells / 1e6}
@@ -147,7 +150,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": workload, "cells": cells, "dx_m": sc.desc.dx,
+        "config": {"workload": workload, "cells": cells, "dx_m": sc.desc.dx, "rows_per_wave": rows,
                    "evacuees": len(sc.agents["x"]), "steps_timed": args.steps,
                    "sim_time_s": [d0["t"], d1["t"]]},
         "secondary": {"ped-steps/s": ped_rate,

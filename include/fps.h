@@ -103,9 +103,12 @@ typedef struct {
     int32_t barrier_layers_done, barrier_active_cell, barrier_bags, barrier_done;
     int32_t drops_total;     /* sandbags delivered */
     int32_t status;          /* FPS_OK or the latched fault */
+    int32_t active;          /* 0 once the end time (fps_set_end_time) is reached */
+    int32_t flood_steps;     /* steps whose flood update ran; the others were dry and skipped */
 } fps_diag;
 
 typedef struct fps_sim fps_sim;
+typedef struct fps_ens fps_ens;
 
 /* Default pedestrian constants (see fps_ped_params). */
 void fps_ped_params_default(fps_ped_params* out);
@@ -166,8 +169,20 @@ int fps_set_time(fps_sim* sim, double t, int64_t step);
 
 /* Advance n_steps coupled steps (sec. 2.4 order: flood update Eq. (2), then
    pedestrians read the new flood state and move, then roughness and bed
-   write-back).  Asynchronous; no host synchronisation inside. */
+   write-back).  Asynchronous; no host synchronisation inside.  A step in
+   which nothing is wet and no inflow enters uses the 1 s dry step of sec. 3
+   and skips the flood update (it would leave the state unchanged).  Steps
+   are replayed from a captured HIP graph in chunks (fps_set_graph).
+   FPS_E_STATE for a member of an ensemble (step the ensemble instead). */
 int fps_step(fps_sim* sim, int32_t n_steps);
+
+/* Stop advancing this scenario once its time reaches t_end (<= 0: never);
+   further steps leave it unchanged.  Synchronises. */
+int fps_set_end_time(fps_sim* sim, double t_end);
+
+/* Steps per captured HIP graph for fps_step (0 = launch every step
+   eagerly); calls with fewer steps run eagerly.  Results are identical. */
+int fps_set_graph(fps_sim* sim, int32_t steps_per_graph);
 
 /* Synchronise the stream and report diagnostics (sec. 3.2 statistics). */
 int fps_get_diag(fps_sim* sim, fps_diag* out);
@@ -188,6 +203,101 @@ int fps_get_bins(fps_sim* sim, int32_t* bin_start, int32_t* perm, int32_t* nbins
    {flood update, pedestrian step, end-of-step finalize (reductions, barrier, bin scan), bin place, bin sort}; ms_out[5]
    (host).  Synchronises. */
 int fps_step_profiled(fps_sim* sim, int32_t n_steps, double* ms_out);
+
+/* Tile shape of the flood update: rows each wave marches through (a power of
+   two in [1, 64]); every choice gives the same flood state, only the FP64
+   mass diagnostic's summation order changes.  Synchronises. */
+int fps_set_rows_per_wave(fps_sim* sim, int32_t rows);
+
+/* Pick the rows per wave for this grid by timing the flood update on the
+   bound state (outputs to scratch; the simulation state is not advanced).
+   cache_path (host string, may be NULL): a text file of lines
+   "<gfx arch> <nx> <ny> <rows> <ms>"; a matching line is used instead of
+   timing, a new result is appended.  rows_out / ms_out may be NULL. */
+int fps_autotune(fps_sim* sim, const char* cache_path, int32_t* rows_out, double* ms_out);
+
+/* ---- Ensembles: S scenarios of uneven grids stepped by one set of launches
+   per step (one flood launch over the tiles of every scenario, one
+   pedestrian launch over every agent, one end-of-step launch with a block per
+   scenario), each scenario with its own time, time step and end time.  The
+   sweep structure follows sec. 3.3 (responder counts x barrier heights). ---- */
+
+/* Workspace bytes for S scenarios (descs[S], max_agents[S] may be NULL = 0). */
+size_t fps_ens_workspace_bytes(int32_t S, const fps_grid_desc* descs, const int32_t* max_agents);
+
+/* Create an ensemble over one caller workspace; peds may be NULL (defaults)
+   or point to S records.  Scenario s is configured through the member handle
+   fps_ens_member(ens, s) with the same calls as a single simulation (bind
+   fields, hydrograph, navigation, agents, barrier, end time, diagnostics). */
+int fps_ens_create(int32_t S, const fps_grid_desc* descs, const fps_ped_params* peds,
+                   const int32_t* max_agents, void* ws, size_t ws_bytes, void* stream,
+                   fps_ens** out);
+void fps_ens_destroy(fps_ens* ens);
+/* Member handle of scenario s (owned by the ensemble; NULL if out of range). */
+fps_sim* fps_ens_member(fps_ens* ens, int32_t s);
+/* Advance every active scenario by n_steps of its own time step; asynchronous. */
+int fps_ens_step(fps_ens* ens, int32_t n_steps);
+/* As fps_step_profiled, for the whole ensemble. */
+int fps_ens_step_profiled(fps_ens* ens, int32_t n_steps, double* ms_out);
+/* Steps per captured HIP graph (0 = eager). */
+int fps_ens_set_graph(fps_ens* ens, int32_t steps_per_graph);
+/* Tile shape per scenario, tuned once per distinct grid size (see fps_autotune). */
+int fps_ens_autotune(fps_ens* ens, const char* cache_path);
+/* Number of scenarios that have not reached their end time.  Synchronises. */
+int fps_ens_active(fps_ens* ens, int32_t* n_active);
+const char* fps_ens_last_error(const fps_ens* ens);
+
+/* ---- Convolutional surrogate (not part of the paper): five 3x3 convolutions,
+   16 -> 64 -> 64 -> 64 -> 64 -> 3 channels, ReLU between, BF16 weights and
+   activations with FP32 accumulation on the matrix cores, FP32 master
+   weights and Adam.  It maps the scaled state (h, hu, hv, z, occupancy) to
+   the scaled change of (h, hu, hv) over k finite-volume steps.  Tensors are
+   channels last: x bf16 [n][H][W][16] (channels 5..15 zero), outputs and
+   targets fp32 [n][H][W][4] (channel 3 zero).  H a multiple of 8, W of 32. ---- */
+typedef struct fps_sur fps_sur;
+
+/* Number of packed FP32 parameters: per layer W[cout][3][3][cin] then b[cout],
+   with the padded channel counts (16 inputs, 16 outputs in the last layer). */
+int32_t fps_sur_param_count(void);
+size_t fps_sur_workspace_bytes(int32_t max_batch, int32_t H, int32_t W);
+int fps_sur_create(int32_t max_batch, int32_t H, int32_t W, void* ws, size_t ws_bytes, void* stream,
+                   fps_sur** out);
+void fps_sur_destroy(fps_sur* sur);
+/* Copy packed FP32 parameters (device) into the master weights; clears Adam. */
+int fps_sur_set_params(fps_sur* sur, const float* params);
+int fps_sur_get_params(fps_sur* sur, float* params);
+/* y = net(x) for n <= max_batch images (device pointers). */
+int fps_sur_forward(fps_sur* sur, int32_t n, const void* x_bf16, float* y);
+/* Mean squared error against target and its gradients (packed like the
+   parameters; grads may be NULL); loss: one device float. */
+int fps_sur_gradients(fps_sur* sur, int32_t n, const void* x_bf16, const float* target, float* grads,
+                      float* loss);
+/* One Adam step with the last gradients (beta 0.9 / 0.999, eps 1e-8). */
+int fps_sur_adam(fps_sur* sur, float lr);
+/* fps_sur_gradients then fps_sur_adam. */
+int fps_sur_train_step(fps_sur* sur, int32_t n, const void* x_bf16, const float* target, float lr,
+                       float* loss);
+/* Network input from a flood state (device float32 [H][W] planes; occupancy:
+   evacuee counts per cell, may be NULL) into x bf16 [H][W][16]; async. */
+int fps_sur_pack(int64_t npix, const float* h, const float* hu, const float* hv, const float* z,
+                 const int32_t* occupancy, void* x_bf16, void* stream);
+/* Training target: the scaled change (U1 - U0) / scale into fp32 [H][W][4]; async. */
+int fps_sur_make_target(int64_t npix, const float* h0, const float* hu0, const float* hv0,
+                        const float* h1, const float* hu1, const float* hv1, float* target, void* stream);
+/* Apply a network output to a flood state in place: U += scale * y, h >= 0,
+   no discharge where h <= h_dry; async.  (Rebind the fields of a simulation
+   afterwards so its next time step is recomputed.) */
+int fps_sur_apply(int64_t npix, const float* y, float* h, float* hu, float* hv, float h_dry, void* stream);
+/* Judge of a surrogate state (a) against a finite-volume state (b) at the
+   cells of the non-exited agents (x, y, state: device SoA of length na):
+   out2[0] = agents whose depth differs by more than tol (m) or whose hazard
+   class (Table 1; thresholds hr_thresholds[3], host) differs; out2[1] = the
+   largest depth difference as float bits.  out2: device int32[2]; async. */
+int fps_sur_judge(int32_t na, const float* x, const float* y, const uint8_t* state, int32_t nx, int32_t ny,
+                  double dx, double dy, const float* ha, const float* qxa, const float* qya,
+                  const float* hb, const float* qxb, const float* qyb, double tol, double h_dry,
+                  const double* hr_thresholds, int32_t* out2, void* stream);
+const char* fps_sur_last_error(const fps_sur* sur);
 
 const char* fps_status_string(int status);
 /* Last error message of this handle (or of the last failed fps_create when sim is NULL). */

@@ -1,21 +1,32 @@
-// C-ABI of libfps (declared in include/fps.h): handle, workspace carving,
-// argument validation and the stream-ordered step loop.
+// C-ABI of libfps (declared in include/fps.h): handles, workspace carving,
+// argument validation, parameter upload and the stream-ordered step loop.
+//
+// An Engine runs S scenarios with one set of launches per step (see the
+// kernels' Batch).  fps_create makes an engine of one scenario and returns its
+// member handle; fps_ens_create makes an engine of S members.  The step's
+// launches take the same arguments every step (parities, time steps and
+// activity live on the device), so chunks of steps are captured once in a HIP
+// graph and replayed on an internal stream ordered after the caller's stream.
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "fps_internal.h"
 
 using namespace fps;
 
+struct Engine;
+
 struct fps_sim {
+    Engine* eng;
+    int idx;
     fps_grid_desc G;
     fps_ped_params P;
     int32_t max_agents;
-    hipStream_t stream;
     char err[512];
     // workspace carve
     DevState* st;
@@ -26,13 +37,14 @@ struct fps_sim {
     float2* xy;
     int32_t* slot;
     uint4* wmask;
-    bool use_wmask;
     int32_t* line;
     int32_t* stats;
     int32_t line_cap;
-    int H, nblocks_fv;
+    int H;
     int nbins, bsx, bsy, nbx, nby, Rx, Ry;
     int n_inflow;
+    bool use_wmask;
+    double t_end;
     // bound caller memory
     float *h, *qx, *qy, *z;
     bool fields_bound;
@@ -49,18 +61,56 @@ struct fps_sim {
     bool numeric_fault;
 };
 
+struct Engine {
+    int S = 0;
+    bool standalone = false;
+    hipStream_t stream = nullptr;   // the caller's stream
+    hipStream_t cap = nullptr;      // internal stream for graph capture and replay
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    std::vector<fps_sim*> m;
+    Scn* scn_d = nullptr;
+    int* tile_off_d = nullptr;
+    int* agent_off_d = nullptr;
+    std::vector<Scn> scn_h;
+    std::vector<int> tile_off_h, agent_off_h;
+    int total_tiles = 0, total_agents = 0, fv_blocks = 0;
+    int64_t max_cells = 0;
+    bool any_big = false;
+    bool dirty = true;
+    int graph_chunk = 16;
+    hipGraphExec_t exec = nullptr;
+    int exec_steps = 0;
+    char err[512] = "";
+};
+
+struct fps_ens : Engine {};
+
 namespace {
 
 char g_err[512] = "";
 
+int failv(char* buf, int code, const char* fmt, va_list ap)
+{
+    vsnprintf(buf, 512, fmt, ap);
+    return code;
+}
+
 int fail(fps_sim* s, int code, const char* fmt, ...)
 {
-    char* buf = s ? s->err : g_err;
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(buf, 512, fmt, ap);
+    int r = failv(s ? s->err : g_err, code, fmt, ap);
     va_end(ap);
-    return code;
+    return r;
+}
+
+int efail(Engine* e, int code, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    int r = failv(e ? e->err : g_err, code, fmt, ap);
+    va_end(ap);
+    return r;
 }
 
 #define HIPCHK(sim, expr)                                                                  \
@@ -70,13 +120,20 @@ int fail(fps_sim* s, int code, const char* fmt, ...)
             return fail(sim, FPS_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
+#define HIPCHK_E(eng, expr)                                                                 \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return efail(eng, FPS_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 bool valid_desc(const fps_grid_desc* d, char* why)
 {
     if (!d) return (snprintf(why, 256, "desc is NULL"), false);
     if (d->nx < 1 || d->ny < 1) return (snprintf(why, 256, "nx, ny must be >= 1"), false);
-    if ((int64_t)d->nx * d->ny > (int64_t)1 << 31) return (snprintf(why, 256, "grid too large"), false);
+    if ((int64_t)d->nx * d->ny > (int64_t)1 << 30) return (snprintf(why, 256, "grid too large"), false);
     if (!(d->dx > 0) || !(d->dy > 0) || !std::isfinite(d->dx) || !std::isfinite(d->dy))
         return (snprintf(why, 256, "dx, dy must be finite and > 0"), false);
     if (!(d->g > 0) || !(d->cfl > 0 && d->cfl <= 1.0) || !(d->h_dry > 0) || !(d->dt_max > 0))
@@ -94,20 +151,18 @@ bool valid_desc(const fps_grid_desc* d, char* why)
     return true;
 }
 
+// Per-scenario part of the workspace (offsets from the member's base).
 struct Layout {
     size_t st, partials, h2, qx2, qy2, np, bin_count, bin_start, rank, key, perm_u, perm, xy, slot,
         wmask, line, stats, total;
-    int nblocks, H;
     int64_t nbins_max;
     int32_t line_cap;
 };
 
-Layout make_layout(const fps_grid_desc* d, int32_t max_agents)
+Layout member_layout(const fps_grid_desc* d, int32_t max_agents)
 {
     Layout L{};
     const int64_t nc = (int64_t)d->nx * d->ny;
-    L.H = fv_rows_per_wave(d->nx, d->ny);
-    L.nblocks = fv_blocks(d->nx, d->ny, L.H);
     L.nbins_max = nc;   // bins are whole cells, at least one cell wide
     L.line_cap = 2 * (d->nx + d->ny);
     size_t o = 0;
@@ -116,13 +171,13 @@ Layout make_layout(const fps_grid_desc* d, int32_t max_agents)
         o = align256(o + bytes);
         return at;
     };
+    const size_t na = (size_t)std::max(max_agents, 0);
     L.st = take(sizeof(DevState));
-    L.partials = take(sizeof(double) * 4 * (size_t)L.nblocks);
+    L.partials = take(sizeof(double) * 4 * (size_t)fv_tiles(d->nx, d->ny, 1));
     L.h2 = take(sizeof(float) * nc);
     L.qx2 = take(sizeof(float) * nc);
     L.qy2 = take(sizeof(float) * nc);
     L.np = take(sizeof(int32_t) * nc);
-    size_t na = (size_t)std::max(max_agents, 0);
     L.bin_count = take(max_agents > 0 ? sizeof(int32_t) * L.nbins_max : 0);
     L.bin_start = take(max_agents > 0 ? sizeof(int32_t) * (L.nbins_max + 1) : 0);
     L.rank = take(sizeof(int32_t) * na);
@@ -138,119 +193,224 @@ Layout make_layout(const fps_grid_desc* d, int32_t max_agents)
     return L;
 }
 
+size_t engine_header_bytes(int S)
+{
+    return align256(sizeof(Scn) * S) + align256(sizeof(int) * (S + 1)) * 2;
+}
+
 template <class T>
 T* at(void* base, size_t off) { return reinterpret_cast<T*>(static_cast<char*>(base) + off); }
 
-FvParams fv_params(const fps_sim* s, int mode, const float* h, const float* qx, const float* qy,
-                   float* ho, float* qxo, float* qyo)
+// carve one member from its part of the workspace; nothing touches the device
+fps_sim* new_member(Engine* e, int idx, const fps_grid_desc* d, const fps_ped_params& P,
+                    int32_t max_agents, void* base)
 {
-    FvParams p{};
-    p.h = h; p.qx = qx; p.qy = qy;
-    p.ho = ho; p.qxo = qxo; p.qyo = qyo;
+    fps_sim* s = new (std::nothrow) fps_sim();
+    if (!s) return nullptr;
+    Layout L = member_layout(d, max_agents);
+    s->eng = e;
+    s->idx = idx;
+    s->G = *d;
+    s->P = P;
+    s->max_agents = max_agents;
+    s->st = at<DevState>(base, L.st);
+    s->partials = at<double>(base, L.partials);
+    s->h2 = at<float>(base, L.h2);
+    s->qx2 = at<float>(base, L.qx2);
+    s->qy2 = at<float>(base, L.qy2);
+    s->np = at<int32_t>(base, L.np);
+    s->bin_count = at<int32_t>(base, L.bin_count);
+    s->bin_start = at<int32_t>(base, L.bin_start);
+    s->rank = at<int32_t>(base, L.rank);
+    s->key = at<int32_t>(base, L.key);
+    s->perm_u = at<int32_t>(base, L.perm_u);
+    s->perm = at<int32_t>(base, L.perm);
+    s->xy = at<float2>(base, L.xy);
+    s->slot = at<int32_t>(base, L.slot);
+    s->wmask = at<uint4>(base, L.wmask);
+    s->line = at<int32_t>(base, L.line);
+    s->stats = at<int32_t>(base, L.stats);
+    s->line_cap = L.line_cap;
+    s->H = fv_rows_per_wave(d->nx, d->ny);
+    s->bsx = std::max(1, (int)std::ceil(P.r_cut / d->dx - 1e-9));
+    s->bsy = std::max(1, (int)std::ceil(P.r_cut / d->dy - 1e-9));
+    s->nbx = (d->nx + s->bsx - 1) / s->bsx;
+    s->nby = (d->ny + s->bsy - 1) / s->bsy;
+    s->nbins = s->nbx * s->nby;
+    s->Rx = s->bsx;
+    s->Ry = s->bsy;
+    s->n_inflow = d->inflow_side >= 0 ? d->inflow_c1 - d->inflow_c0 : 0;
+    s->storage_dest = s->barrier_dest = -1;
+    s->t_end = 0.0;
+    return s;
+}
+
+// zero the member's device state and scratch counters (at creation)
+int init_member_device(fps_sim* s)
+{
+    DevState h0{};
+    h0.dt = (float)s->G.dt_max;
+    h0.dt_prev = (float)s->G.dt_max;
+    h0.active = 1;
+    hipStream_t st = s->eng->stream;
+    HIPCHK(s, hipMemcpyAsync(s->st, &h0, sizeof(h0), hipMemcpyHostToDevice, st));
+    HIPCHK(s, launch_fill_i32(s->np, 0, (int64_t)s->G.nx * s->G.ny, st));
+    if (s->max_agents > 0)
+        HIPCHK(s, launch_fill_i32(s->bin_count, 0, (int64_t)s->G.nx * s->G.ny, st));
+    HIPCHK(s, hipStreamSynchronize(st));
+    return FPS_OK;
+}
+
+void fill_scn(const fps_sim* s, Scn& c)
+{
+    c = Scn{};
+    FvParams& p = c.fv;
+    p.h[0] = s->h; p.h[1] = s->h2;
+    p.qx[0] = s->qx; p.qx[1] = s->qx2;
+    p.qy[0] = s->qy; p.qy[1] = s->qy2;
     p.z = s->z;
     p.np = s->np;
     p.st = s->st;
     p.partials = s->partials;
     p.nx = s->G.nx; p.ny = s->G.ny; p.H = s->H;
     p.nsx = (s->G.nx + kStrip - 1) / kStrip;
-    p.ntiles = p.nsx * ((s->G.ny + s->H - 1) / s->H);
-    p.nblocks = s->nblocks_fv;
+    p.ntiles = fv_tiles(s->G.nx, s->G.ny, s->H);
     for (int k = 0; k < 4; ++k) p.bc[k] = s->G.bc[k];
     p.inflow_side = s->G.inflow_side;
     p.c0 = s->G.inflow_c0;
     p.c1 = s->G.inflow_c1;
     p.n_inflow = s->n_inflow;
     p.np_cap = s->G.np_cap;
-    p.mode = mode;
     p.dx = (float)s->G.dx; p.dy = (float)s->G.dy;
     p.inv_dx = (float)(1.0 / s->G.dx); p.inv_dy = (float)(1.0 / s->G.dy);
     p.g = (float)s->G.g; p.half_g = (float)(0.5 * s->G.g);
     p.eps = (float)s->G.h_dry; p.cfl = (float)s->G.cfl; p.dt_max = (float)s->G.dt_max;
     p.n_base = (float)s->G.n_base;
     p.dxdy = s->G.dx * s->G.dy;
-    return p;
-}
 
-PedParams ped_params(const fps_sim* s, const float* h, const float* qx, const float* qy)
-{
-    PedParams p{};
-    p.x = s->x; p.y = s->y; p.vx = s->vx; p.vy = s->vy; p.vbase = s->vbase;
-    p.role = s->role; p.state = s->state; p.cls = s->cls; p.dest = s->dest; p.timer = s->timer;
-    p.na = s->na;
-    p.h = h; p.qx = qx; p.qy = qy;
-    p.z = s->z;
-    p.np = s->np;
-    p.dist = s->dist; p.walk = s->walk; p.n_dest = s->n_dest; p.n_exit = s->n_exit;
-    p.bin_start = s->bin_start; p.xy = s->xy; p.slot = s->slot; p.wmask = s->wmask;
-    p.use_wmask = s->use_wmask;
-    p.bin_count = s->bin_count; p.rank = s->rank; p.key = s->key;
-    p.st = s->st;
-    p.nx = s->G.nx; p.ny = s->G.ny;
-    p.bsx = s->bsx; p.bsy = s->bsy; p.nbx = s->nbx; p.nby = s->nby; p.Rx = s->Rx; p.Ry = s->Ry;
-    p.nblocks = (s->na + kPedBlock - 1) / kPedBlock;
-    p.dx = (float)s->G.dx; p.dy = (float)s->G.dy; p.eps = (float)s->G.h_dry;
-    p.tau = (float)s->P.tau; p.a_over_m = (float)s->P.a_over_m; p.inv_b = (float)(1.0 / s->P.b_range);
-    p.two_r = (float)(2.0 * s->P.radius); p.radius = (float)s->P.radius;
-    p.r_cut = (float)s->P.r_cut; p.r_arrive = (float)s->P.r_arrive;
-    for (int k = 0; k < 5; ++k) p.v_class[k] = (float)s->P.v_class[k];
-    for (int k = 0; k < 3; ++k) p.hr_t[k] = (float)s->P.hr_t[k];
-    p.pick_s = (float)s->P.pick_s; p.drop_s = (float)s->P.drop_s;
-    p.storage_dest = s->storage_dest; p.barrier_dest = s->barrier_dest;
-    p.fv_partials = s->partials;
-    p.fv_blocks = s->nblocks_fv;
-    return p;
-}
+    PedParams& q = c.ped;
+    q.x = s->x; q.y = s->y; q.vx = s->vx; q.vy = s->vy; q.vbase = s->vbase;
+    q.role = s->role; q.state = s->state; q.cls = s->cls; q.dest = s->dest; q.timer = s->timer;
+    q.na = s->na;
+    q.np = s->np;
+    q.dist = s->dist; q.walk = s->walk; q.n_dest = s->n_dest; q.n_exit = s->n_exit;
+    q.bin_start = s->bin_start; q.xy = s->xy; q.slot = s->slot; q.wmask = s->wmask;
+    q.bin_count = s->bin_count; q.rank = s->rank; q.key = s->key;
+    q.nx = s->G.nx; q.ny = s->G.ny;
+    q.bsx = s->bsx; q.bsy = s->bsy; q.nbx = s->nbx; q.nby = s->nby; q.Rx = s->Rx; q.Ry = s->Ry;
+    q.use_wmask = s->use_wmask;
+    q.dx = (float)s->G.dx; q.dy = (float)s->G.dy; q.eps = (float)s->G.h_dry;
+    q.tau = (float)s->P.tau; q.a_over_m = (float)s->P.a_over_m; q.inv_b = (float)(1.0 / s->P.b_range);
+    q.two_r = (float)(2.0 * s->P.radius); q.radius = (float)s->P.radius;
+    q.r_cut = (float)s->P.r_cut; q.r_arrive = (float)s->P.r_arrive;
+    for (int k = 0; k < 5; ++k) q.v_class[k] = (float)s->P.v_class[k];
+    for (int k = 0; k < 3; ++k) q.hr_t[k] = (float)s->P.hr_t[k];
+    q.pick_s = (float)s->P.pick_s; q.drop_s = (float)s->P.drop_s;
+    q.storage_dest = s->storage_dest; q.barrier_dest = s->barrier_dest;
 
-BinParams bin_params(const fps_sim* s)
-{
-    BinParams b{};
+    BinParams& b = c.bins;
     b.x = s->x; b.y = s->y; b.state = s->state; b.role = s->role;
     b.bin_count = s->bin_count; b.bin_start = s->bin_start; b.rank = s->rank; b.key = s->key;
     b.perm_u = s->perm_u; b.perm = s->perm; b.xy = s->xy; b.slot = s->slot; b.np = s->np;
     b.na = s->na; b.nbins = s->nbins; b.nx = s->G.nx; b.ny = s->G.ny;
     b.bsx = s->bsx; b.bsy = s->bsy; b.nbx = s->nbx;
     b.dx = (float)s->G.dx; b.dy = (float)s->G.dy;
+
+    BarrierParams& r = c.bar;
+    r.z = s->z; r.line = s->line; r.nline = s->nline; r.n_layers = s->n_layers;
+    r.bags_per = s->bags_per; r.t_bag = s->t_bag; r.t_last = s->t_last;
+
+    c.na = s->na;
+    c.inline_place = s->na <= kInlinePlace;
+}
+
+void drop_graph(Engine* e)
+{
+    if (e->exec) (void)hipGraphExecDestroy(e->exec);
+    e->exec = nullptr;
+    e->exec_steps = 0;
+}
+
+// rebuild the device parameter records and launch geometry after any change
+int upload(Engine* e)
+{
+    if (!e->dirty) return FPS_OK;
+    e->tile_off_h.assign(e->S + 1, 0);
+    e->agent_off_h.assign(e->S + 1, 0);
+    e->scn_h.resize(e->S);
+    e->max_cells = 0;
+    e->any_big = false;
+    for (int k = 0; k < e->S; ++k) {
+        fps_sim* s = e->m[k];
+        fill_scn(s, e->scn_h[k]);
+        e->tile_off_h[k + 1] = e->tile_off_h[k] + e->scn_h[k].fv.ntiles;
+        e->agent_off_h[k + 1] = e->agent_off_h[k] + (s->na + kPedBlock - 1) / kPedBlock * kPedBlock;
+        e->max_cells = std::max(e->max_cells, (int64_t)s->G.nx * s->G.ny);
+        e->any_big = e->any_big || s->na > kInlinePlace;
+    }
+    e->total_tiles = e->tile_off_h[e->S];
+    e->total_agents = e->agent_off_h[e->S];
+    e->fv_blocks = fv_blocks_for_tiles(e->total_tiles);
+    HIPCHK_E(e, hipMemcpyAsync(e->scn_d, e->scn_h.data(), sizeof(Scn) * e->S, hipMemcpyHostToDevice, e->stream));
+    HIPCHK_E(e, hipMemcpyAsync(e->tile_off_d, e->tile_off_h.data(), sizeof(int) * (e->S + 1),
+                               hipMemcpyHostToDevice, e->stream));
+    HIPCHK_E(e, hipMemcpyAsync(e->agent_off_d, e->agent_off_h.data(), sizeof(int) * (e->S + 1),
+                               hipMemcpyHostToDevice, e->stream));
+    HIPCHK_E(e, hipStreamSynchronize(e->stream));
+    e->dirty = false;
+    drop_graph(e);
+    return FPS_OK;
+}
+
+Batch batch_of(const Engine* e, int s_only = -1)
+{
+    Batch b{};
+    b.scn = e->scn_d;
+    b.tile_off = e->tile_off_d;
+    b.agent_off = e->agent_off_d;
+    b.S = e->S;
+    b.total_tiles = e->total_tiles;
+    b.total_agents = e->total_agents;
+    b.fv_blocks = e->fv_blocks;
+    b.s_only = s_only;
+    if (s_only >= 0) b.fv_blocks = fv_blocks_for_tiles(e->scn_h[s_only].fv.ntiles);
     return b;
 }
 
-FinParams fin_params(const fps_sim* s, const FvParams& fv, int mode)
-{
-    FinParams f{};
-    f.fv = fv;
-    f.bar.z = s->z;
-    f.bar.line = s->line;
-    f.bar.nline = s->nline;
-    f.bar.n_layers = s->n_layers;
-    f.bar.bags_per = s->bags_per;
-    f.bar.t_bag = s->t_bag;
-    f.bar.t_last = s->t_last;
-    f.bins = bin_params(s);
-    f.do_barrier = mode == 0 && s->na > 0;
-    f.do_scan = mode == 0 && s->na > 0;
-    return f;
-}
+void mark_dirty(fps_sim* s) { s->eng->dirty = true; }
 
-// recompute dt (and the inflow of the next step) from the bound state
+// recompute dt (and the inflow of the next step) of one member from its state
 int prime(fps_sim* s)
 {
     if (!s->fields_bound) return FPS_OK;
-    FvParams p = fv_params(s, 1, s->h, s->qx, s->qy, nullptr, nullptr, nullptr);
-    HIPCHK(s, launch_fv(p, s->stream));
-    HIPCHK(s, launch_finalize(fin_params(s, p, 1), s->stream));
+    Engine* e = s->eng;
+    int rc = upload(e);
+    if (rc != FPS_OK) return fail(s, rc, "%s", e->err);
+    Batch b = batch_of(e);
+    HIPCHK(s, launch_fv_scan(b, s->idx, e->scn_h[s->idx].fv.ntiles, e->stream));
+    HIPCHK(s, launch_finalize(b, 1, s->idx, 1, e->stream));
     return FPS_OK;
+}
+
+BinParams bin_params(const fps_sim* s)
+{
+    Scn c;
+    fill_scn(s, c);
+    return c.bins;
 }
 
 int rebuild_bins(fps_sim* s)
 {
     if (s->na <= 0) return FPS_OK;
+    hipStream_t st = s->eng->stream;
     BinParams b = bin_params(s);
-    HIPCHK(s, launch_fill_i32(s->bin_count, 0, s->nbins, s->stream));
-    HIPCHK(s, launch_bin_keys(b, s->stream));
-    HIPCHK(s, launch_bin_scan(b, s->stream));
-    HIPCHK(s, launch_bin_place(b, s->stream));
-    HIPCHK(s, launch_bin_sort(b, s->stream));
-    HIPCHK(s, launch_fill_i32(s->np, 0, (int64_t)s->G.nx * s->G.ny, s->stream));
-    HIPCHK(s, launch_count(b, s->stream));
+    HIPCHK(s, launch_fill_i32(s->bin_count, 0, s->nbins, st));
+    HIPCHK(s, launch_bin_keys(b, st));
+    HIPCHK(s, launch_bin_scan(b, st));
+    HIPCHK(s, launch_bin_place(b, st));
+    HIPCHK(s, launch_bin_sort(b, st));
+    HIPCHK(s, launch_fill_i32(s->np, 0, (int64_t)s->G.nx * s->G.ny, st));
+    HIPCHK(s, launch_count(b, st));
     return FPS_OK;
 }
 
@@ -260,73 +420,286 @@ struct KernelEvents {
     int n[5];
 };
 
-// one coupled step: flood update from (in) to (out), pedestrians, end of step
-// (reductions, barrier, bin scan), then placement of the agents in the bins
-int step_once(fps_sim* s, const float* hi, const float* qxi, const float* qyi, float* ho,
-              float* qxo, float* qyo, KernelEvents* K)
+// the launches of one step of every scenario
+int step_launches(Engine* e, hipStream_t st, KernelEvents* K)
 {
-    hipStream_t st = s->stream;
+    Batch b = batch_of(e);
     auto rec = [&](int k, int w) {
         if (K) (void)hipEventRecord(K->ev[k][w], st);
     };
-    auto harvest = [&](int k) {
-        if (!K) return;
-        float ms = 0.0f;
-        (void)hipEventSynchronize(K->ev[k][1]);
-        (void)hipEventElapsedTime(&ms, K->ev[k][0], K->ev[k][1]);
-        K->ms[k] += ms;
-        K->n[k] += 1;
-    };
-    FvParams fp = fv_params(s, 0, hi, qxi, qyi, ho, qxo, qyo);
     rec(0, 0);
-    HIPCHK(s, launch_fv(fp, st));
+    HIPCHK_E(e, launch_fv(b, st));
     rec(0, 1);
-    if (s->na > 0) {
-        PedParams pp = ped_params(s, ho, qxo, qyo);
+    if (e->total_agents > 0) {
         rec(1, 0);
-        HIPCHK(s, launch_ped(pp, st));
+        HIPCHK_E(e, launch_ped(b, st));
         rec(1, 1);
     }
     rec(2, 0);
-    HIPCHK(s, launch_finalize(fin_params(s, fp, 0), st));
+    HIPCHK_E(e, launch_finalize(b, 0, 0, e->S, st));
     rec(2, 1);
-    if (s->na > 0) {
-        BinParams b = bin_params(s);
+    if (e->any_big) {
         rec(3, 0);
-        HIPCHK(s, launch_bin_place(b, st));
+        HIPCHK_E(e, launch_bin_place_all(b, st));
         rec(3, 1);
         rec(4, 0);
-        HIPCHK(s, launch_bin_sort(b, st));
+        HIPCHK_E(e, launch_bin_sort_all(b, st));
         rec(4, 1);
     }
-    harvest(0);
-    harvest(2);
-    if (s->na > 0) {
-        harvest(1);
-        harvest(3);
-        harvest(4);
+    if (K) {
+        const bool used[5] = {true, e->total_agents > 0, true, e->any_big, e->any_big};
+        for (int k = 0; k < 5; ++k) {
+            if (!used[k]) continue;
+            float ms = 0.0f;
+            (void)hipEventSynchronize(K->ev[k][1]);
+            (void)hipEventElapsedTime(&ms, K->ev[k][0], K->ev[k][1]);
+            K->ms[k] += ms;
+            K->n[k] += 1;
+        }
     }
     return FPS_OK;
 }
 
-int run_steps(fps_sim* s, int32_t n, KernelEvents* K)
+int capture(Engine* e, int steps)
 {
-    if (!s->fields_bound) return fail(s, FPS_E_STATE, "fps_step: fields not bound");
-    if (s->na > 0 && !s->nav_bound) return fail(s, FPS_E_STATE, "fps_step: agents need a navigation map");
-    if (s->numeric_fault) return fail(s, FPS_E_STATE, "fps_step: numeric fault latched; rebind fields");
-    if (n < 0) return fail(s, FPS_E_INVALID, "fps_step: n_steps < 0");
-    for (int32_t k = 0; k < n; ++k) {
-        int rc;
-        if ((k & 1) == 0) rc = step_once(s, s->h, s->qx, s->qy, s->h2, s->qx2, s->qy2, K);
-        else rc = step_once(s, s->h2, s->qx2, s->qy2, s->h, s->qx, s->qy, K);
+    drop_graph(e);
+    if (!e->cap) {
+        HIPCHK_E(e, hipStreamCreateWithFlags(&e->cap, hipStreamNonBlocking));
+        HIPCHK_E(e, hipEventCreateWithFlags(&e->ev_in, hipEventDisableTiming));
+        HIPCHK_E(e, hipEventCreateWithFlags(&e->ev_out, hipEventDisableTiming));
+    }
+    hipGraph_t g = nullptr;
+    HIPCHK_E(e, hipStreamBeginCapture(e->cap, hipStreamCaptureModeThreadLocal));
+    int rc = FPS_OK;
+    for (int k = 0; k < steps && rc == FPS_OK; ++k) rc = step_launches(e, e->cap, nullptr);
+    hipError_t ce = hipStreamEndCapture(e->cap, &g);
+    if (rc != FPS_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (ce != hipSuccess) return efail(e, FPS_E_DEVICE, "graph capture failed: %s", hipGetErrorString(ce));
+    hipError_t ie = hipGraphInstantiate(&e->exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) {
+        e->exec = nullptr;
+        return efail(e, FPS_E_DEVICE, "graph instantiate failed: %s", hipGetErrorString(ie));
+    }
+    e->exec_steps = steps;
+    return FPS_OK;
+}
+
+int engine_ready(Engine* e)
+{
+    for (fps_sim* s : e->m) {
+        if (!s->fields_bound) return efail(e, FPS_E_STATE, "scenario %d: fields not bound", s->idx);
+        if (s->na > 0 && !s->nav_bound)
+            return efail(e, FPS_E_STATE, "scenario %d: agents need a navigation map", s->idx);
+        if (s->numeric_fault)
+            return efail(e, FPS_E_STATE, "scenario %d: numeric fault latched; rebind fields", s->idx);
+    }
+    return FPS_OK;
+}
+
+int run_steps(Engine* e, int32_t n, KernelEvents* K)
+{
+    if (n < 0) return efail(e, FPS_E_INVALID, "n_steps < 0");
+    int rc = engine_ready(e);
+    if (rc != FPS_OK) return rc;
+    rc = upload(e);
+    if (rc != FPS_OK) return rc;
+    int done = 0;
+    if (!K && e->graph_chunk > 0 && n >= e->graph_chunk) {
+        if (!e->exec || e->exec_steps != e->graph_chunk) {
+            rc = capture(e, e->graph_chunk);
+            if (rc != FPS_OK) return rc;
+        }
+        HIPCHK_E(e, hipEventRecord(e->ev_in, e->stream));
+        HIPCHK_E(e, hipStreamWaitEvent(e->cap, e->ev_in, 0));
+        for (; done + e->exec_steps <= n; done += e->exec_steps) HIPCHK_E(e, hipGraphLaunch(e->exec, e->cap));
+        HIPCHK_E(e, hipEventRecord(e->ev_out, e->cap));
+        HIPCHK_E(e, hipStreamWaitEvent(e->stream, e->ev_out, 0));
+    }
+    for (; done < n; ++done) {
+        rc = step_launches(e, e->stream, K);
         if (rc != FPS_OK) return rc;
     }
-    if (n & 1) {
-        size_t bytes = sizeof(float) * (size_t)s->G.nx * s->G.ny;
-        HIPCHK(s, hipMemcpyAsync(s->h, s->h2, bytes, hipMemcpyDeviceToDevice, s->stream));
-        HIPCHK(s, hipMemcpyAsync(s->qx, s->qx2, bytes, hipMemcpyDeviceToDevice, s->stream));
-        HIPCHK(s, hipMemcpyAsync(s->qy, s->qy2, bytes, hipMemcpyDeviceToDevice, s->stream));
+    if (n > 0) HIPCHK_E(e, launch_sync_back(batch_of(e), e->max_cells, e->stream));
+    return FPS_OK;
+}
+
+int profiled(Engine* e, int32_t n, double* ms_out)
+{
+    KernelEvents K{};
+    for (int k = 0; k < 5; ++k)
+        for (int w = 0; w < 2; ++w) HIPCHK_E(e, hipEventCreate(&K.ev[k][w]));
+    int rc = run_steps(e, n, &K);
+    (void)hipStreamSynchronize(e->stream);
+    for (int k = 0; k < 5; ++k) {
+        ms_out[k] = K.n[k] ? K.ms[k] / K.n[k] : 0.0;
+        for (int w = 0; w < 2; ++w) (void)hipEventDestroy(K.ev[k][w]);
     }
+    return rc;
+}
+
+// mean device ms of one flood-update launch of member s with H rows per wave,
+// measured on its bound state (outputs go to the scratch buffer; nothing is
+// committed: the caller re-primes the member afterwards)
+int time_rows(fps_sim* s, int H, int reps, float* ms_out)
+{
+    Engine* e = s->eng;
+    s->H = H;
+    mark_dirty(s);
+    int rc = upload(e);
+    if (rc != FPS_OK) return fail(s, rc, "%s", e->err);
+    Batch b = batch_of(e, s->idx);
+    hipEvent_t e0, e1;
+    HIPCHK(s, hipEventCreate(&e0));
+    HIPCHK(s, hipEventCreate(&e1));
+    for (int r = 0; r < 2; ++r) HIPCHK(s, launch_fv(b, e->stream));
+    HIPCHK(s, hipEventRecord(e0, e->stream));
+    for (int r = 0; r < reps; ++r) HIPCHK(s, launch_fv(b, e->stream));
+    HIPCHK(s, hipEventRecord(e1, e->stream));
+    HIPCHK(s, hipEventSynchronize(e1));
+    float ms = 0.0f;
+    HIPCHK(s, hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms_out = ms / reps;
+    return FPS_OK;
+}
+
+int current_arch(char* arch, size_t n)
+{
+    hipDeviceProp_t prop;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return -1;
+    snprintf(arch, n, "%s", prop.gcnArchName);
+    for (char* c = arch; *c; ++c)
+        if (*c == ':' || *c == ' ') *c = '\0';
+    return 0;
+}
+
+bool cache_lookup(const char* path, const char* arch, int nx, int ny, int* H, double* ms)
+{
+    if (!path) return false;
+    FILE* f = fopen(path, "r");
+    if (!f) return false;
+    char a[64];
+    int cx, cy, ch;
+    double cm;
+    bool found = false;
+    while (fscanf(f, "%63s %d %d %d %lf", a, &cx, &cy, &ch, &cm) == 5)
+        if (!strcmp(a, arch) && cx == nx && cy == ny && ch >= 1 && ch <= 64 && !(ch & (ch - 1))) {
+            *H = ch;
+            *ms = cm;
+            found = true;
+        }
+    fclose(f);
+    return found;
+}
+
+int tune_member(fps_sim* s, const char* cache_path, int* rows_out, double* ms_out)
+{
+    if (!s->fields_bound) return fail(s, FPS_E_STATE, "fps_autotune: fields not bound");
+    char arch[64] = "unknown";
+    if (current_arch(arch, sizeof(arch)) != 0) return fail(s, FPS_E_DEVICE, "no HIP device");
+    int best = -1;
+    double best_ms = 0.0;
+    if (!cache_lookup(cache_path, arch, s->G.nx, s->G.ny, &best, &best_ms)) {
+        HIPCHK(s, hipStreamSynchronize(s->eng->stream));
+        const int64_t cells = (int64_t)s->G.nx * s->G.ny;
+        const int reps = cells > (1 << 24) ? 5 : 20;
+        best = -1;
+        for (int H = 1; H <= 64; H <<= 1) {
+            if (H > 1 && (H >> 1) >= s->G.ny) break;
+            float ms = 0.0f;
+            int rc = time_rows(s, H, reps, &ms);
+            if (rc != FPS_OK) return rc;
+            if (best < 0 || ms < best_ms) {
+                best = H;
+                best_ms = ms;
+            }
+        }
+        if (cache_path) {
+            FILE* f = fopen(cache_path, "a");
+            if (f) {
+                fprintf(f, "%s %d %d %d %.6f\n", arch, s->G.nx, s->G.ny, best, best_ms);
+                fclose(f);
+            }
+        }
+    }
+    s->H = best;
+    mark_dirty(s);
+    int rc = prime(s);   // timing launches wrote scratch partials and the wet flag
+    if (rc != FPS_OK) return rc;
+    if (rows_out) *rows_out = best;
+    if (ms_out) *ms_out = best_ms;
+    return FPS_OK;
+}
+
+void destroy_engine(Engine* e)
+{
+    if (!e) return;
+    (void)hipStreamSynchronize(e->stream);
+    drop_graph(e);
+    if (e->cap) {
+        (void)hipStreamSynchronize(e->cap);
+        (void)hipStreamDestroy(e->cap);
+    }
+    if (e->ev_in) (void)hipEventDestroy(e->ev_in);
+    if (e->ev_out) (void)hipEventDestroy(e->ev_out);
+    for (fps_sim* s : e->m) delete s;
+    e->m.clear();
+}
+
+int build_engine(Engine* e, int32_t S, const fps_grid_desc* descs, const fps_ped_params* peds,
+                 const int32_t* max_agents, void* ws, size_t ws_bytes, void* stream)
+{
+    char why[256];
+    if (S < 1) return efail(e, FPS_E_INVALID, "need at least one scenario");
+    if (!descs) return efail(e, FPS_E_INVALID, "descs is NULL");
+    for (int k = 0; k < S; ++k) {
+        if (!valid_desc(&descs[k], why)) return efail(e, FPS_E_INVALID, "scenario %d: %s", k, why);
+        if (max_agents && max_agents[k] < 0) return efail(e, FPS_E_INVALID, "scenario %d: max_agents < 0", k);
+        if (peds) {
+            const fps_ped_params& P = peds[k];
+            if (!(P.tau > 0) || !(P.b_range > 0) || !(P.r_cut > 0) || !(P.radius >= 0) || !(P.r_arrive >= 0))
+                return efail(e, FPS_E_INVALID, "scenario %d: pedestrian constants out of range", k);
+        }
+    }
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255))
+        return efail(e, FPS_E_INVALID, "workspace NULL or not 256-byte aligned");
+    size_t need = engine_header_bytes(S);
+    for (int k = 0; k < S; ++k) need += member_layout(&descs[k], max_agents ? max_agents[k] : 0).total;
+    if (ws_bytes < need) return efail(e, FPS_E_CAPACITY, "workspace %zu bytes < %zu needed", ws_bytes, need);
+    e->S = S;
+    e->stream = static_cast<hipStream_t>(stream);
+    size_t o = 0;
+    e->scn_d = at<Scn>(ws, o);
+    o += align256(sizeof(Scn) * S);
+    e->tile_off_d = at<int>(ws, o);
+    o += align256(sizeof(int) * (S + 1));
+    e->agent_off_d = at<int>(ws, o);
+    o += align256(sizeof(int) * (S + 1));
+    for (int k = 0; k < S; ++k) {
+        fps_ped_params P;
+        if (peds) P = peds[k];
+        else fps_ped_params_default(&P);
+        int32_t ma = max_agents ? max_agents[k] : 0;
+        fps_sim* s = new_member(e, k, &descs[k], P, ma, at<char>(ws, o));
+        if (!s) return efail(e, FPS_E_DEVICE, "out of host memory");
+        e->m.push_back(s);
+        o += member_layout(&descs[k], ma).total;
+        int rc = init_member_device(s);
+        if (rc != FPS_OK) return efail(e, rc, "%s", s->err);
+    }
+    return FPS_OK;
+}
+
+int write_state_i32(fps_sim* s, int32_t* field, int32_t v)
+{
+    HIPCHK(s, hipMemcpyAsync(field, &v, sizeof(v), hipMemcpyHostToDevice, s->eng->stream));
+    HIPCHK(s, hipStreamSynchronize(s->eng->stream));
     return FPS_OK;
 }
 
@@ -356,88 +729,138 @@ size_t fps_workspace_bytes(const fps_grid_desc* desc, int32_t max_agents)
 {
     char why[256];
     if (!valid_desc(desc, why) || max_agents < 0) return 0;
-    return make_layout(desc, max_agents).total;
+    return engine_header_bytes(1) + member_layout(desc, max_agents).total;
+}
+
+size_t fps_ens_workspace_bytes(int32_t S, const fps_grid_desc* descs, const int32_t* max_agents)
+{
+    char why[256];
+    if (S < 1 || !descs) return 0;
+    size_t total = engine_header_bytes(S);
+    for (int k = 0; k < S; ++k) {
+        if (!valid_desc(&descs[k], why)) return 0;
+        int32_t ma = max_agents ? max_agents[k] : 0;
+        if (ma < 0) return 0;
+        total += member_layout(&descs[k], ma).total;
+    }
+    return total;
 }
 
 int fps_create(const fps_grid_desc* desc, const fps_ped_params* ped, int32_t max_agents,
                void* ws, size_t ws_bytes, void* stream, fps_sim** out)
 {
-    char why[256];
     if (!out) return fail(nullptr, FPS_E_INVALID, "fps_create: out is NULL");
     *out = nullptr;
-    if (!valid_desc(desc, why)) return fail(nullptr, FPS_E_INVALID, "fps_create: %s", why);
-    if (max_agents < 0) return fail(nullptr, FPS_E_INVALID, "fps_create: max_agents < 0");
-    fps_ped_params P;
-    if (ped) P = *ped;
-    else fps_ped_params_default(&P);
-    if (!(P.tau > 0) || !(P.b_range > 0) || !(P.r_cut > 0) || !(P.radius >= 0) || !(P.r_arrive >= 0))
-        return fail(nullptr, FPS_E_INVALID, "fps_create: pedestrian constants out of range");
-    if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255))
-        return fail(nullptr, FPS_E_INVALID, "fps_create: workspace NULL or not 256-byte aligned");
-    Layout L = make_layout(desc, max_agents);
-    if (ws_bytes < L.total)
-        return fail(nullptr, FPS_E_CAPACITY, "fps_create: workspace %zu bytes < %zu needed", ws_bytes,
-                    L.total);
-    fps_sim* s = new (std::nothrow) fps_sim();
-    if (!s) return fail(nullptr, FPS_E_DEVICE, "fps_create: out of host memory");
-    s->G = *desc;
-    s->P = P;
-    s->max_agents = max_agents;
-    s->stream = static_cast<hipStream_t>(stream);
-    s->st = at<DevState>(ws, L.st);
-    s->partials = at<double>(ws, L.partials);
-    s->h2 = at<float>(ws, L.h2);
-    s->qx2 = at<float>(ws, L.qx2);
-    s->qy2 = at<float>(ws, L.qy2);
-    s->np = at<int32_t>(ws, L.np);
-    s->bin_count = at<int32_t>(ws, L.bin_count);
-    s->bin_start = at<int32_t>(ws, L.bin_start);
-    s->rank = at<int32_t>(ws, L.rank);
-    s->key = at<int32_t>(ws, L.key);
-    s->perm_u = at<int32_t>(ws, L.perm_u);
-    s->perm = at<int32_t>(ws, L.perm);
-    s->xy = at<float2>(ws, L.xy);
-    s->slot = at<int32_t>(ws, L.slot);
-    s->wmask = at<uint4>(ws, L.wmask);
-    s->line = at<int32_t>(ws, L.line);
-    s->stats = at<int32_t>(ws, L.stats);
-    s->line_cap = L.line_cap;
-    s->H = L.H;
-    s->nblocks_fv = L.nblocks;
-    s->bsx = std::max(1, (int)std::ceil(P.r_cut / desc->dx - 1e-9));
-    s->bsy = std::max(1, (int)std::ceil(P.r_cut / desc->dy - 1e-9));
-    s->nbx = (desc->nx + s->bsx - 1) / s->bsx;
-    s->nby = (desc->ny + s->bsy - 1) / s->bsy;
-    s->nbins = s->nbx * s->nby;
-    s->Rx = s->bsx;
-    s->Ry = s->bsy;
-    s->n_inflow = desc->inflow_side >= 0 ? desc->inflow_c1 - desc->inflow_c0 : 0;
-    s->storage_dest = s->barrier_dest = -1;
-    DevState h0{};
-    h0.dt = (float)desc->dt_max;
-    h0.dt_prev = (float)desc->dt_max;
-    hipError_t e = hipMemcpyAsync(s->st, &h0, sizeof(h0), hipMemcpyHostToDevice, s->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-    if (e == hipSuccess) {
-        int rc = FPS_OK;
-        if (launch_fill_i32(s->np, 0, (int64_t)desc->nx * desc->ny, s->stream) != hipSuccess) rc = -1;
-        if (max_agents > 0 && launch_fill_i32(s->bin_count, 0, L.nbins_max, s->stream) != hipSuccess) rc = -1;
-        if (rc != FPS_OK) e = hipErrorLaunchFailure;
+    Engine* e = new (std::nothrow) Engine();
+    if (!e) return fail(nullptr, FPS_E_DEVICE, "fps_create: out of host memory");
+    e->standalone = true;
+    int rc = build_engine(e, 1, desc, ped, &max_agents, ws, ws_bytes, stream);
+    if (rc != FPS_OK) {
+        fail(nullptr, rc, "fps_create: %s", e->err);
+        destroy_engine(e);
+        delete e;
+        return rc;
     }
-    if (e != hipSuccess) {
-        delete s;
-        return fail(nullptr, FPS_E_DEVICE, "fps_create: %s", hipGetErrorString(e));
-    }
-    *out = s;
+    *out = e->m[0];
     return FPS_OK;
 }
 
 void fps_destroy(fps_sim* s)
 {
-    if (!s) return;
-    (void)hipStreamSynchronize(s->stream);
-    delete s;
+    if (!s || !s->eng->standalone) return;   // members belong to their ensemble
+    Engine* e = s->eng;
+    destroy_engine(e);
+    delete e;
 }
+
+int fps_ens_create(int32_t S, const fps_grid_desc* descs, const fps_ped_params* peds,
+                   const int32_t* max_agents, void* ws, size_t ws_bytes, void* stream, fps_ens** out)
+{
+    if (!out) return fail(nullptr, FPS_E_INVALID, "fps_ens_create: out is NULL");
+    *out = nullptr;
+    fps_ens* e = new (std::nothrow) fps_ens();
+    if (!e) return fail(nullptr, FPS_E_DEVICE, "fps_ens_create: out of host memory");
+    int rc = build_engine(e, S, descs, peds, max_agents, ws, ws_bytes, stream);
+    if (rc != FPS_OK) {
+        fail(nullptr, rc, "fps_ens_create: %s", e->err);
+        destroy_engine(e);
+        delete e;
+        return rc;
+    }
+    *out = e;
+    return FPS_OK;
+}
+
+void fps_ens_destroy(fps_ens* e)
+{
+    if (!e) return;
+    destroy_engine(e);
+    delete e;
+}
+
+fps_sim* fps_ens_member(fps_ens* e, int32_t s)
+{
+    if (!e || s < 0 || s >= e->S) return nullptr;
+    return e->m[s];
+}
+
+int fps_ens_step(fps_ens* e, int32_t n_steps)
+{
+    if (!e) return fail(nullptr, FPS_E_INVALID, "fps_ens_step: ens is NULL");
+    return run_steps(e, n_steps, nullptr);
+}
+
+int fps_ens_step_profiled(fps_ens* e, int32_t n_steps, double* ms_out)
+{
+    if (!e || !ms_out) return fail(nullptr, FPS_E_INVALID, "fps_ens_step_profiled: NULL argument");
+    return profiled(e, n_steps, ms_out);
+}
+
+int fps_ens_set_graph(fps_ens* e, int32_t steps_per_graph)
+{
+    if (!e) return fail(nullptr, FPS_E_INVALID, "fps_ens_set_graph: ens is NULL");
+    if (steps_per_graph < 0 || steps_per_graph > 4096) return efail(e, FPS_E_INVALID, "steps_per_graph out of range");
+    e->graph_chunk = steps_per_graph;
+    drop_graph(e);
+    return FPS_OK;
+}
+
+int fps_ens_autotune(fps_ens* e, const char* cache_path)
+{
+    if (!e) return fail(nullptr, FPS_E_INVALID, "fps_ens_autotune: ens is NULL");
+    for (int k = 0; k < e->S; ++k) {
+        fps_sim* s = e->m[k];
+        int reuse = -1;
+        for (int j = 0; j < k; ++j)
+            if (e->m[j]->G.nx == s->G.nx && e->m[j]->G.ny == s->G.ny) reuse = j;
+        if (reuse >= 0) {
+            s->H = e->m[reuse]->H;
+            mark_dirty(s);
+            int rc = prime(s);
+            if (rc != FPS_OK) return efail(e, rc, "%s", s->err);
+            continue;
+        }
+        int rc = tune_member(s, cache_path, nullptr, nullptr);
+        if (rc != FPS_OK) return efail(e, rc, "%s", s->err);
+    }
+    return FPS_OK;
+}
+
+int fps_ens_active(fps_ens* e, int32_t* n_active)
+{
+    if (!e || !n_active) return fail(nullptr, FPS_E_INVALID, "fps_ens_active: NULL argument");
+    HIPCHK_E(e, hipStreamSynchronize(e->stream));
+    int32_t n = 0;
+    for (fps_sim* s : e->m) {
+        int32_t a = 0;
+        HIPCHK_E(e, hipMemcpy(&a, &s->st->active, sizeof(a), hipMemcpyDeviceToHost));
+        n += a;
+    }
+    *n_active = n;
+    return FPS_OK;
+}
+
+const char* fps_ens_last_error(const fps_ens* e) { return e ? e->err : g_err; }
 
 int fps_bind_fields(fps_sim* s, float* h, float* hu, float* hv, float* z)
 {
@@ -446,9 +869,11 @@ int fps_bind_fields(fps_sim* s, float* h, float* hu, float* hv, float* z)
     s->h = h; s->qx = hu; s->qy = hv; s->z = z;
     s->fields_bound = true;
     s->numeric_fault = false;
-    int32_t zero = 0;
-    HIPCHK(s, hipMemcpyAsync(&s->st->status, &zero, sizeof(zero), hipMemcpyHostToDevice, s->stream));
-    HIPCHK(s, hipStreamSynchronize(s->stream));
+    mark_dirty(s);
+    int rc = write_state_i32(s, &s->st->status, 0);
+    if (rc == FPS_OK) rc = write_state_i32(s, &s->st->settled, 0);
+    if (rc == FPS_OK) rc = write_state_i32(s, &s->st->cur, 0);
+    if (rc != FPS_OK) return rc;
     return prime(s);
 }
 
@@ -467,10 +892,11 @@ int fps_set_hydrograph(fps_sim* s, const double* t, const double* q, int32_t npt
         tt[k] = t[k];
         qq[k] = q[k];
     }
-    HIPCHK(s, hipMemcpyAsync(s->st->hyd_t, tt, sizeof(tt), hipMemcpyHostToDevice, s->stream));
-    HIPCHK(s, hipMemcpyAsync(s->st->hyd_q, qq, sizeof(qq), hipMemcpyHostToDevice, s->stream));
-    HIPCHK(s, hipMemcpyAsync(&s->st->nh, &npts, sizeof(npts), hipMemcpyHostToDevice, s->stream));
-    HIPCHK(s, hipStreamSynchronize(s->stream));
+    hipStream_t st = s->eng->stream;
+    HIPCHK(s, hipMemcpyAsync(s->st->hyd_t, tt, sizeof(tt), hipMemcpyHostToDevice, st));
+    HIPCHK(s, hipMemcpyAsync(s->st->hyd_q, qq, sizeof(qq), hipMemcpyHostToDevice, st));
+    HIPCHK(s, hipMemcpyAsync(&s->st->nh, &npts, sizeof(npts), hipMemcpyHostToDevice, st));
+    HIPCHK(s, hipStreamSynchronize(st));
     return prime(s);
 }
 
@@ -487,7 +913,8 @@ int fps_set_navigation(fps_sim* s, int32_t n_dest, int32_t n_exit, const float* 
     s->nav_bound = true;
     s->use_wmask = s->max_agents > 0 && (2 * s->Rx + 1) * (2 * s->Ry + 1) <= kMaskBits;
     if (s->use_wmask)
-        HIPCHK(s, launch_wall_mask(walkable, s->wmask, s->G.nx, s->G.ny, s->Rx, s->Ry, s->stream));
+        HIPCHK(s, launch_wall_mask(walkable, s->wmask, s->G.nx, s->G.ny, s->Rx, s->Ry, s->eng->stream));
+    mark_dirty(s);
     return FPS_OK;
 }
 
@@ -499,14 +926,15 @@ int fps_bind_agents(fps_sim* s, int32_t n, float* x, float* y, float* vx, float*
         return fail(s, FPS_E_CAPACITY, "fps_bind_agents: %d agents, capacity %d", n, s->max_agents);
     if (n > 0 && (!x || !y || !vx || !vy || !v_base || !role || !state || !hr_class || !dest || !timer))
         return fail(s, FPS_E_INVALID, "fps_bind_agents: NULL array");
+    hipStream_t st = s->eng->stream;
     if (n > 0) {
         if (!s->nav_bound) return fail(s, FPS_E_STATE, "fps_bind_agents: set the navigation map first");
-        HIPCHK(s, launch_fill_i32(s->stats, 0, 2, s->stream));
+        HIPCHK(s, launch_fill_i32(s->stats, 0, 2, st));
         HIPCHK(s, launch_check_agents(x, y, role, state, dest, n, (float)(s->G.nx * s->G.dx),
-                                      (float)(s->G.ny * s->G.dy), s->n_dest, s->stats, s->stream));
+                                      (float)(s->G.ny * s->G.dy), s->n_dest, s->stats, st));
         int32_t bad[2] = {0, 0};
-        HIPCHK(s, hipMemcpyAsync(bad, s->stats, sizeof(bad), hipMemcpyDeviceToHost, s->stream));
-        HIPCHK(s, hipStreamSynchronize(s->stream));
+        HIPCHK(s, hipMemcpyAsync(bad, s->stats, sizeof(bad), hipMemcpyDeviceToHost, st));
+        HIPCHK(s, hipStreamSynchronize(st));
         if (bad[0]) return fail(s, FPS_E_INVALID, "fps_bind_agents: %d agents outside the domain", bad[0]);
         if (bad[1])
             return fail(s, FPS_E_INVALID, "fps_bind_agents: %d agents with invalid role/state/dest", bad[1]);
@@ -514,6 +942,7 @@ int fps_bind_agents(fps_sim* s, int32_t n, float* x, float* y, float* vx, float*
     s->na = n;
     s->x = x; s->y = y; s->vx = vx; s->vy = vy; s->vbase = v_base;
     s->role = role; s->state = state; s->cls = hr_class; s->dest = dest; s->timer = timer;
+    mark_dirty(s);
     return rebuild_bins(s);
 }
 
@@ -531,11 +960,12 @@ int fps_set_barrier(fps_sim* s, const int32_t* cells, int32_t ncells, int32_t st
     const int64_t nc = (int64_t)s->G.nx * s->G.ny;
     for (int k = 0; k < ncells; ++k)
         if (cells[k] < 0 || cells[k] >= nc) return fail(s, FPS_E_INVALID, "fps_set_barrier: cell %d out of grid", k);
+    hipStream_t st = s->eng->stream;
     if (ncells > 0)
-        HIPCHK(s, hipMemcpyAsync(s->line, cells, sizeof(int32_t) * ncells, hipMemcpyHostToDevice, s->stream));
+        HIPCHK(s, hipMemcpyAsync(s->line, cells, sizeof(int32_t) * ncells, hipMemcpyHostToDevice, st));
     int32_t zero4[4] = {0, 0, 0, 0};
-    HIPCHK(s, hipMemcpyAsync(&s->st->active, zero4, sizeof(zero4), hipMemcpyHostToDevice, s->stream));
-    HIPCHK(s, hipStreamSynchronize(s->stream));
+    HIPCHK(s, hipMemcpyAsync(&s->st->layers_done, zero4, sizeof(zero4), hipMemcpyHostToDevice, st));
+    HIPCHK(s, hipStreamSynchronize(st));
     s->nline = ncells;
     s->storage_dest = storage_dest;
     s->barrier_dest = barrier_dest;
@@ -543,6 +973,7 @@ int fps_set_barrier(fps_sim* s, const int32_t* cells, int32_t ncells, int32_t st
     s->t_bag = layer_thickness;
     s->t_last = last_thickness;
     s->bags_per = bags_per;
+    mark_dirty(s);
     return FPS_OK;
 }
 
@@ -550,43 +981,67 @@ int fps_set_time(fps_sim* s, double t, int64_t step)
 {
     if (!s) return fail(nullptr, FPS_E_INVALID, "fps_set_time: sim is NULL");
     if (!std::isfinite(t) || step < 0) return fail(s, FPS_E_INVALID, "fps_set_time: bad time/step");
-    HIPCHK(s, hipMemcpyAsync(&s->st->t, &t, sizeof(t), hipMemcpyHostToDevice, s->stream));
-    HIPCHK(s, hipMemcpyAsync(&s->st->step, &step, sizeof(step), hipMemcpyHostToDevice, s->stream));
-    HIPCHK(s, hipStreamSynchronize(s->stream));
+    hipStream_t st = s->eng->stream;
+    HIPCHK(s, hipMemcpyAsync(&s->st->t, &t, sizeof(t), hipMemcpyHostToDevice, st));
+    HIPCHK(s, hipMemcpyAsync(&s->st->step, &step, sizeof(step), hipMemcpyHostToDevice, st));
+    HIPCHK(s, hipStreamSynchronize(st));
+    int rc = write_state_i32(s, &s->st->active, !(s->t_end > 0.0) || t < s->t_end);
+    if (rc != FPS_OK) return rc;
     return prime(s);
+}
+
+int fps_set_end_time(fps_sim* s, double t_end)
+{
+    if (!s) return fail(nullptr, FPS_E_INVALID, "fps_set_end_time: sim is NULL");
+    if (!std::isfinite(t_end)) return fail(s, FPS_E_INVALID, "fps_set_end_time: t_end not finite");
+    hipStream_t st = s->eng->stream;
+    double t = 0.0;
+    HIPCHK(s, hipMemcpyAsync(&s->st->t_end, &t_end, sizeof(t_end), hipMemcpyHostToDevice, st));
+    HIPCHK(s, hipMemcpyAsync(&t, &s->st->t, sizeof(t), hipMemcpyDeviceToHost, st));
+    HIPCHK(s, hipStreamSynchronize(st));
+    s->t_end = t_end;
+    return write_state_i32(s, &s->st->active, !(t_end > 0.0) || t < t_end);
 }
 
 int fps_step(fps_sim* s, int32_t n_steps)
 {
     if (!s) return fail(nullptr, FPS_E_INVALID, "fps_step: sim is NULL");
-    return run_steps(s, n_steps, nullptr);
+    if (!s->eng->standalone) return fail(s, FPS_E_STATE, "fps_step: member of an ensemble; use fps_ens_step");
+    int rc = run_steps(s->eng, n_steps, nullptr);
+    if (rc != FPS_OK) return fail(s, rc, "fps_step: %s", s->eng->err);
+    return FPS_OK;
 }
 
 int fps_step_profiled(fps_sim* s, int32_t n_steps, double* ms_out)
 {
     if (!s || !ms_out) return fail(s, FPS_E_INVALID, "fps_step_profiled: NULL argument");
-    KernelEvents K{};
-    for (int k = 0; k < 5; ++k)
-        for (int w = 0; w < 2; ++w) HIPCHK(s, hipEventCreate(&K.ev[k][w]));
-    int rc = run_steps(s, n_steps, &K);
-    (void)hipStreamSynchronize(s->stream);
-    for (int k = 0; k < 5; ++k) {
-        ms_out[k] = K.n[k] ? K.ms[k] / K.n[k] : 0.0;
-        for (int w = 0; w < 2; ++w) (void)hipEventDestroy(K.ev[k][w]);
-    }
-    return rc;
+    if (!s->eng->standalone) return fail(s, FPS_E_STATE, "fps_step_profiled: member of an ensemble");
+    int rc = profiled(s->eng, n_steps, ms_out);
+    if (rc != FPS_OK) return fail(s, rc, "fps_step_profiled: %s", s->eng->err);
+    return FPS_OK;
+}
+
+int fps_set_graph(fps_sim* s, int32_t steps_per_graph)
+{
+    if (!s) return fail(nullptr, FPS_E_INVALID, "fps_set_graph: sim is NULL");
+    if (steps_per_graph < 0 || steps_per_graph > 4096)
+        return fail(s, FPS_E_INVALID, "fps_set_graph: steps_per_graph out of range");
+    s->eng->graph_chunk = steps_per_graph;
+    drop_graph(s->eng);
+    return FPS_OK;
 }
 
 int fps_get_diag(fps_sim* s, fps_diag* out)
 {
     if (!s || !out) return fail(s, FPS_E_INVALID, "fps_get_diag: NULL argument");
-    HIPCHK(s, launch_fill_i32(s->stats, 0, 16, s->stream));
-    if (s->na > 0) HIPCHK(s, launch_agent_stats(s->state, s->cls, s->na, s->stats, s->stream));
+    hipStream_t st = s->eng->stream;
+    HIPCHK(s, launch_fill_i32(s->stats, 0, 16, st));
+    if (s->na > 0) HIPCHK(s, launch_agent_stats(s->state, s->cls, s->na, s->stats, st));
     DevState d;
     int32_t stats[16];
-    HIPCHK(s, hipMemcpyAsync(&d, s->st, sizeof(d), hipMemcpyDeviceToHost, s->stream));
-    HIPCHK(s, hipMemcpyAsync(stats, s->stats, sizeof(stats), hipMemcpyDeviceToHost, s->stream));
-    HIPCHK(s, hipStreamSynchronize(s->stream));
+    HIPCHK(s, hipMemcpyAsync(&d, s->st, sizeof(d), hipMemcpyDeviceToHost, st));
+    HIPCHK(s, hipMemcpyAsync(stats, s->stats, sizeof(stats), hipMemcpyDeviceToHost, st));
+    HIPCHK(s, hipStreamSynchronize(st));
     std::memset(out, 0, sizeof(*out));
     out->t = d.t;
     out->step = d.step;
@@ -602,11 +1057,13 @@ int fps_get_diag(fps_sim* s, fps_diag* out)
     for (int k = 0; k < 5; ++k) out->class_count[k] = stats[k];
     for (int k = 0; k < 6; ++k) out->state_count[k] = stats[5 + k];
     out->barrier_layers_done = d.layers_done;
-    out->barrier_active_cell = d.active;
+    out->barrier_active_cell = d.active_cell;
     out->barrier_bags = d.bags;
     out->barrier_done = d.done;
     out->drops_total = d.drops_total;
     out->status = d.status;
+    out->active = d.active;
+    out->flood_steps = d.flood_steps;
     if (d.status != FPS_OK) {
         s->numeric_fault = true;
         return fail(s, FPS_E_NUMERIC, "non-finite state or time step detected on the device");
@@ -619,7 +1076,7 @@ int fps_hazard_field(fps_sim* s, float* hr_out)
     if (!s || !hr_out) return fail(s, FPS_E_INVALID, "fps_hazard_field: NULL argument");
     if (!s->fields_bound) return fail(s, FPS_E_STATE, "fps_hazard_field: fields not bound");
     HIPCHK(s, launch_hazard(s->h, s->qx, s->qy, hr_out, (int64_t)s->G.nx * s->G.ny, (float)s->G.h_dry,
-                            s->stream));
+                            s->eng->stream));
     return FPS_OK;
 }
 
@@ -627,7 +1084,7 @@ int fps_get_counts(fps_sim* s, int32_t* counts)
 {
     if (!s || !counts) return fail(s, FPS_E_INVALID, "fps_get_counts: NULL argument");
     HIPCHK(s, hipMemcpyAsync(counts, s->np, sizeof(int32_t) * (size_t)s->G.nx * s->G.ny,
-                             hipMemcpyDeviceToDevice, s->stream));
+                             hipMemcpyDeviceToDevice, s->eng->stream));
     return FPS_OK;
 }
 
@@ -638,10 +1095,33 @@ int fps_get_bins(fps_sim* s, int32_t* bin_start, int32_t* perm, int32_t* nbins_o
     if (s->na <= 0) return FPS_OK;
     if (bin_start)
         HIPCHK(s, hipMemcpyAsync(bin_start, s->bin_start, sizeof(int32_t) * (s->nbins + 1),
-                                 hipMemcpyDeviceToDevice, s->stream));
+                                 hipMemcpyDeviceToDevice, s->eng->stream));
     if (perm)
         HIPCHK(s, hipMemcpyAsync(perm, s->perm, sizeof(int32_t) * s->na, hipMemcpyDeviceToDevice,
-                                 s->stream));
+                                 s->eng->stream));
+    return FPS_OK;
+}
+
+int fps_set_rows_per_wave(fps_sim* s, int32_t rows)
+{
+    if (!s) return fail(nullptr, FPS_E_INVALID, "fps_set_rows_per_wave: sim is NULL");
+    if (rows < 1 || rows > 64 || (rows & (rows - 1)))
+        return fail(s, FPS_E_INVALID, "fps_set_rows_per_wave: rows must be a power of two in [1, 64]");
+    HIPCHK(s, hipStreamSynchronize(s->eng->stream));
+    s->H = rows;
+    mark_dirty(s);
+    return FPS_OK;
+}
+
+int fps_autotune(fps_sim* s, const char* cache_path, int32_t* rows_out, double* ms_out)
+{
+    if (!s) return fail(nullptr, FPS_E_INVALID, "fps_autotune: sim is NULL");
+    int rows = 0;
+    double ms = 0.0;
+    int rc = tune_member(s, cache_path, &rows, &ms);
+    if (rc != FPS_OK) return rc;
+    if (rows_out) *rows_out = rows;
+    if (ms_out) *ms_out = ms;
     return FPS_OK;
 }
 

@@ -6,6 +6,29 @@
 
 namespace fps {
 
+// Scenario owning flattened index g: the largest s with off[s] <= g (off has
+// S + 1 entries, non-decreasing).  Called with wave-uniform arguments.
+__device__ __forceinline__ int find_scenario(const int* off, int S, int g)
+{
+    int lo = 0, hi = S - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// A step whose flood update is the identity and is skipped: nothing is wet,
+// no inflow enters during the step, and the state already came out of a flood
+// update (so dry cells carry no discharge).  The 1 s dry step of sec. 3 then
+// only advances the pedestrians.  Every kernel of the step evaluates this on
+// the same device state before the finalize changes it.
+__device__ __forceinline__ bool flood_skipped(const DevState* st)
+{
+    return st->settled && !st->any_wet && st->inc == 0.0f;
+}
+
 __device__ __forceinline__ double hydro_q(const DevState* st, double t)
 {
     int n = st->nh;
@@ -37,31 +60,40 @@ __device__ inline double hydro_integral(const DevState* st, double a, double b)
 }
 
 // Exclusive scan of the bin histogram by one block of kScanThreads: tiles of
-// 4 * kScanThreads counts, four consecutive counts per lane (16-byte loads), a
-// wave scan by shuffles and a scan of the wave totals; the histogram is
-// cleared behind the scan for the next step.
+// 16 * kScanThreads counts, sixteen consecutive counts per lane (four 16-byte
+// loads), a wave scan by shuffles and a scan of the wave totals; the histogram
+// is cleared behind the scan for the next step.
 __device__ inline void block_scan_bins(const BinParams& b)
 {
+    constexpr int IPT = 16;
     __shared__ int wtot[kScanThreads / kWave];
     __shared__ int carry_s;
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x >> 6;
     if (threadIdx.x == 0) carry_s = 0;
     __syncthreads();
-    for (int base = 0; base < b.nbins; base += 4 * kScanThreads) {
-        const int k0 = base + 4 * threadIdx.x;
-        int v[4] = {0, 0, 0, 0};
-        if (k0 + 3 < b.nbins) {
-            int4 q = *reinterpret_cast<const int4*>(b.bin_count + k0);
-            v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
-            *reinterpret_cast<int4*>(b.bin_count + k0) = make_int4(0, 0, 0, 0);
+    for (int base = 0; base < b.nbins; base += IPT * kScanThreads) {
+        const int k0 = base + IPT * threadIdx.x;
+        int v[IPT];
+        if (k0 + IPT <= b.nbins) {
+#pragma unroll
+            for (int q = 0; q < IPT / 4; ++q) {
+                int4 w = *reinterpret_cast<const int4*>(b.bin_count + k0 + 4 * q);
+                v[4 * q] = w.x; v[4 * q + 1] = w.y; v[4 * q + 2] = w.z; v[4 * q + 3] = w.w;
+                *reinterpret_cast<int4*>(b.bin_count + k0 + 4 * q) = make_int4(0, 0, 0, 0);
+            }
         } else {
-            for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int e = 0; e < IPT; ++e) {
+                v[e] = 0;
                 if (k0 + e < b.nbins) {
                     v[e] = b.bin_count[k0 + e];
                     b.bin_count[k0 + e] = 0;
                 }
+            }
         }
-        const int tsum = v[0] + v[1] + v[2] + v[3];
+        int tsum = 0;
+#pragma unroll
+        for (int e = 0; e < IPT; ++e) tsum += v[e];
         int incl = tsum;
         for (int o = 1; o < kWave; o <<= 1) {
             int u = __shfl_up(incl, o, kWave);
@@ -76,9 +108,21 @@ __device__ inline void block_scan_bins(const BinParams& b)
             total += t;
         }
         int run = carry_s + wbase + incl - tsum;
-        for (int e = 0; e < 4; ++e) {
-            if (k0 + e < b.nbins) b.bin_start[k0 + e] = run;
-            run += v[e];
+        if (k0 + IPT <= b.nbins) {
+#pragma unroll
+            for (int q = 0; q < IPT / 4; ++q) {
+                int4 w;
+                w.x = run; run += v[4 * q];
+                w.y = run; run += v[4 * q + 1];
+                w.z = run; run += v[4 * q + 2];
+                w.w = run; run += v[4 * q + 3];
+                *reinterpret_cast<int4*>(b.bin_start + k0 + 4 * q) = w;
+            }
+        } else {
+            for (int e = 0; e < IPT; ++e) {
+                if (k0 + e < b.nbins) b.bin_start[k0 + e] = run;
+                run += v[e];
+            }
         }
         __syncthreads();
         if (threadIdx.x == 0) carry_s += total;
@@ -86,6 +130,27 @@ __device__ inline void block_scan_bins(const BinParams& b)
     }
     if (threadIdx.x == 0) b.bin_start[b.nbins] = carry_s;
     __syncthreads();
+}
+
+// Placement of the agents into their bins by rank, then the stable order: an
+// agent's final slot counts the smaller ids of its own bin.  Whole-grid
+// version in two kernels; this one-block version runs inside the finalize.
+__device__ inline void place_agent(const BinParams& b, int a)
+{
+    int k = b.key[a];
+    if (k >= 0) b.perm_u[b.bin_start[k] + b.rank[a]] = a;
+}
+__device__ inline void sort_agent(const BinParams& b, int a)
+{
+    int k = b.key[a];
+    if (k < 0) return;
+    int s0 = b.bin_start[k], s1 = b.bin_start[k + 1];
+    int below = 0;
+    for (int s = s0; s < s1; ++s) below += b.perm_u[s] < a;
+    int f = s0 + below;
+    b.perm[f] = a;
+    b.slot[a] = f;
+    b.xy[f] = make_float2(b.x[a], b.y[a]);
 }
 
 }  // namespace fps

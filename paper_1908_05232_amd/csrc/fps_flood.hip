@@ -17,10 +17,12 @@
 // rows), computes the y face above it in registers (the face below is carried
 // from the previous row), and the x face to its east from its neighbour lane's
 // state (cross-lane shuffle); the west face arrives from the neighbour lane.
-// Every face is evaluated once; no LDS staging is needed.  Each block writes
-// partials (FP64 mass / volumes, FP32 max wave speed); a one-block finalize
-// kernel at the end of the step reduces them in a fixed order, advances time
-// and sets the next time step (no cross-block fences inside the update).
+// Every face is evaluated once; no LDS staging is needed.  Each wave writes
+// partials (FP64 mass / volumes, FP32 max wave speed); a finalize kernel (one
+// block per scenario) at the end of the step reduces them in a fixed order,
+// advances time and sets the next time step (no cross-block fences inside the
+// update).  One launch covers the flood tiles of every scenario of an
+// ensemble; each wave finds its scenario and reads its parameters.
 #include "fps_device.h"
 
 namespace fps {
@@ -51,15 +53,22 @@ __device__ __forceinline__ float lane_from_below(float v)
 // interior cell (normal discharge negated at a wall).  Indices beyond the
 // ghost layer clamp into the grid (their values are never used).  The raw
 // load and the derived velocities are split so loads can be issued rows ahead.
-__device__ __forceinline__ Cell load_raw(const FvParams& p, int ii, int j)
+struct Src {
+    const float* __restrict__ h;
+    const float* __restrict__ qx;
+    const float* __restrict__ qy;
+    const float* __restrict__ z;
+};
+
+__device__ __forceinline__ Cell load_raw(const Src& src, const FvParams& p, int ii, int j)
 {
     int jj = min(max(j, 0), p.ny - 1);
     size_t k = (size_t)jj * p.nx + ii;
     Cell c;
-    c.h = p.h[k];
-    c.qx = p.qx[k];
-    c.qy = p.qy[k];
-    c.z = p.z[k];
+    c.h = src.h[k];
+    c.qx = src.qx[k];
+    c.qy = src.qy[k];
+    c.z = src.z[k];
     return c;
 }
 
@@ -147,17 +156,38 @@ __device__ __forceinline__ int xcd_tile_block(int b, int nblocks)
     return (b & 7) * per + (b >> 3);
 }
 
-__global__ __launch_bounds__(kFvBlock) void fv_step_kernel(FvParams p)
+__global__ __launch_bounds__(kFvBlock) void fv_step_kernel(Batch B)
 {
     const int lane = threadIdx.x & (kWave - 1);
-    const int tile = xcd_tile_block(blockIdx.x, p.nblocks) * (kFvBlock / kWave) + (threadIdx.x >> 6);
+    // the wave's flattened tile, its scenario and local tile (wave-uniform)
+    const int g = __builtin_amdgcn_readfirstlane(
+        xcd_tile_block(blockIdx.x, B.fv_blocks) * (kFvBlock / kWave) + (int)(threadIdx.x >> 6));
+    int sc, tile;
+    if (B.s_only >= 0) {
+        sc = B.s_only;
+        tile = g;
+    } else {
+        if (g >= B.total_tiles) return;
+        sc = find_scenario(B.tile_off, B.S, g);
+        tile = g - B.tile_off[sc];
+    }
+    const FvParams& p = B.scn[sc].fv;
+    if (tile >= p.ntiles) return;
+    DevState* st = p.st;
+    if (!st->active || flood_skipped(st)) return;
+    const int cur = st->cur;
+    const Src src{p.h[cur], p.qx[cur], p.qy[cur], p.z};
+    float* __restrict__ ho = p.h[cur ^ 1];
+    float* __restrict__ qxo = p.qx[cur ^ 1];
+    float* __restrict__ qyo = p.qy[cur ^ 1];
+    const int32_t* __restrict__ npp = p.np;
     double m_acc = 0.0, vout_acc = 0.0, vclip_acc = 0.0;
     float smax = 0.0f;
-    const float dt = p.st->dt;
-    const float inc = p.st->inc;
+    const float dt = st->dt;
+    const float inc = st->inc;
     const float lx = dt * p.inv_dx, ly = dt * p.inv_dy;
 
-    if (tile < p.ntiles) {
+    {
         const int sx = tile % p.nsx, sy = tile / p.nsx;
         const int i = sx * kStrip - 1 + lane;
         const int ii = min(max(i, 0), p.nx - 1);
@@ -170,29 +200,37 @@ __global__ __launch_bounds__(kFvBlock) void fv_step_kernel(FvParams p)
         if (p.inflow_side == FPS_SIDE_S || p.inflow_side == FPS_SIDE_N)
             inflow_col = i >= p.c0 && i < p.c1;
 
-        // rows j0-1 and j0 now, rows j0+1 and j0+2 in flight
-        Cell c = load_raw(p, ii, j0 - 1);
-        Cell cn = load_raw(p, ii, j0);
-        Cell pf1 = load_raw(p, ii, j0 + 1);
-        Cell pf2 = load_raw(p, ii, j0 + 2);
+        // Row j0-1 now, rows j0 .. j0+2 in flight.  The first pass of the loop
+        // (j = j0-1) only forms the face below row j0, so every y face goes
+        // through the same code (same rounding) whatever the tile height.
+        Cell c = load_raw(src, p, ii, j0 - 1);
+        Cell pf0 = load_raw(src, p, ii, j0);
+        Cell pf1 = load_raw(src, p, ii, j0 + 1);
+        Cell pf2 = load_raw(src, p, ii, j0 + 2);
         derive(p, c, mirror_x, j0 - 1);
-        derive(p, cn, mirror_x, j0);
-        float Fs0, Fs1, Fs2, p_dummy, pS;
-        face_flux(p, c.h, c.v, c.u, c.z, cn.h, cn.v, cn.u, cn.z,
-                  j0 == 0 && p.bc[2] == FPS_BC_WALL, Fs0, Fs1, Fs2, p_dummy, pS);
-        c = cn;
-        for (int j = j0; j < j1; ++j) {
-            Cell nb = pf1;
+        float Fs0 = 0.0f, Fs1 = 0.0f, Fs2 = 0.0f, pS = 0.0f;
+        for (int j = j0 - 1; j < j1; ++j) {
+            Cell nb = pf0;
+            pf0 = pf1;
             pf1 = pf2;
-            pf2 = load_raw(p, ii, j + 3);
+            pf2 = load_raw(src, p, ii, j + 4);
             derive(p, nb, mirror_x, j + 1);
-            const size_t k = (size_t)j * p.nx + i;
-            int npc = 0;
-            if (out_lane) npc = p.np[k];
             // north face (y normal: pass v as normal, u as tangential)
             float Fn0, Fn1, Fn2, pN, pS_next;
             face_flux(p, c.h, c.v, c.u, c.z, nb.h, nb.v, nb.u, nb.z,
-                      j + 1 == p.ny && p.bc[3] == FPS_BC_WALL, Fn0, Fn1, Fn2, pN, pS_next);
+                      (j + 1 == 0 && p.bc[2] == FPS_BC_WALL) || (j + 1 == p.ny && p.bc[3] == FPS_BC_WALL),
+                      Fn0, Fn1, Fn2, pN, pS_next);
+            if (j < j0) {
+                Fs0 = Fn0;
+                Fs1 = Fn1;
+                Fs2 = Fn2;
+                pS = pS_next;
+                c = nb;
+                continue;
+            }
+            const size_t k = (size_t)j * p.nx + i;
+            int npc = 0;
+            if (out_lane) npc = npp[k];
             // east face with the neighbour lane's cell
             float eh = lane_from_above(c.h), eu = lane_from_above(c.u);
             float ev = lane_from_above(c.v), ez = lane_from_above(c.z);
@@ -252,9 +290,9 @@ __global__ __launch_bounds__(kFvBlock) void fv_step_kernel(FvParams p)
                 if (i == p.nx - 1 && p.bc[1] == FPS_BC_TRANSMISSIVE) vout_acc += (double)Fe0 * dt * p.dy;
                 if (j == 0 && p.bc[2] == FPS_BC_TRANSMISSIVE) vout_acc -= (double)Fs0 * dt * p.dx;
                 if (j == p.ny - 1 && p.bc[3] == FPS_BC_TRANSMISSIVE) vout_acc += (double)Fn0 * dt * p.dx;
-                p.ho[k] = hn;
-                p.qxo[k] = qxn;
-                p.qyo[k] = qyn;
+                ho[k] = hn;
+                qxo[k] = qxn;
+                qyo[k] = qyn;
             }
             Fs0 = Fn0;
             Fs1 = Fn1;
@@ -263,50 +301,40 @@ __global__ __launch_bounds__(kFvBlock) void fv_step_kernel(FvParams p)
             c = nb;
         }
     }
-    // block partials, fixed reduction order; reduced by the finalize kernel
-    __shared__ double wred[kFvBlock / kWave][4];
+    // wave partials, fixed reduction order; reduced by the finalize kernel
     m_acc = wave_sum(m_acc);
     vout_acc = wave_sum(vout_acc);
     vclip_acc = wave_sum(vclip_acc);
     smax = wave_max(smax);
     if (lane == 0) {
-        int w = threadIdx.x >> 6;
-        wred[w][0] = m_acc;
-        wred[w][1] = vout_acc;
-        wred[w][2] = vclip_acc;
-        wred[w][3] = (double)smax;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-        for (int w = 0; w < kFvBlock / kWave; ++w) {
-            s0 += wred[w][0];
-            s1 += wred[w][1];
-            s2 += wred[w][2];
-            s3 = fmax(s3, wred[w][3]);
-        }
-        double* dst = &p.partials[4 * blockIdx.x];
-        dst[0] = s0;
-        dst[1] = s1;
-        dst[2] = s2;
-        dst[3] = s3;
+        double* dst = &p.partials[4 * tile];
+        dst[0] = m_acc;
+        dst[1] = vout_acc;
+        dst[2] = vclip_acc;
+        dst[3] = (double)smax;
+        if (smax > 0.0f) atomicOr(&st->wet_flag, 1);
     }
 }
 
 // Scan of the current state only: mass, wetness and the time step that the
-// next update will use (no time advance).  Same reduction as the step.
-__global__ __launch_bounds__(kFvBlock) void fv_scan_kernel(FvParams p)
+// next update will use (no time advance).  One scenario; one partial per block.
+__global__ __launch_bounds__(kFvBlock) void fv_scan_kernel(Batch B, int sc)
 {
+    const FvParams& p = B.scn[sc].fv;
+    const int cur = p.st->cur;
+    const float* __restrict__ hh = p.h[cur];
+    const float* __restrict__ qxx = p.qx[cur];
+    const float* __restrict__ qyy = p.qy[cur];
     double m_acc = 0.0;
     float smax = 0.0f;
     const int64_t nc = (int64_t)p.nx * p.ny;
     for (int64_t k = (int64_t)blockIdx.x * kFvBlock + threadIdx.x; k < nc;
-         k += (int64_t)p.nblocks * kFvBlock) {
-        float h = p.h[k];
+         k += (int64_t)gridDim.x * kFvBlock) {
+        float h = hh[k];
         m_acc += (double)h;
         if (h > p.eps) {
             float r = rcp(h);
-            float u = p.qx[k] * r, v = p.qy[k] * r;
+            float u = qxx[k] * r, v = qyy[k] * r;
             float cel = sqrt_fast(p.g * h);
             smax = fmaxf(smax, fmaxf((fabsf(u) + cel) * p.inv_dx, (fabsf(v) + cel) * p.inv_dy));
         }
@@ -333,91 +361,134 @@ __global__ __launch_bounds__(kFvBlock) void fv_scan_kernel(FvParams p)
     }
 }
 
-// End of a step (one block of kScanThreads): reduce the flood partials in a
-// fixed order, advance time, set the next CFL time step (sec. 3) and inflow
-// depth; apply the sandbag drops of the step to the barrier line (sec. 2.4);
-// scan the histogram of the new agent bins.
-__global__ __launch_bounds__(kScanThreads) void finalize_kernel(FinParams f)
+// End of a step, one block of kScanThreads per scenario: reduce the flood
+// partials in a fixed order, advance time, set the next CFL time step (sec. 3)
+// and inflow depth; apply the sandbag drops of the step to the barrier line
+// (sec. 2.4); scan the histogram of the new agent bins (and, for small agent
+// counts, place the agents in bin order).  mode 0 ends a step, mode 1 only
+// recomputes the time step and mass of the current state.
+__global__ __launch_bounds__(kScanThreads) void finalize_kernel(Batch B, int mode, int s_first)
 {
-    const FvParams& p = f.fv;
-    __shared__ double red[kScanThreads][4];
+    const int sc = s_first + blockIdx.x;
+    const Scn& S = B.scn[sc];
+    const FvParams& p = S.fv;
+    DevState* st = p.st;
+    if (mode == 0 && !st->active) return;
+    const bool skipped = mode == 0 && flood_skipped(st);
+    __shared__ double red[kScanThreads / kWave][4];
     double m = 0.0, vo = 0.0, vc = 0.0, sm = 0.0;
-    for (int b = threadIdx.x; b < p.nblocks; b += kScanThreads) {
-        m += p.partials[4 * b + 0];
-        vo += p.partials[4 * b + 1];
-        vc += p.partials[4 * b + 2];
-        sm = fmax(sm, p.partials[4 * b + 3]);
-    }
-    red[threadIdx.x][0] = m;
-    red[threadIdx.x][1] = vo;
-    red[threadIdx.x][2] = vc;
-    red[threadIdx.x][3] = sm;
-    __syncthreads();
-    for (int s = kScanThreads / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) {
-            red[threadIdx.x][0] += red[threadIdx.x + s][0];
-            red[threadIdx.x][1] += red[threadIdx.x + s][1];
-            red[threadIdx.x][2] += red[threadIdx.x + s][2];
-            red[threadIdx.x][3] = fmax(red[threadIdx.x][3], red[threadIdx.x + s][3]);
+    if (!skipped) {
+        for (int b = threadIdx.x; b < p.ntiles; b += kScanThreads) {
+            m += p.partials[4 * b + 0];
+            vo += p.partials[4 * b + 1];
+            vc += p.partials[4 * b + 2];
+            sm = fmax(sm, p.partials[4 * b + 3]);
         }
-        __syncthreads();
     }
+    m = wave_sum(m);
+    vo = wave_sum(vo);
+    vc = wave_sum(vc);
+    for (int o = 32; o > 0; o >>= 1) sm = fmax(sm, __shfl_xor(sm, o, kWave));
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        int w = threadIdx.x >> 6;
+        red[w][0] = m;
+        red[w][1] = vo;
+        red[w][2] = vc;
+        red[w][3] = sm;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        DevState* st = p.st;
-        float smax = (float)red[0][3];
-        int wet = smax > 0.0f;
-        double mass = red[0][0] * p.dxdy;
-        if (p.mode == 0) {
+        for (int w = 1; w < kScanThreads / kWave; ++w) {
+            red[0][0] += red[w][0];
+            red[0][1] += red[w][1];
+            red[0][2] += red[w][2];
+            red[0][3] = fmax(red[0][3], red[w][3]);
+        }
+        if (mode == 0) {
             float dt_used = st->dt;
-            st->v_out += red[0][1];
-            st->v_clip += red[0][2] * p.dxdy;
-            st->v_in += (double)st->inc * (double)p.n_inflow * p.dxdy;
             st->t += (double)dt_used;
             st->step += 1;
             st->dt_prev = dt_used;
+            if (!skipped) {
+                st->v_out += red[0][1];
+                st->v_clip += red[0][2] * p.dxdy;
+                st->v_in += (double)st->inc * (double)p.n_inflow * p.dxdy;
+                st->cur ^= 1;
+                st->flood_steps += 1;
+                st->settled = 1;
+            }
         }
-        st->mass = mass;
-        st->any_wet = wet;
-        float dtn = wet ? fminf(p.cfl / smax, p.dt_max) : p.dt_max;
-        st->dt = dtn;
+        if (!skipped) {
+            float smax = (float)red[0][3];
+            st->mass = red[0][0] * p.dxdy;
+            st->any_wet = smax > 0.0f;
+            st->dt = st->any_wet ? fminf(p.cfl / smax, p.dt_max) : p.dt_max;
+        }
+        float dtn = st->dt;
         float inc = 0.0f;
         if (p.inflow_side >= 0) {
             double dn = p.inflow_side <= 1 ? (double)p.dx : (double)p.dy;
             inc = (float)(hydro_integral(st, st->t, st->t + (double)dtn) / dn);
         }
         st->inc = inc;
-        if (!isfinite(mass) || !(dtn > 0.0f) || !isfinite(dtn)) st->status = FPS_E_NUMERIC;
+        if (!isfinite(st->mass) || !(dtn > 0.0f) || !isfinite(dtn)) st->status = FPS_E_NUMERIC;
+        st->wet_flag = 0;
         // sandbag write-back: drops of this step applied to the barrier line in order
-        if (f.do_barrier) {
-            const BarrierParams& B = f.bar;
+        const BarrierParams& Bb = S.bar;
+        if (mode == 0 && S.na > 0) {
             int D = st->drops;
             st->drops = 0;
             st->drops_total += D;
-            if (!st->done && B.nline > 0) {
+            if (!st->done && Bb.nline > 0) {
                 int bags = st->bags + D;
-                int active = st->active, layers = st->layers_done, fin = 0;
-                while (!fin && bags >= B.bags_per) {
-                    bags -= B.bags_per;
-                    float th = layers == B.n_layers - 1 ? B.t_last : B.t_bag;
-                    B.z[B.line[active]] += th;
-                    active += 1;
-                    if (active == B.nline) {
-                        active = 0;
+                int cell = st->active_cell, layers = st->layers_done, fin = 0;
+                while (!fin && bags >= Bb.bags_per) {
+                    bags -= Bb.bags_per;
+                    float th = layers == Bb.n_layers - 1 ? Bb.t_last : Bb.t_bag;
+                    Bb.z[Bb.line[cell]] += th;
+                    cell += 1;
+                    if (cell == Bb.nline) {
+                        cell = 0;
                         layers += 1;
-                        if (layers >= B.n_layers) fin = 1;
+                        if (layers >= Bb.n_layers) fin = 1;
                     }
                 }
                 st->bags = bags;
-                st->active = active;
+                st->active_cell = cell;
                 st->layers_done = layers;
                 st->done = fin;
             }
         }
+        if (mode == 0) st->active = !(st->t_end > 0.0) || st->t < st->t_end;
     }
-    if (f.do_scan) {
+    if (mode == 0 && S.na > 0) {
         __syncthreads();
-        block_scan_bins(f.bins);
+        block_scan_bins(S.bins);
+        if (S.inline_place) {
+            for (int a = threadIdx.x; a < S.bins.na; a += kScanThreads) place_agent(S.bins, a);
+            __syncthreads();
+            for (int a = threadIdx.x; a < S.bins.na; a += kScanThreads) sort_agent(S.bins, a);
+        }
     }
+}
+
+// After the last step of a call: scenarios whose state sits in the scratch
+// buffer copy it back to the caller's buffers (grid: blocks x scenarios).
+__global__ void sync_back_kernel(Batch B)
+{
+    const FvParams& p = B.scn[blockIdx.y].fv;
+    if (p.st->cur == 0) return;
+    const int64_t nc = (int64_t)p.nx * p.ny;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nc;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        p.h[0][k] = p.h[1][k];
+        p.qx[0][k] = p.qx[1][k];
+        p.qy[0][k] = p.qy[1][k];
+    }
+}
+__global__ void reset_cur_kernel(Batch B)
+{
+    for (int s = threadIdx.x; s < B.S; s += blockDim.x) B.scn[s].fv.st->cur = 0;
 }
 
 }  // namespace
@@ -432,26 +503,42 @@ int fv_rows_per_wave(int nx, int ny)
     return H;
 }
 
-int fv_blocks(int nx, int ny, int H)
+int fv_tiles(int nx, int ny, int H)
 {
     const int64_t nsx = (nx + kStrip - 1) / kStrip;
-    const int64_t tiles = nsx * ((ny + H - 1) / H);
+    return (int)(nsx * ((ny + H - 1) / H));
+}
+
+int fv_blocks_for_tiles(int64_t tiles)
+{
     const int64_t blocks = (tiles + kFvBlock / kWave - 1) / (kFvBlock / kWave);
     return (int)((blocks + 7) / 8 * 8);    // a multiple of the 8 XCDs
 }
 
-hipError_t launch_finalize(const FinParams& f, hipStream_t s)
+hipError_t launch_fv(const Batch& b, hipStream_t s)
 {
-    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kScanThreads), 0, s, f);
+    if (b.fv_blocks > 0)
+        hipLaunchKernelGGL(fv_step_kernel, dim3(b.fv_blocks), dim3(kFvBlock), 0, s, b);
     return hipGetLastError();
 }
 
-hipError_t launch_fv(const FvParams& p, hipStream_t s)
+hipError_t launch_fv_scan(const Batch& b, int scenario, int ntiles, hipStream_t s)
 {
-    if (p.mode == 0)
-        hipLaunchKernelGGL(fv_step_kernel, dim3(p.nblocks), dim3(kFvBlock), 0, s, p);
-    else
-        hipLaunchKernelGGL(fv_scan_kernel, dim3(p.nblocks), dim3(kFvBlock), 0, s, p);
+    hipLaunchKernelGGL(fv_scan_kernel, dim3(ntiles), dim3(kFvBlock), 0, s, b, scenario);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const Batch& b, int mode, int s_first, int count, hipStream_t s)
+{
+    hipLaunchKernelGGL(finalize_kernel, dim3(count), dim3(kScanThreads), 0, s, b, mode, s_first);
+    return hipGetLastError();
+}
+
+hipError_t launch_sync_back(const Batch& b, int64_t max_cells, hipStream_t s)
+{
+    int gx = (int)std::min<int64_t>((max_cells + 255) / 256, 2048);
+    hipLaunchKernelGGL(sync_back_kernel, dim3(std::max(gx, 1), b.S), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(reset_cur_kernel, dim3(1), dim3(256), 0, s, b);
     return hipGetLastError();
 }
 

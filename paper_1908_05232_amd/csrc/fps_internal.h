@@ -1,5 +1,12 @@
-// Internal declarations of libfps: device-resident step state, kernel
+// Internal declarations of libfps: device-resident step state, per-scenario
 // parameter blocks and launchers.  Not part of the public ABI (include/fps.h).
+//
+// Every kernel is scenario-indexed: the parameters of each scenario of an
+// ensemble live in a device array of Scn records, flood tiles and agents of
+// all scenarios are flattened into one launch, and each scenario keeps its own
+// time, time step, ping-pong parity and active flag in its DevState.  A
+// standalone simulation is an ensemble of one.  Launch arguments are the same
+// every step, so a step can be captured once in a HIP graph and replayed.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -16,12 +23,14 @@ constexpr int kStrip = kWave - 2;      // output columns of one wave in the floo
 constexpr int kFvBlock = 256;          // 4 waves
 constexpr int kPedBlock = 64;
 constexpr int kScanThreads = 1024;
-constexpr int kMaskBits = 128;       // obstacle bitmask per cell (uint4)
 constexpr int kMaxHydro = 64;
+constexpr int kMaskBits = 128;         // obstacle bitmask per cell (uint4)
+constexpr int kInlinePlace = 8192;     // agent counts binned inside the one-block finalize
 
 // Scalars that live in device memory so that n steps run without the host.
 struct DevState {
     double t;              // time at the start of the next step
+    double t_end;          // the scenario stops advancing at t >= t_end (<= 0: never)
     double mass;           // sum h dx dy after the last step
     double v_in, v_out, v_clip;
     double hyd_t[kMaxHydro], hyd_q[kMaxHydro];
@@ -33,68 +42,59 @@ struct DevState {
     int32_t nh;
     int32_t any_wet;
     int32_t status;
-    uint32_t fv_ctr, ped_ctr;
+    int32_t cur;           // which of the two flood buffers holds the state
+    int32_t active;        // 0 once t >= t_end
+    int32_t flood_steps;   // steps whose flood update ran (the rest were dry and skipped)
     // sandbag barrier (sec. 2.4)
-    int32_t active, layers_done, bags, done, drops, drops_total;
-    int32_t pad[2];
+    int32_t layers_done, active_cell, bags, done, drops, drops_total;
+    int32_t wet_flag;      // set by any flood wave with a wet cell; cleared by the finalize
+    int32_t settled;       // the state came out of a flood update (dry cells carry no discharge)
 };
 
 struct FvParams {
-    const float* __restrict__ h;
-    const float* __restrict__ qx;
-    const float* __restrict__ qy;
-    float* __restrict__ ho;
-    float* __restrict__ qxo;
-    float* __restrict__ qyo;
-    const float* __restrict__ z;
-    const int32_t* __restrict__ np;
+    float* h[2];           // ping-pong flood state; [0] is the caller's buffer
+    float* qx[2];
+    float* qy[2];
+    const float* z;
+    const int32_t* np;
     DevState* st;
-    double* partials;      // [nblocks][4]: mass sum, outflow volume, clipped depth sum, max speed
-    // (the flood kernels only write them; the finalize kernel reduces them)
-    int nx, ny, H, nsx, ntiles, nblocks;
+    double* partials;      // [ntiles][4]: mass sum, outflow volume, clipped depth, max speed
+    int nx, ny, H, nsx, ntiles;
     int bc[4];
     int inflow_side, c0, c1, n_inflow;
     int np_cap;
-    int mode;              // 0 = step, 1 = scan the current state only (first time step)
     float dx, dy, inv_dx, inv_dy, g, half_g, eps, cfl, dt_max, n_base;
     double dxdy;
 };
 
 struct PedParams {
-    float* __restrict__ x;
-    float* __restrict__ y;
-    float* __restrict__ vx;
-    float* __restrict__ vy;
-    const float* __restrict__ vbase;
-    const uint8_t* __restrict__ role;
-    uint8_t* __restrict__ state;
-    uint8_t* __restrict__ cls;
-    int32_t* __restrict__ dest;
-    float* __restrict__ timer;
+    float* x;
+    float* y;
+    float* vx;
+    float* vy;
+    const float* vbase;
+    const uint8_t* role;
+    uint8_t* state;
+    uint8_t* cls;
+    int32_t* dest;
+    float* timer;
     int na;
-    const float* __restrict__ h;   // flood state after this step's update
-    const float* __restrict__ qx;
-    const float* __restrict__ qy;
-    float* z;
     int32_t* np;
-    const float* __restrict__ dist;
-    const uint8_t* __restrict__ walk;
+    const float* dist;
+    const uint8_t* walk;
     int n_dest, n_exit;
-    const int32_t* __restrict__ bin_start;   // bins of the positions at the start of the step
-    const float2* __restrict__ xy;           // positions in bin order
-    const int32_t* __restrict__ slot;        // each agent's place in that order
-    const uint4* __restrict__ wmask;         // per cell: obstacle cells within r_cut (bit per offset)
-    int32_t* bin_count;                      // histogram of the new positions
+    const int32_t* bin_start;   // bins of the positions at the start of the step
+    const float2* xy;           // positions in bin order
+    const int32_t* slot;        // each agent's place in that order
+    const uint4* wmask;         // per cell: obstacle cells within r_cut (bit per offset)
+    int32_t* bin_count;         // histogram of the new positions
     int32_t* rank;
     int32_t* key;
-    DevState* st;
-    int nx, ny, bsx, bsy, nbx, nby, Rx, Ry, nblocks;
-    int use_wmask;                           // masks valid: (2Rx+1)(2Ry+1) <= 128
+    int nx, ny, bsx, bsy, nbx, nby, Rx, Ry;
+    int use_wmask;              // masks valid: (2Rx+1)(2Ry+1) <= 128
     float dx, dy, eps, tau, a_over_m, inv_b, two_r, radius, r_cut, r_arrive;
     float v_class[5], hr_t[3], pick_s, drop_s;
     int storage_dest, barrier_dest;
-    const double* fv_partials;               // flood partials of this step (wetness)
-    int fv_blocks;
 };
 
 // Sandbag barrier of sec. 2.4: the fill order and layer rules.
@@ -123,21 +123,38 @@ struct BinParams {
     float dx, dy;
 };
 
-// End of a step, one block: reduction of the flood partials (time, next time
-// step, inflow, volumes), sandbag write-back, and the scan of the new bins.
-struct FinParams {
+// One scenario: everything its kernels need.
+struct Scn {
     FvParams fv;
-    BarrierParams bar;
+    PedParams ped;
     BinParams bins;
-    int do_barrier, do_scan;
+    BarrierParams bar;
+    int na;
+    int inline_place;      // agents placed in their bins inside the finalize block
+};
+
+// Flattened launch description of an ensemble (device arrays).
+struct Batch {
+    const Scn* scn;
+    const int* tile_off;   // [S+1] prefix of flood tiles (waves) per scenario
+    const int* agent_off;  // [S+1] prefix of agents per scenario
+    int S;
+    int total_tiles, total_agents;
+    int fv_blocks;         // launched flood blocks: a multiple of 8 covering total_tiles
+    int s_only;            // >= 0: restrict the flood launch to one scenario (tuning)
 };
 
 // launchers (stream-ordered, no synchronisation)
-hipError_t launch_finalize(const FinParams& f, hipStream_t s);
-hipError_t launch_fv(const FvParams& p, hipStream_t s);
-int fv_blocks(int nx, int ny, int H);
+int fv_blocks_for_tiles(int64_t tiles);
+int fv_tiles(int nx, int ny, int H);
 int fv_rows_per_wave(int nx, int ny);
-hipError_t launch_ped(const PedParams& p, hipStream_t s);
+hipError_t launch_fv(const Batch& b, hipStream_t s);
+hipError_t launch_fv_scan(const Batch& b, int scenario, int ntiles, hipStream_t s);
+hipError_t launch_finalize(const Batch& b, int mode, int s_first, int count, hipStream_t s);
+hipError_t launch_sync_back(const Batch& b, int64_t max_cells, hipStream_t s);
+hipError_t launch_ped(const Batch& b, hipStream_t s);
+hipError_t launch_bin_place_all(const Batch& b, hipStream_t s);
+hipError_t launch_bin_sort_all(const Batch& b, hipStream_t s);
 hipError_t launch_bin_keys(const BinParams& b, hipStream_t s);   // keys + ranks from positions
 hipError_t launch_bin_scan(const BinParams& b, hipStream_t s);
 hipError_t launch_bin_place(const BinParams& b, hipStream_t s);
@@ -148,9 +165,9 @@ hipError_t launch_hazard(const float* h, const float* qx, const float* qy, float
                          float eps, hipStream_t s);
 hipError_t launch_agent_stats(const uint8_t* state, const uint8_t* cls, int na, int32_t* out11,
                               hipStream_t s);
-// bad2[0]: agents outside the domain; bad2[1]: invalid role / state / destination
 hipError_t launch_wall_mask(const uint8_t* walk, uint4* mask, int nx, int ny, int Rx, int Ry,
                             hipStream_t s);
+// bad2[0]: agents outside the domain; bad2[1]: invalid role / state / destination
 hipError_t launch_check_agents(const float* x, const float* y, const uint8_t* role,
                                const uint8_t* state, const int32_t* dest, int na, float lx,
                                float ly, int n_dest, int32_t* bad2, hipStream_t s);

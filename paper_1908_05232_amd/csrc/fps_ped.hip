@@ -55,8 +55,16 @@ __device__ __forceinline__ int nearest_exit(const PedParams& p, int ci, int cj)
     return best;
 }
 
-__device__ void agent_step(const PedParams& p, int a, float dt, int any_wet, int done,
-                           int& drop)
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// One agent, one step.  The loads are grouped in three dependent rounds: the
+// agent record; everything addressed by its cell (flood state, the nine
+// distances of its destination field, the obstacle mask, the bin bounds of
+// the three bin rows); then the neighbours' positions.  Cell and bin indices
+// use IEEE division so they match the FP32 decisions of the reference exactly.
+__device__ void agent_step(const PedParams& p, const float* __restrict__ fh,
+                           const float* __restrict__ fqx, const float* __restrict__ fqy, int a,
+                           float dt, int any_wet, int done, int& drop)
 {
     const int st0 = p.state[a];
     if (st0 == FPS_ST_EXITED) {
@@ -64,19 +72,38 @@ __device__ void agent_step(const PedParams& p, int a, float dt, int any_wet, int
         return;
     }
     const float x = p.x[a], y = p.y[a];
+    float vx = p.vx[a], vy = p.vy[a];
+    const int role = p.role[a];
+    int dest = p.dest[a];
+    const float vbase = p.vbase[a];
+    const int self = p.slot[a];
     const int ci = clampi(cell_of(x, p.dx, p.nx), 0, p.nx - 1);
     const int cj = clampi(cell_of(y, p.dy, p.ny), 0, p.ny - 1);
     const size_t c = (size_t)cj * p.nx + ci;
-    const int role = p.role[a];
-    // hazard of the containing cell
+    const size_t nc = (size_t)p.nx * p.ny;
+    // round 2: cell-addressed loads
+    const float h = fh[c], qxc = fqx[c], qyc = fqy[c];
+    uint4 m4 = make_uint4(0, 0, 0, 0);
+    if (p.use_wmask) m4 = p.wmask[c];
+    const int bi = ci / p.bsx, bj = cj / p.bsy;
+    const int qi0 = max(bi - 1, 0), qi1 = min(bi + 1, p.nbx - 1);
+    int seg0[3], seg1[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const int qj = bj - 1 + r;
+        const bool ok = qj >= 0 && qj < p.nby;
+        const int row = ok ? qj : bj;
+        seg0[r] = p.bin_start[row * p.nbx + qi0];
+        seg1[r] = ok ? p.bin_start[row * p.nbx + qi1 + 1] : seg0[r];
+    }
+    // hazard of the containing cell (Table 1)
     int cls;
     float v0;
-    const float h = p.h[c];
     if (!(h > p.eps)) {
         cls = FPS_CLS_DRY;
-        v0 = p.vbase[a];
+        v0 = vbase;
     } else {
-        float u = p.qx[c] / h, v = p.qy[c] / h;
+        float u = qxc / h, v = qyc / h;
         float hr = (fmaxf(fabsf(u), fabsf(v)) + 0.5f) * h;
         cls = hr < p.hr_t[0] ? FPS_CLS_LOW
             : hr < p.hr_t[1] ? FPS_CLS_MEDIUM
@@ -85,7 +112,6 @@ __device__ void agent_step(const PedParams& p, int a, float dt, int any_wet, int
     }
     p.cls[a] = (uint8_t)cls;
     int st = st0;
-    int dest = p.dest[a];
     if (dest < 0) {
         if (role == FPS_ROLE_EVACUEE) {
             dest = nearest_exit(p, ci, cj);
@@ -99,7 +125,6 @@ __device__ void agent_step(const PedParams& p, int a, float dt, int any_wet, int
         st = FPS_ST_EVAC;
         dest = nearest_exit(p, ci, cj);
     }
-    float vx = p.vx[a], vy = p.vy[a];
     float xn = x, yn = y;
     bool moving = true;
     if (st == FPS_ST_PICKING || st == FPS_ST_DROPPING) {
@@ -124,22 +149,28 @@ __device__ void agent_step(const PedParams& p, int a, float dt, int any_wet, int
         vx = 0.0f;
         vy = 0.0f;
     } else {
-        // desired direction from the distance field
-        float ex = 0.0f, ey = 0.0f;
-        float here = dist_at(p, dest, ci, cj);
+        // desired direction from the distance field: the nine distances at once
+        const float* D = p.dist + (size_t)dest * nc;
+        const int offx[8] = {1, 0, -1, 0, 1, -1, -1, 1};
+        const int offy[8] = {0, 1, 0, -1, 1, 1, -1, -1};
+        float dk[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int qi = ci + offx[k], qj = cj + offy[k];
+            const bool in = qi >= 0 && qj >= 0 && qi < p.nx && qj < p.ny;
+            const float val = D[(size_t)clampi(qj, 0, p.ny - 1) * p.nx + clampi(qi, 0, p.nx - 1)];
+            dk[k] = in ? val : __builtin_inff();
+        }
+        const float here = D[c];
         int ti = ci, tj = cj;
         bool has_target = true;
         if (!(here == 0.0f)) {
-            const int offx[8] = {1, 0, -1, 0, 1, -1, -1, 1};
-            const int offy[8] = {0, 1, 0, -1, 1, 1, -1, -1};
             float best = here;
             int kb = -1;
+#pragma unroll
             for (int k = 0; k < 8; ++k) {
-                int qi = ci + offx[k], qj = cj + offy[k];
-                if (qi < 0 || qj < 0 || qi >= p.nx || qj >= p.ny) continue;
-                float dk = dist_at(p, dest, qi, qj);
-                if (dk < best) {
-                    best = dk;
+                if (dk[k] < best) {
+                    best = dk[k];
                     kb = k;
                 }
             }
@@ -149,41 +180,38 @@ __device__ void agent_step(const PedParams& p, int a, float dt, int any_wet, int
                 tj = cj + offy[kb];
             }
         }
+        float ex = 0.0f, ey = 0.0f;
         if (has_target) {
             float tx = ((float)ti + 0.5f) * p.dx - x, ty = ((float)tj + 0.5f) * p.dy - y;
-            float len = sqrtf(tx * tx + ty * ty);
-            if (len > 0.0f) {
-                ex = tx / len;
-                ey = ty / len;
+            float len2 = tx * tx + ty * ty;
+            if (len2 > 0.0f) {
+                float il = __builtin_amdgcn_rsqf(len2);
+                ex = tx * il;
+                ey = ty * il;
             }
         }
         // relaxation toward the desired velocity
-        float k = expf(-dt / p.tau);
+        float k = __expf(-dt / p.tau);
         vx = v0 * ex + (vx - v0 * ex) * k;
         vy = v0 * ey + (vy - v0 * ey) * k;
         // repulsion: neighbours in the 3x3 bins, in (bin, id) order; the three
         // bins of one bin row are one contiguous run of the sorted positions
         float fx = 0.0f, fy = 0.0f;
-        const int bi = ci / p.bsx, bj = cj / p.bsy;
-        const int qi0 = max(bi - 1, 0), qi1 = min(bi + 1, p.nbx - 1);
-        const int self = p.slot[a];
-        for (int qj = max(bj - 1, 0); qj <= min(bj + 1, p.nby - 1); ++qj) {
-            const int s0 = p.bin_start[qj * p.nbx + qi0];
-            const int s1 = p.bin_start[qj * p.nbx + qi1 + 1];
-            for (int s = s0; s < s1; ++s) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            for (int s = seg0[r]; s < seg1[r]; ++s) {
                 if (s == self) continue;
                 float2 o = p.xy[s];
                 float rx = x - o.x, ry = y - o.y;
-                float d = sqrtf(rx * rx + ry * ry);
+                float d = __builtin_amdgcn_sqrtf(rx * rx + ry * ry);
                 if (!(d > 0.0f) || !(d < p.r_cut)) continue;
-                float w = p.a_over_m * expf((p.two_r - d) * p.inv_b) / d;
+                float w = p.a_over_m * __expf((p.two_r - d) * p.inv_b) * rcp(d);
                 fx += w * rx;
                 fy += w * ry;
             }
         }
         // obstacle cells within r_cut, in row-major offset order
         if (p.use_wmask) {
-            const uint4 m4 = p.wmask[c];
             const uint32_t mw[4] = {m4.x, m4.y, m4.z, m4.w};
             const int wdth = 2 * p.Rx + 1;
             for (int w = 0; w < 4; ++w) {
@@ -195,9 +223,9 @@ __device__ void agent_step(const PedParams& p, int a, float dt, int any_wet, int
                     float px = fminf(fmaxf(x, (float)wi * p.dx), (float)(wi + 1) * p.dx);
                     float py = fminf(fmaxf(y, (float)wj * p.dy), (float)(wj + 1) * p.dy);
                     float rx = x - px, ry = y - py;
-                    float d = sqrtf(rx * rx + ry * ry);
+                    float d = __builtin_amdgcn_sqrtf(rx * rx + ry * ry);
                     if (!(d > 0.0f) || !(d < p.r_cut)) continue;
-                    float wt = p.a_over_m * expf((p.radius - d) * p.inv_b) / d;
+                    float wt = p.a_over_m * __expf((p.radius - d) * p.inv_b) * rcp(d);
                     fx += wt * rx;
                     fy += wt * ry;
                 }
@@ -213,9 +241,9 @@ __device__ void agent_step(const PedParams& p, int a, float dt, int any_wet, int
                     float px = fminf(fmaxf(x, (float)wi * p.dx), (float)(wi + 1) * p.dx);
                     float py = fminf(fmaxf(y, (float)wj * p.dy), (float)(wj + 1) * p.dy);
                     float rx = x - px, ry = y - py;
-                    float d = sqrtf(rx * rx + ry * ry);
+                    float d = __builtin_amdgcn_sqrtf(rx * rx + ry * ry);
                     if (!(d > 0.0f) || !(d < p.r_cut)) continue;
-                    float wt = p.a_over_m * expf((p.radius - d) * p.inv_b) / d;
+                    float wt = p.a_over_m * __expf((p.radius - d) * p.inv_b) * rcp(d);
                     fx += wt * rx;
                     fy += wt * ry;
                 }
@@ -223,12 +251,12 @@ __device__ void agent_step(const PedParams& p, int a, float dt, int any_wet, int
         }
         vx += dt * fx;
         vy += dt * fy;
-        float sp = sqrtf(vx * vx + vy * vy);
-        if (sp > v0) {
+        float sp2 = vx * vx + vy * vy;
+        if (sp2 > v0 * v0) {
             if (v0 > 0.0f) {
-                float s = v0 / sp;
-                vx *= s;
-                vy *= s;
+                float sc = v0 * __builtin_amdgcn_rsqf(sp2);
+                vx *= sc;
+                vy *= sc;
             } else {
                 vx = 0.0f;
                 vy = 0.0f;
@@ -237,19 +265,21 @@ __device__ void agent_step(const PedParams& p, int a, float dt, int any_wet, int
         // move, rejecting an axis that lands in an obstacle or outside
         xn = x + dt * vx;
         ni = cell_of(xn, p.dx, p.nx);
-        if (ni < 0 || ni >= p.nx || !p.walk[(size_t)cj * p.nx + ni]) {
+        const int ny_try = cell_of(y + dt * vy, p.dy, p.ny);
+        const bool okx = ni >= 0 && ni < p.nx && p.walk[(size_t)cj * p.nx + ni];
+        if (!okx) {
             xn = x;
             vx = 0.0f;
             ni = ci;
         }
         yn = y + dt * vy;
-        nj = cell_of(yn, p.dy, p.ny);
+        nj = ny_try;
         if (nj < 0 || nj >= p.ny || !p.walk[(size_t)nj * p.nx + ni]) {
             yn = y;
             vy = 0.0f;
             nj = cj;
         }
-        if (dist_at(p, dest, ni, nj) <= p.r_arrive) {
+        if (D[(size_t)nj * p.nx + ni] <= p.r_arrive) {
             if (st == FPS_ST_EVAC) {
                 st = FPS_ST_EXITED;
             } else if (st == FPS_ST_TO_STORAGE) {
@@ -287,34 +317,37 @@ __device__ void agent_step(const PedParams& p, int a, float dt, int any_wet, int
     }
 }
 
-__global__ __launch_bounds__(kPedBlock) void ped_step_kernel(PedParams p)
+// One wave (= one block) per 64 agents of one scenario: the agent ranges of
+// the scenarios are padded to whole waves in the flattened index.
+__global__ __launch_bounds__(kPedBlock) void ped_step_kernel(Batch B)
 {
-    __shared__ int drops, active, wet;
-    if (threadIdx.x == 0) {
-        drops = 0;
-        active = 0;
-        wet = 0;
-    }
-    __syncthreads();
-    // evacuation trigger: some cell wet after this step's flood update (any
-    // block of the flood kernel saw a positive wave speed)
-    for (int b = threadIdx.x; b < p.fv_blocks; b += kPedBlock)
-        if (p.fv_partials[4 * b + 3] > 0.0) wet = 1;
-    __syncthreads();
-    const DevState* st = p.st;
+    const int g0 = blockIdx.x * kPedBlock;
+    if (g0 >= B.total_agents) return;
+    const int sc = find_scenario(B.agent_off, B.S, g0);
+    const Scn& S = B.scn[sc];
+    const DevState* st = S.fv.st;
+    if (!st->active) return;
+    const int a = g0 - B.agent_off[sc] + (int)threadIdx.x;
+    const bool skipped = flood_skipped(st);
+    // the flood state this step's pedestrians see: the new one, or the
+    // unchanged one when the dry step skipped the flood update
+    const int fb = skipped ? st->cur : (st->cur ^ 1);
     const float dt = st->dt;            // the step length of this step
     const int done = st->done;
-    const int a = blockIdx.x * kPedBlock + threadIdx.x;
-    if (a < p.na) {
-        int drop = 0;
-        if (p.state[a] != FPS_ST_EXITED) atomicAdd(&active, 1);
-        agent_step(p, a, dt, wet, done, drop);
-        if (drop) atomicAdd(&drops, 1);
+    // evacuation trigger: some cell is wet after this step's flood update
+    const int wet = skipped ? 0 : st->wet_flag;
+    int drop = 0, act = 0;
+    if (a < S.na) {
+        act = S.ped.state[a] != FPS_ST_EXITED;
+        agent_step(S.ped, S.fv.h[fb], S.fv.qx[fb], S.fv.qy[fb], a, dt, wet, done, drop);
     }
-    __syncthreads();
+    // one wave per block: wave-level counts, one atomic each
+    const unsigned long long drops = __popcll(__ballot(drop));
+    const unsigned long long active = __popcll(__ballot(act));
     if (threadIdx.x == 0) {
-        if (drops) atomicAdd(&p.st->drops, drops);
-        if (active) atomicAdd(&p.st->ped_steps, (unsigned long long)active);
+        DevState* stw = S.fv.st;
+        if (drops) atomicAdd(&stw->drops, (int)drops);
+        if (active) atomicAdd(&stw->ped_steps, active);
     }
 }
 
@@ -339,24 +372,36 @@ __global__ __launch_bounds__(kScanThreads) void bin_scan_kernel(BinParams b) { b
 __global__ void bin_place_kernel(BinParams b)
 {
     int a = blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= b.na) return;
-    int k = b.key[a];
-    if (k >= 0) b.perm_u[b.bin_start[k] + b.rank[a]] = a;
+    if (a < b.na) place_agent(b, a);
 }
 
 __global__ void bin_sort_kernel(BinParams b)
 {
     int a = blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= b.na) return;
-    int k = b.key[a];
-    if (k < 0) return;
-    int s0 = b.bin_start[k], s1 = b.bin_start[k + 1];
-    int below = 0;
-    for (int s = s0; s < s1; ++s) below += b.perm_u[s] < a;
-    int f = s0 + below;
-    b.perm[f] = a;
-    b.slot[a] = f;
-    b.xy[f] = make_float2(b.x[a], b.y[a]);
+    if (a < b.na) sort_agent(b, a);
+}
+
+// Ensemble versions for scenarios with more agents than the finalize places
+// inline (same padded flattened index as the pedestrian step).
+__global__ __launch_bounds__(kPedBlock) void bin_place_all_kernel(Batch B)
+{
+    const int g0 = blockIdx.x * kPedBlock;
+    if (g0 >= B.total_agents) return;
+    const int sc = find_scenario(B.agent_off, B.S, g0);
+    const Scn& S = B.scn[sc];
+    if (S.inline_place) return;
+    const int a = g0 - B.agent_off[sc] + (int)threadIdx.x;
+    if (a < S.na) place_agent(S.bins, a);
+}
+__global__ __launch_bounds__(kPedBlock) void bin_sort_all_kernel(Batch B)
+{
+    const int g0 = blockIdx.x * kPedBlock;
+    if (g0 >= B.total_agents) return;
+    const int sc = find_scenario(B.agent_off, B.S, g0);
+    const Scn& S = B.scn[sc];
+    if (S.inline_place) return;
+    const int a = g0 - B.agent_off[sc] + (int)threadIdx.x;
+    if (a < S.na) sort_agent(S.bins, a);
 }
 
 __global__ void count_kernel(BinParams b)
@@ -430,9 +475,22 @@ inline int blocks_for(int64_t n, int t) { return (int)((n + t - 1) / t); }
 
 }  // namespace
 
-hipError_t launch_ped(const PedParams& p, hipStream_t s)
+hipError_t launch_ped(const Batch& b, hipStream_t s)
 {
-    hipLaunchKernelGGL(ped_step_kernel, dim3(p.nblocks), dim3(kPedBlock), 0, s, p);
+    if (b.total_agents > 0)
+        hipLaunchKernelGGL(ped_step_kernel, dim3(b.total_agents / kPedBlock), dim3(kPedBlock), 0, s, b);
+    return hipGetLastError();
+}
+hipError_t launch_bin_place_all(const Batch& b, hipStream_t s)
+{
+    if (b.total_agents > 0)
+        hipLaunchKernelGGL(bin_place_all_kernel, dim3(b.total_agents / kPedBlock), dim3(kPedBlock), 0, s, b);
+    return hipGetLastError();
+}
+hipError_t launch_bin_sort_all(const Batch& b, hipStream_t s)
+{
+    if (b.total_agents > 0)
+        hipLaunchKernelGGL(bin_sort_all_kernel, dim3(b.total_agents / kPedBlock), dim3(kPedBlock), 0, s, b);
     return hipGetLastError();
 }
 hipError_t launch_bin_keys(const BinParams& b, hipStream_t s)

@@ -1,0 +1,782 @@
+// Convolutional flood surrogate on gfx950: BF16 MFMA training and inference
+// kernels with FP32 accumulation (not part of the paper: a learned shortcut that
+// advances the flood state k finite-volume steps per call; the finite-volume
+// update of Eq. (2) stays its fallback and judge).
+//
+// Network: five 3x3 convolutions, channels last, zero padding:
+//   16 (h, hu, hv, z, occupancy scaled; 11 zero channels) -> 64 -> 64 -> 64 -> 64 -> 3
+// ReLU after the first four layers; the last layer is computed with 16 output
+// channels (13 zero) so every layer is a whole number of 16x16x32 MFMA tiles.
+//
+// Kernels
+//   conv_kernel<CIN, COUT, MODE>: implicit GEMM, M = pixels, N = COUT,
+//     K = 9 * CIN.  A block computes an 8 x 32 pixel tile; the input tile with
+//     its one-pixel halo and the whole weight matrix are staged in LDS; each of
+//     the 4 waves owns two image rows (four 16-pixel M tiles) and all COUT
+//     channels, issuing v_mfma_f32_16x16x32_bf16.  Forward and input-gradient
+//     passes use the same kernel (the latter with flipped, transposed weights).
+//   wgrad_kernel<CIN, COUT>: dW[co][tap][ci] = sum_p dz[p][co] x[p + tap][ci],
+//     M = COUT, N = 9 * CIN, K = pixels; dz and x are staged transposed in LDS
+//     (pixel-contiguous), one k-slab is one 32-pixel row of the tile; per-block
+//     FP32 partials are summed in a fixed order by reduce_kernel.
+//   loss / mask / Adam / weight-prep / pack / apply: elementwise.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <new>
+
+#include "fps.h"
+
+namespace fps_sur_impl {
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int TH = 8, TW = 32;     // output tile of one block
+constexpr int kThreads = 256;
+constexpr int kLayers = 5;
+constexpr int kCin[kLayers] = {16, 64, 64, 64, 64};
+constexpr int kCout[kLayers] = {64, 64, 64, 64, 16};   // last: 3 used
+constexpr int kOutUsed = 3;
+constexpr int kWgradBlocks = 512;  // persistent blocks of the weight-gradient pass
+
+__host__ __device__ constexpr int kp_of(int cin) { return (9 * cin + 31) / 32 * 32; }
+
+__device__ __forceinline__ bf16 to_bf16(float f) { return (bf16)f; }
+__device__ __forceinline__ float to_f32(bf16 b) { return (float)b; }
+
+// ----------------------------------------------------------------------------
+// convolution as implicit GEMM (forward and input gradient)
+// MODE 0: bias + ReLU -> bf16 [.., COUT];  1: bias -> bf16 [.., COUT];
+//      2: bias -> fp32 [.., 4] (first kOutUsed channels, 4th zero)
+// ----------------------------------------------------------------------------
+template <int CIN, int COUT, int MODE>
+__global__ __launch_bounds__(kThreads) void conv_kernel(const bf16* __restrict__ X,
+                                                        const bf16* __restrict__ Wt,
+                                                        const float* __restrict__ bias,
+                                                        void* __restrict__ Y, int H, int W)
+{
+    constexpr int KP = kp_of(CIN);
+    constexpr int PIX = CIN + 8;        // padded pixel stride in LDS (bank spread)
+    constexpr int WST = KP + 8;         // padded weight row stride in LDS
+    constexpr int NT = COUT / 16;
+    extern __shared__ __align__(16) unsigned char smem[];
+    bf16* xin = reinterpret_cast<bf16*>(smem);                       // [(TH+2)(TW+2)][PIX]
+    bf16* wl = xin + (TH + 2) * (TW + 2) * PIX;                       // [COUT][WST]
+
+    const int tiles_x = W / TW, tiles_y = H / TH;
+    const int n = blockIdx.x / (tiles_x * tiles_y);
+    const int t = blockIdx.x % (tiles_x * tiles_y);
+    const int y0 = (t / tiles_x) * TH, x0 = (t % tiles_x) * TW;
+    const bf16* Xn = X + (size_t)n * H * W * CIN;
+
+    // stage the input tile with its halo (zeros outside the image), 8 channels per load
+    constexpr int CHUNKS = (TH + 2) * (TW + 2) * (CIN / 8);
+    for (int q = threadIdx.x; q < CHUNKS; q += kThreads) {
+        const int px = q / (CIN / 8), c8 = (q % (CIN / 8)) * 8;
+        const int ly = px / (TW + 2), lx = px % (TW + 2);
+        const int gy = y0 + ly - 1, gx = x0 + lx - 1;
+        bf16x8 v = {};
+        if (gy >= 0 && gy < H && gx >= 0 && gx < W)
+            v = *reinterpret_cast<const bf16x8*>(Xn + ((size_t)gy * W + gx) * CIN + c8);
+        *reinterpret_cast<bf16x8*>(xin + px * PIX + c8) = v;
+    }
+    // stage the weights [COUT][KP]
+    for (int q = threadIdx.x; q < COUT * (KP / 8); q += kThreads) {
+        const int co = q / (KP / 8), k8 = (q % (KP / 8)) * 8;
+        *reinterpret_cast<bf16x8*>(wl + co * WST + k8) =
+            *reinterpret_cast<const bf16x8*>(Wt + (size_t)co * KP + k8);
+    }
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int row16 = lane & 15, kgrp = lane >> 4;
+    f32x4 acc[4][NT];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+
+    for (int slab = 0; slab < KP / 32; ++slab) {
+        const int k0 = slab * 32 + kgrp * 8;
+        const int tap = k0 / CIN, c = k0 % CIN;
+        const bool valid = tap < 9;
+        const int dy = valid ? tap / 3 : 0, dx = valid ? tap % 3 : 0;
+        bf16x8 a[4], b[NT];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            // M tile mt: local row 2*wave + mt/2, columns 16*(mt%2) + row16
+            const int ly = 2 * wave + (mt >> 1) + dy;
+            const int lx = 16 * (mt & 1) + row16 + dx;
+            a[mt] = valid ? *reinterpret_cast<const bf16x8*>(xin + (ly * (TW + 2) + lx) * PIX + c)
+                          : bf16x8{};
+        }
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+            b[nt] = *reinterpret_cast<const bf16x8*>(wl + (16 * nt + row16) * WST + k0);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], b[nt], acc[mt][nt], 0, 0, 0);
+    }
+
+    // D tile: lane holds rows (pixels) 4*kgrp + r, column (channel) row16
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        const int gy = y0 + 2 * wave + (mt >> 1);
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const int co = 16 * nt + row16;
+            const float bb = bias ? bias[co] : 0.0f;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int gx = x0 + 16 * (mt & 1) + 4 * kgrp + r;
+                float v = acc[mt][nt][r] + bb;
+                const size_t p = ((size_t)n * H + gy) * W + gx;
+                if (MODE == 0) {
+                    reinterpret_cast<bf16*>(Y)[p * COUT + co] = to_bf16(fmaxf(v, 0.0f));
+                } else if (MODE == 1) {
+                    reinterpret_cast<bf16*>(Y)[p * COUT + co] = to_bf16(v);
+                } else {
+                    if (co < 4) reinterpret_cast<float*>(Y)[p * 4 + co] = co < kOutUsed ? v : 0.0f;
+                }
+            }
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// weight gradient: per-block partials of dW[co][tap][ci] over pixel tiles
+// ----------------------------------------------------------------------------
+template <int CIN, int COUT>
+__global__ __launch_bounds__(kThreads) void wgrad_kernel(const bf16* __restrict__ X,
+                                                         const bf16* __restrict__ DZ,
+                                                         float* __restrict__ part, int N, int H, int W)
+{
+    constexpr int MT = COUT / 16, NTAP = CIN / 16;     // N tiles per tap
+    constexpr int TILES = MT * 9 * NTAP;               // 16x16 output tiles
+    constexpr int PER_WAVE = (TILES + 3) / 4;
+    constexpr int XROW = TW;                           // transposed x tile row length
+    extern __shared__ __align__(16) unsigned char smem[];
+    bf16* dzT = reinterpret_cast<bf16*>(smem);          // [COUT][TH*TW]
+    bf16* xT = dzT + COUT * TH * TW;                    // [CIN][(TH+2)][XROW] for one dx
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int row16 = lane & 15, kgrp = lane >> 4;
+    f32x4 acc[PER_WAVE];
+#pragma unroll
+    for (int k = 0; k < PER_WAVE; ++k) acc[k] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+
+    const int tiles_x = W / TW, tiles_y = H / TH, per_img = tiles_x * tiles_y;
+    for (int tile = blockIdx.x; tile < N * per_img; tile += gridDim.x) {
+        const int n = tile / per_img, t = tile % per_img;
+        const int y0 = (t / tiles_x) * TH, x0 = (t % tiles_x) * TW;
+        __syncthreads();
+        // dz tile transposed: dzT[co][p], p = row * TW + col
+        for (int q = threadIdx.x; q < TH * TW * (COUT / 8); q += kThreads) {
+            const int p = q / (COUT / 8), c8 = (q % (COUT / 8)) * 8;
+            const int gy = y0 + p / TW, gx = x0 + p % TW;
+            bf16x8 v = *reinterpret_cast<const bf16x8*>(DZ + (((size_t)n * H + gy) * W + gx) * COUT + c8);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) dzT[(c8 + e) * (TH * TW) + p] = v[e];
+        }
+        for (int dx = 0; dx < 3; ++dx) {
+            __syncthreads();
+            // x tile for this column offset, transposed: xT[ci][ly][col] = x[y0+ly-1][x0+col+dx-1][ci]
+            for (int q = threadIdx.x; q < (TH + 2) * XROW * (CIN / 8); q += kThreads) {
+                const int px = q / (CIN / 8), c8 = (q % (CIN / 8)) * 8;
+                const int ly = px / XROW, col = px % XROW;
+                const int gy = y0 + ly - 1, gx = x0 + col + dx - 1;
+                bf16x8 v = {};
+                if (gy >= 0 && gy < H && gx >= 0 && gx < W)
+                    v = *reinterpret_cast<const bf16x8*>(X + (((size_t)n * H + gy) * W + gx) * CIN + c8);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) xT[(c8 + e) * ((TH + 2) * XROW) + ly * XROW + col] = v[e];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < PER_WAVE; ++k) {
+                const int tl = wave + 4 * k;
+                if (tl >= TILES) break;
+                const int mt = tl / (9 * NTAP), rest = tl % (9 * NTAP);
+                const int tap = rest / NTAP, ci0 = (rest % NTAP) * 16;
+                if (tap % 3 != dx) continue;
+                const int dy = tap / 3;
+                const int co = 16 * mt + row16, ci = ci0 + row16;
+                for (int r = 0; r < TH; ++r) {
+                    // k-slab: pixels of tile row r, lane's 8 columns 8*kgrp..
+                    const bf16x8 a = *reinterpret_cast<const bf16x8*>(dzT + co * (TH * TW) + r * TW + 8 * kgrp);
+                    const bf16x8 b = *reinterpret_cast<const bf16x8*>(
+                        xT + ci * ((TH + 2) * XROW) + (r + dy) * XROW + 8 * kgrp);
+                    acc[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[k], 0, 0, 0);
+                }
+            }
+        }
+    }
+    // partial [block][co][tap][ci]; D tile lane holds rows (co) 4*kgrp + r, column (ci) row16
+    float* pb = part + (size_t)blockIdx.x * COUT * 9 * CIN;
+#pragma unroll
+    for (int k = 0; k < PER_WAVE; ++k) {
+        const int tl = wave + 4 * k;
+        if (tl >= TILES) break;
+        const int mt = tl / (9 * NTAP), rest = tl % (9 * NTAP);
+        const int tap = rest / NTAP, ci0 = (rest % NTAP) * 16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int co = 16 * mt + 4 * kgrp + r;
+            pb[((size_t)co * 9 + tap) * CIN + ci0 + row16] = acc[k][r];
+        }
+    }
+}
+
+// dW = sum over blocks (fixed order) and db = sum over pixels of dz (fixed order)
+__global__ void reduce_kernel(const float* __restrict__ part, int nblocks, int count, float* __restrict__ dw)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    float s = 0.0f;
+    for (int b = 0; b < nblocks; ++b) s += part[(size_t)b * count + i];
+    dw[i] = s;
+}
+
+// db partials: block b sums its pixel range for every channel (fixed order)
+__global__ void bias_partial_kernel(const bf16* __restrict__ DZ, int64_t npix, int cout, int per_block,
+                                    float* __restrict__ part)
+{
+    const int co = threadIdx.x;
+    if (co >= cout) return;
+    const int64_t p0 = (int64_t)blockIdx.x * per_block, p1 = min(p0 + per_block, npix);
+    float s = 0.0f;
+    for (int64_t p = p0; p < p1; ++p) s += to_f32(DZ[p * cout + co]);
+    part[(size_t)blockIdx.x * cout + co] = s;
+}
+
+// ----------------------------------------------------------------------------
+// elementwise kernels
+// ----------------------------------------------------------------------------
+// dz = g * (a > 0)   (ReLU derivative from the layer's output)
+__global__ void relu_mask_kernel(const bf16* __restrict__ g, const bf16* __restrict__ a,
+                                 bf16* __restrict__ dz, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dz[i] = to_f32(a[i]) > 0.0f ? g[i] : to_bf16(0.0f);
+}
+
+// MSE: per-block loss partials and dz of the output layer (bf16, 16 channels)
+__global__ void loss_kernel(const float* __restrict__ pred, const float* __restrict__ target, int64_t npix,
+                            float scale, bf16* __restrict__ dz, float* __restrict__ part)
+{
+    __shared__ float red[kThreads];
+    float s = 0.0f;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += (int64_t)gridDim.x * blockDim.x) {
+        bf16x8 z0 = {}, z1 = {};
+#pragma unroll
+        for (int c = 0; c < kOutUsed; ++c) {
+            const float d = pred[p * 4 + c] - target[p * 4 + c];
+            s += d * d;
+            z0[c] = to_bf16(2.0f * d * scale);
+        }
+        *reinterpret_cast<bf16x8*>(dz + p * 16) = z0;
+        *reinterpret_cast<bf16x8*>(dz + p * 16 + 8) = z1;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = kThreads / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void sum_kernel(const float* __restrict__ part, int n, float scale, float* __restrict__ out)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        float s = 0.0f;
+        for (int i = 0; i < n; ++i) s += part[i];
+        *out = s * scale;
+    }
+}
+
+// Adam on FP32 master parameters (bias-corrected)
+__global__ void adam_kernel(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
+                            const float* __restrict__ g, int n, float lr, float b1, float b2, float eps,
+                            float c1, float c2)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// bf16 weights for the forward pass [COUT][KP] (k = tap*CIN + ci) and for the
+// input-gradient pass [CIN][KPd] (k = (8 - tap)*COUT + co), from FP32 master [COUT][9][CIN]
+__global__ void prep_weights_kernel(const float* __restrict__ w, int cin, int cout, bf16* __restrict__ wf,
+                                    bf16* __restrict__ wd)
+{
+    const int kp = kp_of(cin), kpd = kp_of(cout);
+    const int total = cout * kp + (wd ? cin * kpd : 0);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+        if (i < cout * kp) {
+            const int co = i / kp, k = i % kp;
+            wf[i] = to_bf16(k < 9 * cin ? w[((size_t)co * 9 + k / cin) * cin + k % cin] : 0.0f);
+        } else {
+            const int j = i - cout * kp;
+            const int ci = j / kpd, k = j % kpd;
+            float val = 0.0f;
+            if (k < 9 * cout) {
+                const int tapd = k / cout, co = k % cout;
+                val = w[((size_t)co * 9 + (8 - tapd)) * cin + ci];
+            }
+            wd[j] = to_bf16(val);
+        }
+    }
+}
+
+// input scales (h, hu, hv, z, occupancy) and output scales (change of h, hu, hv)
+__constant__ float kInScale[5] = {1.0f, 1.0f, 1.0f, 1.0f / 3.0f, 0.25f};
+__constant__ float kOutScale[3] = {0.05f, 0.05f, 0.05f};
+
+__global__ void pack_kernel(int64_t npix, const float* __restrict__ h, const float* __restrict__ hu,
+                            const float* __restrict__ hv, const float* __restrict__ z,
+                            const int32_t* __restrict__ occ, bf16* __restrict__ x)
+{
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += (int64_t)gridDim.x * blockDim.x) {
+        bf16x8 a = {}, b = {};
+        a[0] = to_bf16(h[p] * kInScale[0]);
+        a[1] = to_bf16(hu[p] * kInScale[1]);
+        a[2] = to_bf16(hv[p] * kInScale[2]);
+        a[3] = to_bf16(z[p] * kInScale[3]);
+        a[4] = to_bf16(occ ? (float)occ[p] * kInScale[4] : 0.0f);
+        *reinterpret_cast<bf16x8*>(x + p * 16) = a;
+        *reinterpret_cast<bf16x8*>(x + p * 16 + 8) = b;
+    }
+}
+
+__global__ void target_kernel(int64_t npix, const float* __restrict__ h0, const float* __restrict__ hu0,
+                              const float* __restrict__ hv0, const float* __restrict__ h1,
+                              const float* __restrict__ hu1, const float* __restrict__ hv1,
+                              float* __restrict__ t)
+{
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += (int64_t)gridDim.x * blockDim.x) {
+        t[p * 4 + 0] = (h1[p] - h0[p]) / kOutScale[0];
+        t[p * 4 + 1] = (hu1[p] - hu0[p]) / kOutScale[1];
+        t[p * 4 + 2] = (hv1[p] - hv0[p]) / kOutScale[2];
+        t[p * 4 + 3] = 0.0f;
+    }
+}
+
+// U += scale * y; depth kept >= 0; no discharge where dry
+__global__ void apply_kernel(int64_t npix, const float* __restrict__ y, float* __restrict__ h,
+                             float* __restrict__ hu, float* __restrict__ hv, float h_dry)
+{
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += (int64_t)gridDim.x * blockDim.x) {
+        float hn = fmaxf(h[p] + kOutScale[0] * y[p * 4 + 0], 0.0f);
+        float qx = hu[p] + kOutScale[1] * y[p * 4 + 1];
+        float qy = hv[p] + kOutScale[2] * y[p * 4 + 2];
+        if (!(hn > h_dry)) {
+            qx = 0.0f;
+            qy = 0.0f;
+        }
+        h[p] = hn;
+        hu[p] = qx;
+        hv[p] = qy;
+    }
+}
+
+__device__ __forceinline__ int hazard_class(float h, float qx, float qy, float eps, const float* thr)
+{
+    if (!(h > eps)) return 0;
+    float hr = (fmaxf(fabsf(qx / h), fabsf(qy / h)) + 0.5f) * h;
+    return hr < thr[0] ? 1 : hr < thr[1] ? 2 : hr < thr[2] ? 3 : 4;
+}
+
+// Judge: over non-exited agents, count those where the two flood states differ
+// in depth by more than tol or in hazard class (Table 1 thresholds), and the
+// largest depth difference.  out[0] = count (int), out[1] = max |dh| (float bits).
+__global__ void judge_kernel(int na, const float* __restrict__ x, const float* __restrict__ y,
+                             const uint8_t* __restrict__ state, int nx, int ny, float dx, float dy,
+                             const float* __restrict__ ha, const float* __restrict__ qxa,
+                             const float* __restrict__ qya, const float* __restrict__ hb,
+                             const float* __restrict__ qxb, const float* __restrict__ qyb, float tol,
+                             float eps, float t1, float t2, float t3, int32_t* __restrict__ out)
+{
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= na || state[a] == 1) return;
+    // containing cell: IEEE division and floor in FP32, clamped to the grid
+    const int i = (int)fminf(fmaxf(floorf(x[a] / dx), 0.0f), (float)(nx - 1));
+    const int j = (int)fminf(fmaxf(floorf(y[a] / dy), 0.0f), (float)(ny - 1));
+    const size_t c = (size_t)j * nx + i;
+    const float thr[3] = {t1, t2, t3};
+    const float d = fabsf(ha[c] - hb[c]);
+    const bool bad = d > tol || hazard_class(ha[c], qxa[c], qya[c], eps, thr) !=
+                                    hazard_class(hb[c], qxb[c], qyb[c], eps, thr);
+    if (bad) atomicAdd(&out[0], 1);
+    atomicMax(&out[1], __float_as_int(d));    // non-negative floats order as ints
+}
+
+}  // namespace fps_sur_impl
+
+// ============================================================================
+// host side
+// ============================================================================
+using namespace fps_sur_impl;
+
+struct fps_sur {
+    int max_batch = 0, H = 0, W = 0;
+    hipStream_t stream = nullptr;
+    char err[512] = "";
+    float *params = nullptr, *m = nullptr, *v = nullptr, *grads = nullptr;
+    bf16* wf[kLayers] = {};
+    bf16* wd[kLayers] = {};
+    bf16* act[kLayers - 1] = {};     // outputs of layers 1..4, [B][H][W][64]
+    float* y = nullptr;              // [B][H][W][4]
+    bf16* g = nullptr;               // input gradient of a layer, [B][H][W][64]
+    bf16* dz = nullptr;              // masked gradient, [B][H][W][64]
+    bf16* dz5 = nullptr;             // output-layer gradient, [B][H][W][16]
+    float* wpart = nullptr;          // weight-gradient partials
+    float* bpart = nullptr;          // bias-gradient partials
+    float* lpart = nullptr;          // loss partials
+    int adam_step = 0;
+    bool have_grads = false;
+};
+
+namespace {
+
+char g_sur_err[512] = "";
+
+int sfail(fps_sur* s, int code, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(s ? s->err : g_sur_err, 512, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+#define SCHK(s, expr)                                                                       \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return sfail(s, FPS_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));   \
+    } while (0)
+
+constexpr int kLossBlocks = 1024;
+constexpr int kBiasBlocks = 512;
+
+size_t a256(size_t v) { return (v + 255) & ~size_t(255); }
+
+int64_t w_count(int l) { return (int64_t)kCout[l] * 9 * kCin[l]; }
+int64_t layer_params(int l) { return w_count(l) + kCout[l]; }
+int64_t param_offset(int l)
+{
+    int64_t o = 0;
+    for (int k = 0; k < l; ++k) o += layer_params(k);
+    return o;
+}
+int64_t total_params() { return param_offset(kLayers); }
+
+struct SurLayout {
+    size_t params, m, v, grads, wf[kLayers], wd[kLayers], act[kLayers - 1], y, g, dz, dz5, wpart, bpart,
+        lpart, total;
+};
+
+SurLayout sur_layout(int B, int H, int W)
+{
+    SurLayout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = a256(o + bytes);
+        return at;
+    };
+    const size_t np = (size_t)total_params();
+    const size_t pix = (size_t)B * H * W;
+    L.params = take(4 * np);
+    L.m = take(4 * np);
+    L.v = take(4 * np);
+    L.grads = take(4 * np);
+    for (int l = 0; l < kLayers; ++l) {
+        L.wf[l] = take(2 * (size_t)kCout[l] * kp_of(kCin[l]));
+        L.wd[l] = take(2 * (size_t)kCin[l] * kp_of(kCout[l]));
+    }
+    for (int l = 0; l < kLayers - 1; ++l) L.act[l] = take(2 * pix * 64);
+    L.y = take(4 * pix * 4);
+    L.g = take(2 * pix * 64);
+    L.dz = take(2 * pix * 64);
+    L.dz5 = take(2 * pix * 16);
+    L.wpart = take(4 * (size_t)kWgradBlocks * 64 * 9 * 64);
+    L.bpart = take(4 * (size_t)kBiasBlocks * 64);
+    L.lpart = take(4 * (size_t)kLossBlocks);
+    L.total = o;
+    return L;
+}
+
+template <int CIN, int COUT, int MODE>
+int conv(fps_sur* s, int n, const bf16* x, const bf16* w, const float* b, void* y)
+{
+    constexpr int KP = kp_of(CIN);
+    const size_t lds = (size_t)(TH + 2) * (TW + 2) * (CIN + 8) * 2 + (size_t)COUT * (KP + 8) * 2;
+    auto k = conv_kernel<CIN, COUT, MODE>;
+    SCHK(s, hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    const int blocks = n * (s->H / TH) * (s->W / TW);
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(kThreads), lds, s->stream, x, w, b, y, s->H, s->W);
+    SCHK(s, hipGetLastError());
+    return FPS_OK;
+}
+
+template <int CIN, int COUT>
+int wgrad(fps_sur* s, int n, const bf16* x, const bf16* dz, int layer)
+{
+    const size_t lds = (size_t)COUT * TH * TW * 2 + (size_t)CIN * (TH + 2) * TW * 2;
+    auto k = wgrad_kernel<CIN, COUT>;
+    SCHK(s, hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    const int tiles = n * (s->H / TH) * (s->W / TW);
+    const int blocks = std::min(tiles, kWgradBlocks);
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(kThreads), lds, s->stream, x, dz, s->wpart, n, s->H, s->W);
+    SCHK(s, hipGetLastError());
+    const int count = COUT * 9 * CIN;
+    float* dw = s->grads + param_offset(layer);
+    hipLaunchKernelGGL(reduce_kernel, dim3((count + 255) / 256), dim3(256), 0, s->stream, s->wpart, blocks,
+                       count, dw);
+    SCHK(s, hipGetLastError());
+    // bias: per-block sums over pixel ranges, then the fixed-order total
+    const int64_t npix = (int64_t)n * s->H * s->W;
+    const int per = (int)((npix + kBiasBlocks - 1) / kBiasBlocks);
+    hipLaunchKernelGGL(bias_partial_kernel, dim3(kBiasBlocks), dim3(64), 0, s->stream, dz, npix, COUT, per,
+                       s->bpart);
+    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(64), 0, s->stream, s->bpart, kBiasBlocks, COUT,
+                       dw + w_count(layer));
+    SCHK(s, hipGetLastError());
+    return FPS_OK;
+}
+
+int prep_weights(fps_sur* s)
+{
+    for (int l = 0; l < kLayers; ++l) {
+        hipLaunchKernelGGL(prep_weights_kernel, dim3(64), dim3(256), 0, s->stream, s->params + param_offset(l),
+                           kCin[l], kCout[l], s->wf[l], l > 0 ? s->wd[l] : (bf16*)nullptr);
+        SCHK(s, hipGetLastError());
+    }
+    return FPS_OK;
+}
+
+const float* bias_of(const fps_sur* s, int l) { return s->params + param_offset(l) + w_count(l); }
+
+int forward(fps_sur* s, int n, const bf16* x, float* y)
+{
+    int rc = conv<16, 64, 0>(s, n, x, s->wf[0], bias_of(s, 0), s->act[0]);
+    for (int l = 1; l < 4 && rc == FPS_OK; ++l)
+        rc = conv<64, 64, 0>(s, n, s->act[l - 1], s->wf[l], bias_of(s, l), s->act[l]);
+    if (rc == FPS_OK) rc = conv<64, 16, 2>(s, n, s->act[3], s->wf[4], bias_of(s, 4), y);
+    return rc;
+}
+
+int check_args(fps_sur* s, int n)
+{
+    if (n < 1 || n > s->max_batch) return sfail(s, FPS_E_CAPACITY, "batch %d outside [1, %d]", n, s->max_batch);
+    return FPS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t fps_sur_param_count(void) { return (int32_t)total_params(); }
+
+size_t fps_sur_workspace_bytes(int32_t max_batch, int32_t H, int32_t W)
+{
+    if (max_batch < 1 || H < TH || W < TW || H % TH || W % TW) return 0;
+    return sur_layout(max_batch, H, W).total;
+}
+
+int fps_sur_create(int32_t max_batch, int32_t H, int32_t W, void* ws, size_t ws_bytes, void* stream,
+                   fps_sur** out)
+{
+    if (!out) return sfail(nullptr, FPS_E_INVALID, "fps_sur_create: out is NULL");
+    *out = nullptr;
+    if (max_batch < 1 || H < TH || W < TW || H % TH || W % TW)
+        return sfail(nullptr, FPS_E_INVALID, "fps_sur_create: need batch >= 1 and H, W multiples of %d, %d", TH, TW);
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255))
+        return sfail(nullptr, FPS_E_INVALID, "fps_sur_create: workspace NULL or not 256-byte aligned");
+    SurLayout L = sur_layout(max_batch, H, W);
+    if (ws_bytes < L.total)
+        return sfail(nullptr, FPS_E_CAPACITY, "fps_sur_create: workspace %zu < %zu bytes", ws_bytes, L.total);
+    fps_sur* s = new (std::nothrow) fps_sur();
+    if (!s) return sfail(nullptr, FPS_E_DEVICE, "fps_sur_create: out of host memory");
+    s->max_batch = max_batch;
+    s->H = H;
+    s->W = W;
+    s->stream = static_cast<hipStream_t>(stream);
+    char* b = static_cast<char*>(ws);
+    s->params = reinterpret_cast<float*>(b + L.params);
+    s->m = reinterpret_cast<float*>(b + L.m);
+    s->v = reinterpret_cast<float*>(b + L.v);
+    s->grads = reinterpret_cast<float*>(b + L.grads);
+    for (int l = 0; l < kLayers; ++l) {
+        s->wf[l] = reinterpret_cast<bf16*>(b + L.wf[l]);
+        s->wd[l] = reinterpret_cast<bf16*>(b + L.wd[l]);
+    }
+    for (int l = 0; l < kLayers - 1; ++l) s->act[l] = reinterpret_cast<bf16*>(b + L.act[l]);
+    s->y = reinterpret_cast<float*>(b + L.y);
+    s->g = reinterpret_cast<bf16*>(b + L.g);
+    s->dz = reinterpret_cast<bf16*>(b + L.dz);
+    s->dz5 = reinterpret_cast<bf16*>(b + L.dz5);
+    s->wpart = reinterpret_cast<float*>(b + L.wpart);
+    s->bpart = reinterpret_cast<float*>(b + L.bpart);
+    s->lpart = reinterpret_cast<float*>(b + L.lpart);
+    *out = s;
+    return FPS_OK;
+}
+
+void fps_sur_destroy(fps_sur* s)
+{
+    if (!s) return;
+    (void)hipStreamSynchronize(s->stream);
+    delete s;
+}
+
+int fps_sur_set_params(fps_sur* s, const float* params)
+{
+    if (!s || !params) return sfail(s, FPS_E_INVALID, "fps_sur_set_params: NULL argument");
+    const size_t bytes = 4 * (size_t)total_params();
+    SCHK(s, hipMemcpyAsync(s->params, params, bytes, hipMemcpyDeviceToDevice, s->stream));
+    SCHK(s, hipMemsetAsync(s->m, 0, bytes, s->stream));
+    SCHK(s, hipMemsetAsync(s->v, 0, bytes, s->stream));
+    s->adam_step = 0;
+    s->have_grads = false;
+    return prep_weights(s);
+}
+
+int fps_sur_get_params(fps_sur* s, float* params)
+{
+    if (!s || !params) return sfail(s, FPS_E_INVALID, "fps_sur_get_params: NULL argument");
+    SCHK(s, hipMemcpyAsync(params, s->params, 4 * (size_t)total_params(), hipMemcpyDeviceToDevice, s->stream));
+    return FPS_OK;
+}
+
+int fps_sur_forward(fps_sur* s, int32_t n, const void* x, float* y)
+{
+    if (!s || !x || !y) return sfail(s, FPS_E_INVALID, "fps_sur_forward: NULL argument");
+    int rc = check_args(s, n);
+    if (rc != FPS_OK) return rc;
+    return forward(s, n, static_cast<const bf16*>(x), y);
+}
+
+int fps_sur_gradients(fps_sur* s, int32_t n, const void* xv, const float* target, float* grads_out,
+                      float* loss)
+{
+    if (!s || !xv || !target || !loss) return sfail(s, FPS_E_INVALID, "fps_sur_gradients: NULL argument");
+    int rc = check_args(s, n);
+    if (rc != FPS_OK) return rc;
+    const bf16* x = static_cast<const bf16*>(xv);
+    rc = forward(s, n, x, s->y);
+    if (rc != FPS_OK) return rc;
+    const int64_t npix = (int64_t)n * s->H * s->W;
+    const float scale = 1.0f / (float)(npix * kOutUsed);
+    hipLaunchKernelGGL(loss_kernel, dim3(kLossBlocks), dim3(kThreads), 0, s->stream, s->y, target, npix, scale,
+                       s->dz5, s->lpart);
+    hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(64), 0, s->stream, s->lpart, kLossBlocks, scale, loss);
+    SCHK(s, hipGetLastError());
+    // layer 5 (no ReLU): dz5 -> dW5, input gradient g (64 channels)
+    rc = wgrad<64, 16>(s, n, s->act[3], s->dz5, 4);
+    if (rc == FPS_OK) rc = conv<16, 64, 1>(s, n, s->dz5, s->wd[4], nullptr, s->g);
+    for (int l = 3; l >= 0 && rc == FPS_OK; --l) {
+        const int64_t cnt = npix * 64;
+        hipLaunchKernelGGL(relu_mask_kernel, dim3(2048), dim3(256), 0, s->stream, s->g, s->act[l], s->dz, cnt);
+        SCHK(s, hipGetLastError());
+        if (l > 0) {
+            rc = wgrad<64, 64>(s, n, s->act[l - 1], s->dz, l);
+            if (rc == FPS_OK) rc = conv<64, 64, 1>(s, n, s->dz, s->wd[l], nullptr, s->g);
+        } else {
+            rc = wgrad<16, 64>(s, n, x, s->dz, 0);
+        }
+    }
+    if (rc != FPS_OK) return rc;
+    s->have_grads = true;
+    if (grads_out)
+        SCHK(s, hipMemcpyAsync(grads_out, s->grads, 4 * (size_t)total_params(), hipMemcpyDeviceToDevice, s->stream));
+    return FPS_OK;
+}
+
+int fps_sur_adam(fps_sur* s, float lr)
+{
+    if (!s) return sfail(nullptr, FPS_E_INVALID, "fps_sur_adam: NULL argument");
+    if (!s->have_grads) return sfail(s, FPS_E_STATE, "fps_sur_adam: no gradients computed");
+    if (!(lr >= 0.0f) || !std::isfinite(lr)) return sfail(s, FPS_E_INVALID, "fps_sur_adam: bad learning rate");
+    s->adam_step += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.0f - std::pow(b1, (float)s->adam_step), c2 = 1.0f - std::pow(b2, (float)s->adam_step);
+    const int n = (int)total_params();
+    hipLaunchKernelGGL(adam_kernel, dim3((n + 255) / 256), dim3(256), 0, s->stream, s->params, s->m, s->v,
+                       s->grads, n, lr, b1, b2, 1e-8f, c1, c2);
+    SCHK(s, hipGetLastError());
+    return prep_weights(s);
+}
+
+int fps_sur_train_step(fps_sur* s, int32_t n, const void* x, const float* target, float lr, float* loss)
+{
+    int rc = fps_sur_gradients(s, n, x, target, nullptr, loss);
+    if (rc != FPS_OK) return rc;
+    return fps_sur_adam(s, lr);
+}
+
+int fps_sur_pack(int64_t npix, const float* h, const float* hu, const float* hv, const float* z,
+                 const int32_t* occupancy, void* x, void* stream)
+{
+    if (npix < 1 || !h || !hu || !hv || !z || !x) return sfail(nullptr, FPS_E_INVALID, "fps_sur_pack: bad argument");
+    hipLaunchKernelGGL(pack_kernel, dim3(2048), dim3(256), 0, static_cast<hipStream_t>(stream), npix, h, hu, hv, z,
+                       occupancy, static_cast<bf16*>(x));
+    SCHK(nullptr, hipGetLastError());
+    return FPS_OK;
+}
+
+int fps_sur_make_target(int64_t npix, const float* h0, const float* hu0, const float* hv0, const float* h1,
+                        const float* hu1, const float* hv1, float* target, void* stream)
+{
+    if (npix < 1 || !h0 || !hu0 || !hv0 || !h1 || !hu1 || !hv1 || !target)
+        return sfail(nullptr, FPS_E_INVALID, "fps_sur_make_target: bad argument");
+    hipLaunchKernelGGL(target_kernel, dim3(2048), dim3(256), 0, static_cast<hipStream_t>(stream), npix, h0, hu0,
+                       hv0, h1, hu1, hv1, target);
+    SCHK(nullptr, hipGetLastError());
+    return FPS_OK;
+}
+
+int fps_sur_apply(int64_t npix, const float* y, float* h, float* hu, float* hv, float h_dry, void* stream)
+{
+    if (npix < 1 || !y || !h || !hu || !hv) return sfail(nullptr, FPS_E_INVALID, "fps_sur_apply: bad argument");
+    hipLaunchKernelGGL(apply_kernel, dim3(2048), dim3(256), 0, static_cast<hipStream_t>(stream), npix, y, h, hu, hv,
+                       h_dry);
+    SCHK(nullptr, hipGetLastError());
+    return FPS_OK;
+}
+
+int fps_sur_judge(int32_t na, const float* x, const float* y, const uint8_t* state, int32_t nx, int32_t ny,
+                  double dx, double dy, const float* ha, const float* qxa, const float* qya, const float* hb,
+                  const float* qxb, const float* qyb, double tol, double h_dry, const double* hr_thresholds,
+                  int32_t* out2, void* stream)
+{
+    if (na < 0 || nx < 1 || ny < 1 || !(dx > 0) || !(dy > 0) || !out2 || !hr_thresholds)
+        return sfail(nullptr, FPS_E_INVALID, "fps_sur_judge: bad argument");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    SCHK(nullptr, hipMemsetAsync(out2, 0, 2 * sizeof(int32_t), st));
+    if (na > 0) {
+        hipLaunchKernelGGL(judge_kernel, dim3((na + 255) / 256), dim3(256), 0, st, na, x, y, state, nx, ny, (float)dx,
+                           (float)dy, ha, qxa, qya, hb, qxb, qyb, (float)tol, (float)h_dry, (float)hr_thresholds[0],
+                           (float)hr_thresholds[1], (float)hr_thresholds[2], out2);
+        SCHK(nullptr, hipGetLastError());
+    }
+    return FPS_OK;
+}
+
+const char* fps_sur_last_error(const fps_sur* s) { return s ? s->err : g_sur_err; }
+
+}  // extern "C"

@@ -49,6 +49,7 @@ class DiagC(C.Structure):
         ("barrier_layers_done", C.c_int32), ("barrier_active_cell", C.c_int32),
         ("barrier_bags", C.c_int32), ("barrier_done", C.c_int32),
         ("drops_total", C.c_int32), ("status", C.c_int32),
+        ("active", C.c_int32), ("flood_steps", C.c_int32),
     ]
 
 
@@ -71,6 +72,38 @@ EXPORTS = {
     "fps_get_counts": (C.c_int, [_vp, _vp]),
     "fps_get_bins": (C.c_int, [_vp, _vp, _vp, C.POINTER(C.c_int32)]),
     "fps_step_profiled": (C.c_int, [_vp, C.c_int32, C.POINTER(C.c_double)]),
+    "fps_set_end_time": (C.c_int, [_vp, C.c_double]),
+    "fps_set_graph": (C.c_int, [_vp, C.c_int32]),
+    "fps_ens_workspace_bytes": (C.c_size_t, [C.c_int32, C.POINTER(GridDescC), C.POINTER(C.c_int32)]),
+    "fps_ens_create": (C.c_int, [C.c_int32, C.POINTER(GridDescC), C.POINTER(PedParamsC),
+                                 C.POINTER(C.c_int32), _vp, C.c_size_t, _vp, C.POINTER(_vp)]),
+    "fps_ens_destroy": (None, [_vp]),
+    "fps_ens_member": (_vp, [_vp, C.c_int32]),
+    "fps_ens_step": (C.c_int, [_vp, C.c_int32]),
+    "fps_ens_step_profiled": (C.c_int, [_vp, C.c_int32, C.POINTER(C.c_double)]),
+    "fps_ens_set_graph": (C.c_int, [_vp, C.c_int32]),
+    "fps_ens_autotune": (C.c_int, [_vp, C.c_char_p]),
+    "fps_ens_active": (C.c_int, [_vp, C.POINTER(C.c_int32)]),
+    "fps_ens_last_error": (C.c_char_p, [_vp]),
+    "fps_sur_param_count": (C.c_int32, []),
+    "fps_sur_workspace_bytes": (C.c_size_t, [C.c_int32, C.c_int32, C.c_int32]),
+    "fps_sur_create": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, _vp, C.c_size_t, _vp, C.POINTER(_vp)]),
+    "fps_sur_destroy": (None, [_vp]),
+    "fps_sur_set_params": (C.c_int, [_vp, _vp]),
+    "fps_sur_get_params": (C.c_int, [_vp, _vp]),
+    "fps_sur_forward": (C.c_int, [_vp, C.c_int32, _vp, _vp]),
+    "fps_sur_gradients": (C.c_int, [_vp, C.c_int32, _vp, _vp, _vp, _vp]),
+    "fps_sur_adam": (C.c_int, [_vp, C.c_float]),
+    "fps_sur_train_step": (C.c_int, [_vp, C.c_int32, _vp, _vp, C.c_float, _vp]),
+    "fps_sur_pack": (C.c_int, [C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "fps_sur_make_target": (C.c_int, [C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "fps_sur_apply": (C.c_int, [C.c_int64, _vp, _vp, _vp, _vp, C.c_float, _vp]),
+    "fps_sur_judge": (C.c_int, [C.c_int32, _vp, _vp, _vp, C.c_int32, C.c_int32, C.c_double, C.c_double,
+                                _vp, _vp, _vp, _vp, _vp, _vp, C.c_double, C.c_double,
+                                C.POINTER(C.c_double), _vp, _vp]),
+    "fps_sur_last_error": (C.c_char_p, [_vp]),
+    "fps_set_rows_per_wave": (C.c_int, [_vp, C.c_int32]),
+    "fps_autotune": (C.c_int, [_vp, C.c_char_p, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     "fps_status_string": (C.c_char_p, [C.c_int]),
     "fps_last_error": (C.c_char_p, [_vp]),
 }
@@ -126,99 +159,76 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr())
 
 
-class Sim:
-    """One scenario on one GPU: device tensors + a libfps handle."""
+class Member:
+    """One scenario's device tensors bound to a libfps handle (standalone or
+    ensemble member).  Argument marshalling only."""
 
-    def __init__(self, sc, device="cuda", stream=None, max_agents=None):
+    def _bind(self, h, sc, device):
         import torch
         self.torch = torch
         self.sc = sc
         self.device = torch.device(device)
-        L = lib()
-        self._lib = L
-        d = sc.desc
-        self.desc_c = grid_desc_c(d)
-        self.ped_c = ped_params_c(sc.ped)
-        na = 0 if sc.agents is None else len(sc.agents["x"])
-        self.max_agents = na if max_agents is None else max_agents
-        nbytes = L.fps_workspace_bytes(C.byref(self.desc_c), self.max_agents)
-        if nbytes == 0:
-            raise FpsError(FPS_E_INVALID, "fps_workspace_bytes rejected the grid description")
-        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
-        off = (-self.ws.data_ptr()) % 256
-        self.ws_ptr = C.c_void_p(self.ws.data_ptr() + off)
-        self.ws_bytes = nbytes
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        self.h_ = C.c_void_p()
-        self._check(L.fps_create(C.byref(self.desc_c), C.byref(self.ped_c), self.max_agents, self.ws_ptr,
-                                 nbytes, C.c_void_p(self.stream.cuda_stream), C.byref(self.h_)), None)
+        self.h_ = h
+        L = self._lib
         f32 = dict(dtype=torch.float32, device=self.device)
         self.h = torch.tensor(np.asarray(sc.h, np.float32), **f32).contiguous()
         self.qx = torch.tensor(np.asarray(sc.qx, np.float32), **f32).contiguous()
         self.qy = torch.tensor(np.asarray(sc.qy, np.float32), **f32).contiguous()
         self.z = torch.tensor(np.asarray(sc.z, np.float32), **f32).contiguous()
-        self._check(L.fps_bind_fields(self.h_, _ptr(self.h), _ptr(self.qx), _ptr(self.qy), _ptr(self.z)))
+        self._check(L.fps_bind_fields(h, _ptr(self.h), _ptr(self.qx), _ptr(self.qy), _ptr(self.z)))
         if sc.hydro_t is not None and len(sc.hydro_t):
             t = np.ascontiguousarray(sc.hydro_t, np.float64)
             q = np.ascontiguousarray(sc.hydro_q, np.float64)
-            self._check(L.fps_set_hydrograph(self.h_, t.ctypes.data_as(C.POINTER(C.c_double)),
+            self._check(L.fps_set_hydrograph(h, t.ctypes.data_as(C.POINTER(C.c_double)),
                                              q.ctypes.data_as(C.POINTER(C.c_double)), len(t)))
         if sc.dist is not None:
             self.dist = torch.tensor(np.asarray(sc.dist, np.float32), **f32).contiguous()
             self.walk = torch.tensor(np.asarray(sc.walk, np.uint8), dtype=torch.uint8,
                                      device=self.device).contiguous()
-            self._check(L.fps_set_navigation(self.h_, self.dist.shape[0], sc.n_exit, _ptr(self.dist),
+            self._check(L.fps_set_navigation(h, self.dist.shape[0], sc.n_exit, _ptr(self.dist),
                                              _ptr(self.walk)))
         if sc.barrier is not None:
             b = sc.barrier
             cells = np.ascontiguousarray(b["cells"], np.int32)
-            self._check(L.fps_set_barrier(self.h_, cells.ctypes.data_as(C.POINTER(C.c_int32)), len(cells),
+            self._check(L.fps_set_barrier(h, cells.ctypes.data_as(C.POINTER(C.c_int32)), len(cells),
                                           b["storage_dest"], b["barrier_dest"], b["n_layers"],
                                           float(b["t_bag"]), float(b["t_last"]), b["bags_per"]))
-        self.na = na
-        if na:
+        self.na = 0 if sc.agents is None else len(sc.agents["x"])
+        if self.na:
             A = sc.agents
             self.agents_t = {
                 k: torch.tensor(np.asarray(A[k]), device=self.device).contiguous()
                 for k in ("x", "y", "vx", "vy", "v_base", "role", "state", "hr_class", "dest", "timer")}
             a = self.agents_t
-            self._check(L.fps_bind_agents(self.h_, na, *[_ptr(a[k]) for k in (
+            self._check(L.fps_bind_agents(h, self.na, *[_ptr(a[k]) for k in (
                 "x", "y", "vx", "vy", "v_base", "role", "state", "hr_class", "dest", "timer")]))
         if sc.t0:
             self.set_time(sc.t0, 0)
 
-    # ------------------------------------------------------------------
     def _check(self, rc, h=0):
         if rc != FPS_OK:
             msg = self._lib.fps_last_error(self.h_ if h == 0 else h)
             raise FpsError(rc, (msg or b"").decode())
         return rc
 
-    def close(self):
-        if getattr(self, "h_", None) and self.h_.value:
-            self._lib.fps_destroy(self.h_)
-            self.h_ = C.c_void_p()
-
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
-
-    def step(self, n=1):
-        return self._check(self._lib.fps_step(self.h_, int(n)))
-
-    def step_profiled(self, n):
-        ms = (C.c_double * 5)()
-        self._check(self._lib.fps_step_profiled(self.h_, int(n), ms))
-        return list(ms)
-
     def set_time(self, t, step=0):
         return self._check(self._lib.fps_set_time(self.h_, float(t), int(step)))
+
+    def set_end_time(self, t_end):
+        return self._check(self._lib.fps_set_end_time(self.h_, float(t_end)))
 
     def rebind_fields(self):
         return self._check(self._lib.fps_bind_fields(self.h_, _ptr(self.h), _ptr(self.qx), _ptr(self.qy),
                                                      _ptr(self.z)))
+
+    def autotune(self, cache_path=None):
+        rows, ms = C.c_int32(), C.c_double()
+        cp = None if cache_path is None else str(cache_path).encode()
+        self._check(self._lib.fps_autotune(self.h_, cp, C.byref(rows), C.byref(ms)))
+        return rows.value, ms.value
+
+    def set_rows_per_wave(self, rows):
+        return self._check(self._lib.fps_set_rows_per_wave(self.h_, int(rows)))
 
     def diag(self, check=True):
         d = DiagC()
@@ -258,3 +268,270 @@ class Sim:
         self.torch.cuda.synchronize(self.device)
         bs = bs.cpu().numpy()
         return bs, perm.cpu().numpy()[: bs[-1]]
+
+
+def _workspace(torch, nbytes, device):
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-ws.data_ptr()) % 256
+    return ws, C.c_void_p(ws.data_ptr() + off)
+
+
+class Sim(Member):
+    """One scenario on one GPU: device tensors + a standalone libfps handle."""
+
+    def __init__(self, sc, device="cuda", stream=None, max_agents=None):
+        import torch
+        self._lib = L = lib()
+        d = sc.desc
+        self.desc_c = grid_desc_c(d)
+        self.ped_c = ped_params_c(sc.ped)
+        na = 0 if sc.agents is None else len(sc.agents["x"])
+        self.max_agents = na if max_agents is None else max_agents
+        nbytes = L.fps_workspace_bytes(C.byref(self.desc_c), self.max_agents)
+        if nbytes == 0:
+            raise FpsError(FPS_E_INVALID, "fps_workspace_bytes rejected the grid description")
+        dev = torch.device(device)
+        self.ws, self.ws_ptr = _workspace(torch, nbytes, dev)
+        self.ws_bytes = nbytes
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        h = C.c_void_p()
+        self.h_ = h
+        self._check(L.fps_create(C.byref(self.desc_c), C.byref(self.ped_c), self.max_agents, self.ws_ptr,
+                                 nbytes, C.c_void_p(self.stream.cuda_stream), C.byref(h)), None)
+        self._bind(h, sc, device)
+
+    def close(self):
+        if getattr(self, "h_", None) and self.h_.value:
+            self._lib.fps_destroy(self.h_)
+            self.h_ = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n=1):
+        return self._check(self._lib.fps_step(self.h_, int(n)))
+
+    def step_profiled(self, n):
+        ms = (C.c_double * 5)()
+        self._check(self._lib.fps_step_profiled(self.h_, int(n), ms))
+        return list(ms)
+
+    def set_graph(self, steps_per_graph):
+        return self._check(self._lib.fps_set_graph(self.h_, int(steps_per_graph)))
+
+
+class _EnsMember(Member):
+    def __init__(self, lib_, handle, sc, device):
+        self._lib = lib_
+        self._bind(handle, sc, device)
+
+
+class Ensemble:
+    """S scenarios of uneven grids stepped together by one set of launches per step."""
+
+    def __init__(self, scenarios, device="cuda", stream=None):
+        import torch
+        self.torch = torch
+        self._lib = L = lib()
+        S = len(scenarios)
+        self.descs = (GridDescC * S)(*[grid_desc_c(sc.desc) for sc in scenarios])
+        self.peds = (PedParamsC * S)(*[ped_params_c(sc.ped) for sc in scenarios])
+        na = [0 if sc.agents is None else len(sc.agents["x"]) for sc in scenarios]
+        self.max_agents = (C.c_int32 * S)(*na)
+        nbytes = L.fps_ens_workspace_bytes(S, self.descs, self.max_agents)
+        if nbytes == 0:
+            raise FpsError(FPS_E_INVALID, "fps_ens_workspace_bytes rejected the scenarios")
+        dev = torch.device(device)
+        self.ws, ws_ptr = _workspace(torch, nbytes, dev)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        self.e_ = C.c_void_p()
+        rc = L.fps_ens_create(S, self.descs, self.peds, self.max_agents, ws_ptr, nbytes,
+                              C.c_void_p(self.stream.cuda_stream), C.byref(self.e_))
+        if rc != FPS_OK:
+            raise FpsError(rc, (L.fps_last_error(None) or b"").decode())
+        self.members = [_EnsMember(L, C.c_void_p(L.fps_ens_member(self.e_, k)), sc, device)
+                        for k, sc in enumerate(scenarios)]
+
+    def _check(self, rc):
+        if rc != FPS_OK:
+            raise FpsError(rc, (self._lib.fps_ens_last_error(self.e_) or b"").decode())
+        return rc
+
+    def __len__(self):
+        return len(self.members)
+
+    def __getitem__(self, k):
+        return self.members[k]
+
+    def step(self, n=1):
+        return self._check(self._lib.fps_ens_step(self.e_, int(n)))
+
+    def step_profiled(self, n):
+        ms = (C.c_double * 5)()
+        self._check(self._lib.fps_ens_step_profiled(self.e_, int(n), ms))
+        return list(ms)
+
+    def set_graph(self, steps_per_graph):
+        return self._check(self._lib.fps_ens_set_graph(self.e_, int(steps_per_graph)))
+
+    def autotune(self, cache_path=None):
+        cp = None if cache_path is None else str(cache_path).encode()
+        return self._check(self._lib.fps_ens_autotune(self.e_, cp))
+
+    def active(self):
+        n = C.c_int32()
+        self._check(self._lib.fps_ens_active(self.e_, C.byref(n)))
+        return n.value
+
+    def close(self):
+        if getattr(self, "e_", None) and self.e_.value:
+            self.torch.cuda.synchronize()
+            self._lib.fps_ens_destroy(self.e_)
+            self.e_ = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Surrogate:
+    """BF16 MFMA convolutional surrogate (training and inference in libfps).
+    Inputs/outputs are torch device tensors: x bf16 [n, H, W, 16], y / target
+    fp32 [n, H, W, 4]."""
+
+    def __init__(self, max_batch, H, W, device="cuda", stream=None):
+        import torch
+        self.torch = torch
+        self._lib = L = lib()
+        self.H, self.W, self.max_batch = H, W, max_batch
+        nbytes = L.fps_sur_workspace_bytes(max_batch, H, W)
+        if nbytes == 0:
+            raise FpsError(FPS_E_INVALID, "surrogate shape rejected (H % 8, W % 32)")
+        dev = torch.device(device)
+        self.device = dev
+        self.ws, ws_ptr = _workspace(torch, nbytes, dev)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        self.s_ = C.c_void_p()
+        rc = L.fps_sur_create(max_batch, H, W, ws_ptr, nbytes, C.c_void_p(self.stream.cuda_stream),
+                              C.byref(self.s_))
+        if rc != FPS_OK:
+            raise FpsError(rc, (L.fps_sur_last_error(None) or b"").decode())
+        self.n_params = L.fps_sur_param_count()
+        self.loss_t = torch.zeros(1, dtype=torch.float32, device=dev)
+
+    def _check(self, rc):
+        if rc != FPS_OK:
+            raise FpsError(rc, (self._lib.fps_sur_last_error(self.s_) or b"").decode())
+        return rc
+
+    def set_params(self, params):
+        p = params.to(self.device, self.torch.float32).contiguous()
+        assert p.numel() == self.n_params
+        self._keep = p
+        return self._check(self._lib.fps_sur_set_params(self.s_, _ptr(p)))
+
+    def get_params(self):
+        p = self.torch.empty(self.n_params, dtype=self.torch.float32, device=self.device)
+        self._check(self._lib.fps_sur_get_params(self.s_, _ptr(p)))
+        return p
+
+    def forward(self, x, y=None):
+        n = x.shape[0]
+        if y is None:
+            y = self.torch.empty((n, self.H, self.W, 4), dtype=self.torch.float32, device=self.device)
+        self._check(self._lib.fps_sur_forward(self.s_, n, _ptr(x), _ptr(y)))
+        return y
+
+    def gradients(self, x, target):
+        g = self.torch.empty(self.n_params, dtype=self.torch.float32, device=self.device)
+        self._check(self._lib.fps_sur_gradients(self.s_, x.shape[0], _ptr(x), _ptr(target), _ptr(g),
+                                                _ptr(self.loss_t)))
+        return self.loss_t, g
+
+    def train_step(self, x, target, lr):
+        self._check(self._lib.fps_sur_train_step(self.s_, x.shape[0], _ptr(x), _ptr(target), float(lr),
+                                                 _ptr(self.loss_t)))
+        return self.loss_t
+
+    def close(self):
+        if getattr(self, "s_", None) and self.s_.value:
+            self.torch.cuda.synchronize()
+            self._lib.fps_sur_destroy(self.s_)
+            self.s_ = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _stream_ptr(torch, t, stream):
+    st = stream if stream is not None else torch.cuda.current_stream(t.device)
+    return C.c_void_p(st.cuda_stream)
+
+
+def sur_pack(h, hu, hv, z, occupancy=None, out=None, stream=None):
+    """Surrogate input bf16 [H, W, 16] from float32 device planes [H, W]
+    (occupancy: int32 evacuee counts per cell, or None)."""
+    import torch
+    if out is None:
+        out = torch.empty(h.shape + (16,), dtype=torch.bfloat16, device=h.device)
+    occ = _ptr(occupancy) if occupancy is not None else None
+    rc = lib().fps_sur_pack(h.numel(), _ptr(h), _ptr(hu), _ptr(hv), _ptr(z), occ, _ptr(out),
+                            _stream_ptr(torch, h, stream))
+    if rc != FPS_OK:
+        raise FpsError(rc, (lib().fps_sur_last_error(None) or b"").decode())
+    return out
+
+
+def sur_make_target(s0, s1, out=None, stream=None):
+    """Training target fp32 [H, W, 4] from two flood states (h, hu, hv)."""
+    import torch
+    h0 = s0[0]
+    if out is None:
+        out = torch.empty(h0.shape + (4,), dtype=torch.float32, device=h0.device)
+    rc = lib().fps_sur_make_target(h0.numel(), *[_ptr(a) for a in (*s0, *s1)], _ptr(out),
+                                   _stream_ptr(torch, h0, stream))
+    if rc != FPS_OK:
+        raise FpsError(rc, (lib().fps_sur_last_error(None) or b"").decode())
+    return out
+
+
+def sur_apply(y, h, hu, hv, h_dry=1e-5, stream=None):
+    """Apply a surrogate output fp32 [H, W, 4] to (h, hu, hv) in place."""
+    import torch
+    rc = lib().fps_sur_apply(h.numel(), _ptr(y), _ptr(h), _ptr(hu), _ptr(hv), float(h_dry),
+                             _stream_ptr(torch, h, stream))
+    if rc != FPS_OK:
+        raise FpsError(rc, (lib().fps_sur_last_error(None) or b"").decode())
+
+
+def sur_judge(x, y, state, nx, ny, dx, dy, a, b, tol=0.01, h_dry=1e-5,
+              hr_thresholds=(0.75, 1.5, 2.5), out=None, stream=None):
+    """Judge a surrogate state a = (h, qx, qy) against a finite-volume state b
+    at the agents' cells; returns the device int32[2] result (count of agents
+    with |dh| > tol or another hazard class, max |dh| as float bits)."""
+    import torch
+    if out is None:
+        out = torch.empty(2, dtype=torch.int32, device=a[0].device)
+    thr = (C.c_double * 3)(*hr_thresholds)
+    rc = lib().fps_sur_judge(int(x.numel()), _ptr(x), _ptr(y), _ptr(state), int(nx), int(ny), float(dx),
+                             float(dy), *[_ptr(t) for t in (*a, *b)], float(tol), float(h_dry), thr,
+                             _ptr(out), _stream_ptr(torch, a[0], stream))
+    if rc != FPS_OK:
+        raise FpsError(rc, (lib().fps_sur_last_error(None) or b"").decode())
+    return out
+
+
+def judge_result(out):
+    """(count, max |dh|) from a sur_judge result tensor."""
+    import numpy as np
+    v = out.cpu().numpy().astype(np.int32)
+    return int(v[0]), float(v[1:2].view(np.float32)[0])
+

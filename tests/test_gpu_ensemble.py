@@ -1,0 +1,94 @@
+"""GPU checks of the ensemble path: one set of launches per step over
+scenarios of uneven grids must give, scenario by scenario, exactly the
+results of running each scenario alone; graph replay must equal eager
+launches; end times and the dry-step skip must hold."""
+import numpy as np
+import pytest
+
+from paper_1908_05232_amd import fps, inputs as I
+from tests.gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+
+def mixed_scenarios():
+    a = I.shopping_centre(n=96, dx=0.5, seed=11, n_evac=300, q_peak=1.5, duration=120.0)
+    b = I.shopping_centre(n=160, dx=0.5, seed=12, n_evac=700, q_peak=2.5, duration=120.0)
+    b = I.add_barrier(b, seed=12, n_resp=30, height=0.4)
+    c = I.cfg1_dam_break(n_ped=150)
+    d = I.lake_at_rest(70, 33, 0.5, seed=5)
+    return [a, b, c, d]
+
+
+def test_ensemble_equals_solo_runs():
+    scs = mixed_scenarios()
+    ens = fps.Ensemble(scs)
+    ens.step(157)
+    for k, sc in enumerate(scs):
+        solo = fps.Sim(sc)
+        solo.step(157)
+        fe, fs = ens[k].fields(), solo.fields()
+        for x, y in zip(fe, fs):
+            assert np.array_equal(x, y), (k, sc.name)
+        if sc.agents is not None:
+            A, B = ens[k].agents(), solo.agents()
+            for key in A:
+                assert np.array_equal(A[key], B[key]), (k, key)
+        de, ds = ens[k].diag(), solo.diag()
+        assert de["t"] == ds["t"] and de["mass"] == ds["mass"] and de["drops_total"] == ds["drops_total"]
+        say(f"scenario {k} ({sc.name}): t = {de['t']:.3f} s, identical to the solo run")
+
+
+def test_graph_replay_equals_eager():
+    sc = I.shopping_centre(n=128, dx=0.5, seed=8, n_evac=400)
+    a, b = fps.Sim(sc), fps.Sim(sc)
+    a.set_graph(0)
+    b.set_graph(16)
+    a.step(200)
+    b.step(200)       # 12 graph replays + 8 eager steps
+    for x, y in zip(a.fields(), b.fields()):
+        assert np.array_equal(x, y)
+    A, B = a.agents(), b.agents()
+    for k in A:
+        assert np.array_equal(A[k], B[k])
+    assert a.diag()["t"] == b.diag()["t"]
+
+
+def test_end_times_stop_scenarios():
+    scs = mixed_scenarios()[:3]
+    ens = fps.Ensemble(scs)
+    ends = [2.0, 5.0, 1e9]
+    for m, t_end in zip(ens.members, ends):
+        m.set_end_time(t_end)
+    assert ens.active() == 3
+    ens.step(400)
+    d = [m.diag() for m in ens.members]
+    say("times:", [x["t"] for x in d], "active:", [x["active"] for x in d])
+    assert ens.active() == 1
+    for x, t_end in zip(d[:2], ends[:2]):
+        assert x["t"] >= t_end and x["t"] - x["dt_last"] < t_end and x["active"] == 0
+    # stopped scenarios no longer change
+    f0 = ens[0].fields()
+    ens.step(10)
+    assert all(np.array_equal(x, y) for x, y in zip(f0, ens[0].fields()))
+
+
+def test_dry_steps_skip_the_flood_update(oracle):
+    sc = I.shopping_centre(n=128, dx=0.5, seed=21, n_evac=50, t_flood=30.0, q_peak=1.0,
+                           duration=60.0)
+    sc = I.add_barrier(sc, seed=21, n_resp=20, height=0.2)
+    sim = fps.Sim(sc)
+    sim.step(40)
+    d = sim.diag()
+    say(f"after 40 steps: t = {d['t']:.2f} s, flood updates run: {d['flood_steps']}")
+    # 30 dry steps of 1 s before the hydrograph starts; the first step always runs
+    assert d["flood_steps"] < d["step"] and d["any_wet"] == 1
+    ref = oracle.OracleSim(sc)
+    dts = []
+    sim2 = fps.Sim(sc)
+    for _ in range(40):
+        sim2.step(1)
+        dts.append(sim2.diag()["dt_last"])
+    ref.run(40, dts=np.array(dts))
+    h, _, _, _ = sim2.fields()
+    assert np.abs(h - ref.fields()[0]).max() <= 1e-4

@@ -100,3 +100,23 @@ def test_bulk_equals_single_steps_and_repeatable():
     for x, y, w in zip(fa, fb, fc):
         assert np.array_equal(x, y) and np.array_equal(x, w)
     assert a.diag()["t"] == b.diag()["t"] == c.diag()["t"]
+
+
+def test_tile_shape_does_not_change_results(tmp_path):
+    sc = I.shopping_centre(n=200, dx=0.5, seed=4, n_evac=10)
+    sc.agents = None
+    out = []
+    for rows in (1, 4, 64):
+        sim = fps.Sim(sc)
+        sim.set_rows_per_wave(rows)
+        sim.step(120)
+        out.append(sim.fields())
+    for f in out[1:]:
+        for x, y in zip(out[0], f):
+            assert np.array_equal(x, y)
+    sim = fps.Sim(sc)
+    cache = tmp_path / "tiles.txt"
+    rows, ms = sim.autotune(cache)
+    say(f"autotuned rows per wave {rows} ({ms:.4f} ms)")
+    assert rows in (1, 2, 4, 8, 16, 32, 64) and ms > 0
+    assert sim.autotune(cache)[0] == rows and len(cache.read_text().splitlines()) == 1
