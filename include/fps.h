@@ -180,6 +180,23 @@ int fps_step(fps_sim* sim, int32_t n_steps);
    further steps leave it unchanged.  Synchronises. */
 int fps_set_end_time(fps_sim* sim, double t_end);
 
+/* Judge region (used to check a learned flood update against the finite-
+   volume method on part of the grid): while mask is set, a flood update
+   writes only the cells of waves that meet a set block of the mask, a
+   device uint8 [ceil(ny/block)][ceil(nx/block)] array of block x block cell
+   blocks (caller-owned, read at every step, so its contents may change
+   between calls), and every step has length dt_max (no CFL limit).  Cells
+   outside the region keep stale values; a region of k steps is exact at
+   cells more than k cells inside its border.  mask NULL restores the
+   normal update.  block in [1, 4096]. */
+int fps_set_judge_region(fps_sim* sim, const uint8_t* mask, int32_t block);
+
+/* Per-cell evacuee counts that raise the Manning coefficient (sec. 2.3) for
+   a simulation with no agents bound: device int32 [ny][nx], copied
+   (asynchronously) and kept until the next call; NULL clears them.
+   FPS_E_STATE when agents are bound (their counts are used). */
+int fps_set_occupancy(fps_sim* sim, const int32_t* counts);
+
 /* Steps per captured HIP graph for fps_step (0 = launch every step
    eagerly); calls with fewer steps run eagerly.  Results are identical. */
 int fps_set_graph(fps_sim* sim, int32_t steps_per_graph);
@@ -289,14 +306,31 @@ int fps_sur_make_target(int64_t npix, const float* h0, const float* hu0, const f
    afterwards so its next time step is recomputed.) */
 int fps_sur_apply(int64_t npix, const float* y, float* h, float* hu, float* hv, float h_dry, void* stream);
 /* Judge of a surrogate state (a) against a finite-volume state (b) at the
-   cells of the non-exited agents (x, y, state: device SoA of length na):
-   out2[0] = agents whose depth differs by more than tol (m) or whose hazard
-   class (Table 1; thresholds hr_thresholds[3], host) differs; out2[1] = the
-   largest depth difference as float bits.  out2: device int32[2]; async. */
-int fps_sur_judge(int32_t na, const float* x, const float* y, const uint8_t* state, int32_t nx, int32_t ny,
-                  double dx, double dy, const float* ha, const float* qxa, const float* qya,
-                  const float* hb, const float* qxb, const float* qyb, double tol, double h_dry,
-                  const double* hr_thresholds, int32_t* out2, void* stream);
+   cells of the sampled agents: every stride-th agent of the device SoA
+   (x, y, state) of length na that has not exited.  out2[0] = sampled agents
+   whose depth differs by more than tol (m) or whose hazard class (Table 1;
+   thresholds hr_thresholds[3], host) differs; out2[1] = the largest depth
+   difference as float bits.  Cells: floor(x / dx) in FP32, clamped to the
+   grid.  out2: device int32[2]; async. */
+int fps_sur_judge(int32_t na, int32_t stride, const float* x, const float* y, const uint8_t* state,
+                  int32_t nx, int32_t ny, double dx, double dy, const float* ha, const float* qxa,
+                  const float* qya, const float* hb, const float* qxb, const float* qyb, double tol,
+                  double h_dry, const double* hr_thresholds, int32_t* out2, void* stream);
+/* Judge region for fps_set_judge_region: clears mask (device uint8
+   [ceil(ny/block)][ceil(nx/block)]) and marks every block within halo cells of
+   the cell of a sampled agent (the same sample as fps_sur_judge); async. */
+int fps_sur_judge_mask(int32_t na, int32_t stride, const float* x, const float* y, const uint8_t* state,
+                       int32_t nx, int32_t ny, double dx, double dy, int32_t halo, int32_t block,
+                       uint8_t* mask, void* stream);
+/* Per-cell counts of evacuees still evacuating (role evacuee, state EVAC),
+   the counts that raise the Manning coefficient (sec. 2.3), into device int32
+   [ny][nx]; async. */
+int fps_sur_occupancy(int32_t na, const float* x, const float* y, const uint8_t* role,
+                      const uint8_t* state, int32_t nx, int32_t ny, double dx, double dy,
+                      int32_t* counts, void* stream);
+/* Device copy of a flood state (h, hu, hv) of npix cells; async. */
+int fps_sur_copy_state(int64_t npix, const float* h, const float* hu, const float* hv, float* h_out,
+                       float* hu_out, float* hv_out, void* stream);
 const char* fps_sur_last_error(const fps_sur* sur);
 
 const char* fps_status_string(int status);

@@ -11,6 +11,14 @@ scaled by fixed constants and padded with zeros to 16 channels -> 64 -> 64 ->
 scaled change of (h, hu, hv) over the k steps.  Loss: mean squared error over
 all outputs.  Optimiser: Adam (Kingma & Ba 2015) on FP32 master weights.
 
+Precision: the network keeps its weights, activations and the gradients
+that flow between layers in BF16 and accumulates in FP32.  With bf16=True
+the oracle rounds at exactly those points (weights are passed in already
+rounded; each hidden activation after its ReLU, the loss gradient and each
+input gradient of a layer are rounded to BF16, round-to-nearest-even through
+FP32) and computes everything else in FP64; with bf16=False it is the plain
+FP64 network.
+
 Everything here is the definition written out with plain loops over the nine
 kernel taps and one matrix product per tap (a library primitive as a step).
 """
@@ -24,6 +32,16 @@ LAYERS = [(CIN0, WIDTH), (WIDTH, WIDTH), (WIDTH, WIDTH), (WIDTH, WIDTH), (WIDTH,
 # fixed input / output scales: h, hu, hv, z, occupancy  ->  O(1) values
 IN_SCALE = np.array([1.0, 1.0, 1.0, 1.0 / 3.0, 0.25] + [0.0] * 11)
 OUT_SCALE = np.array([0.05, 0.05, 0.05])     # scaled change of (h, hu, hv) over k steps
+
+
+def bf16_round(a):
+    """Round to the nearest BF16 value (ties to even), through FP32: keep the
+    upper 16 bits of the FP32 pattern after adding half of the dropped part's
+    unit, plus one when the kept part is odd."""
+    f = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64).reshape(f.shape)
 
 
 def init_params(seed: int = 0):
@@ -68,7 +86,11 @@ def conv3x3_backward(x, w, dy):
     return dxp[:, 1:-1, 1:-1, :], dw, db
 
 
-def forward(params, x):
+def _round(a, bf16):
+    return bf16_round(a) if bf16 else a
+
+
+def forward(params, x, bf16=False):
     """Returns the output and the per-layer inputs / pre-activations."""
     acts, pres = [], []
     a = x
@@ -76,16 +98,16 @@ def forward(params, x):
         acts.append(a)
         z = conv3x3(a, w, b)
         pres.append(z)
-        a = np.maximum(z, 0.0) if li < len(params) - 1 else z
+        a = _round(np.maximum(z, 0.0), bf16) if li < len(params) - 1 else z
     return a, acts, pres
 
 
-def loss_and_grads(params, x, target):
+def loss_and_grads(params, x, target, bf16=False):
     """MSE loss over all outputs and its gradients (list of (dw, db))."""
-    y, acts, pres = forward(params, x)
+    y, acts, pres = forward(params, x, bf16)
     diff = y - target
     loss = float(np.mean(diff * diff))
-    g = 2.0 * diff / diff.size
+    g = _round(2.0 * diff / diff.size, bf16)
     grads = [None] * len(params)
     for li in range(len(params) - 1, -1, -1):
         w, _ = params[li]
@@ -93,7 +115,7 @@ def loss_and_grads(params, x, target):
             g = g * (pres[li] > 0.0)
         dxl, dw, db = conv3x3_backward(acts[li], w, g)
         grads[li] = (dw, db)
-        g = dxl
+        g = _round(dxl, bf16)
     return loss, grads
 
 

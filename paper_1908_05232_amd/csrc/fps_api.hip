@@ -45,6 +45,8 @@ struct fps_sim {
     int n_inflow;
     bool use_wmask;
     double t_end;
+    const uint8_t* jmask;  // judge region (NULL: whole grid, CFL time step)
+    int jb;
     // bound caller memory
     float *h, *qx, *qy, *z;
     bool fields_bound;
@@ -242,6 +244,8 @@ fps_sim* new_member(Engine* e, int idx, const fps_grid_desc* d, const fps_ped_pa
     s->n_inflow = d->inflow_side >= 0 ? d->inflow_c1 - d->inflow_c0 : 0;
     s->storage_dest = s->barrier_dest = -1;
     s->t_end = 0.0;
+    s->jmask = nullptr;
+    s->jb = 0;
     return s;
 }
 
@@ -255,6 +259,10 @@ int init_member_device(fps_sim* s)
     hipStream_t st = s->eng->stream;
     HIPCHK(s, hipMemcpyAsync(s->st, &h0, sizeof(h0), hipMemcpyHostToDevice, st));
     HIPCHK(s, launch_fill_i32(s->np, 0, (int64_t)s->G.nx * s->G.ny, st));
+    // the second flood buffer starts as a dry state (a judge region updates
+    // only part of it and reads the rest)
+    for (float* f : {s->h2, s->qx2, s->qy2})
+        HIPCHK(s, launch_fill_i32(reinterpret_cast<int32_t*>(f), 0, (int64_t)s->G.nx * s->G.ny, st));
     if (s->max_agents > 0)
         HIPCHK(s, launch_fill_i32(s->bin_count, 0, (int64_t)s->G.nx * s->G.ny, st));
     HIPCHK(s, hipStreamSynchronize(st));
@@ -287,6 +295,10 @@ void fill_scn(const fps_sim* s, Scn& c)
     p.eps = (float)s->G.h_dry; p.cfl = (float)s->G.cfl; p.dt_max = (float)s->G.dt_max;
     p.n_base = (float)s->G.n_base;
     p.dxdy = s->G.dx * s->G.dy;
+    p.jmask = s->jmask;
+    p.jb = s->jb > 0 ? s->jb : 1;
+    p.jbx = (s->G.nx + p.jb - 1) / p.jb;
+    p.jby = (s->G.ny + p.jb - 1) / p.jb;
 
     PedParams& q = c.ped;
     q.x = s->x; q.y = s->y; q.vx = s->vx; q.vy = s->vy; q.vbase = s->vbase;
@@ -988,6 +1000,28 @@ int fps_set_time(fps_sim* s, double t, int64_t step)
     int rc = write_state_i32(s, &s->st->active, !(s->t_end > 0.0) || t < s->t_end);
     if (rc != FPS_OK) return rc;
     return prime(s);
+}
+
+int fps_set_judge_region(fps_sim* s, const uint8_t* mask, int32_t block)
+{
+    if (!s) return fail(nullptr, FPS_E_INVALID, "fps_set_judge_region: sim is NULL");
+    if (mask && (block < 1 || block > 4096))
+        return fail(s, FPS_E_INVALID, "fps_set_judge_region: block must be in [1, 4096]");
+    s->jmask = mask;
+    s->jb = mask ? block : 0;
+    mark_dirty(s);
+    return FPS_OK;
+}
+
+int fps_set_occupancy(fps_sim* s, const int32_t* counts)
+{
+    if (!s) return fail(nullptr, FPS_E_INVALID, "fps_set_occupancy: sim is NULL");
+    if (s->na > 0) return fail(s, FPS_E_STATE, "fps_set_occupancy: agents are bound; counts come from them");
+    hipStream_t st = s->eng->stream;
+    const size_t nc = (size_t)s->G.nx * s->G.ny;
+    if (counts) HIPCHK(s, hipMemcpyAsync(s->np, counts, sizeof(int32_t) * nc, hipMemcpyDeviceToDevice, st));
+    else HIPCHK(s, launch_fill_i32(s->np, 0, (int64_t)nc, st));
+    return FPS_OK;
 }
 
 int fps_set_end_time(fps_sim* s, double t_end)

@@ -189,6 +189,24 @@ __global__ __launch_bounds__(kFvBlock) void fv_step_kernel(Batch B)
 
     {
         const int sx = tile % p.nsx, sy = tile / p.nsx;
+        if (p.jmask) {
+            // judge region: skip waves whose output cells meet no set block
+            const int bx0 = sx * kStrip / p.jb, bx1 = min(sx * kStrip + kStrip - 1, p.nx - 1) / p.jb;
+            const int by0 = sy * p.H / p.jb, by1 = (min(sy * p.H + p.H, p.ny) - 1) / p.jb;
+            int any = 0;
+            for (int by = by0; by <= by1 && !any; ++by)
+                for (int bx = bx0; bx <= bx1; ++bx) any |= p.jmask[by * p.jbx + bx];
+            if (!any) {
+                if (lane == 0) {
+                    double* dst = &p.partials[4 * tile];
+                    dst[0] = 0.0;
+                    dst[1] = 0.0;
+                    dst[2] = 0.0;
+                    dst[3] = 0.0;
+                }
+                return;
+            }
+        }
         const int i = sx * kStrip - 1 + lane;
         const int ii = min(max(i, 0), p.nx - 1);
         const int j0 = sy * p.H, j1 = min(j0 + p.H, p.ny);
@@ -422,7 +440,7 @@ __global__ __launch_bounds__(kScanThreads) void finalize_kernel(Batch B, int mod
             float smax = (float)red[0][3];
             st->mass = red[0][0] * p.dxdy;
             st->any_wet = smax > 0.0f;
-            st->dt = st->any_wet ? fminf(p.cfl / smax, p.dt_max) : p.dt_max;
+            st->dt = st->any_wet && !p.jmask ? fminf(p.cfl / smax, p.dt_max) : p.dt_max;
         }
         float dtn = st->dt;
         float inc = 0.0f;

@@ -65,6 +65,11 @@ struct FvParams {
     int np_cap;
     float dx, dy, inv_dx, inv_dy, g, half_g, eps, cfl, dt_max, n_base;
     double dxdy;
+    // judge region: only waves whose cells meet a set block of jmask
+    // ([ceil(ny/jb)][jbx] blocks of jb x jb cells) update; the time step is
+    // then dt_max, not the CFL step
+    const uint8_t* jmask;
+    int jb, jbx, jby;
 };
 
 struct PedParams {

@@ -399,28 +399,75 @@ __device__ __forceinline__ int hazard_class(float h, float qx, float qy, float e
     return hr < thr[0] ? 1 : hr < thr[1] ? 2 : hr < thr[2] ? 3 : 4;
 }
 
-// Judge: over non-exited agents, count those where the two flood states differ
-// in depth by more than tol or in hazard class (Table 1 thresholds), and the
-// largest depth difference.  out[0] = count (int), out[1] = max |dh| (float bits).
-__global__ void judge_kernel(int na, const float* __restrict__ x, const float* __restrict__ y,
+// containing cell: IEEE division and floor in FP32, clamped to the grid
+__device__ __forceinline__ int cell_index(float x, float d, int n)
+{
+    return (int)fminf(fmaxf(floorf(x / d), 0.0f), (float)(n - 1));
+}
+
+// Judge: over the sampled agents (every stride-th) that have not exited,
+// count those where the two flood states differ in depth by more than tol or
+// in hazard class (Table 1 thresholds), and the largest depth difference.
+// out[0] = count (int), out[1] = max |dh| (float bits).
+__global__ void judge_kernel(int na, int stride, const float* __restrict__ x, const float* __restrict__ y,
                              const uint8_t* __restrict__ state, int nx, int ny, float dx, float dy,
                              const float* __restrict__ ha, const float* __restrict__ qxa,
                              const float* __restrict__ qya, const float* __restrict__ hb,
                              const float* __restrict__ qxb, const float* __restrict__ qyb, float tol,
                              float eps, float t1, float t2, float t3, int32_t* __restrict__ out)
 {
-    const int a = blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= na || state[a] == 1) return;
-    // containing cell: IEEE division and floor in FP32, clamped to the grid
-    const int i = (int)fminf(fmaxf(floorf(x[a] / dx), 0.0f), (float)(nx - 1));
-    const int j = (int)fminf(fmaxf(floorf(y[a] / dy), 0.0f), (float)(ny - 1));
-    const size_t c = (size_t)j * nx + i;
+    const int64_t a = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * stride;
+    if (a >= na || state[a] == FPS_ST_EXITED) return;
+    const size_t c = (size_t)cell_index(y[a], dy, ny) * nx + cell_index(x[a], dx, nx);
     const float thr[3] = {t1, t2, t3};
     const float d = fabsf(ha[c] - hb[c]);
     const bool bad = d > tol || hazard_class(ha[c], qxa[c], qya[c], eps, thr) !=
                                     hazard_class(hb[c], qxb[c], qyb[c], eps, thr);
     if (bad) atomicAdd(&out[0], 1);
     atomicMax(&out[1], __float_as_int(d));    // non-negative floats order as ints
+}
+
+__global__ void fill_u8_kernel(uint8_t* p, int64_t n)
+{
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+        p[k] = 0;
+}
+
+// Judge region: mark every block x block cell block within halo cells of a
+// sampled agent's cell (same sample as the judge).
+__global__ void judge_mask_kernel(int na, int stride, const float* __restrict__ x, const float* __restrict__ y,
+                                  const uint8_t* __restrict__ state, int nx, int ny, float dx, float dy, int halo,
+                                  int block, uint8_t* __restrict__ mask)
+{
+    const int64_t a = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * stride;
+    if (a >= na || state[a] == FPS_ST_EXITED) return;
+    const int i = cell_index(x[a], dx, nx), j = cell_index(y[a], dy, ny);
+    const int mbx = (nx + block - 1) / block;
+    const int bx0 = max(i - halo, 0) / block, bx1 = min(i + halo, nx - 1) / block;
+    const int by0 = max(j - halo, 0) / block, by1 = min(j + halo, ny - 1) / block;
+    for (int by = by0; by <= by1; ++by)
+        for (int bx = bx0; bx <= bx1; ++bx) mask[(size_t)by * mbx + bx] = 1;
+}
+
+// per-cell counts of evacuees still evacuating (the rule of the coupled step)
+__global__ void occupancy_kernel(int na, const float* __restrict__ x, const float* __restrict__ y,
+                                 const uint8_t* __restrict__ role, const uint8_t* __restrict__ state, int nx,
+                                 int ny, float dx, float dy, int32_t* __restrict__ counts)
+{
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= na || role[a] != FPS_ROLE_EVACUEE || state[a] != FPS_ST_EVAC) return;
+    atomicAdd(&counts[(size_t)cell_index(y[a], dy, ny) * nx + cell_index(x[a], dx, nx)], 1);
+}
+
+__global__ void copy3_kernel(int64_t n, const float* __restrict__ a, const float* __restrict__ b,
+                             const float* __restrict__ c, float* __restrict__ A, float* __restrict__ B,
+                             float* __restrict__ Cc)
+{
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        A[k] = a[k];
+        B[k] = b[k];
+        Cc[k] = c[k];
+    }
 }
 
 }  // namespace fps_sur_impl
@@ -759,21 +806,68 @@ int fps_sur_apply(int64_t npix, const float* y, float* h, float* hu, float* hv, 
     return FPS_OK;
 }
 
-int fps_sur_judge(int32_t na, const float* x, const float* y, const uint8_t* state, int32_t nx, int32_t ny,
-                  double dx, double dy, const float* ha, const float* qxa, const float* qya, const float* hb,
-                  const float* qxb, const float* qyb, double tol, double h_dry, const double* hr_thresholds,
-                  int32_t* out2, void* stream)
+int fps_sur_judge(int32_t na, int32_t stride, const float* x, const float* y, const uint8_t* state, int32_t nx,
+                  int32_t ny, double dx, double dy, const float* ha, const float* qxa, const float* qya,
+                  const float* hb, const float* qxb, const float* qyb, double tol, double h_dry,
+                  const double* hr_thresholds, int32_t* out2, void* stream)
 {
-    if (na < 0 || nx < 1 || ny < 1 || !(dx > 0) || !(dy > 0) || !out2 || !hr_thresholds)
+    if (na < 0 || stride < 1 || nx < 1 || ny < 1 || !(dx > 0) || !(dy > 0) || !out2 || !hr_thresholds)
         return sfail(nullptr, FPS_E_INVALID, "fps_sur_judge: bad argument");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    SCHK(nullptr, hipMemsetAsync(out2, 0, 2 * sizeof(int32_t), st));
-    if (na > 0) {
-        hipLaunchKernelGGL(judge_kernel, dim3((na + 255) / 256), dim3(256), 0, st, na, x, y, state, nx, ny, (float)dx,
-                           (float)dy, ha, qxa, qya, hb, qxb, qyb, (float)tol, (float)h_dry, (float)hr_thresholds[0],
-                           (float)hr_thresholds[1], (float)hr_thresholds[2], out2);
+    hipLaunchKernelGGL(fill_u8_kernel, dim3(1), dim3(64), 0, st, reinterpret_cast<uint8_t*>(out2), (int64_t)8);
+    const int64_t ns = ((int64_t)na + stride - 1) / stride;
+    if (ns > 0) {
+        hipLaunchKernelGGL(judge_kernel, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, na, stride, x, y,
+                           state, nx, ny, (float)dx, (float)dy, ha, qxa, qya, hb, qxb, qyb, (float)tol,
+                           (float)h_dry, (float)hr_thresholds[0], (float)hr_thresholds[1],
+                           (float)hr_thresholds[2], out2);
         SCHK(nullptr, hipGetLastError());
     }
+    return FPS_OK;
+}
+
+int fps_sur_judge_mask(int32_t na, int32_t stride, const float* x, const float* y, const uint8_t* state,
+                       int32_t nx, int32_t ny, double dx, double dy, int32_t halo, int32_t block, uint8_t* mask,
+                       void* stream)
+{
+    if (na < 0 || stride < 1 || nx < 1 || ny < 1 || !(dx > 0) || !(dy > 0) || halo < 0 || block < 1 || !mask)
+        return sfail(nullptr, FPS_E_INVALID, "fps_sur_judge_mask: bad argument");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t nm = (int64_t)((nx + block - 1) / block) * ((ny + block - 1) / block);
+    hipLaunchKernelGGL(fill_u8_kernel, dim3((unsigned)std::min<int64_t>((nm + 255) / 256, 1024)), dim3(256), 0, st,
+                       mask, nm);
+    const int64_t ns = ((int64_t)na + stride - 1) / stride;
+    if (ns > 0)
+        hipLaunchKernelGGL(judge_mask_kernel, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, na, stride, x,
+                           y, state, nx, ny, (float)dx, (float)dy, halo, block, mask);
+    SCHK(nullptr, hipGetLastError());
+    return FPS_OK;
+}
+
+int fps_sur_occupancy(int32_t na, const float* x, const float* y, const uint8_t* role, const uint8_t* state,
+                      int32_t nx, int32_t ny, double dx, double dy, int32_t* counts, void* stream)
+{
+    if (na < 0 || nx < 1 || ny < 1 || !(dx > 0) || !(dy > 0) || !counts)
+        return sfail(nullptr, FPS_E_INVALID, "fps_sur_occupancy: bad argument");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t nc = (int64_t)nx * ny;
+    hipLaunchKernelGGL(fill_u8_kernel, dim3((unsigned)std::min<int64_t>((4 * nc + 255) / 256, 4096)), dim3(256), 0,
+                       st, reinterpret_cast<uint8_t*>(counts), 4 * nc);
+    if (na > 0)
+        hipLaunchKernelGGL(occupancy_kernel, dim3((na + 255) / 256), dim3(256), 0, st, na, x, y, role, state, nx, ny,
+                           (float)dx, (float)dy, counts);
+    SCHK(nullptr, hipGetLastError());
+    return FPS_OK;
+}
+
+int fps_sur_copy_state(int64_t npix, const float* h, const float* hu, const float* hv, float* h_out,
+                       float* hu_out, float* hv_out, void* stream)
+{
+    if (npix < 1 || !h || !hu || !hv || !h_out || !hu_out || !hv_out)
+        return sfail(nullptr, FPS_E_INVALID, "fps_sur_copy_state: bad argument");
+    hipLaunchKernelGGL(copy3_kernel, dim3((unsigned)std::min<int64_t>((npix + 255) / 256, 4096)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), npix, h, hu, hv, h_out, hu_out, hv_out);
+    SCHK(nullptr, hipGetLastError());
     return FPS_OK;
 }
 

@@ -95,12 +95,19 @@ EXPORTS = {
     "fps_sur_gradients": (C.c_int, [_vp, C.c_int32, _vp, _vp, _vp, _vp]),
     "fps_sur_adam": (C.c_int, [_vp, C.c_float]),
     "fps_sur_train_step": (C.c_int, [_vp, C.c_int32, _vp, _vp, C.c_float, _vp]),
+    "fps_set_judge_region": (C.c_int, [_vp, _vp, C.c_int32]),
+    "fps_set_occupancy": (C.c_int, [_vp, _vp]),
     "fps_sur_pack": (C.c_int, [C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "fps_sur_make_target": (C.c_int, [C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "fps_sur_apply": (C.c_int, [C.c_int64, _vp, _vp, _vp, _vp, C.c_float, _vp]),
-    "fps_sur_judge": (C.c_int, [C.c_int32, _vp, _vp, _vp, C.c_int32, C.c_int32, C.c_double, C.c_double,
-                                _vp, _vp, _vp, _vp, _vp, _vp, C.c_double, C.c_double,
+    "fps_sur_judge": (C.c_int, [C.c_int32, C.c_int32, _vp, _vp, _vp, C.c_int32, C.c_int32, C.c_double,
+                                C.c_double, _vp, _vp, _vp, _vp, _vp, _vp, C.c_double, C.c_double,
                                 C.POINTER(C.c_double), _vp, _vp]),
+    "fps_sur_judge_mask": (C.c_int, [C.c_int32, C.c_int32, _vp, _vp, _vp, C.c_int32, C.c_int32, C.c_double,
+                                     C.c_double, C.c_int32, C.c_int32, _vp, _vp]),
+    "fps_sur_occupancy": (C.c_int, [C.c_int32, _vp, _vp, _vp, _vp, C.c_int32, C.c_int32, C.c_double,
+                                    C.c_double, _vp, _vp]),
+    "fps_sur_copy_state": (C.c_int, [C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "fps_sur_last_error": (C.c_char_p, [_vp]),
     "fps_set_rows_per_wave": (C.c_int, [_vp, C.c_int32]),
     "fps_autotune": (C.c_int, [_vp, C.c_char_p, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
@@ -220,6 +227,16 @@ class Member:
     def rebind_fields(self):
         return self._check(self._lib.fps_bind_fields(self.h_, _ptr(self.h), _ptr(self.qx), _ptr(self.qy),
                                                      _ptr(self.z)))
+
+    def set_judge_region(self, mask, block):
+        """mask: device uint8 [ceil(ny/block), ceil(nx/block)] tensor or None."""
+        self._jmask = mask
+        ptr = _ptr(mask) if mask is not None else None
+        return self._check(self._lib.fps_set_judge_region(self.h_, ptr, int(block)))
+
+    def set_occupancy(self, counts):
+        self._occ = counts
+        return self._check(self._lib.fps_set_occupancy(self.h_, _ptr(counts) if counts is not None else None))
 
     def autotune(self, cache_path=None):
         rows, ms = C.c_int32(), C.c_double()
@@ -512,21 +529,55 @@ def sur_apply(y, h, hu, hv, h_dry=1e-5, stream=None):
         raise FpsError(rc, (lib().fps_sur_last_error(None) or b"").decode())
 
 
+def _sur_rc(rc):
+    if rc != FPS_OK:
+        raise FpsError(rc, (lib().fps_sur_last_error(None) or b"").decode())
+
+
 def sur_judge(x, y, state, nx, ny, dx, dy, a, b, tol=0.01, h_dry=1e-5,
-              hr_thresholds=(0.75, 1.5, 2.5), out=None, stream=None):
+              hr_thresholds=(0.75, 1.5, 2.5), stride=1, out=None, stream=None):
     """Judge a surrogate state a = (h, qx, qy) against a finite-volume state b
-    at the agents' cells; returns the device int32[2] result (count of agents
-    with |dh| > tol or another hazard class, max |dh| as float bits)."""
+    at the cells of every stride-th agent; returns the device int32[2] result
+    (count of agents with |dh| > tol or another hazard class, max |dh| as
+    float bits)."""
     import torch
     if out is None:
         out = torch.empty(2, dtype=torch.int32, device=a[0].device)
     thr = (C.c_double * 3)(*hr_thresholds)
-    rc = lib().fps_sur_judge(int(x.numel()), _ptr(x), _ptr(y), _ptr(state), int(nx), int(ny), float(dx),
-                             float(dy), *[_ptr(t) for t in (*a, *b)], float(tol), float(h_dry), thr,
-                             _ptr(out), _stream_ptr(torch, a[0], stream))
-    if rc != FPS_OK:
-        raise FpsError(rc, (lib().fps_sur_last_error(None) or b"").decode())
+    _sur_rc(lib().fps_sur_judge(int(x.numel()), int(stride), _ptr(x), _ptr(y), _ptr(state), int(nx), int(ny),
+                                float(dx), float(dy), *[_ptr(t) for t in (*a, *b)], float(tol), float(h_dry),
+                                thr, _ptr(out), _stream_ptr(torch, a[0], stream)))
     return out
+
+
+def sur_judge_mask(x, y, state, nx, ny, dx, dy, halo, block, stride=1, out=None, stream=None):
+    """Judge-region mask (uint8 [ceil(ny/block), ceil(nx/block)]) around the
+    sampled agents' cells."""
+    import torch
+    if out is None:
+        out = torch.empty(((ny + block - 1) // block, (nx + block - 1) // block), dtype=torch.uint8,
+                          device=x.device)
+    _sur_rc(lib().fps_sur_judge_mask(int(x.numel()), int(stride), _ptr(x), _ptr(y), _ptr(state), int(nx),
+                                     int(ny), float(dx), float(dy), int(halo), int(block), _ptr(out),
+                                     _stream_ptr(torch, x, stream)))
+    return out
+
+
+def sur_occupancy(x, y, role, state, nx, ny, dx, dy, out=None, stream=None):
+    """Per-cell counts of evacuees still evacuating (int32 [ny, nx])."""
+    import torch
+    if out is None:
+        out = torch.empty((ny, nx), dtype=torch.int32, device=x.device)
+    _sur_rc(lib().fps_sur_occupancy(int(x.numel()), _ptr(x), _ptr(y), _ptr(role), _ptr(state), int(nx),
+                                    int(ny), float(dx), float(dy), _ptr(out), _stream_ptr(torch, x, stream)))
+    return out
+
+
+def sur_copy_state(src, dst, stream=None):
+    """Copy a flood state (h, hu, hv) into dst (three tensors of the same size)."""
+    import torch
+    _sur_rc(lib().fps_sur_copy_state(src[0].numel(), *[_ptr(t) for t in (*src, *dst)],
+                                     _stream_ptr(torch, src[0], stream)))
 
 
 def judge_result(out):

@@ -1,9 +1,15 @@
 """GPU parity of the BF16 MFMA surrogate kernels against the FP64 oracle.
 
-The GPU rounds weights and activations to BF16 and accumulates in FP32; the
-oracle gets the same BF16-rounded weights and inputs and computes in FP64.
-Bars: forward relative L2 error <= 2e-2; per-tensor gradients cosine >= 0.999
-and relative L2 error <= 2e-2."""
+The GPU keeps weights, activations and inter-layer gradients in BF16 and
+accumulates in FP32.  The oracle rounds at the same points (bf16=True) and
+computes the rest in FP64; against it the bars are forward relative L2
+<= 5e-3 and per-tensor gradients cosine >= 0.9999 and relative L2 <= 1e-2
+(what remains is FP32 against FP64 accumulation, which can move a BF16
+rounding by one unit).  Against the plain FP64 network (bf16=False) the bars
+are those of BF16 rounding compounded over four layers of backward pass:
+forward relative L2 <= 2e-2, gradients cosine >= 0.995 and relative L2
+<= 0.1 (the first layer's weight gradient is a sum with strong cancellation;
+a CPU run with BF16 rounding alone gives 3-6e-2 there)."""
 import numpy as np
 import pytest
 import torch
@@ -16,8 +22,7 @@ pytestmark = pytest.mark.gpu
 COUT_GPU = [64, 64, 64, 64, 16]
 
 
-def bf16_round(a):
-    return torch.tensor(np.asarray(a, np.float32)).bfloat16().float().numpy().astype(np.float64)
+bf16_round = S.bf16_round
 
 
 def pack(params):
@@ -77,29 +82,34 @@ def test_forward_matches_oracle():
     p, xt, _ = to_dev(params, x, target)
     sur.set_params(p)
     y = sur.forward(xt).cpu().numpy()
+    yb, _, _ = S.forward(params, x, bf16=True)
     yo, _, _ = S.forward(params, x)
-    err = rel_l2(y[..., :3], yo)
-    say(f"surrogate forward rel L2 {err:.2e}")
-    assert err <= 2e-2
+    eb, eo = rel_l2(y[..., :3], yb), rel_l2(y[..., :3], yo)
+    say(f"surrogate forward rel L2 {eb:.2e} (bf16 points), {eo:.2e} (fp64)")
+    assert eb <= 5e-3 and eo <= 2e-2
     assert np.all(y[..., 3] == 0.0)
 
 
-def test_gradients_match_oracle():
-    params, x, target = make_case(2, 2, 16, 64)
+@pytest.mark.parametrize("seed", [2, 5])
+def test_gradients_match_oracle(seed):
+    params, x, target = make_case(seed, 2, 16, 64)
     sur = fps.Surrogate(2, 16, 64)
     p, xt, tt = to_dev(params, x, target)
     sur.set_params(p)
     loss, g = sur.gradients(xt, tt)
+    lb, gb = S.loss_and_grads(params, x, target, bf16=True)
     lo, go = S.loss_and_grads(params, x, target)
-    assert float(loss.item()) == pytest.approx(lo, rel=2e-2)
+    assert float(loss.item()) == pytest.approx(lb, rel=5e-3)
     gg = unpack(g.cpu().numpy().astype(np.float64), params)
-    for li, ((dw, db), (dwo, dbo)) in enumerate(zip(gg, go)):
-        if li == 0:
-            dw, dwo = dw[..., :5], dwo[..., :5]       # zero input channels carry no gradient
-        c, e = cosine(dw, dwo), rel_l2(dw, dwo)
-        cb, eb = cosine(db, dbo), rel_l2(db, dbo)
-        say(f"layer {li + 1}: dW cos {c:.6f} rel {e:.2e}; db cos {cb:.6f} rel {eb:.2e}")
-        assert c >= 0.999 and e <= 2e-2 and cb >= 0.999 and eb <= 2e-2
+    for li in range(len(gg)):
+        for ref, cos_min, rel_max, tag in ((gb, 0.9999, 1e-2, "bf16"), (go, 0.995, 0.1, "fp64")):
+            (dw, db), (dwo, dbo) = gg[li], ref[li]
+            if li == 0:
+                dw, dwo = dw[..., :5], dwo[..., :5]       # zero input channels carry no gradient
+            c, e = cosine(dw, dwo), rel_l2(dw, dwo)
+            cb, eb = cosine(db, dbo), rel_l2(db, dbo)
+            say(f"layer {li + 1} vs {tag}: dW cos {c:.6f} rel {e:.2e}; db cos {cb:.6f} rel {eb:.2e}")
+            assert c >= cos_min and e <= rel_max and cb >= cos_min and eb <= rel_max
 
 
 def test_training_reduces_loss_and_matches_adam():
@@ -174,15 +184,92 @@ def test_judge_matches_oracle():
     x = rng.uniform(-1, nx * dx + 1, na).astype(np.float32)
     y = rng.uniform(-1, ny * dy + 1, na).astype(np.float32)
     st = rng.integers(0, 3, na).astype(np.uint8)
-    want = S.judge(x, y, st, nx, ny, dx, dy, a, b, 0.01, 1e-5, (0.75, 1.5, 2.5))
     dv = lambda arr: torch.tensor(arr).cuda()
-    out = fps.sur_judge(dv(x), dv(y), dv(st), nx, ny, dx, dy, tuple(map(dv, a)), tuple(map(dv, b)))
-    got = fps.judge_result(out)
-    say(f"judge: {got} oracle {want}")
-    assert got[0] == want[0] and got[1] == want[1] and want[0] > 0
+    for stride in (1, 3):
+        want = S.judge(x[::stride], y[::stride], st[::stride], nx, ny, dx, dy, a, b, 0.01, 1e-5,
+                       (0.75, 1.5, 2.5))
+        out = fps.sur_judge(dv(x), dv(y), dv(st), nx, ny, dx, dy, tuple(map(dv, a)), tuple(map(dv, b)),
+                            stride=stride)
+        got = fps.judge_result(out)
+        say(f"judge stride {stride}: {got} oracle {want}")
+        assert got[0] == want[0] and got[1] == want[1] and want[0] > 0
     # no agents -> (0, 0); identical states -> (0, 0)
     out0 = fps.sur_judge(dv(x[:0]), dv(y[:0]), dv(st[:0]), nx, ny, dx, dy, tuple(map(dv, a)),
                          tuple(map(dv, b)))
     assert fps.judge_result(out0) == (0, 0.0)
     same = fps.sur_judge(dv(x), dv(y), dv(st), nx, ny, dx, dy, tuple(map(dv, b)), tuple(map(dv, b)))
     assert fps.judge_result(same) == (0, 0.0)
+
+
+def _cells(x, y, nx, ny, dx, dy):
+    i = np.clip(np.floor(x / np.float32(dx)), 0, nx - 1).astype(np.int64)
+    j = np.clip(np.floor(y / np.float32(dy)), 0, ny - 1).astype(np.int64)
+    return i, j
+
+
+def test_occupancy_and_judge_mask():
+    rng = np.random.default_rng(13)
+    nx, ny, dx, dy = 75, 50, 0.25, 0.25
+    na = 4000
+    x = rng.uniform(0, nx * dx, na).astype(np.float32)
+    y = rng.uniform(0, ny * dy, na).astype(np.float32)
+    role = (rng.uniform(size=na) < 0.1).astype(np.uint8)
+    st = rng.integers(0, 3, na).astype(np.uint8)
+    dv = lambda arr: torch.tensor(arr).cuda()
+    occ = fps.sur_occupancy(dv(x), dv(y), dv(role), dv(st), nx, ny, dx, dy).cpu().numpy()
+    i, j = _cells(x, y, nx, ny, dx, dy)
+    keep = (role == 0) & (st == 0)
+    want = np.zeros((ny, nx), np.int64)
+    np.add.at(want, (j[keep], i[keep]), 1)
+    assert np.array_equal(occ, want)
+    halo, block, stride = 8, 16, 7
+    m = fps.sur_judge_mask(dv(x), dv(y), dv(st), nx, ny, dx, dy, halo, block, stride=stride).cpu().numpy()
+    wm = np.zeros(((ny + block - 1) // block, (nx + block - 1) // block), np.uint8)
+    for a in range(0, na, stride):
+        if st[a] == 1:
+            continue
+        wm[max(j[a] - halo, 0) // block:min(j[a] + halo, ny - 1) // block + 1,
+           max(i[a] - halo, 0) // block:min(i[a] + halo, nx - 1) // block + 1] = 1
+    assert np.array_equal(m, wm)
+
+
+def test_judge_region_is_exact_inside():
+    """k steps on a judge region equal k full steps (same fixed step) at cells
+    at least k cells inside the region, bit for bit."""
+    from paper_1908_05232_amd import inputs as I
+    from tests.gpu_util import random_wet_dry
+    sc = random_wet_dry(300, 170, 0.25, seed=21, bc=(0, 1, 0, 1), inflow=(2, 100, 140))
+    sc.desc.dt_max = 0.001                     # below the CFL step of this state
+    full, part = fps.Sim(sc), fps.Sim(sc)
+    full.set_graph(0)
+    part.set_graph(0)
+    block, halo, k = 16, 8, 8
+    rng = np.random.default_rng(3)
+    na = 12
+    x = rng.uniform(0, 300 * 0.25, na).astype(np.float32)
+    y = rng.uniform(0, 170 * 0.25, na).astype(np.float32)
+    st = np.zeros(na, np.uint8)
+    dv = lambda arr: torch.tensor(arr).cuda()
+    mask = fps.sur_judge_mask(dv(x), dv(y), dv(st), 300, 170, 0.25, 0.25, halo, block)
+    part.set_judge_region(mask, block)
+    for _ in range(2):                          # two blocks: stale values from the first stay outside
+        full.step(k)
+        part.step(k)
+        assert full.diag()["dt_last"] == np.float32(0.001) and part.diag()["dt_last"] == np.float32(0.001)
+        F, P = full.fields(), part.fields()
+        i, j = _cells(x, y, 300, 170, 0.25, 0.25)
+        for a, b in zip(F[:3], P[:3]):
+            assert np.array_equal(a[j, i], b[j, i])
+        # and every cell whose whole (2k+1)^2 neighbourhood lies in marked blocks
+        mb = np.kron(mask.cpu().numpy(), np.ones((block, block), np.uint8))[:170, :300].astype(bool)
+        from scipy.ndimage import binary_erosion
+        inner = binary_erosion(mb, np.ones((2 * k + 1, 2 * k + 1), bool), border_value=1)
+        for a, b in zip(F[:3], P[:3]):
+            assert np.array_equal(a[inner], b[inner])
+        say(f"judge region: {inner.sum()} inner cells of {mb.sum()} marked, identical")
+        # start the next block from the full state
+        for t_, src in zip((part.h, part.qx, part.qy), (full.h, full.qx, full.qy)):
+            t_.copy_(src)
+        part.rebind_fields()
+        part.set_time(full.diag()["t"], full.diag()["step"])
+    part.set_judge_region(None, 1)

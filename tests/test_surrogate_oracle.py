@@ -124,3 +124,32 @@ def test_judge_counts_by_hand():
     assert dmax == np.float32(0.52) - np.float32(0.5)
     same = S.judge(x, y, st, nx, ny, dx, dy, (hb, qb, qb), (hb, qb, qb), 0.01, 1e-5, thr)
     assert same == (0, 0.0)
+
+
+def test_bf16_round_ties_to_even_and_matches_library():
+    one = 1.0
+    assert S.bf16_round(one + 2.0 ** -8) == 1.0                    # tie -> even (down)
+    assert S.bf16_round(one + 3 * 2.0 ** -8) == one + 2.0 ** -6    # tie -> even (up)
+    assert S.bf16_round(one + 2.0 ** -8 + 2.0 ** -20) == one + 2.0 ** -7
+    assert S.bf16_round(-3.0) == -3.0 and S.bf16_round(0.0) == 0.0
+    import torch
+    v = np.random.default_rng(6).normal(0, 10, 10000)
+    lib = torch.tensor(v, dtype=torch.float32).bfloat16().double().numpy()
+    assert np.array_equal(S.bf16_round(v), lib)
+
+
+def test_bf16_rounding_points_change_only_rounding():
+    """The BF16 network stays within BF16 rounding of the FP64 one: output
+    relative error a few BF16 units, last-layer gradients close."""
+    rng = np.random.default_rng(8)
+    params = [(S.bf16_round(w), b) for w, b in S.init_params(8)]
+    x = np.zeros((1, 6, 7, S.CIN0))
+    x[..., :5] = S.bf16_round(rng.uniform(-1, 1, (1, 6, 7, 5)))
+    t = rng.normal(0, 0.5, (1, 6, 7, 3))
+    y0, _, _ = S.forward(params, x)
+    y1, _, _ = S.forward(params, x, bf16=True)
+    assert 0 < np.linalg.norm(y1 - y0) / np.linalg.norm(y0) < 2e-2
+    _, g0 = S.loss_and_grads(params, x, t)
+    _, g1 = S.loss_and_grads(params, x, t, bf16=True)
+    dw0, dw1 = g0[-1][0], g1[-1][0]
+    assert np.linalg.norm(dw1 - dw0) / np.linalg.norm(dw0) < 2e-2
