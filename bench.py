@@ -28,6 +28,11 @@ HBM_PEAK_GBS = 8000.0
 FV_BYTES_PER_CELL = 32   # read h, hu, hv, z (4 B each) + evacuee count (4 B); write h, hu, hv
 
 
+def log(*a):
+    """Progress on stderr (the JSON line alone goes to stdout)."""
+    print(*a, file=sys.stderr, flush=True)
+
+
 def kernel_source_hash():
     src = os.path.join(ROOT, "paper_1908_05232_amd", "csrc", "fps_flood.hip")
     return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
@@ -58,6 +63,135 @@ def cpu_baseline(sc, n_steps):
                       f"({cells * n_steps:.3g} cell-updates, {dt:.1f} s, FP64 C, one thread)"}
 
 
+def ensemble_section(args, stream):
+    """Batched ensemble: the pre-flood intervention sweep, all members stepped
+    by one set of launches per coupled step."""
+    import torch
+    from paper_1908_05232_amd import fps, inputs as I
+    scs = I.intervention_sweep(args.ens_scenarios, workers=8)
+    log(f"ensemble: {len(scs)} scenarios built")
+    cells = sum(sc.desc.nx * sc.desc.ny for sc in scs)
+    agents = sum(len(sc.agents["x"]) for sc in scs)
+    ens = fps.Ensemble(scs, stream=stream)
+    ens.autotune()
+    log("ensemble: autotuned")
+    ens.step(args.ens_warmup)
+    torch.cuda.synchronize()
+    p0 = sum(m.diag()["ped_steps"] for m in ens.members)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    ens.step(args.ens_steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    p1 = sum(m.diag()["ped_steps"] for m in ens.members)
+    kms = ens.step_profiled(20)
+    out = {"workload": f"intervention_sweep_{len(scs)} (grids 256/512/1024 at 0.25 m, barrier, responders, "
+                       f"evacuees; seed 3303)",
+           "scenarios": len(scs), "cells_per_step": cells, "agents": agents, "steps": args.ens_steps,
+           "ms_per_step": ms / args.ens_steps,
+           "cell_updates_per_s": cells * args.ens_steps / (ms * 1e-3),
+           "scenario_steps_per_s": len(scs) * args.ens_steps / (ms * 1e-3),
+           "ped_steps_per_s": (p1 - p0) / (ms * 1e-3),
+           "flood_update_ms_per_launch": kms[0],
+           "flood_update_GBs": FV_BYTES_PER_CELL * cells / (kms[0] * 1e-3) / 1e9}
+    ens.close()
+    del ens
+    torch.cuda.empty_cache()
+    return out
+
+
+def surrogate_section(args):
+    """Learned flood update: train on finite-volume trajectories of 256^2
+    random layouts, judge held-out pairs, then the surrogate-assisted
+    ensemble against the plain finite-volume ensemble on large grids."""
+    import numpy as np
+    import torch
+    from paper_1908_05232_amd import fps, surrogate as SG
+    t_all = time.perf_counter()
+    n, per = 256, 64
+    pairs = args.sur_pairs
+    n_traj = args.sur_traj // per * per
+    ds = SG.Dataset(n_traj * pairs, n)
+    t0 = time.perf_counter()
+    fixed = []
+    for b in range(n_traj // per):
+        cases = [SG.flood_case(100000 + b * per + k, n=n) for k in range(per)]
+        fixed.append(SG.generate_pairs(cases, ds, warmup=50 + 25 * (b % 8), pairs=pairs, every=24))
+        if b % 8 == 0:
+            log(f"surrogate: trajectories {(b + 1) * per}/{n_traj}")
+    t_gen = time.perf_counter() - t0
+    sur = fps.Surrogate(args.sur_batch, n, n)
+    sur.set_params(torch.tensor(SG.init_params(0)).cuda())
+    (hist, t_train) = SG.timed(SG.train, sur, ds, args.sur_train_steps, args.sur_batch, lr=1e-3,
+                               log_every=max(1, args.sur_train_steps // 10))
+    log(f"surrogate: trained, loss {hist[0][1]:.4g} -> {hist[-1][1]:.4g}")
+    flops_train = 3 * 230400 * n * n * args.sur_batch * args.sur_train_steps
+    del ds
+    torch.cuda.empty_cache()
+    # held-out pairs
+    held = [SG.flood_case(900000 + k, n=n) for k in range(per)]
+    kept = []
+    hds = SG.Dataset(per * 2, n)
+    SG.generate_pairs(held, hds, warmup=150, pairs=2, every=40, keep=kept)
+    ev = SG.evaluate(sur, held, kept)
+    log(f"surrogate: held-out {ev}")
+    del hds, kept
+    torch.cuda.empty_cache()
+    # surrogate-assisted ensemble against plain finite volume, same cases
+    rng = np.random.default_rng(5)
+    big = [SG.flood_case(500000 + k, n=args.sur_big_n, n_evac=args.sur_big_people,
+                         barrier_height=float(rng.uniform(0.2, 1.0))) for k in range(args.sur_big_s)]
+    log("surrogate: large cases built")
+    plain, _ = SG._flood_ensemble(big)
+    _, t_plain = SG.timed(plain.step, SG.K_STEPS * args.sur_blocks)
+    A = SG.AssistedEnsemble(big, sur, chunk=args.sur_chunk, stride=args.sur_stride)
+    t0 = time.perf_counter()
+    for b in range(args.sur_blocks):
+        A.block()
+        log(f"surrogate: assisted block {b + 1}/{args.sur_blocks} {A.stats}")
+    torch.cuda.synchronize()
+    t_assist = time.perf_counter() - t0
+    # agreement at every person after the run
+    worst, bad, people = 0.0, 0, 0
+    for k in range(len(big)):
+        cr = A.crowds[k].t
+        d = big[k].sc.desc
+        r = fps.judge_result(fps.sur_judge(cr["x"], cr["y"], cr["state"], d.nx, d.ny, d.dx, d.dy,
+                                           SG._state(A.E[k]), SG._state(plain[k]), tol=0.01))
+        bad += r[0]
+        worst = max(worst, r[1])
+        people += len(big[k].agents["x"])
+    # forward throughput alone (one chunk)
+    x = torch.zeros((args.sur_chunk, args.sur_big_n, args.sur_big_n, 16), dtype=torch.bfloat16, device="cuda")
+    sur_big = A.sur
+    _, t_fwd = SG.timed(sur_big.forward, x, A.y[:args.sur_chunk])
+    px = args.sur_chunk * args.sur_big_n ** 2
+    out = {
+        "training": {"workload": f"{n_traj} finite-volume trajectories of {n}x{n} random layouts, {pairs} "
+                                 f"pairs each (t -> t + {SG.K_STEPS} steps of 0.01 s)",
+                     "generate_s": t_gen, "fixed_step_fraction": float(np.mean(fixed)),
+                     "train_steps": args.sur_train_steps, "batch": args.sur_batch, "train_s": t_train,
+                     "train_TFLOPs": flops_train / t_train / 1e12, "loss_history": hist},
+        "held_out": ev,
+        "assisted_vs_fv": {
+            "workload": f"{args.sur_big_s} x {args.sur_big_n}^2 random layouts, {args.sur_big_people} people each, "
+                        f"barrier U(0.2, 1.0) m, {args.sur_blocks} blocks of {SG.K_STEPS} steps",
+            "horizon_s": args.sur_blocks * SG.K_STEPS * 0.01,
+            "fv_scenarios_per_s": args.sur_big_s / t_plain,
+            "assisted_scenarios_per_s": args.sur_big_s / t_assist,
+            "fv_s": t_plain, "assisted_s": t_assist,
+            "ratio_assisted_over_fv": t_plain / t_assist,
+            "blocks_accepted": A.stats["accepted"], "blocks_fallback": A.stats["fallback"],
+            "judge_stride": args.sur_stride, "judged_cell_fraction": A.stats["judged_fraction"],
+            "people_off_by_more_than_1cm_or_class": bad, "people": people, "max_dh_m": worst,
+            "forward_TFLOPs": 230400 * px / t_fwd / 1e12, "forward_ms_per_chunk": t_fwd * 1e3},
+        "section_s": time.perf_counter() - t_all,
+    }
+    A.E.close(); A.J.close(); plain.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -69,6 +203,23 @@ def main():
     ap.add_argument("--probe-n", type=int, default=8192,
                     help="side of the fully wet grid used for the HBM probe (0 = skip)")
     ap.add_argument("--probe-steps", type=int, default=50)
+    ap.add_argument("--no-graph", action="store_true",
+                    help="launch every kernel eagerly (profilers trace graph-replayed kernels poorly)")
+    ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--ens-scenarios", type=int, default=64)
+    ap.add_argument("--ens-steps", type=int, default=500)
+    ap.add_argument("--ens-warmup", type=int, default=50)
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--sur-traj", type=int, default=2000)
+    ap.add_argument("--sur-pairs", type=int, default=4)
+    ap.add_argument("--sur-batch", type=int, default=8)
+    ap.add_argument("--sur-train-steps", type=int, default=2000)
+    ap.add_argument("--sur-big-s", type=int, default=32)
+    ap.add_argument("--sur-big-n", type=int, default=2048)
+    ap.add_argument("--sur-big-people", type=int, default=50000)
+    ap.add_argument("--sur-blocks", type=int, default=10)
+    ap.add_argument("--sur-chunk", type=int, default=4)
+    ap.add_argument("--sur-stride", type=int, default=250)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of 1 GiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -96,6 +247,8 @@ def main():
     stream = torch.cuda.current_stream()
     sim = fps.Sim(sc, stream=stream)
     rows, _ = sim.autotune()          # flood-update tile shape for this grid
+    if args.no_graph:
+        sim.set_graph(0)
 
     sim.step(args.warmup)
     torch.cuda.synchronize()
@@ -124,6 +277,8 @@ def main():
         bsim = fps.Sim(big, stream=stream)
         del big
         brows, _ = bsim.autotune()
+        if args.no_graph:
+            bsim.set_graph(0)
         bsim.step(4)
         bk = bsim.step_profiled(args.probe_steps)
         bcells = args.probe_n * args.probe_n
@@ -162,6 +317,11 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "fv_step_kernel", "bytes_per_cell": FV_BYTES_PER_CELL},
     }
+    sim.close()
+    if not args.no_ensemble:
+        out["secondary"]["ensemble"] = ensemble_section(args, stream)
+    if not args.no_surrogate:
+        out["secondary"]["surrogate"] = surrogate_section(args)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_steps)
     print(json.dumps(out), flush=True)

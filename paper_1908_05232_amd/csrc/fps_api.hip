@@ -31,6 +31,7 @@ struct fps_sim {
     // workspace carve
     DevState* st;
     double* partials;
+    int32_t* wet;
     float *h2, *qx2, *qy2;
     int32_t* np;
     int32_t *bin_count, *bin_start, *rank, *key, *perm_u, *perm;
@@ -155,7 +156,7 @@ bool valid_desc(const fps_grid_desc* d, char* why)
 
 // Per-scenario part of the workspace (offsets from the member's base).
 struct Layout {
-    size_t st, partials, h2, qx2, qy2, np, bin_count, bin_start, rank, key, perm_u, perm, xy, slot,
+    size_t st, partials, wet, h2, qx2, qy2, np, bin_count, bin_start, rank, key, perm_u, perm, xy, slot,
         wmask, line, stats, total;
     int64_t nbins_max;
     int32_t line_cap;
@@ -176,6 +177,7 @@ Layout member_layout(const fps_grid_desc* d, int32_t max_agents)
     const size_t na = (size_t)std::max(max_agents, 0);
     L.st = take(sizeof(DevState));
     L.partials = take(sizeof(double) * 4 * (size_t)fv_tiles(d->nx, d->ny, 1));
+    L.wet = take(sizeof(int32_t) * kWetSlots * kWetStride);
     L.h2 = take(sizeof(float) * nc);
     L.qx2 = take(sizeof(float) * nc);
     L.qy2 = take(sizeof(float) * nc);
@@ -217,6 +219,7 @@ fps_sim* new_member(Engine* e, int idx, const fps_grid_desc* d, const fps_ped_pa
     s->max_agents = max_agents;
     s->st = at<DevState>(base, L.st);
     s->partials = at<double>(base, L.partials);
+    s->wet = at<int32_t>(base, L.wet);
     s->h2 = at<float>(base, L.h2);
     s->qx2 = at<float>(base, L.qx2);
     s->qy2 = at<float>(base, L.qy2);
@@ -259,6 +262,7 @@ int init_member_device(fps_sim* s)
     hipStream_t st = s->eng->stream;
     HIPCHK(s, hipMemcpyAsync(s->st, &h0, sizeof(h0), hipMemcpyHostToDevice, st));
     HIPCHK(s, launch_fill_i32(s->np, 0, (int64_t)s->G.nx * s->G.ny, st));
+    HIPCHK(s, launch_fill_i32(s->wet, 0, (int64_t)kWetSlots * kWetStride, st));
     // the second flood buffer starts as a dry state (a judge region updates
     // only part of it and reads the rest)
     for (float* f : {s->h2, s->qx2, s->qy2})
@@ -280,6 +284,7 @@ void fill_scn(const fps_sim* s, Scn& c)
     p.np = s->np;
     p.st = s->st;
     p.partials = s->partials;
+    p.wet = s->wet;
     p.nx = s->G.nx; p.ny = s->G.ny; p.H = s->H;
     p.nsx = (s->G.nx + kStrip - 1) / kStrip;
     p.ntiles = fv_tiles(s->G.nx, s->G.ny, s->H);
@@ -878,10 +883,13 @@ int fps_bind_fields(fps_sim* s, float* h, float* hu, float* hv, float* z)
 {
     if (!s) return fail(nullptr, FPS_E_INVALID, "fps_bind_fields: sim is NULL");
     if (!h || !hu || !hv || !z) return fail(s, FPS_E_INVALID, "fps_bind_fields: NULL field");
+    // the same buffers again (new contents): launch parameters and captured
+    // graphs stay valid
+    const bool same = s->fields_bound && s->h == h && s->qx == hu && s->qy == hv && s->z == z;
     s->h = h; s->qx = hu; s->qy = hv; s->z = z;
     s->fields_bound = true;
     s->numeric_fault = false;
-    mark_dirty(s);
+    if (!same) mark_dirty(s);
     int rc = write_state_i32(s, &s->st->status, 0);
     if (rc == FPS_OK) rc = write_state_i32(s, &s->st->settled, 0);
     if (rc == FPS_OK) rc = write_state_i32(s, &s->st->cur, 0);

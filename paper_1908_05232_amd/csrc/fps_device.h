@@ -4,6 +4,16 @@
 
 #include "fps_internal.h"
 
+// Pointers read from memory are generic (flat) to the compiler; a cast to
+// the global address space makes their loads and stores global_* ones, which
+// wait on the vector-memory counter only.
+#define FPS_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ FPS_GLOBAL T* gmem(T* p)
+{
+    return (FPS_GLOBAL T*)p;
+}
+
 namespace fps {
 
 // Scenario owning flattened index g: the largest s with off[s] <= g (off has

@@ -54,21 +54,35 @@ __device__ __forceinline__ float lane_from_below(float v)
 // ghost layer clamp into the grid (their values are never used).  The raw
 // load and the derived velocities are split so loads can be issued rows ahead.
 struct Src {
-    const float* __restrict__ h;
-    const float* __restrict__ qx;
-    const float* __restrict__ qy;
-    const float* __restrict__ z;
+    const FPS_GLOBAL float* __restrict__ h;
+    const FPS_GLOBAL float* __restrict__ qx;
+    const FPS_GLOBAL float* __restrict__ qy;
+    const FPS_GLOBAL float* __restrict__ z;
 };
+
+// Element idx of a grid array: a 32-bit byte offset from a wave-uniform base
+// (grids hold fewer than 2^30 cells), so the access is one global load or
+// store with the base in scalar registers and no 64-bit address arithmetic.
+template <class T>
+__device__ __forceinline__ T ld(const FPS_GLOBAL T* base, uint32_t idx)
+{
+    return *(const FPS_GLOBAL T*)((const FPS_GLOBAL char*)base + idx * (uint32_t)sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ void st_at(FPS_GLOBAL T* base, uint32_t idx, T v)
+{
+    *(FPS_GLOBAL T*)((FPS_GLOBAL char*)base + idx * (uint32_t)sizeof(T)) = v;
+}
 
 __device__ __forceinline__ Cell load_raw(const Src& src, const FvParams& p, int ii, int j)
 {
-    int jj = min(max(j, 0), p.ny - 1);
-    size_t k = (size_t)jj * p.nx + ii;
+    const int jj = min(max(j, 0), p.ny - 1);
+    const uint32_t k = (uint32_t)jj * (uint32_t)p.nx + (uint32_t)ii;
     Cell c;
-    c.h = src.h[k];
-    c.qx = src.qx[k];
-    c.qy = src.qy[k];
-    c.z = src.z[k];
+    c.h = ld(src.h, k);
+    c.qx = ld(src.qx, k);
+    c.qy = ld(src.qy, k);
+    c.z = ld(src.z, k);
     return c;
 }
 
@@ -171,20 +185,26 @@ __global__ __launch_bounds__(kFvBlock) void fv_step_kernel(Batch B)
         sc = find_scenario(B.tile_off, B.S, g);
         tile = g - B.tile_off[sc];
     }
-    const FvParams& p = B.scn[sc].fv;
+    // parameters by value: wave-uniform registers, not reloaded after the
+    // stores of the march (which the compiler cannot tell apart from them)
+    const FvParams p = B.scn[sc].fv;
     if (tile >= p.ntiles) return;
     DevState* st = p.st;
     if (!st->active || flood_skipped(st)) return;
-    const int cur = st->cur;
-    const Src src{p.h[cur], p.qx[cur], p.qy[cur], p.z};
-    float* __restrict__ ho = p.h[cur ^ 1];
-    float* __restrict__ qxo = p.qx[cur ^ 1];
-    float* __restrict__ qyo = p.qy[cur ^ 1];
-    const int32_t* __restrict__ npp = p.np;
+    // the state words are read through a generic pointer: make them wave-uniform
+    // so that the buffer selects below are scalar
+    const int cur = __builtin_amdgcn_readfirstlane(st->cur);
+    // selects, not indexing, so that the parameter copy stays in registers
+    const Src src{gmem<const float>(cur ? p.h[1] : p.h[0]), gmem<const float>(cur ? p.qx[1] : p.qx[0]),
+                  gmem<const float>(cur ? p.qy[1] : p.qy[0]), gmem(p.z)};
+    FPS_GLOBAL float* __restrict__ ho = gmem(cur ? p.h[0] : p.h[1]);
+    FPS_GLOBAL float* __restrict__ qxo = gmem(cur ? p.qx[0] : p.qx[1]);
+    FPS_GLOBAL float* __restrict__ qyo = gmem(cur ? p.qy[0] : p.qy[1]);
+    const FPS_GLOBAL int32_t* __restrict__ npp = gmem(p.np);
     double m_acc = 0.0, vout_acc = 0.0, vclip_acc = 0.0;
     float smax = 0.0f;
-    const float dt = st->dt;
-    const float inc = st->inc;
+    const float dt = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, st->dt)));
+    const float inc = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, st->inc)));
     const float lx = dt * p.inv_dx, ly = dt * p.inv_dy;
 
     {
@@ -198,7 +218,7 @@ __global__ __launch_bounds__(kFvBlock) void fv_step_kernel(Batch B)
                 for (int bx = bx0; bx <= bx1; ++bx) any |= p.jmask[by * p.jbx + bx];
             if (!any) {
                 if (lane == 0) {
-                    double* dst = &p.partials[4 * tile];
+                    FPS_GLOBAL double* dst = gmem(&p.partials[4 * tile]);
                     dst[0] = 0.0;
                     dst[1] = 0.0;
                     dst[2] = 0.0;
@@ -246,9 +266,9 @@ __global__ __launch_bounds__(kFvBlock) void fv_step_kernel(Batch B)
                 c = nb;
                 continue;
             }
-            const size_t k = (size_t)j * p.nx + i;
+            const uint32_t k = (uint32_t)j * (uint32_t)p.nx + (uint32_t)i;
             int npc = 0;
-            if (out_lane) npc = npp[k];
+            if (out_lane) npc = ld(npp, k);
             // east face with the neighbour lane's cell
             float eh = lane_from_above(c.h), eu = lane_from_above(c.u);
             float ev = lane_from_above(c.v), ez = lane_from_above(c.z);
@@ -304,13 +324,15 @@ __global__ __launch_bounds__(kFvBlock) void fv_step_kernel(Batch B)
                 }
                 m_acc += (double)hn;
                 // outflow through transmissive sides
-                if (i == 0 && p.bc[0] == FPS_BC_TRANSMISSIVE) vout_acc -= (double)Fw0 * dt * p.dy;
-                if (i == p.nx - 1 && p.bc[1] == FPS_BC_TRANSMISSIVE) vout_acc += (double)Fe0 * dt * p.dy;
-                if (j == 0 && p.bc[2] == FPS_BC_TRANSMISSIVE) vout_acc -= (double)Fs0 * dt * p.dx;
-                if (j == p.ny - 1 && p.bc[3] == FPS_BC_TRANSMISSIVE) vout_acc += (double)Fn0 * dt * p.dx;
-                ho[k] = hn;
-                qxo[k] = qxn;
-                qyo[k] = qyn;
+                if (i == 0 || i == p.nx - 1 || j == 0 || j == p.ny - 1) {    // rare: skipped by most waves
+                    if (i == 0 && p.bc[0] == FPS_BC_TRANSMISSIVE) vout_acc -= (double)Fw0 * dt * p.dy;
+                    if (i == p.nx - 1 && p.bc[1] == FPS_BC_TRANSMISSIVE) vout_acc += (double)Fe0 * dt * p.dy;
+                    if (j == 0 && p.bc[2] == FPS_BC_TRANSMISSIVE) vout_acc -= (double)Fs0 * dt * p.dx;
+                    if (j == p.ny - 1 && p.bc[3] == FPS_BC_TRANSMISSIVE) vout_acc += (double)Fn0 * dt * p.dx;
+                }
+                st_at(ho, k, hn);
+                st_at(qxo, k, qxn);
+                st_at(qyo, k, qyn);
             }
             Fs0 = Fn0;
             Fs1 = Fn1;
@@ -325,12 +347,18 @@ __global__ __launch_bounds__(kFvBlock) void fv_step_kernel(Batch B)
     vclip_acc = wave_sum(vclip_acc);
     smax = wave_max(smax);
     if (lane == 0) {
-        double* dst = &p.partials[4 * tile];
+        FPS_GLOBAL double* dst = gmem(&p.partials[4 * tile]);
         dst[0] = m_acc;
         dst[1] = vout_acc;
         dst[2] = vclip_acc;
         dst[3] = (double)smax;
-        if (smax > 0.0f) atomicOr(&st->wet_flag, 1);
+        if (smax > 0.0f) {
+            // one flag per group of blocks, set once: a device-wide flag hit by
+            // every wave serialises the atomics
+            int* f = p.wet + kWetStride * (blockIdx.x & (kWetSlots - 1));
+            if (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+                __hip_atomic_fetch_or(f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
 }
 
@@ -393,6 +421,8 @@ __global__ __launch_bounds__(kScanThreads) void finalize_kernel(Batch B, int mod
     DevState* st = p.st;
     if (mode == 0 && !st->active) return;
     const bool skipped = mode == 0 && flood_skipped(st);
+    // the pedestrians of this step have read the wetness flags: clear them
+    if (threadIdx.x < kWetSlots) p.wet[kWetStride * threadIdx.x] = 0;
     __shared__ double red[kScanThreads / kWave][4];
     double m = 0.0, vo = 0.0, vc = 0.0, sm = 0.0;
     if (!skipped) {
@@ -450,7 +480,6 @@ __global__ __launch_bounds__(kScanThreads) void finalize_kernel(Batch B, int mod
         }
         st->inc = inc;
         if (!isfinite(st->mass) || !(dtn > 0.0f) || !isfinite(dtn)) st->status = FPS_E_NUMERIC;
-        st->wet_flag = 0;
         // sandbag write-back: drops of this step applied to the barrier line in order
         const BarrierParams& Bb = S.bar;
         if (mode == 0 && S.na > 0) {
@@ -481,11 +510,12 @@ __global__ __launch_bounds__(kScanThreads) void finalize_kernel(Batch B, int mod
     }
     if (mode == 0 && S.na > 0) {
         __syncthreads();
-        block_scan_bins(S.bins);
+        const BinParams bp = S.bins;     // by value: not reloaded after the stores below
+        block_scan_bins(bp);
         if (S.inline_place) {
-            for (int a = threadIdx.x; a < S.bins.na; a += kScanThreads) place_agent(S.bins, a);
+            for (int a = threadIdx.x; a < bp.na; a += kScanThreads) place_agent(bp, a);
             __syncthreads();
-            for (int a = threadIdx.x; a < S.bins.na; a += kScanThreads) sort_agent(S.bins, a);
+            for (int a = threadIdx.x; a < bp.na; a += kScanThreads) sort_agent(bp, a);
         }
     }
 }

@@ -26,6 +26,8 @@ constexpr int kScanThreads = 1024;
 constexpr int kMaxHydro = 64;
 constexpr int kMaskBits = 128;         // obstacle bitmask per cell (uint4)
 constexpr int kInlinePlace = 8192;     // agent counts binned inside the one-block finalize
+constexpr int kWetSlots = 64;          // wetness flags of a flood update, one per group of blocks
+constexpr int kWetStride = 32;         // ints between flags (one 128-byte line each)
 
 // Scalars that live in device memory so that n steps run without the host.
 struct DevState {
@@ -47,7 +49,6 @@ struct DevState {
     int32_t flood_steps;   // steps whose flood update ran (the rest were dry and skipped)
     // sandbag barrier (sec. 2.4)
     int32_t layers_done, active_cell, bags, done, drops, drops_total;
-    int32_t wet_flag;      // set by any flood wave with a wet cell; cleared by the finalize
     int32_t settled;       // the state came out of a flood update (dry cells carry no discharge)
 };
 
@@ -59,6 +60,7 @@ struct FvParams {
     const int32_t* np;
     DevState* st;
     double* partials;      // [ntiles][4]: mass sum, outflow volume, clipped depth, max speed
+    int32_t* wet;          // [kWetSlots * kWetStride]: set by waves with a wet cell, cleared by the finalize
     int nx, ny, H, nsx, ntiles;
     int bc[4];
     int inflow_side, c0, c1, n_inflow;

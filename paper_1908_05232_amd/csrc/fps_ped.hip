@@ -108,7 +108,10 @@ __device__ void agent_step(const PedParams& p, const float* __restrict__ fh,
         cls = hr < p.hr_t[0] ? FPS_CLS_LOW
             : hr < p.hr_t[1] ? FPS_CLS_MEDIUM
             : hr < p.hr_t[2] ? FPS_CLS_HIGH : FPS_CLS_HIGHEST;
-        v0 = p.v_class[cls];
+        // constant indices keep the parameter copy in registers
+        v0 = cls == FPS_CLS_LOW ? p.v_class[FPS_CLS_LOW]
+           : cls == FPS_CLS_MEDIUM ? p.v_class[FPS_CLS_MEDIUM]
+           : cls == FPS_CLS_HIGH ? p.v_class[FPS_CLS_HIGH] : p.v_class[FPS_CLS_HIGHEST];
     }
     p.cls[a] = (uint8_t)cls;
     int st = st0;
@@ -335,11 +338,14 @@ __global__ __launch_bounds__(kPedBlock) void ped_step_kernel(Batch B)
     const float dt = st->dt;            // the step length of this step
     const int done = st->done;
     // evacuation trigger: some cell is wet after this step's flood update
-    const int wet = skipped ? 0 : st->wet_flag;
+    // one wetness flag per lane (the flood update sets them per group of blocks)
+    const int wet = skipped ? 0 : (__ballot(S.fv.wet[kWetStride * threadIdx.x] != 0) != 0ull);
     int drop = 0, act = 0;
     if (a < S.na) {
         act = S.ped.state[a] != FPS_ST_EXITED;
-        agent_step(S.ped, S.fv.h[fb], S.fv.qx[fb], S.fv.qy[fb], a, dt, wet, done, drop);
+        const PedParams P = S.ped;     // by value: not reloaded after the agent's stores
+        agent_step(P, fb ? S.fv.h[1] : S.fv.h[0], fb ? S.fv.qx[1] : S.fv.qx[0], fb ? S.fv.qy[1] : S.fv.qy[0],
+                   a, dt, wet, done, drop);
     }
     // one wave per block: wave-level counts, one atomic each
     const unsigned long long drops = __popcll(__ballot(drop));
@@ -391,7 +397,10 @@ __global__ __launch_bounds__(kPedBlock) void bin_place_all_kernel(Batch B)
     const Scn& S = B.scn[sc];
     if (S.inline_place) return;
     const int a = g0 - B.agent_off[sc] + (int)threadIdx.x;
-    if (a < S.na) place_agent(S.bins, a);
+    if (a < S.na) {
+        const BinParams b = S.bins;    // by value: not reloaded after the stores
+        place_agent(b, a);
+    }
 }
 __global__ __launch_bounds__(kPedBlock) void bin_sort_all_kernel(Batch B)
 {
@@ -401,7 +410,10 @@ __global__ __launch_bounds__(kPedBlock) void bin_sort_all_kernel(Batch B)
     const Scn& S = B.scn[sc];
     if (S.inline_place) return;
     const int a = g0 - B.agent_off[sc] + (int)threadIdx.x;
-    if (a < S.na) sort_agent(S.bins, a);
+    if (a < S.na) {
+        const BinParams b = S.bins;
+        sort_agent(b, a);
+    }
 }
 
 __global__ void count_kernel(BinParams b)

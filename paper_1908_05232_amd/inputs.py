@@ -362,3 +362,31 @@ def wet_probe(n: int = 8192, dx: float = 0.25, seed: int = 8192) -> Scenario:
     zeros = np.zeros((n, n), np.float32)
     return Scenario(desc=desc, h=h.astype(np.float32), qx=zeros, qy=zeros.copy(),
                     z=np.ascontiguousarray(z, np.float32), name=f"wet_probe_{n}")
+
+
+def _sweep_member(args):
+    seed, k = args
+    rng = rng_of(seed * 1000 + k)
+    n = int(rng.choice([256, 512, 1024]))
+    height = float(rng.choice([0.2, 0.4, 0.6, 0.8]))
+    n_resp = int(rng.integers(10, 201))
+    n_evac = int(rng.integers(500, 5001))
+    q_peak = float(rng.uniform(1.0, 3.0))
+    sc = shopping_centre(n=n, dx=0.25, seed=seed * 1000 + k, n_evac=n_evac, q_peak=q_peak)
+    sc = add_barrier(sc, seed=seed * 1000 + k, n_resp=n_resp, height=height)
+    sc.name = f"sweep_{k}_{n}_bar{height}_resp{n_resp}_evac{n_evac}"
+    return sc
+
+
+def intervention_sweep(S: int = 64, seed: int = 3303, workers: int = 8):
+    """Pre-flood intervention sweep (sec. 3.3 as a batch): S shopping centres
+    with grids drawn from {256^2, 512^2, 1024^2} at 0.25 m, sandbag barrier
+    height from {0.2, 0.4, 0.6, 0.8} m, 10-200 responders, 500-5,000
+    evacuees and hydrograph peak U(1, 3) m^2/s, each member from its own seed.
+    The host set-up (layouts and navigation fields) runs in worker processes."""
+    jobs = [(seed, k) for k in range(S)]
+    if workers <= 1:
+        return [_sweep_member(j) for j in jobs]
+    import concurrent.futures as cf
+    with cf.ProcessPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(_sweep_member, jobs))

@@ -1,0 +1,77 @@
+"""GPU checks of the surrogate workflow: the finite-volume fallback of the
+assisted ensemble reproduces the plain finite-volume ensemble bit for bit,
+an accepted block is exactly the network's update, and training on pairs
+that the finite-volume engine generates lowers the loss."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1908_05232_amd import fps, surrogate as SG
+from tests.gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+
+def _cases(seeds, n=64, **kw):
+    return [SG.flood_case(s, n=n, **kw) for s in seeds]
+
+
+def _random_surrogate(batch, n, seed=0):
+    sur = fps.Surrogate(batch, n, n)
+    g = torch.Generator().manual_seed(seed)
+    p = torch.randn(sur.n_params, generator=g) * 0.02
+    sur.set_params(p.cuda())
+    return sur
+
+
+def test_fallback_equals_plain_fv():
+    cases = _cases([31, 32, 33])
+    sur = _random_surrogate(2, 64)
+    A = SG.AssistedEnsemble(cases, sur, chunk=2, tol=-1.0)      # every block rejected
+    plain, _ = SG._flood_ensemble(cases)
+    for _ in range(3):
+        acc = A.block()
+        assert not acc.any()
+    plain.step(3 * SG.K_STEPS)
+    for k in range(len(cases)):
+        for a, b in zip(A.E[k].fields(), plain[k].fields()):
+            assert np.array_equal(a, b), k
+        assert A.E[k].diag()["t"] == plain[k].diag()["t"] == A.t[k]
+    say(f"fallback: {A.stats}")
+
+
+def test_accepted_block_is_the_network_update():
+    cases = _cases([41, 42], n=64)
+    for c in cases:                                  # no crowd: nothing to judge, every block accepted
+        c.agents = {k: v[:0] for k, v in c.agents.items()}
+    sur = _random_surrogate(2, 64, seed=3)
+    A = SG.AssistedEnsemble(cases, sur, chunk=2)
+    u0 = [tuple(t.clone() for t in SG._state(A.E[k])) for k in range(2)]
+    acc = A.block()
+    assert acc.all()
+    for k in range(2):
+        x = torch.empty((1, 64, 64, 16), dtype=torch.bfloat16, device="cuda")
+        y = torch.empty((1, 64, 64, 4), dtype=torch.float32, device="cuda")
+        fps.sur_pack(*u0[k], A.E[k].z, A.crowds[k].occ, out=x[0])
+        sur.forward(x, y)
+        fps.sur_apply(y[0], *u0[k], h_dry=cases[k].sc.desc.h_dry)
+        for a, b in zip(SG._state(A.E[k]), u0[k]):
+            assert torch.equal(a, b)
+        assert A.E[k].diag()["t"] == A.t[k] == A._acc_time(0.0)
+
+
+def test_pairs_and_training():
+    cases = _cases(range(50, 58), n=64)
+    ds = SG.Dataset(8 * 4, 64)
+    frac = SG.generate_pairs(cases, ds, warmup=40, pairs=4, every=16)
+    assert ds.size == 32 and frac == 1.0
+    t = ds.t[:, :, :, :3]
+    assert torch.isfinite(t).all() and float(t.abs().max()) > 0
+    assert float(ds.t[..., 3].abs().max()) == 0.0
+    sur = fps.Surrogate(8, 64, 64)
+    init = torch.tensor(SG.init_params(5))
+    assert init.numel() == sur.n_params
+    sur.set_params(init.cuda())
+    hist = SG.train(sur, ds, steps=200, batch=8, lr=1e-3, log_every=50)
+    say(f"training loss {hist}")
+    assert hist[-1][1] < 0.5 * hist[0][1]
