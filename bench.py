@@ -116,7 +116,10 @@ def surrogate_section(args):
     t0 = time.perf_counter()
     fixed = []
     for b in range(n_traj // per):
-        cases = [SG.flood_case(100000 + b * per + k, n=n) for k in range(per)]
+        # half the layouts carry a completed sandbag line (raised bed) as in the sweeps
+        cases = [SG.flood_case(100000 + b * per + k, n=n,
+                               barrier_height=0.2 + 0.8 * ((b * per + k) % 7) / 6 if k % 2 else None)
+                 for k in range(per)]
         fixed.append(SG.generate_pairs(cases, ds, warmup=50 + 25 * (b % 8), pairs=pairs, every=24))
         if b % 8 == 0:
             log(f"surrogate: trajectories {(b + 1) * per}/{n_traj}")
@@ -130,7 +133,7 @@ def surrogate_section(args):
     del ds
     torch.cuda.empty_cache()
     # held-out pairs
-    held = [SG.flood_case(900000 + k, n=n) for k in range(per)]
+    held = [SG.flood_case(900000 + k, n=n, barrier_height=0.5 if k % 2 else None) for k in range(per)]
     kept = []
     hds = SG.Dataset(per * 2, n)
     SG.generate_pairs(held, hds, warmup=150, pairs=2, every=40, keep=kept)
@@ -145,7 +148,7 @@ def surrogate_section(args):
     log("surrogate: large cases built")
     plain, _ = SG._flood_ensemble(big)
     _, t_plain = SG.timed(plain.step, SG.K_STEPS * args.sur_blocks)
-    A = SG.AssistedEnsemble(big, sur, chunk=args.sur_chunk, stride=args.sur_stride)
+    A = SG.AssistedEnsemble(big, sur.get_params(), chunk=args.sur_chunk, stride=args.sur_stride)
     t0 = time.perf_counter()
     for b in range(args.sur_blocks):
         A.block()

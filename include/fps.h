@@ -180,6 +180,11 @@ int fps_step(fps_sim* sim, int32_t n_steps);
    further steps leave it unchanged.  Synchronises. */
 int fps_set_end_time(fps_sim* sim, double t_end);
 
+/* Depth the inflow adds to each inflow cell over [t0, t1]: the exact
+   integral of the piecewise-linear hydrograph divided by the cell width
+   normal to the inflow side (sec. 3.1); 0 without an inflow.  Host result. */
+int fps_inflow_depth(fps_sim* sim, double t0, double t1, double* depth);
+
 /* Judge region (used to check a learned flood update against the finite-
    volume method on part of the grid): while mask is set, a flood update
    writes only the cells of waves that meet a set block of the mask, a
@@ -294,17 +299,24 @@ int fps_sur_adam(fps_sur* sur, float lr);
 /* fps_sur_gradients then fps_sur_adam. */
 int fps_sur_train_step(fps_sur* sur, int32_t n, const void* x_bf16, const float* target, float lr,
                        float* loss);
-/* Network input from a flood state (device float32 [H][W] planes; occupancy:
-   evacuee counts per cell, may be NULL) into x bf16 [H][W][16]; async. */
-int fps_sur_pack(int64_t npix, const float* h, const float* hu, const float* hv, const float* z,
-                 const int32_t* occupancy, void* x_bf16, void* stream);
+/* Network input from a flood state into x bf16 [ny][nx][16], channels h, hu,
+   hv, z / 3, occupancy / 4 and, on the cells of the inflow segment (the
+   boundary cells of side inflow_side, -1 = none, from c0 to c1 - 1), the depth
+   the inflow adds over the block (fps_inflow_depth); the rest zero.  h, hu,
+   hv, z: device float32 [ny][nx]; occupancy: evacuee counts per cell, device
+   int32 [ny][nx] or NULL.  Async. */
+int fps_sur_pack(int32_t nx, int32_t ny, const float* h, const float* hu, const float* hv, const float* z,
+                 const int32_t* occupancy, int32_t inflow_side, int32_t inflow_c0, int32_t inflow_c1,
+                 double inflow_depth, void* x_bf16, void* stream);
 /* Training target: the scaled change (U1 - U0) / scale into fp32 [H][W][4]; async. */
 int fps_sur_make_target(int64_t npix, const float* h0, const float* hu0, const float* hv0,
                         const float* h1, const float* hu1, const float* hv1, float* target, void* stream);
-/* Apply a network output to a flood state in place: U += scale * y, h >= 0,
-   no discharge where h <= h_dry; async.  (Rebind the fields of a simulation
-   afterwards so its next time step is recomputed.) */
-int fps_sur_apply(int64_t npix, const float* y, float* h, float* hu, float* hv, float h_dry, void* stream);
+/* Apply a network output to a flood state in place: U += scale * y, h >= 0;
+   a cell that was dry (h <= h_dry) stays dry unless the update puts at least
+   h_snap metres on it; no discharge where h <= h_dry.  Async.  (Rebind the
+   fields of a simulation afterwards so its next time step is recomputed.) */
+int fps_sur_apply(int64_t npix, const float* y, float* h, float* hu, float* hv, float h_dry, float h_snap,
+                  void* stream);
 /* Judge of a surrogate state (a) against a finite-volume state (b) at the
    cells of the sampled agents: every stride-th agent of the device SoA
    (x, y, state) of length na that has not exited.  out2[0] = sampled agents

@@ -6,7 +6,8 @@ never by the product path; it shares no code with the GPU kernels.
 The surrogate is not part of the paper: it is a learned shortcut that advances
 the flood state k finite-volume steps at once.  Network (channels-last, 3x3
 kernels, zero padding, stride 1): input planes (h, hu, hv, z, occupancy)
-scaled by fixed constants and padded with zeros to 16 channels -> 64 -> 64 ->
+and the depth the inflow adds over the block on the inflow cells, scaled by
+fixed constants and padded with zeros to 16 channels -> 64 -> 64 ->
 64 -> 64 -> 3, ReLU after the first four layers; the three outputs are the
 scaled change of (h, hu, hv) over the k steps.  Loss: mean squared error over
 all outputs.  Optimiser: Adam (Kingma & Ba 2015) on FP32 master weights.
@@ -30,7 +31,8 @@ CIN0 = 16                      # first layer input channels (5 used + 11 zero)
 WIDTH = 64
 LAYERS = [(CIN0, WIDTH), (WIDTH, WIDTH), (WIDTH, WIDTH), (WIDTH, WIDTH), (WIDTH, 3)]
 # fixed input / output scales: h, hu, hv, z, occupancy  ->  O(1) values
-IN_SCALE = np.array([1.0, 1.0, 1.0, 1.0 / 3.0, 0.25] + [0.0] * 11)
+IN_SCALE = np.array([1.0, 1.0, 1.0, 1.0 / 3.0, 0.25, 1.0] + [0.0] * 10)
+N_IN = 6                       # used input channels: h, hu, hv, z, occupancy, inflow depth
 OUT_SCALE = np.array([0.05, 0.05, 0.05])     # scaled change of (h, hu, hv) over k steps
 
 
@@ -52,7 +54,7 @@ def init_params(seed: int = 0):
         std = np.sqrt(2.0 / (9 * cin))
         w = rng.normal(0.0, std, size=(cout, 3, 3, cin))
         if cin == CIN0:
-            w[..., 5:] = 0.0
+            w[..., N_IN:] = 0.0
         params.append((w, np.zeros(cout)))
     return params
 
@@ -128,11 +130,24 @@ def adam_update(param, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     return param - lr * mhat / (np.sqrt(vhat) + eps), m, v
 
 
-def pack_input(h, hu, hv, z, occ):
-    """Scaled channels-last input [H, W, 16] from the state planes."""
+def pack_input(h, hu, hv, z, occ, inflow=None):
+    """Scaled channels-last input [H, W, 16] from the state planes.  inflow:
+    (side, c0, c1, depth) puts the block's inflow depth on the boundary cells
+    of the inflow segment (sides W, E, S, N = 0, 1, 2, 3)."""
     x = np.zeros(h.shape + (CIN0,))
     for c, plane in enumerate((h, hu, hv, z, occ)):
         x[..., c] = plane * IN_SCALE[c]
+    if inflow is not None and inflow[0] >= 0:
+        side, c0, c1, depth = inflow
+        ny, nx = h.shape
+        if side == 2:
+            x[0, c0:c1, 5] = depth * IN_SCALE[5]
+        elif side == 3:
+            x[ny - 1, c0:c1, 5] = depth * IN_SCALE[5]
+        elif side == 0:
+            x[c0:c1, 0, 5] = depth * IN_SCALE[5]
+        else:
+            x[c0:c1, nx - 1, 5] = depth * IN_SCALE[5]
     return x
 
 
@@ -143,10 +158,12 @@ def make_target(h0, hu0, hv0, h1, hu1, hv1):
                      (hv1 - hv0) / OUT_SCALE[2]], axis=-1)
 
 
-def apply_output(h, hu, hv, y, h_dry=1e-5):
-    """State after the surrogate call: U + OUT_SCALE * y, depth kept >= 0 and
+def apply_output(h, hu, hv, y, h_dry=1e-5, h_snap=1e-3):
+    """State after the surrogate call: U + OUT_SCALE * y, depth kept >= 0; a
+    cell that was dry stays dry unless the update puts at least h_snap on it;
     no discharge in cells left dry (h <= h_dry), as in the flood update."""
     hn = np.maximum(h + OUT_SCALE[0] * y[..., 0], 0.0)
+    hn = np.where((h <= h_dry) & (hn < h_snap), 0.0, hn)
     wet = hn > h_dry
     qx = np.where(wet, hu + OUT_SCALE[1] * y[..., 1], 0.0)
     qy = np.where(wet, hv + OUT_SCALE[2] * y[..., 2], 0.0)

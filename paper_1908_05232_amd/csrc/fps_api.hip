@@ -46,6 +46,8 @@ struct fps_sim {
     int n_inflow;
     bool use_wmask;
     double t_end;
+    double hyd_t[kMaxHydro], hyd_q[kMaxHydro];   // host copy of the hydrograph
+    int hyd_n;
     const uint8_t* jmask;  // judge region (NULL: whole grid, CFL time step)
     int jb;
     // bound caller memory
@@ -78,6 +80,7 @@ struct Engine {
     std::vector<int> tile_off_h, agent_off_h;
     int total_tiles = 0, total_agents = 0, fv_blocks = 0;
     int64_t max_cells = 0;
+    int fin_lds_bytes = 0;
     bool any_big = false;
     bool dirty = true;
     int graph_chunk = 16;
@@ -249,6 +252,7 @@ fps_sim* new_member(Engine* e, int idx, const fps_grid_desc* d, const fps_ped_pa
     s->t_end = 0.0;
     s->jmask = nullptr;
     s->jb = 0;
+    s->hyd_n = 0;
     return s;
 }
 
@@ -339,6 +343,7 @@ void fill_scn(const fps_sim* s, Scn& c)
 
     c.na = s->na;
     c.inline_place = s->na <= kInlinePlace;
+    c.lds_bins = c.inline_place && s->na > 0 && (int64_t)s->nbins + 1 + s->na <= kLdsBinWords;
 }
 
 void drop_graph(Engine* e)
@@ -357,6 +362,7 @@ int upload(Engine* e)
     e->scn_h.resize(e->S);
     e->max_cells = 0;
     e->any_big = false;
+    e->fin_lds_bytes = 0;
     for (int k = 0; k < e->S; ++k) {
         fps_sim* s = e->m[k];
         fill_scn(s, e->scn_h[k]);
@@ -364,7 +370,10 @@ int upload(Engine* e)
         e->agent_off_h[k + 1] = e->agent_off_h[k] + (s->na + kPedBlock - 1) / kPedBlock * kPedBlock;
         e->max_cells = std::max(e->max_cells, (int64_t)s->G.nx * s->G.ny);
         e->any_big = e->any_big || s->na > kInlinePlace;
+        if (e->scn_h[k].lds_bins)
+            e->fin_lds_bytes = std::max(e->fin_lds_bytes, (int)(sizeof(int) * (s->nbins + 1 + s->na)));
     }
+    HIPCHK_E(e, prepare_finalize(e->fin_lds_bytes));
     e->total_tiles = e->tile_off_h[e->S];
     e->total_agents = e->agent_off_h[e->S];
     e->fv_blocks = fv_blocks_for_tiles(e->total_tiles);
@@ -389,6 +398,7 @@ Batch batch_of(const Engine* e, int s_only = -1)
     b.total_tiles = e->total_tiles;
     b.total_agents = e->total_agents;
     b.fv_blocks = e->fv_blocks;
+    b.fin_lds_bytes = e->fin_lds_bytes;
     b.s_only = s_only;
     if (s_only >= 0) b.fv_blocks = fv_blocks_for_tiles(e->scn_h[s_only].fv.ntiles);
     return b;
@@ -912,6 +922,11 @@ int fps_set_hydrograph(fps_sim* s, const double* t, const double* q, int32_t npt
         tt[k] = t[k];
         qq[k] = q[k];
     }
+    for (int k = 0; k < kMaxHydro; ++k) {
+        s->hyd_t[k] = tt[k];
+        s->hyd_q[k] = qq[k];
+    }
+    s->hyd_n = npts;
     hipStream_t st = s->eng->stream;
     HIPCHK(s, hipMemcpyAsync(s->st->hyd_t, tt, sizeof(tt), hipMemcpyHostToDevice, st));
     HIPCHK(s, hipMemcpyAsync(s->st->hyd_q, qq, sizeof(qq), hipMemcpyHostToDevice, st));
@@ -1008,6 +1023,46 @@ int fps_set_time(fps_sim* s, double t, int64_t step)
     int rc = write_state_i32(s, &s->st->active, !(s->t_end > 0.0) || t < s->t_end);
     if (rc != FPS_OK) return rc;
     return prime(s);
+}
+
+namespace {
+// unit discharge of the hydrograph at time t: piecewise linear between the
+// breakpoints, the end values held outside them (as the flood update does)
+double host_hydro_q(const fps_sim* s, double t)
+{
+    const int n = s->hyd_n;
+    if (n <= 0) return 0.0;
+    if (t <= s->hyd_t[0]) return s->hyd_q[0];
+    if (t >= s->hyd_t[n - 1]) return s->hyd_q[n - 1];
+    for (int k = 0; k + 1 < n; ++k)
+        if (t >= s->hyd_t[k] && t <= s->hyd_t[k + 1]) {
+            const double w = (t - s->hyd_t[k]) / (s->hyd_t[k + 1] - s->hyd_t[k]);
+            return s->hyd_q[k] + w * (s->hyd_q[k + 1] - s->hyd_q[k]);
+        }
+    return s->hyd_q[n - 1];
+}
+}  // namespace
+
+int fps_inflow_depth(fps_sim* s, double t0, double t1, double* depth)
+{
+    if (!s || !depth) return fail(s, FPS_E_INVALID, "fps_inflow_depth: NULL argument");
+    if (!std::isfinite(t0) || !std::isfinite(t1) || t1 < t0)
+        return fail(s, FPS_E_INVALID, "fps_inflow_depth: need finite t0 <= t1");
+    *depth = 0.0;
+    if (s->G.inflow_side < 0 || s->hyd_n <= 0) return FPS_OK;
+    // exact integral of the piecewise-linear discharge over [t0, t1]
+    double total = 0.0, lo = t0;
+    for (int k = 0; k < s->hyd_n; ++k) {
+        const double tk = s->hyd_t[k];
+        if (tk > lo && tk < t1) {
+            total += 0.5 * (host_hydro_q(s, lo) + host_hydro_q(s, tk)) * (tk - lo);
+            lo = tk;
+        }
+    }
+    total += 0.5 * (host_hydro_q(s, lo) + host_hydro_q(s, t1)) * (t1 - lo);
+    const double dn = s->G.inflow_side <= FPS_SIDE_E ? s->G.dx : s->G.dy;
+    *depth = total / dn;
+    return FPS_OK;
 }
 
 int fps_set_judge_region(fps_sim* s, const uint8_t* mask, int32_t block)

@@ -73,7 +73,7 @@ __device__ inline double hydro_integral(const DevState* st, double a, double b)
 // 16 * kScanThreads counts, sixteen consecutive counts per lane (four 16-byte
 // loads), a wave scan by shuffles and a scan of the wave totals; the histogram
 // is cleared behind the scan for the next step.
-__device__ inline void block_scan_bins(const BinParams& b)
+__device__ inline void block_scan_bins(const BinParams& b, int* lds_starts = nullptr)
 {
     constexpr int IPT = 16;
     __shared__ int wtot[kScanThreads / kWave];
@@ -127,10 +127,14 @@ __device__ inline void block_scan_bins(const BinParams& b)
                 w.z = run; run += v[4 * q + 2];
                 w.w = run; run += v[4 * q + 3];
                 *reinterpret_cast<int4*>(b.bin_start + k0 + 4 * q) = w;
+                if (lds_starts) *reinterpret_cast<int4*>(lds_starts + k0 + 4 * q) = w;
             }
         } else {
             for (int e = 0; e < IPT; ++e) {
-                if (k0 + e < b.nbins) b.bin_start[k0 + e] = run;
+                if (k0 + e < b.nbins) {
+                    b.bin_start[k0 + e] = run;
+                    if (lds_starts) lds_starts[k0 + e] = run;
+                }
                 run += v[e];
             }
         }
@@ -138,7 +142,10 @@ __device__ inline void block_scan_bins(const BinParams& b)
         if (threadIdx.x == 0) carry_s += total;
         __syncthreads();
     }
-    if (threadIdx.x == 0) b.bin_start[b.nbins] = carry_s;
+    if (threadIdx.x == 0) {
+        b.bin_start[b.nbins] = carry_s;
+        if (lds_starts) lds_starts[b.nbins] = carry_s;
+    }
     __syncthreads();
 }
 
@@ -161,6 +168,49 @@ __device__ inline void sort_agent(const BinParams& b, int a)
     b.perm[f] = a;
     b.slot[a] = f;
     b.xy[f] = make_float2(b.x[a], b.y[a]);
+}
+
+// One-block binning with the bin starts and the unordered placement in LDS
+// (dynamic shared memory of nbins + 1 + na words, the starts 16-byte
+// aligned): the agents' keys, ranks and positions are loaded while the
+// histogram is scanned, then the placement and the stable order run in LDS
+// and only the results are stored.  Same results as the global version above.
+__device__ inline void bin_place_lds(const BinParams& b)
+{
+    extern __shared__ int4 fin_lds4[];
+    int* lb = reinterpret_cast<int*>(fin_lds4);    // [nbins + 1]: bin starts
+    int* lp = lb + b.nbins + 1;                    // [na]: agents by bin, unordered
+    constexpr int APT = kInlinePlace / kScanThreads;
+    int key[APT], rank[APT];
+    float ax[APT], ay[APT];
+#pragma unroll
+    for (int q = 0; q < APT; ++q) {
+        const int a = threadIdx.x + q * kScanThreads;
+        key[q] = -1;
+        if (a < b.na) {
+            key[q] = b.key[a];
+            rank[q] = b.rank[a];
+            ax[q] = b.x[a];
+            ay[q] = b.y[a];
+        }
+    }
+    block_scan_bins(b, lb);
+#pragma unroll
+    for (int q = 0; q < APT; ++q)
+        if (key[q] >= 0) lp[lb[key[q]] + rank[q]] = threadIdx.x + q * kScanThreads;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < APT; ++q) {
+        if (key[q] < 0) continue;
+        const int a = threadIdx.x + q * kScanThreads;
+        const int s0 = lb[key[q]], s1 = lb[key[q] + 1];
+        int below = 0;
+        for (int s = s0; s < s1; ++s) below += lp[s] < a;
+        const int f = s0 + below;
+        b.perm[f] = a;
+        b.slot[a] = f;
+        b.xy[f] = make_float2(ax[q], ay[q]);
+    }
 }
 
 }  // namespace fps

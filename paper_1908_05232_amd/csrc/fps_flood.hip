@@ -238,20 +238,21 @@ __global__ __launch_bounds__(kFvBlock) void fv_step_kernel(Batch B)
         if (p.inflow_side == FPS_SIDE_S || p.inflow_side == FPS_SIDE_N)
             inflow_col = i >= p.c0 && i < p.c1;
 
-        // Row j0-1 now, rows j0 .. j0+2 in flight.  The first pass of the loop
+        // Row j0-1 now, rows j0 .. j0+2 in flight (rows past j1 are never needed).  The first pass of the loop
         // (j = j0-1) only forms the face below row j0, so every y face goes
         // through the same code (same rounding) whatever the tile height.
         Cell c = load_raw(src, p, ii, j0 - 1);
         Cell pf0 = load_raw(src, p, ii, j0);
-        Cell pf1 = load_raw(src, p, ii, j0 + 1);
-        Cell pf2 = load_raw(src, p, ii, j0 + 2);
+        Cell pf1 = {}, pf2 = {};
+        if (j0 + 1 <= j1) pf1 = load_raw(src, p, ii, j0 + 1);
+        if (j0 + 2 <= j1) pf2 = load_raw(src, p, ii, j0 + 2);
         derive(p, c, mirror_x, j0 - 1);
         float Fs0 = 0.0f, Fs1 = 0.0f, Fs2 = 0.0f, pS = 0.0f;
         for (int j = j0 - 1; j < j1; ++j) {
             Cell nb = pf0;
             pf0 = pf1;
             pf1 = pf2;
-            pf2 = load_raw(src, p, ii, j + 4);
+            if (j + 4 <= j1) pf2 = load_raw(src, p, ii, j + 4);   // rows above the tile's last need stay unread
             derive(p, nb, mirror_x, j + 1);
             // north face (y normal: pass v as normal, u as tangential)
             float Fn0, Fn1, Fn2, pN, pS_next;
@@ -418,8 +419,18 @@ __global__ __launch_bounds__(kScanThreads) void finalize_kernel(Batch B, int mod
     const int sc = s_first + blockIdx.x;
     const Scn& S = B.scn[sc];
     const FvParams& p = S.fv;
-    DevState* st = p.st;
-    if (mode == 0 && !st->active) return;
+    DevState* gst = p.st;
+    if (mode == 0 && !gst->active) return;
+    // The scenario's state words go through LDS: one cooperative load, the
+    // serial end-of-step logic on the copy, one cooperative store.  (Nothing
+    // else touches them while this kernel runs.)
+    __shared__ DevState sst;
+    constexpr int kWords = (int)(sizeof(DevState) / sizeof(uint32_t));
+    static_assert(sizeof(DevState) % sizeof(uint32_t) == 0, "DevState is copied as words");
+    for (int w = threadIdx.x; w < kWords; w += kScanThreads)
+        reinterpret_cast<uint32_t*>(&sst)[w] = reinterpret_cast<const uint32_t*>(gst)[w];
+    __syncthreads();
+    DevState* st = &sst;
     const bool skipped = mode == 0 && flood_skipped(st);
     // the pedestrians of this step have read the wetness flags: clear them
     if (threadIdx.x < kWetSlots) p.wet[kWetStride * threadIdx.x] = 0;
@@ -508,14 +519,20 @@ __global__ __launch_bounds__(kScanThreads) void finalize_kernel(Batch B, int mod
         }
         if (mode == 0) st->active = !(st->t_end > 0.0) || st->t < st->t_end;
     }
+    __syncthreads();
+    for (int w = threadIdx.x; w < kWords; w += kScanThreads)
+        reinterpret_cast<uint32_t*>(gst)[w] = reinterpret_cast<const uint32_t*>(&sst)[w];
     if (mode == 0 && S.na > 0) {
-        __syncthreads();
         const BinParams bp = S.bins;     // by value: not reloaded after the stores below
-        block_scan_bins(bp);
-        if (S.inline_place) {
-            for (int a = threadIdx.x; a < bp.na; a += kScanThreads) place_agent(bp, a);
-            __syncthreads();
-            for (int a = threadIdx.x; a < bp.na; a += kScanThreads) sort_agent(bp, a);
+        if (S.lds_bins) {
+            bin_place_lds(bp);
+        } else {
+            block_scan_bins(bp);
+            if (S.inline_place) {
+                for (int a = threadIdx.x; a < bp.na; a += kScanThreads) place_agent(bp, a);
+                __syncthreads();
+                for (int a = threadIdx.x; a < bp.na; a += kScanThreads) sort_agent(bp, a);
+            }
         }
     }
 }
@@ -576,9 +593,20 @@ hipError_t launch_fv_scan(const Batch& b, int scenario, int ntiles, hipStream_t 
     return hipGetLastError();
 }
 
+hipError_t prepare_finalize(int lds_bytes)
+{
+    static int granted = 0;     // the attribute is per kernel: raise it once to the largest size
+    if (lds_bytes <= granted) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute((const void*)finalize_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       lds_bytes);
+    if (e == hipSuccess) granted = lds_bytes;
+    return e;
+}
+
 hipError_t launch_finalize(const Batch& b, int mode, int s_first, int count, hipStream_t s)
 {
-    hipLaunchKernelGGL(finalize_kernel, dim3(count), dim3(kScanThreads), 0, s, b, mode, s_first);
+    const int lds = mode == 0 ? b.fin_lds_bytes : 0;
+    hipLaunchKernelGGL(finalize_kernel, dim3(count), dim3(kScanThreads), lds, s, b, mode, s_first);
     return hipGetLastError();
 }
 

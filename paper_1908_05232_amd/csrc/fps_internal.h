@@ -26,6 +26,7 @@ constexpr int kScanThreads = 1024;
 constexpr int kMaxHydro = 64;
 constexpr int kMaskBits = 128;         // obstacle bitmask per cell (uint4)
 constexpr int kInlinePlace = 8192;     // agent counts binned inside the one-block finalize
+constexpr int kLdsBinWords = 30 * 1024;  // LDS words for bin starts + placement in the finalize
 constexpr int kWetSlots = 64;          // wetness flags of a flood update, one per group of blocks
 constexpr int kWetStride = 32;         // ints between flags (one 128-byte line each)
 
@@ -138,6 +139,7 @@ struct Scn {
     BarrierParams bar;
     int na;
     int inline_place;      // agents placed in their bins inside the finalize block
+    int lds_bins;          // ... with the bin starts and the placement in LDS (small grids)
 };
 
 // Flattened launch description of an ensemble (device arrays).
@@ -148,6 +150,7 @@ struct Batch {
     int S;
     int total_tiles, total_agents;
     int fv_blocks;         // launched flood blocks: a multiple of 8 covering total_tiles
+    int fin_lds_bytes;     // dynamic LDS of the finalize launch (LDS binning)
     int s_only;            // >= 0: restrict the flood launch to one scenario (tuning)
 };
 
@@ -158,6 +161,7 @@ int fv_rows_per_wave(int nx, int ny);
 hipError_t launch_fv(const Batch& b, hipStream_t s);
 hipError_t launch_fv_scan(const Batch& b, int scenario, int ntiles, hipStream_t s);
 hipError_t launch_finalize(const Batch& b, int mode, int s_first, int count, hipStream_t s);
+hipError_t prepare_finalize(int lds_bytes);   // host, outside any capture: allow that much dynamic LDS
 hipError_t launch_sync_back(const Batch& b, int64_t max_cells, hipStream_t s);
 hipError_t launch_ped(const Batch& b, hipStream_t s);
 hipError_t launch_bin_place_all(const Batch& b, hipStream_t s);

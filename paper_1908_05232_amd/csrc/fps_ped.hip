@@ -202,15 +202,23 @@ __device__ void agent_step(const PedParams& p, const float* __restrict__ fh,
         float fx = 0.0f, fy = 0.0f;
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
-            for (int s = seg0[r]; s < seg1[r]; ++s) {
-                if (s == self) continue;
-                float2 o = p.xy[s];
-                float rx = x - o.x, ry = y - o.y;
-                float d = __builtin_amdgcn_sqrtf(rx * rx + ry * ry);
-                if (!(d > 0.0f) || !(d < p.r_cut)) continue;
-                float w = p.a_over_m * __expf((p.two_r - d) * p.inv_b) * rcp(d);
-                fx += w * rx;
-                fy += w * ry;
+            // positions read four at a time (independent loads), summed in order
+            for (int s0 = seg0[r]; s0 < seg1[r]; s0 += 4) {
+                float2 o4[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    o4[u] = s0 + u < seg1[r] ? p.xy[s0 + u] : make_float2(0.0f, 0.0f);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int s = s0 + u;
+                    if (s >= seg1[r] || s == self) continue;
+                    float rx = x - o4[u].x, ry = y - o4[u].y;
+                    float d = __builtin_amdgcn_sqrtf(rx * rx + ry * ry);
+                    if (!(d > 0.0f) || !(d < p.r_cut)) continue;
+                    float w = p.a_over_m * __expf((p.two_r - d) * p.inv_b) * rcp(d);
+                    fx += w * rx;
+                    fy += w * ry;
+                }
             }
         }
         // obstacle cells within r_cut, in row-major offset order
@@ -265,24 +273,35 @@ __device__ void agent_step(const PedParams& p, const float* __restrict__ fh,
                 vy = 0.0f;
             }
         }
-        // move, rejecting an axis that lands in an obstacle or outside
+        // move, rejecting an axis that lands in an obstacle or outside.  The
+        // cells the outcome can depend on are read together (one round of
+        // loads instead of three dependent ones), then selected.
         xn = x + dt * vx;
-        ni = cell_of(xn, p.dx, p.nx);
+        const int ni_try = cell_of(xn, p.dx, p.nx);
         const int ny_try = cell_of(y + dt * vy, p.dy, p.ny);
-        const bool okx = ni >= 0 && ni < p.nx && p.walk[(size_t)cj * p.nx + ni];
+        const bool in_x = ni_try >= 0 && ni_try < p.nx, in_y = ny_try >= 0 && ny_try < p.ny;
+        const size_t ix = (size_t)clampi(ni_try, 0, p.nx - 1), iy = (size_t)clampi(ny_try, 0, p.ny - 1);
+        const size_t nxs = (size_t)p.nx;
+        const uint8_t w_x = p.walk[(size_t)cj * nxs + ix];      // (ni_try, cj)
+        const uint8_t w_xy = p.walk[iy * nxs + ix];             // (ni_try, ny_try)
+        const uint8_t w_y = p.walk[iy * nxs + ci];              // (ci, ny_try)
+        const float d_xy = D[iy * nxs + ix], d_x = D[(size_t)cj * nxs + ix];
+        const float d_y = D[iy * nxs + ci], d_0 = D[(size_t)cj * nxs + ci];
+        const bool okx = in_x && w_x;
+        ni = okx ? ni_try : ci;
         if (!okx) {
             xn = x;
             vx = 0.0f;
-            ni = ci;
         }
         yn = y + dt * vy;
-        nj = ny_try;
-        if (nj < 0 || nj >= p.ny || !p.walk[(size_t)nj * p.nx + ni]) {
+        const bool oky = in_y && (okx ? w_xy : w_y);
+        nj = oky ? ny_try : cj;
+        if (!oky) {
             yn = y;
             vy = 0.0f;
-            nj = cj;
         }
-        if (D[(size_t)nj * p.nx + ni] <= p.r_arrive) {
+        const float d_new = okx ? (oky ? d_xy : d_x) : (oky ? d_y : d_0);
+        if (d_new <= p.r_arrive) {
             if (st == FPS_ST_EVAC) {
                 st = FPS_ST_EXITED;
             } else if (st == FPS_ST_TO_STORAGE) {

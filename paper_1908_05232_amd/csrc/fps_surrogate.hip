@@ -341,21 +341,32 @@ __global__ void prep_weights_kernel(const float* __restrict__ w, int cin, int co
     }
 }
 
-// input scales (h, hu, hv, z, occupancy) and output scales (change of h, hu, hv)
-__constant__ float kInScale[5] = {1.0f, 1.0f, 1.0f, 1.0f / 3.0f, 0.25f};
+// input scales (h, hu, hv, z, occupancy, inflow depth) and output scales
+// (change of h, hu, hv)
+__constant__ float kInScale[6] = {1.0f, 1.0f, 1.0f, 1.0f / 3.0f, 0.25f, 1.0f};
 __constant__ float kOutScale[3] = {0.05f, 0.05f, 0.05f};
 
-__global__ void pack_kernel(int64_t npix, const float* __restrict__ h, const float* __restrict__ hu,
-                            const float* __restrict__ hv, const float* __restrict__ z,
-                            const int32_t* __restrict__ occ, bf16* __restrict__ x)
+// Network input of one state: channels h, hu, hv, z, occupancy and the depth
+// the inflow adds over the block (on the cells of the inflow segment only).
+__global__ void pack_kernel(int64_t npix, int nx, int ny, const float* __restrict__ h,
+                            const float* __restrict__ hu, const float* __restrict__ hv,
+                            const float* __restrict__ z, const int32_t* __restrict__ occ, int inflow_side,
+                            int c0, int c1, float inflow_depth, bf16* __restrict__ x)
 {
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(p % nx), j = (int)(p / nx);
+        bool in = false;
+        if (inflow_side == FPS_SIDE_S) in = j == 0 && i >= c0 && i < c1;
+        else if (inflow_side == FPS_SIDE_N) in = j == ny - 1 && i >= c0 && i < c1;
+        else if (inflow_side == FPS_SIDE_W) in = i == 0 && j >= c0 && j < c1;
+        else if (inflow_side == FPS_SIDE_E) in = i == nx - 1 && j >= c0 && j < c1;
         bf16x8 a = {}, b = {};
         a[0] = to_bf16(h[p] * kInScale[0]);
         a[1] = to_bf16(hu[p] * kInScale[1]);
         a[2] = to_bf16(hv[p] * kInScale[2]);
         a[3] = to_bf16(z[p] * kInScale[3]);
         a[4] = to_bf16(occ ? (float)occ[p] * kInScale[4] : 0.0f);
+        a[5] = to_bf16(in ? inflow_depth * kInScale[5] : 0.0f);
         *reinterpret_cast<bf16x8*>(x + p * 16) = a;
         *reinterpret_cast<bf16x8*>(x + p * 16 + 8) = b;
     }
@@ -374,12 +385,15 @@ __global__ void target_kernel(int64_t npix, const float* __restrict__ h0, const 
     }
 }
 
-// U += scale * y; depth kept >= 0; no discharge where dry
+// U += scale * y; depth kept >= 0; a cell that was dry stays dry unless the
+// network puts at least h_snap of water on it; no discharge where dry
 __global__ void apply_kernel(int64_t npix, const float* __restrict__ y, float* __restrict__ h,
-                             float* __restrict__ hu, float* __restrict__ hv, float h_dry)
+                             float* __restrict__ hu, float* __restrict__ hv, float h_dry, float h_snap)
 {
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += (int64_t)gridDim.x * blockDim.x) {
-        float hn = fmaxf(h[p] + kOutScale[0] * y[p * 4 + 0], 0.0f);
+        const float h0 = h[p];
+        float hn = fmaxf(h0 + kOutScale[0] * y[p * 4 + 0], 0.0f);
+        if (!(h0 > h_dry) && hn < h_snap) hn = 0.0f;
         float qx = hu[p] + kOutScale[1] * y[p * 4 + 1];
         float qy = hv[p] + kOutScale[2] * y[p * 4 + 2];
         if (!(hn > h_dry)) {
@@ -776,12 +790,17 @@ int fps_sur_train_step(fps_sur* s, int32_t n, const void* x, const float* target
     return fps_sur_adam(s, lr);
 }
 
-int fps_sur_pack(int64_t npix, const float* h, const float* hu, const float* hv, const float* z,
-                 const int32_t* occupancy, void* x, void* stream)
+int fps_sur_pack(int32_t nx, int32_t ny, const float* h, const float* hu, const float* hv, const float* z,
+                 const int32_t* occupancy, int32_t inflow_side, int32_t inflow_c0, int32_t inflow_c1,
+                 double inflow_depth, void* x, void* stream)
 {
-    if (npix < 1 || !h || !hu || !hv || !z || !x) return sfail(nullptr, FPS_E_INVALID, "fps_sur_pack: bad argument");
-    hipLaunchKernelGGL(pack_kernel, dim3(2048), dim3(256), 0, static_cast<hipStream_t>(stream), npix, h, hu, hv, z,
-                       occupancy, static_cast<bf16*>(x));
+    if (nx < 1 || ny < 1 || !h || !hu || !hv || !z || !x || inflow_side < -1 || inflow_side > FPS_SIDE_N ||
+        !std::isfinite(inflow_depth))
+        return sfail(nullptr, FPS_E_INVALID, "fps_sur_pack: bad argument");
+    const int64_t npix = (int64_t)nx * ny;
+    hipLaunchKernelGGL(pack_kernel, dim3((unsigned)std::min<int64_t>((npix + 255) / 256, 4096)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), npix, nx, ny, h, hu, hv, z, occupancy, inflow_side,
+                       inflow_c0, inflow_c1, (float)inflow_depth, static_cast<bf16*>(x));
     SCHK(nullptr, hipGetLastError());
     return FPS_OK;
 }
@@ -797,11 +816,13 @@ int fps_sur_make_target(int64_t npix, const float* h0, const float* hu0, const f
     return FPS_OK;
 }
 
-int fps_sur_apply(int64_t npix, const float* y, float* h, float* hu, float* hv, float h_dry, void* stream)
+int fps_sur_apply(int64_t npix, const float* y, float* h, float* hu, float* hv, float h_dry, float h_snap,
+                  void* stream)
 {
-    if (npix < 1 || !y || !h || !hu || !hv) return sfail(nullptr, FPS_E_INVALID, "fps_sur_apply: bad argument");
-    hipLaunchKernelGGL(apply_kernel, dim3(2048), dim3(256), 0, static_cast<hipStream_t>(stream), npix, y, h, hu, hv,
-                       h_dry);
+    if (npix < 1 || !y || !h || !hu || !hv || !(h_snap >= 0.0f))
+        return sfail(nullptr, FPS_E_INVALID, "fps_sur_apply: bad argument");
+    hipLaunchKernelGGL(apply_kernel, dim3((unsigned)std::min<int64_t>((npix + 255) / 256, 4096)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), npix, y, h, hu, hv, h_dry, h_snap);
     SCHK(nullptr, hipGetLastError());
     return FPS_OK;
 }

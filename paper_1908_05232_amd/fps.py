@@ -96,10 +96,12 @@ EXPORTS = {
     "fps_sur_adam": (C.c_int, [_vp, C.c_float]),
     "fps_sur_train_step": (C.c_int, [_vp, C.c_int32, _vp, _vp, C.c_float, _vp]),
     "fps_set_judge_region": (C.c_int, [_vp, _vp, C.c_int32]),
+    "fps_inflow_depth": (C.c_int, [_vp, C.c_double, C.c_double, C.POINTER(C.c_double)]),
     "fps_set_occupancy": (C.c_int, [_vp, _vp]),
-    "fps_sur_pack": (C.c_int, [C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "fps_sur_pack": (C.c_int, [C.c_int32, C.c_int32, _vp, _vp, _vp, _vp, _vp, C.c_int32, C.c_int32, C.c_int32,
+                               C.c_double, _vp, _vp]),
     "fps_sur_make_target": (C.c_int, [C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
-    "fps_sur_apply": (C.c_int, [C.c_int64, _vp, _vp, _vp, _vp, C.c_float, _vp]),
+    "fps_sur_apply": (C.c_int, [C.c_int64, _vp, _vp, _vp, _vp, C.c_float, C.c_float, _vp]),
     "fps_sur_judge": (C.c_int, [C.c_int32, C.c_int32, _vp, _vp, _vp, C.c_int32, C.c_int32, C.c_double,
                                 C.c_double, _vp, _vp, _vp, _vp, _vp, _vp, C.c_double, C.c_double,
                                 C.POINTER(C.c_double), _vp, _vp]),
@@ -227,6 +229,17 @@ class Member:
     def rebind_fields(self):
         return self._check(self._lib.fps_bind_fields(self.h_, _ptr(self.h), _ptr(self.qx), _ptr(self.qy),
                                                      _ptr(self.z)))
+
+    def inflow_depth(self, t0, t1):
+        """Depth the inflow adds to each inflow cell over [t0, t1] (host float)."""
+        d = C.c_double()
+        self._check(self._lib.fps_inflow_depth(self.h_, float(t0), float(t1), C.byref(d)))
+        return d.value
+
+    def inflow_feature(self, t0, t1):
+        """(side, c0, c1, depth) for sur_pack."""
+        g = self.sc.desc
+        return (g.inflow_side, g.inflow_c0, g.inflow_c1, self.inflow_depth(t0, t1))
 
     def set_judge_region(self, mask, block):
         """mask: device uint8 [ceil(ny/block), ceil(nx/block)] tensor or None."""
@@ -457,20 +470,36 @@ class Surrogate:
         self._check(self._lib.fps_sur_get_params(self.s_, _ptr(p)))
         return p
 
-    def forward(self, x, y=None):
+    def _check_x(self, x):
         n = x.shape[0]
+        if (tuple(x.shape[1:]) != (self.H, self.W, 16) or x.dtype != self.torch.bfloat16 or not x.is_contiguous()
+                or not 1 <= n <= self.max_batch):
+            raise FpsError(FPS_E_INVALID, f"surrogate input {tuple(x.shape)} {x.dtype}: expected contiguous bf16 "
+                                          f"[1..{self.max_batch}, {self.H}, {self.W}, 16]")
+        return n
+
+    def _check_y(self, y, n):
+        if tuple(y.shape) != (n, self.H, self.W, 4) or y.dtype != self.torch.float32 or not y.is_contiguous():
+            raise FpsError(FPS_E_INVALID, f"surrogate output/target {tuple(y.shape)}: expected contiguous fp32 "
+                                          f"[{n}, {self.H}, {self.W}, 4]")
+
+    def forward(self, x, y=None):
+        n = self._check_x(x)
         if y is None:
             y = self.torch.empty((n, self.H, self.W, 4), dtype=self.torch.float32, device=self.device)
+        self._check_y(y, n)
         self._check(self._lib.fps_sur_forward(self.s_, n, _ptr(x), _ptr(y)))
         return y
 
     def gradients(self, x, target):
+        self._check_y(target, self._check_x(x))
         g = self.torch.empty(self.n_params, dtype=self.torch.float32, device=self.device)
         self._check(self._lib.fps_sur_gradients(self.s_, x.shape[0], _ptr(x), _ptr(target), _ptr(g),
                                                 _ptr(self.loss_t)))
         return self.loss_t, g
 
     def train_step(self, x, target, lr):
+        self._check_y(target, self._check_x(x))
         self._check(self._lib.fps_sur_train_step(self.s_, x.shape[0], _ptr(x), _ptr(target), float(lr),
                                                  _ptr(self.loss_t)))
         return self.loss_t
@@ -493,15 +522,19 @@ def _stream_ptr(torch, t, stream):
     return C.c_void_p(st.cuda_stream)
 
 
-def sur_pack(h, hu, hv, z, occupancy=None, out=None, stream=None):
-    """Surrogate input bf16 [H, W, 16] from float32 device planes [H, W]
-    (occupancy: int32 evacuee counts per cell, or None)."""
+def sur_pack(h, hu, hv, z, occupancy=None, inflow=None, out=None, stream=None):
+    """Surrogate input bf16 [ny, nx, 16] from float32 device planes [ny, nx]
+    (occupancy: int32 evacuee counts per cell or None; inflow: (side, c0, c1,
+    depth over the block) or None)."""
     import torch
+    ny, nx = h.shape
     if out is None:
-        out = torch.empty(h.shape + (16,), dtype=torch.bfloat16, device=h.device)
+        out = torch.empty((ny, nx, 16), dtype=torch.bfloat16, device=h.device)
+    assert out.shape == (ny, nx, 16) and out.dtype == torch.bfloat16 and out.is_contiguous()
     occ = _ptr(occupancy) if occupancy is not None else None
-    rc = lib().fps_sur_pack(h.numel(), _ptr(h), _ptr(hu), _ptr(hv), _ptr(z), occ, _ptr(out),
-                            _stream_ptr(torch, h, stream))
+    side, c0, c1, depth = inflow if inflow is not None else (-1, 0, 0, 0.0)
+    rc = lib().fps_sur_pack(nx, ny, _ptr(h), _ptr(hu), _ptr(hv), _ptr(z), occ, int(side), int(c0), int(c1),
+                            float(depth), _ptr(out), _stream_ptr(torch, h, stream))
     if rc != FPS_OK:
         raise FpsError(rc, (lib().fps_sur_last_error(None) or b"").decode())
     return out
@@ -520,10 +553,11 @@ def sur_make_target(s0, s1, out=None, stream=None):
     return out
 
 
-def sur_apply(y, h, hu, hv, h_dry=1e-5, stream=None):
-    """Apply a surrogate output fp32 [H, W, 4] to (h, hu, hv) in place."""
+def sur_apply(y, h, hu, hv, h_dry=1e-5, h_snap=1e-3, stream=None):
+    """Apply a surrogate output fp32 [ny, nx, 4] to (h, hu, hv) in place."""
     import torch
-    rc = lib().fps_sur_apply(h.numel(), _ptr(y), _ptr(h), _ptr(hu), _ptr(hv), float(h_dry),
+    assert y.shape == h.shape + (4,)
+    rc = lib().fps_sur_apply(h.numel(), _ptr(y), _ptr(h), _ptr(hu), _ptr(hv), float(h_dry), float(h_snap),
                              _stream_ptr(torch, h, stream))
     if rc != FPS_OK:
         raise FpsError(rc, (lib().fps_sur_last_error(None) or b"").decode())

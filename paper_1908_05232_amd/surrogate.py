@@ -35,6 +35,8 @@ from . import inputs as I
 
 K_STEPS = 8
 JUDGE_BLOCK = 16          # cells per side of a judge-region mask block
+N_IN = 6                  # used input channels: h, hu, hv, z, occupancy, inflow depth
+H_SNAP = 1e-3             # a dry cell stays dry unless the update puts this much water on it
 
 
 @dataclasses.dataclass
@@ -87,14 +89,14 @@ LAYERS = [(16, 64), (64, 64), (64, 64), (64, 64), (64, 16)]
 
 
 def init_params(seed: int = 0):
-    """He-normal weights (zero for the 11 unused input channels and the 13
+    """He-normal weights (zero for the 10 unused input channels and the 13
     padding outputs) and zero biases, packed as the library expects."""
     rng = I.rng_of(seed)
     out = []
     for li, (cin, cout) in enumerate(LAYERS):
         w = rng.normal(0.0, np.sqrt(2.0 / (9 * cin)), size=(cout, 3, 3, cin))
         if li == 0:
-            w[..., 5:] = 0.0
+            w[..., N_IN:] = 0.0
         if li == len(LAYERS) - 1:
             w[3:] = 0.0
         out += [w.reshape(-1), np.zeros(cout)]
@@ -140,7 +142,7 @@ def generate_pairs(cases, ds: Dataset, warmup: int, pairs: int, every: int = K_S
     """Step the cases together on the finite-volume engine and append `pairs`
     pairs per case to ds (state at t, scaled change over K steps), one every
     `every` steps after `warmup` steps.  keep: optional list collecting
-    (case index, U0 copy, U1 copy) for evaluation.  Returns the fraction of
+    (case index, inflow feature, U0 copy, U1 copy) for evaluation.  Returns the fraction of
     pairs whose K steps all had the fixed length."""
     import torch
     ens, crowds = _flood_ensemble(cases)
@@ -149,17 +151,19 @@ def generate_pairs(cases, ds: Dataset, warmup: int, pairs: int, every: int = K_S
         ens.step(warmup)
     u0 = [tuple(torch.empty_like(a) for a in _state(m)) for m in ens.members]
     ok = 0
+    span = K_STEPS * float(np.float32(dt_s))
     for r in range(pairs):
         t0 = [m.diag()["t"] for m in ens.members]
+        feats = [m.inflow_feature(t, t + span) for m, t in zip(ens.members, t0)]
         base = ds.size
         for k, m in enumerate(ens.members):
-            fps.sur_pack(m.h, m.qx, m.qy, m.z, crowds[k].occ, out=ds.x[base + k])
+            fps.sur_pack(m.h, m.qx, m.qy, m.z, crowds[k].occ, inflow=feats[k], out=ds.x[base + k])
             fps.sur_copy_state(_state(m), u0[k])
         ens.step(K_STEPS)
         for k, m in enumerate(ens.members):
             fps.sur_make_target(u0[k], _state(m), out=ds.t[base + k])
             if keep is not None:
-                keep.append((k, tuple(a.clone() for a in u0[k]), tuple(a.clone() for a in _state(m))))
+                keep.append((k, feats[k], tuple(a.clone() for a in u0[k]), tuple(a.clone() for a in _state(m))))
             ok += abs(m.diag()["t"] - t0[k] - K_STEPS * float(np.float32(dt_s))) < 1e-6
         ds.size += len(cases)
         if every > K_STEPS and r + 1 < pairs:
@@ -197,13 +201,13 @@ def evaluate(sur: fps.Surrogate, cases, kept, tol=0.01, h_dry=1e-5):
            "sur_bad_people": 0, "persist_bad_people": 0, "people": 0, "sur_rmse_h": 0.0, "persist_rmse_h": 0.0}
     se_s = se_p = 0.0
     cells = 0
-    for k, u0, u1 in kept:
+    for k, feat, u0, u1 in kept:
         cr = crowds[k].t
         z = torch.tensor(np.asarray(cases[k].sc.z, np.float32), device="cuda")
-        fps.sur_pack(*u0, z, crowds[k].occ, out=x[0])
+        fps.sur_pack(*u0, z, crowds[k].occ, inflow=feat, out=x[0])
         sur.forward(x, y)
         us = tuple(a.clone() for a in u0)
-        fps.sur_apply(y[0], *us, h_dry=h_dry)
+        fps.sur_apply(y[0], *us, h_dry=h_dry, h_snap=H_SNAP)
         js = fps.judge_result(fps.sur_judge(cr["x"], cr["y"], cr["state"], d.nx, d.ny, d.dx, d.dy, us, u1, tol=tol))
         jp = fps.judge_result(fps.sur_judge(cr["x"], cr["y"], cr["state"], d.nx, d.ny, d.dx, d.dy, u0, u1, tol=tol))
         res["pairs"] += 1
@@ -227,11 +231,14 @@ class AssistedEnsemble:
     fallback (see the module docstring).  All cases share one grid size.
     stride: every stride-th person of each crowd is a judge point."""
 
-    def __init__(self, cases, sur: fps.Surrogate, chunk: int, stride: int = 1, tol: float = 0.01,
-                 halo: int = K_STEPS):
+    def __init__(self, cases, params, chunk: int, stride: int = 1, tol: float = 0.01, halo: int = K_STEPS):
+        """params: packed FP32 parameters of a trained network (any grid size)."""
         import torch
         self.torch = torch
-        self.cases, self.sur, self.chunk = cases, sur, chunk
+        d0 = cases[0].sc.desc
+        self.sur = fps.Surrogate(chunk, d0.ny, d0.nx)
+        self.sur.set_params(params)
+        self.cases, self.chunk = cases, chunk
         self.stride, self.tol = stride, tol
         d = cases[0].sc.desc
         assert all(c.sc.desc.nx == d.nx and c.sc.desc.ny == d.ny for c in cases)
@@ -261,15 +268,17 @@ class AssistedEnsemble:
         S = len(self.cases)
         E, J = self.E.members, self.J.members
         # 1. the network's proposal for every case, in chunks
+        span = K_STEPS * self.dt
         for c0 in range(0, S, self.chunk):
             cnt = min(self.chunk, S - c0)
             for k in range(c0, c0 + cnt):
                 m = E[k]
-                fps.sur_pack(m.h, m.qx, m.qy, m.z, self.crowds[k].occ, out=self.x[k - c0])
+                fps.sur_pack(m.h, m.qx, m.qy, m.z, self.crowds[k].occ,
+                             inflow=m.inflow_feature(self.t[k], self.t[k] + span), out=self.x[k - c0])
             self.sur.forward(self.x[:cnt], self.y[:cnt])
             for k in range(c0, c0 + cnt):
                 fps.sur_copy_state(_state(E[k]), self.us[k])
-                fps.sur_apply(self.y[k - c0], *self.us[k], h_dry=self.d.h_dry)
+                fps.sur_apply(self.y[k - c0], *self.us[k], h_dry=self.d.h_dry, h_snap=H_SNAP)
         # 2. the finite-volume judge on the judge regions
         for k in range(S):
             fps.sur_copy_state(_state(E[k]), _state(J[k]))

@@ -148,14 +148,20 @@ def test_pack_target_apply_match_oracle():
     z = rng.uniform(-1, 3, (H, W)).astype(np.float32)
     occ = rng.integers(0, 6, (H, W)).astype(np.int32)
     dev = [torch.tensor(a).cuda() for a in (h, hu, hv, z, occ)]
-    x = fps.sur_pack(*dev).float().cpu().numpy()
-    xo = S.pack_input(*(a.astype(np.float64) for a in (h, hu, hv, z, occ)))
+    inflow = (2, 5, 20, 0.37)
+    x = fps.sur_pack(*dev, inflow=inflow).float().cpu().numpy()
+    xo = S.pack_input(*(a.astype(np.float64) for a in (h, hu, hv, z, occ)), inflow=inflow)
+    assert np.count_nonzero(xo[..., 5]) == 15
     xr = bf16_round(xo)
     keep = [0, 1, 2, 4] + list(range(5, 16))
     assert np.array_equal(x[..., keep], xr[..., keep])
     assert np.allclose(x[..., 3], xr[..., 3], rtol=2.0 ** -7, atol=0)   # z / 3: one bf16 ulp
-    x0 = fps.sur_pack(*dev[:4]).float().cpu().numpy()       # no occupancy
-    assert np.all(x0[..., 4] == 0) and np.array_equal(x0[..., :4], x[..., :4])
+    x0 = fps.sur_pack(*dev[:4]).float().cpu().numpy()       # no occupancy, no inflow
+    assert np.all(x0[..., 4:] == 0) and np.array_equal(x0[..., :4], x[..., :4])
+    for side, c0, c1 in ((0, 3, 9), (1, 0, 24), (3, 30, 37)):
+        xs = fps.sur_pack(*dev, inflow=(side, c0, c1, 0.2)).float().cpu().numpy()
+        xso = S.pack_input(*(a.astype(np.float64) for a in (h, hu, hv, z, occ)), inflow=(side, c0, c1, 0.2))
+        assert np.array_equal(xs[..., 5], bf16_round(xso[..., 5]))
     # target and apply: U1 reproduced from U0 and its target (within FP32 rounding)
     h1, hu1, hv1 = _planes(rng, H, W)
     s0 = [torch.tensor(a).cuda() for a in (h, hu, hv)]

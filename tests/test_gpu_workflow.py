@@ -27,7 +27,7 @@ def _random_surrogate(batch, n, seed=0):
 def test_fallback_equals_plain_fv():
     cases = _cases([31, 32, 33])
     sur = _random_surrogate(2, 64)
-    A = SG.AssistedEnsemble(cases, sur, chunk=2, tol=-1.0)      # every block rejected
+    A = SG.AssistedEnsemble(cases, sur.get_params(), chunk=2, tol=-1.0)      # every block rejected
     plain, _ = SG._flood_ensemble(cases)
     for _ in range(3):
         acc = A.block()
@@ -45,16 +45,18 @@ def test_accepted_block_is_the_network_update():
     for c in cases:                                  # no crowd: nothing to judge, every block accepted
         c.agents = {k: v[:0] for k, v in c.agents.items()}
     sur = _random_surrogate(2, 64, seed=3)
-    A = SG.AssistedEnsemble(cases, sur, chunk=2)
+    A = SG.AssistedEnsemble(cases, sur.get_params(), chunk=2)
     u0 = [tuple(t.clone() for t in SG._state(A.E[k])) for k in range(2)]
+    feats = [A.E[k].inflow_feature(0.0, SG.K_STEPS * A.dt) for k in range(2)]
+    assert all(f[3] > 0 for f in feats)
     acc = A.block()
     assert acc.all()
     for k in range(2):
         x = torch.empty((1, 64, 64, 16), dtype=torch.bfloat16, device="cuda")
         y = torch.empty((1, 64, 64, 4), dtype=torch.float32, device="cuda")
-        fps.sur_pack(*u0[k], A.E[k].z, A.crowds[k].occ, out=x[0])
+        fps.sur_pack(*u0[k], A.E[k].z, A.crowds[k].occ, inflow=feats[k], out=x[0])
         sur.forward(x, y)
-        fps.sur_apply(y[0], *u0[k], h_dry=cases[k].sc.desc.h_dry)
+        fps.sur_apply(y[0], *u0[k], h_dry=cases[k].sc.desc.h_dry, h_snap=SG.H_SNAP)
         for a, b in zip(SG._state(A.E[k]), u0[k]):
             assert torch.equal(a, b)
         assert A.E[k].diag()["t"] == A.t[k] == A._acc_time(0.0)

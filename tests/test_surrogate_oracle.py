@@ -153,3 +153,29 @@ def test_bf16_rounding_points_change_only_rounding():
     _, g1 = S.loss_and_grads(params, x, t, bf16=True)
     dw0, dw1 = g0[-1][0], g1[-1][0]
     assert np.linalg.norm(dw1 - dw0) / np.linalg.norm(dw0) < 2e-2
+
+
+def test_apply_output_keeps_dry_cells_dry_below_snap():
+    h = np.array([[0.0, 0.0, 5e-6, 0.3]])
+    z = np.zeros_like(h)
+    y = np.zeros((1, 4, 3))
+    y[0, :, 0] = [0.5e-3 / 0.05, 2e-3 / 0.05, 0.5e-3 / 0.05, -0.299 / 0.05]
+    y[0, :, 1] = 0.2
+    hn, qx, qy = S.apply_output(h, z, z, y)
+    # 0.5 mm on a dry cell: stays dry; 2 mm: wets; 1 mm left on a wet cell: kept
+    assert hn[0, 0] == 0.0 and qx[0, 0] == 0.0
+    assert abs(hn[0, 1] - 2e-3) < 1e-15 and qx[0, 1] == 0.2 * 0.05
+    assert hn[0, 2] == 0.0
+    assert abs(hn[0, 3] - 1e-3) < 1e-12
+
+
+def test_pack_input_inflow_channel_on_each_side():
+    ny, nx = 5, 7
+    zero = np.zeros((ny, nx))
+    for side, where in ((2, (0, slice(2, 5))), (3, (ny - 1, slice(2, 5))), (0, (slice(2, 5), 0)),
+                        (1, (slice(2, 5), nx - 1))):
+        x = S.pack_input(zero, zero, zero, zero, zero, inflow=(side, 2, 5, 0.3))
+        want = np.zeros((ny, nx))
+        want[where] = 0.3
+        assert np.array_equal(x[..., 5], want)
+    assert np.all(S.pack_input(zero, zero, zero, zero, zero, inflow=(-1, 0, 0, 1.0))[..., 5] == 0)
