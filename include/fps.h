@@ -275,7 +275,7 @@ const char* fps_ens_last_error(const fps_ens* ens);
    weights and Adam.  It maps the scaled state (h, hu, hv, z, occupancy) to
    the scaled change of (h, hu, hv) over k finite-volume steps.  Tensors are
    channels last: x bf16 [n][H][W][16] (channels 5..15 zero), outputs and
-   targets fp32 [n][H][W][4] (channel 3 zero).  H a multiple of 8, W of 32. ---- */
+   targets fp32 [n][H][W][4] (channel 3 zero).  H a multiple of 16, W of 32. ---- */
 typedef struct fps_sur fps_sur;
 
 /* Number of packed FP32 parameters: per layer W[cout][3][3][cin] then b[cout],

@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <utility>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -36,7 +37,9 @@ typedef __bf16 bf16;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int TH = 8, TW = 32;     // output tile of one block
+constexpr int TH = 8, TW = 32;     // pixel tile of one weight-gradient block
+constexpr int CTH = 16;            // rows of the output tile of one convolution block (x TW columns)
+constexpr int kMtPerWave = 8;      // 16-pixel M tiles per wave in the convolution (4 rows x 2)
 constexpr int kThreads = 256;
 constexpr int kLayers = 5;
 constexpr int kCin[kLayers] = {16, 64, 64, 64, 64};
@@ -51,101 +54,141 @@ __device__ __forceinline__ float to_f32(bf16 b) { return (float)b; }
 
 // ----------------------------------------------------------------------------
 // convolution as implicit GEMM (forward and input gradient)
-// MODE 0: bias + ReLU -> bf16 [.., COUT];  1: bias -> bf16 [.., COUT];
-//      2: bias -> fp32 [.., 4] (first kOutUsed channels, 4th zero)
+// MODE 0: bias + ReLU -> bf16 [.., COUT];  2: bias -> fp32 [.., 4] (first
+// kOutUsed channels, 4th zero);  3: input gradient masked by the ReLU of the
+// layer below (mask[p][co] > 0) -> bf16 [.., COUT]
+// Persistent blocks, one per CU: the weights are staged in LDS once, then
+// the block walks CTH x TW output tiles; while the matrix cores work on one
+// tile, the next tile's input (with halo) is already loading into registers
+// and is written to LDS after the tile.  Each wave holds 8 M tiles (4 rows of
+// 32 pixels) x COUT/16 N tiles of accumulators.
 // ----------------------------------------------------------------------------
 template <int CIN, int COUT, int MODE>
 __global__ __launch_bounds__(kThreads) void conv_kernel(const bf16* __restrict__ X,
                                                         const bf16* __restrict__ Wt,
                                                         const float* __restrict__ bias,
-                                                        void* __restrict__ Y, int H, int W)
+                                                        void* __restrict__ Y, int N, int H, int W,
+                                                        const bf16* __restrict__ mask)
 {
     constexpr int KP = kp_of(CIN);
-    constexpr int PIX = CIN + 8;        // padded pixel stride in LDS (bank spread)
+    constexpr int PIX = CIN + 8;        // padded pixel stride in LDS (bank spread, 16-byte rows)
     constexpr int WST = KP + 8;         // padded weight row stride in LDS
     constexpr int NT = COUT / 16;
+    constexpr int MT = kMtPerWave;
+    constexpr int CHUNKS = (CTH + 2) * (TW + 2) * (CIN / 8);
+    constexpr int XPT = (CHUNKS + kThreads - 1) / kThreads;
+    constexpr int WCH = COUT * (KP / 8);
     extern __shared__ __align__(16) unsigned char smem[];
-    bf16* xin = reinterpret_cast<bf16*>(smem);                       // [(TH+2)(TW+2)][PIX]
-    bf16* wl = xin + (TH + 2) * (TW + 2) * PIX;                       // [COUT][WST]
+    bf16* xin = reinterpret_cast<bf16*>(smem);                        // [(CTH+2)(TW+2)][PIX]
+    bf16* wl = xin + (CTH + 2) * (TW + 2) * PIX;                       // [COUT][WST]
 
-    const int tiles_x = W / TW, tiles_y = H / TH;
-    const int n = blockIdx.x / (tiles_x * tiles_y);
-    const int t = blockIdx.x % (tiles_x * tiles_y);
-    const int y0 = (t / tiles_x) * TH, x0 = (t % tiles_x) * TW;
-    const bf16* Xn = X + (size_t)n * H * W * CIN;
+    const int tiles_x = W / TW, tiles_y = H / CTH, per_img = tiles_x * tiles_y;
+    const int ntiles = N * per_img;
+    bf16x8 xb[XPT];
+    // input tile (with halo, zeros outside the image) of tile t into registers
+    auto fetch = [&](int t) {
+        const int n = t / per_img, r = t % per_img;
+        const int y0 = (r / tiles_x) * CTH, x0 = (r % tiles_x) * TW;
+        const bf16* Xn = X + (size_t)n * H * W * CIN;
+#pragma unroll
+        for (int u = 0; u < XPT; ++u) {
+            const int q = threadIdx.x + u * kThreads;
+            xb[u] = bf16x8{};
+            if (q < CHUNKS) {
+                const int px = q / (CIN / 8), c8 = (q % (CIN / 8)) * 8;
+                const int gy = y0 + px / (TW + 2) - 1, gx = x0 + px % (TW + 2) - 1;
+                if (gy >= 0 && gy < H && gx >= 0 && gx < W)
+                    xb[u] = *reinterpret_cast<const bf16x8*>(Xn + ((size_t)gy * W + gx) * CIN + c8);
+            }
+        }
+    };
+    auto deposit = [&]() {
+#pragma unroll
+        for (int u = 0; u < XPT; ++u) {
+            const int q = threadIdx.x + u * kThreads;
+            if (q < CHUNKS) {
+                const int px = q / (CIN / 8), c8 = (q % (CIN / 8)) * 8;
+                *reinterpret_cast<bf16x8*>(xin + px * PIX + c8) = xb[u];
+            }
+        }
+    };
 
-    // stage the input tile with its halo (zeros outside the image), 8 channels per load
-    constexpr int CHUNKS = (TH + 2) * (TW + 2) * (CIN / 8);
-    for (int q = threadIdx.x; q < CHUNKS; q += kThreads) {
-        const int px = q / (CIN / 8), c8 = (q % (CIN / 8)) * 8;
-        const int ly = px / (TW + 2), lx = px % (TW + 2);
-        const int gy = y0 + ly - 1, gx = x0 + lx - 1;
-        bf16x8 v = {};
-        if (gy >= 0 && gy < H && gx >= 0 && gx < W)
-            v = *reinterpret_cast<const bf16x8*>(Xn + ((size_t)gy * W + gx) * CIN + c8);
-        *reinterpret_cast<bf16x8*>(xin + px * PIX + c8) = v;
-    }
-    // stage the weights [COUT][KP]
-    for (int q = threadIdx.x; q < COUT * (KP / 8); q += kThreads) {
+    int t = blockIdx.x;
+    if (t >= ntiles) return;
+    fetch(t);
+    // the weights [COUT][KP], once per block
+    for (int q = threadIdx.x; q < WCH; q += kThreads) {
         const int co = q / (KP / 8), k8 = (q % (KP / 8)) * 8;
-        *reinterpret_cast<bf16x8*>(wl + co * WST + k8) =
-            *reinterpret_cast<const bf16x8*>(Wt + (size_t)co * KP + k8);
+        *reinterpret_cast<bf16x8*>(wl + co * WST + k8) = *reinterpret_cast<const bf16x8*>(Wt + (size_t)co * KP + k8);
     }
+    deposit();
     __syncthreads();
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int row16 = lane & 15, kgrp = lane >> 4;
-    f32x4 acc[4][NT];
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (; t < ntiles; t += gridDim.x) {
+        const int n = t / per_img, r = t % per_img;
+        const int y0 = (r / tiles_x) * CTH, x0 = (r % tiles_x) * TW;
+        const int tn = t + gridDim.x;
+        if (tn < ntiles) fetch(tn);                     // in flight during the matrix work below
 
-    for (int slab = 0; slab < KP / 32; ++slab) {
-        const int k0 = slab * 32 + kgrp * 8;
-        const int tap = k0 / CIN, c = k0 % CIN;
-        const bool valid = tap < 9;
-        const int dy = valid ? tap / 3 : 0, dx = valid ? tap % 3 : 0;
-        bf16x8 a[4], b[NT];
+        f32x4 acc[MT][NT];
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) {
-            // M tile mt: local row 2*wave + mt/2, columns 16*(mt%2) + row16
-            const int ly = 2 * wave + (mt >> 1) + dy;
-            const int lx = 16 * (mt & 1) + row16 + dx;
-            a[mt] = valid ? *reinterpret_cast<const bf16x8*>(xin + (ly * (TW + 2) + lx) * PIX + c)
-                          : bf16x8{};
-        }
+        for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt)
-            b[nt] = *reinterpret_cast<const bf16x8*>(wl + (16 * nt + row16) * WST + k0);
+            for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int slab = 0; slab < KP / 32; ++slab) {
+            const int k0 = slab * 32 + kgrp * 8;
+            const int tap = k0 / CIN, c = k0 % CIN;
+            const bool valid = tap < 9;
+            const int dy = valid ? tap / 3 : 0, dx = valid ? tap % 3 : 0;
+            bf16x8 a[MT], b[NT];
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt)
+            for (int mt = 0; mt < MT; ++mt) {
+                // M tile mt: local row 4*wave + mt/2, columns 16*(mt%2) + row16
+                const int ly = 4 * wave + (mt >> 1) + dy;
+                const int lx = 16 * (mt & 1) + row16 + dx;
+                a[mt] = valid ? *reinterpret_cast<const bf16x8*>(xin + (ly * (TW + 2) + lx) * PIX + c)
+                              : bf16x8{};
+            }
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt)
-                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], b[nt], acc[mt][nt], 0, 0, 0);
-    }
+                b[nt] = *reinterpret_cast<const bf16x8*>(wl + (16 * nt + row16) * WST + k0);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], b[nt], acc[mt][nt], 0, 0, 0);
+        }
 
-    // D tile: lane holds rows (pixels) 4*kgrp + r, column (channel) row16
+        // D tile: lane holds rows (pixels) 4*kgrp + r, column (channel) row16
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
-        const int gy = y0 + 2 * wave + (mt >> 1);
+        for (int mt = 0; mt < MT; ++mt) {
+            const int gy = y0 + 4 * wave + (mt >> 1);
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-            const int co = 16 * nt + row16;
-            const float bb = bias ? bias[co] : 0.0f;
+            for (int nt = 0; nt < NT; ++nt) {
+                const int co = 16 * nt + row16;
+                const float bb = bias ? bias[co] : 0.0f;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int gx = x0 + 16 * (mt & 1) + 4 * kgrp + r;
-                float v = acc[mt][nt][r] + bb;
-                const size_t p = ((size_t)n * H + gy) * W + gx;
-                if (MODE == 0) {
-                    reinterpret_cast<bf16*>(Y)[p * COUT + co] = to_bf16(fmaxf(v, 0.0f));
-                } else if (MODE == 1) {
-                    reinterpret_cast<bf16*>(Y)[p * COUT + co] = to_bf16(v);
-                } else {
-                    if (co < 4) reinterpret_cast<float*>(Y)[p * 4 + co] = co < kOutUsed ? v : 0.0f;
+                for (int rr = 0; rr < 4; ++rr) {
+                    const int gx = x0 + 16 * (mt & 1) + 4 * kgrp + rr;
+                    float v = acc[mt][nt][rr] + bb;
+                    const size_t p = ((size_t)n * H + gy) * W + gx;
+                    if (MODE == 0) {
+                        reinterpret_cast<bf16*>(Y)[p * COUT + co] = to_bf16(fmaxf(v, 0.0f));
+                    } else if (MODE == 3) {
+                        reinterpret_cast<bf16*>(Y)[p * COUT + co] =
+                            to_f32(mask[p * COUT + co]) > 0.0f ? to_bf16(v) : to_bf16(0.0f);
+                    } else {
+                        if (co < 4) reinterpret_cast<float*>(Y)[p * 4 + co] = co < kOutUsed ? v : 0.0f;
+                    }
                 }
             }
+        }
+        if (tn < ntiles) {
+            __syncthreads();          // every wave is done with this tile's input
+            deposit();
+            __syncthreads();
         }
     }
 }
@@ -156,7 +199,8 @@ __global__ __launch_bounds__(kThreads) void conv_kernel(const bf16* __restrict__
 template <int CIN, int COUT>
 __global__ __launch_bounds__(kThreads) void wgrad_kernel(const bf16* __restrict__ X,
                                                          const bf16* __restrict__ DZ,
-                                                         float* __restrict__ part, int N, int H, int W)
+                                                         float* __restrict__ part, float* __restrict__ bpart,
+                                                         int N, int H, int W)
 {
     constexpr int MT = COUT / 16, NTAP = CIN / 16;     // N tiles per tap
     constexpr int TILES = MT * 9 * NTAP;               // 16x16 output tiles
@@ -171,32 +215,63 @@ __global__ __launch_bounds__(kThreads) void wgrad_kernel(const bf16* __restrict_
     f32x4 acc[PER_WAVE];
 #pragma unroll
     for (int k = 0; k < PER_WAVE; ++k) acc[k] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    // bias gradient: this thread always stages the same 8 channels (kThreads is
+    // a multiple of COUT / 8), so it sums them as it goes
+    static_assert(kThreads % (COUT / 8) == 0, "fixed channel group per thread");
+    float bsum[8] = {};
 
     const int tiles_x = W / TW, tiles_y = H / TH, per_img = tiles_x * tiles_y;
     for (int tile = blockIdx.x; tile < N * per_img; tile += gridDim.x) {
         const int n = tile / per_img, t = tile % per_img;
         const int y0 = (t / tiles_x) * TH, x0 = (t % tiles_x) * TW;
         __syncthreads();
-        // dz tile transposed: dzT[co][p], p = row * TW + col
-        for (int q = threadIdx.x; q < TH * TW * (COUT / 8); q += kThreads) {
+        // dz tile transposed: dzT[co][p], p = row * TW + col (loads first, then the stores)
+        constexpr int DCH = TH * TW * (COUT / 8);
+        static_assert(DCH % kThreads == 0, "whole dz chunks per thread");
+        bf16x8 dv[DCH / kThreads];
+#pragma unroll
+        for (int u = 0; u < DCH / kThreads; ++u) {
+            const int q = threadIdx.x + u * kThreads;
             const int p = q / (COUT / 8), c8 = (q % (COUT / 8)) * 8;
             const int gy = y0 + p / TW, gx = x0 + p % TW;
-            bf16x8 v = *reinterpret_cast<const bf16x8*>(DZ + (((size_t)n * H + gy) * W + gx) * COUT + c8);
+            dv[u] = *reinterpret_cast<const bf16x8*>(DZ + (((size_t)n * H + gy) * W + gx) * COUT + c8);
+        }
 #pragma unroll
-            for (int e = 0; e < 8; ++e) dzT[(c8 + e) * (TH * TW) + p] = v[e];
+        for (int u = 0; u < DCH / kThreads; ++u) {
+            const int q = threadIdx.x + u * kThreads;
+            const int p = q / (COUT / 8), c8 = (q % (COUT / 8)) * 8;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                dzT[(c8 + e) * (TH * TW) + p] = dv[u][e];
+                bsum[e] += to_f32(dv[u][e]);
+            }
         }
         for (int dx = 0; dx < 3; ++dx) {
             __syncthreads();
             // x tile for this column offset, transposed: xT[ci][ly][col] = x[y0+ly-1][x0+col+dx-1][ci]
-            for (int q = threadIdx.x; q < (TH + 2) * XROW * (CIN / 8); q += kThreads) {
-                const int px = q / (CIN / 8), c8 = (q % (CIN / 8)) * 8;
-                const int ly = px / XROW, col = px % XROW;
-                const int gy = y0 + ly - 1, gx = x0 + col + dx - 1;
-                bf16x8 v = {};
-                if (gy >= 0 && gy < H && gx >= 0 && gx < W)
-                    v = *reinterpret_cast<const bf16x8*>(X + (((size_t)n * H + gy) * W + gx) * CIN + c8);
+            constexpr int XCH = (TH + 2) * XROW * (CIN / 8);
+            constexpr int XPT = (XCH + kThreads - 1) / kThreads;
+            bf16x8 xv[XPT];
 #pragma unroll
-                for (int e = 0; e < 8; ++e) xT[(c8 + e) * ((TH + 2) * XROW) + ly * XROW + col] = v[e];
+            for (int u = 0; u < XPT; ++u) {
+                const int q = threadIdx.x + u * kThreads;
+                xv[u] = bf16x8{};
+                if (q < XCH) {
+                    const int px = q / (CIN / 8), c8 = (q % (CIN / 8)) * 8;
+                    const int gy = y0 + px / XROW - 1, gx = x0 + px % XROW + dx - 1;
+                    if (gy >= 0 && gy < H && gx >= 0 && gx < W)
+                        xv[u] = *reinterpret_cast<const bf16x8*>(X + (((size_t)n * H + gy) * W + gx) * CIN + c8);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < XPT; ++u) {
+                const int q = threadIdx.x + u * kThreads;
+                if (q < XCH) {
+                    const int px = q / (CIN / 8), c8 = (q % (CIN / 8)) * 8;
+                    const int ly = px / XROW, col = px % XROW;
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) xT[(c8 + e) * ((TH + 2) * XROW) + ly * XROW + col] = xv[u][e];
+                }
             }
             __syncthreads();
 #pragma unroll
@@ -218,6 +293,18 @@ __global__ __launch_bounds__(kThreads) void wgrad_kernel(const bf16* __restrict_
             }
         }
     }
+    // bias partial of the block: the threads of each channel group in thread order
+    __syncthreads();
+    float* bs = reinterpret_cast<float*>(smem);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) bs[threadIdx.x * 8 + e] = bsum[e];
+    __syncthreads();
+    if (threadIdx.x < COUT) {
+        const int g = threadIdx.x / 8, e = threadIdx.x % 8;
+        float t = 0.0f;
+        for (int th = g; th < kThreads; th += COUT / 8) t += bs[th * 8 + e];
+        bpart[(size_t)blockIdx.x * COUT + threadIdx.x] = t;
+    }
     // partial [block][co][tap][ci]; D tile lane holds rows (co) 4*kgrp + r, column (ci) row16
     float* pb = part + (size_t)blockIdx.x * COUT * 9 * CIN;
 #pragma unroll
@@ -234,38 +321,40 @@ __global__ __launch_bounds__(kThreads) void wgrad_kernel(const bf16* __restrict_
     }
 }
 
-// dW = sum over blocks (fixed order) and db = sum over pixels of dz (fixed order)
-__global__ void reduce_kernel(const float* __restrict__ part, int nblocks, int count, float* __restrict__ dw)
+// Sum of the per-block partials of every output element in a fixed order:
+// 16 threads per element each sum every 16th block, then the 16 sums are
+// added in thread order.  Block: 64 elements x 16 groups.
+__global__ __launch_bounds__(1024) void reduce_kernel(const float* __restrict__ part, int nblocks, int count,
+                                                      float* __restrict__ out)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= count) return;
+    __shared__ float red[16][64];
+    const int o = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int i = blockIdx.x * 64 + o;
     float s = 0.0f;
-    for (int b = 0; b < nblocks; ++b) s += part[(size_t)b * count + i];
-    dw[i] = s;
-}
-
-// db partials: block b sums its pixel range for every channel (fixed order)
-__global__ void bias_partial_kernel(const bf16* __restrict__ DZ, int64_t npix, int cout, int per_block,
-                                    float* __restrict__ part)
-{
-    const int co = threadIdx.x;
-    if (co >= cout) return;
-    const int64_t p0 = (int64_t)blockIdx.x * per_block, p1 = min(p0 + per_block, npix);
-    float s = 0.0f;
-    for (int64_t p = p0; p < p1; ++p) s += to_f32(DZ[p * cout + co]);
-    part[(size_t)blockIdx.x * cout + co] = s;
+    if (i < count) {
+        int b = g;
+        for (; b + 48 < nblocks; b += 64) {     // four independent loads in flight
+            const float v0 = part[(size_t)b * count + i], v1 = part[(size_t)(b + 16) * count + i];
+            const float v2 = part[(size_t)(b + 32) * count + i], v3 = part[(size_t)(b + 48) * count + i];
+            s += v0;
+            s += v1;
+            s += v2;
+            s += v3;
+        }
+        for (; b < nblocks; b += 16) s += part[(size_t)b * count + i];
+    }
+    red[g][o] = s;
+    __syncthreads();
+    if (g == 0 && i < count) {
+        float t = 0.0f;
+        for (int k = 0; k < 16; ++k) t += red[k][o];
+        out[i] = t;
+    }
 }
 
 // ----------------------------------------------------------------------------
 // elementwise kernels
 // ----------------------------------------------------------------------------
-// dz = g * (a > 0)   (ReLU derivative from the layer's output)
-__global__ void relu_mask_kernel(const bf16* __restrict__ g, const bf16* __restrict__ a,
-                                 bf16* __restrict__ dz, int64_t n)
-{
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        dz[i] = to_f32(a[i]) > 0.0f ? g[i] : to_bf16(0.0f);
-}
 
 // MSE: per-block loss partials and dz of the output layer (bf16, 16 channels)
 __global__ void loss_kernel(const float* __restrict__ pred, const float* __restrict__ target, int64_t npix,
@@ -493,6 +582,7 @@ using namespace fps_sur_impl;
 
 struct fps_sur {
     int max_batch = 0, H = 0, W = 0;
+    int cus = 256;                   // compute units of the device (persistent convolution blocks)
     hipStream_t stream = nullptr;
     char err[512] = "";
     float *params = nullptr, *m = nullptr, *v = nullptr, *grads = nullptr;
@@ -531,7 +621,6 @@ int sfail(fps_sur* s, int code, const char* fmt, ...)
     } while (0)
 
 constexpr int kLossBlocks = 1024;
-constexpr int kBiasBlocks = 512;
 
 size_t a256(size_t v) { return (v + 255) & ~size_t(255); }
 
@@ -575,25 +664,27 @@ SurLayout sur_layout(int B, int H, int W)
     L.dz = take(2 * pix * 64);
     L.dz5 = take(2 * pix * 16);
     L.wpart = take(4 * (size_t)kWgradBlocks * 64 * 9 * 64);
-    L.bpart = take(4 * (size_t)kBiasBlocks * 64);
+    L.bpart = take(4 * (size_t)kWgradBlocks * 64);
     L.lpart = take(4 * (size_t)kLossBlocks);
     L.total = o;
     return L;
 }
 
 template <int CIN, int COUT, int MODE>
-int conv(fps_sur* s, int n, const bf16* x, const bf16* w, const float* b, void* y)
+int conv(fps_sur* s, int n, const bf16* x, const bf16* w, const float* b, void* y, const bf16* mask = nullptr)
 {
     constexpr int KP = kp_of(CIN);
-    const size_t lds = (size_t)(TH + 2) * (TW + 2) * (CIN + 8) * 2 + (size_t)COUT * (KP + 8) * 2;
+    const size_t lds = (size_t)(CTH + 2) * (TW + 2) * (CIN + 8) * 2 + (size_t)COUT * (KP + 8) * 2;
     auto k = conv_kernel<CIN, COUT, MODE>;
     SCHK(s, hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    const int blocks = n * (s->H / TH) * (s->W / TW);
-    hipLaunchKernelGGL(k, dim3(blocks), dim3(kThreads), lds, s->stream, x, w, b, y, s->H, s->W);
+    const int tiles = n * (s->H / CTH) * (s->W / TW);
+    const int blocks = std::min(tiles, s->cus);          // persistent: one block per compute unit
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(kThreads), lds, s->stream, x, w, b, y, n, s->H, s->W, mask);
     SCHK(s, hipGetLastError());
     return FPS_OK;
 }
 
+// weight and bias gradients of one layer: per-block partials, then the fixed-order sums
 template <int CIN, int COUT>
 int wgrad(fps_sur* s, int n, const bf16* x, const bf16* dz, int layer)
 {
@@ -602,19 +693,14 @@ int wgrad(fps_sur* s, int n, const bf16* x, const bf16* dz, int layer)
     SCHK(s, hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     const int tiles = n * (s->H / TH) * (s->W / TW);
     const int blocks = std::min(tiles, kWgradBlocks);
-    hipLaunchKernelGGL(k, dim3(blocks), dim3(kThreads), lds, s->stream, x, dz, s->wpart, n, s->H, s->W);
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(kThreads), lds, s->stream, x, dz, s->wpart, s->bpart, n, s->H,
+                       s->W);
     SCHK(s, hipGetLastError());
     const int count = COUT * 9 * CIN;
     float* dw = s->grads + param_offset(layer);
-    hipLaunchKernelGGL(reduce_kernel, dim3((count + 255) / 256), dim3(256), 0, s->stream, s->wpart, blocks,
-                       count, dw);
-    SCHK(s, hipGetLastError());
-    // bias: per-block sums over pixel ranges, then the fixed-order total
-    const int64_t npix = (int64_t)n * s->H * s->W;
-    const int per = (int)((npix + kBiasBlocks - 1) / kBiasBlocks);
-    hipLaunchKernelGGL(bias_partial_kernel, dim3(kBiasBlocks), dim3(64), 0, s->stream, dz, npix, COUT, per,
-                       s->bpart);
-    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(64), 0, s->stream, s->bpart, kBiasBlocks, COUT,
+    hipLaunchKernelGGL(reduce_kernel, dim3((count + 63) / 64), dim3(1024), 0, s->stream, s->wpart, blocks, count,
+                       dw);
+    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, s->stream, s->bpart, blocks, COUT,
                        dw + w_count(layer));
     SCHK(s, hipGetLastError());
     return FPS_OK;
@@ -655,7 +741,7 @@ int32_t fps_sur_param_count(void) { return (int32_t)total_params(); }
 
 size_t fps_sur_workspace_bytes(int32_t max_batch, int32_t H, int32_t W)
 {
-    if (max_batch < 1 || H < TH || W < TW || H % TH || W % TW) return 0;
+    if (max_batch < 1 || H < CTH || W < TW || H % CTH || W % TW) return 0;
     return sur_layout(max_batch, H, W).total;
 }
 
@@ -664,8 +750,9 @@ int fps_sur_create(int32_t max_batch, int32_t H, int32_t W, void* ws, size_t ws_
 {
     if (!out) return sfail(nullptr, FPS_E_INVALID, "fps_sur_create: out is NULL");
     *out = nullptr;
-    if (max_batch < 1 || H < TH || W < TW || H % TH || W % TW)
-        return sfail(nullptr, FPS_E_INVALID, "fps_sur_create: need batch >= 1 and H, W multiples of %d, %d", TH, TW);
+    if (max_batch < 1 || H < CTH || W < TW || H % CTH || W % TW)
+        return sfail(nullptr, FPS_E_INVALID, "fps_sur_create: need batch >= 1 and H, W multiples of %d, %d", CTH,
+                     TW);
     if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255))
         return sfail(nullptr, FPS_E_INVALID, "fps_sur_create: workspace NULL or not 256-byte aligned");
     SurLayout L = sur_layout(max_batch, H, W);
@@ -677,6 +764,12 @@ int fps_sur_create(int32_t max_batch, int32_t H, int32_t W, void* ws, size_t ws_
     s->H = H;
     s->W = W;
     s->stream = static_cast<hipStream_t>(stream);
+    {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            s->cus = cus;
+    }
     char* b = static_cast<char*>(ws);
     s->params = reinterpret_cast<float*>(b + L.params);
     s->m = reinterpret_cast<float*>(b + L.m);
@@ -747,18 +840,20 @@ int fps_sur_gradients(fps_sur* s, int32_t n, const void* xv, const float* target
                        s->dz5, s->lpart);
     hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(64), 0, s->stream, s->lpart, kLossBlocks, scale, loss);
     SCHK(s, hipGetLastError());
-    // layer 5 (no ReLU): dz5 -> dW5, input gradient g (64 channels)
+    // layer 5 (no ReLU): dz5 -> dW5; its input gradient masked by the ReLU of
+    // layer 4 is dz of layer 4.  Then down the layers, dz ping-ponging
+    // between two buffers.
     rc = wgrad<64, 16>(s, n, s->act[3], s->dz5, 4);
-    if (rc == FPS_OK) rc = conv<16, 64, 1>(s, n, s->dz5, s->wd[4], nullptr, s->g);
+    bf16* dz_cur = s->dz;
+    bf16* dz_next = s->g;
+    if (rc == FPS_OK) rc = conv<16, 64, 3>(s, n, s->dz5, s->wd[4], nullptr, dz_cur, s->act[3]);
     for (int l = 3; l >= 0 && rc == FPS_OK; --l) {
-        const int64_t cnt = npix * 64;
-        hipLaunchKernelGGL(relu_mask_kernel, dim3(2048), dim3(256), 0, s->stream, s->g, s->act[l], s->dz, cnt);
-        SCHK(s, hipGetLastError());
         if (l > 0) {
-            rc = wgrad<64, 64>(s, n, s->act[l - 1], s->dz, l);
-            if (rc == FPS_OK) rc = conv<64, 64, 1>(s, n, s->dz, s->wd[l], nullptr, s->g);
+            rc = wgrad<64, 64>(s, n, s->act[l - 1], dz_cur, l);
+            if (rc == FPS_OK) rc = conv<64, 64, 3>(s, n, dz_cur, s->wd[l], nullptr, dz_next, s->act[l - 1]);
+            std::swap(dz_cur, dz_next);
         } else {
-            rc = wgrad<16, 64>(s, n, x, s->dz, 0);
+            rc = wgrad<16, 64>(s, n, x, dz_cur, 0);
         }
     }
     if (rc != FPS_OK) return rc;

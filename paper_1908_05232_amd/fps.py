@@ -441,7 +441,7 @@ class Surrogate:
         self.H, self.W, self.max_batch = H, W, max_batch
         nbytes = L.fps_sur_workspace_bytes(max_batch, H, W)
         if nbytes == 0:
-            raise FpsError(FPS_E_INVALID, "surrogate shape rejected (H % 8, W % 32)")
+            raise FpsError(FPS_E_INVALID, "surrogate shape rejected (H % 16, W % 32)")
         dev = torch.device(device)
         self.device = dev
         self.ws, ws_ptr = _workspace(torch, nbytes, dev)
