@@ -195,6 +195,51 @@ def surrogate_section(args):
     return out
 
 
+def surrogate_probe(fwd_only=False):
+    """Timing probe of the surrogate kernels alone (for the profiler): 23
+    training steps and 20 forwards at 8 x 256^2, 6 forwards at 4 x 2048^2;
+    with fwd_only, only 3 forwards at 4 x 2048^2."""
+    import torch
+    from paper_1908_05232_amd import fps, surrogate as SG
+    params = torch.tensor(SG.init_params(0)).cuda()
+    out = {}
+
+    def timed(fn, reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    if not fwd_only:
+        sur = fps.Surrogate(8, 256, 256)
+        sur.set_params(params)
+        g = torch.Generator(device="cuda").manual_seed(0)
+        x = (torch.randn(8, 256, 256, 16, device="cuda", generator=g) * 0.5).bfloat16()
+        x[..., 6:] = 0
+        t = torch.randn(8, 256, 256, 4, device="cuda", generator=g) * 0.1
+        t[..., 3] = 0
+        for _ in range(3):
+            sur.train_step(x, t, 1e-4)
+        dt = timed(lambda: sur.train_step(x, t, 1e-4), 20)
+        out["train_step_ms_8x256"] = dt * 1e3
+        out["train_TFLOPs"] = 3 * 230400 * 8 * 65536 / dt / 1e12
+        y = torch.empty(8, 256, 256, 4, device="cuda")
+        dt = timed(lambda: sur.forward(x, y), 20)
+        out["forward_ms_8x256"] = dt * 1e3
+        out["forward_TFLOPs_8x256"] = 230400 * 8 * 65536 / dt / 1e12
+    big = fps.Surrogate(4, 2048, 2048)
+    big.set_params(params)
+    xb = torch.zeros(4, 2048, 2048, 16, device="cuda", dtype=torch.bfloat16)
+    yb = torch.empty(4, 2048, 2048, 4, device="cuda")
+    big.forward(xb, yb)
+    dt = timed(lambda: big.forward(xb, yb), 3 if fwd_only else 5)
+    out["forward_ms_4x2048"] = dt * 1e3
+    out["forward_TFLOPs_4x2048"] = 230400 * 4 * 2048 * 2048 / dt / 1e12
+    print(json.dumps({"surrogate_probe": out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -223,6 +268,8 @@ def main():
     ap.add_argument("--sur-blocks", type=int, default=10)
     ap.add_argument("--sur-chunk", type=int, default=4)
     ap.add_argument("--sur-stride", type=int, default=250)
+    ap.add_argument("--sur-probe", choices=["all", "forward"], default=None,
+                    help="only time the surrogate kernels (profiler runs) and exit")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of 1 GiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -233,6 +280,10 @@ def main():
 
     import torch
     from paper_1908_05232_amd import fps, inputs as I
+
+    if args.sur_probe:
+        surrogate_probe(fwd_only=args.sur_probe == "forward")
+        return
 
     if args.copy_probe:
         n = 1 << 28                                   # 2^28 floats = 1 GiB each way
