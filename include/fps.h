@@ -226,6 +226,12 @@ int fps_get_bins(fps_sim* sim, int32_t* bin_start, int32_t* perm, int32_t* nbins
    (host).  Synchronises. */
 int fps_step_profiled(fps_sim* sim, int32_t n_steps, double* ms_out);
 
+/* Average duration of one flood-update launch of this simulation in its
+   current tile shape: reps back-to-back launches on the current state between
+   two HIP events on the library's stream (the state is left unchanged).
+   Synchronises. */
+int fps_time_flood(fps_sim* sim, int32_t reps, double* ms_per_launch);
+
 /* Tile shape of the flood update: rows each wave marches through (a power of
    two in [1, 64]); every choice gives the same flood state, only the FP64
    mass diagnostic's summation order changes.  Synchronises. */

@@ -1199,6 +1199,17 @@ int fps_get_bins(fps_sim* s, int32_t* bin_start, int32_t* perm, int32_t* nbins_o
     return FPS_OK;
 }
 
+int fps_time_flood(fps_sim* s, int32_t reps, double* ms_per_launch)
+{
+    if (!s || !ms_per_launch || reps < 1) return fail(s, FPS_E_INVALID, "fps_time_flood: bad argument");
+    if (!s->fields_bound) return fail(s, FPS_E_STATE, "fps_time_flood: fields not bound");
+    float ms = 0.0f;
+    int rc = time_rows(s, s->H, reps, &ms);
+    if (rc != FPS_OK) return rc;
+    *ms_per_launch = ms;
+    return prime(s);    // the timing launches wrote scratch partials and the wetness flags
+}
+
 int fps_set_rows_per_wave(fps_sim* s, int32_t rows)
 {
     if (!s) return fail(nullptr, FPS_E_INVALID, "fps_set_rows_per_wave: sim is NULL");

@@ -97,6 +97,7 @@ EXPORTS = {
     "fps_sur_train_step": (C.c_int, [_vp, C.c_int32, _vp, _vp, C.c_float, _vp]),
     "fps_set_judge_region": (C.c_int, [_vp, _vp, C.c_int32]),
     "fps_inflow_depth": (C.c_int, [_vp, C.c_double, C.c_double, C.POINTER(C.c_double)]),
+    "fps_time_flood": (C.c_int, [_vp, C.c_int32, C.POINTER(C.c_double)]),
     "fps_set_occupancy": (C.c_int, [_vp, _vp]),
     "fps_sur_pack": (C.c_int, [C.c_int32, C.c_int32, _vp, _vp, _vp, _vp, _vp, C.c_int32, C.c_int32, C.c_int32,
                                C.c_double, _vp, _vp]),
@@ -256,6 +257,12 @@ class Member:
         cp = None if cache_path is None else str(cache_path).encode()
         self._check(self._lib.fps_autotune(self.h_, cp, C.byref(rows), C.byref(ms)))
         return rows.value, ms.value
+
+    def time_flood(self, reps=200):
+        """Average ms per flood-update launch (back-to-back launches, state unchanged)."""
+        ms = C.c_double()
+        self._check(self._lib.fps_time_flood(self.h_, int(reps), C.byref(ms)))
+        return ms.value
 
     def set_rows_per_wave(self, rows):
         return self._check(self._lib.fps_set_rows_per_wave(self.h_, int(rows)))

@@ -109,3 +109,24 @@ def test_hazard_field_definition():
     with np.errstate(divide="ignore", invalid="ignore"):
         ref = np.where(h > 1e-5, (np.maximum(np.abs(qx / h), np.abs(qy / h)) + 0.5) * h, 0.0)
     assert np.allclose(hz, ref, rtol=1e-6, atol=1e-7)
+
+
+def test_time_flood_leaves_the_state_unchanged():
+    sc = I.shopping_centre(n=128, dx=0.5, seed=9, n_evac=300)
+    a, b = fps.Sim(sc), fps.Sim(sc)
+    a.step(40)
+    b.step(40)
+    before = a.fields()
+    ms = a.time_flood(25)
+    say(f"flood update 128^2: {ms * 1e3:.1f} us per launch")
+    assert ms > 0
+    for x, y in zip(before, a.fields()):
+        assert np.array_equal(x, y)
+    assert a.diag()["dt_next"] == b.diag()["dt_next"]
+    a.step(30)
+    b.step(30)
+    for x, y in zip(a.fields(), b.fields()):
+        assert np.array_equal(x, y)
+    A, B = a.agents(), b.agents()
+    for k in A:
+        assert np.array_equal(A[k], B[k])
