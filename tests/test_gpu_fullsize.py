@@ -1,0 +1,158 @@
+"""Parity at the full sizes of the benchmark workloads, in the launch
+configuration the benchmark times (autotuned tiles, graph-captured steps):
+checks on sampled outputs the oracle computes one by one, or properties that
+hold at any size.
+
+* 512^2 shopping centre with 2,000 evacuees: after 2,000 graph-replayed steps
+  one coupled step matches the FP64 oracle from the GPU's state; bins and
+  per-cell counts are bit-exact; the volume budget closes.
+* the 64-scenario intervention sweep: three members (one of each grid size)
+  equal their solo runs bit for bit; every member closes its volume budget.
+* the surrogate at 8 x 256^2: sampled output pixels equal the oracle network
+  evaluated on the 11 x 11 receptive field of each pixel.
+* the learned update on 2048^2 grids with 50,000 people: the assisted
+  ensemble with every block rejected equals the plain finite-volume
+  ensemble; the judge's count at full size equals the oracle judge."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import surrogate_oracle as S
+from paper_1908_05232_amd import fps, inputs as I, surrogate as SG
+from tests.gpu_util import say, snapshot
+
+pytestmark = pytest.mark.gpu
+
+
+def budget_ok(d, rel=1e-5):
+    budget = d["v_in"] - d["v_out"] + d["v_clip"]
+    return abs(d["mass"] - budget) <= rel * max(d["v_in"], 1e-9), budget
+
+
+def test_shopping_centre_512_bench_configuration(oracle):
+    sc = I.shopping_centre(n=512)
+    sim = fps.Sim(sc)
+    rows, _ = sim.autotune()
+    sim.step(2000)                       # graph replays, as timed
+    ok, budget = budget_ok(sim.diag())
+    assert ok, (sim.diag()["mass"], budget)
+    start, d0 = snapshot(sim, sc)
+    ref = oracle.OracleSim(start)
+    ref.S.t = d0["t"]
+    assert np.array_equal(sim.counts().cpu().numpy().reshape(-1), ref.np_)
+    sim.step(1)
+    dt = sim.diag()["dt_last"]
+    ref.coupled_step(dt)
+    h = sim.fields()[0]
+    dh = float(np.abs(h - ref.fields()[0]).max())
+    A = sim.agents()
+    act = start.agents["state"] != 1
+    dpos = max(np.abs(A["x"] - ref.x)[act].max(), np.abs(A["y"] - ref.y)[act].max())
+    say(f"512^2 after 2000 steps (H = {rows}): t {d0['t']:.2f} s, one step max|dh| {dh:.2e}, max|dpos| {dpos:.2e}")
+    assert dh <= 1e-4 and dpos <= 1e-4
+
+
+def test_intervention_sweep_members_equal_solo_runs():
+    scs = I.intervention_sweep(64, workers=8)
+    ens = fps.Ensemble(scs)
+    ens.autotune()
+    ens.step(120)
+    for k, m in enumerate(ens.members):
+        ok, budget = budget_ok(m.diag())
+        assert ok, (k, m.diag()["mass"], budget)
+    picked = {}
+    for k, sc in enumerate(scs):
+        picked.setdefault(sc.desc.nx, k)
+    for n, k in sorted(picked.items()):
+        solo = fps.Sim(scs[k])            # its own tile shape: results do not depend on it
+        solo.step(120)
+        for x, y in zip(ens[k].fields(), solo.fields()):
+            assert np.array_equal(x, y), (k, n)
+        A, B = ens[k].agents(), solo.agents()
+        for key in A:
+            assert np.array_equal(A[key], B[key]), (k, key)
+        say(f"sweep member {k} ({n}^2, {len(A['x'])} agents): identical to its solo run")
+
+
+def _receptive_forward(params, x_img, i, j):
+    """Oracle output at pixel (i, j) of one image: the network on the 11 x 11
+    neighbourhood (zero outside the image), read at its centre."""
+    H, W, _ = x_img.shape
+    crop = np.zeros((11, 11, x_img.shape[2]))
+    for a in range(11):
+        for b in range(11):
+            y, x = i + a - 5, j + b - 5
+            if 0 <= y < H and 0 <= x < W:
+                crop[a, b] = x_img[y, x]
+    # layers see zero padding at the image edge, not at the crop edge: mask
+    # every intermediate activation outside the image back to zero
+    inside = np.zeros((11, 11, 1))
+    for a in range(11):
+        for b in range(11):
+            inside[a, b, 0] = 0 <= i + a - 5 < H and 0 <= j + b - 5 < W
+    act = crop[None]
+    for li, (w, bb) in enumerate(params):
+        z = S.conv3x3(act, w, bb)
+        act = S.bf16_round(np.maximum(z, 0.0)) * inside if li < len(params) - 1 else z
+    return act[0, 5, 5]
+
+
+def test_surrogate_forward_sampled_pixels_at_training_size():
+    n, H, W = 8, 256, 256
+    sur = fps.Surrogate(n, H, W)
+    vec = SG.init_params(7)
+    rng = np.random.default_rng(7)
+    vec = vec + (rng.normal(0, 0.02, vec.shape) * (vec != 0)).astype(np.float32)
+    sur.set_params(torch.tensor(vec).cuda())
+    # oracle parameters: the BF16 copies the kernels use, the 3 real outputs
+    params, o = [], 0
+    for cin, cout in SG.LAYERS:
+        wn = cout * 9 * cin
+        w = S.bf16_round(vec[o:o + wn].reshape(cout, 3, 3, cin).astype(np.float64))
+        o += wn
+        b = vec[o:o + cout].astype(np.float64)
+        o += cout
+        if cout == 16:
+            w, b = w[:3], b[:3]
+        params.append((w, b))
+    x = np.zeros((n, H, W, 16), np.float32)
+    x[..., :6] = rng.uniform(-1, 1, (n, H, W, 6))
+    xt = torch.tensor(x).bfloat16().cuda()
+    xb = xt.float().cpu().numpy().astype(np.float64)
+    y = sur.forward(xt).cpu().numpy()
+    pix = [(0, 0, 0), (1, 255, 255), (2, 0, 131), (3, 77, 0), (4, 128, 64), (5, 200, 201), (6, 15, 240),
+           (7, 250, 3)] + [(int(a), int(b), int(c)) for a, b, c in zip(rng.integers(0, n, 8),
+                                                                    rng.integers(0, H, 8), rng.integers(0, W, 8))]
+    worst = 0.0
+    for (k, i, j) in pix:
+        want = _receptive_forward(params, xb[k], i, j)
+        got = y[k, i, j, :3]
+        err = float(np.abs(got - want).max() / max(np.abs(want).max(), 1e-3))
+        worst = max(worst, err)
+    say(f"surrogate 8x256^2: worst relative error over {len(pix)} sampled pixels {worst:.2e}")
+    assert worst <= 1e-2
+
+
+def test_learned_update_full_size_fallback_and_judge():
+    cases = [SG.flood_case(500000 + k, n=2048, n_evac=50000, barrier_height=0.3 + 0.2 * k) for k in range(3)]
+    params = torch.tensor(SG.init_params(1)).cuda()
+    A = SG.AssistedEnsemble(cases, params, chunk=1, stride=250, tol=-1.0)   # every block rejected
+    plain, _ = SG._flood_ensemble(cases)
+    for _ in range(2):
+        assert not A.block().any()
+    plain.step(2 * SG.K_STEPS)
+    for k in range(len(cases)):
+        for a, b in zip(SG._state(A.E[k]), SG._state(plain[k])):
+            assert torch.equal(a, b), k
+    # the judge at full size against the oracle judge on host copies
+    d = cases[0].sc.desc
+    cr = A.crowds[0].t
+    us = tuple(t.clone() for t in SG._state(A.E[0]))
+    us[0].add_(torch.where(us[0] > 0, 0.004, 0.0) * (torch.rand_like(us[0]) < 0.3))
+    out = fps.judge_result(fps.sur_judge(cr["x"], cr["y"], cr["state"], d.nx, d.ny, d.dx, d.dy, us,
+                                         SG._state(plain[0]), tol=0.003, stride=1))
+    host = lambda t: tuple(a.cpu().numpy() for a in t)
+    want = S.judge(cr["x"].cpu().numpy(), cr["y"].cpu().numpy(), cr["state"].cpu().numpy(), d.nx, d.ny,
+                   d.dx, d.dy, host(us), host(SG._state(plain[0])), 0.003, d.h_dry, (0.75, 1.5, 2.5))
+    say(f"judge at 2048^2 with 50,000 people: {out} (oracle {want})")
+    assert out[0] == want[0] and out[1] == want[1]
