@@ -427,23 +427,34 @@ __global__ __launch_bounds__(kScanThreads) void finalize_kernel(Batch B, int mod
     __shared__ DevState sst;
     constexpr int kWords = (int)(sizeof(DevState) / sizeof(uint32_t));
     static_assert(sizeof(DevState) % sizeof(uint32_t) == 0, "DevState is copied as words");
+    // every load of the step's end is issued here, before the first barrier
+    // (which waits for them): the state words, and for the LDS binning the
+    // histogram and the agents' keys and positions
+    const bool lds_path = mode == 0 && S.na > 0 && S.lds_bins;
+    LdsBinRegs lr;
+    if (lds_path) lds_bins_prefetch(S.bins, lr);
     for (int w = threadIdx.x; w < kWords; w += kScanThreads)
         reinterpret_cast<uint32_t*>(&sst)[w] = reinterpret_cast<const uint32_t*>(gst)[w];
+    // the flood partials (read whether or not the update ran; dropped below if not)
+    double m = 0.0, vo = 0.0, vc = 0.0, sm = 0.0;
+    for (int b = threadIdx.x; b < p.ntiles; b += kScanThreads) {
+        m += p.partials[4 * b + 0];
+        vo += p.partials[4 * b + 1];
+        vc += p.partials[4 * b + 2];
+        sm = fmax(sm, p.partials[4 * b + 3]);
+    }
     __syncthreads();
     DevState* st = &sst;
     const bool skipped = mode == 0 && flood_skipped(st);
+    if (skipped) {
+        m = 0.0;
+        vo = 0.0;
+        vc = 0.0;
+        sm = 0.0;
+    }
     // the pedestrians of this step have read the wetness flags: clear them
     if (threadIdx.x < kWetSlots) p.wet[kWetStride * threadIdx.x] = 0;
     __shared__ double red[kScanThreads / kWave][4];
-    double m = 0.0, vo = 0.0, vc = 0.0, sm = 0.0;
-    if (!skipped) {
-        for (int b = threadIdx.x; b < p.ntiles; b += kScanThreads) {
-            m += p.partials[4 * b + 0];
-            vo += p.partials[4 * b + 1];
-            vc += p.partials[4 * b + 2];
-            sm = fmax(sm, p.partials[4 * b + 3]);
-        }
-    }
     m = wave_sum(m);
     vo = wave_sum(vo);
     vc = wave_sum(vc);
@@ -524,8 +535,8 @@ __global__ __launch_bounds__(kScanThreads) void finalize_kernel(Batch B, int mod
         reinterpret_cast<uint32_t*>(gst)[w] = reinterpret_cast<const uint32_t*>(&sst)[w];
     if (mode == 0 && S.na > 0) {
         const BinParams bp = S.bins;     // by value: not reloaded after the stores below
-        if (S.lds_bins) {
-            bin_place_lds(bp);
+        if (lds_path) {
+            lds_bins_finish(bp, lr);
         } else {
             block_scan_bins(bp);
             if (S.inline_place) {

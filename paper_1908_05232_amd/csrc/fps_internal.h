@@ -27,6 +27,7 @@ constexpr int kMaxHydro = 64;
 constexpr int kMaskBits = 128;         // obstacle bitmask per cell (uint4)
 constexpr int kInlinePlace = 8192;     // agent counts binned inside the one-block finalize
 constexpr int kLdsBinWords = 30 * 1024;  // LDS words for bin starts + placement in the finalize
+constexpr int kLdsScanBins = 16 * kScanThreads;   // bins the LDS binning scans in one pass
 constexpr int kWetSlots = 64;          // wetness flags of a flood update, one per group of blocks
 constexpr int kWetStride = 32;         // ints between flags (one 128-byte line each)
 
@@ -103,6 +104,7 @@ struct PedParams {
     float dx, dy, eps, tau, a_over_m, inv_b, two_r, radius, r_cut, r_arrive;
     float v_class[5], hr_t[3], pick_s, drop_s;
     int storage_dest, barrier_dest;
+    int need_rank;              // record each agent's rank in its bin (the global binning needs it)
 };
 
 // Sandbag barrier of sec. 2.4: the fill order and layer rules.

@@ -333,7 +333,8 @@ __device__ void agent_step(const PedParams& p, const float* __restrict__ fh,
     if (st != FPS_ST_EXITED) {
         int b = (nj / p.bsy) * p.nbx + ni / p.bsx;
         p.key[a] = b;
-        p.rank[a] = atomicAdd(&p.bin_count[b], 1);
+        if (p.need_rank) p.rank[a] = atomicAdd(&p.bin_count[b], 1);
+        else atomicAdd(&p.bin_count[b], 1);   // no return: nothing waits on it
     } else {
         p.key[a] = -1;
     }
