@@ -148,23 +148,41 @@ def surrogate_section(args):
     log("surrogate: large cases built")
     plain, _ = SG._flood_ensemble(big)
     _, t_plain = SG.timed(plain.step, SG.K_STEPS * args.sur_blocks)
-    A = SG.AssistedEnsemble(big, sur.get_params(), chunk=args.sur_chunk, stride=args.sur_stride)
-    t0 = time.perf_counter()
-    for b in range(args.sur_blocks):
-        A.block()
-        log(f"surrogate: assisted block {b + 1}/{args.sur_blocks} {A.stats}")
-    torch.cuda.synchronize()
-    t_assist = time.perf_counter() - t0
-    # agreement at every person after the run
-    worst, bad, people = 0.0, 0, 0
-    for k in range(len(big)):
-        cr = A.crowds[k].t
-        d = big[k].sc.desc
-        r = fps.judge_result(fps.sur_judge(cr["x"], cr["y"], cr["state"], d.nx, d.ny, d.dx, d.dy,
-                                           SG._state(A.E[k]), SG._state(plain[k]), tol=0.01))
-        bad += r[0]
-        worst = max(worst, r[1])
-        people += len(big[k].agents["x"])
+    params = sur.get_params()
+
+    def assisted_run(stride):
+        A = SG.AssistedEnsemble(big, params, chunk=args.sur_chunk, stride=stride)
+        t0 = time.perf_counter()
+        for b in range(args.sur_blocks):
+            A.block()
+            log(f"surrogate: stride {stride}, assisted block {b + 1}/{args.sur_blocks} {A.stats}")
+        torch.cuda.synchronize()
+        t_assist = time.perf_counter() - t0
+        # agreement at every person after the run
+        worst, bad, people = 0.0, 0, 0
+        for k in range(len(big)):
+            cr = A.crowds[k].t
+            d = big[k].sc.desc
+            r = fps.judge_result(fps.sur_judge(cr["x"], cr["y"], cr["state"], d.nx, d.ny, d.dx, d.dy,
+                                               SG._state(A.E[k]), SG._state(plain[k]), tol=0.01))
+            bad += r[0]
+            worst = max(worst, r[1])
+            people += len(big[k].agents["x"])
+        return A, t_assist, bad, worst, people
+
+    strides = [int(v) for v in str(args.sur_strides).split(",") if v]
+    runs = []
+    for st in strides[1:]:
+        A, ta, bad, worst, people = assisted_run(st)
+        runs.append({"judge_stride": st, "judged_cell_fraction": A.stats["judged_fraction"], "assisted_s": ta,
+                     "ratio_assisted_over_fv": t_plain / ta, "blocks_accepted": A.stats["accepted"],
+                     "blocks_fallback": A.stats["fallback"], "people_off_by_more_than_1cm_or_class": bad,
+                     "max_dh_m": worst})
+        A.E.close(); A.J.close()
+        del A
+        torch.cuda.empty_cache()
+    args.sur_stride = strides[0]
+    A, t_assist, bad, worst, people = assisted_run(strides[0])
     # forward throughput alone (one chunk)
     x = torch.zeros((args.sur_chunk, args.sur_big_n, args.sur_big_n, 16), dtype=torch.bfloat16, device="cuda")
     sur_big = A.sur
@@ -188,7 +206,8 @@ def surrogate_section(args):
             "blocks_accepted": A.stats["accepted"], "blocks_fallback": A.stats["fallback"],
             "judge_stride": args.sur_stride, "judged_cell_fraction": A.stats["judged_fraction"],
             "people_off_by_more_than_1cm_or_class": bad, "people": people, "max_dh_m": worst,
-            "forward_TFLOPs": 230400 * px / t_fwd / 1e12, "forward_ms_per_chunk": t_fwd * 1e3},
+            "forward_TFLOPs": 230400 * px / t_fwd / 1e12, "forward_ms_per_chunk": t_fwd * 1e3,
+            "other_judge_strides": runs},
         "section_s": time.perf_counter() - t_all,
     }
     A.E.close(); A.J.close(); plain.close()
@@ -267,7 +286,8 @@ def main():
     ap.add_argument("--sur-big-people", type=int, default=50000)
     ap.add_argument("--sur-blocks", type=int, default=10)
     ap.add_argument("--sur-chunk", type=int, default=4)
-    ap.add_argument("--sur-stride", type=int, default=250)
+    ap.add_argument("--sur-strides", default="250,50,10",
+                    help="judge every k-th person; the first value is the headline run, the others are reported too")
     ap.add_argument("--sur-probe", choices=["all", "forward"], default=None,
                     help="only time the surrogate kernels (profiler runs) and exit")
     ap.add_argument("--copy-probe", action="store_true",
