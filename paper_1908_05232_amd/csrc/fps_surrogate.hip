@@ -39,7 +39,10 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int TH = 8, TW = 32;     // pixel tile of one weight-gradient block
 constexpr int CTH = 16;            // rows of the output tile of one convolution block (x TW columns)
-constexpr int kMtPerWave = 8;      // 16-pixel M tiles per wave in the convolution (4 rows x 2)
+constexpr int kMtPerWave = 4;      // 16-pixel M tiles per wave in the convolution (2 rows x 2)
+constexpr int kConvThreads = 512;  // 8 waves, two per SIMD: one computes while the other waits
+constexpr int kWgThreads = 512;    // weight gradient: 8 waves as well
+constexpr int kWgWaves = kWgThreads / 64;
 constexpr int kThreads = 256;
 constexpr int kLayers = 5;
 constexpr int kCin[kLayers] = {16, 64, 64, 64, 64};
@@ -60,11 +63,11 @@ __device__ __forceinline__ float to_f32(bf16 b) { return (float)b; }
 // Persistent blocks, one per CU: the weights are staged in LDS once, then
 // the block walks CTH x TW output tiles; while the matrix cores work on one
 // tile, the next tile's input (with halo) is already loading into registers
-// and is written to LDS after the tile.  Each wave holds 8 M tiles (4 rows of
-// 32 pixels) x COUT/16 N tiles of accumulators.
+// and is written to LDS after the tile.  Eight waves (two per SIMD), each
+// holding 4 M tiles (2 rows of 32 pixels) x COUT/16 N tiles of accumulators.
 // ----------------------------------------------------------------------------
 template <int CIN, int COUT, int MODE>
-__global__ __launch_bounds__(kThreads) void conv_kernel(const bf16* __restrict__ X,
+__global__ __launch_bounds__(kConvThreads) void conv_kernel(const bf16* __restrict__ X,
                                                         const bf16* __restrict__ Wt,
                                                         const float* __restrict__ bias,
                                                         void* __restrict__ Y, int N, int H, int W,
@@ -76,7 +79,7 @@ __global__ __launch_bounds__(kThreads) void conv_kernel(const bf16* __restrict__
     constexpr int NT = COUT / 16;
     constexpr int MT = kMtPerWave;
     constexpr int CHUNKS = (CTH + 2) * (TW + 2) * (CIN / 8);
-    constexpr int XPT = (CHUNKS + kThreads - 1) / kThreads;
+    constexpr int XPT = (CHUNKS + kConvThreads - 1) / kConvThreads;
     constexpr int WCH = COUT * (KP / 8);
     extern __shared__ __align__(16) unsigned char smem[];
     bf16* xin = reinterpret_cast<bf16*>(smem);                        // [(CTH+2)(TW+2)][PIX]
@@ -92,7 +95,7 @@ __global__ __launch_bounds__(kThreads) void conv_kernel(const bf16* __restrict__
         const bf16* Xn = X + (size_t)n * H * W * CIN;
 #pragma unroll
         for (int u = 0; u < XPT; ++u) {
-            const int q = threadIdx.x + u * kThreads;
+            const int q = threadIdx.x + u * kConvThreads;
             xb[u] = bf16x8{};
             if (q < CHUNKS) {
                 const int px = q / (CIN / 8), c8 = (q % (CIN / 8)) * 8;
@@ -105,7 +108,7 @@ __global__ __launch_bounds__(kThreads) void conv_kernel(const bf16* __restrict__
     auto deposit = [&]() {
 #pragma unroll
         for (int u = 0; u < XPT; ++u) {
-            const int q = threadIdx.x + u * kThreads;
+            const int q = threadIdx.x + u * kConvThreads;
             if (q < CHUNKS) {
                 const int px = q / (CIN / 8), c8 = (q % (CIN / 8)) * 8;
                 *reinterpret_cast<bf16x8*>(xin + px * PIX + c8) = xb[u];
@@ -117,7 +120,7 @@ __global__ __launch_bounds__(kThreads) void conv_kernel(const bf16* __restrict__
     if (t >= ntiles) return;
     fetch(t);
     // the weights [COUT][KP], once per block
-    for (int q = threadIdx.x; q < WCH; q += kThreads) {
+    for (int q = threadIdx.x; q < WCH; q += kConvThreads) {
         const int co = q / (KP / 8), k8 = (q % (KP / 8)) * 8;
         *reinterpret_cast<bf16x8*>(wl + co * WST + k8) = *reinterpret_cast<const bf16x8*>(Wt + (size_t)co * KP + k8);
     }
@@ -145,8 +148,8 @@ __global__ __launch_bounds__(kThreads) void conv_kernel(const bf16* __restrict__
             bf16x8 a[MT], b[NT];
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) {
-                // M tile mt: local row 4*wave + mt/2, columns 16*(mt%2) + row16
-                const int ly = 4 * wave + (mt >> 1) + dy;
+                // M tile mt: local row 2*wave + mt/2, columns 16*(mt%2) + row16
+                const int ly = 2 * wave + (mt >> 1) + dy;
                 const int lx = 16 * (mt & 1) + row16 + dx;
                 a[mt] = valid ? *reinterpret_cast<const bf16x8*>(xin + (ly * (TW + 2) + lx) * PIX + c)
                               : bf16x8{};
@@ -164,7 +167,7 @@ __global__ __launch_bounds__(kThreads) void conv_kernel(const bf16* __restrict__
         // D tile: lane holds rows (pixels) 4*kgrp + r, column (channel) row16
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
-            const int gy = y0 + 4 * wave + (mt >> 1);
+            const int gy = y0 + 2 * wave + (mt >> 1);
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
                 const int co = 16 * nt + row16;
@@ -197,14 +200,14 @@ __global__ __launch_bounds__(kThreads) void conv_kernel(const bf16* __restrict__
 // weight gradient: per-block partials of dW[co][tap][ci] over pixel tiles
 // ----------------------------------------------------------------------------
 template <int CIN, int COUT>
-__global__ __launch_bounds__(kThreads) void wgrad_kernel(const bf16* __restrict__ X,
+__global__ __launch_bounds__(kWgThreads) void wgrad_kernel(const bf16* __restrict__ X,
                                                          const bf16* __restrict__ DZ,
                                                          float* __restrict__ part, float* __restrict__ bpart,
                                                          int N, int H, int W)
 {
     constexpr int MT = COUT / 16, NTAP = CIN / 16;     // N tiles per tap
     constexpr int TILES = MT * 9 * NTAP;               // 16x16 output tiles
-    constexpr int PER_WAVE = (TILES + 3) / 4;
+    constexpr int PER_WAVE = (TILES + kWgWaves - 1) / kWgWaves;
     constexpr int XROW = TW;                           // transposed x tile row length
     extern __shared__ __align__(16) unsigned char smem[];
     bf16* dzT = reinterpret_cast<bf16*>(smem);          // [COUT][TH*TW]
@@ -215,9 +218,9 @@ __global__ __launch_bounds__(kThreads) void wgrad_kernel(const bf16* __restrict_
     f32x4 acc[PER_WAVE];
 #pragma unroll
     for (int k = 0; k < PER_WAVE; ++k) acc[k] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    // bias gradient: this thread always stages the same 8 channels (kThreads is
+    // bias gradient: this thread always stages the same 8 channels (kWgThreads is
     // a multiple of COUT / 8), so it sums them as it goes
-    static_assert(kThreads % (COUT / 8) == 0, "fixed channel group per thread");
+    static_assert(kWgThreads % (COUT / 8) == 0, "fixed channel group per thread");
     float bsum[8] = {};
 
     const int tiles_x = W / TW, tiles_y = H / TH, per_img = tiles_x * tiles_y;
@@ -227,18 +230,18 @@ __global__ __launch_bounds__(kThreads) void wgrad_kernel(const bf16* __restrict_
         __syncthreads();
         // dz tile transposed: dzT[co][p], p = row * TW + col (loads first, then the stores)
         constexpr int DCH = TH * TW * (COUT / 8);
-        static_assert(DCH % kThreads == 0, "whole dz chunks per thread");
-        bf16x8 dv[DCH / kThreads];
+        static_assert(DCH % kWgThreads == 0, "whole dz chunks per thread");
+        bf16x8 dv[DCH / kWgThreads];
 #pragma unroll
-        for (int u = 0; u < DCH / kThreads; ++u) {
-            const int q = threadIdx.x + u * kThreads;
+        for (int u = 0; u < DCH / kWgThreads; ++u) {
+            const int q = threadIdx.x + u * kWgThreads;
             const int p = q / (COUT / 8), c8 = (q % (COUT / 8)) * 8;
             const int gy = y0 + p / TW, gx = x0 + p % TW;
             dv[u] = *reinterpret_cast<const bf16x8*>(DZ + (((size_t)n * H + gy) * W + gx) * COUT + c8);
         }
 #pragma unroll
-        for (int u = 0; u < DCH / kThreads; ++u) {
-            const int q = threadIdx.x + u * kThreads;
+        for (int u = 0; u < DCH / kWgThreads; ++u) {
+            const int q = threadIdx.x + u * kWgThreads;
             const int p = q / (COUT / 8), c8 = (q % (COUT / 8)) * 8;
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
@@ -250,11 +253,11 @@ __global__ __launch_bounds__(kThreads) void wgrad_kernel(const bf16* __restrict_
             __syncthreads();
             // x tile for this column offset, transposed: xT[ci][ly][col] = x[y0+ly-1][x0+col+dx-1][ci]
             constexpr int XCH = (TH + 2) * XROW * (CIN / 8);
-            constexpr int XPT = (XCH + kThreads - 1) / kThreads;
+            constexpr int XPT = (XCH + kWgThreads - 1) / kWgThreads;
             bf16x8 xv[XPT];
 #pragma unroll
             for (int u = 0; u < XPT; ++u) {
-                const int q = threadIdx.x + u * kThreads;
+                const int q = threadIdx.x + u * kWgThreads;
                 xv[u] = bf16x8{};
                 if (q < XCH) {
                     const int px = q / (CIN / 8), c8 = (q % (CIN / 8)) * 8;
@@ -265,7 +268,7 @@ __global__ __launch_bounds__(kThreads) void wgrad_kernel(const bf16* __restrict_
             }
 #pragma unroll
             for (int u = 0; u < XPT; ++u) {
-                const int q = threadIdx.x + u * kThreads;
+                const int q = threadIdx.x + u * kWgThreads;
                 if (q < XCH) {
                     const int px = q / (CIN / 8), c8 = (q % (CIN / 8)) * 8;
                     const int ly = px / XROW, col = px % XROW;
@@ -276,7 +279,7 @@ __global__ __launch_bounds__(kThreads) void wgrad_kernel(const bf16* __restrict_
             __syncthreads();
 #pragma unroll
             for (int k = 0; k < PER_WAVE; ++k) {
-                const int tl = wave + 4 * k;
+                const int tl = wave + kWgWaves * k;
                 if (tl >= TILES) break;
                 const int mt = tl / (9 * NTAP), rest = tl % (9 * NTAP);
                 const int tap = rest / NTAP, ci0 = (rest % NTAP) * 16;
@@ -302,14 +305,14 @@ __global__ __launch_bounds__(kThreads) void wgrad_kernel(const bf16* __restrict_
     if (threadIdx.x < COUT) {
         const int g = threadIdx.x / 8, e = threadIdx.x % 8;
         float t = 0.0f;
-        for (int th = g; th < kThreads; th += COUT / 8) t += bs[th * 8 + e];
+        for (int th = g; th < kWgThreads; th += COUT / 8) t += bs[th * 8 + e];
         bpart[(size_t)blockIdx.x * COUT + threadIdx.x] = t;
     }
     // partial [block][co][tap][ci]; D tile lane holds rows (co) 4*kgrp + r, column (ci) row16
     float* pb = part + (size_t)blockIdx.x * COUT * 9 * CIN;
 #pragma unroll
     for (int k = 0; k < PER_WAVE; ++k) {
-        const int tl = wave + 4 * k;
+        const int tl = wave + kWgWaves * k;
         if (tl >= TILES) break;
         const int mt = tl / (9 * NTAP), rest = tl % (9 * NTAP);
         const int tap = rest / NTAP, ci0 = (rest % NTAP) * 16;
@@ -679,7 +682,7 @@ int conv(fps_sur* s, int n, const bf16* x, const bf16* w, const float* b, void* 
     SCHK(s, hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     const int tiles = n * (s->H / CTH) * (s->W / TW);
     const int blocks = std::min(tiles, s->cus);          // persistent: one block per compute unit
-    hipLaunchKernelGGL(k, dim3(blocks), dim3(kThreads), lds, s->stream, x, w, b, y, n, s->H, s->W, mask);
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(kConvThreads), lds, s->stream, x, w, b, y, n, s->H, s->W, mask);
     SCHK(s, hipGetLastError());
     return FPS_OK;
 }
@@ -693,7 +696,7 @@ int wgrad(fps_sur* s, int n, const bf16* x, const bf16* dz, int layer)
     SCHK(s, hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     const int tiles = n * (s->H / TH) * (s->W / TW);
     const int blocks = std::min(tiles, kWgradBlocks);
-    hipLaunchKernelGGL(k, dim3(blocks), dim3(kThreads), lds, s->stream, x, dz, s->wpart, s->bpart, n, s->H,
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(kWgThreads), lds, s->stream, x, dz, s->wpart, s->bpart, n, s->H,
                        s->W);
     SCHK(s, hipGetLastError());
     const int count = COUT * 9 * CIN;
