@@ -218,8 +218,8 @@ __global__ __launch_bounds__(kWgThreads) void wgrad_kernel(const bf16* __restric
     f32x4 acc[PER_WAVE];
 #pragma unroll
     for (int k = 0; k < PER_WAVE; ++k) acc[k] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    // bias gradient: this thread always stages the same 8 channels (kWgThreads is
-    // a multiple of COUT / 8), so it sums them as it goes
+    // bias gradient: a thread always stages the same 8 channels (channel group
+    // threadIdx.x % (COUT / 8)), so it sums them as it goes
     static_assert(kWgThreads % (COUT / 8) == 0, "fixed channel group per thread");
     float bsum[8] = {};
 
@@ -228,52 +228,56 @@ __global__ __launch_bounds__(kWgThreads) void wgrad_kernel(const bf16* __restric
         const int n = tile / per_img, t = tile % per_img;
         const int y0 = (t / tiles_x) * TH, x0 = (t % tiles_x) * TW;
         __syncthreads();
-        // dz tile transposed: dzT[co][p], p = row * TW + col (loads first, then the stores)
-        constexpr int DCH = TH * TW * (COUT / 8);
-        static_assert(DCH % kWgThreads == 0, "whole dz chunks per thread");
-        bf16x8 dv[DCH / kWgThreads];
+        // dz tile transposed: dzT[co][p], p = row * TW + col.  A thread takes
+        // an 8-pixel x 8-channel block: eight 16-byte loads, an 8 x 8
+        // transpose in registers, eight 16-byte LDS stores.  Pixel blocks are
+        // XOR-swizzled by the channel group (the MFMA reads use the same map)
+        // so that the stores of neighbouring channel groups hit other banks.
+        constexpr int NCG = COUT / 8, NPG = TH * TW / 8;
+        static_assert(NCG * NPG <= kWgThreads, "one dz block per thread");
+        if (threadIdx.x < NCG * NPG) {
+            const int cg = threadIdx.x % NCG, pg = threadIdx.x / NCG;
+            const int gy = y0 + (8 * pg) / TW, gx = x0 + (8 * pg) % TW;
+            const bf16* src = DZ + (((size_t)n * H + gy) * W + gx) * COUT + 8 * cg;
+            bf16x8 v[8];
 #pragma unroll
-        for (int u = 0; u < DCH / kWgThreads; ++u) {
-            const int q = threadIdx.x + u * kWgThreads;
-            const int p = q / (COUT / 8), c8 = (q % (COUT / 8)) * 8;
-            const int gy = y0 + p / TW, gx = x0 + p % TW;
-            dv[u] = *reinterpret_cast<const bf16x8*>(DZ + (((size_t)n * H + gy) * W + gx) * COUT + c8);
-        }
-#pragma unroll
-        for (int u = 0; u < DCH / kWgThreads; ++u) {
-            const int q = threadIdx.x + u * kWgThreads;
-            const int p = q / (COUT / 8), c8 = (q % (COUT / 8)) * 8;
+            for (int q = 0; q < 8; ++q) v[q] = *reinterpret_cast<const bf16x8*>(src + (size_t)q * COUT);
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-                dzT[(c8 + e) * (TH * TW) + p] = dv[u][e];
-                bsum[e] += to_f32(dv[u][e]);
+                bf16x8 t;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    t[q] = v[q][e];
+                    bsum[e] += to_f32(v[q][e]);
+                }
+                *reinterpret_cast<bf16x8*>(dzT + (8 * cg + e) * (TH * TW) + 8 * (pg ^ (cg & 7))) = t;
             }
         }
         for (int dx = 0; dx < 3; ++dx) {
             __syncthreads();
-            // x tile for this column offset, transposed: xT[ci][ly][col] = x[y0+ly-1][x0+col+dx-1][ci]
-            constexpr int XCH = (TH + 2) * XROW * (CIN / 8);
-            constexpr int XPT = (XCH + kWgThreads - 1) / kWgThreads;
-            bf16x8 xv[XPT];
+            // x tile for this column offset, transposed: xT[ci][ly][col] = x[y0+ly-1][x0+col+dx-1][ci],
+            // in 8-column x 8-channel blocks as above (column blocks swizzled by the channel group)
+            constexpr int NCI = CIN / 8, NXB = (TH + 2) * (XROW / 8);
+            static_assert(NCI * NXB <= kWgThreads, "one x block per thread");
+            if (threadIdx.x < NCI * NXB) {
+                const int cg = threadIdx.x % NCI, xb = threadIdx.x / NCI;
+                const int ly = xb / (XROW / 8), cb = xb % (XROW / 8);
+                const int gy = y0 + ly - 1, gx0 = x0 + 8 * cb + dx - 1;
+                bf16x8 v[8];
 #pragma unroll
-            for (int u = 0; u < XPT; ++u) {
-                const int q = threadIdx.x + u * kWgThreads;
-                xv[u] = bf16x8{};
-                if (q < XCH) {
-                    const int px = q / (CIN / 8), c8 = (q % (CIN / 8)) * 8;
-                    const int gy = y0 + px / XROW - 1, gx = x0 + px % XROW + dx - 1;
+                for (int q = 0; q < 8; ++q) {
+                    const int gx = gx0 + q;
+                    v[q] = bf16x8{};
                     if (gy >= 0 && gy < H && gx >= 0 && gx < W)
-                        xv[u] = *reinterpret_cast<const bf16x8*>(X + (((size_t)n * H + gy) * W + gx) * CIN + c8);
+                        v[q] = *reinterpret_cast<const bf16x8*>(X + (((size_t)n * H + gy) * W + gx) * CIN + 8 * cg);
                 }
-            }
 #pragma unroll
-            for (int u = 0; u < XPT; ++u) {
-                const int q = threadIdx.x + u * kWgThreads;
-                if (q < XCH) {
-                    const int px = q / (CIN / 8), c8 = (q % (CIN / 8)) * 8;
-                    const int ly = px / XROW, col = px % XROW;
+                for (int e = 0; e < 8; ++e) {
+                    bf16x8 t;
 #pragma unroll
-                    for (int e = 0; e < 8; ++e) xT[(c8 + e) * ((TH + 2) * XROW) + ly * XROW + col] = xv[u][e];
+                    for (int q = 0; q < 8; ++q) t[q] = v[q][e];
+                    *reinterpret_cast<bf16x8*>(xT + (8 * cg + e) * ((TH + 2) * XROW) + ly * XROW +
+                                               8 * (cb ^ (cg & (XROW / 8 - 1)))) = t;
                 }
             }
             __syncthreads();
@@ -287,10 +291,11 @@ __global__ __launch_bounds__(kWgThreads) void wgrad_kernel(const bf16* __restric
                 const int dy = tap / 3;
                 const int co = 16 * mt + row16, ci = ci0 + row16;
                 for (int r = 0; r < TH; ++r) {
-                    // k-slab: pixels of tile row r, lane's 8 columns 8*kgrp..
-                    const bf16x8 a = *reinterpret_cast<const bf16x8*>(dzT + co * (TH * TW) + r * TW + 8 * kgrp);
+                    // k-slab: pixels of tile row r, the lane's 8 columns 8*kgrp.. (swizzled blocks)
+                    const bf16x8 a = *reinterpret_cast<const bf16x8*>(
+                        dzT + co * (TH * TW) + 8 * ((r * (TW / 8) + kgrp) ^ ((co / 8) & 7)));
                     const bf16x8 b = *reinterpret_cast<const bf16x8*>(
-                        xT + ci * ((TH + 2) * XROW) + (r + dy) * XROW + 8 * kgrp);
+                        xT + ci * ((TH + 2) * XROW) + (r + dy) * XROW + 8 * (kgrp ^ ((ci / 8) & (XROW / 8 - 1))));
                     acc[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[k], 0, 0, 0);
                 }
             }
