@@ -345,7 +345,7 @@ void fill_scn(const fps_sim* s, Scn& c)
     c.inline_place = s->na <= kInlinePlace;
     c.lds_bins = c.inline_place && s->na > 0 && s->nbins <= kLdsScanBins &&
                  (int64_t)s->nbins + 1 + s->na <= kLdsBinWords;
-    c.ped.need_rank = !c.lds_bins;       // the LDS binning places agents by LDS atomics
+    c.ped.need_rank = !c.lds_bins;       // the LDS binning counts the keys itself
 }
 
 void drop_graph(Engine* e)

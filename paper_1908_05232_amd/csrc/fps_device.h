@@ -171,63 +171,61 @@ __device__ inline void sort_agent(const BinParams& b, int a)
 }
 
 // One-block binning in LDS for small grids (nbins <= 16 * kScanThreads, at
-// most kInlinePlace agents; dynamic shared memory of nbins + 1 + na words).
-// The loads it needs (the histogram, sixteen bins per thread, and the
-// agents' keys and new positions) are issued at the start of the end-of-step
-// kernel together with its other loads; then the exclusive scan, the
-// placement by LDS atomics and the stable order by id run in LDS, and only
-// the results are stored.  Same results as the global binning.
-struct LdsBinRegs {
-    static constexpr int APT = kInlinePlace / kScanThreads;
-    int hist[16];
-    int key[APT];
-    float ax[APT], ay[APT];
-};
-
-__device__ inline void lds_bins_prefetch(const BinParams& b, LdsBinRegs& r)
+// most kInlinePlace agents; dynamic shared memory of nbins + 1 + na words),
+// run by a block of its own beside the end-of-step state update.  It starts
+// from the agents' bin keys alone: a histogram by LDS atomics, the exclusive
+// scan (sixteen bins per thread, the wave by shuffles, the waves in LDS), the
+// placement by LDS atomics and the stable order by id; only the results are
+// stored.  Being a function of the keys, it gives the same bins however often
+// it runs on them (a scenario that did not step keeps its bins).  Same results
+// as the global binning.
+__device__ inline void lds_bins_build(const BinParams& b)
 {
-    const int k0 = 16 * threadIdx.x;
-    if (k0 + 16 <= b.nbins) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int4 w = *reinterpret_cast<const int4*>(b.bin_count + k0 + 4 * q);
-            r.hist[4 * q] = w.x; r.hist[4 * q + 1] = w.y; r.hist[4 * q + 2] = w.z; r.hist[4 * q + 3] = w.w;
-        }
-    } else {
-#pragma unroll
-        for (int e = 0; e < 16; ++e) r.hist[e] = k0 + e < b.nbins ? b.bin_count[k0 + e] : 0;
-    }
-#pragma unroll
-    for (int q = 0; q < LdsBinRegs::APT; ++q) {
-        const int a = threadIdx.x + q * kScanThreads;
-        r.key[q] = -1;
-        if (a < b.na) {
-            r.key[q] = b.key[a];
-            r.ax[q] = b.x[a];
-            r.ay[q] = b.y[a];
-        }
-    }
-}
-
-__device__ inline void lds_bins_finish(const BinParams& b, const LdsBinRegs& r)
-{
+    constexpr int APT = kInlinePlace / kScanThreads;
     extern __shared__ int4 fin_lds4[];
-    int* lb = reinterpret_cast<int*>(fin_lds4);    // [nbins + 1]: bin starts, then bin ends
+    int* lb = reinterpret_cast<int*>(fin_lds4);    // [nbins + 1]: counts, then starts, then ends
     int* lp = lb + b.nbins + 1;                    // [na]: agents by bin, unordered
     __shared__ int wtot[kScanThreads / kWave];
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x >> 6;
     const int k0 = 16 * threadIdx.x;
-    // clear the histogram for the next step
-    if (k0 + 16 <= b.nbins) {
+    const bool full = k0 + 16 <= b.nbins;
+    int key[APT];
+    float ax[APT], ay[APT];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) *reinterpret_cast<int4*>(b.bin_count + k0 + 4 * q) = make_int4(0, 0, 0, 0);
-    } else {
-        for (int e = 0; e < 16 && k0 + e < b.nbins; ++e) b.bin_count[k0 + e] = 0;
+    for (int q = 0; q < APT; ++q) {
+        const int a = threadIdx.x + q * kScanThreads;
+        key[q] = -1;
+        if (a < b.na) {
+            key[q] = b.key[a];
+            ax[q] = b.x[a];
+            ay[q] = b.y[a];
+        }
     }
-    // exclusive scan: sixteen bins per thread, the wave by shuffles, the waves in LDS
+    if (full) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) reinterpret_cast<int4*>(lb + k0)[q] = make_int4(0, 0, 0, 0);
+    } else {
+        for (int e = k0; e < b.nbins; ++e) lb[e] = 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < APT; ++q)
+        if (key[q] >= 0) atomicAdd(&lb[key[q]], 1);
+    __syncthreads();
+    int hist[16];
+    if (full) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int4 w = reinterpret_cast<const int4*>(lb + k0)[q];
+            hist[4 * q] = w.x; hist[4 * q + 1] = w.y; hist[4 * q + 2] = w.z; hist[4 * q + 3] = w.w;
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) hist[e] = k0 + e < b.nbins ? lb[k0 + e] : 0;
+    }
     int tsum = 0;
 #pragma unroll
-    for (int e = 0; e < 16; ++e) tsum += r.hist[e];
+    for (int e = 0; e < 16; ++e) tsum += hist[e];
     int incl = tsum;
     for (int o = 1; o < kWave; o <<= 1) {
         const int u = __shfl_up(incl, o, kWave);
@@ -240,22 +238,22 @@ __device__ inline void lds_bins_finish(const BinParams& b, const LdsBinRegs& r)
         run += w < wid ? wtot[w] : 0;
         total += wtot[w];
     }
-    if (k0 + 16 <= b.nbins) {
+    if (full) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             int4 w;
-            w.x = run; run += r.hist[4 * q];
-            w.y = run; run += r.hist[4 * q + 1];
-            w.z = run; run += r.hist[4 * q + 2];
-            w.w = run; run += r.hist[4 * q + 3];
-            *reinterpret_cast<int4*>(b.bin_start + k0 + 4 * q) = w;
-            *reinterpret_cast<int4*>(lb + k0 + 4 * q) = w;
+            w.x = run; run += hist[4 * q];
+            w.y = run; run += hist[4 * q + 1];
+            w.z = run; run += hist[4 * q + 2];
+            w.w = run; run += hist[4 * q + 3];
+            reinterpret_cast<int4*>(b.bin_start + k0)[q] = w;
+            reinterpret_cast<int4*>(lb + k0)[q] = w;
         }
     } else {
         for (int e = 0; e < 16 && k0 + e < b.nbins; ++e) {
             b.bin_start[k0 + e] = run;
             lb[k0 + e] = run;
-            run += r.hist[e];
+            run += hist[e];
         }
     }
     if (threadIdx.x == 0) {
@@ -266,13 +264,13 @@ __device__ inline void lds_bins_finish(const BinParams& b, const LdsBinRegs& r)
     // unordered placement: each agent takes the next free slot of its bin;
     // afterwards lb[k] is the end of bin k (= start of bin k + 1)
 #pragma unroll
-    for (int q = 0; q < LdsBinRegs::APT; ++q)
-        if (r.key[q] >= 0) lp[atomicAdd(&lb[r.key[q]], 1)] = threadIdx.x + q * kScanThreads;
+    for (int q = 0; q < APT; ++q)
+        if (key[q] >= 0) lp[atomicAdd(&lb[key[q]], 1)] = threadIdx.x + q * kScanThreads;
     __syncthreads();
     // stable order: an agent's slot counts the smaller ids of its bin
 #pragma unroll
-    for (int q = 0; q < LdsBinRegs::APT; ++q) {
-        const int k = r.key[q];
+    for (int q = 0; q < APT; ++q) {
+        const int k = key[q];
         if (k < 0) continue;
         const int a = threadIdx.x + q * kScanThreads;
         const int s0 = k > 0 ? lb[k - 1] : 0, s1 = lb[k];
@@ -281,7 +279,7 @@ __device__ inline void lds_bins_finish(const BinParams& b, const LdsBinRegs& r)
         const int f = s0 + below;
         b.perm[f] = a;
         b.slot[a] = f;
-        b.xy[f] = make_float2(r.ax[q], r.ay[q]);
+        b.xy[f] = make_float2(ax[q], ay[q]);
     }
 }
 

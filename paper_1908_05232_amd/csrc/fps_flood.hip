@@ -408,43 +408,128 @@ __global__ __launch_bounds__(kFvBlock) void fv_scan_kernel(Batch B, int sc)
     }
 }
 
-// End of a step, one block of kScanThreads per scenario: reduce the flood
-// partials in a fixed order, advance time, set the next CFL time step (sec. 3)
-// and inflow depth; apply the sandbag drops of the step to the barrier line
-// (sec. 2.4); scan the histogram of the new agent bins (and, for small agent
-// counts, place the agents in bin order).  mode 0 ends a step, mode 1 only
-// recomputes the time step and mass of the current state.
+__device__ __forceinline__ double readlane_f64(double v, int l)
+{
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// Exact integral over [a, b] of the piecewise-linear hydrograph (sec. 3.1),
+// on one wave whose lane k holds knot k (tk, qk) for k < nh: lane k takes the
+// part of [a, b] in [t_k, t_k+1] by the trapezoid rule (exact on a linear
+// piece), lane 0 the constant part before the first knot, lane nh - 1 the
+// constant part after the last; the pieces are added in time order.  Every
+// lane returns the total.
+__device__ double wave_hydro_integral(int nh, double tk, double qk, double a, double b)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const double tn = __shfl_down(tk, 1, kWave), qn = __shfl_down(qk, 1, kWave);
+    if (nh <= 0 || !(b > a)) return 0.0;
+    double piece = 0.0, before = 0.0, after = 0.0;
+    if (lane + 1 < nh) {
+        const double lo = fmax(a, tk), hi = fmin(b, tn);
+        if (hi > lo) {
+            const double ql = qk + ((lo - tk) / (tn - tk)) * (qn - qk);
+            const double qh = qk + ((hi - tk) / (tn - tk)) * (qn - qk);
+            piece = 0.5 * (ql + qh) * (hi - lo);
+        }
+    }
+    if (lane == 0 && a < tk) before = qk * (fmin(b, tk) - a);
+    if (lane == nh - 1 && b > tk) after = qk * (b - fmax(a, tk));
+    double total = readlane_f64(before, 0);
+    for (unsigned long long m = __ballot(piece != 0.0); m; m &= m - 1)
+        total += readlane_f64(piece, __builtin_ctzll(m));
+    return total + readlane_f64(after, nh - 1);
+}
+
+// End of a step: blocks (scenario, 0) update the state, blocks (scenario, 1)
+// rebuild the neighbour bins of scenarios binned in LDS; the two run side by
+// side (they share no data).  The state update reduces the flood partials in
+// a fixed order, advances time, sets the next CFL time step (sec. 3) and
+// inflow depth, applies the sandbag drops of the step to the barrier line
+// (sec. 2.4) and, for scenarios binned in global memory, scans the histogram
+// of the new agent bins (and, for small agent counts, places the agents in bin
+// order).  Mode 1 only recomputes the time step and mass of the current state.
 __global__ __launch_bounds__(kScanThreads) void finalize_kernel(Batch B, int mode, int s_first)
 {
     const int sc = s_first + blockIdx.x;
     const Scn& S = B.scn[sc];
+    if (blockIdx.y == 1) {
+        if (S.lds_bins && S.na > 0) lds_bins_build(S.bins);
+        return;
+    }
+    // the parameters used, in registers: loaded in the first round, not
+    // reloaded after the stores below
     const FvParams& p = S.fv;
     DevState* gst = p.st;
-    if (mode == 0 && !gst->active) return;
+    const double* partials = p.partials;
+    int32_t* wet = p.wet;
+    const int ntiles = p.ntiles, n_inflow = p.n_inflow, inflow_side = p.inflow_side;
+    const double dxdy = p.dxdy;
+    const float cfl = p.cfl, dt_max = p.dt_max, dn = inflow_side <= 1 ? p.dx : p.dy;
+    const bool jmask = p.jmask != nullptr;
+    const int na = S.na, inline_place = S.inline_place, lds_bins = S.lds_bins, nline = S.bar.nline;
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x >> 6;
     // The scenario's state words go through LDS: one cooperative load, the
-    // serial end-of-step logic on the copy, one cooperative store.  (Nothing
-    // else touches them while this kernel runs.)
+    // serial end-of-step logic on the copy, one cooperative store.  Nothing
+    // else touches them while this block runs.  The hydrograph knots stay out
+    // of the copy (they do not change): the first wave holds them in
+    // registers, one knot per lane.
     __shared__ DevState sst;
     constexpr int kWords = (int)(sizeof(DevState) / sizeof(uint32_t));
+    constexpr int kHyd0 = (int)(offsetof(DevState, hyd_t) / sizeof(uint32_t));
+    constexpr int kHyd1 = (int)(offsetof(DevState, step) / sizeof(uint32_t));
+    constexpr int kCopy = kHyd0 + kWords - kHyd1;
     static_assert(sizeof(DevState) % sizeof(uint32_t) == 0, "DevState is copied as words");
-    // every load of the step's end is issued here, before the first barrier
-    // (which waits for them): the state words, and for the LDS binning the
-    // histogram and the agents' keys and positions
-    const bool lds_path = mode == 0 && S.na > 0 && S.lds_bins;
-    LdsBinRegs lr;
-    if (lds_path) lds_bins_prefetch(S.bins, lr);
-    for (int w = threadIdx.x; w < kWords; w += kScanThreads)
-        reinterpret_cast<uint32_t*>(&sst)[w] = reinterpret_cast<const uint32_t*>(gst)[w];
-    // the flood partials (read whether or not the update ran; dropped below if not)
+    static_assert(offsetof(DevState, hyd_q) == offsetof(DevState, hyd_t) + sizeof(double) * kMaxHydro &&
+                  offsetof(DevState, step) == offsetof(DevState, hyd_q) + sizeof(double) * kMaxHydro,
+                  "the hydrograph knots are one run of words");
+    static_assert(kCopy <= kScanThreads && kMaxHydro <= kWave, "one word per thread, one knot per lane");
+    // every load of the block is issued before the first barrier
+    const int cw = threadIdx.x < kHyd0 ? (int)threadIdx.x : (int)threadIdx.x - kHyd0 + kHyd1;
+    if (threadIdx.x < kCopy)
+        reinterpret_cast<uint32_t*>(&sst)[cw] = reinterpret_cast<const uint32_t*>(gst)[cw];
+    double hk_t = 0.0, hk_q = 0.0;
+    if (wid == 0) {
+        hk_t = gst->hyd_t[lane];
+        hk_q = gst->hyd_q[lane];
+    }
+    // the flood partials, four per thread in one round of loads, summed in
+    // tile order (read whether or not the update ran; dropped below if not)
     double m = 0.0, vo = 0.0, vc = 0.0, sm = 0.0;
-    for (int b = threadIdx.x; b < p.ntiles; b += kScanThreads) {
-        m += p.partials[4 * b + 0];
-        vo += p.partials[4 * b + 1];
-        vc += p.partials[4 * b + 2];
-        sm = fmax(sm, p.partials[4 * b + 3]);
+    {
+        constexpr int kPU = 4;
+        const double2* P2 = reinterpret_cast<const double2*>(partials);
+        double2 a[kPU], c[kPU];
+#pragma unroll
+        for (int u = 0; u < kPU; ++u) {
+            const int b = threadIdx.x + u * kScanThreads;
+            a[u] = make_double2(0.0, 0.0);
+            c[u] = make_double2(0.0, 0.0);
+            if (b < ntiles) {
+                a[u] = P2[2 * b];
+                c[u] = P2[2 * b + 1];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kPU; ++u) {
+            m += a[u].x;
+            vo += a[u].y;
+            vc += c[u].x;
+            sm = fmax(sm, c[u].y);
+        }
+        for (int b = threadIdx.x + kPU * kScanThreads; b < ntiles; b += kScanThreads) {
+            m += partials[4 * b + 0];
+            vo += partials[4 * b + 1];
+            vc += partials[4 * b + 2];
+            sm = fmax(sm, partials[4 * b + 3]);
+        }
     }
     __syncthreads();
     DevState* st = &sst;
+    if (mode == 0 && !st->active) return;     // the whole block: one LDS word
     const bool skipped = mode == 0 && flood_skipped(st);
     if (skipped) {
         m = 0.0;
@@ -453,97 +538,113 @@ __global__ __launch_bounds__(kScanThreads) void finalize_kernel(Batch B, int mod
         sm = 0.0;
     }
     // the pedestrians of this step have read the wetness flags: clear them
-    if (threadIdx.x < kWetSlots) p.wet[kWetStride * threadIdx.x] = 0;
+    if (threadIdx.x < kWetSlots) wet[kWetStride * threadIdx.x] = 0;
     __shared__ double red[kScanThreads / kWave][4];
     m = wave_sum(m);
     vo = wave_sum(vo);
     vc = wave_sum(vc);
     for (int o = 32; o > 0; o >>= 1) sm = fmax(sm, __shfl_xor(sm, o, kWave));
-    if ((threadIdx.x & (kWave - 1)) == 0) {
-        int w = threadIdx.x >> 6;
-        red[w][0] = m;
-        red[w][1] = vo;
-        red[w][2] = vc;
-        red[w][3] = sm;
+    if (lane == 0) {
+        red[wid][0] = m;
+        red[wid][1] = vo;
+        red[wid][2] = vc;
+        red[wid][3] = sm;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int w = 1; w < kScanThreads / kWave; ++w) {
-            red[0][0] += red[w][0];
-            red[0][1] += red[w][1];
-            red[0][2] += red[w][2];
-            red[0][3] = fmax(red[0][3], red[w][3]);
+    if (wid == 0) {
+        // the serial end of the step, on every lane of the first wave (same
+        // values); lane 0 stores
+        // lanes 0-3 combine one quantity each over the waves, in wave order
+        double acc = 0.0;
+        if (lane < 4) {
+            acc = red[0][lane];
+            for (int w = 1; w < kScanThreads / kWave; ++w)
+                acc = lane == 3 ? fmax(acc, red[w][lane]) : acc + red[w][lane];
         }
+        const double M = readlane_f64(acc, 0), VO = readlane_f64(acc, 1), VC = readlane_f64(acc, 2),
+                     SM = readlane_f64(acc, 3);
+        double t = st->t, v_out = st->v_out, v_clip = st->v_clip, v_in = st->v_in, mass = st->mass;
+        int64_t step = st->step;
+        float dt = st->dt, dt_prev = st->dt_prev;
+        int cur = st->cur, flood_steps = st->flood_steps, settled = st->settled, any_wet = st->any_wet;
+        int status = st->status;
         if (mode == 0) {
-            float dt_used = st->dt;
-            st->t += (double)dt_used;
-            st->step += 1;
-            st->dt_prev = dt_used;
+            t += (double)dt;
+            step += 1;
+            dt_prev = dt;
             if (!skipped) {
-                st->v_out += red[0][1];
-                st->v_clip += red[0][2] * p.dxdy;
-                st->v_in += (double)st->inc * (double)p.n_inflow * p.dxdy;
-                st->cur ^= 1;
-                st->flood_steps += 1;
-                st->settled = 1;
+                v_out += VO;
+                v_clip += VC * dxdy;
+                v_in += (double)st->inc * (double)n_inflow * dxdy;
+                cur ^= 1;
+                flood_steps += 1;
+                settled = 1;
             }
         }
         if (!skipped) {
-            float smax = (float)red[0][3];
-            st->mass = red[0][0] * p.dxdy;
-            st->any_wet = smax > 0.0f;
-            st->dt = st->any_wet && !p.jmask ? fminf(p.cfl / smax, p.dt_max) : p.dt_max;
+            const float smax = (float)SM;
+            mass = M * dxdy;
+            any_wet = smax > 0.0f;
+            dt = any_wet && !jmask ? fminf(cfl / smax, dt_max) : dt_max;
         }
-        float dtn = st->dt;
         float inc = 0.0f;
-        if (p.inflow_side >= 0) {
-            double dn = p.inflow_side <= 1 ? (double)p.dx : (double)p.dy;
-            inc = (float)(hydro_integral(st, st->t, st->t + (double)dtn) / dn);
-        }
-        st->inc = inc;
-        if (!isfinite(st->mass) || !(dtn > 0.0f) || !isfinite(dtn)) st->status = FPS_E_NUMERIC;
-        // sandbag write-back: drops of this step applied to the barrier line in order
-        const BarrierParams& Bb = S.bar;
-        if (mode == 0 && S.na > 0) {
-            int D = st->drops;
-            st->drops = 0;
-            st->drops_total += D;
-            if (!st->done && Bb.nline > 0) {
-                int bags = st->bags + D;
-                int cell = st->active_cell, layers = st->layers_done, fin = 0;
-                while (!fin && bags >= Bb.bags_per) {
-                    bags -= Bb.bags_per;
-                    float th = layers == Bb.n_layers - 1 ? Bb.t_last : Bb.t_bag;
-                    Bb.z[Bb.line[cell]] += th;
-                    cell += 1;
-                    if (cell == Bb.nline) {
-                        cell = 0;
-                        layers += 1;
-                        if (layers >= Bb.n_layers) fin = 1;
+        if (inflow_side >= 0)
+            inc = (float)(wave_hydro_integral(st->nh, hk_t, hk_q, t, t + (double)dt) / (double)dn);
+        if (!isfinite(mass) || !(dt > 0.0f) || !isfinite(dt)) status = FPS_E_NUMERIC;
+        if (lane == 0) {
+            st->t = t;
+            st->step = step;
+            st->dt_prev = dt_prev;
+            st->v_out = v_out;
+            st->v_clip = v_clip;
+            st->v_in = v_in;
+            st->cur = cur;
+            st->flood_steps = flood_steps;
+            st->settled = settled;
+            st->mass = mass;
+            st->any_wet = any_wet;
+            st->dt = dt;
+            st->inc = inc;
+            st->status = status;
+            // sandbag write-back: drops of this step applied to the barrier line in order
+            if (mode == 0 && na > 0) {
+                const int D = st->drops;
+                st->drops = 0;
+                st->drops_total += D;
+                if (!st->done && nline > 0) {
+                    const BarrierParams& Bb = S.bar;     // read only while a barrier is built
+                    int bags = st->bags + D;
+                    int cell = st->active_cell, layers = st->layers_done, fin = 0;
+                    while (!fin && bags >= Bb.bags_per) {
+                        bags -= Bb.bags_per;
+                        const float th = layers == Bb.n_layers - 1 ? Bb.t_last : Bb.t_bag;
+                        Bb.z[Bb.line[cell]] += th;
+                        cell += 1;
+                        if (cell == Bb.nline) {
+                            cell = 0;
+                            layers += 1;
+                            if (layers >= Bb.n_layers) fin = 1;
+                        }
                     }
+                    st->bags = bags;
+                    st->active_cell = cell;
+                    st->layers_done = layers;
+                    st->done = fin;
                 }
-                st->bags = bags;
-                st->active_cell = cell;
-                st->layers_done = layers;
-                st->done = fin;
             }
+            if (mode == 0) st->active = !(st->t_end > 0.0) || t < st->t_end;
         }
-        if (mode == 0) st->active = !(st->t_end > 0.0) || st->t < st->t_end;
     }
     __syncthreads();
-    for (int w = threadIdx.x; w < kWords; w += kScanThreads)
-        reinterpret_cast<uint32_t*>(gst)[w] = reinterpret_cast<const uint32_t*>(&sst)[w];
-    if (mode == 0 && S.na > 0) {
-        const BinParams bp = S.bins;     // by value: not reloaded after the stores below
-        if (lds_path) {
-            lds_bins_finish(bp, lr);
-        } else {
-            block_scan_bins(bp);
-            if (S.inline_place) {
-                for (int a = threadIdx.x; a < bp.na; a += kScanThreads) place_agent(bp, a);
-                __syncthreads();
-                for (int a = threadIdx.x; a < bp.na; a += kScanThreads) sort_agent(bp, a);
-            }
+    if (threadIdx.x < kCopy)
+        reinterpret_cast<uint32_t*>(gst)[cw] = reinterpret_cast<const uint32_t*>(&sst)[cw];
+    if (mode == 0 && na > 0 && !lds_bins) {
+        const BinParams bp = S.bins;
+        block_scan_bins(bp);
+        if (inline_place) {
+            for (int a = threadIdx.x; a < bp.na; a += kScanThreads) place_agent(bp, a);
+            __syncthreads();
+            for (int a = threadIdx.x; a < bp.na; a += kScanThreads) sort_agent(bp, a);
         }
     }
 }
@@ -616,8 +717,10 @@ hipError_t prepare_finalize(int lds_bytes)
 
 hipError_t launch_finalize(const Batch& b, int mode, int s_first, int count, hipStream_t s)
 {
-    const int lds = mode == 0 ? b.fin_lds_bytes : 0;
-    hipLaunchKernelGGL(finalize_kernel, dim3(count), dim3(kScanThreads), lds, s, b, mode, s_first);
+    // the binning blocks only where some scenario is binned in LDS
+    const bool bins = mode == 0 && b.fin_lds_bytes > 0;
+    hipLaunchKernelGGL(finalize_kernel, dim3(count, bins ? 2 : 1), dim3(kScanThreads), bins ? b.fin_lds_bytes : 0, s,
+                       b, mode, s_first);
     return hipGetLastError();
 }
 

@@ -22,6 +22,8 @@ constexpr int kWave = 64;
 constexpr int kStrip = kWave - 2;      // output columns of one wave in the flood march
 constexpr int kFvBlock = 256;          // 4 waves
 constexpr int kPedBlock = 64;
+constexpr int kPedLanes = 8;           // lanes per agent in the pedestrian step
+constexpr int kPedAgents = kWave / kPedLanes;   // agents per pedestrian-step wave
 constexpr int kScanThreads = 1024;
 constexpr int kMaxHydro = 64;
 constexpr int kMaskBits = 128;         // obstacle bitmask per cell (uint4)
@@ -104,7 +106,7 @@ struct PedParams {
     float dx, dy, eps, tau, a_over_m, inv_b, two_r, radius, r_cut, r_arrive;
     float v_class[5], hr_t[3], pick_s, drop_s;
     int storage_dest, barrier_dest;
-    int need_rank;              // record each agent's rank in its bin (the global binning needs it)
+    int need_rank;              // histogram + each agent's rank in its bin (the global binning needs them)
 };
 
 // Sandbag barrier of sec. 2.4: the fill order and layer rules.

@@ -1,10 +1,11 @@
 // Pedestrian step and neighbour binning on gfx950 (sec. 2.3-2.4, Table 1).
 //
-// One lane per agent.  Each agent reads the flood state of the navigation
-// cell that contains it, takes its hazard class and walking speed (Table 1,
-// HR = (max(|u|,|v|) + 0.5) h), follows its destination's distance field, is
-// repelled by neighbours found in the 3x3 bins around it and by obstacle
-// cells, and moves.  Evacuee counts per cell (the N_p of the roughness rule)
+// Eight lanes per agent: they share its neighbour and obstacle loops, and do
+// the rest of its work in step.  Each agent reads the flood state of the
+// navigation cell that contains it, takes its hazard class and walking speed
+// (Table 1, HR = (max(|u|,|v|) + 0.5) h), follows its destination's distance
+// field, is repelled by neighbours found in the 3x3 bins around it and by
+// obstacle cells, and moves.  Evacuee counts per cell (the N_p of the roughness rule)
 // are kept by integer atomics on the old and new cells; responders deliver
 // sandbags that the last block applies to the barrier line in order.
 //
@@ -57,26 +58,52 @@ __device__ __forceinline__ int nearest_exit(const PedParams& p, int ci, int cj)
 
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// One agent, one step.  The loads are grouped in three dependent rounds: the
-// agent record; everything addressed by its cell (flood state, the nine
-// distances of its destination field, the obstacle mask, the bin bounds of
-// the three bin rows); then the neighbours' positions.  Cell and bin indices
-// use IEEE division so they match the FP32 decisions of the reference exactly.
+// Repulsion of one neighbour or obstacle point at offset (rx, ry) from the
+// agent: A/m exp((r0 - d)/B) along the unit offset, zero outside (0, r_cut).
+__device__ __forceinline__ void repel(const PedParams& p, float rx, float ry, float r0, float& fx, float& fy)
+{
+    const float d = __builtin_amdgcn_sqrtf(rx * rx + ry * ry);
+    if (!(d > 0.0f) || !(d < p.r_cut)) return;
+    const float w = p.a_over_m * __expf((r0 - d) * p.inv_b) * rcp(d);
+    fx += w * rx;
+    fy += w * ry;
+}
+
+// Sum over the kPedLanes lanes of an agent's group; every lane of the group
+// gets the same bits (each butterfly level adds the same two values, in
+// either order).
+__device__ __forceinline__ float group_sum(float v)
+{
+#pragma unroll
+    for (int o = 1; o < kPedLanes; o <<= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// One agent, one step, on the kPedLanes lanes of its group (q = lane in the
+// group).  Every lane evaluates the agent's own state; the lanes share the
+// neighbour and obstacle loops and the group sum combines their forces; lane
+// 0 stores.  The loads come in dependent rounds: the agent record; everything
+// addressed by its cell (flood state, the nine distances of its destination
+// field, the obstacle mask, the bin bounds of the three bin rows); the
+// neighbours' positions; the cells of the move.  Cell and bin indices use IEEE
+// division so they match the FP32 decisions of the reference exactly.
 __device__ void agent_step(const PedParams& p, const float* __restrict__ fh,
-                           const float* __restrict__ fqx, const float* __restrict__ fqy, int a,
+                           const float* __restrict__ fqx, const float* __restrict__ fqy, int a, int q,
                            float dt, int any_wet, int done, int& drop)
 {
+    const bool lead = q == 0;
+    // round 1: the whole record (in bounds whatever the state)
     const int st0 = p.state[a];
-    if (st0 == FPS_ST_EXITED) {
-        p.key[a] = -1;
-        return;
-    }
     const float x = p.x[a], y = p.y[a];
     float vx = p.vx[a], vy = p.vy[a];
     const int role = p.role[a];
     int dest = p.dest[a];
     const float vbase = p.vbase[a];
     const int self = p.slot[a];
+    if (st0 == FPS_ST_EXITED) {
+        if (lead) p.key[a] = -1;
+        return;
+    }
     const int ci = clampi(cell_of(x, p.dx, p.nx), 0, p.nx - 1);
     const int cj = clampi(cell_of(y, p.dy, p.ny), 0, p.ny - 1);
     const size_t c = (size_t)cj * p.nx + ci;
@@ -113,7 +140,7 @@ __device__ void agent_step(const PedParams& p, const float* __restrict__ fh,
            : cls == FPS_CLS_MEDIUM ? p.v_class[FPS_CLS_MEDIUM]
            : cls == FPS_CLS_HIGH ? p.v_class[FPS_CLS_HIGH] : p.v_class[FPS_CLS_HIGHEST];
     }
-    p.cls[a] = (uint8_t)cls;
+    if (lead) p.cls[a] = (uint8_t)cls;
     int st = st0;
     if (dest < 0) {
         if (role == FPS_ROLE_EVACUEE) {
@@ -132,7 +159,7 @@ __device__ void agent_step(const PedParams& p, const float* __restrict__ fh,
     bool moving = true;
     if (st == FPS_ST_PICKING || st == FPS_ST_DROPPING) {
         float tm = p.timer[a] - dt;
-        p.timer[a] = tm;
+        if (lead) p.timer[a] = tm;
         if (tm > 0.0f) {
             moving = false;
         } else if (st == FPS_ST_PICKING) {
@@ -197,69 +224,57 @@ __device__ void agent_step(const PedParams& p, const float* __restrict__ fh,
         float k = __expf(-dt / p.tau);
         vx = v0 * ex + (vx - v0 * ex) * k;
         vy = v0 * ey + (vy - v0 * ey) * k;
-        // repulsion: neighbours in the 3x3 bins, in (bin, id) order; the three
-        // bins of one bin row are one contiguous run of the sorted positions
+        // repulsion from the neighbours in the 3x3 bins: the three bins of one
+        // bin row are one contiguous run of the sorted positions; the runs of
+        // the three rows are numbered one after the other and the lanes of the
+        // group take every kPedLanes-th entry, two loads at a time
         float fx = 0.0f, fy = 0.0f;
+        const int n0 = seg1[0] - seg0[0], n01 = n0 + seg1[1] - seg0[1];
+        const int ntot = n01 + seg1[2] - seg0[2];
+        for (int k0 = q; k0 < ntot; k0 += 2 * kPedLanes) {
+            int sl[2];
+            float2 o[2];
 #pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            // positions read four at a time (independent loads), summed in order
-            for (int s0 = seg0[r]; s0 < seg1[r]; s0 += 4) {
-                float2 o4[4];
+            for (int u = 0; u < 2; ++u) {
+                const int kk = k0 + u * kPedLanes;
+                sl[u] = kk < n0 ? seg0[0] + kk : kk < n01 ? seg0[1] + (kk - n0) : seg0[2] + (kk - n01);
+                o[u] = kk < ntot ? p.xy[sl[u]] : make_float2(x, y);
+            }
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    o4[u] = s0 + u < seg1[r] ? p.xy[s0 + u] : make_float2(0.0f, 0.0f);
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int s = s0 + u;
-                    if (s >= seg1[r] || s == self) continue;
-                    float rx = x - o4[u].x, ry = y - o4[u].y;
-                    float d = __builtin_amdgcn_sqrtf(rx * rx + ry * ry);
-                    if (!(d > 0.0f) || !(d < p.r_cut)) continue;
-                    float w = p.a_over_m * __expf((p.two_r - d) * p.inv_b) * rcp(d);
-                    fx += w * rx;
-                    fy += w * ry;
-                }
+            for (int u = 0; u < 2; ++u)
+                if (sl[u] != self) repel(p, x - o[u].x, y - o[u].y, p.two_r, fx, fy);
+        }
+        // obstacle cells of the window [-Rx, Rx] x [-Ry, Ry] around the cell,
+        // row-major; the lanes take every kPedLanes-th cell.  Nearest point of
+        // the obstacle cell to the agent.
+        const int wdth = 2 * p.Rx + 1, wcells = wdth * (2 * p.Ry + 1);
+        int col = q, row = 0;
+        while (col >= wdth) {
+            col -= wdth;
+            ++row;
+        }
+        for (int b = q; b < wcells; b += kPedLanes) {
+            const int wi = ci + col - p.Rx, wj = cj + row - p.Ry;
+            bool obst;
+            if (p.use_wmask) {
+                const uint32_t word = b < 32 ? m4.x : b < 64 ? m4.y : b < 96 ? m4.z : m4.w;
+                obst = (word >> (b & 31)) & 1u;
+            } else {
+                obst = wi >= 0 && wj >= 0 && wi < p.nx && wj < p.ny && !p.walk[(size_t)wj * p.nx + wi];
+            }
+            if (obst) {
+                const float px = fminf(fmaxf(x, (float)wi * p.dx), (float)(wi + 1) * p.dx);
+                const float py = fminf(fmaxf(y, (float)wj * p.dy), (float)(wj + 1) * p.dy);
+                repel(p, x - px, y - py, p.radius, fx, fy);
+            }
+            col += kPedLanes;
+            while (col >= wdth) {
+                col -= wdth;
+                ++row;
             }
         }
-        // obstacle cells within r_cut, in row-major offset order
-        if (p.use_wmask) {
-            const uint32_t mw[4] = {m4.x, m4.y, m4.z, m4.w};
-            const int wdth = 2 * p.Rx + 1;
-            for (int w = 0; w < 4; ++w) {
-                uint32_t m = mw[w];
-                while (m) {
-                    const int bit = 32 * w + __builtin_ctz(m);
-                    m &= m - 1;
-                    const int wi = ci + bit % wdth - p.Rx, wj = cj + bit / wdth - p.Ry;
-                    float px = fminf(fmaxf(x, (float)wi * p.dx), (float)(wi + 1) * p.dx);
-                    float py = fminf(fmaxf(y, (float)wj * p.dy), (float)(wj + 1) * p.dy);
-                    float rx = x - px, ry = y - py;
-                    float d = __builtin_amdgcn_sqrtf(rx * rx + ry * ry);
-                    if (!(d > 0.0f) || !(d < p.r_cut)) continue;
-                    float wt = p.a_over_m * __expf((p.radius - d) * p.inv_b) * rcp(d);
-                    fx += wt * rx;
-                    fy += wt * ry;
-                }
-            }
-        } else {
-            for (int dj = -p.Ry; dj <= p.Ry; ++dj) {
-                int wj = cj + dj;
-                if (wj < 0 || wj >= p.ny) continue;
-                for (int di = -p.Rx; di <= p.Rx; ++di) {
-                    int wi = ci + di;
-                    if (wi < 0 || wi >= p.nx) continue;
-                    if (p.walk[(size_t)wj * p.nx + wi]) continue;
-                    float px = fminf(fmaxf(x, (float)wi * p.dx), (float)(wi + 1) * p.dx);
-                    float py = fminf(fmaxf(y, (float)wj * p.dy), (float)(wj + 1) * p.dy);
-                    float rx = x - px, ry = y - py;
-                    float d = __builtin_amdgcn_sqrtf(rx * rx + ry * ry);
-                    if (!(d > 0.0f) || !(d < p.r_cut)) continue;
-                    float wt = p.a_over_m * __expf((p.radius - d) * p.inv_b) * rcp(d);
-                    fx += wt * rx;
-                    fy += wt * ry;
-                }
-            }
-        }
+        fx = group_sum(fx);
+        fy = group_sum(fy);
         vx += dt * fx;
         vy += dt * fy;
         float sp2 = vx * vx + vy * vy;
@@ -306,17 +321,18 @@ __device__ void agent_step(const PedParams& p, const float* __restrict__ fh,
                 st = FPS_ST_EXITED;
             } else if (st == FPS_ST_TO_STORAGE) {
                 st = FPS_ST_PICKING;
-                p.timer[a] = p.pick_s;
+                if (lead) p.timer[a] = p.pick_s;
                 vx = 0.0f;
                 vy = 0.0f;
             } else if (st == FPS_ST_TO_BARRIER) {
                 st = FPS_ST_DROPPING;
-                p.timer[a] = p.drop_s;
+                if (lead) p.timer[a] = p.drop_s;
                 vx = 0.0f;
                 vy = 0.0f;
             }
         }
     }
+    if (!lead) return;
     p.x[a] = xn;
     p.y[a] = yn;
     p.vx[a] = vx;
@@ -329,28 +345,31 @@ __device__ void agent_step(const PedParams& p, const float* __restrict__ fh,
     const bool now = role == FPS_ROLE_EVACUEE && st == FPS_ST_EVAC;
     if (was && !(now && cn == c)) atomicSub(&p.np[c], 1);
     if (now && !(was && cn == c)) atomicAdd(&p.np[cn], 1);
-    // histogram of the new positions
+    // bin key of the new position; the global binning also needs the
+    // histogram and each agent's rank in its bin (the LDS binning counts the
+    // keys itself)
     if (st != FPS_ST_EXITED) {
         int b = (nj / p.bsy) * p.nbx + ni / p.bsx;
         p.key[a] = b;
         if (p.need_rank) p.rank[a] = atomicAdd(&p.bin_count[b], 1);
-        else atomicAdd(&p.bin_count[b], 1);   // no return: nothing waits on it
     } else {
         p.key[a] = -1;
     }
 }
 
-// One wave (= one block) per 64 agents of one scenario: the agent ranges of
-// the scenarios are padded to whole waves in the flattened index.
-__global__ __launch_bounds__(kPedBlock) void ped_step_kernel(Batch B)
+// One wave (= one block) per kPedAgents agents of one scenario: the agent
+// ranges of the scenarios are padded to whole multiples of kWave agents in the
+// flattened index, so no block straddles two scenarios.
+__global__ __launch_bounds__(kWave) void ped_step_kernel(Batch B)
 {
-    const int g0 = blockIdx.x * kPedBlock;
+    const int g0 = blockIdx.x * kPedAgents;
     if (g0 >= B.total_agents) return;
     const int sc = find_scenario(B.agent_off, B.S, g0);
     const Scn& S = B.scn[sc];
     const DevState* st = S.fv.st;
     if (!st->active) return;
-    const int a = g0 - B.agent_off[sc] + (int)threadIdx.x;
+    const int q = (int)threadIdx.x & (kPedLanes - 1);
+    const int a = g0 - B.agent_off[sc] + (int)threadIdx.x / kPedLanes;
     const bool skipped = flood_skipped(st);
     // the flood state this step's pedestrians see: the new one, or the
     // unchanged one when the dry step skipped the flood update
@@ -362,13 +381,13 @@ __global__ __launch_bounds__(kPedBlock) void ped_step_kernel(Batch B)
     const int wet = skipped ? 0 : (__ballot(S.fv.wet[kWetStride * threadIdx.x] != 0) != 0ull);
     int drop = 0, act = 0;
     if (a < S.na) {
-        act = S.ped.state[a] != FPS_ST_EXITED;
+        act = q == 0 && S.ped.state[a] != FPS_ST_EXITED;
         const PedParams P = S.ped;     // by value: not reloaded after the agent's stores
         agent_step(P, fb ? S.fv.h[1] : S.fv.h[0], fb ? S.fv.qx[1] : S.fv.qx[0], fb ? S.fv.qy[1] : S.fv.qy[0],
-                   a, dt, wet, done, drop);
+                   a, q, dt, wet, done, drop);
     }
-    // one wave per block: wave-level counts, one atomic each
-    const unsigned long long drops = __popcll(__ballot(drop));
+    // one wave per block: wave-level counts (lane 0 of each group), one atomic each
+    const unsigned long long drops = __popcll(__ballot(drop && q == 0));
     const unsigned long long active = __popcll(__ballot(act));
     if (threadIdx.x == 0) {
         DevState* stw = S.fv.st;
@@ -510,7 +529,7 @@ inline int blocks_for(int64_t n, int t) { return (int)((n + t - 1) / t); }
 hipError_t launch_ped(const Batch& b, hipStream_t s)
 {
     if (b.total_agents > 0)
-        hipLaunchKernelGGL(ped_step_kernel, dim3(b.total_agents / kPedBlock), dim3(kPedBlock), 0, s, b);
+        hipLaunchKernelGGL(ped_step_kernel, dim3(b.total_agents / kPedAgents), dim3(kWave), 0, s, b);
     return hipGetLastError();
 }
 hipError_t launch_bin_place_all(const Batch& b, hipStream_t s)
