@@ -403,6 +403,7 @@ Batch batch_of(const Engine* e, int s_only = -1)
     b.fin_lds_bytes = e->fin_lds_bytes;
     b.s_only = s_only;
     if (s_only >= 0) b.fv_blocks = fv_blocks_for_tiles(e->scn_h[s_only].fv.ntiles);
+    if (e->S == 1) b.one = e->scn_h[0];
     return b;
 }
 

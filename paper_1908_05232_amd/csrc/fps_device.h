@@ -29,6 +29,16 @@ __device__ __forceinline__ int find_scenario(const int* off, int S, int g)
     return lo;
 }
 
+// The scenario record of a step kernel.  A launch that holds one scenario
+// reads it from its kernel arguments (one round of dependent loads fewer than
+// the device table the ensemble launches read).
+template <bool kOne>
+__device__ __forceinline__ const Scn& scn_at(const Batch& B, int sc)
+{
+    if constexpr (kOne) return B.one;
+    else return B.scn[sc];
+}
+
 // A step whose flood update is the identity and is skipped: nothing is wet,
 // no inflow enters during the step, and the state already came out of a flood
 // update (so dry cells carry no discharge).  The 1 s dry step of sec. 3 then

@@ -170,6 +170,7 @@ __device__ __forceinline__ int xcd_tile_block(int b, int nblocks)
     return (b & 7) * per + (b >> 3);
 }
 
+template <bool kOne>
 __global__ __launch_bounds__(kFvBlock) void fv_step_kernel(Batch B)
 {
     const int lane = threadIdx.x & (kWave - 1);
@@ -177,7 +178,10 @@ __global__ __launch_bounds__(kFvBlock) void fv_step_kernel(Batch B)
     const int g = __builtin_amdgcn_readfirstlane(
         xcd_tile_block(blockIdx.x, B.fv_blocks) * (kFvBlock / kWave) + (int)(threadIdx.x >> 6));
     int sc, tile;
-    if (B.s_only >= 0) {
+    if (kOne) {
+        sc = 0;
+        tile = g;
+    } else if (B.s_only >= 0) {
         sc = B.s_only;
         tile = g;
     } else {
@@ -187,7 +191,7 @@ __global__ __launch_bounds__(kFvBlock) void fv_step_kernel(Batch B)
     }
     // parameters by value: wave-uniform registers, not reloaded after the
     // stores of the march (which the compiler cannot tell apart from them)
-    const FvParams p = B.scn[sc].fv;
+    const FvParams p = scn_at<kOne>(B, sc).fv;
     if (tile >= p.ntiles) return;
     DevState* st = p.st;
     if (!st->active || flood_skipped(st)) return;
@@ -452,10 +456,11 @@ __device__ double wave_hydro_integral(int nh, double tk, double qk, double a, do
 // (sec. 2.4) and, for scenarios binned in global memory, scans the histogram
 // of the new agent bins (and, for small agent counts, places the agents in bin
 // order).  Mode 1 only recomputes the time step and mass of the current state.
+template <bool kOne>
 __global__ __launch_bounds__(kScanThreads) void finalize_kernel(Batch B, int mode, int s_first)
 {
     const int sc = s_first + blockIdx.x;
-    const Scn& S = B.scn[sc];
+    const Scn& S = scn_at<kOne>(B, sc);
     if (blockIdx.y == 1) {
         if (S.lds_bins && S.na > 0) lds_bins_build(S.bins);
         return;
@@ -694,8 +699,10 @@ int fv_blocks_for_tiles(int64_t tiles)
 
 hipError_t launch_fv(const Batch& b, hipStream_t s)
 {
-    if (b.fv_blocks > 0)
-        hipLaunchKernelGGL(fv_step_kernel, dim3(b.fv_blocks), dim3(kFvBlock), 0, s, b);
+    if (b.fv_blocks > 0) {
+        if (b.S == 1) hipLaunchKernelGGL(fv_step_kernel<true>, dim3(b.fv_blocks), dim3(kFvBlock), 0, s, b);
+        else hipLaunchKernelGGL(fv_step_kernel<false>, dim3(b.fv_blocks), dim3(kFvBlock), 0, s, b);
+    }
     return hipGetLastError();
 }
 
@@ -709,8 +716,11 @@ hipError_t prepare_finalize(int lds_bytes)
 {
     static int granted = 0;     // the attribute is per kernel: raise it once to the largest size
     if (lds_bytes <= granted) return hipSuccess;
-    hipError_t e = hipFuncSetAttribute((const void*)finalize_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       lds_bytes);
+    hipError_t e = hipFuncSetAttribute((const void*)finalize_kernel<true>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)finalize_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                lds_bytes);
     if (e == hipSuccess) granted = lds_bytes;
     return e;
 }
@@ -719,8 +729,10 @@ hipError_t launch_finalize(const Batch& b, int mode, int s_first, int count, hip
 {
     // the binning blocks only where some scenario is binned in LDS
     const bool bins = mode == 0 && b.fin_lds_bytes > 0;
-    hipLaunchKernelGGL(finalize_kernel, dim3(count, bins ? 2 : 1), dim3(kScanThreads), bins ? b.fin_lds_bytes : 0, s,
-                       b, mode, s_first);
+    const dim3 grid(count, bins ? 2 : 1);
+    const int lds = bins ? b.fin_lds_bytes : 0;
+    if (b.S == 1) hipLaunchKernelGGL(finalize_kernel<true>, grid, dim3(kScanThreads), lds, s, b, mode, s_first);
+    else hipLaunchKernelGGL(finalize_kernel<false>, grid, dim3(kScanThreads), lds, s, b, mode, s_first);
     return hipGetLastError();
 }
 

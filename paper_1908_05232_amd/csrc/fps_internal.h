@@ -156,6 +156,7 @@ struct Batch {
     int fv_blocks;         // launched flood blocks: a multiple of 8 covering total_tiles
     int fin_lds_bytes;     // dynamic LDS of the finalize launch (LDS binning)
     int s_only;            // >= 0: restrict the flood launch to one scenario (tuning)
+    Scn one;               // S == 1: the scenario itself, read from the kernel arguments
 };
 
 // launchers (stream-ordered, no synchronisation)

@@ -87,19 +87,39 @@ __device__ __forceinline__ float group_sum(float v)
 // field, the obstacle mask, the bin bounds of the three bin rows); the
 // neighbours' positions; the cells of the move.  Cell and bin indices use IEEE
 // division so they match the FP32 decisions of the reference exactly.
-__device__ void agent_step(const PedParams& p, const float* __restrict__ fh,
+// The agent's record, read before anything else of the step.
+struct AgentRec {
+    float x, y, vx, vy, vbase;
+    int state, role, dest, slot;
+};
+
+__device__ __forceinline__ AgentRec load_agent(const PedParams& p, int a)
+{
+    AgentRec r;
+    r.state = p.state[a];
+    r.x = p.x[a];
+    r.y = p.y[a];
+    r.vx = p.vx[a];
+    r.vy = p.vy[a];
+    r.role = p.role[a];
+    r.dest = p.dest[a];
+    r.vbase = p.vbase[a];
+    r.slot = p.slot[a];
+    return r;
+}
+
+__device__ void agent_step(const PedParams& p, const AgentRec& rec, const float* __restrict__ fh,
                            const float* __restrict__ fqx, const float* __restrict__ fqy, int a, int q,
                            float dt, int any_wet, int done, int& drop)
 {
     const bool lead = q == 0;
-    // round 1: the whole record (in bounds whatever the state)
-    const int st0 = p.state[a];
-    const float x = p.x[a], y = p.y[a];
-    float vx = p.vx[a], vy = p.vy[a];
-    const int role = p.role[a];
-    int dest = p.dest[a];
-    const float vbase = p.vbase[a];
-    const int self = p.slot[a];
+    const int st0 = rec.state;
+    const float x = rec.x, y = rec.y;
+    float vx = rec.vx, vy = rec.vy;
+    const int role = rec.role;
+    int dest = rec.dest;
+    const float vbase = rec.vbase;
+    const int self = rec.slot;
     if (st0 == FPS_ST_EXITED) {
         if (lead) p.key[a] = -1;
         return;
@@ -360,16 +380,21 @@ __device__ void agent_step(const PedParams& p, const float* __restrict__ fh,
 // One wave (= one block) per kPedAgents agents of one scenario: the agent
 // ranges of the scenarios are padded to whole multiples of kWave agents in the
 // flattened index, so no block straddles two scenarios.
+template <bool kOne>
 __global__ __launch_bounds__(kWave) void ped_step_kernel(Batch B)
 {
     const int g0 = blockIdx.x * kPedAgents;
     if (g0 >= B.total_agents) return;
-    const int sc = find_scenario(B.agent_off, B.S, g0);
-    const Scn& S = B.scn[sc];
+    const int sc = kOne ? 0 : find_scenario(B.agent_off, B.S, g0);
+    const Scn& S = scn_at<kOne>(B, sc);
+    const int q = (int)threadIdx.x & (kPedLanes - 1);
+    const int a = g0 - (kOne ? 0 : B.agent_off[sc]) + (int)threadIdx.x / kPedLanes;
+    const PedParams P = S.ped;     // by value: not reloaded after the agent's stores
+    // the agent's record in the same round of loads as the scenario's state words
+    AgentRec rec{};
+    if (a < S.na) rec = load_agent(P, a);
     const DevState* st = S.fv.st;
     if (!st->active) return;
-    const int q = (int)threadIdx.x & (kPedLanes - 1);
-    const int a = g0 - B.agent_off[sc] + (int)threadIdx.x / kPedLanes;
     const bool skipped = flood_skipped(st);
     // the flood state this step's pedestrians see: the new one, or the
     // unchanged one when the dry step skipped the flood update
@@ -381,9 +406,8 @@ __global__ __launch_bounds__(kWave) void ped_step_kernel(Batch B)
     const int wet = skipped ? 0 : (__ballot(S.fv.wet[kWetStride * threadIdx.x] != 0) != 0ull);
     int drop = 0, act = 0;
     if (a < S.na) {
-        act = q == 0 && S.ped.state[a] != FPS_ST_EXITED;
-        const PedParams P = S.ped;     // by value: not reloaded after the agent's stores
-        agent_step(P, fb ? S.fv.h[1] : S.fv.h[0], fb ? S.fv.qx[1] : S.fv.qx[0], fb ? S.fv.qy[1] : S.fv.qy[0],
+        act = q == 0 && rec.state != FPS_ST_EXITED;
+        agent_step(P, rec, fb ? S.fv.h[1] : S.fv.h[0], fb ? S.fv.qx[1] : S.fv.qx[0], fb ? S.fv.qy[1] : S.fv.qy[0],
                    a, q, dt, wet, done, drop);
     }
     // one wave per block: wave-level counts (lane 0 of each group), one atomic each
@@ -528,8 +552,11 @@ inline int blocks_for(int64_t n, int t) { return (int)((n + t - 1) / t); }
 
 hipError_t launch_ped(const Batch& b, hipStream_t s)
 {
-    if (b.total_agents > 0)
-        hipLaunchKernelGGL(ped_step_kernel, dim3(b.total_agents / kPedAgents), dim3(kWave), 0, s, b);
+    if (b.total_agents > 0) {
+        const dim3 grid(b.total_agents / kPedAgents);
+        if (b.S == 1) hipLaunchKernelGGL(ped_step_kernel<true>, grid, dim3(kWave), 0, s, b);
+        else hipLaunchKernelGGL(ped_step_kernel<false>, grid, dim3(kWave), 0, s, b);
+    }
     return hipGetLastError();
 }
 hipError_t launch_bin_place_all(const Batch& b, hipStream_t s)
