@@ -38,16 +38,17 @@ def kernel_source_hash():
     return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
 
 
-def measured_traffic(workload, launches_cells):
+def measured_traffic(workload, rows):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current flood kernel source; else None."""
+    was taken on the current flood kernel source at the same tile shape (rows
+    per wave); else None."""
     path = os.path.join(ROOT, "profiles", f"fv_step_counters_{workload}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     if rec.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    return rec.get("hbm_bytes_per_launch")
+    return rec.get("hbm_bytes_per_launch_by_rows", {}).get(str(rows))
 
 
 def cpu_baseline(sc, n_steps):
@@ -267,6 +268,8 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=500)
     ap.add_argument("--cpu-steps", type=int, default=1000)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--rows", type=int, default=0,
+                    help="rows per wave of the flood update on the main workload (0: autotune)")
     ap.add_argument("--probe-n", type=int, default=8192,
                     help="side of the fully wet grid used for the HBM probe (0 = skip)")
     ap.add_argument("--probe-steps", type=int, default=50)
@@ -320,7 +323,11 @@ def main():
     cells = sc.desc.nx * sc.desc.ny
     stream = torch.cuda.current_stream()
     sim = fps.Sim(sc, stream=stream)
-    rows, _ = sim.autotune()          # flood-update tile shape for this grid
+    if args.rows:
+        sim.set_rows_per_wave(args.rows)
+        rows = args.rows
+    else:
+        rows, _ = sim.autotune()      # flood-update tile shape for this grid
     if args.no_graph:
         sim.set_graph(0)
 
@@ -344,7 +351,7 @@ def main():
     # stream the kernels run on (the events' own cost amortised)
     fv_ms = sim.time_flood(args.profile_steps)
     achieved = FV_BYTES_PER_CELL * cells / (fv_ms * 1e-3) / 1e9
-    traffic = measured_traffic(workload, cells)
+    traffic = measured_traffic(workload, rows)
 
     probe = None
     if args.probe_n > 0:
