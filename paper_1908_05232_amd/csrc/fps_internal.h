@@ -22,7 +22,7 @@ constexpr int kWave = 64;
 constexpr int kStrip = kWave - 2;      // output columns of one wave in the flood march
 constexpr int kFvBlock = 256;          // 4 waves
 constexpr int kPedBlock = 64;
-constexpr int kPedLanes = 8;           // lanes per agent in the pedestrian step
+constexpr int kPedLanes = 16;          // lanes per agent in the pedestrian step
 constexpr int kPedAgents = kWave / kPedLanes;   // agents per pedestrian-step wave
 constexpr int kScanThreads = 1024;
 constexpr int kMaxHydro = 64;

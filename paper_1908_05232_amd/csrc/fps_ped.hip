@@ -1,13 +1,14 @@
 // Pedestrian step and neighbour binning on gfx950 (sec. 2.3-2.4, Table 1).
 //
-// Eight lanes per agent: they share its neighbour and obstacle loops, and do
-// the rest of its work in step.  Each agent reads the flood state of the
-// navigation cell that contains it, takes its hazard class and walking speed
-// (Table 1, HR = (max(|u|,|v|) + 0.5) h), follows its destination's distance
-// field, is repelled by neighbours found in the 3x3 bins around it and by
-// obstacle cells, and moves.  Evacuee counts per cell (the N_p of the roughness rule)
-// are kept by integer atomics on the old and new cells; responders deliver
-// sandbags that the last block applies to the barrier line in order.
+// kPedLanes (16) lanes per agent: they share its neighbour and obstacle
+// loops, and do the rest of its work in step.  Each agent reads the flood
+// state of the navigation cell that contains it, takes its hazard class and
+// walking speed (Table 1, HR = (max(|u|,|v|) + 0.5) h), follows its
+// destination's distance field, is repelled by neighbours found in the 3x3
+// bins around it and by obstacle cells, and moves.  Evacuee counts per cell
+// (the N_p of the roughness rule) are kept by integer atomics on the old and
+// new cells; responders deliver sandbags that the end-of-step kernel applies
+// to the barrier line in order.
 //
 // Readings (the paper defers the pedestrian model to Karmakharm et al. 2010
 // and Helbing's social force): exact relaxation v <- v0 e + (v - v0 e)
