@@ -37,16 +37,17 @@ __device__ __forceinline__ float sqrt_fast(float x) { return __builtin_amdgcn_sq
 
 // Whole-wave DPP shifts (a VALU move, no LDS traffic): lane i receives lane
 // i + 1 (wave_shl:1) or lane i - 1 (wave_shr:1); the lane without a source
-// receives 0 (never used: lanes 0 and 63 are halo lanes).
+// receives 0 by the bound control (never used: lanes 0 and 63 are halo
+// lanes), so no old value has to be set first.
 __device__ __forceinline__ float lane_from_above(float v)
 {
     return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
-                                                                 0x130, 0xF, 0xF, false));
+                                                                 0x130, 0xF, 0xF, true));
 }
 __device__ __forceinline__ float lane_from_below(float v)
 {
     return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
-                                                                 0x138, 0xF, 0xF, false));
+                                                                 0x138, 0xF, 0xF, true));
 }
 
 // Cell (i, j) with i in [-1, nx], j in [-1, ny]; a ghost mirrors the adjacent
@@ -114,7 +115,10 @@ __device__ __forceinline__ void face_flux(const FvParams& p, float hL, float unL
                                           bool wall, float& F0, float& F1, float& F2,
                                           float& pL, float& pR)
 {
-    float zf = fmaxf(zL, zR);
+    // max(zL, zR) by compare and select: fmaxf would first quieten the two
+    // raw loaded values (bed elevations are finite, and the result is one of
+    // them either way)
+    float zf = zL > zR ? zL : zR;
     float hl = hL - (zf - zL);
     float hr = hR - (zf - zR);
     hl = hl > p.eps ? hl : 0.0f;
