@@ -22,8 +22,7 @@ constexpr int kWave = 64;
 constexpr int kStrip = kWave - 2;      // output columns of one wave in the flood march
 constexpr int kFvBlock = 256;          // 4 waves
 constexpr int kPedBlock = 64;
-constexpr int kPedLanes = 16;          // lanes per agent in the pedestrian step
-constexpr int kPedAgents = kWave / kPedLanes;   // agents per pedestrian-step wave
+constexpr int kSlots = 16;             // partial sums of an agent's forces (the most lanes per agent)
 constexpr int kScanThreads = 1024;
 constexpr int kMaxHydro = 64;
 constexpr int kMaskBits = 128;         // obstacle bitmask per cell (uint4)
@@ -169,6 +168,7 @@ hipError_t launch_finalize(const Batch& b, int mode, int s_first, int count, hip
 hipError_t prepare_finalize(int lds_bytes);   // host, outside any capture: allow that much dynamic LDS
 hipError_t launch_sync_back(const Batch& b, int64_t max_cells, hipStream_t s);
 hipError_t launch_ped(const Batch& b, hipStream_t s);
+int ped_lanes(int64_t total_agents);     // lanes per agent of the pedestrian step
 hipError_t launch_bin_place_all(const Batch& b, hipStream_t s);
 hipError_t launch_bin_sort_all(const Batch& b, hipStream_t s);
 hipError_t launch_bin_keys(const BinParams& b, hipStream_t s);   // keys + ranks from positions

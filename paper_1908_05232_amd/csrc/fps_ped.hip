@@ -1,7 +1,7 @@
 // Pedestrian step and neighbour binning on gfx950 (sec. 2.3-2.4, Table 1).
 //
-// kPedLanes (16) lanes per agent: they share its neighbour and obstacle
-// loops, and do the rest of its work in step.  Each agent reads the flood
+// 1, 4 or 16 lanes per agent (fewer when there are many agents): they share
+// its neighbour and obstacle loops, and do the rest of its work in step.  Each agent reads the flood
 // state of the navigation cell that contains it, takes its hazard class and
 // walking speed (Table 1, HR = (max(|u|,|v|) + 0.5) h), follows its
 // destination's distance field, is repelled by neighbours found in the 3x3
@@ -23,6 +23,14 @@
 // finds its final slot by counting the smaller ids of its own bin, so the
 // result is deterministic and equal to a stable sort.
 #include "fps_device.h"
+
+// No contraction of a * b + c into fused multiply-adds in this file: the
+// compiler would choose them per instantiation (the kernel is built for 1, 4
+// and 16 lanes per agent, one scenario or many), and the pedestrian dynamics
+// grow a last-bit difference into a different walk within a few steps.  With
+// every multiply and add rounded on its own, every instantiation gives the
+// same bits.
+#pragma clang fp contract(off)
 
 namespace fps {
 namespace {
@@ -70,24 +78,39 @@ __device__ __forceinline__ void repel(const PedParams& p, float rx, float ry, fl
     fy += w * ry;
 }
 
-// Sum over the kPedLanes lanes of an agent's group; every lane of the group
-// gets the same bits (each butterfly level adds the same two values, in
-// either order).
-__device__ __forceinline__ float group_sum(float v)
+// The kSlots partial sums of an agent, slot s = q + jL held by lane q of its
+// group as v[j], added by a butterfly over the slot index (levels 1, 2, 4,
+// 8): across lanes for the levels below L, within the lane above.  Every slot
+// ends with the total, with the same bits for any L (each level adds the same
+// two values).
+template <int L>
+__device__ __forceinline__ float slot_sum(float (&v)[kSlots / L])
 {
+    constexpr int J = kSlots / L;
 #pragma unroll
-    for (int o = 1; o < kPedLanes; o <<= 1) v += __shfl_xor(v, o, kWave);
-    return v;
+    for (int o = 1; o < kSlots; o <<= 1) {
+        if (o < L) {
+#pragma unroll
+            for (int j = 0; j < J; ++j) v[j] += __shfl_xor(v[j], o, kWave);
+        } else {
+            float w[J];
+#pragma unroll
+            for (int j = 0; j < J; ++j) w[j] = v[j] + v[j ^ (o / L)];
+#pragma unroll
+            for (int j = 0; j < J; ++j) v[j] = w[j];
+        }
+    }
+    return v[0];
 }
 
-// One agent, one step, on the kPedLanes lanes of its group (q = lane in the
-// group).  Every lane evaluates the agent's own state; the lanes share the
-// neighbour and obstacle loops and the group sum combines their forces; lane
-// 0 stores.  The loads come in dependent rounds: the agent record; everything
-// addressed by its cell (flood state, the nine distances of its destination
-// field, the obstacle mask, the bin bounds of the three bin rows); the
-// neighbours' positions; the cells of the move.  Cell and bin indices use IEEE
-// division so they match the FP32 decisions of the reference exactly.
+// Row of cell b (< wcells) of a window wdth cells wide: b * ceil(2^20 /
+// wdth) >> 20 is exact while b < 2^20 / wdth, so windows of fewer cells than
+// that use it; larger ones divide.
+__device__ __forceinline__ int window_row(int b, int wdth, int wcells, uint32_t wmagic)
+{
+    return wcells <= (1 << 20) / wdth ? (int)(((uint64_t)(uint32_t)b * wmagic) >> 20) : b / wdth;
+}
+
 // The agent's record, read before anything else of the step.
 struct AgentRec {
     float x, y, vx, vy, vbase;
@@ -109,6 +132,14 @@ __device__ __forceinline__ AgentRec load_agent(const PedParams& p, int a)
     return r;
 }
 
+// One agent, one step, on the L lanes of its group (q = lane in the group).
+// Every lane evaluates the agent's own state; the lanes share the neighbour
+// and obstacle loops and the group sum combines their forces; lane 0 stores.  The loads come in dependent rounds: the agent record; everything
+// addressed by its cell (flood state, the nine distances of its destination
+// field, the obstacle mask, the bin bounds of the three bin rows); the
+// neighbours' positions; the cells of the move.  Cell and bin indices use IEEE
+// division so they match the FP32 decisions of the reference exactly.
+template <int L>
 __device__ void agent_step(const PedParams& p, const AgentRec& rec, const float* __restrict__ fh,
                            const float* __restrict__ fqx, const float* __restrict__ fqy, int a, int q,
                            float dt, int any_wet, int done, int& drop)
@@ -245,59 +276,67 @@ __device__ void agent_step(const PedParams& p, const AgentRec& rec, const float*
         float k = __expf(-dt / p.tau);
         vx = v0 * ex + (vx - v0 * ex) * k;
         vy = v0 * ey + (vy - v0 * ey) * k;
-        // repulsion from the neighbours in the 3x3 bins: the three bins of one
+        // repulsion from the neighbours in the 3x3 bins (the three bins of one
         // bin row are one contiguous run of the sorted positions; the runs of
-        // the three rows are numbered one after the other and the lanes of the
-        // group take every kPedLanes-th entry, two loads at a time
-        float fx = 0.0f, fy = 0.0f;
+        // the three rows are numbered one after the other), then from the
+        // obstacle cells of the window [-Rx, Rx] x [-Ry, Ry] around the cell
+        // (row-major; nearest point of the obstacle cell to the agent).  Entry
+        // k of each list goes into slot k mod kSlots, in list order; the slots
+        // are then added by a fixed tree.  Lane q holds slots q, q + L, ...,
+        // so the sum has the same bits whatever the number L of lanes.
+        constexpr int J = kSlots / L;
+        constexpr int U = J >= 8 ? 1 : 2;      // slot batches per round of loads
+        float fx[J], fy[J];
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            fx[j] = 0.0f;
+            fy[j] = 0.0f;
+        }
         const int n0 = seg1[0] - seg0[0], n01 = n0 + seg1[1] - seg0[1];
         const int ntot = n01 + seg1[2] - seg0[2];
-        for (int k0 = q; k0 < ntot; k0 += 2 * kPedLanes) {
-            int sl[2];
-            float2 o[2];
+        for (int k0 = 0; k0 < ntot; k0 += U * kSlots) {
+            int sl[U][J];
+            float2 o[U][J];
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const int kk = k0 + u * kPedLanes;
-                sl[u] = kk < n0 ? seg0[0] + kk : kk < n01 ? seg0[1] + (kk - n0) : seg0[2] + (kk - n01);
-                o[u] = kk < ntot ? p.xy[sl[u]] : make_float2(x, y);
-            }
+            for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int u = 0; u < 2; ++u)
-                if (sl[u] != self) repel(p, x - o[u].x, y - o[u].y, p.two_r, fx, fy);
+                for (int j = 0; j < J; ++j) {
+                    const int kk = k0 + u * kSlots + q + j * L;
+                    sl[u][j] = kk < n0 ? seg0[0] + kk : kk < n01 ? seg0[1] + (kk - n0) : seg0[2] + (kk - n01);
+                    o[u][j] = kk < ntot ? p.xy[sl[u][j]] : make_float2(x, y);
+                }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int j = 0; j < J; ++j)
+                    if (sl[u][j] != self) repel(p, x - o[u][j].x, y - o[u][j].y, p.two_r, fx[j], fy[j]);
         }
-        // obstacle cells of the window [-Rx, Rx] x [-Ry, Ry] around the cell,
-        // row-major; the lanes take every kPedLanes-th cell.  Nearest point of
-        // the obstacle cell to the agent.
         const int wdth = 2 * p.Rx + 1, wcells = wdth * (2 * p.Ry + 1);
-        int col = q, row = 0;
-        while (col >= wdth) {
-            col -= wdth;
-            ++row;
-        }
-        for (int b = q; b < wcells; b += kPedLanes) {
-            const int wi = ci + col - p.Rx, wj = cj + row - p.Ry;
-            bool obst;
-            if (p.use_wmask) {
-                const uint32_t word = b < 32 ? m4.x : b < 64 ? m4.y : b < 96 ? m4.z : m4.w;
-                obst = (word >> (b & 31)) & 1u;
-            } else {
-                obst = wi >= 0 && wj >= 0 && wi < p.nx && wj < p.ny && !p.walk[(size_t)wj * p.nx + wi];
-            }
-            if (obst) {
-                const float px = fminf(fmaxf(x, (float)wi * p.dx), (float)(wi + 1) * p.dx);
-                const float py = fminf(fmaxf(y, (float)wj * p.dy), (float)(wj + 1) * p.dy);
-                repel(p, x - px, y - py, p.radius, fx, fy);
-            }
-            col += kPedLanes;
-            while (col >= wdth) {
-                col -= wdth;
-                ++row;
+        const uint32_t wmagic = ((1u << 20) + (uint32_t)wdth - 1u) / (uint32_t)wdth;
+        for (int b0 = 0; b0 < wcells; b0 += kSlots) {
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                const int b = b0 + q + j * L;
+                if (b >= wcells) continue;
+                const int row = window_row(b, wdth, wcells, wmagic), col = b - row * wdth;
+                const int wi = ci + col - p.Rx, wj = cj + row - p.Ry;
+                bool obst;
+                if (p.use_wmask) {
+                    const uint32_t word = b < 32 ? m4.x : b < 64 ? m4.y : b < 96 ? m4.z : m4.w;
+                    obst = (word >> (b & 31)) & 1u;
+                } else {
+                    obst = wi >= 0 && wj >= 0 && wi < p.nx && wj < p.ny && !p.walk[(size_t)wj * p.nx + wi];
+                }
+                if (obst) {
+                    const float px = fminf(fmaxf(x, (float)wi * p.dx), (float)(wi + 1) * p.dx);
+                    const float py = fminf(fmaxf(y, (float)wj * p.dy), (float)(wj + 1) * p.dy);
+                    repel(p, x - px, y - py, p.radius, fx[j], fy[j]);
+                }
             }
         }
-        fx = group_sum(fx);
-        fy = group_sum(fy);
-        vx += dt * fx;
-        vy += dt * fy;
+        const float fsx = slot_sum<L>(fx), fsy = slot_sum<L>(fy);
+        vx += dt * fsx;
+        vy += dt * fsy;
         float sp2 = vx * vx + vy * vy;
         if (sp2 > v0 * v0) {
             if (v0 > 0.0f) {
@@ -378,18 +417,18 @@ __device__ void agent_step(const PedParams& p, const AgentRec& rec, const float*
     }
 }
 
-// One wave (= one block) per kPedAgents agents of one scenario: the agent
+// One wave (= one block) per kWave / L agents of one scenario: the agent
 // ranges of the scenarios are padded to whole multiples of kWave agents in the
 // flattened index, so no block straddles two scenarios.
-template <bool kOne>
+template <bool kOne, int L>
 __global__ __launch_bounds__(kWave) void ped_step_kernel(Batch B)
 {
-    const int g0 = blockIdx.x * kPedAgents;
+    const int g0 = blockIdx.x * (kWave / L);
     if (g0 >= B.total_agents) return;
     const int sc = kOne ? 0 : find_scenario(B.agent_off, B.S, g0);
     const Scn& S = scn_at<kOne>(B, sc);
-    const int q = (int)threadIdx.x & (kPedLanes - 1);
-    const int a = g0 - (kOne ? 0 : B.agent_off[sc]) + (int)threadIdx.x / kPedLanes;
+    const int q = (int)threadIdx.x & (L - 1);
+    const int a = g0 - (kOne ? 0 : B.agent_off[sc]) + (int)threadIdx.x / L;
     const PedParams P = S.ped;     // by value: not reloaded after the agent's stores
     // the agent's record in the same round of loads as the scenario's state words
     AgentRec rec{};
@@ -408,7 +447,7 @@ __global__ __launch_bounds__(kWave) void ped_step_kernel(Batch B)
     int drop = 0, act = 0;
     if (a < S.na) {
         act = q == 0 && rec.state != FPS_ST_EXITED;
-        agent_step(P, rec, fb ? S.fv.h[1] : S.fv.h[0], fb ? S.fv.qx[1] : S.fv.qx[0], fb ? S.fv.qy[1] : S.fv.qy[0],
+        agent_step<L>(P, rec, fb ? S.fv.h[1] : S.fv.h[0], fb ? S.fv.qx[1] : S.fv.qx[0], fb ? S.fv.qy[1] : S.fv.qy[0],
                    a, q, dt, wet, done, drop);
     }
     // one wave per block: wave-level counts (lane 0 of each group), one atomic each
@@ -549,14 +588,32 @@ __global__ void check_agents_kernel(const float* x, const float* y, const uint8_
 
 inline int blocks_for(int64_t n, int t) { return (int)((n + t - 1) / t); }
 
+template <int L>
+void launch_ped_lanes(const Batch& b, hipStream_t s)
+{
+    const dim3 grid(b.total_agents / (kWave / L));
+    if (b.S == 1) hipLaunchKernelGGL((ped_step_kernel<true, L>), grid, dim3(kWave), 0, s, b);
+    else hipLaunchKernelGGL((ped_step_kernel<false, L>), grid, dim3(kWave), 0, s, b);
+}
+
 }  // namespace
+
+// Lanes per agent: as many as keep about two waves per SIMD busy (1024 SIMDs
+// of 64 lanes), 16 at most; beyond that the agents' own work fills the chip
+// and the repeated per-agent work of more lanes only costs.
+int ped_lanes(int64_t total_agents)
+{
+    return total_agents <= 8192 ? 16 : total_agents <= 32768 ? 4 : 1;
+}
 
 hipError_t launch_ped(const Batch& b, hipStream_t s)
 {
     if (b.total_agents > 0) {
-        const dim3 grid(b.total_agents / kPedAgents);
-        if (b.S == 1) hipLaunchKernelGGL(ped_step_kernel<true>, grid, dim3(kWave), 0, s, b);
-        else hipLaunchKernelGGL(ped_step_kernel<false>, grid, dim3(kWave), 0, s, b);
+        switch (ped_lanes(b.total_agents)) {
+        case 16: launch_ped_lanes<16>(b, s); break;
+        case 4: launch_ped_lanes<4>(b, s); break;
+        default: launch_ped_lanes<1>(b, s); break;
+        }
     }
     return hipGetLastError();
 }

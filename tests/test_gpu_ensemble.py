@@ -39,6 +39,30 @@ def test_ensemble_equals_solo_runs():
         say(f"scenario {k} ({sc.name}): t = {de['t']:.3f} s, identical to the solo run")
 
 
+@pytest.mark.parametrize("copies", [4, 12])
+def test_lanes_per_agent_do_not_change_results(copies):
+    """An ensemble of many agents gives each agent fewer lanes than a solo run
+    (4 lanes from 8,193 agents, 1 from 32,769; 16 below): the forces are
+    summed in the same slot order either way, so every member still equals
+    its solo run bit for bit."""
+    scs = [I.shopping_centre(n=160, dx=0.5, seed=40 + k, n_evac=3000, q_peak=4.0, duration=60.0)
+           for k in range(copies)]
+    ens = fps.Ensemble(scs)
+    ens.step(180)
+    moved = 0
+    for k in (0, copies - 1):
+        solo = fps.Sim(scs[k])
+        solo.step(180)
+        A, B = ens[k].agents(), solo.agents()
+        for key in A:
+            assert np.array_equal(A[key], B[key]), (copies, k, key)
+        for x, y in zip(ens[k].fields(), solo.fields()):
+            assert np.array_equal(x, y), (copies, k)
+        moved += int((np.abs(A["x"] - scs[k].agents["x"]) > 0).sum())
+    say(f"{copies} x 3000 agents: members 0 and {copies - 1} equal their solo runs ({moved} agents moved)")
+    assert moved > 0
+
+
 def test_graph_replay_equals_eager():
     sc = I.shopping_centre(n=128, dx=0.5, seed=8, n_evac=400)
     a, b = fps.Sim(sc), fps.Sim(sc)
