@@ -154,15 +154,61 @@ __device__ __forceinline__ void face_flux(const FvParams& p, float hL, float unL
     F2 = (none || wall) ? 0.0f : F2;
 }
 
+// Wave reductions by DPP lane moves (VALU only, no LDS round trips): pairs,
+// quads (quad permutes), eight and sixteen lanes (half-row and row mirrors)
+// leave every lane of a row with the row's total; the row broadcasts of lanes
+// 15 and 31 then add the rows, lane 63 ending with the wave's total, which is
+// returned to every lane.  Rows a broadcast does not write receive 0.  A fixed
+// order, so the result is reproducible.
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ int dpp_i32(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, kCtrl, kRowMask, 0xF, false);
+}
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)dpp_i32<kCtrl, kRowMask>((int)(unsigned)u);
+    const unsigned hi = (unsigned)dpp_i32<kCtrl, kRowMask>((int)(unsigned)(u >> 32));
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ float dpp_f32(float v)
+{
+    return __builtin_bit_cast(float, dpp_i32<kCtrl, kRowMask>(__builtin_bit_cast(int, v)));
+}
+constexpr int kQuadSwap1 = 0xB1, kQuadSwap2 = 0x4E;          // quad_perm [1,0,3,2], [2,3,0,1]
+constexpr int kRowHalfMirror = 0x141, kRowMirror = 0x140, kRowBcast15 = 0x142, kRowBcast31 = 0x143;
+
+__device__ __forceinline__ double readlane_f64(double v, int l)
+{
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
 __device__ __forceinline__ double wave_sum(double v)
 {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
+    v += dpp_f64<kQuadSwap1, 0xF>(v);
+    v += dpp_f64<kQuadSwap2, 0xF>(v);
+    v += dpp_f64<kRowHalfMirror, 0xF>(v);
+    v += dpp_f64<kRowMirror, 0xF>(v);
+    v += dpp_f64<kRowBcast15, 0xA>(v);
+    v += dpp_f64<kRowBcast31, 0xC>(v);
+    return readlane_f64(v, kWave - 1);
 }
+// maximum of non-negative values (the rows a broadcast skips receive 0)
 __device__ __forceinline__ float wave_max(float v)
 {
-    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
-    return v;
+    v = fmaxf(v, dpp_f32<kQuadSwap1, 0xF>(v));
+    v = fmaxf(v, dpp_f32<kQuadSwap2, 0xF>(v));
+    v = fmaxf(v, dpp_f32<kRowHalfMirror, 0xF>(v));
+    v = fmaxf(v, dpp_f32<kRowMirror, 0xF>(v));
+    v = fmaxf(v, dpp_f32<kRowBcast15, 0xA>(v));
+    v = fmaxf(v, dpp_f32<kRowBcast31, 0xC>(v));
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), kWave - 1));
 }
 
 // Blocks are handed to the 8 XCDs round-robin by block id; this mapping gives
@@ -350,10 +396,15 @@ __global__ __launch_bounds__(kFvBlock) void fv_step_kernel(Batch B)
             c = nb;
         }
     }
-    // wave partials, fixed reduction order; reduced by the finalize kernel
+    // wave partials, fixed reduction order; reduced by the finalize kernel.
+    // Outflow and clipped volumes are zero in almost every wave (outflow only
+    // on transmissive sides, clipping only where a depth went negative): their
+    // sums are skipped when no lane holds a non-zero value.
     m_acc = wave_sum(m_acc);
-    vout_acc = wave_sum(vout_acc);
-    vclip_acc = wave_sum(vclip_acc);
+    if (__ballot(vout_acc != 0.0)) vout_acc = wave_sum(vout_acc);
+    else vout_acc = 0.0;
+    if (__ballot(vclip_acc != 0.0)) vclip_acc = wave_sum(vclip_acc);
+    else vclip_acc = 0.0;
     smax = wave_max(smax);
     if (lane == 0) {
         FPS_GLOBAL double* dst = gmem(&p.partials[4 * tile]);
@@ -414,14 +465,6 @@ __global__ __launch_bounds__(kFvBlock) void fv_scan_kernel(Batch B, int sc)
         dst[2] = 0.0;
         dst[3] = s3;
     }
-}
-
-__device__ __forceinline__ double readlane_f64(double v, int l)
-{
-    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
-    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, l);
-    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
-    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
 // Exact integral over [a, b] of the piecewise-linear hydrograph (sec. 3.1),
