@@ -158,12 +158,13 @@ __device__ __forceinline__ void face_flux(const FvParams& p, float hL, float unL
 // quads (quad permutes), eight and sixteen lanes (half-row and row mirrors)
 // leave every lane of a row with the row's total; the row broadcasts of lanes
 // 15 and 31 then add the rows, lane 63 ending with the wave's total, which is
-// returned to every lane.  Rows a broadcast does not write receive 0.  A fixed
-// order, so the result is reproducible.
+// returned to every lane.  Rows a broadcast does not write receive 0; the
+// first four moves have a source for every lane, so no old value is set for
+// them.  A fixed order, so the result is reproducible.
 template <int kCtrl, int kRowMask>
 __device__ __forceinline__ int dpp_i32(int v)
 {
-    return __builtin_amdgcn_update_dpp(0, v, kCtrl, kRowMask, 0xF, false);
+    return __builtin_amdgcn_update_dpp(0, v, kCtrl, kRowMask, 0xF, kRowMask == 0xF);
 }
 template <int kCtrl, int kRowMask>
 __device__ __forceinline__ double dpp_f64(double v)
@@ -172,11 +173,6 @@ __device__ __forceinline__ double dpp_f64(double v)
     const unsigned lo = (unsigned)dpp_i32<kCtrl, kRowMask>((int)(unsigned)u);
     const unsigned hi = (unsigned)dpp_i32<kCtrl, kRowMask>((int)(unsigned)(u >> 32));
     return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
-}
-template <int kCtrl, int kRowMask>
-__device__ __forceinline__ float dpp_f32(float v)
-{
-    return __builtin_bit_cast(float, dpp_i32<kCtrl, kRowMask>(__builtin_bit_cast(int, v)));
 }
 constexpr int kQuadSwap1 = 0xB1, kQuadSwap2 = 0x4E;          // quad_perm [1,0,3,2], [2,3,0,1]
 constexpr int kRowHalfMirror = 0x141, kRowMirror = 0x140, kRowBcast15 = 0x142, kRowBcast31 = 0x143;
@@ -199,16 +195,20 @@ __device__ __forceinline__ double wave_sum(double v)
     v += dpp_f64<kRowBcast31, 0xC>(v);
     return readlane_f64(v, kWave - 1);
 }
-// maximum of non-negative values (the rows a broadcast skips receive 0)
+// Maximum of non-negative floats (the wave speeds): their bit patterns order
+// as the values do, so an unsigned maximum of the bits serves (one
+// instruction; a NaN, above every finite pattern, comes through to the time
+// step check).  The rows a broadcast skips receive 0 = +0.0.
 __device__ __forceinline__ float wave_max(float v)
 {
-    v = fmaxf(v, dpp_f32<kQuadSwap1, 0xF>(v));
-    v = fmaxf(v, dpp_f32<kQuadSwap2, 0xF>(v));
-    v = fmaxf(v, dpp_f32<kRowHalfMirror, 0xF>(v));
-    v = fmaxf(v, dpp_f32<kRowMirror, 0xF>(v));
-    v = fmaxf(v, dpp_f32<kRowBcast15, 0xA>(v));
-    v = fmaxf(v, dpp_f32<kRowBcast31, 0xC>(v));
-    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), kWave - 1));
+    unsigned u = __builtin_bit_cast(unsigned, v);
+    u = max(u, (unsigned)dpp_i32<kQuadSwap1, 0xF>((int)u));
+    u = max(u, (unsigned)dpp_i32<kQuadSwap2, 0xF>((int)u));
+    u = max(u, (unsigned)dpp_i32<kRowHalfMirror, 0xF>((int)u));
+    u = max(u, (unsigned)dpp_i32<kRowMirror, 0xF>((int)u));
+    u = max(u, (unsigned)dpp_i32<kRowBcast15, 0xA>((int)u));
+    u = max(u, (unsigned)dpp_i32<kRowBcast31, 0xC>((int)u));
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane((int)u, kWave - 1));
 }
 
 // Blocks are handed to the 8 XCDs round-robin by block id; this mapping gives
