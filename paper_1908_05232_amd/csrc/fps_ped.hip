@@ -78,28 +78,47 @@ __device__ __forceinline__ void repel(const PedParams& p, float rx, float ry, fl
     fy += w * ry;
 }
 
+// The partner of a lane at butterfly distance O within its group, by a DPP
+// move: lane ^ 1 and lane ^ 2 by quad permutes; at distances 4 and 8 the
+// half-row and row mirrors (lane 7 - k, 15 - k) serve, since by then every
+// lane of an aligned group of O holds the same value.
+template <int O>
+__device__ __forceinline__ float lane_partner(float v)
+{
+    constexpr int kCtrl = O == 1 ? 0xB1 : O == 2 ? 0x4E : O == 4 ? 0x141 : 0x140;
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), kCtrl, 0xF, 0xF, true));
+}
+
+// One butterfly level over the slot index: across lanes below L, within the
+// lane from L on.
+template <int O, int L>
+__device__ __forceinline__ void slot_level(float (&v)[kSlots / L])
+{
+    constexpr int J = kSlots / L;
+    if constexpr (O < L) {
+#pragma unroll
+        for (int j = 0; j < J; ++j) v[j] += lane_partner<O>(v[j]);
+    } else {
+        float w[J];
+#pragma unroll
+        for (int j = 0; j < J; ++j) w[j] = v[j] + v[j ^ (O / L)];
+#pragma unroll
+        for (int j = 0; j < J; ++j) v[j] = w[j];
+    }
+}
+
 // The kSlots partial sums of an agent, slot s = q + jL held by lane q of its
 // group as v[j], added by a butterfly over the slot index (levels 1, 2, 4,
-// 8): across lanes for the levels below L, within the lane above.  Every slot
-// ends with the total, with the same bits for any L (each level adds the same
-// two values).
+// 8).  Every slot ends with the total, with the same bits for any L (each
+// level adds the same two values).
 template <int L>
 __device__ __forceinline__ float slot_sum(float (&v)[kSlots / L])
 {
-    constexpr int J = kSlots / L;
-#pragma unroll
-    for (int o = 1; o < kSlots; o <<= 1) {
-        if (o < L) {
-#pragma unroll
-            for (int j = 0; j < J; ++j) v[j] += __shfl_xor(v[j], o, kWave);
-        } else {
-            float w[J];
-#pragma unroll
-            for (int j = 0; j < J; ++j) w[j] = v[j] + v[j ^ (o / L)];
-#pragma unroll
-            for (int j = 0; j < J; ++j) v[j] = w[j];
-        }
-    }
+    static_assert(kSlots == 16, "four butterfly levels");
+    slot_level<1, L>(v);
+    slot_level<2, L>(v);
+    slot_level<4, L>(v);
+    slot_level<8, L>(v);
     return v[0];
 }
 
