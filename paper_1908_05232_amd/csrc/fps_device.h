@@ -39,6 +39,21 @@ __device__ __forceinline__ const Scn& scn_at(const Batch& B, int sc)
     else return B.scn[sc];
 }
 
+// Inclusive prefix sum over the 64 lanes of a wave by DPP lane moves (VALU
+// only): shifts by 1, 2, 4 and 8 within each row of 16 lanes (lanes without a
+// source add 0), then the row broadcasts of lanes 15 and 31 carry the row
+// totals into the rows above.  Integer, so the result is exact.
+__device__ __forceinline__ int wave_inclusive_scan(int v)
+{
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, true);   // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, true);   // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, true);   // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, true);   // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);  // row_bcast:15 into rows 1, 3
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false);  // row_bcast:31 into rows 2, 3
+    return v;
+}
+
 // A step whose flood update is the identity and is skipped: nothing is wet,
 // no inflow enters during the step, and the state already came out of a flood
 // update (so dry cells carry no discharge).  The 1 s dry step of sec. 3 then
@@ -114,11 +129,7 @@ __device__ inline void block_scan_bins(const BinParams& b, int* lds_starts = nul
         int tsum = 0;
 #pragma unroll
         for (int e = 0; e < IPT; ++e) tsum += v[e];
-        int incl = tsum;
-        for (int o = 1; o < kWave; o <<= 1) {
-            int u = __shfl_up(incl, o, kWave);
-            if (lane >= o) incl += u;
-        }
+        const int incl = wave_inclusive_scan(tsum);
         if (lane == kWave - 1) wtot[wid] = incl;
         __syncthreads();
         int wbase = 0, total = 0;
@@ -236,11 +247,7 @@ __device__ inline void lds_bins_build(const BinParams& b)
     int tsum = 0;
 #pragma unroll
     for (int e = 0; e < 16; ++e) tsum += hist[e];
-    int incl = tsum;
-    for (int o = 1; o < kWave; o <<= 1) {
-        const int u = __shfl_up(incl, o, kWave);
-        if (lane >= o) incl += u;
-    }
+    const int incl = wave_inclusive_scan(tsum);
     if (lane == kWave - 1) wtot[wid] = incl;
     __syncthreads();
     int run = incl - tsum, total = 0;

@@ -595,7 +595,7 @@ __global__ __launch_bounds__(kScanThreads) void finalize_kernel(Batch B, int mod
     m = wave_sum(m);
     vo = wave_sum(vo);
     vc = wave_sum(vc);
-    for (int o = 32; o > 0; o >>= 1) sm = fmax(sm, __shfl_xor(sm, o, kWave));
+    sm = (double)wave_max((float)sm);     // the partials hold FP32 wave speeds
     if (lane == 0) {
         red[wid][0] = m;
         red[wid][1] = vo;
@@ -642,7 +642,7 @@ __global__ __launch_bounds__(kScanThreads) void finalize_kernel(Batch B, int mod
         float inc = 0.0f;
         if (inflow_side >= 0)
             inc = (float)(wave_hydro_integral(st->nh, hk_t, hk_q, t, t + (double)dt) / (double)dn);
-        if (!isfinite(mass) || !(dt > 0.0f) || !isfinite(dt)) status = FPS_E_NUMERIC;
+        if (!isfinite(mass) || !(dt > 0.0f) || !isfinite(dt) || !(SM == SM)) status = FPS_E_NUMERIC;
         if (lane == 0) {
             st->t = t;
             st->step = step;
