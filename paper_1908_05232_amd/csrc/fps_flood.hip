@@ -476,7 +476,9 @@ __global__ __launch_bounds__(kFvBlock) void fv_scan_kernel(Batch B, int sc)
 __device__ double wave_hydro_integral(int nh, double tk, double qk, double a, double b)
 {
     const int lane = threadIdx.x & (kWave - 1);
-    const double tn = __shfl_down(tk, 1, kWave), qn = __shfl_down(qk, 1, kWave);
+    // the next knot from the lane above (a whole-wave DPP shift; lane 63,
+    // which gets 0, has no next knot: nh <= 64)
+    const double tn = dpp_f64<0x130, 0xF>(tk), qn = dpp_f64<0x130, 0xF>(qk);
     if (nh <= 0 || !(b > a)) return 0.0;
     double piece = 0.0, before = 0.0, after = 0.0;
     if (lane + 1 < nh) {
