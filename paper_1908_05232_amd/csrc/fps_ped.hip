@@ -179,7 +179,7 @@ __device__ void agent_step(const PedParams& p, const AgentRec& rec, const float*
     const int cj = clampi(cell_of(y, p.dy, p.ny), 0, p.ny - 1);
     const size_t c = (size_t)cj * p.nx + ci;
     const size_t nc = (size_t)p.nx * p.ny;
-    // round 2: cell-addressed loads
+    // second load round: everything addressed by the cell
     const float h = fh[c], qxc = fqx[c], qyc = fqy[c];
     uint4 m4 = make_uint4(0, 0, 0, 0);
     if (p.use_wmask) m4 = p.wmask[c];
