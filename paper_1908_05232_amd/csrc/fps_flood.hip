@@ -412,13 +412,10 @@ __global__ __launch_bounds__(kFvBlock) void fv_step_kernel(Batch B)
         dst[1] = vout_acc;
         dst[2] = vclip_acc;
         dst[3] = (double)smax;
-        if (smax > 0.0f) {
-            // one flag per group of blocks, set once: a device-wide flag hit by
-            // every wave serialises the atomics
-            int* f = p.wet + kWetStride * (blockIdx.x & (kWetSlots - 1));
-            if (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
-                __hip_atomic_fetch_or(f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+        // one flag per group of blocks; every wet wave of the group stores the
+        // same 1 with a plain store (no read-modify-write, nothing to wait for:
+        // the wave ends as soon as its stores are issued)
+        if (smax > 0.0f) st_at(gmem(p.wet), (uint32_t)(kWetStride * (blockIdx.x & (kWetSlots - 1))), 1);
     }
 }
 

@@ -463,19 +463,19 @@ __global__ __launch_bounds__(kWave) void ped_step_kernel(Batch B)
     // evacuation trigger: some cell is wet after this step's flood update
     // one wetness flag per lane (the flood update sets them per group of blocks)
     const int wet = skipped ? 0 : (__ballot(S.fv.wet[kWetStride * threadIdx.x] != 0) != 0ull);
-    int drop = 0, act = 0;
-    if (a < S.na) {
-        act = q == 0 && rec.state != FPS_ST_EXITED;
+    int drop = 0;
+    if (a < S.na)
         agent_step<L>(P, rec, fb ? S.fv.h[1] : S.fv.h[0], fb ? S.fv.qx[1] : S.fv.qx[0], fb ? S.fv.qy[1] : S.fv.qy[0],
                    a, q, dt, wet, done, drop);
-    }
-    // one wave per block: wave-level counts (lane 0 of each group), one atomic each
+    // one wave per block: the sandbag drops of the wave (lane 0 of each
+    // group), one atomic; the agent-steps of the step are the agents that
+    // start it outside the exits, which the bins hold: one add per scenario,
+    // by its first block, instead of a same-address atomic from every block
     const unsigned long long drops = __popcll(__ballot(drop && q == 0));
-    const unsigned long long active = __popcll(__ballot(act));
     if (threadIdx.x == 0) {
         DevState* stw = S.fv.st;
         if (drops) atomicAdd(&stw->drops, (int)drops);
-        if (active) atomicAdd(&stw->ped_steps, active);
+        if (a == 0) atomicAdd(&stw->ped_steps, (unsigned long long)P.bin_start[P.nbx * P.nby]);
     }
 }
 

@@ -183,3 +183,25 @@ def test_barrier_scenario_matches_oracle(oracle):
         off_line = np.ones(zg.size, bool)
         off_line[sc.barrier["cells"]] = False
         assert np.array_equal(zg.reshape(-1)[off_line], zr.reshape(-1)[off_line].astype(np.float32))
+
+
+def test_ped_steps_count_agents_outside_the_exits():
+    """The agent-step counter adds, every step, the agents that start the step
+    outside the exits (walking, standing or waiting), in single steps and in
+    graph-replayed chunks alike."""
+    sc = I.cfg1_dam_break()
+    n = len(sc.agents["x"])
+    one = fps.Sim(sc)
+    one.set_graph(0)
+    expect = 0
+    for _ in range(400):
+        expect += n - one.diag()["state_count"][1]
+        one.step(1)
+    d1 = one.diag()
+    many = fps.Sim(sc)
+    many.step(400)
+    d2 = many.diag()
+    say("cfg1 400 steps: ped_steps", d1["ped_steps"], d2["ped_steps"], "expected", expect,
+        "exited", d1["state_count"][1])
+    assert d1["ped_steps"] == expect
+    assert d2["ped_steps"] == expect
