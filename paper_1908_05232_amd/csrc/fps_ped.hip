@@ -132,7 +132,7 @@ __device__ __forceinline__ int window_row(int b, int wdth, int wcells, uint32_t 
 
 // The agent's record, read before anything else of the step.
 struct AgentRec {
-    float x, y, vx, vy, vbase;
+    float x, y, vx, vy, vbase, timer;
     int state, role, dest, slot;
 };
 
@@ -148,6 +148,7 @@ __device__ __forceinline__ AgentRec load_agent(const PedParams& p, int a)
     r.dest = p.dest[a];
     r.vbase = p.vbase[a];
     r.slot = p.slot[a];
+    r.timer = p.timer[a];
     return r;
 }
 
@@ -179,20 +180,109 @@ __device__ void agent_step(const PedParams& p, const AgentRec& rec, const float*
     const int cj = clampi(cell_of(y, p.dy, p.ny), 0, p.ny - 1);
     const size_t c = (size_t)cj * p.nx + ci;
     const size_t nc = (size_t)p.nx * p.ny;
+    // the agent's state and destination, from its record alone (the new
+    // destination of an agent without one reads the exits' distances), so
+    // that the record is complete before the next round of loads goes out
+    int st = st0;
+    if (dest < 0) {
+        if (role == FPS_ROLE_EVACUEE) {
+            dest = nearest_exit(p, ci, cj);
+            st = FPS_ST_EVAC;
+        } else {
+            dest = p.storage_dest;
+            st = FPS_ST_TO_STORAGE;
+        }
+    }
+    if (role == FPS_ROLE_RESPONDER && done && st != FPS_ST_EVAC) {
+        st = FPS_ST_EVAC;
+        dest = nearest_exit(p, ci, cj);
+    }
+    bool moving = true;
+    if (st == FPS_ST_PICKING || st == FPS_ST_DROPPING) {
+        float tm = rec.timer - dt;
+        if (lead) p.timer[a] = tm;
+        if (tm > 0.0f) {
+            moving = false;
+        } else if (st == FPS_ST_PICKING) {
+            st = FPS_ST_TO_BARRIER;
+            dest = p.barrier_dest;
+        } else {
+            drop = 1;
+            st = FPS_ST_TO_STORAGE;
+            dest = p.storage_dest;
+        }
+    }
+    if (moving && role == FPS_ROLE_EVACUEE && !any_wet) moving = false;
+    // an agent without a valid destination (e.g. a responder with no barrier set) stands
+    if (dest < 0 || dest >= p.n_dest) moving = false;
     // second load round: everything addressed by the cell
     const float h = fh[c], qxc = fqx[c], qyc = fqy[c];
     uint4 m4 = make_uint4(0, 0, 0, 0);
     if (p.use_wmask) m4 = p.wmask[c];
     const int bi = ci / p.bsx, bj = cj / p.bsy;
     const int qi0 = max(bi - 1, 0), qi1 = min(bi + 1, p.nbx - 1);
+    // both bounds of every bin row are loaded (a row outside the grid reads
+    // the agent's own row and is then made empty), so that the six loads go
+    // out together: a load under a condition would make the empty-row copy
+    // wait for the one before it
     int seg0[3], seg1[3];
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
         const int qj = bj - 1 + r;
         const bool ok = qj >= 0 && qj < p.nby;
         const int row = ok ? qj : bj;
-        seg0[r] = p.bin_start[row * p.nbx + qi0];
-        seg1[r] = ok ? p.bin_start[row * p.nbx + qi1 + 1] : seg0[r];
+        const int s0 = p.bin_start[row * p.nbx + qi0], s1 = p.bin_start[row * p.nbx + qi1 + 1];
+        seg0[r] = s0;
+        seg1[r] = ok ? s1 : s0;
+    }
+    // the direction from the nine distances of the destination field: their
+    // loads go out before the wait for the cell's flood state (the hazard
+    // class below), so that they travel in the same round as the cell's
+    const int offx[8] = {1, 0, -1, 0, 1, -1, -1, 1};
+    const int offy[8] = {0, 1, 0, -1, 1, 1, -1, -1};
+    // a 32 x 32 -> 64-bit product: the 64 x 64 one leaves its upper addend
+    // undefined, and the register chosen for it can be a load still in flight
+    const float* D = p.dist + (uint64_t)(uint32_t)(moving ? dest : 0) * (uint64_t)(uint32_t)nc;
+    float ex = 0.0f, ey = 0.0f;    // desired direction
+    if (moving) {
+        float dk[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int qi = ci + offx[k], qj = cj + offy[k];
+            const bool in = qi >= 0 && qj >= 0 && qi < p.nx && qj < p.ny;
+            const float val = D[(size_t)clampi(qj, 0, p.ny - 1) * p.nx + clampi(qi, 0, p.nx - 1)];
+            dk[k] = in ? val : __builtin_inff();
+        }
+        const float here = D[c];
+        // steepest descent: the first of the smallest neighbour distances
+        // below the agent's own; on the destination (distance 0) the target
+        // is the agent's cell.  Selected without a branch on the agent's own
+        // distance (which would hold the other eight loads back until it
+        // arrives) and with the offsets as constants (no offset table read).
+        float best = here;
+        int box = 0, boy = 0;
+        bool found = false;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (dk[k] < best) {
+                best = dk[k];
+                box = offx[k];
+                boy = offy[k];
+                found = true;
+            }
+        }
+        const bool at_goal = here == 0.0f;
+        const bool has_target = at_goal || found;
+        const int ti = at_goal ? ci : ci + box, tj = at_goal ? cj : cj + boy;
+        if (has_target) {
+            float tx = ((float)ti + 0.5f) * p.dx - x, ty = ((float)tj + 0.5f) * p.dy - y;
+            float len2 = tx * tx + ty * ty;
+            if (len2 > 0.0f) {
+                float il = __builtin_amdgcn_rsqf(len2);
+                ex = tx * il;
+                ey = ty * il;
+            }
+        }
     }
     // hazard of the containing cell (Table 1)
     int cls;
@@ -212,85 +302,15 @@ __device__ void agent_step(const PedParams& p, const AgentRec& rec, const float*
            : cls == FPS_CLS_HIGH ? p.v_class[FPS_CLS_HIGH] : p.v_class[FPS_CLS_HIGHEST];
     }
     if (lead) p.cls[a] = (uint8_t)cls;
-    int st = st0;
-    if (dest < 0) {
-        if (role == FPS_ROLE_EVACUEE) {
-            dest = nearest_exit(p, ci, cj);
-            st = FPS_ST_EVAC;
-        } else {
-            dest = p.storage_dest;
-            st = FPS_ST_TO_STORAGE;
-        }
-    }
-    if (role == FPS_ROLE_RESPONDER && done && st != FPS_ST_EVAC) {
-        st = FPS_ST_EVAC;
-        dest = nearest_exit(p, ci, cj);
-    }
+    // the direction is needed here: this keeps the compiler from moving its
+    // loads below the neighbour loop, where they would form a round of their own
+    asm volatile("" : "+v"(ex), "+v"(ey));
     float xn = x, yn = y;
-    bool moving = true;
-    if (st == FPS_ST_PICKING || st == FPS_ST_DROPPING) {
-        float tm = p.timer[a] - dt;
-        if (lead) p.timer[a] = tm;
-        if (tm > 0.0f) {
-            moving = false;
-        } else if (st == FPS_ST_PICKING) {
-            st = FPS_ST_TO_BARRIER;
-            dest = p.barrier_dest;
-        } else {
-            drop = 1;
-            st = FPS_ST_TO_STORAGE;
-            dest = p.storage_dest;
-        }
-    }
-    if (moving && role == FPS_ROLE_EVACUEE && !any_wet) moving = false;
-    // an agent without a valid destination (e.g. a responder with no barrier set) stands
-    if (dest < 0 || dest >= p.n_dest) moving = false;
     int ni = ci, nj = cj;
     if (!moving) {
         vx = 0.0f;
         vy = 0.0f;
     } else {
-        // desired direction from the distance field: the nine distances at once
-        const float* D = p.dist + (size_t)dest * nc;
-        const int offx[8] = {1, 0, -1, 0, 1, -1, -1, 1};
-        const int offy[8] = {0, 1, 0, -1, 1, 1, -1, -1};
-        float dk[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int qi = ci + offx[k], qj = cj + offy[k];
-            const bool in = qi >= 0 && qj >= 0 && qi < p.nx && qj < p.ny;
-            const float val = D[(size_t)clampi(qj, 0, p.ny - 1) * p.nx + clampi(qi, 0, p.nx - 1)];
-            dk[k] = in ? val : __builtin_inff();
-        }
-        const float here = D[c];
-        int ti = ci, tj = cj;
-        bool has_target = true;
-        if (!(here == 0.0f)) {
-            float best = here;
-            int kb = -1;
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                if (dk[k] < best) {
-                    best = dk[k];
-                    kb = k;
-                }
-            }
-            if (kb < 0) has_target = false;
-            else {
-                ti = ci + offx[kb];
-                tj = cj + offy[kb];
-            }
-        }
-        float ex = 0.0f, ey = 0.0f;
-        if (has_target) {
-            float tx = ((float)ti + 0.5f) * p.dx - x, ty = ((float)tj + 0.5f) * p.dy - y;
-            float len2 = tx * tx + ty * ty;
-            if (len2 > 0.0f) {
-                float il = __builtin_amdgcn_rsqf(len2);
-                ex = tx * il;
-                ey = ty * il;
-            }
-        }
         // relaxation toward the desired velocity
         float k = __expf(-dt / p.tau);
         vx = v0 * ex + (vx - v0 * ex) * k;
