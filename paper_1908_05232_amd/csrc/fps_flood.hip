@@ -526,8 +526,8 @@ __global__ __launch_bounds__(kScanThreads) void finalize_kernel(Batch B, int mod
     // The scenario's state words go through LDS: one cooperative load, the
     // serial end-of-step logic on the copy, one cooperative store.  Nothing
     // else touches them while this block runs.  The hydrograph knots stay out
-    // of the copy (they do not change): the first wave holds them in
-    // registers, one knot per lane.
+    // of the copy (they do not change): they are loaded into registers, one
+    // knot per lane, and the first wave uses them.
     __shared__ DevState sst;
     constexpr int kWords = (int)(sizeof(DevState) / sizeof(uint32_t));
     constexpr int kHyd0 = (int)(offsetof(DevState, hyd_t) / sizeof(uint32_t));
@@ -538,38 +538,36 @@ __global__ __launch_bounds__(kScanThreads) void finalize_kernel(Batch B, int mod
                   offsetof(DevState, step) == offsetof(DevState, hyd_q) + sizeof(double) * kMaxHydro,
                   "the hydrograph knots are one run of words");
     static_assert(kCopy <= kScanThreads && kMaxHydro <= kWave, "one word per thread, one knot per lane");
-    // every load of the block is issued before the first barrier
+    // Every load of the block goes out before the first wait: the state words
+    // and the hydrograph knots into registers (written to LDS afterwards), and
+    // eight flood partials per thread.  The loads are unconditional, at
+    // clamped indices, and the values past the end are dropped when summed: a
+    // load under a condition makes the compiler wait for it before the
+    // lanes that skip it may touch its register.
     const int cw = threadIdx.x < kHyd0 ? (int)threadIdx.x : (int)threadIdx.x - kHyd0 + kHyd1;
-    if (threadIdx.x < kCopy)
-        reinterpret_cast<uint32_t*>(&sst)[cw] = reinterpret_cast<const uint32_t*>(gst)[cw];
-    double hk_t = 0.0, hk_q = 0.0;
-    if (wid == 0) {
-        hk_t = gst->hyd_t[lane];
-        hk_q = gst->hyd_q[lane];
-    }
-    // the flood partials, four per thread in one round of loads, summed in
-    // tile order (read whether or not the update ran; dropped below if not)
+    const uint32_t word = reinterpret_cast<const uint32_t*>(gst)[threadIdx.x < kCopy ? cw : 0];
+    const double hk_t = gst->hyd_t[lane], hk_q = gst->hyd_q[lane];
+    // the flood partials summed in tile order
     double m = 0.0, vo = 0.0, vc = 0.0, sm = 0.0;
     {
-        constexpr int kPU = 4;
+        constexpr int kPU = 8;
         const double2* P2 = reinterpret_cast<const double2*>(partials);
         double2 a[kPU], c[kPU];
 #pragma unroll
         for (int u = 0; u < kPU; ++u) {
-            const int b = threadIdx.x + u * kScanThreads;
-            a[u] = make_double2(0.0, 0.0);
-            c[u] = make_double2(0.0, 0.0);
-            if (b < ntiles) {
-                a[u] = P2[2 * b];
-                c[u] = P2[2 * b + 1];
-            }
+            const int b = threadIdx.x + u * kScanThreads, bc = b < ntiles ? b : 0;
+            a[u] = P2[2 * bc];
+            c[u] = P2[2 * bc + 1];
         }
+        if (threadIdx.x < kCopy) reinterpret_cast<uint32_t*>(&sst)[cw] = word;
 #pragma unroll
         for (int u = 0; u < kPU; ++u) {
-            m += a[u].x;
-            vo += a[u].y;
-            vc += c[u].x;
-            sm = fmax(sm, c[u].y);
+            if (threadIdx.x + u * kScanThreads < ntiles) {
+                m += a[u].x;
+                vo += a[u].y;
+                vc += c[u].x;
+                sm = fmax(sm, c[u].y);
+            }
         }
         for (int b = threadIdx.x + kPU * kScanThreads; b < ntiles; b += kScanThreads) {
             m += partials[4 * b + 0];
