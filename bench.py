@@ -375,6 +375,23 @@ def main():
         bsim.close()
         del bsim
         torch.cuda.empty_cache()
+        # the practical streaming rate of the part: a plain 1 GiB device copy
+        # (bytes read + bytes written per second)
+        ca = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        cb = torch.empty_like(ca)
+        for _ in range(3):
+            cb.copy_(ca)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            cb.copy_(ca)
+        e1.record()
+        torch.cuda.synchronize()
+        copy_gbs = 2 * ca.numel() * 4 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        probe["copy_1GiB_GBs"] = copy_gbs
+        probe["frac_of_copy"] = bach / copy_gbs
+        del ca, cb
+        torch.cuda.empty_cache()
 
     out = {
         "metric": "FV cell-updates/s",

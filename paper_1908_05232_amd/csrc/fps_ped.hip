@@ -154,11 +154,12 @@ __device__ __forceinline__ AgentRec load_agent(const PedParams& p, int a)
 
 // One agent, one step, on the L lanes of its group (q = lane in the group).
 // Every lane evaluates the agent's own state; the lanes share the neighbour
-// and obstacle loops and the group sum combines their forces; lane 0 stores.  The loads come in dependent rounds: the agent record; everything
+// and obstacle loops and the group sum combines their forces; lane 0 stores.
+// The loads come in four dependent rounds: the agent record; everything
 // addressed by its cell (flood state, the nine distances of its destination
 // field, the obstacle mask, the bin bounds of the three bin rows); the
 // neighbours' positions; the cells of the move.  Cell and bin indices use IEEE
-// division so they match the FP32 decisions of the reference exactly.
+// division so they match the FP32 decisions of the oracle exactly.
 template <int L>
 __device__ void agent_step(const PedParams& p, const AgentRec& rec, const float* __restrict__ fh,
                            const float* __restrict__ fqx, const float* __restrict__ fqy, int a, int q,
