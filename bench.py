@@ -351,6 +351,10 @@ def main():
     # the flood update alone, HIP events around back-to-back launches on the
     # stream the kernels run on (the events' own cost amortised)
     fv_ms = sim.time_flood(args.profile_steps)
+    # the HLL variant of the face flux on the same state (timing only)
+    sim.set_flux(fps.FPS_FLUX_HLL)
+    fv_ms_hll = sim.time_flood(args.profile_steps)
+    sim.set_flux(fps.FPS_FLUX_HLLC)
     achieved = FV_BYTES_PER_CELL * cells / (fv_ms * 1e-3) / 1e9
     traffic = measured_traffic(workload, rows)
 
@@ -365,12 +369,15 @@ def main():
             bsim.set_graph(0)
         bsim.step(4)
         bms = bsim.time_flood(args.probe_steps)
+        bsim.set_flux(fps.FPS_FLUX_HLL)
+        bms_hll = bsim.time_flood(args.probe_steps)
         bcells = args.probe_n * args.probe_n
         bach = FV_BYTES_PER_CELL * bcells / (bms * 1e-3) / 1e9
         probe = {"workload": f"wet_probe_{args.probe_n} (fully wet dam break, {bcells} cells)",
                  "rows_per_wave": brows,
                  "ms_per_launch": bms, "cell_updates_per_s": bcells / (bms * 1e-3),
                  "achieved_GBs": bach, "frac": bach / HBM_PEAK_GBS,
+                 "hll_flux_ms_per_launch": bms_hll,
                  "working_set_MB": (FV_BYTES_PER_CELL + 12) * bcells / 1e6}
         bsim.close()
         del bsim
@@ -411,6 +418,7 @@ def main():
                    "sim_time_s": [d0["t"], d1["t"]]},
         "secondary": {"ped-steps/s": ped_rate,
                       "flood_update_ms_per_launch": fv_ms,
+                      "flood_update_ms_per_launch_hll_flux": fv_ms_hll,
                       "kernel_ms_per_launch_in_step": {"flood_update": kms[0], "ped_step": kms[1],
                                                "end_of_step": kms[2], "bin_place": kms[3],
                                                "bin_sort": kms[4]},

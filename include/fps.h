@@ -50,6 +50,9 @@ typedef enum {
 /* boundary kinds, sides */
 enum { FPS_BC_WALL = 0, FPS_BC_TRANSMISSIVE = 1 };
 enum { FPS_SIDE_W = 0, FPS_SIDE_E = 1, FPS_SIDE_S = 2, FPS_SIDE_N = 3 };
+/* face flux of the finite-volume update (sec. 2.2 defers the Riemann solver
+   to Wang et al. 2011): HLLC (the default) or HLL for all three components */
+enum { FPS_FLUX_HLLC = 0, FPS_FLUX_HLL = 1 };
 /* agent roles (sec. 2.4), states, hazard classes (Table 1, plus DRY) */
 enum { FPS_ROLE_EVACUEE = 0, FPS_ROLE_RESPONDER = 1 };
 enum {
@@ -206,6 +209,15 @@ int fps_set_occupancy(fps_sim* sim, const int32_t* counts);
    eagerly); calls with fewer steps run eagerly.  Results are identical. */
 int fps_set_graph(fps_sim* sim, int32_t steps_per_graph);
 
+/* Face flux of the flood update (sec. 2.2, Eq. 2): FPS_FLUX_HLLC (default;
+   the tangential momentum flux taken from the side of the contact wave) or
+   FPS_FLUX_HLL (the tangential momentum averaged between the two outer waves
+   like mass and normal momentum; those two are identical in both).  Same
+   reconstruction, wave speeds, bed-slope terms and wall treatment.  Applies
+   from the next step.  FPS_E_INVALID for another value; FPS_E_STATE for an
+   ensemble member (the whole ensemble shares one flux: fps_ens_set_flux). */
+int fps_set_flux(fps_sim* sim, int32_t flux);
+
 /* Synchronise the stream and report diagnostics (sec. 3.2 statistics). */
 int fps_get_diag(fps_sim* sim, fps_diag* out);
 
@@ -269,6 +281,8 @@ int fps_ens_step(fps_ens* ens, int32_t n_steps);
 int fps_ens_step_profiled(fps_ens* ens, int32_t n_steps, double* ms_out);
 /* Steps per captured HIP graph (0 = eager). */
 int fps_ens_set_graph(fps_ens* ens, int32_t steps_per_graph);
+/* Face flux of every scenario (see fps_set_flux). */
+int fps_ens_set_flux(fps_ens* ens, int32_t flux);
 /* Tile shape per scenario, tuned once per distinct grid size (see fps_autotune). */
 int fps_ens_autotune(fps_ens* ens, const char* cache_path);
 /* Number of scenarios that have not reached their end time.  Synchronises. */

@@ -21,7 +21,10 @@
  * Readings where the paper is silent (each also listed in the design notes):
  *   R1 Riemann solver: HLLC (Toro) with dry-bed wave speeds.  HLL part written
  *      anchored at the left state, which is the same formula rearranged so that
- *      two identical states return F(U) exactly.
+ *      two identical states return F(U) exactly.  Variant (P->flux): plain HLL
+ *      (Harten, Lax & van Leer 1983) for all three components, the tangential
+ *      momentum averaged like the other two instead of taken from the upwind
+ *      side of the contact.
  *   R2 wetting/drying + terrain: non-negative hydrostatic reconstruction
  *      (Audusse et al. 2004), z_f = max(zL, zR), h* = h - (z_f - z); a face side
  *      with h* <= h_dry counts as dry and h* := 0.  Velocities come from the
@@ -112,6 +115,42 @@ void or_hllc(double g, double hL, double uL, double vL, double hR, double uR, do
     F[2] = F[0] * (sM >= 0.0 ? vL : vR);
 }
 
+/* HLL for all three components: the same wave speeds as or_hllc and the
+   same left-anchored form of (sR FL - sL FR + sL sR (UR - UL)) / (sR - sL),
+   with U = (h, h un, h ut); mass and normal momentum equal or_hllc's exactly. */
+void or_hll(double g, double hL, double uL, double vL, double hR, double uR, double vR,
+            double F[3])
+{
+    if (hL == 0.0 && hR == 0.0) {
+        F[0] = F[1] = F[2] = 0.0;
+        return;
+    }
+    double cL = sqrt(g * hL), cR = sqrt(g * hR);
+    double sL, sR;
+    if (hL == 0.0) {
+        sL = uR - 2.0 * cR;
+        sR = uR + cR;
+    } else if (hR == 0.0) {
+        sL = uL - cL;
+        sR = uL + 2.0 * cL;
+    } else {
+        double us = 0.5 * (uL + uR) + cL - cR;
+        double cs = 0.5 * (cL + cR) + 0.25 * (uL - uR);
+        sL = fmin(uL - cL, us - cs);
+        sR = fmax(uR + cR, us + cs);
+    }
+    double qL = hL * uL, qR = hR * uR;
+    double FL[3] = {qL, qL * uL + 0.5 * g * hL * hL, qL * vL};
+    double FR[3] = {qR, qR * uR + 0.5 * g * hR * hR, qR * vR};
+    double UL[3] = {hL, qL, hL * vL};
+    double UR[3] = {hR, qR, hR * vR};
+    for (int k = 0; k < 3; ++k) {
+        if (sL >= 0.0) F[k] = FL[k];
+        else if (sR <= 0.0) F[k] = FR[k];
+        else F[k] = FL[k] + sL * ((FL[k] - FR[k]) + sR * (UR[k] - UL[k])) * (1.0 / (sR - sL));
+    }
+}
+
 /* one face: hydrostatic reconstruction (R2) then the flux.  hsL/hsR return the
    reconstructed depths each side sees, used by the bed-slope correction. */
 void or_face(const or_params *P, double hL, double qnL, double qtL, double zL,
@@ -127,7 +166,8 @@ void or_face(const or_params *P, double hL, double qnL, double qtL, double zL,
     double unL = 0.0, utL = 0.0, unR = 0.0, utR = 0.0;
     if (hL > eps) { unL = qnL / hL; utL = qtL / hL; }
     if (hR > eps) { unR = qnR / hR; utR = qtR / hR; }
-    or_hllc(P->g, hl, unL, utL, hr, unR, utR, F);
+    if (P->flux == OR_FLUX_HLL) or_hll(P->g, hl, unL, utL, hr, unR, utR, F);
+    else or_hllc(P->g, hl, unL, utL, hr, unR, utR, F);
     if (wall) {                          /* R6: a wall passes no mass */
         F[0] = 0.0;
         F[2] = 0.0;

@@ -36,6 +36,8 @@ extern "C" {
 #define OR_CLS_MEDIUM 2
 #define OR_CLS_HIGH 3
 #define OR_CLS_HIGHEST 4
+#define OR_FLUX_HLLC 0
+#define OR_FLUX_HLL 1
 
 typedef struct {
     int32_t nx, ny;
@@ -51,6 +53,7 @@ typedef struct {
     double v_class[5];                   /* index by class; [0] unused (dry uses v_base) */
     double hr_t[3];                      /* class thresholds 0.75, 1.5, 2.5 */
     double pick_s, drop_s;
+    int32_t flux;                        /* OR_FLUX_HLLC (R1) or OR_FLUX_HLL (variant) */
 } or_params;
 
 typedef struct {
@@ -89,6 +92,8 @@ typedef struct {
 /* ---- single operations (exposed for the pins) ---- */
 void or_hllc(double g, double hL, double uL, double vL, double hR, double uR, double vR,
              double F[3]);
+void or_hll(double g, double hL, double uL, double vL, double hR, double uR, double vR,
+            double F[3]);
 void or_face(const or_params *P, double hL, double qnL, double qtL, double zL,
              double hR, double qnR, double qtR, double zR, int wall, double F[3],
              double *hsL, double *hsR);

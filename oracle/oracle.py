@@ -26,6 +26,7 @@ WALL, TRANSMISSIVE = 0, 1
 ROLE_EVACUEE, ROLE_RESPONDER = 0, 1
 ST_EVAC, ST_EXITED, ST_TO_STORAGE, ST_PICKING, ST_TO_BARRIER, ST_DROPPING = range(6)
 CLS_DRY, CLS_LOW, CLS_MEDIUM, CLS_HIGH, CLS_HIGHEST = range(5)
+FLUX_HLLC, FLUX_HLL = 0, 1
 
 
 class OrParams(C.Structure):
@@ -40,6 +41,7 @@ class OrParams(C.Structure):
         ("radius", C.c_double), ("r_cut", C.c_double), ("r_arrive", C.c_double),
         ("v_class", C.c_double * 5), ("hr_t", C.c_double * 3),
         ("pick_s", C.c_double), ("drop_s", C.c_double),
+        ("flux", C.c_int32),
     ]
 
 
@@ -84,6 +86,7 @@ def lib():
         _lib = C.CDLL(build())
         L = _lib
         L.or_hllc.argtypes = [C.c_double] * 7 + [_dp]
+        L.or_hll.argtypes = [C.c_double] * 7 + [_dp]
         L.or_face.argtypes = [C.POINTER(OrParams)] + [C.c_double] * 8 + [C.c_int, _dp, _dp, _dp]
         L.or_hydro_integral.argtypes = [C.c_int32, _dp, _dp, C.c_double, C.c_double]
         L.or_hydro_integral.restype = C.c_double
@@ -131,6 +134,7 @@ def make_params(desc, ped=None) -> OrParams:
     for k in range(3):
         P.hr_t[k] = ped.hr_t[k]
     P.pick_s, P.drop_s = ped.pick_s, ped.drop_s
+    P.flux = getattr(desc, "flux", FLUX_HLLC)
     return P
 
 
@@ -256,6 +260,12 @@ class OracleSim:
 def hllc(g, hL, uL, vL, hR, uR, vR):
     F = (C.c_double * 3)()
     lib().or_hllc(g, hL, uL, vL, hR, uR, vR, F)
+    return np.array(F[:])
+
+
+def hll(g, hL, uL, vL, hR, uR, vR):
+    F = (C.c_double * 3)()
+    lib().or_hll(g, hL, uL, vL, hR, uR, vR, F)
     return np.array(F[:])
 
 

@@ -84,6 +84,7 @@ struct Engine {
     bool any_big = false;
     bool dirty = true;
     int graph_chunk = 16;
+    int hll = 0;                     // face flux of every scenario: HLL instead of HLLC
     hipGraphExec_t exec = nullptr;
     int exec_steps = 0;
     char err[512] = "";
@@ -402,6 +403,7 @@ Batch batch_of(const Engine* e, int s_only = -1)
     b.fv_blocks = e->fv_blocks;
     b.fin_lds_bytes = e->fin_lds_bytes;
     b.s_only = s_only;
+    b.hll = e->hll;
     if (s_only >= 0) b.fv_blocks = fv_blocks_for_tiles(e->scn_h[s_only].fv.ntiles);
     if (e->S == 1) b.one = e->scn_h[0];
     return b;
@@ -855,6 +857,15 @@ int fps_ens_set_graph(fps_ens* e, int32_t steps_per_graph)
     return FPS_OK;
 }
 
+int fps_ens_set_flux(fps_ens* e, int32_t flux)
+{
+    if (!e) return fail(nullptr, FPS_E_INVALID, "fps_ens_set_flux: ens is NULL");
+    if (flux != FPS_FLUX_HLLC && flux != FPS_FLUX_HLL) return efail(e, FPS_E_INVALID, "unknown flux %d", flux);
+    e->hll = flux == FPS_FLUX_HLL;
+    drop_graph(e);      // the captured launches name the kernel of the old flux
+    return FPS_OK;
+}
+
 int fps_ens_autotune(fps_ens* e, const char* cache_path)
 {
     if (!e) return fail(nullptr, FPS_E_INVALID, "fps_ens_autotune: ens is NULL");
@@ -1101,6 +1112,16 @@ int fps_set_end_time(fps_sim* s, double t_end)
     HIPCHK(s, hipStreamSynchronize(st));
     s->t_end = t_end;
     return write_state_i32(s, &s->st->active, !(t_end > 0.0) || t < t_end);
+}
+
+int fps_set_flux(fps_sim* s, int32_t flux)
+{
+    if (!s) return fail(nullptr, FPS_E_INVALID, "fps_set_flux: sim is NULL");
+    if (flux != FPS_FLUX_HLLC && flux != FPS_FLUX_HLL) return fail(s, FPS_E_INVALID, "fps_set_flux: unknown flux %d", flux);
+    if (!s->eng->standalone) return fail(s, FPS_E_STATE, "fps_set_flux: member of an ensemble; use fps_ens_set_flux");
+    s->eng->hll = flux == FPS_FLUX_HLL;
+    drop_graph(s->eng);
+    return FPS_OK;
 }
 
 int fps_step(fps_sim* s, int32_t n_steps)

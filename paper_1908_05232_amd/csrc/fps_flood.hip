@@ -5,7 +5,8 @@
 // step of sec. 3 reduced on the device for the next step.
 //
 // Readings of the paper used here (the scheme is deferred to Wang et al. 2011):
-//   HLLC face flux (Toro) with dry-bed wave speeds; non-negative hydrostatic
+//   HLLC face flux (Toro) with dry-bed wave speeds (or, selected per launch,
+//   HLL for all three components); non-negative hydrostatic
 //   reconstruction z_f = max(zL, zR), h* = h - (z_f - z), h* <= h_dry counts
 //   as dry; bed slope as the one-sided pressure correction 1/2 g h*^2; walls by
 //   mirrored ghost cells passing no mass; transmissive sides by copied ghosts;
@@ -110,6 +111,10 @@ __device__ __forceinline__ float pressure(float half_g, float h)
 // tangential momentum; pL / pR the pressures 1/2 g h*^2 of the reconstructed
 // depth each side sees (the bed-slope correction of the two cells).
 // Written without divergent branches: every case is evaluated and selected.
+// kHll: the tangential momentum by the HLL average of the two outer waves, in
+// the same left-anchored form as mass and normal momentum, instead of from the
+// side of the contact wave.
+template <bool kHll>
 __device__ __forceinline__ void face_flux(const FvParams& p, float hL, float unL, float utL,
                                           float zL, float hR, float unR, float utR, float zR,
                                           bool wall, float& F0, float& F1, float& F2,
@@ -141,9 +146,14 @@ __device__ __forceinline__ void face_flux(const FvParams& p, float hL, float unL
     float inv = rcp(sR - sL);
     float H0 = FL0 + sL * ((FL0 - FR0) + sR * (hr - hl)) * inv;
     float H1 = FL1 + sL * ((FL1 - FR1) + sR * (qR - qL)) * inv;
-    // contact speed s_M = num / den with den < 0 here, so s_M >= 0 iff num <= 0
-    float num = sL * hr * (unR - sR) - sR * hl * (unL - sL);
-    float H2 = H0 * (num <= 0.0f ? utL : utR);
+    float H2;
+    if (kHll) {
+        H2 = FL2 + sL * ((FL2 - FR2) + sR * (hr * utR - hl * utL)) * inv;
+    } else {
+        // contact speed s_M = num / den with den < 0 here, so s_M >= 0 iff num <= 0
+        float num = sL * hr * (unR - sR) - sR * hl * (unL - sL);
+        H2 = H0 * (num <= 0.0f ? utL : utR);
+    }
     const bool left = sL >= 0.0f, right = sR <= 0.0f;
     F0 = left ? FL0 : (right ? FR0 : H0);
     F1 = left ? FL1 : (right ? FR1 : H1);
@@ -220,7 +230,7 @@ __device__ __forceinline__ int xcd_tile_block(int b, int nblocks)
     return (b & 7) * per + (b >> 3);
 }
 
-template <bool kOne>
+template <bool kOne, bool kHll>
 __global__ __launch_bounds__(kFvBlock) void fv_step_kernel(Batch B)
 {
     const int lane = threadIdx.x & (kWave - 1);
@@ -310,7 +320,7 @@ __global__ __launch_bounds__(kFvBlock) void fv_step_kernel(Batch B)
             derive(p, nb, mirror_x, j + 1);
             // north face (y normal: pass v as normal, u as tangential)
             float Fn0, Fn1, Fn2, pN, pS_next;
-            face_flux(p, c.h, c.v, c.u, c.z, nb.h, nb.v, nb.u, nb.z,
+            face_flux<kHll>(p, c.h, c.v, c.u, c.z, nb.h, nb.v, nb.u, nb.z,
                       (j + 1 == 0 && p.bc[2] == FPS_BC_WALL) || (j + 1 == p.ny && p.bc[3] == FPS_BC_WALL),
                       Fn0, Fn1, Fn2, pN, pS_next);
             if (j < j0) {
@@ -328,7 +338,7 @@ __global__ __launch_bounds__(kFvBlock) void fv_step_kernel(Batch B)
             float eh = lane_from_above(c.h), eu = lane_from_above(c.u);
             float ev = lane_from_above(c.v), ez = lane_from_above(c.z);
             float Fe0, Fe1, Fe2, pE, pW_east;
-            face_flux(p, c.h, c.u, c.v, c.z, eh, eu, ev, ez, xwall, Fe0, Fe1, Fe2, pE, pW_east);
+            face_flux<kHll>(p, c.h, c.u, c.v, c.z, eh, eu, ev, ez, xwall, Fe0, Fe1, Fe2, pE, pW_east);
             // west face = east face of the lane below
             float Fw0 = lane_from_below(Fe0), Fw1 = lane_from_below(Fe1);
             float Fw2 = lane_from_below(Fe2), pW = lane_from_below(pW_east);
@@ -744,8 +754,14 @@ int fv_blocks_for_tiles(int64_t tiles)
 hipError_t launch_fv(const Batch& b, hipStream_t s)
 {
     if (b.fv_blocks > 0) {
-        if (b.S == 1) hipLaunchKernelGGL(fv_step_kernel<true>, dim3(b.fv_blocks), dim3(kFvBlock), 0, s, b);
-        else hipLaunchKernelGGL(fv_step_kernel<false>, dim3(b.fv_blocks), dim3(kFvBlock), 0, s, b);
+        const dim3 grid(b.fv_blocks), block(kFvBlock);
+        if (b.S == 1) {
+            if (b.hll) hipLaunchKernelGGL((fv_step_kernel<true, true>), grid, block, 0, s, b);
+            else hipLaunchKernelGGL((fv_step_kernel<true, false>), grid, block, 0, s, b);
+        } else {
+            if (b.hll) hipLaunchKernelGGL((fv_step_kernel<false, true>), grid, block, 0, s, b);
+            else hipLaunchKernelGGL((fv_step_kernel<false, false>), grid, block, 0, s, b);
+        }
     }
     return hipGetLastError();
 }

@@ -156,6 +156,7 @@ struct Batch {
     int fin_lds_bytes;     // dynamic LDS of the finalize launch (LDS binning)
     int s_only;            // >= 0: restrict the flood launch to one scenario (tuning)
     Scn one;               // S == 1: the scenario itself, read from the kernel arguments
+    int hll;               // face flux: HLL (1) or HLLC (0), the same for every scenario
 };
 
 // launchers (stream-ordered, no synchronisation)

@@ -15,6 +15,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libfps.so")
 
 FPS_OK, FPS_E_INVALID, FPS_E_DEVICE, FPS_E_STATE, FPS_E_CAPACITY, FPS_E_NUMERIC = 0, -1, -2, -3, -4, -5
+FPS_FLUX_HLLC, FPS_FLUX_HLL = 0, 1
 
 _vp = C.c_void_p
 
@@ -74,12 +75,14 @@ EXPORTS = {
     "fps_step_profiled": (C.c_int, [_vp, C.c_int32, C.POINTER(C.c_double)]),
     "fps_set_end_time": (C.c_int, [_vp, C.c_double]),
     "fps_set_graph": (C.c_int, [_vp, C.c_int32]),
+    "fps_set_flux": (C.c_int, [_vp, C.c_int32]),
     "fps_ens_workspace_bytes": (C.c_size_t, [C.c_int32, C.POINTER(GridDescC), C.POINTER(C.c_int32)]),
     "fps_ens_create": (C.c_int, [C.c_int32, C.POINTER(GridDescC), C.POINTER(PedParamsC),
                                  C.POINTER(C.c_int32), _vp, C.c_size_t, _vp, C.POINTER(_vp)]),
     "fps_ens_destroy": (None, [_vp]),
     "fps_ens_member": (_vp, [_vp, C.c_int32]),
     "fps_ens_step": (C.c_int, [_vp, C.c_int32]),
+    "fps_ens_set_flux": (C.c_int, [_vp, C.c_int32]),
     "fps_ens_step_profiled": (C.c_int, [_vp, C.c_int32, C.POINTER(C.c_double)]),
     "fps_ens_set_graph": (C.c_int, [_vp, C.c_int32]),
     "fps_ens_autotune": (C.c_int, [_vp, C.c_char_p]),
@@ -227,6 +230,11 @@ class Member:
     def set_end_time(self, t_end):
         return self._check(self._lib.fps_set_end_time(self.h_, float(t_end)))
 
+    def set_flux(self, flux):
+        """Face flux of the flood update: FPS_FLUX_HLLC or FPS_FLUX_HLL
+        (a standalone simulation; an ensemble sets it for all its members)."""
+        return self._check(self._lib.fps_set_flux(self.h_, int(flux)))
+
     def rebind_fields(self):
         return self._check(self._lib.fps_bind_fields(self.h_, _ptr(self.h), _ptr(self.qx), _ptr(self.qy),
                                                      _ptr(self.z)))
@@ -336,6 +344,8 @@ class Sim(Member):
         self._check(L.fps_create(C.byref(self.desc_c), C.byref(self.ped_c), self.max_agents, self.ws_ptr,
                                  nbytes, C.c_void_p(self.stream.cuda_stream), C.byref(h)), None)
         self._bind(h, sc, device)
+        if getattr(d, "flux", FPS_FLUX_HLLC) != FPS_FLUX_HLLC:
+            self.set_flux(d.flux)
 
     def close(self):
         if getattr(self, "h_", None) and self.h_.value:
@@ -358,6 +368,7 @@ class Sim(Member):
 
     def set_graph(self, steps_per_graph):
         return self._check(self._lib.fps_set_graph(self.h_, int(steps_per_graph)))
+
 
 
 class _EnsMember(Member):
@@ -391,6 +402,11 @@ class Ensemble:
             raise FpsError(rc, (L.fps_last_error(None) or b"").decode())
         self.members = [_EnsMember(L, C.c_void_p(L.fps_ens_member(self.e_, k)), sc, device)
                         for k, sc in enumerate(scenarios)]
+        fluxes = {getattr(sc.desc, "flux", FPS_FLUX_HLLC) for sc in scenarios}
+        if len(fluxes) > 1:
+            raise FpsError(FPS_E_INVALID, "the scenarios of an ensemble share one face flux")
+        if fluxes != {FPS_FLUX_HLLC}:
+            self.set_flux(fluxes.pop())
 
     def _check(self, rc):
         if rc != FPS_OK:
@@ -413,6 +429,9 @@ class Ensemble:
 
     def set_graph(self, steps_per_graph):
         return self._check(self._lib.fps_ens_set_graph(self.e_, int(steps_per_graph)))
+
+    def set_flux(self, flux):
+        return self._check(self._lib.fps_ens_set_flux(self.e_, int(flux)))
 
     def autotune(self, cache_path=None):
         cp = None if cache_path is None else str(cache_path).encode()

@@ -44,6 +44,7 @@ class GridDesc:
     inflow_c1: int = 0
     n_base: float = 0.01         # clear cement (sec. 2.4)
     np_cap: int = 20             # at most 20 evacuees counted per cell (sec. 2.4)
+    flux: int = 0                # face flux: 0 = HLLC, 1 = HLL for all three components
 
 
 @dataclasses.dataclass

@@ -116,3 +116,20 @@ def test_dry_steps_skip_the_flood_update(oracle):
     ref.run(40, dts=np.array(dts))
     h, _, _, _ = sim2.fields()
     assert np.abs(h - ref.fields()[0]).max() <= 1e-4
+
+
+def test_ensemble_hll_equals_solo_runs():
+    """The HLL flux set on a whole ensemble equals solo HLL runs bit for bit;
+    a member's own flux cannot differ from its ensemble's."""
+    scs = mixed_scenarios()[:2]
+    for sc in scs:
+        sc.desc.flux = fps.FPS_FLUX_HLL
+    ens = fps.Ensemble(scs)
+    ens.step(120)
+    for k, sc in enumerate(scs):
+        solo = fps.Sim(sc)
+        solo.step(120)
+        for x, y in zip(ens[k].fields(), solo.fields()):
+            assert np.array_equal(x, y), (k, sc.name)
+    with pytest.raises(fps.FpsError):
+        ens[0].set_flux(fps.FPS_FLUX_HLLC)

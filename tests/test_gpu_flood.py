@@ -120,3 +120,65 @@ def test_tile_shape_does_not_change_results(tmp_path):
     say(f"autotuned rows per wave {rows} ({ms:.4f} ms)")
     assert rows in (1, 2, 4, 8, 16, 32, 64) and ms > 0
     assert sim.autotune(cache)[0] == rows and len(cache.read_text().splitlines()) == 1
+
+
+# --------------------------------------------------------------------------
+# the HLL variant of the face flux (fps_set_flux)
+# --------------------------------------------------------------------------
+def test_hll_variant_parity(oracle):
+    """HLL for all three components against the oracle's HLL: rough random
+    data with tangential flow, and the shopping centre with its inflow."""
+    sc = random_wet_dry(70, 45, 0.5, seed=77, bc=(0, 1, 0, 1))
+    sc.desc.flux = fps.FPS_FLUX_HLL
+    sim = fps.Sim(sc)
+    check_window(oracle, sim, sc, 200, "HLL random 70x45", throughput=True)
+    sc = I.shopping_centre(n=128, dx=0.5, seed=3, n_evac=10)
+    sc.agents = None
+    sc.desc.flux = fps.FPS_FLUX_HLL
+    sim = fps.Sim(sc)
+    sim.step(400)
+    check_window(oracle, sim, sc, 500, "HLL shopping centre 128^2 steps 400-900")
+
+
+def test_hll_switch_changes_only_the_tangential_flux():
+    """With no tangential flow anywhere the two fluxes agree (mass and normal
+    momentum are the same formula; the oracle gives the same bits, the two
+    compiled kernels may round a fused multiply-add differently); with it they
+    differ; and switching a simulation's flux mid-run (graphs recaptured)
+    equals a run that used it from that step on, bit for bit."""
+    a, b = (I.dam_break_1d(256, 32.0, 1.0, 0.1) for _ in range(2))
+    b.desc.flux = fps.FPS_FLUX_HLL
+    sa, sb = fps.Sim(a), fps.Sim(b)
+    sa.step(300)
+    sb.step(300)
+    (ha, qxa, qya, _), (hb, qxb, qyb, _) = sa.fields(), sb.fields()
+    d_h, d_q = float(np.abs(ha - hb).max()), float(np.abs(qxa - qxb).max())
+    say(f"1D dam break, 300 steps, HLL vs HLLC: max|dh| {d_h:.2e}  max|dqx| {d_q:.2e}  "
+        f"bitwise {np.array_equal(ha, hb) and np.array_equal(qxa, qxb)}")
+    # rounding-level differences grown over 300 steps of a moving shock (the
+    # parity bar against the oracle is 1e-4 m); no tangential flow appears
+    assert d_h <= 2e-5 and d_q <= 2e-5 and not np.any(qyb)
+    sc = random_wet_dry(64, 40, 0.5, seed=78, bc=(0, 1, 0, 1))
+    hllc, hll, mixed = fps.Sim(sc), fps.Sim(sc), fps.Sim(sc)
+    hll.set_flux(fps.FPS_FLUX_HLL)
+    for s in (hllc, hll, mixed):
+        s.step(64)
+    dh = float(np.abs(hllc.fields()[0] - hll.fields()[0]).max())
+    say(f"HLL vs HLLC after 64 steps of rough data: max|dh| = {dh:.3e}")
+    assert dh > 0.0
+    mixed.set_flux(fps.FPS_FLUX_HLL)
+    mixed.step(64)
+    mixed.set_flux(fps.FPS_FLUX_HLLC)
+    mixed.step(32)
+    ref = fps.Sim(sc)
+    ref.step(64)
+    ref.set_flux(fps.FPS_FLUX_HLL)
+    for _ in range(64):
+        ref.step(1)
+    ref.set_flux(fps.FPS_FLUX_HLLC)
+    for _ in range(32):
+        ref.step(1)
+    for x, y in zip(mixed.fields(), ref.fields()):
+        assert np.array_equal(x, y)
+    with pytest.raises(fps.FpsError):
+        hll.set_flux(7)

@@ -157,6 +157,123 @@ def test_contact_carries_tangential_velocity(oracle):
 
 
 # --------------------------------------------------------------------------
+# the HLL variant of the face flux
+# --------------------------------------------------------------------------
+def test_hll_consistency_and_shared_components(oracle):
+    """Identical states give F(U) exactly; mass and normal momentum are the
+    HLLC ones bit for bit (same wave speeds, same left-anchored HLL form);
+    both sides dry give no flux."""
+    g = 9.81
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        h = rng.uniform(0.01, 3.0)
+        u, v = rng.uniform(-4, 4, 2)
+        F = oracle.hll(g, h, u, v, h, u, v)
+        assert np.array_equal(F, np.array([h * u, (h * u) * u + 0.5 * g * h * h, (h * u) * v]))
+        hL, hR = rng.uniform(0.0, 2.0, 2)
+        if rng.random() < 0.2:
+            hR = 0.0
+        uL, uR, vL, vR = rng.uniform(-3, 3, 4)
+        a = oracle.hll(g, hL, uL, vL, hR, uR, vR)
+        b = oracle.hllc(g, hL, uL, vL, hR, uR, vR)
+        assert a[0] == b[0] and a[1] == b[1]
+    assert np.all(oracle.hll(g, 0.0, 1.0, 1.0, 0.0, -1.0, 2.0) == 0.0)
+
+
+def test_hll_shear_flux_closed_form(oracle):
+    """Still water with a jump of tangential velocity: the wave speeds are -c
+    and +c, so HLL diffuses the shear, -(c / 2) h (vR - vL), where HLLC
+    passes none (the contact does not move)."""
+    g = 9.81
+    for h, vL, vR in [(1.0, 1.0, -0.5), (0.3, -2.0, 0.7), (2.5, 0.1, 0.4)]:
+        c = math.sqrt(g * h)
+        F = oracle.hll(g, h, 0.0, vL, h, 0.0, vR)
+        assert abs(F[0]) <= 1e-15
+        assert abs(F[1] - 0.5 * g * h * h) <= 1e-13 * g * h * h
+        assert abs(F[2] - (-0.5 * c * h * (vR - vL))) <= 1e-13 * c * h
+        assert oracle.hllc(g, h, 0.0, vL, h, 0.0, vR)[2] == 0.0
+
+
+def test_hll_reflection_invariance_and_upwind(oracle):
+    g = 9.81
+    rng = np.random.default_rng(4)
+    for _ in range(200):
+        hL, hR = rng.uniform(0.0, 2.0, 2)
+        if rng.random() < 0.2:
+            hL = 0.0
+        uL, uR, vL, vR = rng.uniform(-3, 3, 4)
+        F = oracle.hll(g, hL, uL, vL, hR, uR, vR)
+        Fm = oracle.hll(g, hR, -uR, vR, hL, -uL, vL)
+        np.testing.assert_allclose([F[0], F[1], F[2]], [-Fm[0], Fm[1], -Fm[2]], rtol=1e-12, atol=1e-12)
+    hL, uL, vL, hR, uR, vR = 0.2, 5.0, 0.3, 0.1, 4.0, -0.2
+    F = oracle.hll(g, hL, uL, vL, hR, uR, vR)
+    np.testing.assert_allclose(F, [hL * uL, hL * uL * uL + 0.5 * g * hL * hL, hL * uL * vL], rtol=1e-15)
+
+
+def test_hll_lake_at_rest_mass_and_symmetry(oracle):
+    """The variant keeps still water exactly still, conserves mass to round-off
+    behind walls, and transposes bit for bit."""
+    sc = I.lake_at_rest(40, 33, 0.5, seed=11)
+    sc.desc.flux = 1
+    s = oracle.OracleSim(sc)
+    h0 = s.h.copy()
+    s.run(1000, with_peds=False)
+    assert np.abs(s.qx).max() <= 1e-12 and np.abs(s.qy).max() <= 1e-12
+    assert np.abs(s.h - h0).max() <= 1e-12
+    sc = I.cfg1_dam_break()
+    sc.desc.flux = 1
+    s = oracle.OracleSim(sc)
+    m0 = s.mass()
+    s.run(1000, with_peds=False)
+    assert abs(s.mass() - m0) / m0 <= 1e-13
+    rng = I.rng_of(6)
+    nx, ny = 31, 19
+    z = rng.uniform(0, 0.4, (ny, nx))
+    h = np.maximum(rng.uniform(-0.2, 1.0, (ny, nx)), 0.0)
+    qx = rng.uniform(-0.3, 0.3, (ny, nx)) * (h > 0)
+    qy = rng.uniform(-0.3, 0.3, (ny, nx)) * (h > 0)
+    d = I.GridDesc(nx=nx, ny=ny, dx=0.5, dy=0.5, bc=(0, 1, 0, 1), n_base=0.03, flux=1)
+    a = oracle.OracleSim(I.Scenario(desc=d, h=h, qx=qx, qy=qy, z=z))
+    t = _transpose_scenario(I.Scenario(desc=d, h=h, qx=qx, qy=qy, z=z))
+    t.desc.flux = 1
+    b = oracle.OracleSim(t)
+    a.run(60, with_peds=False)
+    b.run(60, with_peds=False)
+    ha, qxa, qya, _ = a.fields()
+    hb, qxb, qyb, _ = b.fields()
+    assert np.array_equal(ha, hb.T) and np.array_equal(qxa, qyb.T) and np.array_equal(qya, qxb.T)
+
+
+def test_hll_smears_the_shear_layer_but_converges(oracle):
+    """The passive shear of the dam break: with HLL the tangential velocity
+    still converges to the exact solution, with a larger error than HLLC at
+    every resolution; with no tangential flow the two schemes agree bit for bit."""
+    L, x0, T = 32.0, 16.0, 2.0
+    err = {0: [], 1: []}
+    for nx in (128, 256, 512):
+        for flux in (0, 1):
+            sc = I.dam_break_1d(nx, L, 1.0, 0.1, x0=x0)
+            sc.qy = np.where(sc.h > 0.5, 1.0 * sc.h, -0.5 * sc.h)
+            sc.desc.bc = (0, 0, 1, 1)
+            sc.desc.flux = flux
+            s = oracle.OracleSim(sc)
+            run_to(oracle, s, T)
+            xc = (np.arange(nx) + 0.5) * (L / nx)
+            he, ue, ve = dam_break_exact(xc, T, x0, 1.0, 0.1, vL=1.0, vR=-0.5)
+            err[flux].append(np.sum(np.abs(s.qy - he * ve)) * (L / nx))
+    assert all(err[1][k] > err[0][k] for k in range(3)), err
+    assert err[1][2] < 0.8 * err[1][1] < 0.8 * 0.8 * err[1][0] * 1.01, err
+    fields = []
+    for flux in (0, 1):
+        sc = I.dam_break_1d(256, L, 1.0, 0.1, x0=x0)
+        sc.desc.flux = flux
+        s = oracle.OracleSim(sc)
+        run_to(oracle, s, T)
+        fields.append(s.fields())
+    assert all(np.array_equal(p, q) for p, q in zip(fields[0], fields[1]))
+
+
+# --------------------------------------------------------------------------
 # conservation, symmetry, positivity, time step
 # --------------------------------------------------------------------------
 def test_mass_conserved_closed_walls(oracle):
