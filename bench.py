@@ -95,7 +95,9 @@ def ensemble_section(args, stream):
            "scenario_steps_per_s": len(scs) * args.ens_steps / (ms * 1e-3),
            "ped_steps_per_s": (p1 - p0) / (ms * 1e-3),
            "flood_update_ms_per_launch": kms[0],
-           "flood_update_GBs": FV_BYTES_PER_CELL * cells / (kms[0] * 1e-3) / 1e9}
+           "flood_update_GBs": FV_BYTES_PER_CELL * cells / (kms[0] * 1e-3) / 1e9,
+           "kernel_ms_per_launch_in_step": {"flood_update": kms[0], "ped_step": kms[1], "end_of_step": kms[2],
+                                            "bin_place": kms[3], "bin_sort": kms[4]}}
     ens.close()
     del ens
     torch.cuda.empty_cache()
