@@ -191,6 +191,50 @@ __device__ inline void sort_agent(const BinParams& b, int a)
     b.xy[f] = make_float2(b.x[a], b.y[a]);
 }
 
+// Placement and stable order of at most kInlinePlace agents by one block,
+// after its scan of the global histogram (grids with more bins than the LDS
+// binning takes).  Every global load goes out in two rounds (the agents' keys,
+// ranks and positions; then the bounds of their bins), the unordered
+// placement lives in LDS, and an agent's final slot counts the smaller ids of
+// its bin there.  Same results as place_agent followed by sort_agent.
+__device__ inline void inline_bins_place(const BinParams& b)
+{
+    constexpr int APT = kInlinePlace / kScanThreads;
+    __shared__ int lp[kInlinePlace];
+    int key[APT], rank[APT], s0[APT], s1[APT];
+    float ax[APT], ay[APT];
+#pragma unroll
+    for (int q = 0; q < APT; ++q) {
+        const int a = threadIdx.x + q * kScanThreads, ac = a < b.na ? a : 0;
+        const int k = b.key[ac];
+        rank[q] = b.rank[ac];
+        ax[q] = b.x[ac];
+        ay[q] = b.y[ac];
+        key[q] = a < b.na ? k : -1;
+    }
+#pragma unroll
+    for (int q = 0; q < APT; ++q) {
+        const int kc = key[q] >= 0 ? key[q] : 0;
+        s0[q] = b.bin_start[kc];
+        s1[q] = b.bin_start[kc + 1];
+    }
+#pragma unroll
+    for (int q = 0; q < APT; ++q)
+        if (key[q] >= 0) lp[s0[q] + rank[q]] = threadIdx.x + q * kScanThreads;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < APT; ++q) {
+        if (key[q] < 0) continue;
+        const int a = threadIdx.x + q * kScanThreads;
+        int below = 0;
+        for (int s = s0[q]; s < s1[q]; ++s) below += lp[s] < a;
+        const int f = s0[q] + below;
+        b.perm[f] = a;
+        b.slot[a] = f;
+        b.xy[f] = make_float2(ax[q], ay[q]);
+    }
+}
+
 // One-block binning in LDS for small grids (nbins <= 16 * kScanThreads, at
 // most kInlinePlace agents; dynamic shared memory of nbins + 1 + na words),
 // run by a block of its own beside the end-of-step state update.  It starts

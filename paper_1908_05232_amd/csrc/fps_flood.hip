@@ -700,11 +700,7 @@ __global__ __launch_bounds__(kScanThreads) void finalize_kernel(Batch B, int mod
     if (mode == 0 && na > 0 && !lds_bins) {
         const BinParams bp = S.bins;
         block_scan_bins(bp);
-        if (inline_place) {
-            for (int a = threadIdx.x; a < bp.na; a += kScanThreads) place_agent(bp, a);
-            __syncthreads();
-            for (int a = threadIdx.x; a < bp.na; a += kScanThreads) sort_agent(bp, a);
-        }
+        if (inline_place) inline_bins_place(bp);
     }
 }
 

@@ -22,13 +22,14 @@ def recount(sc, A):
     return cnt.reshape(d.ny, d.nx)
 
 
-@pytest.mark.parametrize("which", ["cfg1", "one", "centre", "big"])
+@pytest.mark.parametrize("which", ["cfg1", "one", "centre", "wide", "big"])
 def test_bins_and_counts_bit_exact(oracle, which):
     """The bins after the step against the oracle's stable counting sort:
-    the one-block LDS binning (cfg1, one agent, centre), and the global
-    histogram, scan and placement kernels (big: 22,500 bins, more than one
-    block scans in LDS, and 9,000 agents, more than the end-of-step block
-    places itself)."""
+    the one-block LDS binning (cfg1, one agent, centre), the global histogram
+    scanned by the end-of-step block which also places the agents (wide:
+    22,500 bins, more than the LDS binning takes, and 3,000 agents), and the
+    global scan with the placement kernels (big: 9,000 agents, more than the
+    end-of-step block places itself)."""
     if which == "cfg1":
         sc = I.cfg1_dam_break(n_ped=400)
         checkpoints = (0, 5, 60)
@@ -38,6 +39,9 @@ def test_bins_and_counts_bit_exact(oracle, which):
     elif which == "centre":
         sc = I.shopping_centre(n=256, dx=0.25, seed=9, n_evac=3000)
         checkpoints = (0, 20, 200)
+    elif which == "wide":
+        sc = I.shopping_centre(n=600, dx=0.25, seed=19, n_evac=3000)
+        checkpoints = (0, 10, 100)
     else:
         sc = I.shopping_centre(n=600, dx=0.25, seed=19, n_evac=9000)
         checkpoints = (0, 10, 100)
