@@ -96,83 +96,88 @@ __device__ inline double hydro_integral(const DevState* st, double a, double b)
 
 // Exclusive scan of the bin histogram by one block of kScanThreads: tiles of
 // 16 * kScanThreads counts, sixteen consecutive counts per lane (four 16-byte
-// loads), a wave scan by shuffles and a scan of the wave totals; the histogram
-// is cleared behind the scan for the next step.
-__device__ inline void block_scan_bins(const BinParams& b, int* lds_starts = nullptr)
+// loads), a wave scan and a scan of the wave totals per tile.  The counts of
+// up to four tiles are loaded in one round before any of them is scanned (a
+// round per tile made the scan of a large grid a chain of dependent loads);
+// the histogram is cleared behind the loads for the next step.
+__device__ inline void block_scan_bins(const BinParams& b)
 {
-    constexpr int IPT = 16;
+    constexpr int IPT = 16, TILES = 4, TILE = IPT * kScanThreads;
     __shared__ int wtot[kScanThreads / kWave];
-    __shared__ int carry_s;
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x >> 6;
-    if (threadIdx.x == 0) carry_s = 0;
-    __syncthreads();
-    for (int base = 0; base < b.nbins; base += IPT * kScanThreads) {
-        const int k0 = base + IPT * threadIdx.x;
-        int v[IPT];
-        if (k0 + IPT <= b.nbins) {
+    int carry = 0;     // bins before the current tile (uniform)
+    for (int base = 0; base < b.nbins; base += TILES * TILE) {
+        int v[TILES][IPT];
 #pragma unroll
-            for (int q = 0; q < IPT / 4; ++q) {
-                int4 w = *reinterpret_cast<const int4*>(b.bin_count + k0 + 4 * q);
-                v[4 * q] = w.x; v[4 * q + 1] = w.y; v[4 * q + 2] = w.z; v[4 * q + 3] = w.w;
-                *reinterpret_cast<int4*>(b.bin_count + k0 + 4 * q) = make_int4(0, 0, 0, 0);
+        for (int t = 0; t < TILES; ++t) {
+            const int k0 = base + t * TILE + IPT * threadIdx.x;
+            if (k0 + IPT <= b.nbins) {
+#pragma unroll
+                for (int q = 0; q < IPT / 4; ++q) {
+                    const int4 w = *reinterpret_cast<const int4*>(b.bin_count + k0 + 4 * q);
+                    v[t][4 * q] = w.x; v[t][4 * q + 1] = w.y; v[t][4 * q + 2] = w.z; v[t][4 * q + 3] = w.w;
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < IPT; ++e) v[t][e] = k0 + e < b.nbins ? b.bin_count[k0 + e] : 0;
             }
-        } else {
+        }
 #pragma unroll
-            for (int e = 0; e < IPT; ++e) {
-                v[e] = 0;
-                if (k0 + e < b.nbins) {
-                    v[e] = b.bin_count[k0 + e];
-                    b.bin_count[k0 + e] = 0;
+        for (int t = 0; t < TILES; ++t) {
+            const int k0 = base + t * TILE + IPT * threadIdx.x;
+            if (k0 + IPT <= b.nbins) {
+#pragma unroll
+                for (int q = 0; q < IPT / 4; ++q)
+                    *reinterpret_cast<int4*>(b.bin_count + k0 + 4 * q) = make_int4(0, 0, 0, 0);
+            } else {
+                for (int e = 0; e < IPT; ++e)
+                    if (k0 + e < b.nbins) b.bin_count[k0 + e] = 0;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < TILES; ++t) {
+            if (base + t * TILE >= b.nbins) break;      // uniform
+            const int k0 = base + t * TILE + IPT * threadIdx.x;
+            int tsum = 0;
+#pragma unroll
+            for (int e = 0; e < IPT; ++e) tsum += v[t][e];
+            const int incl = wave_inclusive_scan(tsum);
+            if (lane == kWave - 1) wtot[wid] = incl;
+            __syncthreads();
+            int wbase = 0, total = 0;
+            for (int w = 0; w < kScanThreads / kWave; ++w) {
+                const int x = wtot[w];
+                wbase += w < wid ? x : 0;
+                total += x;
+            }
+            int run = carry + wbase + incl - tsum;
+            if (k0 + IPT <= b.nbins) {
+#pragma unroll
+                for (int q = 0; q < IPT / 4; ++q) {
+                    int4 w;
+                    w.x = run; run += v[t][4 * q];
+                    w.y = run; run += v[t][4 * q + 1];
+                    w.z = run; run += v[t][4 * q + 2];
+                    w.w = run; run += v[t][4 * q + 3];
+                    *reinterpret_cast<int4*>(b.bin_start + k0 + 4 * q) = w;
+                }
+            } else {
+                for (int e = 0; e < IPT; ++e) {
+                    if (k0 + e < b.nbins) b.bin_start[k0 + e] = run;
+                    run += v[t][e];
                 }
             }
+            carry += total;
+            __syncthreads();      // wtot is rewritten by the next tile
         }
-        int tsum = 0;
-#pragma unroll
-        for (int e = 0; e < IPT; ++e) tsum += v[e];
-        const int incl = wave_inclusive_scan(tsum);
-        if (lane == kWave - 1) wtot[wid] = incl;
-        __syncthreads();
-        int wbase = 0, total = 0;
-        for (int w = 0; w < kScanThreads / kWave; ++w) {
-            int t = wtot[w];
-            wbase += w < wid ? t : 0;
-            total += t;
-        }
-        int run = carry_s + wbase + incl - tsum;
-        if (k0 + IPT <= b.nbins) {
-#pragma unroll
-            for (int q = 0; q < IPT / 4; ++q) {
-                int4 w;
-                w.x = run; run += v[4 * q];
-                w.y = run; run += v[4 * q + 1];
-                w.z = run; run += v[4 * q + 2];
-                w.w = run; run += v[4 * q + 3];
-                *reinterpret_cast<int4*>(b.bin_start + k0 + 4 * q) = w;
-                if (lds_starts) *reinterpret_cast<int4*>(lds_starts + k0 + 4 * q) = w;
-            }
-        } else {
-            for (int e = 0; e < IPT; ++e) {
-                if (k0 + e < b.nbins) {
-                    b.bin_start[k0 + e] = run;
-                    if (lds_starts) lds_starts[k0 + e] = run;
-                }
-                run += v[e];
-            }
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) carry_s += total;
-        __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        b.bin_start[b.nbins] = carry_s;
-        if (lds_starts) lds_starts[b.nbins] = carry_s;
-    }
+    if (threadIdx.x == 0) b.bin_start[b.nbins] = carry;
     __syncthreads();
 }
 
 // Placement of the agents into their bins by rank, then the stable order: an
 // agent's final slot counts the smaller ids of its own bin.  Whole-grid
-// version in two kernels; this one-block version runs inside the finalize.
+// version, in two kernels (one thread per agent).
 __device__ inline void place_agent(const BinParams& b, int a)
 {
     int k = b.key[a];
