@@ -283,7 +283,12 @@ int fps_ens_step_profiled(fps_ens* ens, int32_t n_steps, double* ms_out);
 int fps_ens_set_graph(fps_ens* ens, int32_t steps_per_graph);
 /* Face flux of every scenario (see fps_set_flux). */
 int fps_ens_set_flux(fps_ens* ens, int32_t flux);
-/* Tile shape per scenario, tuned once per distinct grid size (see fps_autotune). */
+/* Rows per wave of every scenario (see fps_set_rows_per_wave), tuned for the
+   duration of the ensemble's whole flood launch on the bound states: one value
+   for all scenarios, then each distinct grid size moved by factors of two
+   while the launch gets shorter.  The states are not advanced; results do not
+   depend on the choice.  cache_path is accepted and not used (the best values
+   depend on the whole mix of grids).  Synchronises. */
 int fps_ens_autotune(fps_ens* ens, const char* cache_path);
 /* Number of scenarios that have not reached their end time.  Synchronises. */
 int fps_ens_active(fps_ens* ens, int32_t* n_active);

@@ -735,6 +735,28 @@ int write_state_i32(fps_sim* s, int32_t* field, int32_t v)
     return FPS_OK;
 }
 
+// reps back-to-back launches of the whole ensemble's flood update on the
+// current state (outputs to scratch; the state is not advanced)
+int time_ensemble_flood(Engine* e, int reps, float* ms_out)
+{
+    int rc = upload(e);
+    if (rc != FPS_OK) return rc;
+    const Batch b = batch_of(e);
+    hipEvent_t e0, e1;
+    HIPCHK_E(e, hipEventCreate(&e0));
+    HIPCHK_E(e, hipEventCreate(&e1));
+    for (int r = 0; r < 2; ++r) HIPCHK_E(e, launch_fv(b, e->stream));
+    HIPCHK_E(e, hipEventRecord(e0, e->stream));
+    for (int r = 0; r < reps; ++r) HIPCHK_E(e, launch_fv(b, e->stream));
+    HIPCHK_E(e, hipEventRecord(e1, e->stream));
+    HIPCHK_E(e, hipEventSynchronize(e1));
+    float ms = 0.0f;
+    HIPCHK_E(e, hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms_out = ms / reps;
+    return FPS_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -868,20 +890,79 @@ int fps_ens_set_flux(fps_ens* e, int32_t flux)
 
 int fps_ens_autotune(fps_ens* e, const char* cache_path)
 {
+    (void)cache_path;    // the best heights depend on the whole mix of grids, not on one size
     if (!e) return fail(nullptr, FPS_E_INVALID, "fps_ens_autotune: ens is NULL");
-    for (int k = 0; k < e->S; ++k) {
-        fps_sim* s = e->m[k];
-        int reuse = -1;
-        for (int j = 0; j < k; ++j)
-            if (e->m[j]->G.nx == s->G.nx && e->m[j]->G.ny == s->G.ny) reuse = j;
-        if (reuse >= 0) {
-            s->H = e->m[reuse]->H;
+    for (fps_sim* s : e->m)
+        if (!s->fields_bound) return efail(e, FPS_E_STATE, "fps_ens_autotune: scenario %d: fields not bound", s->idx);
+    HIPCHK_E(e, hipStreamSynchronize(e->stream));
+    // The flood update of an ensemble is one launch over the tiles of every
+    // member, which fills the chip: tune the rows per wave for that launch's
+    // duration, not for each member alone (alone, a small grid is latency
+    // bound and prefers short marches).  One height for every member first,
+    // then each distinct grid size moved by factors of two while the launch
+    // gets shorter by more than 1 %.
+    int64_t cells = 0;
+    for (fps_sim* s : e->m) cells += (int64_t)s->G.nx * s->G.ny;
+    const int reps = cells > (1 << 26) ? 3 : 10;
+    auto set_all = [&](int H) {
+        for (fps_sim* s : e->m) {
+            s->H = H;
             mark_dirty(s);
-            int rc = prime(s);
-            if (rc != FPS_OK) return efail(e, rc, "%s", s->err);
-            continue;
         }
-        int rc = tune_member(s, cache_path, nullptr, nullptr);
+    };
+    int best_h = 1;
+    float best = 0.0f;
+    for (int H = 1; H <= 64; H <<= 1) {
+        set_all(H);
+        float ms = 0.0f;
+        int rc = time_ensemble_flood(e, reps, &ms);
+        if (rc != FPS_OK) return rc;
+        if (H == 1 || ms < best) {
+            best = ms;
+            best_h = H;
+        }
+    }
+    set_all(best_h);
+    std::vector<int> sizes;      // distinct grid sizes, as nx * 65536 + ny
+    for (fps_sim* s : e->m) {
+        const int key = s->G.nx * 65536 + s->G.ny;
+        if (std::find(sizes.begin(), sizes.end(), key) == sizes.end()) sizes.push_back(key);
+    }
+    if (sizes.size() > 1) {
+        for (int pass = 0; pass < 2; ++pass) {
+            bool moved = false;
+            for (int key : sizes) {
+                int cur_h = 0;
+                for (fps_sim* s : e->m)
+                    if (s->G.nx * 65536 + s->G.ny == key) cur_h = s->H;
+                for (int H : {cur_h * 2, cur_h / 2}) {
+                    if (H < 1 || H > 64) continue;
+                    for (fps_sim* s : e->m)
+                        if (s->G.nx * 65536 + s->G.ny == key) {
+                            s->H = H;
+                            mark_dirty(s);
+                        }
+                    float ms = 0.0f;
+                    int rc = time_ensemble_flood(e, reps, &ms);
+                    if (rc != FPS_OK) return rc;
+                    if (ms < 0.99f * best) {
+                        best = ms;
+                        cur_h = H;
+                        moved = true;
+                    }
+                    for (fps_sim* s : e->m)
+                        if (s->G.nx * 65536 + s->G.ny == key) {
+                            s->H = cur_h;
+                            mark_dirty(s);
+                        }
+                }
+            }
+            if (!moved) break;
+        }
+    }
+    // the timing launches wrote scratch partials and the wetness flags
+    for (fps_sim* s : e->m) {
+        int rc = prime(s);
         if (rc != FPS_OK) return efail(e, rc, "%s", s->err);
     }
     return FPS_OK;
@@ -1042,7 +1123,7 @@ int fps_set_time(fps_sim* s, double t, int64_t step)
 namespace {
 // unit discharge of the hydrograph at time t: piecewise linear between the
 // breakpoints, the end values held outside them (as the flood update does)
-double host_hydro_q(const fps_sim* s, double t)
+static double host_hydro_q(const fps_sim* s, double t)
 {
     const int n = s->hyd_n;
     if (n <= 0) return 0.0;
