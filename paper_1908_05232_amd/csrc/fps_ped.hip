@@ -638,12 +638,13 @@ void launch_ped_lanes(const Batch& b, hipStream_t s)
 
 }  // namespace
 
-// Lanes per agent: as many as keep about two waves per SIMD busy (1024 SIMDs
-// of 64 lanes), 16 at most; beyond that the agents' own work fills the chip
-// and the repeated per-agent work of more lanes only costs.
+// Lanes per agent, by measurement: 16 for small crowds (latency bound: the
+// lanes share an agent's neighbour and obstacle loops), 4 up to 2^18 agents
+// (the 64-scenario sweep with 170 k agents: 58 us per step against 66 with
+// 1 lane and 88 with 16), then 1, where the agents' own work fills the chip.
 int ped_lanes(int64_t total_agents)
 {
-    return total_agents <= 8192 ? 16 : total_agents <= 32768 ? 4 : 1;
+    return total_agents <= 8192 ? 16 : total_agents <= 262144 ? 4 : 1;
 }
 
 hipError_t launch_ped(const Batch& b, hipStream_t s)
