@@ -348,20 +348,24 @@ int fps_sur_apply(int64_t npix, const float* y, float* h, float* hu, float* hv, 
    whose depth differs by more than tol (m) or whose hazard class (Table 1;
    thresholds hr_thresholds[3], host) differs; out2[1] = the largest depth
    difference as float bits.  Cells: floor(x / dx) in FP32, clamped to the
-   grid.  out2: device int32[2]; async. */
+   grid.  out2: device int32[2]; async.  FPS_E_INVALID, before any device
+   call, for bad sizes or a NULL array (the agent and flood arrays may be NULL
+   only when na = 0). */
 int fps_sur_judge(int32_t na, int32_t stride, const float* x, const float* y, const uint8_t* state,
                   int32_t nx, int32_t ny, double dx, double dy, const float* ha, const float* qxa,
                   const float* qya, const float* hb, const float* qxb, const float* qyb, double tol,
                   double h_dry, const double* hr_thresholds, int32_t* out2, void* stream);
 /* Judge region for fps_set_judge_region: clears mask (device uint8
    [ceil(ny/block)][ceil(nx/block)]) and marks every block within halo cells of
-   the cell of a sampled agent (the same sample as fps_sur_judge); async. */
+   the cell of a sampled agent (the same sample as fps_sur_judge); async.
+   FPS_E_INVALID for bad sizes, a NULL mask, or NULL agent arrays with na > 0. */
 int fps_sur_judge_mask(int32_t na, int32_t stride, const float* x, const float* y, const uint8_t* state,
                        int32_t nx, int32_t ny, double dx, double dy, int32_t halo, int32_t block,
                        uint8_t* mask, void* stream);
 /* Per-cell counts of evacuees still evacuating (role evacuee, state EVAC),
    the counts that raise the Manning coefficient (sec. 2.3), into device int32
-   [ny][nx]; async. */
+   [ny][nx]; async.  FPS_E_INVALID for bad sizes, NULL counts, or NULL agent
+   arrays with na > 0. */
 int fps_sur_occupancy(int32_t na, const float* x, const float* y, const uint8_t* role,
                       const uint8_t* state, int32_t nx, int32_t ny, double dx, double dy,
                       int32_t* counts, void* stream);

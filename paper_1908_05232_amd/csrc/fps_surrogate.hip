@@ -935,7 +935,8 @@ int fps_sur_judge(int32_t na, int32_t stride, const float* x, const float* y, co
                   const float* hb, const float* qxb, const float* qyb, double tol, double h_dry,
                   const double* hr_thresholds, int32_t* out2, void* stream)
 {
-    if (na < 0 || stride < 1 || nx < 1 || ny < 1 || !(dx > 0) || !(dy > 0) || !out2 || !hr_thresholds)
+    if (na < 0 || stride < 1 || nx < 1 || ny < 1 || !(dx > 0) || !(dy > 0) || !out2 || !hr_thresholds ||
+        (na > 0 && (!x || !y || !state || !ha || !qxa || !qya || !hb || !qxb || !qyb)))
         return sfail(nullptr, FPS_E_INVALID, "fps_sur_judge: bad argument");
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipLaunchKernelGGL(fill_u8_kernel, dim3(1), dim3(64), 0, st, reinterpret_cast<uint8_t*>(out2), (int64_t)8);
@@ -954,7 +955,8 @@ int fps_sur_judge_mask(int32_t na, int32_t stride, const float* x, const float* 
                        int32_t nx, int32_t ny, double dx, double dy, int32_t halo, int32_t block, uint8_t* mask,
                        void* stream)
 {
-    if (na < 0 || stride < 1 || nx < 1 || ny < 1 || !(dx > 0) || !(dy > 0) || halo < 0 || block < 1 || !mask)
+    if (na < 0 || stride < 1 || nx < 1 || ny < 1 || !(dx > 0) || !(dy > 0) || halo < 0 || block < 1 || !mask ||
+        (na > 0 && (!x || !y || !state)))
         return sfail(nullptr, FPS_E_INVALID, "fps_sur_judge_mask: bad argument");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int64_t nm = (int64_t)((nx + block - 1) / block) * ((ny + block - 1) / block);
@@ -971,7 +973,8 @@ int fps_sur_judge_mask(int32_t na, int32_t stride, const float* x, const float* 
 int fps_sur_occupancy(int32_t na, const float* x, const float* y, const uint8_t* role, const uint8_t* state,
                       int32_t nx, int32_t ny, double dx, double dy, int32_t* counts, void* stream)
 {
-    if (na < 0 || nx < 1 || ny < 1 || !(dx > 0) || !(dy > 0) || !counts)
+    if (na < 0 || nx < 1 || ny < 1 || !(dx > 0) || !(dy > 0) || !counts ||
+        (na > 0 && (!x || !y || !role || !state)))
         return sfail(nullptr, FPS_E_INVALID, "fps_sur_occupancy: bad argument");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int64_t nc = (int64_t)nx * ny;

@@ -81,3 +81,22 @@ def test_create_rejects_bad_arguments_without_touching_the_device():
     L.fps_ped_params_default(C.byref(p))
     assert list(p.v_class) == [0.0, 1.8, 0.9, 0.45, 0.0] and list(p.hr_t) == [0.75, 1.5, 2.5]
     assert p.pick_s == 30.0 and p.drop_s == 30.0
+
+
+def test_agent_sample_calls_reject_null_arrays_without_touching_the_device():
+    L = fps.lib()
+    buf = C.c_void_p(4096)          # never dereferenced: every call below fails its checks first
+    thr = (C.c_double * 3)(0.75, 1.5, 2.5)
+    flood = [buf] * 6
+    # judge: NULL agent or flood arrays are rejected when there are agents to sample
+    assert L.fps_sur_judge(4, 1, None, buf, buf, 8, 8, 1.0, 1.0, *flood, 0.05, 1e-5, thr, buf,
+                           None) == fps.FPS_E_INVALID
+    assert L.fps_sur_judge(4, 1, buf, buf, buf, 8, 8, 1.0, 1.0, buf, None, *flood[2:], 0.05, 1e-5, thr, buf,
+                           None) == fps.FPS_E_INVALID
+    assert L.fps_sur_judge(4, 0, buf, buf, buf, 8, 8, 1.0, 1.0, *flood, 0.05, 1e-5, thr, buf,
+                           None) == fps.FPS_E_INVALID
+    assert L.fps_sur_judge_mask(4, 1, buf, buf, None, 8, 8, 1.0, 1.0, 1, 4, buf, None) == fps.FPS_E_INVALID
+    assert L.fps_sur_judge_mask(4, 1, buf, buf, buf, 8, 8, 1.0, 1.0, 1, 0, buf, None) == fps.FPS_E_INVALID
+    assert L.fps_sur_occupancy(4, buf, buf, None, buf, 8, 8, 1.0, 1.0, buf, None) == fps.FPS_E_INVALID
+    assert L.fps_sur_occupancy(-1, buf, buf, buf, buf, 8, 8, 1.0, 1.0, buf, None) == fps.FPS_E_INVALID
+    assert b"fps_sur_occupancy" in L.fps_sur_last_error(None)
