@@ -2,7 +2,8 @@
 
 Scenario 1 (sec. 3.2): the evacuation run twice, with and without the
 people's effect on the flood (the roughness rule of sec. 2.4 switched off by a
-zero evacuee cap).  Scenario 2 (sec. 3.3): the pre-flood deployment sweep, six
+zero evacuee cap), at several breach discharges, since on this layout the
+crowd only meets the water once the breach carries more than a few m^2/s.  Scenario 2 (sec. 3.3): the pre-flood deployment sweep, six
 responder group sizes (5 % to 50 % of the population) times one to six sandbag
 layers, each run until its barrier is complete or 12 hours have passed, then
 the flood over each finished barrier height.
@@ -32,6 +33,7 @@ GROUPS = (0.05, 0.10, 0.20, 0.30, 0.40, 0.50)
 LAYERS = (1, 2, 3, 4, 5, 6)
 LAYER_M = 0.25                 # sandbag thickness per layer (sec. 3.3: three layers reach 0.75 m)
 DEPLOY_WINDOW_S = 12 * 3600.0  # the 12-hour deployment window (sec. 3.3)
+BREACH_Q = (2.0, 5.0, 10.0, 20.0)  # peak unit discharges of the evacuation runs (m^2/s)
 NO_FLOOD = 1.0e9               # hydrograph start of the dry deployment runs
 ST_EXITED = 1                  # agent state: left through an exit (include/fps.h)
 
@@ -50,14 +52,16 @@ def evacuation_pair(population=1000, seed=5232, n=SITE_N, dx=SITE_DX, q_peak=2.0
     return [with_people, without]
 
 
-def run_evacuation(scs, t_max=3600.0, poll_steps=100):
+def run_evacuation(scs, t_max=3600.0, poll_steps=10):
     """Step an ensemble until every evacuee has left or ``t_max``; per member the
     evacuation time and the largest number of people seen at once in each
     hazard class (Table 1), polled every ``poll_steps`` steps."""
     ens = fps.Ensemble(scs)
     ens.autotune()
     n = [len(sc.agents["x"]) for sc in scs]
-    out = [dict(name=sc.name, evacuees=k, t_evacuated=None, peak_class_count=[0] * 5) for sc, k in zip(scs, n)]
+    q = [float(np.max(sc.hydro_q)) if sc.hydro_q is not None and len(sc.hydro_q) else 0.0 for sc in scs]
+    out = [dict(name=sc.name, evacuees=k, q_peak=qp, t_evacuated=None, peak_class_count=[0] * 5)
+           for sc, k, qp in zip(scs, n, q)]
     t = 0.0
     while t < t_max and any(o["t_evacuated"] is None for o in out):
         ens.step(poll_steps)
@@ -166,12 +170,13 @@ def main(argv=None):
     args = ap.parse_args(argv)
     t0 = time.perf_counter()
     if args.quick:
-        res = dict(evacuation=run_evacuation(evacuation_pair(population=300), t_max=1200.0),
+        res = dict(evacuation=[run_evacuation(evacuation_pair(population=300, q_peak=q), t_max=1200.0)
+                               for q in (2.0, 10.0)],
                    deployment=run_deployment(deployment_sweep(population=300, groups=(0.2, 0.5), layers=(1, 2)),
                                              t_max=4 * 3600.0),
                    barrier_floods=barrier_floods(layers=(0, 1, 2), t_run=900.0))
     else:
-        res = dict(evacuation=run_evacuation(evacuation_pair()),
+        res = dict(evacuation=[run_evacuation(evacuation_pair(q_peak=q)) for q in BREACH_Q],
                    deployment=run_deployment(deployment_sweep()),
                    barrier_floods=barrier_floods())
     res["wall_s"] = time.perf_counter() - t0
