@@ -28,40 +28,44 @@
  *   R2 wetting/drying + terrain: non-negative hydrostatic reconstruction
  *      (Audusse et al. 2004), z_f = max(zL, zR), h* = h - (z_f - z); a face side
  *      with h* <= h_dry counts as dry and h* := 0.  Velocities come from the
- *      unreconstructed cell (0 if h <= h_dry).  The bed slope enters as the
- *      one-sided pressure correction 1/2 g h*^2 of the same reconstruction.
- *   R3 Eq. (2) prints "+ S" without a time factor; read as + dt S.
- *   R4 Manning friction: splitting point-implicit (Liang & Marche 2009) with a
+ *      unreconstructed cell (0 if h <= h_dry).
+ *   R3 the bed slope enters as the one-sided pressure correction 1/2 g h*^2 of
+ *      the same reconstruction (exactly zero for a lake at rest).
+ *   R4 Eq. (2) prints "+ S" without a time factor; read as + dt S.
+ *   R5 Manning friction: splitting point-implicit (Liang & Marche 2009) with a
  *      no-reversal limiter, applied after the flux update where h > h_dry.
- *   R5 dt = min(CFL * min_wet min(dx/(|u|+c), dy/(|v|+c)), dt_max), dt_max = 1 s;
+ *   R6 dt = min(CFL * min_wet min(dx/(|u|+c), dy/(|v|+c)), dt_max), dt_max = 1 s;
  *      dt_max when nothing is wet.
- *   R6 boundaries by ghost cells: wall = mirror (normal discharge negated; the
+ *   R7 g and h_dry are parameters (9.81 m/s^2 and 1e-5 m in every scenario).
+ *   R8 boundaries by ghost cells: wall = mirror (normal discharge negated; the
  *      wall face carries zero mass and tangential flux exactly); transmissive
  *      = copy.  The "slip" north side of sec. 3.1 is read as transmissive.
- *   R7 inflow: a line mass source on the cells along the inflow segment,
+ *   R9 inflow: a line mass source on the cells along the inflow segment,
  *      depth += (1/dn) * integral of q over the step; piecewise-linear q
  *      integrated exactly; no momentum added.
- *   R8 cleanup: h := max(h, 0) (clipped volume recorded), q := 0 where h <= h_dry.
- *   R9 coupled order per step: flood update with n and z of the previous step,
+ *   R10 coupled order per step: flood update with n and z of the previous step,
  *      then pedestrians with the new flood state, then write-back of n and z.
- *   R10 hazard: a dry cell (h <= h_dry) is class DRY at the agent's own base
+ *   R11 hazard: a dry cell (h <= h_dry) is class DRY at the agent's own base
  *      speed; class intervals are half-open [from, to); above 20 stays HIGHEST.
- *   R11 roughness: n_eff = n0 (1 + min(Np, cap)), recomputed every step from
+ *   R12 V in HR = (V + 0.5) h is max(|u|, |v|) as printed, not the speed.
+ *   R13 roughness: n_eff = n0 (1 + min(Np, cap)), recomputed every step from
  *      the active evacuees whose containing cell it is (not cumulative).
- *   R12 navigation: per-destination distance field (input); step toward the
+ *   R14 navigation: per-destination distance field (input); step toward the
  *      centre of the 8-neighbour with the smallest distance, ties in the order
  *      E, N, W, S, NE, NW, SW, SE; inside a destination cell toward its centre.
- *   R13 movement: social force of Helbing, Farkas & Vicsek (2000): exact
+ *   R15 movement: social force of Helbing, Farkas & Vicsek (2000): exact
  *      relaxation to v0 e over tau, exponential repulsion from neighbours in
  *      the 3x3 bins and from obstacle cells within r_cut, |v| <= v0, explicit
  *      position update with an axis-wise rejection of moves into obstacles or
  *      out of the domain.
- *   R14 arrival when the distance field at the new cell is <= r_arrive.
- *   R15 evacuees stay put until any cell is wet (evacuation trigger, sec. 2.4).
- *   R16 barrier: completed drops of a step are summed, then applied in order;
+ *   R16 arrival when the distance field at the new cell is <= r_arrive.
+ *   R17 evacuees stay put until any cell is wet (evacuation trigger, sec. 2.4).
+ *   R18 barrier: completed drops of a step are summed, then applied in order;
  *      one bag per drop; a cell-layer takes bags_per bags; z += layer thickness.
- *   R17 cell / bin indices are decided in FP32 (the GPU kernel's precision):
+ *   R19 cell / bin indices are decided in FP32 (the GPU kernel's precision):
  *      i = floor((float)x / (float)dx).
+ *   R21 cleanup after the update: h := max(h, 0) (clipped volume recorded),
+ *      q := 0 where h <= h_dry.
  */
 #include "fps_oracle.h"
 
@@ -168,7 +172,7 @@ void or_face(const or_params *P, double hL, double qnL, double qtL, double zL,
     if (hR > eps) { unR = qnR / hR; utR = qtR / hR; }
     if (P->flux == OR_FLUX_HLL) or_hll(P->g, hl, unL, utL, hr, unR, utR, F);
     else or_hllc(P->g, hl, unL, utL, hr, unR, utR, F);
-    if (wall) {                          /* R6: a wall passes no mass */
+    if (wall) {                          /* R8: a wall passes no mass */
         F[0] = 0.0;
         F[2] = 0.0;
     }
@@ -176,7 +180,7 @@ void or_face(const or_params *P, double hL, double qnL, double qtL, double zL,
     *hsR = hr;
 }
 
-/* exact integral of the piecewise-linear hydrograph over [a, b] (R7) */
+/* exact integral of the piecewise-linear hydrograph over [a, b] (R9) */
 static double hydro_q(int32_t nh, const double *ht, const double *hq, double t)
 {
     if (nh <= 0) return 0.0;
@@ -207,7 +211,7 @@ double or_hydro_integral(int32_t nh, const double *ht, const double *hq, double 
 }
 
 /* ------------------------------------------------------------------------ */
-/* Hazard rate and class (Table 1, sec. 2.4; R10)                             */
+/* Hazard rate and class (Table 1, sec. 2.4; R11, R12)                        */
 /* ------------------------------------------------------------------------ */
 int32_t or_hr_class(const or_params *P, double h, double qx, double qy, double *hr_out)
 {
@@ -225,14 +229,14 @@ int32_t or_hr_class(const or_params *P, double h, double qx, double qy, double *
     return OR_CLS_HIGHEST;
 }
 
-/* roughness write-back (sec. 2.4; R11) */
+/* roughness write-back (sec. 2.4; R13) */
 double or_n_eff(const or_params *P, int32_t np)
 {
     int32_t k = np < P->np_cap ? np : P->np_cap;
     return P->n_base + (double)k * P->n_base;
 }
 
-/* Manning friction, splitting point-implicit (R4) */
+/* Manning friction, splitting point-implicit (R5) */
 void or_friction(const or_params *P, double dt, double h, double n, double *qx, double *qy)
 {
     if (!(h > P->h_dry)) return;
@@ -254,7 +258,7 @@ void or_friction(const or_params *P, double dt, double h, double n, double *qx, 
 }
 
 /* ------------------------------------------------------------------------ */
-/* Time step (sec. 3; R5)                                                     */
+/* Time step (sec. 3; R6)                                                     */
 /* ------------------------------------------------------------------------ */
 double or_compute_dt(const or_sim *S)
 {
@@ -285,9 +289,9 @@ double or_mass(const or_sim *S)
 }
 
 /* ------------------------------------------------------------------------ */
-/* Finite-volume update, Eq. (2) with R1-R8                                   */
+/* Finite-volume update, Eq. (2) with R1-R9, R21                              */
 /* ------------------------------------------------------------------------ */
-/* the ghost of interior cell c across side s (R6) */
+/* the ghost of interior cell c across side s (R8) */
 static void ghost(const or_sim *S, int32_t side, int64_t c, double *h, double *qx, double *qy,
                   double *z, int *wall)
 {
@@ -369,7 +373,7 @@ void or_fv_step(or_sim *S, double dt)
         for (int32_t i = 0; i < nx; ++i) vout += FY[3 * ((int64_t)ny * nx + i)] * P->dx;
     S->v_out += vout * dt;
 
-    /* inflow depth for this step (R7) */
+    /* inflow depth for this step (R9) */
     double inc = 0.0;
     if (P->inflow_side >= 0) {
         double dn = P->inflow_side <= 1 ? P->dx : P->dy;
@@ -412,7 +416,7 @@ void or_fv_step(or_sim *S, double dt)
                     S->v_in += inc * P->dx * P->dy;
                 }
             }
-            /* cleanup (R8) */
+            /* cleanup (R21) */
             if (hn < 0.0) {
                 S->v_clip += -hn * P->dx * P->dy;
                 hn = 0.0;
@@ -421,7 +425,7 @@ void or_fv_step(or_sim *S, double dt)
                 qxn = 0.0;
                 qyn = 0.0;
             }
-            /* friction with the effective roughness (R4, R11) */
+            /* friction with the effective roughness (R5, R13) */
             or_friction(P, dt, hn, or_n_eff(P, S->np[c]), &qxn, &qyn);
             /* in place is safe: every face was computed before this loop */
             S->h[c] = hn;
@@ -443,7 +447,7 @@ void or_fv_step(or_sim *S, double dt)
 /* ------------------------------------------------------------------------ */
 int32_t or_cell_index(double x, double d, int32_t n)
 {
-    /* R17: decided in FP32; the result may lie outside [0, n) */
+    /* R19: decided in FP32; the result may lie outside [0, n) */
     float q = (float)x / (float)d;
     float f = floorf(q);
     if (f < -1.0f) return -1;
@@ -517,7 +521,7 @@ static int32_t nearest_exit(const or_sim *S, int32_t ci, int32_t cj)
     return best;
 }
 
-/* desired direction (R12) */
+/* desired direction (R14) */
 static void direction(const or_sim *S, int32_t d, int32_t ci, int32_t cj, double x, double y,
                       double *ex, double *ey)
 {
@@ -614,14 +618,14 @@ void or_ped_step(or_sim *S, double dt)
                 S->dest[a] = S->storage_dest;
             }
         }
-        /* evacuation trigger (R15); an agent without a destination stands */
+        /* evacuation trigger (R17); an agent without a destination stands */
         if ((S->role[a] == OR_ROLE_EVACUEE && !S->any_wet) || S->dest[a] < 0 ||
             S->dest[a] >= S->n_dest) {
             vx1[a] = 0.0; vy1[a] = 0.0;
             S->state[a] = (uint8_t)st;
             continue;
         }
-        /* social force (R13) */
+        /* social force (R15) */
         double ex, ey;
         direction(S, S->dest[a], ci, cj, x, y, &ex, &ey);
         double k = exp(-dt / P->tau);
@@ -675,7 +679,7 @@ void or_ped_step(or_sim *S, double dt)
                 vy = 0.0;
             }
         }
-        /* move with axis-wise rejection (R13) */
+        /* move with axis-wise rejection (R15) */
         double xn = x + dt * vx;
         int32_t ni = or_cell_index(xn, P->dx, nx);
         if (ni < 0 || ni >= nx || !S->walk[(int64_t)cj * nx + ni]) {
@@ -690,7 +694,7 @@ void or_ped_step(or_sim *S, double dt)
             vy = 0.0;
             nj = cj;
         }
-        /* arrival (R14) */
+        /* arrival (R16) */
         if (dist_at(S, S->dest[a], ni, nj) <= (float)P->r_arrive) {
             if (st == OR_ST_EVAC) {
                 st = OR_ST_EXITED;
@@ -710,7 +714,7 @@ void or_ped_step(or_sim *S, double dt)
     for (int32_t a = 0; a < na; ++a) {
         S->x[a] = x1[a]; S->y[a] = y1[a]; S->vx[a] = vx1[a]; S->vy[a] = vy1[a];
     }
-    /* barrier fill (R16) */
+    /* barrier fill (R18) */
     S->drops_total += drops;
     if (!S->done && S->nline > 0) {
         S->bags += drops;
