@@ -250,7 +250,8 @@ int fps_time_flood(fps_sim* sim, int32_t reps, double* ms_per_launch);
 int fps_set_rows_per_wave(fps_sim* sim, int32_t rows);
 
 /* Pick the rows per wave for this grid by timing the flood update on the
-   bound state (outputs to scratch; the simulation state is not advanced).
+   bound state (outputs to scratch; the simulation state is not advanced):
+   every H in three interleaved passes, each H keeping its fastest pass.
    cache_path (host string, may be NULL): a text file of lines
    "<gfx arch> <nx> <ny> <rows> <ms>"; a matching line is used instead of
    timing, a new result is appended.  rows_out / ms_out may be NULL. */
