@@ -266,6 +266,7 @@ double or_compute_dt(const or_sim *S)
     int64_t nc = (int64_t)P->nx * P->ny;
     double lam = INFINITY;
     int any = 0;
+#pragma omp parallel for schedule(static) reduction(min : lam) reduction(| : any)
     for (int64_t c = 0; c < nc; ++c) {
         double h = S->h[c];
         if (!(h > P->h_dry)) continue;
@@ -319,6 +320,7 @@ void or_fv_step(or_sim *S, double dt)
            *HYR = malloc(sizeof(double) * nfy);
     double vout = 0.0;
 
+#pragma omp parallel for schedule(static)
     for (int32_t j = 0; j < ny; ++j) {
         for (int32_t f = 0; f <= nx; ++f) {
             double hL, qxL, qyL, zL, hR, qxR, qyR, zR;
@@ -340,6 +342,7 @@ void or_fv_step(or_sim *S, double dt)
             or_face(P, hL, qxL, qyL, zL, hR, qxR, qyR, zR, wall, &FX[3 * k], &HXL[k], &HXR[k]);
         }
     }
+#pragma omp parallel for schedule(static)
     for (int32_t j = 0; j <= ny; ++j) {
         for (int32_t i = 0; i < nx; ++i) {
             double hL, qxL, qyL, zL, hR, qxR, qyR, zR;
@@ -381,6 +384,10 @@ void or_fv_step(or_sim *S, double dt)
     }
 
     const double lx = dt / P->dx, ly = dt / P->dy;
+    /* inflow and clipped volumes: one partial per row, added in row order below,
+       so any number of threads gives the same sums */
+    double *row_in = calloc((size_t)ny, sizeof(double)), *row_clip = calloc((size_t)ny, sizeof(double));
+#pragma omp parallel for schedule(static)
     for (int32_t j = 0; j < ny; ++j) {
         for (int32_t i = 0; i < nx; ++i) {
             int64_t c = (int64_t)j * nx + i;
@@ -413,12 +420,12 @@ void or_fv_step(or_sim *S, double dt)
                 if (P->inflow_side == 3 && j == ny - 1) along = i;
                 if (along >= P->inflow_c0 && along < P->inflow_c1) {
                     hn += inc;
-                    S->v_in += inc * P->dx * P->dy;
+                    row_in[j] += inc * P->dx * P->dy;
                 }
             }
             /* cleanup (R21) */
             if (hn < 0.0) {
-                S->v_clip += -hn * P->dx * P->dy;
+                row_clip[j] += -hn * P->dx * P->dy;
                 hn = 0.0;
             }
             if (!(hn > eps)) {
@@ -433,6 +440,12 @@ void or_fv_step(or_sim *S, double dt)
             S->qy[c] = qyn;
         }
     }
+    for (int32_t j = 0; j < ny; ++j) {
+        S->v_in += row_in[j];
+        S->v_clip += row_clip[j];
+    }
+    free(row_in);
+    free(row_clip);
     int wet = 0;
     int64_t nc = (int64_t)nx * ny;
     for (int64_t c = 0; c < nc; ++c)
@@ -575,6 +588,8 @@ void or_ped_step(or_sim *S, double dt)
     const int32_t Rx = (int32_t)ceil(P->r_cut / P->dx - 1e-9), Ry = (int32_t)ceil(P->r_cut / P->dy - 1e-9);
     int32_t drops = 0;
 
+    /* every agent reads the start-of-step state and writes only its own record */
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : drops)
     for (int32_t a = 0; a < na; ++a) {
         double x = S->x[a], y = S->y[a];
         x1[a] = x; y1[a] = y; vx1[a] = S->vx[a]; vy1[a] = S->vy[a];

@@ -16,6 +16,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_LIB_OMP_PATH = os.path.join(_HERE, "liboracle_omp.so")
 
 _dp = C.POINTER(C.c_double)
 _fp = C.POINTER(C.c_float)
@@ -67,24 +68,30 @@ class OrSim(C.Structure):
     ]
 
 
-def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (plain -O2, no FMA contraction, no fast-math)."""
+def build(force: bool = False, omp: bool = False) -> str:
+    """Compile the oracle with gcc (plain -O2, no FMA contraction, no
+    fast-math).  omp=True builds the same source with OpenMP (loops over grid
+    rows and over agents; every result identical to the serial build) for
+    timing on all host cores."""
     src = os.path.join(_HERE, "fps_oracle.c")
-    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(src):
+    path = _LIB_OMP_PATH if omp else _LIB_PATH
+    if force or not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(src):
+        tmp = path + f".tmp{os.getpid()}"
         subprocess.check_call([
             "gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
-            "-fno-fast-math", "-Wall", "-o", _LIB_PATH, src, "-lm"])
-    return _LIB_PATH
+            "-fno-fast-math", "-Wall", "-Wno-unknown-pragmas", *(["-fopenmp"] if omp else []),
+            "-o", tmp, src, "-lm"])
+        os.replace(tmp, path)
+    return path
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        _lib = C.CDLL(build())
-        L = _lib
+def lib(omp: bool = False):
+    """The loaded oracle (serial, or the OpenMP build with omp=True)."""
+    if omp not in _libs:
+        L = _libs[omp] = C.CDLL(build(omp=omp))
         L.or_hllc.argtypes = [C.c_double] * 7 + [_dp]
         L.or_hll.argtypes = [C.c_double] * 7 + [_dp]
         L.or_face.argtypes = [C.POINTER(OrParams)] + [C.c_double] * 8 + [C.c_int, _dp, _dp, _dp]
@@ -109,7 +116,7 @@ def lib():
         L.or_run.argtypes = [C.POINTER(OrSim), C.c_int32, _dp, _dp, C.c_int32]
         L.or_mass.argtypes = [C.POINTER(OrSim)]
         L.or_mass.restype = C.c_double
-    return _lib
+    return _libs[omp]
 
 
 def _ptr(a, t):
@@ -141,8 +148,8 @@ def make_params(desc, ped=None) -> OrParams:
 class OracleSim:
     """FP64 oracle state built from a ``inputs.Scenario``; arrays are numpy, kept alive here."""
 
-    def __init__(self, sc):
-        L = lib()
+    def __init__(self, sc, omp: bool = False):
+        self.L = L = lib(omp)
         self.sc = sc
         d = sc.desc
         self.S = OrSim()
@@ -213,7 +220,7 @@ class OracleSim:
     # -- views -----------------------------------------------------------
     def bins_dims(self):
         a = [C.c_int32() for _ in range(4)]
-        lib().or_bins_dims(C.byref(self.S.P), *[C.byref(v) for v in a])
+        self.L.or_bins_dims(C.byref(self.S.P), *[C.byref(v) for v in a])
         return tuple(v.value for v in a)
 
     @property
@@ -226,7 +233,7 @@ class OracleSim:
                 self.qy.reshape(d.ny, d.nx), self.z.reshape(d.ny, d.nx))
 
     def mass(self):
-        return lib().or_mass(C.byref(self.S))
+        return self.L.or_mass(C.byref(self.S))
 
     def set_fields(self, h, qx, qy, z=None):
         self.h[:] = np.asarray(h, dtype=np.float64).reshape(-1)
@@ -238,22 +245,22 @@ class OracleSim:
 
     # -- stepping --------------------------------------------------------
     def compute_dt(self):
-        return lib().or_compute_dt(C.byref(self.S))
+        return self.L.or_compute_dt(C.byref(self.S))
 
     def fv_step(self, dt):
-        lib().or_fv_step(C.byref(self.S), float(dt))
+        self.L.or_fv_step(C.byref(self.S), float(dt))
         self.S.t += float(dt)
         self.S.step += 1
 
     def run(self, n, dts=None, with_peds=True):
         dt_used = np.zeros(n, dtype=np.float64)
         d = None if dts is None else np.ascontiguousarray(dts, dtype=np.float64)
-        lib().or_run(C.byref(self.S), int(n), _ptr(d, _dp) if d is not None else None,
+        self.L.or_run(C.byref(self.S), int(n), _ptr(d, _dp) if d is not None else None,
                      _ptr(dt_used, _dp), int(bool(with_peds) and self.S.na > 0))
         return dt_used
 
     def coupled_step(self, dt=0.0):
-        return lib().or_coupled_step(C.byref(self.S), float(dt))
+        return self.L.or_coupled_step(C.byref(self.S), float(dt))
 
 
 # -- free functions used by the pins ------------------------------------------
