@@ -2,17 +2,22 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
 
-Workload (synthetic shopping centre): 512 x 512 cells of 0.25 m with random
-+3 m building blocks, a triangular inflow of 2 m^2/s peak over 600 s through
-the central 30% of the south side, a transmissive north side, and 2,000
-evacuees heading for two north exits.  One step = one coupled time step:
-flood update (Eq. 2), pedestrian step (hazard, movement, roughness count),
-neighbour re-binning and sandbag write-back, all on the GPU.
+Headline workload (the large sweep): 32 synthetic shopping centres of
+2048 x 2048 cells of 0.25 m (random +3 m building blocks, a completed sandbag
+line of U(0.2, 1.0) m, the triangular south inflow already under way, the
+free area already wet), 50,000 evacuees each heading for the nearest of two
+north exits: 134 M cells and 1.6 M people per step, stepped as one ensemble.
+One step = one coupled time step of every scenario: flood update (Eq. 2),
+pedestrian step (hazard, movement, roughness count), neighbour re-binning and
+sandbag write-back, all on the GPU, from one set of graph-replayed launches.
 
 Prints one JSON line: FV cell-updates/s over the K timed steps (inputs
-resident in HBM), the roofline of the flood-update kernel (HIP events around
-each launch, on the stream the kernels run on), and the FP64 CPU oracle timed
-on a bounded sample of the same workload on this host.
+resident in HBM), the roofline of the flood-update launch (HIP events around
+back-to-back launches on the stream the kernels run on), the FP64 CPU oracle
+(OpenMP on every host core) timed on a bounded sample of the same workload,
+and secondary sections: the 512^2 shopping centre (a cache-resident,
+latency-bound rate), an 8192^2 fully wet probe with the copy ceilings, the
+64-scenario intervention sweep, and the learned update.
 """
 import argparse
 import hashlib
@@ -51,17 +56,45 @@ def measured_traffic(workload, rows):
     return rec.get("hbm_bytes_per_launch_by_rows", {}).get(str(rows))
 
 
-def cpu_baseline(sc, n_steps):
-    """The FP64 oracle (single thread) on the first n_steps of the same workload."""
+def host_info():
+    """Host cores seen by this process and the CPU model (lscpu)."""
+    import subprocess
+    info = {"nproc": os.cpu_count(), "affinity_cores": len(os.sched_getaffinity(0))}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core", "CPU(s)"):
+                info[k.strip()] = v.strip()
+    except Exception as exc:      # lscpu missing: the counts above still stand
+        info["lscpu"] = f"unavailable ({exc})"
+    return info
+
+
+def omp_threads():
+    """Threads an OpenMP parallel region of the oracle's build uses."""
+    import ctypes
+    try:
+        return int(ctypes.CDLL("libgomp.so.1").omp_get_max_threads())
+    except OSError:
+        return None
+
+
+def cpu_baseline(sc, n_steps, what, omp=True):
+    """The FP64 oracle (OpenMP build on every host core, or one thread) on the
+    first n_steps of one scenario of the workload."""
     from oracle import oracle as O
-    ref = O.OracleSim(sc)
+    ref = O.OracleSim(sc, omp=omp)
     t0 = time.perf_counter()
     ref.run(n_steps)
     dt = time.perf_counter() - t0
     cells = sc.desc.nx * sc.desc.ny
-    return {"value": cells * n_steps / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {n_steps} coupled steps of the same 512x512 workload "
-                      f"({cells * n_steps:.3g} cell-updates, {dt:.1f} s, FP64 C, one thread)"}
+    cores = omp_threads() if omp else 1
+    return {"value": cells * n_steps / dt, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {n_steps} coupled steps of {what} ({cells * n_steps:.3g} cell-updates, "
+                      f"{len(sc.agents['x']) if sc.agents else 0} agents, {dt:.1f} s wall, FP64 C, "
+                      f"{'OpenMP, ' + str(cores) + ' threads' if omp else 'one thread'})",
+            "wall_s": dt}
 
 
 def ensemble_section(args, stream):
@@ -262,16 +295,167 @@ def surrogate_probe(fwd_only=False):
     print(json.dumps({"surrogate_probe": out}), flush=True)
 
 
+def headline_section(args, stream):
+    """The large sweep as one ensemble: K timed coupled steps (graph replay),
+    then the flood launch timed alone and the per-kernel breakdown."""
+    import torch
+    from paper_1908_05232_amd import fps, inputs as I
+    t0 = time.perf_counter()
+    scs = I.large_sweep(args.large_s, n=args.large_n, n_evac=args.large_people, workers=8)
+    log(f"headline: {len(scs)} scenarios of {args.large_n}^2 built in {time.perf_counter() - t0:.1f} s")
+    cells = sum(sc.desc.nx * sc.desc.ny for sc in scs)
+    agents = sum(len(sc.agents["x"]) for sc in scs)
+    sample = scs[0]
+    ens = fps.Ensemble(scs, stream=stream)
+    del scs
+    if args.rows:
+        for m in ens.members:
+            m.set_rows_per_wave(args.rows)
+    else:
+        ens.autotune()
+    rows = sorted({m.rows_per_wave() for m in ens.members})
+    log(f"headline: rows per wave {rows}")
+    ens.set_graph(0 if args.no_graph else 16)
+    ens.step(args.warmup)
+    torch.cuda.synchronize()
+    d0 = [m.diag() for m in ens.members]
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    ens.step(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    d1 = [m.diag() for m in ens.members]
+    log(f"headline: {args.steps} steps in {ms:.2f} ms")
+    kms = ens.step_profiled(args.profile_steps)
+    fv_ms = ens.time_flood(args.flood_reps)
+    ens.set_flux(fps.FPS_FLUX_HLL)
+    fv_ms_hll = ens.time_flood(args.flood_reps)
+    ens.set_flux(fps.FPS_FLUX_HLLC)
+    wet = sum(float((m.h > 1e-5).float().mean()) for m in ens.members) / len(ens.members)
+    out = {
+        "cells": cells, "agents": agents, "rows": rows, "ms": ms, "fv_ms": fv_ms,
+        "config": {"workload": f"large_sweep_{len(ens.members)}x{args.large_n}",
+                   "scenarios": len(ens.members), "grid": [args.large_n, args.large_n], "dx_m": 0.25,
+                   "cells_per_step": cells, "evacuees": agents, "rows_per_wave": rows,
+                   "steps_timed": args.steps,
+                   "sim_time_s": [min(d["t"] for d in d0), max(d["t"] for d in d1)],
+                   "wet_cell_fraction_after": wet,
+                   "recipe": "inputs.large_sweep(32, n=2048, n_evac=50000, seed=5)"},
+        "secondary": {
+            "ped-steps/s": (sum(d["ped_steps"] for d in d1) - sum(d["ped_steps"] for d in d0)) / (ms * 1e-3),
+            "scenario_steps_per_s": len(ens.members) * args.steps / (ms * 1e-3),
+            "flood_update_ms_per_launch": fv_ms,
+            "flood_update_ms_per_launch_hll_flux": fv_ms_hll,
+            "kernel_ms_per_launch_in_step": {"flood_update": kms[0], "ped_step": kms[1], "end_of_step": kms[2],
+                                             "bin_place": kms[3], "bin_sort": kms[4]}},
+    }
+    ens.close()
+    del ens
+    torch.cuda.empty_cache()
+    return out, sample
+
+
+def cache_resident_section(args, stream):
+    """The 512^2 shopping centre with 2,000 evacuees: a 12.6 MB working set that
+    stays in the caches, so its rate is set by launch and dependency latency."""
+    import torch
+    from paper_1908_05232_amd import fps, inputs as I
+    sc = I.shopping_centre(n=512)
+    cells = sc.desc.nx * sc.desc.ny
+    sim = fps.Sim(sc, stream=stream)
+    rows, _ = sim.autotune()
+    sim.set_graph(0 if args.no_graph else 64)
+    sim.step(args.small_warmup)
+    torch.cuda.synchronize()
+    d0 = sim.diag()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    sim.step(args.small_steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    d1 = sim.diag()
+    kms = sim.step_profiled(500)
+    fv_ms = sim.time_flood(500)
+    sim.close()
+    return {"workload": "shopping_centre_512 (cache-resident rate)", "bound": "latency",
+            "cells": cells, "evacuees": len(sc.agents["x"]), "rows_per_wave": rows,
+            "steps": args.small_steps, "ms_per_step": ms / args.small_steps,
+            "cell_updates_per_s": cells * args.small_steps / (ms * 1e-3),
+            "ped_steps_per_s": (d1["ped_steps"] - d0["ped_steps"]) / (ms * 1e-3),
+            "sim_time_s": [d0["t"], d1["t"]],
+            "flood_update_ms_per_launch": fv_ms,
+            "flood_update_GBs_algorithmic": FV_BYTES_PER_CELL * cells / (fv_ms * 1e-3) / 1e9,
+            "kernel_ms_per_launch_in_step": {"flood_update": kms[0], "ped_step": kms[1], "end_of_step": kms[2],
+                                             "bin_place": kms[3], "bin_sort": kms[4]}}
+
+
+def probe_section(args, stream):
+    """The flood kernel on one fully wet 8192^2 grid, beside the copy ceilings
+    of the part (torch's device copy and the library's own streaming copy)."""
+    import torch
+    from paper_1908_05232_amd import fps, inputs as I
+    big = I.wet_probe(args.probe_n)
+    bsim = fps.Sim(big, stream=stream)
+    del big
+    brows, _ = bsim.autotune()
+    if args.no_graph:
+        bsim.set_graph(0)
+    bsim.step(4)
+    bms = bsim.time_flood(args.probe_steps)
+    bsim.set_flux(fps.FPS_FLUX_HLL)
+    bms_hll = bsim.time_flood(args.probe_steps)
+    bcells = args.probe_n * args.probe_n
+    bach = FV_BYTES_PER_CELL * bcells / (bms * 1e-3) / 1e9
+    probe = {"workload": f"wet_probe_{args.probe_n} (fully wet dam break, {bcells} cells)",
+             "rows_per_wave": brows,
+             "ms_per_launch": bms, "cell_updates_per_s": bcells / (bms * 1e-3),
+             "achieved_GBs": bach, "frac": bach / HBM_PEAK_GBS,
+             "hll_flux_ms_per_launch": bms_hll,
+             "working_set_MB": (FV_BYTES_PER_CELL + 12) * bcells / 1e6}
+    bsim.close()
+    del bsim
+    torch.cuda.empty_cache()
+    # the practical streaming rate of the part: a plain 1 GiB device copy
+    # (bytes read + bytes written per second)
+    ca = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    cb = torch.empty_like(ca)
+    for _ in range(3):
+        cb.copy_(ca)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        cb.copy_(ca)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * ca.numel() * 4 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    probe["copy_1GiB_GBs"] = copy_gbs
+    probe["frac_of_copy"] = bach / copy_gbs
+    del ca, cb
+    torch.cuda.empty_cache()
+    return probe
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20000)
-    ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--profile-steps", type=int, default=500)
-    ap.add_argument("--cpu-steps", type=int, default=1000)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--large-s", type=int, default=32, help="scenarios of the headline sweep")
+    ap.add_argument("--large-n", type=int, default=2048, help="grid side of the headline sweep")
+    ap.add_argument("--large-people", type=int, default=50000, help="evacuees per scenario")
+    ap.add_argument("--profile-steps", type=int, default=20)
+    ap.add_argument("--flood-reps", type=int, default=50)
+    ap.add_argument("--cpu-steps", type=int, default=40)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--oracle-full", action="store_true",
+                    help="also time the oracle over the whole 20,000-step 512^2 run (one thread and OpenMP)")
     ap.add_argument("--rows", type=int, default=0,
-                    help="rows per wave of the flood update on the main workload (0: autotune)")
+                    help="rows per wave of the flood update on the headline workload (0: autotune)")
+    ap.add_argument("--small-steps", type=int, default=20000)
+    ap.add_argument("--small-warmup", type=int, default=200)
+    ap.add_argument("--no-small", action="store_true")
     ap.add_argument("--probe-n", type=int, default=8192,
                     help="side of the fully wet grid used for the HBM probe (0 = skip)")
     ap.add_argument("--probe-steps", type=int, default=50)
@@ -297,6 +481,8 @@ def main():
                     help="only time the surrogate kernels (profiler runs) and exit")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of 1 GiB (counter calibration) and exit")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the headline workload (profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the library has no multi-GPU path); got --gpus {args.gpus}",
@@ -304,7 +490,7 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_1908_05232_amd import fps, inputs as I
+    from paper_1908_05232_amd import fps  # noqa: F401  (fails loudly without the HIP library)
 
     if args.sur_probe:
         surrogate_probe(fwd_only=args.sur_probe == "forward")
@@ -320,88 +506,13 @@ def main():
         print(json.dumps({"copy_probe_bytes_each_way": 4 * n}), flush=True)
         return
 
-    workload = "shopping_centre_512"
-    sc = I.shopping_centre(n=512)
-    cells = sc.desc.nx * sc.desc.ny
     stream = torch.cuda.current_stream()
-    sim = fps.Sim(sc, stream=stream)
-    if args.rows:
-        sim.set_rows_per_wave(args.rows)
-        rows = args.rows
-    else:
-        rows, _ = sim.autotune()      # flood-update tile shape for this grid
-    # 64 steps per captured graph (fewer graph launches between steps than
-    # the library's default of 16)
-    sim.set_graph(0 if args.no_graph else 64)
-
-    sim.step(args.warmup)
-    torch.cuda.synchronize()
-    d0 = sim.diag()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    sim.step(args.steps)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1)
-    d1 = sim.diag()
+    head, sample = headline_section(args, stream)
+    cells, ms, fv_ms = head["cells"], head["ms"], head["fv_ms"]
+    workload = head["config"]["workload"]
     value = cells * args.steps / (ms * 1e-3)
-    ped_rate = (d1["ped_steps"] - d0["ped_steps"]) / (ms * 1e-3)
-
-    # per-launch duration of each kernel, HIP events around every launch (breakdown)
-    kms = sim.step_profiled(args.profile_steps)
-    # the flood update alone, HIP events around back-to-back launches on the
-    # stream the kernels run on (the events' own cost amortised)
-    fv_ms = sim.time_flood(args.profile_steps)
-    # the HLL variant of the face flux on the same state (timing only)
-    sim.set_flux(fps.FPS_FLUX_HLL)
-    fv_ms_hll = sim.time_flood(args.profile_steps)
-    sim.set_flux(fps.FPS_FLUX_HLLC)
     achieved = FV_BYTES_PER_CELL * cells / (fv_ms * 1e-3) / 1e9
-    traffic = measured_traffic(workload, rows)
-
-    probe = None
-    if args.probe_n > 0:
-        # the same flood kernel on a working set well beyond the 256 MB cache
-        big = I.wet_probe(args.probe_n)
-        bsim = fps.Sim(big, stream=stream)
-        del big
-        brows, _ = bsim.autotune()
-        if args.no_graph:
-            bsim.set_graph(0)
-        bsim.step(4)
-        bms = bsim.time_flood(args.probe_steps)
-        bsim.set_flux(fps.FPS_FLUX_HLL)
-        bms_hll = bsim.time_flood(args.probe_steps)
-        bcells = args.probe_n * args.probe_n
-        bach = FV_BYTES_PER_CELL * bcells / (bms * 1e-3) / 1e9
-        probe = {"workload": f"wet_probe_{args.probe_n} (fully wet dam break, {bcells} cells)",
-                 "rows_per_wave": brows,
-                 "ms_per_launch": bms, "cell_updates_per_s": bcells / (bms * 1e-3),
-                 "achieved_GBs": bach, "frac": bach / HBM_PEAK_GBS,
-                 "hll_flux_ms_per_launch": bms_hll,
-                 "working_set_MB": (FV_BYTES_PER_CELL + 12) * bcells / 1e6}
-        bsim.close()
-        del bsim
-        torch.cuda.empty_cache()
-        # the practical streaming rate of the part: a plain 1 GiB device copy
-        # (bytes read + bytes written per second)
-        ca = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
-        cb = torch.empty_like(ca)
-        for _ in range(3):
-            cb.copy_(ca)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(10):
-            cb.copy_(ca)
-        e1.record()
-        torch.cuda.synchronize()
-        copy_gbs = 2 * ca.numel() * 4 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
-        probe["copy_1GiB_GBs"] = copy_gbs
-        probe["frac_of_copy"] = bach / copy_gbs
-        del ca, cb
-        torch.cuda.empty_cache()
-
+    traffic = measured_traffic(workload, head["rows"][0]) if len(head["rows"]) == 1 else None
     out = {
         "metric": "FV cell-updates/s",
         "value": value,
@@ -415,27 +526,35 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": workload, "cells": cells, "dx_m": sc.desc.dx, "rows_per_wave": rows,
-                   "evacuees": len(sc.agents["x"]), "steps_timed": args.steps,
-                   "sim_time_s": [d0["t"], d1["t"]]},
-        "secondary": {"ped-steps/s": ped_rate,
-                      "flood_update_ms_per_launch": fv_ms,
-                      "flood_update_ms_per_launch_hll_flux": fv_ms_hll,
-                      "kernel_ms_per_launch_in_step": {"flood_update": kms[0], "ped_step": kms[1],
-                                               "end_of_step": kms[2], "bin_place": kms[3],
-                                               "bin_sort": kms[4]},
-                      "hbm_probe": probe},
+        "config": head["config"],
+        "secondary": head["secondary"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "fv_step_kernel", "bytes_per_cell": FV_BYTES_PER_CELL},
+                     "kernel": "fv_step_kernel", "bytes_per_cell": FV_BYTES_PER_CELL,
+                     "launch": f"one launch over the {cells} cells of every scenario",
+                     "ms_per_launch": fv_ms},
     }
-    sim.close()
-    if not args.no_ensemble:
-        out["secondary"]["ensemble"] = ensemble_section(args, stream)
-    if not args.no_surrogate:
-        out["secondary"]["surrogate"] = surrogate_section(args)
+    if not args.headline_only:
+        if not args.no_small:
+            out["secondary"]["cache_resident_512"] = cache_resident_section(args, stream)
+            log("cache-resident 512^2 done")
+        if args.probe_n > 0:
+            out["secondary"]["hbm_probe"] = probe_section(args, stream)
+            log("probe done")
+        if not args.no_ensemble:
+            out["secondary"]["ensemble"] = ensemble_section(args, stream)
+        if not args.no_surrogate:
+            out["secondary"]["surrogate"] = surrogate_section(args)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(sc, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(sample, args.cpu_steps, "one 2048^2 scenario of the same sweep")
+        one = cpu_baseline(sample, max(2, args.cpu_steps // 4), "one 2048^2 scenario of the same sweep", omp=False)
+        out["secondary"]["oracle_timing"] = {"host": host_info(), "one_thread": one}
+        if args.oracle_full:
+            from paper_1908_05232_amd import inputs as I
+            sc2 = I.shopping_centre(n=512)
+            out["secondary"]["oracle_timing"]["shopping_centre_512_full"] = {
+                "openmp": cpu_baseline(sc2, 20000, "the 512^2 shopping centre (whole run)"),
+                "one_thread": cpu_baseline(sc2, 20000, "the 512^2 shopping centre (whole run)", omp=False)}
     print(json.dumps(out), flush=True)
 
 

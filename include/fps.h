@@ -249,6 +249,9 @@ int fps_time_flood(fps_sim* sim, int32_t reps, double* ms_per_launch);
    mass diagnostic's summation order changes.  Synchronises. */
 int fps_set_rows_per_wave(fps_sim* sim, int32_t rows);
 
+/* Current tile shape of the flood update (rows per wave) into *rows (host). */
+int fps_get_rows_per_wave(fps_sim* sim, int32_t* rows);
+
 /* Pick the rows per wave for this grid by timing the flood update on the
    bound state (outputs to scratch; the simulation state is not advanced):
    every H in three interleaved passes, each H keeping its fastest pass.
@@ -291,6 +294,11 @@ int fps_ens_set_flux(fps_ens* ens, int32_t flux);
    depend on the choice.  cache_path is accepted and not used (the best values
    depend on the whole mix of grids).  Synchronises. */
 int fps_ens_autotune(fps_ens* ens, const char* cache_path);
+/* Average duration of the ensemble's flood-update launch (one launch over
+   the tiles of every member) in the current tile shapes: reps back-to-back
+   launches on the current states between two HIP events on the ensemble's
+   stream; the states are left unchanged.  Synchronises. */
+int fps_ens_time_flood(fps_ens* ens, int32_t reps, double* ms_per_launch);
 /* Number of scenarios that have not reached their end time.  Synchronises. */
 int fps_ens_active(fps_ens* ens, int32_t* n_active);
 const char* fps_ens_last_error(const fps_ens* ens);
@@ -308,6 +316,14 @@ typedef struct fps_sur fps_sur;
    with the padded channel counts (16 inputs, 16 outputs in the last layer). */
 int32_t fps_sur_param_count(void);
 size_t fps_sur_workspace_bytes(int32_t max_batch, int32_t H, int32_t W);
+/* Caps on the blocks the convolution and weight-gradient kernels launch
+   (0 = the defaults: one block per compute unit, and up to 512 blocks of
+   weight-gradient partials).  Both kernels walk their tiles with a stride of
+   the grid, so a cap makes every block take several tiles at any size (used to
+   test that path on small images); the forward pass and input gradients are
+   unchanged bit for bit, the weight gradients change only in the grouping of
+   their FP32 partial sums.  FPS_E_INVALID for a negative cap. */
+int fps_sur_set_blocks(fps_sur* sur, int32_t conv_blocks, int32_t wgrad_blocks);
 int fps_sur_create(int32_t max_batch, int32_t H, int32_t W, void* ws, size_t ws_bytes, void* stream,
                    fps_sur** out);
 void fps_sur_destroy(fps_sur* sur);

@@ -981,6 +981,23 @@ int fps_ens_autotune(fps_ens* e, const char* cache_path)
     return FPS_OK;
 }
 
+int fps_ens_time_flood(fps_ens* e, int32_t reps, double* ms_per_launch)
+{
+    if (!e || !ms_per_launch || reps < 1) return fail(nullptr, FPS_E_INVALID, "fps_ens_time_flood: bad argument");
+    for (fps_sim* s : e->m)
+        if (!s->fields_bound) return efail(e, FPS_E_STATE, "fps_ens_time_flood: scenario %d: fields not bound", s->idx);
+    float ms = 0.0f;
+    int rc = time_ensemble_flood(e, reps, &ms);
+    if (rc != FPS_OK) return rc;
+    *ms_per_launch = ms;
+    // the timing launches wrote scratch partials and the wetness flags
+    for (fps_sim* s : e->m) {
+        rc = prime(s);
+        if (rc != FPS_OK) return efail(e, rc, "%s", s->err);
+    }
+    return FPS_OK;
+}
+
 int fps_ens_active(fps_ens* e, int32_t* n_active)
 {
     if (!e || !n_active) return fail(nullptr, FPS_E_INVALID, "fps_ens_active: NULL argument");
@@ -1336,6 +1353,13 @@ int fps_set_rows_per_wave(fps_sim* s, int32_t rows)
     HIPCHK(s, hipStreamSynchronize(s->eng->stream));
     s->H = rows;
     mark_dirty(s);
+    return FPS_OK;
+}
+
+int fps_get_rows_per_wave(fps_sim* s, int32_t* rows)
+{
+    if (!s || !rows) return fail(s, FPS_E_INVALID, "fps_get_rows_per_wave: NULL argument");
+    *rows = s->H;
     return FPS_OK;
 }
 

@@ -591,6 +591,7 @@ using namespace fps_sur_impl;
 struct fps_sur {
     int max_batch = 0, H = 0, W = 0;
     int cus = 256;                   // compute units of the device (persistent convolution blocks)
+    int conv_cap = 0, wgrad_cap = 0; // caps on the blocks of the two kernels (0 = none)
     hipStream_t stream = nullptr;
     char err[512] = "";
     float *params = nullptr, *m = nullptr, *v = nullptr, *grads = nullptr;
@@ -686,7 +687,8 @@ int conv(fps_sur* s, int n, const bf16* x, const bf16* w, const float* b, void* 
     auto k = conv_kernel<CIN, COUT, MODE>;
     SCHK(s, hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     const int tiles = n * (s->H / CTH) * (s->W / TW);
-    const int blocks = std::min(tiles, s->cus);          // persistent: one block per compute unit
+    // persistent: one block per compute unit (or fewer, when capped)
+    const int blocks = std::min(tiles, s->conv_cap > 0 ? std::min(s->conv_cap, s->cus) : s->cus);
     hipLaunchKernelGGL(k, dim3(blocks), dim3(kConvThreads), lds, s->stream, x, w, b, y, n, s->H, s->W, mask);
     SCHK(s, hipGetLastError());
     return FPS_OK;
@@ -700,7 +702,7 @@ int wgrad(fps_sur* s, int n, const bf16* x, const bf16* dz, int layer)
     auto k = wgrad_kernel<CIN, COUT>;
     SCHK(s, hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     const int tiles = n * (s->H / TH) * (s->W / TW);
-    const int blocks = std::min(tiles, kWgradBlocks);
+    const int blocks = std::min(tiles, s->wgrad_cap > 0 ? std::min(s->wgrad_cap, kWgradBlocks) : kWgradBlocks);
     hipLaunchKernelGGL(k, dim3(blocks), dim3(kWgThreads), lds, s->stream, x, dz, s->wpart, s->bpart, n, s->H,
                        s->W);
     SCHK(s, hipGetLastError());
@@ -746,6 +748,15 @@ int check_args(fps_sur* s, int n)
 extern "C" {
 
 int32_t fps_sur_param_count(void) { return (int32_t)total_params(); }
+
+int fps_sur_set_blocks(fps_sur* s, int32_t conv_blocks, int32_t wgrad_blocks)
+{
+    if (!s) return sfail(nullptr, FPS_E_INVALID, "fps_sur_set_blocks: sur is NULL");
+    if (conv_blocks < 0 || wgrad_blocks < 0) return sfail(s, FPS_E_INVALID, "fps_sur_set_blocks: negative cap");
+    s->conv_cap = conv_blocks;
+    s->wgrad_cap = wgrad_blocks;
+    return FPS_OK;
+}
 
 size_t fps_sur_workspace_bytes(int32_t max_batch, int32_t H, int32_t W)
 {

@@ -87,9 +87,11 @@ EXPORTS = {
     "fps_ens_set_graph": (C.c_int, [_vp, C.c_int32]),
     "fps_ens_autotune": (C.c_int, [_vp, C.c_char_p]),
     "fps_ens_active": (C.c_int, [_vp, C.POINTER(C.c_int32)]),
+    "fps_ens_time_flood": (C.c_int, [_vp, C.c_int32, C.POINTER(C.c_double)]),
     "fps_ens_last_error": (C.c_char_p, [_vp]),
     "fps_sur_param_count": (C.c_int32, []),
     "fps_sur_workspace_bytes": (C.c_size_t, [C.c_int32, C.c_int32, C.c_int32]),
+    "fps_sur_set_blocks": (C.c_int, [_vp, C.c_int32, C.c_int32]),
     "fps_sur_create": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, _vp, C.c_size_t, _vp, C.POINTER(_vp)]),
     "fps_sur_destroy": (None, [_vp]),
     "fps_sur_set_params": (C.c_int, [_vp, _vp]),
@@ -116,6 +118,7 @@ EXPORTS = {
     "fps_sur_copy_state": (C.c_int, [C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "fps_sur_last_error": (C.c_char_p, [_vp]),
     "fps_set_rows_per_wave": (C.c_int, [_vp, C.c_int32]),
+    "fps_get_rows_per_wave": (C.c_int, [_vp, C.POINTER(C.c_int32)]),
     "fps_autotune": (C.c_int, [_vp, C.c_char_p, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     "fps_status_string": (C.c_char_p, [C.c_int]),
     "fps_last_error": (C.c_char_p, [_vp]),
@@ -274,6 +277,11 @@ class Member:
 
     def set_rows_per_wave(self, rows):
         return self._check(self._lib.fps_set_rows_per_wave(self.h_, int(rows)))
+
+    def rows_per_wave(self):
+        r = C.c_int32()
+        self._check(self._lib.fps_get_rows_per_wave(self.h_, C.byref(r)))
+        return r.value
 
     def diag(self, check=True):
         d = DiagC()
@@ -437,6 +445,13 @@ class Ensemble:
         cp = None if cache_path is None else str(cache_path).encode()
         return self._check(self._lib.fps_ens_autotune(self.e_, cp))
 
+    def time_flood(self, reps=50):
+        """Average ms per flood-update launch over every member (back-to-back
+        launches, states unchanged)."""
+        ms = C.c_double()
+        self._check(self._lib.fps_ens_time_flood(self.e_, int(reps), C.byref(ms)))
+        return ms.value
+
     def active(self):
         n = C.c_int32()
         self._check(self._lib.fps_ens_active(self.e_, C.byref(n)))
@@ -484,6 +499,10 @@ class Surrogate:
         if rc != FPS_OK:
             raise FpsError(rc, (self._lib.fps_sur_last_error(self.s_) or b"").decode())
         return rc
+
+    def set_blocks(self, conv_blocks=0, wgrad_blocks=0):
+        """Cap the blocks of the convolution / weight-gradient kernels (0 = default)."""
+        return self._check(self._lib.fps_sur_set_blocks(self.s_, int(conv_blocks), int(wgrad_blocks)))
 
     def set_params(self, params):
         p = params.to(self.device, self.torch.float32).contiguous()

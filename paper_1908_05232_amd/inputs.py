@@ -275,12 +275,16 @@ def _connected(walk, a_cells, b_cells):
 def shopping_centre(n: int = 512, dx: float = 0.25, seed: int = 5232, n_evac: int = 2000,
                     q_peak: float = 2.0, duration: float = 600.0, t_flood: float = 0.0,
                     exit_width: float = 2.0, v_base: float = 1.4, n_exits: int = 2,
-                    n_manning: float = 0.01) -> Scenario:
+                    n_manning: float = 0.01, nearest_exit_field: bool = False) -> Scenario:
     """Synthetic shopping-centre evacuation: random building tiling (+3 m
     blocks), south breach over the central 30% of the south edge carrying a
     triangular hydrograph, transmissive ("slip") north side, walls east and
     west, ``n_exits`` exits of ``exit_width`` on the north wall at x = L/3, 2L/3,
-    evacuees uniform over the free space at the paper's 1.4 m/s."""
+    evacuees uniform over the free space at the paper's 1.4 m/s.  With
+    ``nearest_exit_field`` the navigation map holds one distance field to the
+    nearest cell of any exit instead of one per exit (the same route for every
+    evacuee, who heads for the nearest exit either way; one Dijkstra run
+    instead of n_exits on large grids)."""
     L = n * dx
     s = seed
     while True:
@@ -296,7 +300,11 @@ def shopping_centre(n: int = 512, dx: float = 0.25, seed: int = 5232, n_evac: in
             break
         s += 1
     rng = rng_of(seed)
-    dist = np.stack([distance_field(walk, e, dx, dx) for e in exits])
+    if nearest_exit_field:
+        dist = distance_field(walk, [c for e in exits for c in e], dx, dx)[None]
+        n_exits = 1
+    else:
+        dist = np.stack([distance_field(walk, e, dx, dx) for e in exits])
     desc = GridDesc(nx=n, ny=n, dx=dx, dy=dx, bc=(WALL, WALL, WALL, TRANSMISSIVE),
                     inflow_side=SIDE_S, inflow_c0=c0, inflow_c1=c1, n_base=n_manning)
     ht, hq = triangular_hydrograph(q_peak, duration, t_flood)
@@ -391,3 +399,46 @@ def intervention_sweep(S: int = 64, seed: int = 3303, workers: int = 8):
     import concurrent.futures as cf
     with cf.ProcessPoolExecutor(max_workers=workers) as ex:
         return list(ex.map(_sweep_member, jobs))
+
+
+def _large_member(args):
+    seed, k, n, n_evac = args
+    rng = rng_of(seed * 1000 + k)
+    height = float(rng.uniform(0.2, 1.0))
+    q_peak = float(rng.uniform(1.0, 3.0))
+    t_flood = -float(rng.uniform(0.0, 300.0))
+    sheet = float(rng.uniform(0.02, 0.1))
+    sc = shopping_centre(n=n, dx=0.25, seed=seed * 1000 + k, n_evac=n_evac, q_peak=q_peak,
+                         t_flood=t_flood, nearest_exit_field=True)
+    walk = sc.walk.astype(bool)
+    # the water of the earlier part of the flood: a shallow sheet over the free
+    # area and 1-3 deeper ponds, so that every free cell is wet and moving
+    h = np.where(walk, sheet, 0.0)
+    for _ in range(int(rng.integers(1, 4))):
+        w, hh = rng.integers(n // 16, n // 4, size=2)
+        i0, j0 = rng.integers(0, n - w), rng.integers(n // 8, n - hh)
+        h[j0:j0 + hh, i0:i0 + w] = np.where(walk[j0:j0 + hh, i0:i0 + w], rng.uniform(0.2, 1.0), 0.0)
+    sc.h = h
+    # a completed sandbag line of the drawn height across the free cells of the
+    # row at 0.7 of the site (raised bed; the people still cross it)
+    jb = int(0.7 * n)
+    sc.z[jb, :] += height * walk[jb, :]
+    sc.name = f"large_{k}_{n}_bar{height:.2f}_sheet{sheet:.3f}"
+    return sc
+
+
+def large_sweep(S: int = 32, n: int = 2048, n_evac: int = 50000, seed: int = 5, workers: int = 8):
+    """Large sweep: S shopping centres of n x n cells of 0.25 m (random
+    building tiling as above), each with a completed sandbag line of height
+    U(0.2, 1.0) m across the row at 0.7 of the site, ``n_evac`` evacuees
+    uniform over the free space heading for the nearest of two north exits,
+    the triangular hydrograph (peak U(1, 3) m^2/s over 600 s) already
+    U(0, 300) s under way, and the site already wet: a sheet of U(0.02, 0.1) m
+    over the free area plus 1-3 ponds of U(0.2, 1.0) m.  Each member from its
+    own seed; the host set-up runs in worker processes."""
+    jobs = [(seed, k, n, n_evac) for k in range(S)]
+    if workers <= 1:
+        return [_large_member(j) for j in jobs]
+    import concurrent.futures as cf
+    with cf.ProcessPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(_large_member, jobs))
