@@ -1,8 +1,12 @@
 """GPU parity of the flood update (HIP path through the C-ABI vs the FP64 oracle).
 
-Tolerances: max |dh| <= 1e-4 m and relative mass error <= 1e-6 per window of
-up to 1000 steps, the oracle replaying the GPU's time steps; the oracle's own
-time step must agree to 1e-5 relative.  The random rough-data cases (random
+Tolerances: max |dh| <= 1e-4 m, max |dq| <= 5e-4 m^2/s (for hu and hv) and
+relative mass error <= 1e-6 per window of up to 1000 steps, the oracle
+replaying the GPU's time steps; the oracle's own time step must agree to 1e-5
+relative.  The discharge bar is the depth bar carried at a wave speed of
+5 m/s: a depth difference dh moves the discharge of a gravity wave by about
+(|u| + sqrt(g h)) dh, and |u| + sqrt(g h) stays below 5 m/s in every case here
+(dam breaks of 1 m: 2.3 + 2.0 m/s; the shopping centre's inflow: under 4 m/s).  The random rough-data cases (random
 discontinuous water over random terrain, open sides draining most of it)
 exercise boundaries and indexing over 200-step windows, and measure the mass
 error against the volume that went through the domain (initial + inflow +
@@ -16,7 +20,7 @@ from tests.gpu_util import flood_window, random_wet_dry, say
 
 pytestmark = pytest.mark.gpu
 
-DH_TOL, MASS_TOL, DT_TOL = 1e-4, 1e-6, 1e-5
+DH_TOL, DQ_TOL, MASS_TOL, DT_TOL = 1e-4, 5e-4, 1e-6, 1e-5
 
 
 def check_window(oracle, sim, sc, n, label, throughput=False):
@@ -27,7 +31,8 @@ def check_window(oracle, sim, sc, n, label, throughput=False):
         through = m0 + d["v_in"] + abs(d["v_out"])
         rel = rel * ref.mass() / through if through > 0 else abs(d["mass"] - ref.mass())
     say(f"[{label}] {n} steps: max|dh| {dh:.2e}  max|dq| {dq:.2e}  mass rel {rel:.2e}  dt rel {wdt:.2e}")
-    assert dh <= DH_TOL and rel <= MASS_TOL and wdt <= DT_TOL
+    assert dh <= DH_TOL and dq <= DQ_TOL and rel <= MASS_TOL and wdt <= DT_TOL
+    return ref
 
 
 def test_lake_at_rest_gpu_exact():
@@ -85,6 +90,18 @@ def test_shopping_centre_512_parity(oracle):
     budget = d["v_in"] - d["v_out"] + d["v_clip"]
     say("mass budget:", d["mass"], budget)
     assert abs(d["mass"] - budget) <= 1e-5 * d["v_in"]
+    # the hydrograph's peak (300 s) and its drawdown to the end of the run
+    sim.step(4000)
+    check_window(oracle, sim, sc, 1000, "shopping centre 512^2 steps 9000-10000")
+    t_peak = sim.diag()["t"]
+    sim.step(9000)
+    check_window(oracle, sim, sc, 1000, "shopping centre 512^2 steps 19000-20000")
+    d = sim.diag()
+    wet = float((sim.fields()[0] > 1e-5).mean())
+    say(f"t at step 10000: {t_peak:.1f} s, at step 20000: {d['t']:.1f} s, wet fraction {wet:.2f}")
+    budget = d["v_in"] - d["v_out"] + d["v_clip"]
+    assert abs(d["mass"] - budget) <= 1e-5 * d["v_in"]
+    assert d["v_out"] > 0.0
 
 
 def test_bulk_equals_single_steps_and_repeatable():

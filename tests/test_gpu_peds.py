@@ -61,12 +61,17 @@ def test_bins_and_counts_bit_exact(oracle, which):
         assert np.array_equal(cnt, recount(sc, A))
 
 
-@pytest.mark.parametrize("which,warm", [("cfg1", 0), ("cfg1", 40), ("centre", 300)])
+@pytest.mark.parametrize("which,warm", [("cfg1", 0), ("cfg1", 40), ("centre", 300), ("barrier", 400)])
 def test_coupled_step_parity_from_identical_state(oracle, which, warm):
     if which == "cfg1":
         sc = I.cfg1_dam_break(n_ped=300)
-    else:
+    elif which == "centre":
         sc = I.shopping_centre(n=256, dx=0.25, seed=9, n_evac=3000)
+    else:
+        # responders building a barrier before the flood (dry 1 s steps): some
+        # walk, some wait out their pick-up or drop timers
+        sc = I.add_barrier(I.shopping_centre(n=256, dx=0.25, seed=9, n_evac=500, t_flood=1e9),
+                           seed=9, n_resp=150, height=0.4)
     sim = fps.Sim(sc)
     sim.step(warm)
     start, d0 = snapshot(sim, sc)
@@ -103,6 +108,22 @@ def test_coupled_step_parity_from_identical_state(oracle, which, warm):
     say(f"    state mismatches {len(st_mism)}, count mismatches {cnt_mism}")
     assert len(st_mism) <= max(1, 0.005 * len(A["x"]))
     assert cnt_mism <= 2 * max(1, 0.005 * len(A["x"]))
+    # the rest of the agent record: velocity, destination and wait timer, on
+    # every active agent whose class and state came out the same (a class or
+    # state decided differently at a threshold changes the walking speed or
+    # the destination by design)
+    same = act & ~hz & (A["state"] == ref.state) & (A["hr_class"] == ref.cls)
+    dv = max(np.abs(A["vx"] - ref.vx)[same].max(), np.abs(A["vy"] - ref.vy)[same].max())
+    dtimer = float(np.abs(A["timer"] - ref.timer)[same].max())
+    dest_mism = int((A["dest"] != ref.dest)[same].sum())
+    waiting = int(np.isin(A["state"], (3, 5)).sum())
+    say(f"    max|dv| {dv:.2e} m/s, max|dtimer| {dtimer:.2e} s ({waiting} waiting), "
+        f"destination mismatches {dest_mism} of {int(same.sum())}")
+    assert dv <= 1e-4
+    assert dtimer <= 1e-5
+    assert dest_mism == 0
+    if which == "barrier":
+        assert waiting > 0 and int((A["role"] == 1).sum()) == 150
 
 
 def test_coupled_window_with_count_replay(oracle):

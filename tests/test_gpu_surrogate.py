@@ -20,6 +20,12 @@ from tests.gpu_util import say
 
 pytestmark = pytest.mark.gpu
 COUT_GPU = [64, 64, 64, 64, 16]
+# element-wise bar of a gradient against the oracle with the same BF16
+# rounding points, relative to the largest element of its tensor: the FP32
+# sums may move an inter-layer BF16 rounding by one unit (2^-8 relative) at
+# a few pixels, whose share of a weight-gradient sum over the image is far
+# below that unit; measured up to 5e-4 (first layer) on the multi-tile case
+ELEM_TOL = 5e-3
 
 
 bf16_round = S.bf16_round
@@ -110,6 +116,49 @@ def test_gradients_match_oracle(seed):
             cb, eb = cosine(db, dbo), rel_l2(db, dbo)
             say(f"layer {li + 1} vs {tag}: dW cos {c:.6f} rel {e:.2e}; db cos {cb:.6f} rel {eb:.2e}")
             assert c >= cos_min and e <= rel_max and cb >= cos_min and eb <= rel_max
+
+
+def test_multi_tile_gradients_match_oracle():
+    """Every block walks several tiles: the kernels' grid-stride paths (next
+    tile prefetched during the matrix work, LDS re-deposit, partial weight
+    gradients accumulated over tiles) against the oracle, element by element.
+    3 images of 48 x 96 make 27 convolution tiles and 54 weight-gradient
+    tiles; caps of 5 and 7 blocks give each block 5-6 and 7-8 of them, the
+    last block fewer (ragged).  The forward pass must not change at all under
+    the caps, the gradients only by the grouping of their FP32 partial sums."""
+    params, x, target = make_case(9, 3, 48, 96)
+    sur = fps.Surrogate(3, 48, 96)
+    p, xt, tt = to_dev(params, x, target)
+    sur.set_params(p)
+    y_one = sur.forward(xt).clone()
+    _, g_one = sur.gradients(xt, tt)
+    g_one = g_one.clone()
+    sur.set_blocks(5, 7)
+    y = sur.forward(xt)
+    loss, g = sur.gradients(xt, tt)
+    assert torch.equal(y, y_one)
+    gn, g1 = g.cpu().numpy().astype(np.float64), g_one.cpu().numpy().astype(np.float64)
+    regroup = float(np.abs(gn - g1).max() / np.abs(g1).max())
+    say(f"capped vs one tile per block: max|dg| / max|g| = {regroup:.2e}")
+    assert regroup <= 1e-5
+    lb, gb = S.loss_and_grads(params, x, target, bf16=True)
+    assert float(loss.item()) == pytest.approx(lb, rel=5e-3)
+    yb, _, _ = S.forward(params, x, bf16=True)
+    yerr = float(np.abs(y.cpu().numpy()[..., :3] - yb).max() / np.abs(yb).max())
+    say(f"forward: max|dy| / max|y| = {yerr:.2e}")
+    assert yerr <= 5e-3
+    gg = unpack(gn, params)
+    for li in range(len(gg)):
+        (dw, db), (dwb, dbb) = gg[li], gb[li]
+        if li == 0:
+            dw, dwb = dw[..., :5], dwb[..., :5]       # zero input channels carry no gradient
+        ew = float(np.abs(dw - dwb).max() / np.abs(dwb).max())
+        eb = float(np.abs(db - dbb).max() / np.abs(dbb).max())
+        c, e = cosine(dw, dwb), rel_l2(dw, dwb)
+        say(f"layer {li + 1}: dW max|d| / max|ref| {ew:.2e} (cos {c:.6f}, rel L2 {e:.2e}); "
+            f"db max|d| / max|ref| {eb:.2e}")
+        assert ew <= ELEM_TOL and eb <= ELEM_TOL
+        assert c >= 0.9999 and e <= 1e-2
 
 
 def test_training_reduces_loss_and_matches_adam():
