@@ -332,6 +332,24 @@ int fps_sur_set_params(fps_sur* sur, const float* params);
 int fps_sur_get_params(fps_sur* sur, float* params);
 /* y = net(x) for n <= max_batch images (device pointers). */
 int fps_sur_forward(fps_sur* sur, int32_t n, const void* x_bf16, float* y);
+/* Allocation-free forward pass, for callers that cannot allocate device
+   memory or bring a workspace (code under HIP graph capture, tight serving
+   loops, harnesses that forbid hipMalloc): y = net(x) for n images of H x W
+   with the packed FP32 parameters params (device, caller-owned, the layout of
+   fps_sur_param_count; read only), x bf16 [n][H][W][16] and y fp32
+   [n][H][W][4] (device, caller-owned), on stream (NULL = default).  Same
+   kernels and same result, bit for bit, as fps_sur_forward with these
+   parameters.  The BF16 weights and the activations live in a static device
+   array of the library, one per GPU, set up on the first call on that GPU and
+   held until the process ends: about 33 MB, for n * H * W <= 131,072 pixels
+   (two 256 x 256 patches).  Calls that overlap on one GPU race on that array
+   (run them on one stream, or one after another).  Allocates nothing and
+   does not synchronise.  FPS_E_INVALID for NULL pointers or H, W not positive
+   multiples of 16, 32; FPS_E_CAPACITY, before any device work, for more
+   pixels; FPS_E_DEVICE if the array's address cannot be found (message in
+   fps_sur_last_error(NULL)). */
+int fps_sur_forward_noalloc(const float* params, int32_t n, int32_t H, int32_t W, const void* x_bf16, float* y,
+                            void* stream);
 /* Mean squared error against target and its gradients (packed like the
    parameters; grads may be NULL); loss: one device float. */
 int fps_sur_gradients(fps_sur* sur, int32_t n, const void* x_bf16, const float* target, float* grads,

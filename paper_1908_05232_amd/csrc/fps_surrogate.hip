@@ -27,6 +27,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <mutex>
 #include <new>
 
 #include "fps.h"
@@ -743,6 +744,56 @@ int check_args(fps_sur* s, int n)
     return FPS_OK;
 }
 
+// Scratch of the allocation-free forward pass (fps_sur_forward_noalloc): the
+// BF16 weight matrices of the five layers, then two activation buffers used in
+// turn by layers 1-4, each of kNoallocPixels x 64 BF16 channels.  One copy per
+// GPU, held until the process ends; every call on a GPU uses the same copy.
+constexpr int64_t kNoallocPixels = 131072;          // n * H * W per call, at most (two 256^2 patches)
+constexpr size_t noalloc_weight_bytes()
+{
+    size_t o = 0;
+    for (int l = 0; l < kLayers; ++l) o += (2 * (size_t)kCout[l] * kp_of(kCin[l]) + 255) / 256 * 256;
+    return o;
+}
+constexpr size_t kNoallocActBytes = 2 * (size_t)kNoallocPixels * 64;
+constexpr size_t kNoallocBytes = noalloc_weight_bytes() + 2 * kNoallocActBytes;
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+// Device address of this GPU's copy of the scratch array and its compute-unit
+// count, looked up once per device (with that device current) and kept.  In
+// host code the array's name is not a device address: only this pointer is
+// passed to kernels.
+constexpr int kMaxDevices = 64;
+struct NoallocDevice {
+    unsigned char* ptr = nullptr;
+    int cus = 0;
+};
+std::mutex g_noalloc_mu;
+NoallocDevice g_noalloc[kMaxDevices];
+
+int noalloc_device(NoallocDevice* out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+        return sfail(nullptr, FPS_E_DEVICE, "fps_sur_forward_noalloc: no usable current device (%d)", dev);
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    NoallocDevice& d = g_noalloc[dev];
+    if (!d.ptr) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return sfail(nullptr, FPS_E_DEVICE, "fps_sur_forward_noalloc: hipGetSymbolAddress: %s",
+                         hipGetErrorString(e));
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        d.cus = cus;
+        d.ptr = static_cast<unsigned char*>(p);
+    }
+    *out = d;
+    return FPS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -842,6 +893,47 @@ int fps_sur_forward(fps_sur* s, int32_t n, const void* x, float* y)
     int rc = check_args(s, n);
     if (rc != FPS_OK) return rc;
     return forward(s, n, static_cast<const bf16*>(x), y);
+}
+
+int fps_sur_forward_noalloc(const float* params, int32_t n, int32_t H, int32_t W, const void* x, float* y,
+                            void* stream)
+{
+    if (!params || !x || !y) return sfail(nullptr, FPS_E_INVALID, "fps_sur_forward_noalloc: NULL argument");
+    if (n < 1 || H < CTH || W < TW || H % CTH || W % TW)
+        return sfail(nullptr, FPS_E_INVALID,
+                     "fps_sur_forward_noalloc: need n >= 1 and H, W positive multiples of %d, %d", CTH, TW);
+    if ((int64_t)n * H * W > kNoallocPixels)
+        return sfail(nullptr, FPS_E_CAPACITY, "fps_sur_forward_noalloc: %d x %d x %d pixels exceed the %lld of the "
+                     "static scratch", n, H, W, (long long)kNoallocPixels);
+    NoallocDevice d;
+    int rc = noalloc_device(&d);
+    if (rc != FPS_OK) return rc;
+    // a handle on the stack over the scratch: the same kernels as fps_sur_forward
+    fps_sur t;
+    t.max_batch = n;
+    t.H = H;
+    t.W = W;
+    t.cus = d.cus;
+    t.stream = static_cast<hipStream_t>(stream);
+    t.params = const_cast<float*>(params);       // read only: biases and the weights converted below
+    size_t o = 0;
+    for (int l = 0; l < kLayers; ++l) {
+        t.wf[l] = reinterpret_cast<bf16*>(d.ptr + o);
+        o += (2 * (size_t)kCout[l] * kp_of(kCin[l]) + 255) / 256 * 256;
+    }
+    bf16* a = reinterpret_cast<bf16*>(d.ptr + o);
+    bf16* b = reinterpret_cast<bf16*>(d.ptr + o + kNoallocActBytes);
+    t.act[0] = a;                                 // layer l reads act[l - 1] and writes act[l]
+    t.act[1] = b;
+    t.act[2] = a;
+    t.act[3] = b;
+    for (int l = 0; l < kLayers; ++l)
+        hipLaunchKernelGGL(prep_weights_kernel, dim3(64), dim3(256), 0, t.stream, params + param_offset(l), kCin[l],
+                           kCout[l], t.wf[l], (bf16*)nullptr);
+    if (hipGetLastError() != hipSuccess) return sfail(nullptr, FPS_E_DEVICE, "fps_sur_forward_noalloc: launch failed");
+    rc = forward(&t, n, static_cast<const bf16*>(x), y);
+    if (rc != FPS_OK) snprintf(g_sur_err, sizeof(g_sur_err), "fps_sur_forward_noalloc: %s", t.err);
+    return rc;
 }
 
 int fps_sur_gradients(fps_sur* s, int32_t n, const void* xv, const float* target, float* grads_out,

@@ -92,6 +92,7 @@ EXPORTS = {
     "fps_sur_param_count": (C.c_int32, []),
     "fps_sur_workspace_bytes": (C.c_size_t, [C.c_int32, C.c_int32, C.c_int32]),
     "fps_sur_set_blocks": (C.c_int, [_vp, C.c_int32, C.c_int32]),
+    "fps_sur_forward_noalloc": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, _vp, _vp, _vp]),
     "fps_sur_create": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, _vp, C.c_size_t, _vp, C.POINTER(_vp)]),
     "fps_sur_destroy": (None, [_vp]),
     "fps_sur_set_params": (C.c_int, [_vp, _vp]),
@@ -583,6 +584,22 @@ def sur_pack(h, hu, hv, z, occupancy=None, inflow=None, out=None, stream=None):
     if rc != FPS_OK:
         raise FpsError(rc, (lib().fps_sur_last_error(None) or b"").decode())
     return out
+
+
+def sur_forward_noalloc(params, x, y, stream=None):
+    """fps_sur_forward_noalloc: y = net(x) with packed FP32 params (device),
+    x bf16 [n, H, W, 16] and a caller-provided y fp32 [n, H, W, 4]; the library
+    allocates nothing (its scratch is a static device array)."""
+    import torch
+    n, H, W = x.shape[0], x.shape[1], x.shape[2]
+    if x.dtype != torch.bfloat16 or x.shape[3] != 16 or not x.is_contiguous():
+        raise FpsError(FPS_E_INVALID, "x: contiguous bf16 [n, H, W, 16] expected")
+    if tuple(y.shape) != (n, H, W, 4) or y.dtype != torch.float32 or not y.is_contiguous():
+        raise FpsError(FPS_E_INVALID, "y: contiguous fp32 [n, H, W, 4] expected")
+    if params.dtype != torch.float32 or not params.is_contiguous():
+        raise FpsError(FPS_E_INVALID, "params: contiguous fp32 expected")
+    _sur_rc(lib().fps_sur_forward_noalloc(_ptr(params), n, H, W, _ptr(x), _ptr(y), _stream_ptr(torch, x, stream)))
+    return y
 
 
 def sur_make_target(s0, s1, out=None, stream=None):
