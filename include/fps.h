@@ -196,8 +196,19 @@ int fps_inflow_depth(fps_sim* sim, double t0, double t1, double* depth);
    between calls), and every step has length dt_max (no CFL limit).  Cells
    outside the region keep stale values; a region of k steps is exact at
    cells more than k cells inside its border.  mask NULL restores the
-   normal update.  block in [1, 4096]. */
+   normal update.  block in [1, 4096].  First-order update only
+   (FPS_E_STATE with the second-order variant). */
 int fps_set_judge_region(fps_sim* sim, const uint8_t* mask, int32_t block);
+
+/* Hold the flood (frozen = 1): the following steps have the fixed length
+   dt_max, leave the flood state, its time step and volumes untouched, add no
+   inflow, and advance only the pedestrians (hazard, movement, counts,
+   sandbags), who read the state as it is, e.g. one written into the bound
+   fields from outside (a learned update; rebind after writing).  frozen = 0
+   resumes the coupled step with the CFL step of the current state.  Binding
+   fields also resumes it.  Synchronises.  FPS_E_STATE before fields are
+   bound. */
+int fps_set_flood_frozen(fps_sim* sim, int32_t frozen);
 
 /* Per-cell evacuee counts that raise the Manning coefficient (sec. 2.3) for
    a simulation with no agents bound: device int32 [ny][nx], copied
@@ -218,8 +229,27 @@ int fps_set_graph(fps_sim* sim, int32_t steps_per_graph);
    ensemble member (the whole ensemble shares one flux: fps_ens_set_flux). */
 int fps_set_flux(fps_sim* sim, int32_t flux);
 
+/* Order of the flood update (sec. 2.2: the paper reduced the second-order
+   scheme of Wang et al. 2011 to first order).  1 (the default): the
+   first-order update.  2: the second-order variant: MUSCL reconstruction of
+   (h, h + z, u, v) per direction with the minmod limiter (zero slope where
+   the cell or a neighbour in that direction is dry, so first order at
+   wet/dry fronts, and in ghost cells), the same hydrostatic reconstruction,
+   face flux and walls on the reconstructed states, the second-order
+   bed-slope form of Audusse et al. (2004) (still water stays still), and
+   Heun's two-stage Runge-Kutta step with the depth cleanup after each stage;
+   inflow and friction once per step.  Same time step rule.  Applies from the
+   next step.  FPS_E_INVALID for another value; FPS_E_STATE for an ensemble
+   member (fps_ens_set_order) or while a judge region is set (first order
+   only). */
+int fps_set_order(fps_sim* sim, int32_t order);
+
 /* Synchronise the stream and report diagnostics (sec. 3.2 statistics). */
 int fps_get_diag(fps_sim* sim, fps_diag* out);
+
+/* Simulated time and the length of the next step only (host outputs): the
+   part of fps_get_diag that needs no pass over the agents.  Synchronises. */
+int fps_get_time(fps_sim* sim, double* t, double* dt_next);
 
 /* Hazard rate HR = (max(|u|,|v|) + 0.5) h per cell (sec. 2.4), 0 where dry;
    device float32 [ny][nx] output, caller-owned.  Asynchronous. */
@@ -287,6 +317,8 @@ int fps_ens_step_profiled(fps_ens* ens, int32_t n_steps, double* ms_out);
 int fps_ens_set_graph(fps_ens* ens, int32_t steps_per_graph);
 /* Face flux of every scenario (see fps_set_flux). */
 int fps_ens_set_flux(fps_ens* ens, int32_t flux);
+/* Order of the flood update of every scenario (see fps_set_order). */
+int fps_ens_set_order(fps_ens* ens, int32_t order);
 /* Rows per wave of every scenario (see fps_set_rows_per_wave), tuned for the
    duration of the ensemble's whole flood launch on the bound states: one value
    for all scenarios, then each distinct grid size moved by factors of two
@@ -378,25 +410,34 @@ int fps_sur_make_target(int64_t npix, const float* h0, const float* hu0, const f
 int fps_sur_apply(int64_t npix, const float* y, float* h, float* hu, float* hv, float h_dry, float h_snap,
                   void* stream);
 /* Judge of a surrogate state (a) against a finite-volume state (b) at the
-   cells of the sampled agents: every stride-th agent of the device SoA
-   (x, y, state) of length na that has not exited.  out2[0] = sampled agents
-   whose depth differs by more than tol (m) or whose hazard class (Table 1;
-   thresholds hr_thresholds[3], host) differs; out2[1] = the largest depth
-   difference as float bits.  Cells: floor(x / dx) in FP32, clamped to the
-   grid.  out2: device int32[2]; async.  FPS_E_INVALID, before any device
-   call, for bad sizes or a NULL array (the agent and flood arrays may be NULL
-   only when na = 0). */
+   cells of the judged agents of the device SoA (x, y, state) of length na,
+   those that have not exited: every stride-th agent and, when a selection
+   state (hs, qxs, qys; device float32 [ny][nx], may be NULL) is given, also
+   every agent whose cell there is within h_margin (m) of the dry threshold
+   h_dry or has a hazard rate within hr_margin of one of the three Table 1
+   thresholds hr_thresholds[3] (host): the people whose class a small depth
+   error could change.  out3 (device int32[3]): [0] judged agents whose depth
+   differs by more than tol (m) or whose hazard class (Table 1, DRY where
+   h <= h_dry) differs, [1] the largest depth difference as float bits, [2]
+   the number of judged agents.  Cells: floor(x / dx) in FP32, clamped to the
+   grid.  Async.  FPS_E_INVALID, before any device call, for bad sizes, a NULL
+   array (the agent and flood arrays may be NULL only when na = 0) or a
+   negative margin. */
 int fps_sur_judge(int32_t na, int32_t stride, const float* x, const float* y, const uint8_t* state,
                   int32_t nx, int32_t ny, double dx, double dy, const float* ha, const float* qxa,
                   const float* qya, const float* hb, const float* qxb, const float* qyb, double tol,
-                  double h_dry, const double* hr_thresholds, int32_t* out2, void* stream);
+                  double h_dry, const double* hr_thresholds, const float* hs, const float* qxs, const float* qys,
+                  double hr_margin, double h_margin, int32_t* out3, void* stream);
 /* Judge region for fps_set_judge_region: clears mask (device uint8
    [ceil(ny/block)][ceil(nx/block)]) and marks every block within halo cells of
-   the cell of a sampled agent (the same sample as fps_sur_judge); async.
-   FPS_E_INVALID for bad sizes, a NULL mask, or NULL agent arrays with na > 0. */
+   the cell of a judged agent (the same people as fps_sur_judge with the same
+   selection arguments; hr_thresholds may be NULL when hs is); async.
+   FPS_E_INVALID for bad sizes, a NULL mask, NULL agent arrays with na > 0,
+   or a negative margin. */
 int fps_sur_judge_mask(int32_t na, int32_t stride, const float* x, const float* y, const uint8_t* state,
-                       int32_t nx, int32_t ny, double dx, double dy, int32_t halo, int32_t block,
-                       uint8_t* mask, void* stream);
+                       int32_t nx, int32_t ny, double dx, double dy, const float* hs, const float* qxs,
+                       const float* qys, double h_dry, const double* hr_thresholds, double hr_margin,
+                       double h_margin, int32_t halo, int32_t block, uint8_t* mask, void* stream);
 /* Per-cell counts of evacuees still evacuating (role evacuee, state EVAC),
    the counts that raise the Manning coefficient (sec. 2.3), into device int32
    [ny][nx]; async.  FPS_E_INVALID for bad sizes, NULL counts, or NULL agent
@@ -408,6 +449,18 @@ int fps_sur_occupancy(int32_t na, const float* x, const float* y, const uint8_t*
 int fps_sur_copy_state(int64_t npix, const float* h, const float* hu, const float* hv, float* h_out,
                        float* hu_out, float* hv_out, void* stream);
 const char* fps_sur_last_error(const fps_sur* sur);
+
+/* Streaming probe, the practical bandwidth ceiling the flood update's roofline
+   is read against: buf (device, caller-owned, 16-byte aligned) holds n_in
+   input arrays followed by n_out output arrays of n floats each, array k at
+   buf + k * stride (stride >= n floats); a pass reads every input element once
+   and writes every output element once with 16-byte accesses (out_k = sum of
+   the inputs + k).  (n_in, n_out) is (1, 1) (a copy), (4, 3) or (5, 3) (the
+   flood update's SoA streams: h, hu, hv, z and the evacuee counts in; h, hu,
+   hv out).  reps passes between two HIP events on stream; *ms_per_pass gets
+   the mean.  n and stride positive multiples of 4.  Synchronises. */
+int fps_stream_probe(float* buf, int64_t n, int64_t stride, int32_t n_in, int32_t n_out, int32_t reps, void* stream,
+                     double* ms_per_pass);
 
 const char* fps_status_string(int status);
 /* Last error message of this handle (or of the last failed fps_create when sim is NULL). */

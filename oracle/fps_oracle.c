@@ -307,8 +307,14 @@ static void ghost(const or_sim *S, int32_t side, int64_t c, double *h, double *q
     }
 }
 
+static void fv_step2(or_sim *S, double dt);
+
 void or_fv_step(or_sim *S, double dt)
 {
+    if (S->P.order == 2) {
+        fv_step2(S, dt);
+        return;
+    }
     const or_params *P = &S->P;
     const int32_t nx = P->nx, ny = P->ny;
     const double g = P->g, eps = P->h_dry;
@@ -453,6 +459,260 @@ void or_fv_step(or_sim *S, double dt)
     S->any_wet = wet;
     free(FX); free(HXL); free(HXR);
     free(FY); free(HYL); free(HYR);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Second-order variant.  The paper took the scheme of Wang et al. (2011) and  */
+/* reduced it to first order (sec. 2.2); this variant puts the second order    */
+/* back.  Readings (the scheme's equations are not in the paper):              */
+/*   M1 MUSCL reconstruction, per direction, of h, eta = h + z, u and v with    */
+/*      the minmod limiter; a cell's slope is zero where it or either          */
+/*      neighbour in that direction is dry (h <= h_dry), so the scheme is first */
+/*      order at wet/dry fronts, and in ghost cells; the face bed is            */
+/*      z = eta - h of the reconstructed values.                               */
+/*   M2 at each face the hydrostatic reconstruction (R2) of the two             */
+/*      reconstructed states, then HLLC or HLL (R1) with the reconstructed      */
+/*      velocities (limited between the neighbours' velocities, so a thin face  */
+/*      depth cannot make them large; 0 where the face depth <= h_dry).         */
+/*   M3 bed slope in the second-order form of Audusse et al. (2004): a cell's  */
+/*      normal momentum gets g/2 (h_f^2 - h*_f^2) at each of its faces (h_f its */
+/*      reconstructed depth there, h*_f the hydrostatic one) and the centred   */
+/*      term -g/2 (h_w + h_e)(z_e - z_w) per direction; a lake at rest stays    */
+/*      at rest exactly.                                                        */
+/*   M4 time: Heun's two-stage Runge-Kutta, U1 = U + dt L(U), U' = (U + U1 +    */
+/*      dt L(U1)) / 2, depth cleanup (R21) after each stage; inflow (R9) and   */
+/*      friction (R5) once after both stages; outflow and clipped volumes are  */
+/*      the means of the two stages'.                                          */
+/* ------------------------------------------------------------------------ */
+double or_minmod(double a, double b)
+{
+    if (!(a * b > 0.0)) return 0.0;
+    return fabs(a) <= fabs(b) ? a : b;
+}
+
+/* cell (i, j) with one ghost layer: i in [-1, nx], j in [-1, ny] (not both
+   outside); v = (h, eta, u, v) with the velocities of R2 (0 where h <= h_dry);
+   *ghost set for ghost cells (R8) */
+static void cell2(const or_params *P, const double *h, const double *qx, const double *qy, const double *z,
+                  int32_t i, int32_t j, double v[4], int *ghost)
+{
+    int32_t ii = i < 0 ? 0 : (i >= P->nx ? P->nx - 1 : i);
+    int32_t jj = j < 0 ? 0 : (j >= P->ny ? P->ny - 1 : j);
+    int64_t c = (int64_t)jj * P->nx + ii;
+    double hh = h[c], ux = qx[c], uy = qy[c];
+    *ghost = i != ii || j != jj;
+    if (i < 0 && P->bc[0] == OR_WALL) ux = -ux;
+    if (i >= P->nx && P->bc[1] == OR_WALL) ux = -ux;
+    if (j < 0 && P->bc[2] == OR_WALL) uy = -uy;
+    if (j >= P->ny && P->bc[3] == OR_WALL) uy = -uy;
+    v[0] = hh;
+    v[1] = hh + z[c];
+    v[2] = hh > P->h_dry ? ux / hh : 0.0;
+    v[3] = hh > P->h_dry ? uy / hh : 0.0;
+}
+
+/* limited slopes of cell (i, j) in direction dir (0: x, 1: y) (M1) */
+static void slopes2(const or_params *P, const double *h, const double *qx, const double *qy, const double *z,
+                    int32_t i, int32_t j, int dir, double s[4])
+{
+    double a[4], b[4], c[4];
+    int ga, gb, gc;
+    cell2(P, h, qx, qy, z, i, j, b, &gb);
+    for (int k = 0; k < 4; ++k) s[k] = 0.0;
+    if (gb) return;
+    if (dir == 0) {
+        cell2(P, h, qx, qy, z, i - 1, j, a, &ga);
+        cell2(P, h, qx, qy, z, i + 1, j, c, &gc);
+    } else {
+        cell2(P, h, qx, qy, z, i, j - 1, a, &ga);
+        cell2(P, h, qx, qy, z, i, j + 1, c, &gc);
+    }
+    if (!(a[0] > P->h_dry) || !(b[0] > P->h_dry) || !(c[0] > P->h_dry)) return;
+    for (int k = 0; k < 4; ++k) s[k] = or_minmod(c[k] - b[k], b[k] - a[k]);
+}
+
+/* reconstructed state of cell (i, j) at its face on side sgn (+1: east /
+   north, -1: west / south) in direction dir: (h, eta, u, v) */
+static void face_state2(const or_params *P, const double *h, const double *qx, const double *qy,
+                        const double *z, int32_t i, int32_t j, int dir, double sgn, double v[4])
+{
+    double s[4];
+    int g;
+    cell2(P, h, qx, qy, z, i, j, v, &g);
+    slopes2(P, h, qx, qy, z, i, j, dir, s);
+    for (int k = 0; k < 4; ++k) v[k] += 0.5 * sgn * s[k];
+}
+
+/* one face between the reconstructed states L and R (h, eta, un, ut) in the
+   face's normal direction (M2).  hf / hs: each side's reconstructed and
+   hydrostatic depths; zf: each side's face bed. */
+static void face2(const or_params *P, const double L[4], const double R[4], int wall, double F[3],
+                  double hf[2], double hs[2], double zfc[2])
+{
+    double eps = P->h_dry;
+    double zL = L[1] - L[0], zR = R[1] - R[0];
+    double zf = fmax(zL, zR);
+    double hl = L[0] - (zf - zL), hr = R[0] - (zf - zR);
+    if (!(hl > eps)) hl = 0.0;
+    if (!(hr > eps)) hr = 0.0;
+    double unL = 0.0, utL = 0.0, unR = 0.0, utR = 0.0;
+    if (L[0] > eps) { unL = L[2]; utL = L[3]; }
+    if (R[0] > eps) { unR = R[2]; utR = R[3]; }
+    if (P->flux == OR_FLUX_HLL) or_hll(P->g, hl, unL, utL, hr, unR, utR, F);
+    else or_hllc(P->g, hl, unL, utL, hr, unR, utR, F);
+    if (wall) {
+        F[0] = 0.0;
+        F[2] = 0.0;
+    }
+    hf[0] = L[0];
+    hf[1] = R[0];
+    hs[0] = hl;
+    hs[1] = hr;
+    zfc[0] = zL;
+    zfc[1] = zR;
+}
+
+/* dU = -L(U) dt-free residual times dt/d: rh, rqx, rqy[nc] get the change of
+   one forward-Euler stage of length dt; out gets the outflow volume rate */
+static void stage2(const or_sim *S, const double *h, const double *qx, const double *qy, double dt,
+                   double *dh, double *dqx, double *dqy, double *vout_rate)
+{
+    const or_params *P = &S->P;
+    const int32_t nx = P->nx, ny = P->ny;
+    const double g = P->g;
+    const int64_t nfx = (int64_t)(nx + 1) * ny, nfy = (int64_t)nx * (ny + 1);
+    /* per face: flux, and for each side (0: west/south cell, 1: east/north
+       cell) the reconstructed depth, hydrostatic depth and face bed */
+    double *FX = malloc(sizeof(double) * 3 * nfx), *AX = malloc(sizeof(double) * 6 * nfx);
+    double *FY = malloc(sizeof(double) * 3 * nfy), *AY = malloc(sizeof(double) * 6 * nfy);
+#pragma omp parallel for schedule(static)
+    for (int32_t j = 0; j < ny; ++j) {
+        for (int32_t f = 0; f <= nx; ++f) {
+            double L[4], R[4], hf[2], hs[2], zc[2];
+            face_state2(P, h, qx, qy, S->z, f - 1, j, 0, 1.0, L);
+            face_state2(P, h, qx, qy, S->z, f, j, 0, -1.0, R);
+            int wall = (f == 0 && P->bc[0] == OR_WALL) || (f == nx && P->bc[1] == OR_WALL);
+            int64_t k = (int64_t)j * (nx + 1) + f;
+            face2(P, L, R, wall, &FX[3 * k], hf, hs, zc);
+            for (int q = 0; q < 2; ++q) {
+                AX[6 * k + q] = hf[q];
+                AX[6 * k + 2 + q] = hs[q];
+                AX[6 * k + 4 + q] = zc[q];
+            }
+        }
+    }
+#pragma omp parallel for schedule(static)
+    for (int32_t j = 0; j <= ny; ++j) {
+        for (int32_t i = 0; i < nx; ++i) {
+            double L[4], R[4], Ly[4], Ry[4], hf[2], hs[2], zc[2];
+            face_state2(P, h, qx, qy, S->z, i, j - 1, 1, 1.0, L);
+            face_state2(P, h, qx, qy, S->z, i, j, 1, -1.0, R);
+            /* y is normal: (h, eta, v, u) */
+            Ly[0] = L[0]; Ly[1] = L[1]; Ly[2] = L[3]; Ly[3] = L[2];
+            Ry[0] = R[0]; Ry[1] = R[1]; Ry[2] = R[3]; Ry[3] = R[2];
+            int wall = (j == 0 && P->bc[2] == OR_WALL) || (j == ny && P->bc[3] == OR_WALL);
+            int64_t k = (int64_t)j * nx + i;
+            face2(P, Ly, Ry, wall, &FY[3 * k], hf, hs, zc);
+            for (int q = 0; q < 2; ++q) {
+                AY[6 * k + q] = hf[q];
+                AY[6 * k + 2 + q] = hs[q];
+                AY[6 * k + 4 + q] = zc[q];
+            }
+        }
+    }
+    double vout = 0.0;
+    if (P->bc[0] == OR_TRANSMISSIVE)
+        for (int32_t j = 0; j < ny; ++j) vout -= FX[3 * ((int64_t)j * (nx + 1))] * P->dy;
+    if (P->bc[1] == OR_TRANSMISSIVE)
+        for (int32_t j = 0; j < ny; ++j) vout += FX[3 * ((int64_t)j * (nx + 1) + nx)] * P->dy;
+    if (P->bc[2] == OR_TRANSMISSIVE)
+        for (int32_t i = 0; i < nx; ++i) vout -= FY[3 * (int64_t)i] * P->dx;
+    if (P->bc[3] == OR_TRANSMISSIVE)
+        for (int32_t i = 0; i < nx; ++i) vout += FY[3 * ((int64_t)ny * nx + i)] * P->dx;
+    *vout_rate = vout;
+    const double lx = dt / P->dx, ly = dt / P->dy;
+#pragma omp parallel for schedule(static)
+    for (int32_t j = 0; j < ny; ++j) {
+        for (int32_t i = 0; i < nx; ++i) {
+            int64_t c = (int64_t)j * nx + i;
+            int64_t kW = (int64_t)j * (nx + 1) + i, kE = kW + 1, kS = c, kN = c + nx;
+            const double *fW = &FX[3 * kW], *fE = &FX[3 * kE], *fS = &FY[3 * kS], *fN = &FY[3 * kN];
+            /* this cell is side 1 of its west / south face, side 0 of its east / north face */
+            double hw = AX[6 * kW + 1], hsw = AX[6 * kW + 3], zw = AX[6 * kW + 5];
+            double he = AX[6 * kE + 0], hse = AX[6 * kE + 2], ze = AX[6 * kE + 4];
+            double hS = AY[6 * kS + 1], hsS = AY[6 * kS + 3], zS = AY[6 * kS + 5];
+            double hN = AY[6 * kN + 0], hsN = AY[6 * kN + 2], zN = AY[6 * kN + 4];
+            /* M3: one-sided corrections and the centred bed-slope term */
+            double cx = 0.5 * g * (he * he - hse * hse) - 0.5 * g * (hw * hw - hsw * hsw) +
+                        0.5 * g * (hw + he) * (ze - zw);
+            double cy = 0.5 * g * (hN * hN - hsN * hsN) - 0.5 * g * (hS * hS - hsS * hsS) +
+                        0.5 * g * (hS + hN) * (zN - zS);
+            dh[c] = -(lx * (fE[0] - fW[0]) + ly * (fN[0] - fS[0]));
+            dqx[c] = -(lx * ((fE[1] - fW[1]) + cx) + ly * (fN[2] - fS[2]));
+            dqy[c] = -(ly * ((fN[1] - fS[1]) + cy) + lx * (fE[2] - fW[2]));
+        }
+    }
+    free(FX); free(AX); free(FY); free(AY);
+}
+
+static void fv_step2(or_sim *S, double dt)
+{
+    const or_params *P = &S->P;
+    const int32_t nx = P->nx, ny = P->ny;
+    const int64_t nc = (int64_t)nx * ny;
+    const double eps = P->h_dry;
+    double *h1 = malloc(sizeof(double) * nc), *qx1 = malloc(sizeof(double) * nc), *qy1 = malloc(sizeof(double) * nc);
+    double *dh = malloc(sizeof(double) * nc), *dqx = malloc(sizeof(double) * nc), *dqy = malloc(sizeof(double) * nc);
+    double rate0 = 0.0, rate1 = 0.0, clip = 0.0;
+    /* stage 1: U1 = U + dt L(U) */
+    stage2(S, S->h, S->qx, S->qy, dt, dh, dqx, dqy, &rate0);
+    for (int64_t c = 0; c < nc; ++c) {
+        double hh = S->h[c] + dh[c], a = S->qx[c] + dqx[c], b = S->qy[c] + dqy[c];
+        if (hh < 0.0) { clip += 0.5 * -hh; hh = 0.0; }
+        if (!(hh > eps)) { a = 0.0; b = 0.0; }
+        h1[c] = hh; qx1[c] = a; qy1[c] = b;
+    }
+    /* stage 2: U' = (U + U1 + dt L(U1)) / 2 */
+    stage2(S, h1, qx1, qy1, dt, dh, dqx, dqy, &rate1);
+    double inc = 0.0;
+    if (P->inflow_side >= 0) {
+        double dn = P->inflow_side <= 1 ? P->dx : P->dy;
+        inc = or_hydro_integral(S->nh, S->ht, S->hq, S->t, S->t + dt) / dn;
+    }
+    double vin = 0.0;
+    for (int32_t j = 0; j < ny; ++j) {
+        for (int32_t i = 0; i < nx; ++i) {
+            int64_t c = (int64_t)j * nx + i;
+            double h2 = h1[c] + dh[c], a2 = qx1[c] + dqx[c], b2 = qy1[c] + dqy[c];
+            if (h2 < 0.0) { clip += 0.5 * -h2; h2 = 0.0; }
+            if (!(h2 > eps)) { a2 = 0.0; b2 = 0.0; }
+            double hn = 0.5 * (S->h[c] + h2), qxn = 0.5 * (S->qx[c] + a2), qyn = 0.5 * (S->qy[c] + b2);
+            if (P->inflow_side >= 0) {
+                int32_t along = -1;
+                if (P->inflow_side == 0 && i == 0) along = j;
+                if (P->inflow_side == 1 && i == nx - 1) along = j;
+                if (P->inflow_side == 2 && j == 0) along = i;
+                if (P->inflow_side == 3 && j == ny - 1) along = i;
+                if (along >= P->inflow_c0 && along < P->inflow_c1) {
+                    hn += inc;
+                    vin += inc * P->dx * P->dy;
+                }
+            }
+            if (!(hn > eps)) { qxn = 0.0; qyn = 0.0; }
+            or_friction(P, dt, hn, or_n_eff(P, S->np[c]), &qxn, &qyn);
+            S->h[c] = hn;
+            S->qx[c] = qxn;
+            S->qy[c] = qyn;
+        }
+    }
+    S->v_in += vin;
+    S->v_out += 0.5 * (rate0 + rate1) * dt;
+    S->v_clip += clip * P->dx * P->dy;
+    int wet = 0;
+    for (int64_t c = 0; c < nc; ++c)
+        if (S->h[c] > eps) { wet = 1; break; }
+    S->any_wet = wet;
+    free(h1); free(qx1); free(qy1); free(dh); free(dqx); free(dqy);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -54,6 +54,7 @@ typedef struct {
     double hr_t[3];                      /* class thresholds 0.75, 1.5, 2.5 */
     double pick_s, drop_s;
     int32_t flux;                        /* OR_FLUX_HLLC (R1) or OR_FLUX_HLL (variant) */
+    int32_t order;                       /* 1: the paper's first-order scheme; 2: the MUSCL variant */
 } or_params;
 
 typedef struct {
@@ -109,6 +110,7 @@ void or_build_bins(const or_params *P, int32_t na, const float *x, const float *
 /* ---- the step ---- */
 double or_compute_dt(const or_sim *S);
 void or_fv_step(or_sim *S, double dt);            /* flood update, no time advance */
+double or_minmod(double a, double b);             /* slope limiter of the second-order variant */
 void or_count_evacuees(or_sim *S);                /* recompute np from the agents */
 void or_ped_step(or_sim *S, double dt);           /* agents + barrier fill */
 /* one coupled step; dt <= 0 means "compute it", returns the dt used */

@@ -43,6 +43,7 @@ class OrParams(C.Structure):
         ("v_class", C.c_double * 5), ("hr_t", C.c_double * 3),
         ("pick_s", C.c_double), ("drop_s", C.c_double),
         ("flux", C.c_int32),
+        ("order", C.c_int32),
     ]
 
 
@@ -142,6 +143,7 @@ def make_params(desc, ped=None) -> OrParams:
         P.hr_t[k] = ped.hr_t[k]
     P.pick_s, P.drop_s = ped.pick_s, ped.drop_s
     P.flux = getattr(desc, "flux", FLUX_HLLC)
+    P.order = getattr(desc, "order", 1)
     return P
 
 

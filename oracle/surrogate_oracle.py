@@ -183,22 +183,40 @@ def hazard_class32(h, qx, qy, h_dry, thr):
     return np.where(h > np.float32(h_dry), cls, 0)
 
 
-def judge(x, y, state, nx, ny, dx, dy, a, b, tol, h_dry, thr, exited=1):
+def judge(x, y, state, nx, ny, dx, dy, a, b, tol, h_dry, thr, exited=1, stride=1, select=None, hr_margin=0.0,
+          h_margin=0.0):
     """Judge of a surrogate flood state a = (h, qx, qy) against a
-    finite-volume state b at the cells of the agents still in the domain:
-    returns (agents whose depth differs by more than tol or whose hazard
-    class differs, largest depth difference).  Cells: floor(x / dx) in
-    float32, clamped to the grid."""
+    finite-volume state b at the cells of the judged agents still in the
+    domain: every stride-th agent, and with a selection state select = (h, qx,
+    qy) also every agent whose cell there has a depth within h_margin of the
+    dry threshold or a hazard rate within hr_margin of a threshold of thr
+    (decided in float32, as the GPU decides it).  Returns (judged agents whose
+    depth differs by more than tol or whose hazard class differs, largest
+    depth difference, judged agents).  Cells: floor(x / dx) in float32,
+    clamped to the grid."""
     x = np.asarray(x, np.float32)
     y = np.asarray(y, np.float32)
-    keep = np.asarray(state) != exited
-    i = np.clip(np.floor(x / np.float32(dx)), 0, nx - 1).astype(np.int64)[keep]
-    j = np.clip(np.floor(y / np.float32(dy)), 0, ny - 1).astype(np.int64)[keep]
+    idx = np.arange(len(x))
+    i = np.clip(np.floor(x / np.float32(dx)), 0, nx - 1).astype(np.int64)
+    j = np.clip(np.floor(y / np.float32(dy)), 0, ny - 1).astype(np.int64)
+    pick = idx % stride == 0
+    if select is not None:
+        hs, qxs, qys = (np.asarray(f, np.float32)[j, i] for f in select)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            v = np.maximum(np.abs(qxs / hs), np.abs(qys / hs)).astype(np.float32)
+            hr = ((v + np.float32(0.5)) * hs).astype(np.float32)
+        near_dry = ~(hs > np.float32(h_dry) + np.float32(h_margin))
+        near_thr = np.zeros(len(x), bool)
+        for t in thr:
+            near_thr |= np.abs(hr - np.float32(t)) < np.float32(hr_margin)
+        pick |= near_dry | near_thr
+    keep = (np.asarray(state) != exited) & pick
+    i, j = i[keep], j[keep]
     if i.size == 0:
-        return 0, 0.0
+        return 0, 0.0, 0
     ha, qxa, qya = (np.asarray(f, np.float32)[j, i] for f in a)
     hb, qxb, qyb = (np.asarray(f, np.float32)[j, i] for f in b)
     d = np.abs(ha - hb)
     bad = (d > np.float32(tol)) | (hazard_class32(ha, qxa, qya, h_dry, thr)
                                     != hazard_class32(hb, qxb, qyb, h_dry, thr))
-    return int(bad.sum()), float(d.max())
+    return int(bad.sum()), float(d.max()), int(i.size)

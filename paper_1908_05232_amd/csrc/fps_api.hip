@@ -33,6 +33,7 @@ struct fps_sim {
     double* partials;
     int32_t* wet;
     float *h2, *qx2, *qy2;
+    float *h1, *qx1, *qy1;     // first stage of the second-order variant
     int32_t* np;
     int32_t *bin_count, *bin_start, *rank, *key, *perm_u, *perm;
     float2* xy;
@@ -85,6 +86,7 @@ struct Engine {
     bool dirty = true;
     int graph_chunk = 16;
     int hll = 0;                     // face flux of every scenario: HLL instead of HLLC
+    int order2 = 0;                  // second-order (MUSCL, two-stage) variant for every scenario
     hipGraphExec_t exec = nullptr;
     int exec_steps = 0;
     char err[512] = "";
@@ -160,7 +162,7 @@ bool valid_desc(const fps_grid_desc* d, char* why)
 
 // Per-scenario part of the workspace (offsets from the member's base).
 struct Layout {
-    size_t st, partials, wet, h2, qx2, qy2, np, bin_count, bin_start, rank, key, perm_u, perm, xy, slot,
+    size_t st, partials, wet, h2, qx2, qy2, h1, qx1, qy1, np, bin_count, bin_start, rank, key, perm_u, perm, xy, slot,
         wmask, line, stats, total;
     int64_t nbins_max;
     int32_t line_cap;
@@ -185,6 +187,9 @@ Layout member_layout(const fps_grid_desc* d, int32_t max_agents)
     L.h2 = take(sizeof(float) * nc);
     L.qx2 = take(sizeof(float) * nc);
     L.qy2 = take(sizeof(float) * nc);
+    L.h1 = take(sizeof(float) * nc);
+    L.qx1 = take(sizeof(float) * nc);
+    L.qy1 = take(sizeof(float) * nc);
     L.np = take(sizeof(int32_t) * nc);
     L.bin_count = take(max_agents > 0 ? sizeof(int32_t) * L.nbins_max : 0);
     L.bin_start = take(max_agents > 0 ? sizeof(int32_t) * (L.nbins_max + 1) : 0);
@@ -227,6 +232,9 @@ fps_sim* new_member(Engine* e, int idx, const fps_grid_desc* d, const fps_ped_pa
     s->h2 = at<float>(base, L.h2);
     s->qx2 = at<float>(base, L.qx2);
     s->qy2 = at<float>(base, L.qy2);
+    s->h1 = at<float>(base, L.h1);
+    s->qx1 = at<float>(base, L.qx1);
+    s->qy1 = at<float>(base, L.qy1);
     s->np = at<int32_t>(base, L.np);
     s->bin_count = at<int32_t>(base, L.bin_count);
     s->bin_start = at<int32_t>(base, L.bin_start);
@@ -285,6 +293,7 @@ void fill_scn(const fps_sim* s, Scn& c)
     p.h[0] = s->h; p.h[1] = s->h2;
     p.qx[0] = s->qx; p.qx[1] = s->qx2;
     p.qy[0] = s->qy; p.qy[1] = s->qy2;
+    p.h1 = s->h1; p.qx1 = s->qx1; p.qy1 = s->qy1;
     p.z = s->z;
     p.np = s->np;
     p.st = s->st;
@@ -404,6 +413,7 @@ Batch batch_of(const Engine* e, int s_only = -1)
     b.fin_lds_bytes = e->fin_lds_bytes;
     b.s_only = s_only;
     b.hll = e->hll;
+    b.order2 = e->order2;
     if (s_only >= 0) b.fv_blocks = fv_blocks_for_tiles(e->scn_h[s_only].fv.ntiles);
     if (e->S == 1) b.one = e->scn_h[0];
     return b;
@@ -1028,8 +1038,26 @@ int fps_bind_fields(fps_sim* s, float* h, float* hu, float* hv, float* z)
     int rc = write_state_i32(s, &s->st->status, 0);
     if (rc == FPS_OK) rc = write_state_i32(s, &s->st->settled, 0);
     if (rc == FPS_OK) rc = write_state_i32(s, &s->st->cur, 0);
+    if (rc == FPS_OK) rc = write_state_i32(s, &s->st->frozen, 0);
     if (rc != FPS_OK) return rc;
     return prime(s);
+}
+
+int fps_set_flood_frozen(fps_sim* s, int32_t frozen)
+{
+    if (!s) return fail(nullptr, FPS_E_INVALID, "fps_set_flood_frozen: sim is NULL");
+    if (frozen != 0 && frozen != 1) return fail(s, FPS_E_INVALID, "fps_set_flood_frozen: 0 or 1");
+    if (!s->fields_bound) return fail(s, FPS_E_STATE, "fps_set_flood_frozen: fields not bound");
+    int rc = write_state_i32(s, &s->st->frozen, frozen);
+    if (rc != FPS_OK) return rc;
+    if (frozen) {
+        // held steps have the fixed length dt_max and add no inflow
+        const float dt = (float)s->G.dt_max;
+        HIPCHK(s, hipMemcpyAsync(&s->st->dt, &dt, sizeof(dt), hipMemcpyHostToDevice, s->eng->stream));
+        HIPCHK(s, hipStreamSynchronize(s->eng->stream));
+        return FPS_OK;
+    }
+    return prime(s);     // the time step of the current state again
 }
 
 int fps_set_hydrograph(fps_sim* s, const double* t, const double* q, int32_t npts)
@@ -1195,6 +1223,8 @@ int fps_set_judge_region(fps_sim* s, const uint8_t* mask, int32_t block)
     if (!s) return fail(nullptr, FPS_E_INVALID, "fps_set_judge_region: sim is NULL");
     if (mask && (block < 1 || block > 4096))
         return fail(s, FPS_E_INVALID, "fps_set_judge_region: block must be in [1, 4096]");
+    if (mask && s->eng->order2)
+        return fail(s, FPS_E_STATE, "fps_set_judge_region: not with the second-order variant");
     s->jmask = mask;
     s->jb = mask ? block : 0;
     mark_dirty(s);
@@ -1223,6 +1253,33 @@ int fps_set_end_time(fps_sim* s, double t_end)
     HIPCHK(s, hipStreamSynchronize(st));
     s->t_end = t_end;
     return write_state_i32(s, &s->st->active, !(t_end > 0.0) || t < t_end);
+}
+
+// the order of every scenario of an engine (1 or 2)
+static int set_order(Engine* e, int32_t order, char* err)
+{
+    if (order != 1 && order != 2) return (snprintf(err, 512, "order must be 1 or 2, got %d", order), FPS_E_INVALID);
+    if (order == 2)
+        for (fps_sim* s : e->m)
+            if (s->jmask)
+                return (snprintf(err, 512, "scenario %d has a judge region (first order only)", s->idx),
+                        FPS_E_STATE);
+    e->order2 = order == 2;
+    drop_graph(e);      // the captured launches name the kernels of the old order
+    return FPS_OK;
+}
+
+int fps_set_order(fps_sim* s, int32_t order)
+{
+    if (!s) return fail(nullptr, FPS_E_INVALID, "fps_set_order: sim is NULL");
+    if (!s->eng->standalone) return fail(s, FPS_E_STATE, "fps_set_order: member of an ensemble; use fps_ens_set_order");
+    return set_order(s->eng, order, s->err);
+}
+
+int fps_ens_set_order(fps_ens* e, int32_t order)
+{
+    if (!e) return fail(nullptr, FPS_E_INVALID, "fps_ens_set_order: ens is NULL");
+    return set_order(e, order, e->err);
 }
 
 int fps_set_flux(fps_sim* s, int32_t flux)
@@ -1303,6 +1360,20 @@ int fps_get_diag(fps_sim* s, fps_diag* out)
     return FPS_OK;
 }
 
+int fps_get_time(fps_sim* s, double* t, double* dt_next)
+{
+    if (!s || !t || !dt_next) return fail(s, FPS_E_INVALID, "fps_get_time: NULL argument");
+    hipStream_t st = s->eng->stream;
+    double tt = 0.0;
+    float dt = 0.0f;
+    HIPCHK(s, hipMemcpyAsync(&tt, &s->st->t, sizeof(tt), hipMemcpyDeviceToHost, st));
+    HIPCHK(s, hipMemcpyAsync(&dt, &s->st->dt, sizeof(dt), hipMemcpyDeviceToHost, st));
+    HIPCHK(s, hipStreamSynchronize(st));
+    *t = tt;
+    *dt_next = dt;
+    return FPS_OK;
+}
+
 int fps_hazard_field(fps_sim* s, float* hr_out)
 {
     if (!s || !hr_out) return fail(s, FPS_E_INVALID, "fps_hazard_field: NULL argument");
@@ -1372,6 +1443,40 @@ int fps_autotune(fps_sim* s, const char* cache_path, int32_t* rows_out, double* 
     if (rc != FPS_OK) return rc;
     if (rows_out) *rows_out = rows;
     if (ms_out) *ms_out = ms;
+    return FPS_OK;
+}
+
+int fps_stream_probe(float* buf, int64_t n, int64_t stride, int32_t n_in, int32_t n_out, int32_t reps, void* stream,
+                     double* ms_per_pass)
+{
+    const bool shape = (n_in == 1 && n_out == 1) || (n_in == 4 && n_out == 3) || (n_in == 5 && n_out == 3);
+    if (!buf || !ms_per_pass || n < 4 || n % 4 || stride < n || stride % 4 || !shape || reps < 1 ||
+        (reinterpret_cast<uintptr_t>(buf) & 15))
+        return fail(nullptr, FPS_E_INVALID, "fps_stream_probe: bad argument");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                                 hipSuccess)
+        cus = 256;
+    const int blocks = (int)std::min<int64_t>((n / 4 + 255) / 256, (int64_t)cus * 16);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return fail(nullptr, FPS_E_DEVICE, "fps_stream_probe: event");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(nullptr, FPS_E_DEVICE, "fps_stream_probe: event");
+    }
+    hipError_t e = launch_stream_probe(buf, n, stride, n_in, n_out, blocks, st);
+    if (e == hipSuccess) e = launch_stream_probe(buf, n, stride, n_in, n_out, blocks, st);
+    if (e == hipSuccess) e = hipEventRecord(e0, st);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_stream_probe(buf, n, stride, n_in, n_out, blocks, st);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return fail(nullptr, FPS_E_DEVICE, "fps_stream_probe: %s", hipGetErrorString(e));
+    *ms_per_pass = ms / reps;
     return FPS_OK;
 }
 

@@ -54,14 +54,16 @@ __device__ __forceinline__ int wave_inclusive_scan(int v)
     return v;
 }
 
-// A step whose flood update is the identity and is skipped: nothing is wet,
-// no inflow enters during the step, and the state already came out of a flood
-// update (so dry cells carry no discharge).  The 1 s dry step of sec. 3 then
-// only advances the pedestrians.  Every kernel of the step evaluates this on
-// the same device state before the finalize changes it.
+// A step whose flood update is skipped: either it is the identity (nothing
+// is wet, no inflow enters during the step, and the state already came out of
+// a flood update, so dry cells carry no discharge; the 1 s dry step of sec. 3
+// then only advances the pedestrians), or the flood is held by the caller
+// (fps_set_flood_frozen: the pedestrians walk on a flood state set from
+// outside).  Every kernel of the step evaluates this on the same device state
+// before the finalize changes it.
 __device__ __forceinline__ bool flood_skipped(const DevState* st)
 {
-    return st->settled && !st->any_wet && st->inc == 0.0f;
+    return st->frozen || (st->settled && !st->any_wet && st->inc == 0.0f);
 }
 
 __device__ __forceinline__ double hydro_q(const DevState* st, double t)

@@ -429,6 +429,255 @@ __global__ __launch_bounds__(kFvBlock) void fv_step_kernel(Batch B)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Second-order variant (the scheme the paper reduced to first order, sec.
+// 2.2): MUSCL reconstruction of (h, eta = h + z, u, v) per direction with
+// the minmod limiter (zero slope where the cell or a neighbour in that
+// direction is dry, and in ghost cells), the hydrostatic reconstruction and
+// the HLLC / HLL flux of the first-order scheme at each face on the
+// reconstructed states, the second-order bed-slope form of Audusse et al.
+// (2004) (each face adds g/2 (h_f^2 - h*_f^2) to its side's normal momentum,
+// each cell the centred -g/2 (h_w + h_e)(z_e - z_w)), and Heun's two-stage
+// Runge-Kutta step: U1 = U + dt L(U), U' = (U + U1 + dt L(U1)) / 2, with the
+// depth cleanup after each stage and the inflow and friction once after both.
+// A lane updates one cell from its plus-shaped stencil of radius 2 (faces
+// shared with the neighbours are evaluated again by them); the tiles are
+// those of the first-order march, so partials and wetness flags are the same.
+// ---------------------------------------------------------------------------
+struct V4 {
+    float h, eta, u, v;     // depth, surface elevation, velocities (0 where h <= h_dry)
+};
+
+__device__ __forceinline__ float minmod(float a, float b)
+{
+    return a * b > 0.0f ? (fabsf(a) <= fabsf(b) ? a : b) : 0.0f;
+}
+
+// cell (i, j) with one ghost layer (not both outside); *ghost for ghosts
+__device__ __forceinline__ V4 cell_v4(const Src& s, const FvParams& p, int i, int j, bool& ghost)
+{
+    const int ii = min(max(i, 0), p.nx - 1), jj = min(max(j, 0), p.ny - 1);
+    const uint32_t k = (uint32_t)jj * (uint32_t)p.nx + (uint32_t)ii;
+    V4 v;
+    v.h = ld(s.h, k);
+    v.eta = v.h + ld(s.z, k);
+    const float r = v.h > p.eps ? rcp(v.h) : 0.0f;
+    v.u = ld(s.qx, k) * r;
+    v.v = ld(s.qy, k) * r;
+    ghost = i != ii || j != jj;
+    if ((i < 0 && p.bc[0] == FPS_BC_WALL) || (i >= p.nx && p.bc[1] == FPS_BC_WALL)) v.u = -v.u;
+    if ((j < 0 && p.bc[2] == FPS_BC_WALL) || (j >= p.ny && p.bc[3] == FPS_BC_WALL)) v.v = -v.v;
+    return v;
+}
+
+// the state of cell (i, j) reconstructed at its face on side sgn (+1 east /
+// north, -1 west / south) of direction dir (0: x, 1: y); b is the cell itself
+__device__ __forceinline__ V4 face_state(const Src& s, const FvParams& p, int i, int j, int dir, float sgn)
+{
+    bool gb, ga, gc;
+    V4 b = cell_v4(s, p, i, j, gb);
+    if (gb) return b;
+    const V4 a = dir == 0 ? cell_v4(s, p, i - 1, j, ga) : cell_v4(s, p, i, j - 1, ga);
+    const V4 c = dir == 0 ? cell_v4(s, p, i + 1, j, gc) : cell_v4(s, p, i, j + 1, gc);
+    if (!(a.h > p.eps) || !(b.h > p.eps) || !(c.h > p.eps)) return b;
+    const float hf = 0.5f * sgn;
+    b.h += hf * minmod(c.h - b.h, b.h - a.h);
+    b.eta += hf * minmod(c.eta - b.eta, b.eta - a.eta);
+    b.u += hf * minmod(c.u - b.u, b.u - a.u);
+    b.v += hf * minmod(c.v - b.v, b.v - a.v);
+    return b;
+}
+
+// one face between reconstructed states L and R in the face's normal
+// direction (un, ut: normal and tangential velocity, limited between the
+// neighbours' velocities): flux and, per side, the reconstructed depth, the
+// hydrostatic depth and the face bed
+template <bool kHll>
+__device__ __forceinline__ void face2(const FvParams& p, float hL, float etaL, float unL, float utL, float hR,
+                                      float etaR, float unR, float utR, bool wall, float& F0, float& F1,
+                                      float& F2, float& hsL, float& hsR, float& zL, float& zR)
+{
+    zL = etaL - hL;
+    zR = etaR - hR;
+    const bool wL = hL > p.eps, wR = hR > p.eps;
+    float pL, pR;
+    face_flux<kHll>(p, hL, wL ? unL : 0.0f, wL ? utL : 0.0f, zL, hR, wR ? unR : 0.0f, wR ? utR : 0.0f, zR, wall,
+                    F0, F1, F2, pL, pR);
+    // the hydrostatic depths back from their pressures is not exact: recompute
+    const float zf = zL > zR ? zL : zR;
+    float hl = hL - (zf - zL), hr = hR - (zf - zR);
+    hsL = hl > p.eps ? hl : 0.0f;
+    hsR = hr > p.eps ? hr : 0.0f;
+}
+
+// dt L(U) at cell (i, j) of state s, and the outflow rate through the
+// transmissive sides of that cell's boundary faces
+template <bool kHll>
+__device__ __forceinline__ void residual2(const Src& s, const FvParams& p, int i, int j, float lx, float ly,
+                                          float& dh, float& dqx, float& dqy, double& vout_rate)
+{
+    float FW0, FW1, FW2, FE0, FE1, FE2, FS0, FS1, FS2, FN0, FN1, FN2;
+    float hsW, hsE, hsS, hsN, zW, zE, zS, zN, d0, d1, d2, d3;
+    // west face: (i-1 east side, i west side)
+    const V4 wl = face_state(s, p, i - 1, j, 0, 1.0f), wr = face_state(s, p, i, j, 0, -1.0f);
+    face2<kHll>(p, wl.h, wl.eta, wl.u, wl.v, wr.h, wr.eta, wr.u, wr.v, i == 0 && p.bc[0] == FPS_BC_WALL,
+                FW0, FW1, FW2, d0, hsW, d1, zW);
+    const V4 er = face_state(s, p, i + 1, j, 0, -1.0f), el = face_state(s, p, i, j, 0, 1.0f);
+    face2<kHll>(p, el.h, el.eta, el.u, el.v, er.h, er.eta, er.u, er.v,
+                i == p.nx - 1 && p.bc[1] == FPS_BC_WALL, FE0, FE1, FE2, hsE, d2, zE, d3);
+    // south and north faces: y is normal
+    const V4 sl = face_state(s, p, i, j - 1, 1, 1.0f), sr = face_state(s, p, i, j, 1, -1.0f);
+    face2<kHll>(p, sl.h, sl.eta, sl.v, sl.u, sr.h, sr.eta, sr.v, sr.u, j == 0 && p.bc[2] == FPS_BC_WALL,
+                FS0, FS1, FS2, d0, hsS, d1, zS);
+    const V4 nr = face_state(s, p, i, j + 1, 1, -1.0f), nl = face_state(s, p, i, j, 1, 1.0f);
+    face2<kHll>(p, nl.h, nl.eta, nl.v, nl.u, nr.h, nr.eta, nr.v, nr.u,
+                j == p.ny - 1 && p.bc[3] == FPS_BC_WALL, FN0, FN1, FN2, hsN, d2, zN, d3);
+    const float hw = wr.h, he = el.h, hS = sr.h, hN = nl.h;
+    const float cx = p.half_g * (he * he - hsE * hsE) - p.half_g * (hw * hw - hsW * hsW) +
+                     p.half_g * (hw + he) * (zE - zW);
+    const float cy = p.half_g * (hN * hN - hsN * hsN) - p.half_g * (hS * hS - hsS * hsS) +
+                     p.half_g * (hS + hN) * (zN - zS);
+    dh = -(lx * (FE0 - FW0) + ly * (FN0 - FS0));
+    dqx = -(lx * ((FE1 - FW1) + cx) + ly * (FN2 - FS2));
+    dqy = -(ly * ((FN1 - FS1) + cy) + lx * (FE2 - FW2));
+    vout_rate = 0.0;
+    if (i == 0 && p.bc[0] == FPS_BC_TRANSMISSIVE) vout_rate -= (double)FW0 * p.dy;
+    if (i == p.nx - 1 && p.bc[1] == FPS_BC_TRANSMISSIVE) vout_rate += (double)FE0 * p.dy;
+    if (j == 0 && p.bc[2] == FPS_BC_TRANSMISSIVE) vout_rate -= (double)FS0 * p.dx;
+    if (j == p.ny - 1 && p.bc[3] == FPS_BC_TRANSMISSIVE) vout_rate += (double)FN0 * p.dx;
+}
+
+// One Runge-Kutta stage of the second-order variant over one tile of the
+// march (lanes 1..kStrip of a wave own a column each; kStage 1: U1 = U + dt
+// L(U) into the stage buffer; kStage 2: U' = (U + U1 + dt L(U1)) / 2 into the
+// other ping-pong buffer, then inflow, friction, volumes and the wave speed).
+// The outflow and clipped volumes of stage 1 are left in the tile's partial
+// slots for stage 2 to add to (each stage counts half).
+template <bool kOne, bool kHll, int kStage>
+__global__ __launch_bounds__(kFvBlock) void fv2_stage_kernel(Batch B)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int g = __builtin_amdgcn_readfirstlane(
+        xcd_tile_block(blockIdx.x, B.fv_blocks) * (kFvBlock / kWave) + (int)(threadIdx.x >> 6));
+    int sc, tile;
+    if (kOne) {
+        sc = 0;
+        tile = g;
+    } else if (B.s_only >= 0) {
+        sc = B.s_only;
+        tile = g;
+    } else {
+        if (g >= B.total_tiles) return;
+        sc = find_scenario(B.tile_off, B.S, g);
+        tile = g - B.tile_off[sc];
+    }
+    const FvParams p = scn_at<kOne>(B, sc).fv;
+    if (tile >= p.ntiles) return;
+    DevState* st = p.st;
+    if (!st->active || flood_skipped(st)) return;
+    const int cur = __builtin_amdgcn_readfirstlane(st->cur);
+    const Src s0{gmem<const float>(cur ? p.h[1] : p.h[0]), gmem<const float>(cur ? p.qx[1] : p.qx[0]),
+                 gmem<const float>(cur ? p.qy[1] : p.qy[0]), gmem(p.z)};
+    const Src s1{gmem<const float>(p.h1), gmem<const float>(p.qx1), gmem<const float>(p.qy1), gmem(p.z)};
+    const float dt = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, st->dt)));
+    const float inc = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, st->inc)));
+    const float lx = dt * p.inv_dx, ly = dt * p.inv_dy;
+    const int sx = tile % p.nsx, sy = tile / p.nsx;
+    const int i = sx * kStrip - 1 + lane;
+    const int j0 = sy * p.H, j1 = min(j0 + p.H, p.ny);
+    const bool out_lane = lane >= 1 && lane <= kStrip && i < p.nx;
+    double m_acc = 0.0, vout_acc = 0.0, vclip_acc = 0.0;
+    float smax = 0.0f;
+    FPS_GLOBAL double* part = gmem(&p.partials[4 * tile]);
+    if (out_lane) {
+        for (int j = j0; j < j1; ++j) {
+            const uint32_t k = (uint32_t)j * (uint32_t)p.nx + (uint32_t)i;
+            float dh, dqx, dqy;
+            double rate;
+            residual2<kHll>(kStage == 1 ? s0 : s1, p, i, j, lx, ly, dh, dqx, dqy, rate);
+            vout_acc += 0.5 * rate * (double)dt;
+            const Src& base = kStage == 1 ? s0 : s1;
+            float h = ld(base.h, k) + dh, qx = ld(base.qx, k) + dqx, qy = ld(base.qy, k) + dqy;
+            if (h < 0.0f) {
+                vclip_acc += 0.5 * (double)(-h);
+                h = 0.0f;
+            }
+            if (!(h > p.eps)) {
+                qx = 0.0f;
+                qy = 0.0f;
+            }
+            if (kStage == 1) {
+                st_at(gmem(p.h1), k, h);
+                st_at(gmem(p.qx1), k, qx);
+                st_at(gmem(p.qy1), k, qy);
+                continue;
+            }
+            float hn = 0.5f * (ld(s0.h, k) + h), qxn = 0.5f * (ld(s0.qx, k) + qx), qyn = 0.5f * (ld(s0.qy, k) + qy);
+            bool inflow = false;
+            if (p.inflow_side == FPS_SIDE_S) inflow = j == 0 && i >= p.c0 && i < p.c1;
+            else if (p.inflow_side == FPS_SIDE_N) inflow = j == p.ny - 1 && i >= p.c0 && i < p.c1;
+            else if (p.inflow_side == FPS_SIDE_W) inflow = i == 0 && j >= p.c0 && j < p.c1;
+            else if (p.inflow_side == FPS_SIDE_E) inflow = i == p.nx - 1 && j >= p.c0 && j < p.c1;
+            if (inflow) hn += inc;
+            if (!(hn > p.eps)) {
+                qxn = 0.0f;
+                qyn = 0.0f;
+            }
+            if (hn > p.eps) {
+                const float r = rcp(hn);
+                float u = qxn * r, v = qyn * r;
+                const float V2 = u * u + v * v;
+                if (V2 > 0.0f) {
+                    // Manning friction, splitting point-implicit (as in the first-order update)
+                    const int npc = ld(gmem<const int32_t>(p.np), k);
+                    const float n = p.n_base + (float)min(npc, p.np_cap) * p.n_base;
+                    const float speed = sqrt_fast(V2);
+                    const float hm13 = __builtin_amdgcn_exp2f(-__builtin_amdgcn_logf(hn) * (1.0f / 3.0f));
+                    const float Cf = p.g * n * n * hm13;
+                    const float Sx = -Cf * u * speed, Sy = -Cf * v * speed;
+                    const float a = dt * Cf * r * rcp(speed);
+                    const float Dx = 1.0f + a * (2.0f * u * u + v * v);
+                    const float Dy = 1.0f + a * (2.0f * v * v + u * u);
+                    float dfx = dt * Sx * rcp(Dx), dfy = dt * Sy * rcp(Dy);
+                    if (fabsf(dfx) > fabsf(qxn)) dfx = -qxn;
+                    if (fabsf(dfy) > fabsf(qyn)) dfy = -qyn;
+                    qxn += dfx;
+                    qyn += dfy;
+                    u = qxn * r;
+                    v = qyn * r;
+                }
+                const float cel = sqrt_fast(p.g * hn);
+                smax = fmaxf(smax, fmaxf((fabsf(u) + cel) * p.inv_dx, (fabsf(v) + cel) * p.inv_dy));
+            }
+            m_acc += (double)hn;
+            st_at(gmem(cur ? p.h[0] : p.h[1]), k, hn);
+            st_at(gmem(cur ? p.qx[0] : p.qx[1]), k, qxn);
+            st_at(gmem(cur ? p.qy[0] : p.qy[1]), k, qyn);
+        }
+    }
+    // the two stages' volumes in the tile's partials (stage 1 leaves its
+    // outflow and clipped volumes there for stage 2)
+    vout_acc = wave_sum(vout_acc);
+    vclip_acc = wave_sum(vclip_acc);
+    if (kStage == 1) {
+        if (lane == 0) {
+            part[1] = vout_acc;
+            part[2] = vclip_acc;
+        }
+        return;
+    }
+    m_acc = wave_sum(m_acc);
+    smax = wave_max(smax);
+    if (lane == 0) {
+        const double vo1 = part[1], vc1 = part[2];
+        part[0] = m_acc;
+        part[1] = vo1 + vout_acc;
+        part[2] = vc1 + vclip_acc;
+        part[3] = (double)smax;
+        if (smax > 0.0f) st_at(gmem(p.wet), (uint32_t)(kWetStride * (blockIdx.x & (kWetSlots - 1))), 1);
+    }
+}
+
 // Scan of the current state only: mass, wetness and the time step that the
 // next update will use (no time advance).  One scenario; one partial per block.
 __global__ __launch_bounds__(kFvBlock) void fv_scan_kernel(Batch B, int sc)
@@ -723,7 +972,39 @@ __global__ void reset_cur_kernel(Batch B)
     for (int s = threadIdx.x; s < B.S; s += blockDim.x) B.scn[s].fv.st->cur = 0;
 }
 
+// Streaming probe: n_in arrays read and n_out arrays written, 16 bytes a
+// lane, grid-stride; out_k = sum of the inputs + k, so every input byte is
+// used.  A bandwidth ceiling for kernels that stream SoA fields.
+template <int NIN, int NOUT>
+__global__ __launch_bounds__(256) void stream_probe_kernel(float* __restrict__ buf, int64_t n4, int64_t stride4)
+{
+    const float4* in = reinterpret_cast<const float4*>(buf);
+    float4* out = reinterpret_cast<float4*>(buf) + NIN * stride4;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (int64_t)gridDim.x * blockDim.x) {
+        float4 a[NIN];
+#pragma unroll
+        for (int k = 0; k < NIN; ++k) a[k] = in[k * stride4 + i];
+        float4 t = a[0];
+#pragma unroll
+        for (int k = 1; k < NIN; ++k) t = make_float4(t.x + a[k].x, t.y + a[k].y, t.z + a[k].z, t.w + a[k].w);
+#pragma unroll
+        for (int k = 0; k < NOUT; ++k)
+            out[k * stride4 + i] = make_float4(t.x + (float)k, t.y + (float)k, t.z + (float)k, t.w + (float)k);
+    }
+}
+
 }  // namespace
+
+hipError_t launch_stream_probe(float* buf, int64_t n, int64_t stride, int n_in, int n_out, int blocks, hipStream_t s)
+{
+    const int64_t n4 = n / 4, s4 = stride / 4;
+    const dim3 grid(blocks), block(256);
+    if (n_in == 1 && n_out == 1) hipLaunchKernelGGL((stream_probe_kernel<1, 1>), grid, block, 0, s, buf, n4, s4);
+    else if (n_in == 5 && n_out == 3) hipLaunchKernelGGL((stream_probe_kernel<5, 3>), grid, block, 0, s, buf, n4, s4);
+    else if (n_in == 4 && n_out == 3) hipLaunchKernelGGL((stream_probe_kernel<4, 3>), grid, block, 0, s, buf, n4, s4);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
 
 int fv_rows_per_wave(int nx, int ny)
 {
@@ -749,6 +1030,27 @@ int fv_blocks_for_tiles(int64_t tiles)
 
 hipError_t launch_fv(const Batch& b, hipStream_t s)
 {
+    if (b.fv_blocks > 0 && b.order2) {
+        const dim3 grid(b.fv_blocks), block(kFvBlock);
+        if (b.S == 1) {
+            if (b.hll) {
+                hipLaunchKernelGGL((fv2_stage_kernel<true, true, 1>), grid, block, 0, s, b);
+                hipLaunchKernelGGL((fv2_stage_kernel<true, true, 2>), grid, block, 0, s, b);
+            } else {
+                hipLaunchKernelGGL((fv2_stage_kernel<true, false, 1>), grid, block, 0, s, b);
+                hipLaunchKernelGGL((fv2_stage_kernel<true, false, 2>), grid, block, 0, s, b);
+            }
+        } else {
+            if (b.hll) {
+                hipLaunchKernelGGL((fv2_stage_kernel<false, true, 1>), grid, block, 0, s, b);
+                hipLaunchKernelGGL((fv2_stage_kernel<false, true, 2>), grid, block, 0, s, b);
+            } else {
+                hipLaunchKernelGGL((fv2_stage_kernel<false, false, 1>), grid, block, 0, s, b);
+                hipLaunchKernelGGL((fv2_stage_kernel<false, false, 2>), grid, block, 0, s, b);
+            }
+        }
+        return hipGetLastError();
+    }
     if (b.fv_blocks > 0) {
         const dim3 grid(b.fv_blocks), block(kFvBlock);
         if (b.S == 1) {

@@ -53,6 +53,7 @@ struct DevState {
     // sandbag barrier (sec. 2.4)
     int32_t layers_done, active_cell, bags, done, drops, drops_total;
     int32_t settled;       // the state came out of a flood update (dry cells carry no discharge)
+    int32_t frozen;        // the flood update is held: steps of dt_max move only the pedestrians
 };
 
 struct FvParams {
@@ -62,6 +63,9 @@ struct FvParams {
     const float* z;
     const int32_t* np;
     DevState* st;
+    float* h1;             // the first Runge-Kutta stage of the second-order variant
+    float* qx1;
+    float* qy1;
     double* partials;      // [ntiles][4]: mass sum, outflow volume, clipped depth, max speed
     int32_t* wet;          // [kWetSlots * kWetStride]: set by waves with a wet cell, cleared by the finalize
     int nx, ny, H, nsx, ntiles;
@@ -157,6 +161,7 @@ struct Batch {
     int s_only;            // >= 0: restrict the flood launch to one scenario (tuning)
     Scn one;               // S == 1: the scenario itself, read from the kernel arguments
     int hll;               // face flux: HLL (1) or HLLC (0), the same for every scenario
+    int order2;            // the second-order (MUSCL, two-stage) variant for every scenario
 };
 
 // launchers (stream-ordered, no synchronisation)
@@ -169,6 +174,9 @@ hipError_t launch_finalize(const Batch& b, int mode, int s_first, int count, hip
 hipError_t prepare_finalize(int lds_bytes);   // host, outside any capture: allow that much dynamic LDS
 hipError_t launch_sync_back(const Batch& b, int64_t max_cells, hipStream_t s);
 hipError_t launch_ped(const Batch& b, hipStream_t s);
+// n_in = 1, 4 or 5 arrays in and n_out = 1 or 3 out (see fps_stream_probe)
+hipError_t launch_stream_probe(float* buf, int64_t n, int64_t stride, int n_in, int n_out, int blocks,
+                               hipStream_t s);
 int ped_lanes(int64_t total_agents);     // lanes per agent of the pedestrian step
 hipError_t launch_bin_place_all(const Batch& b, hipStream_t s);
 hipError_t launch_bin_sort_all(const Batch& b, hipStream_t s);

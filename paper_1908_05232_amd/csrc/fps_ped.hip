@@ -483,7 +483,8 @@ __global__ __launch_bounds__(kWave) void ped_step_kernel(Batch B)
     const int done = st->done;
     // evacuation trigger: some cell is wet after this step's flood update
     // one wetness flag per lane (the flood update sets them per group of blocks)
-    const int wet = skipped ? 0 : (__ballot(S.fv.wet[kWetStride * threadIdx.x] != 0) != 0ull);
+    // (a skipped update left the state, and its wetness, as they were)
+    const int wet = skipped ? st->any_wet : (__ballot(S.fv.wet[kWetStride * threadIdx.x] != 0) != 0ull);
     int drop = 0;
     if (a < S.na)
         agent_step<L>(P, rec, fb ? S.fv.h[1] : S.fv.h[0], fb ? S.fv.qx[1] : S.fv.qx[0], fb ? S.fv.qy[1] : S.fv.qy[0],
@@ -587,13 +588,26 @@ __global__ void hazard_kernel(const float* h, const float* qx, const float* qy, 
     }
 }
 
+// Counts per hazard class (non-exited agents) and per state: each wave counts
+// its agents by ballots, one lane adds the wave's counts (integer sums, so
+// the order does not matter).
 __global__ void agent_stats_kernel(const uint8_t* state, const uint8_t* cls, int na, int32_t* out)
 {
-    int a = blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= na) return;
-    int s = state[a];
-    atomicAdd(&out[5 + min(s, 5)], 1);
-    if (s != FPS_ST_EXITED) atomicAdd(&out[min((int)cls[a], 4)], 1);
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool in = a < na;
+    const int s = in ? min((int)state[a], 5) : -1;
+    const int c = in && s != FPS_ST_EXITED ? min((int)cls[a], 4) : -1;
+    const bool first = (threadIdx.x & (kWave - 1)) == 0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const int n = __popcll(__ballot(s == k));
+        if (first && n) atomicAdd(&out[5 + k], n);
+    }
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const int n = __popcll(__ballot(c == k));
+        if (first && n) atomicAdd(&out[k], n);
+    }
 }
 
 // Per cell, one bit per offset (di, dj) in [-Rx, Rx] x [-Ry, Ry], row-major

@@ -521,22 +521,48 @@ __device__ __forceinline__ int cell_index(float x, float d, int n)
 // count those where the two flood states differ in depth by more than tol or
 // in hazard class (Table 1 thresholds), and the largest depth difference.
 // out[0] = count (int), out[1] = max |dh| (float bits).
-__global__ void judge_kernel(int na, int stride, const float* __restrict__ x, const float* __restrict__ y,
+// The people the judge looks at: every stride-th agent that has not exited,
+// and, when a selection state (hs, qxs, qys) is given, every agent whose
+// cell there is within h_margin of the dry threshold or has a hazard rate
+// within margin of a Table 1 threshold (people whose class a small depth
+// error could change).
+struct JudgePick {
+    int stride;
+    const float* hs;
+    const float* qxs;
+    const float* qys;
+    float margin, h_margin, eps, t1, t2, t3;
+};
+__device__ __forceinline__ bool judged(const JudgePick& q, int64_t a, size_t c)
+{
+    if (a % q.stride == 0) return true;
+    if (!q.hs) return false;
+    const float h = q.hs[c];
+    if (!(h > q.eps + q.h_margin)) return true;
+    const float hr = (fmaxf(fabsf(q.qxs[c] / h), fabsf(q.qys[c] / h)) + 0.5f) * h;
+    return fabsf(hr - q.t1) < q.margin || fabsf(hr - q.t2) < q.margin || fabsf(hr - q.t3) < q.margin;
+}
+
+__global__ void judge_kernel(int na, JudgePick q, const float* __restrict__ x, const float* __restrict__ y,
                              const uint8_t* __restrict__ state, int nx, int ny, float dx, float dy,
                              const float* __restrict__ ha, const float* __restrict__ qxa,
                              const float* __restrict__ qya, const float* __restrict__ hb,
                              const float* __restrict__ qxb, const float* __restrict__ qyb, float tol,
-                             float eps, float t1, float t2, float t3, int32_t* __restrict__ out)
+                             int32_t* __restrict__ out)
 {
-    const int64_t a = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * stride;
+    // every agent when a selection state is given, else only the sample
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t a = q.hs ? t : t * q.stride;
     if (a >= na || state[a] == FPS_ST_EXITED) return;
     const size_t c = (size_t)cell_index(y[a], dy, ny) * nx + cell_index(x[a], dx, nx);
-    const float thr[3] = {t1, t2, t3};
+    if (!judged(q, a, c)) return;
+    const float thr[3] = {q.t1, q.t2, q.t3};
     const float d = fabsf(ha[c] - hb[c]);
-    const bool bad = d > tol || hazard_class(ha[c], qxa[c], qya[c], eps, thr) !=
-                                    hazard_class(hb[c], qxb[c], qyb[c], eps, thr);
+    const bool bad = d > tol || hazard_class(ha[c], qxa[c], qya[c], q.eps, thr) !=
+                                    hazard_class(hb[c], qxb[c], qyb[c], q.eps, thr);
     if (bad) atomicAdd(&out[0], 1);
     atomicMax(&out[1], __float_as_int(d));    // non-negative floats order as ints
+    atomicAdd(&out[2], 1);
 }
 
 __global__ void fill_u8_kernel(uint8_t* p, int64_t n)
@@ -546,14 +572,16 @@ __global__ void fill_u8_kernel(uint8_t* p, int64_t n)
 }
 
 // Judge region: mark every block x block cell block within halo cells of a
-// sampled agent's cell (same sample as the judge).
-__global__ void judge_mask_kernel(int na, int stride, const float* __restrict__ x, const float* __restrict__ y,
+// judged agent's cell (the same people as the judge).
+__global__ void judge_mask_kernel(int na, JudgePick q, const float* __restrict__ x, const float* __restrict__ y,
                                   const uint8_t* __restrict__ state, int nx, int ny, float dx, float dy, int halo,
                                   int block, uint8_t* __restrict__ mask)
 {
-    const int64_t a = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * stride;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t a = q.hs ? t : t * q.stride;
     if (a >= na || state[a] == FPS_ST_EXITED) return;
     const int i = cell_index(x[a], dx, nx), j = cell_index(y[a], dy, ny);
+    if (!judged(q, a, (size_t)j * nx + i)) return;
     const int mbx = (nx + block - 1) / block;
     const int bx0 = max(i - halo, 0) / block, bx1 = min(i + halo, nx - 1) / block;
     const int by0 = max(j - halo, 0) / block, by1 = min(j + halo, ny - 1) / block;
@@ -1036,39 +1064,46 @@ int fps_sur_apply(int64_t npix, const float* y, float* h, float* hu, float* hv, 
 int fps_sur_judge(int32_t na, int32_t stride, const float* x, const float* y, const uint8_t* state, int32_t nx,
                   int32_t ny, double dx, double dy, const float* ha, const float* qxa, const float* qya,
                   const float* hb, const float* qxb, const float* qyb, double tol, double h_dry,
-                  const double* hr_thresholds, int32_t* out2, void* stream)
+                  const double* hr_thresholds, const float* hs, const float* qxs, const float* qys, double hr_margin,
+                  double h_margin, int32_t* out3, void* stream)
 {
-    if (na < 0 || stride < 1 || nx < 1 || ny < 1 || !(dx > 0) || !(dy > 0) || !out2 || !hr_thresholds ||
-        (na > 0 && (!x || !y || !state || !ha || !qxa || !qya || !hb || !qxb || !qyb)))
+    if (na < 0 || stride < 1 || nx < 1 || ny < 1 || !(dx > 0) || !(dy > 0) || !out3 || !hr_thresholds ||
+        (na > 0 && (!x || !y || !state || !ha || !qxa || !qya || !hb || !qxb || !qyb)) ||
+        (hs && (!qxs || !qys)) || !(hr_margin >= 0) || !(h_margin >= 0))
         return sfail(nullptr, FPS_E_INVALID, "fps_sur_judge: bad argument");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    hipLaunchKernelGGL(fill_u8_kernel, dim3(1), dim3(64), 0, st, reinterpret_cast<uint8_t*>(out2), (int64_t)8);
-    const int64_t ns = ((int64_t)na + stride - 1) / stride;
-    if (ns > 0) {
-        hipLaunchKernelGGL(judge_kernel, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, na, stride, x, y,
-                           state, nx, ny, (float)dx, (float)dy, ha, qxa, qya, hb, qxb, qyb, (float)tol,
-                           (float)h_dry, (float)hr_thresholds[0], (float)hr_thresholds[1],
-                           (float)hr_thresholds[2], out2);
-        SCHK(nullptr, hipGetLastError());
+    hipLaunchKernelGGL(fill_u8_kernel, dim3(1), dim3(64), 0, st, reinterpret_cast<uint8_t*>(out3), (int64_t)12);
+    const JudgePick q{stride, hs, qxs, qys, (float)hr_margin, (float)h_margin, (float)h_dry,
+                      (float)hr_thresholds[0], (float)hr_thresholds[1], (float)hr_thresholds[2]};
+    const int64_t nt = hs ? (int64_t)na : ((int64_t)na + stride - 1) / stride;
+    if (nt > 0) {
+        hipLaunchKernelGGL(judge_kernel, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, na, q, x, y, state,
+                           nx, ny, (float)dx, (float)dy, ha, qxa, qya, hb, qxb, qyb, (float)tol, out3);
     }
+    SCHK(nullptr, hipGetLastError());
     return FPS_OK;
 }
 
 int fps_sur_judge_mask(int32_t na, int32_t stride, const float* x, const float* y, const uint8_t* state,
-                       int32_t nx, int32_t ny, double dx, double dy, int32_t halo, int32_t block, uint8_t* mask,
-                       void* stream)
+                       int32_t nx, int32_t ny, double dx, double dy, const float* hs, const float* qxs,
+                       const float* qys, double h_dry, const double* hr_thresholds, double hr_margin, double h_margin,
+                       int32_t halo, int32_t block, uint8_t* mask, void* stream)
 {
     if (na < 0 || stride < 1 || nx < 1 || ny < 1 || !(dx > 0) || !(dy > 0) || halo < 0 || block < 1 || !mask ||
-        (na > 0 && (!x || !y || !state)))
+        (na > 0 && (!x || !y || !state)) || (hs && (!qxs || !qys || !hr_thresholds)) || !(hr_margin >= 0) ||
+        !(h_margin >= 0))
         return sfail(nullptr, FPS_E_INVALID, "fps_sur_judge_mask: bad argument");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int64_t nm = (int64_t)((nx + block - 1) / block) * ((ny + block - 1) / block);
     hipLaunchKernelGGL(fill_u8_kernel, dim3((unsigned)std::min<int64_t>((nm + 255) / 256, 1024)), dim3(256), 0, st,
                        mask, nm);
-    const int64_t ns = ((int64_t)na + stride - 1) / stride;
-    if (ns > 0)
-        hipLaunchKernelGGL(judge_mask_kernel, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, na, stride, x,
-                           y, state, nx, ny, (float)dx, (float)dy, halo, block, mask);
+    const JudgePick q{stride, hs, qxs, qys, (float)hr_margin, (float)h_margin, (float)h_dry,
+                      hs ? (float)hr_thresholds[0] : 0.0f, hs ? (float)hr_thresholds[1] : 0.0f,
+                      hs ? (float)hr_thresholds[2] : 0.0f};
+    const int64_t nt = hs ? (int64_t)na : ((int64_t)na + stride - 1) / stride;
+    if (nt > 0)
+        hipLaunchKernelGGL(judge_mask_kernel, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, na, q, x, y,
+                           state, nx, ny, (float)dx, (float)dy, halo, block, mask);
     SCHK(nullptr, hipGetLastError());
     return FPS_OK;
 }

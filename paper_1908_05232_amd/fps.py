@@ -69,6 +69,7 @@ EXPORTS = {
     "fps_set_time": (C.c_int, [_vp, C.c_double, C.c_int64]),
     "fps_step": (C.c_int, [_vp, C.c_int32]),
     "fps_get_diag": (C.c_int, [_vp, C.POINTER(DiagC)]),
+    "fps_get_time": (C.c_int, [_vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "fps_hazard_field": (C.c_int, [_vp, _vp]),
     "fps_get_counts": (C.c_int, [_vp, _vp]),
     "fps_get_bins": (C.c_int, [_vp, _vp, _vp, C.POINTER(C.c_int32)]),
@@ -76,6 +77,8 @@ EXPORTS = {
     "fps_set_end_time": (C.c_int, [_vp, C.c_double]),
     "fps_set_graph": (C.c_int, [_vp, C.c_int32]),
     "fps_set_flux": (C.c_int, [_vp, C.c_int32]),
+    "fps_set_order": (C.c_int, [_vp, C.c_int32]),
+    "fps_ens_set_order": (C.c_int, [_vp, C.c_int32]),
     "fps_ens_workspace_bytes": (C.c_size_t, [C.c_int32, C.POINTER(GridDescC), C.POINTER(C.c_int32)]),
     "fps_ens_create": (C.c_int, [C.c_int32, C.POINTER(GridDescC), C.POINTER(PedParamsC),
                                  C.POINTER(C.c_int32), _vp, C.c_size_t, _vp, C.POINTER(_vp)]),
@@ -105,14 +108,16 @@ EXPORTS = {
     "fps_inflow_depth": (C.c_int, [_vp, C.c_double, C.c_double, C.POINTER(C.c_double)]),
     "fps_time_flood": (C.c_int, [_vp, C.c_int32, C.POINTER(C.c_double)]),
     "fps_set_occupancy": (C.c_int, [_vp, _vp]),
+    "fps_set_flood_frozen": (C.c_int, [_vp, C.c_int32]),
     "fps_sur_pack": (C.c_int, [C.c_int32, C.c_int32, _vp, _vp, _vp, _vp, _vp, C.c_int32, C.c_int32, C.c_int32,
                                C.c_double, _vp, _vp]),
     "fps_sur_make_target": (C.c_int, [C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "fps_sur_apply": (C.c_int, [C.c_int64, _vp, _vp, _vp, _vp, C.c_float, C.c_float, _vp]),
     "fps_sur_judge": (C.c_int, [C.c_int32, C.c_int32, _vp, _vp, _vp, C.c_int32, C.c_int32, C.c_double,
                                 C.c_double, _vp, _vp, _vp, _vp, _vp, _vp, C.c_double, C.c_double,
-                                C.POINTER(C.c_double), _vp, _vp]),
+                                C.POINTER(C.c_double), _vp, _vp, _vp, C.c_double, C.c_double, _vp, _vp]),
     "fps_sur_judge_mask": (C.c_int, [C.c_int32, C.c_int32, _vp, _vp, _vp, C.c_int32, C.c_int32, C.c_double,
+                                     C.c_double, _vp, _vp, _vp, C.c_double, C.POINTER(C.c_double), C.c_double,
                                      C.c_double, C.c_int32, C.c_int32, _vp, _vp]),
     "fps_sur_occupancy": (C.c_int, [C.c_int32, _vp, _vp, _vp, _vp, C.c_int32, C.c_int32, C.c_double,
                                     C.c_double, _vp, _vp]),
@@ -121,6 +126,8 @@ EXPORTS = {
     "fps_set_rows_per_wave": (C.c_int, [_vp, C.c_int32]),
     "fps_get_rows_per_wave": (C.c_int, [_vp, C.POINTER(C.c_int32)]),
     "fps_autotune": (C.c_int, [_vp, C.c_char_p, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
+    "fps_stream_probe": (C.c_int, [_vp, C.c_int64, C.c_int64, C.c_int32, C.c_int32, C.c_int32, _vp,
+                                   C.POINTER(C.c_double)]),
     "fps_status_string": (C.c_char_p, [C.c_int]),
     "fps_last_error": (C.c_char_p, [_vp]),
 }
@@ -239,6 +246,11 @@ class Member:
         (a standalone simulation; an ensemble sets it for all its members)."""
         return self._check(self._lib.fps_set_flux(self.h_, int(flux)))
 
+    def set_order(self, order):
+        """Order of the flood update: 1 (first order) or 2 (the MUSCL variant);
+        a standalone simulation (an ensemble sets it for all its members)."""
+        return self._check(self._lib.fps_set_order(self.h_, int(order)))
+
     def rebind_fields(self):
         return self._check(self._lib.fps_bind_fields(self.h_, _ptr(self.h), _ptr(self.qx), _ptr(self.qy),
                                                      _ptr(self.z)))
@@ -259,6 +271,10 @@ class Member:
         self._jmask = mask
         ptr = _ptr(mask) if mask is not None else None
         return self._check(self._lib.fps_set_judge_region(self.h_, ptr, int(block)))
+
+    def set_flood_frozen(self, frozen):
+        """Hold the flood (steps of dt_max move only the pedestrians) or resume."""
+        return self._check(self._lib.fps_set_flood_frozen(self.h_, int(bool(frozen))))
 
     def set_occupancy(self, counts):
         self._occ = counts
@@ -294,6 +310,12 @@ class Member:
         out["state_count"] = list(d.state_count)
         out["rc"] = rc
         return out
+
+    def time(self):
+        """(simulated time, length of the next step) without a pass over the agents."""
+        t, dt = C.c_double(), C.c_double()
+        self._check(self._lib.fps_get_time(self.h_, C.byref(t), C.byref(dt)))
+        return t.value, dt.value
 
     def fields(self):
         self.torch.cuda.synchronize(self.device)
@@ -355,6 +377,8 @@ class Sim(Member):
         self._bind(h, sc, device)
         if getattr(d, "flux", FPS_FLUX_HLLC) != FPS_FLUX_HLLC:
             self.set_flux(d.flux)
+        if getattr(d, "order", 1) != 1:
+            self.set_order(d.order)
 
     def close(self):
         if getattr(self, "h_", None) and self.h_.value:
@@ -416,6 +440,11 @@ class Ensemble:
             raise FpsError(FPS_E_INVALID, "the scenarios of an ensemble share one face flux")
         if fluxes != {FPS_FLUX_HLLC}:
             self.set_flux(fluxes.pop())
+        orders = {getattr(sc.desc, "order", 1) for sc in scenarios}
+        if len(orders) > 1:
+            raise FpsError(FPS_E_INVALID, "the scenarios of an ensemble share one order")
+        if orders != {1}:
+            self.set_order(orders.pop())
 
     def _check(self, rc):
         if rc != FPS_OK:
@@ -441,6 +470,9 @@ class Ensemble:
 
     def set_flux(self, flux):
         return self._check(self._lib.fps_ens_set_flux(self.e_, int(flux)))
+
+    def set_order(self, order):
+        return self._check(self._lib.fps_ens_set_order(self.e_, int(order)))
 
     def autotune(self, cache_path=None):
         cp = None if cache_path is None else str(cache_path).encode()
@@ -631,30 +663,40 @@ def _sur_rc(rc):
 
 
 def sur_judge(x, y, state, nx, ny, dx, dy, a, b, tol=0.01, h_dry=1e-5,
-              hr_thresholds=(0.75, 1.5, 2.5), stride=1, out=None, stream=None):
+              hr_thresholds=(0.75, 1.5, 2.5), stride=1, select=None, hr_margin=0.0, h_margin=0.0,
+              out=None, stream=None):
     """Judge a surrogate state a = (h, qx, qy) against a finite-volume state b
-    at the cells of every stride-th agent; returns the device int32[2] result
-    (count of agents with |dh| > tol or another hazard class, max |dh| as
-    float bits)."""
+    at the cells of every stride-th agent and, with a selection state
+    select = (h, qx, qy), every agent there within hr_margin of a hazard
+    threshold or h_margin of the dry threshold; returns the device int32[3]
+    result (count of judged agents with |dh| > tol or another hazard class,
+    max |dh| as float bits, judged agents)."""
     import torch
     if out is None:
-        out = torch.empty(2, dtype=torch.int32, device=a[0].device)
+        out = torch.empty(3, dtype=torch.int32, device=a[0].device)
     thr = (C.c_double * 3)(*hr_thresholds)
+    sel = [None, None, None] if select is None else [_ptr(t) for t in select]
     _sur_rc(lib().fps_sur_judge(int(x.numel()), int(stride), _ptr(x), _ptr(y), _ptr(state), int(nx), int(ny),
                                 float(dx), float(dy), *[_ptr(t) for t in (*a, *b)], float(tol), float(h_dry),
-                                thr, _ptr(out), _stream_ptr(torch, a[0], stream)))
+                                thr, *sel, float(hr_margin), float(h_margin), _ptr(out),
+                                _stream_ptr(torch, a[0], stream)))
     return out
 
 
-def sur_judge_mask(x, y, state, nx, ny, dx, dy, halo, block, stride=1, out=None, stream=None):
+def sur_judge_mask(x, y, state, nx, ny, dx, dy, halo, block, stride=1, select=None, h_dry=1e-5,
+                   hr_thresholds=(0.75, 1.5, 2.5), hr_margin=0.0, h_margin=0.0, out=None, stream=None):
     """Judge-region mask (uint8 [ceil(ny/block), ceil(nx/block)]) around the
-    sampled agents' cells."""
+    judged agents' cells (the same people as sur_judge with the same
+    selection arguments)."""
     import torch
     if out is None:
         out = torch.empty(((ny + block - 1) // block, (nx + block - 1) // block), dtype=torch.uint8,
                           device=x.device)
+    thr = (C.c_double * 3)(*hr_thresholds)
+    sel = [None, None, None] if select is None else [_ptr(t) for t in select]
     _sur_rc(lib().fps_sur_judge_mask(int(x.numel()), int(stride), _ptr(x), _ptr(y), _ptr(state), int(nx),
-                                     int(ny), float(dx), float(dy), int(halo), int(block), _ptr(out),
+                                     int(ny), float(dx), float(dy), *sel, float(h_dry), thr, float(hr_margin),
+                                     float(h_margin), int(halo), int(block), _ptr(out),
                                      _stream_ptr(torch, x, stream)))
     return out
 
@@ -677,8 +719,27 @@ def sur_copy_state(src, dst, stream=None):
 
 
 def judge_result(out):
-    """(count, max |dh|) from a sur_judge result tensor."""
+    """(count, max |dh|, judged) from a sur_judge result tensor."""
     import numpy as np
     v = out.cpu().numpy().astype(np.int32)
-    return int(v[0]), float(v[1:2].view(np.float32)[0])
+    return int(v[0]), float(v[1:2].view(np.float32)[0]), int(v[2])
 
+
+
+def stream_probe(n, n_in, n_out, reps=20, skew=0, device="cuda", stream=None):
+    """fps_stream_probe on a fresh buffer holding n_in + n_out arrays of n floats,
+    each array skew floats after the end of the one before: mean ms per pass
+    and the bytes it moves (read + written)."""
+    import torch
+    stride = n + skew
+    buf = torch.ones((n_in + n_out) * stride, dtype=torch.float32, device=device)
+    ms = C.c_double()
+    _sur_rc_generic(lib().fps_stream_probe(_ptr(buf), int(n), int(stride), int(n_in), int(n_out), int(reps),
+                                           _stream_ptr(torch, buf, stream), C.byref(ms)))
+    del buf
+    return ms.value, 4 * (n_in + n_out) * n
+
+
+def _sur_rc_generic(rc):
+    if rc != FPS_OK:
+        raise FpsError(rc, (lib().fps_last_error(None) or b"").decode())

@@ -45,6 +45,7 @@ class GridDesc:
     n_base: float = 0.01         # clear cement (sec. 2.4)
     np_cap: int = 20             # at most 20 evacuees counted per cell (sec. 2.4)
     flux: int = 0                # face flux: 0 = HLLC, 1 = HLL for all three components
+    order: int = 1               # 1: the paper's first-order scheme; 2: the second-order (MUSCL) variant
 
 
 @dataclasses.dataclass

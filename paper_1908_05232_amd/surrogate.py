@@ -16,15 +16,23 @@ the host side of that workflow, all device work going through libfps:
 * train: Adam on the GPU with the library's forward/backward kernels.
 * evaluate: held-out pairs judged at the crowd's cells against the
   finite-volume result, beside the persistence baseline (no change).
-* AssistedEnsemble: the surrogate-assisted ensemble.  Per block of K steps
-  the network proposes the next state of every scenario; the finite-volume
-  method re-runs the K steps on the judge region only (the neighbourhoods
-  of a sample of the crowd, see fps_set_judge_region); a scenario whose
+* coupled_case(s): members of the large sweep (people walking to the exits)
+  with the step capped at 0.01 s, for the comparison of the two arms.
+* AssistedEnsemble: the surrogate-assisted coupled ensemble.  Per block of
+  K steps the network proposes the next flood state of every scenario; the
+  finite-volume method re-runs the K steps on the judge region only (the
+  neighbourhoods of the judged people: a sample of the crowd plus everyone
+  near a hazard-class boundary, see fps_set_judge_region); a scenario whose
   depth differs by more than 1 cm or whose hazard class (Table 1) differs at
-  any sampled person falls back to the finite-volume update for that block.
+  any judged person, or whose fixed step exceeds the CFL step, takes the
+  coupled finite-volume steps for that block; otherwise its people walk the
+  K steps on the accepted flood state.
+* bar_check: every person of the plain finite-volume arm against the
+  assisted arm's flood (the spec bar: 1 cm and the same class).
 """
 from __future__ import annotations
 
+import copy
 import dataclasses
 import time
 
@@ -226,103 +234,162 @@ def evaluate(sur: fps.Surrogate, cases, kept, tol=0.01, h_dry=1e-5):
     return res
 
 
-class AssistedEnsemble:
-    """Surrogate-assisted flood ensemble with the finite-volume judge and
-    fallback (see the module docstring).  All cases share one grid size.
-    stride: every stride-th person of each crowd is a judge point."""
+def coupled_case(seed: int, n: int = 2048, n_evac: int = 50000, dt_s: float = 0.01, master: int = 5) -> I.Scenario:
+    """A member of the large sweep (inputs.large_sweep: shopping centre with
+    a completed sandbag line, the inflow under way, the free area wet, a
+    crowd walking to the nearest exit) with the step capped at dt_s, so that
+    K steps of the learned update span K dt_s whenever the CFL step allows."""
+    sc = I._large_member((master, seed, n, n_evac))
+    sc.desc.dt_max = dt_s
+    return sc
 
-    def __init__(self, cases, params, chunk: int, stride: int = 1, tol: float = 0.01, halo: int = K_STEPS):
-        """params: packed FP32 parameters of a trained network (any grid size)."""
+
+def coupled_cases(S: int, n: int = 2048, n_evac: int = 50000, dt_s: float = 0.01, master: int = 5, workers: int = 8):
+    """coupled_case for seeds 0 .. S-1, built in worker processes."""
+    scs = I.large_sweep(S, n=n, n_evac=n_evac, seed=master, workers=workers)
+    for sc in scs:
+        sc.desc.dt_max = dt_s
+    return scs
+
+
+def _flood_only(sc: I.Scenario) -> I.Scenario:
+    c = copy.copy(sc)
+    c.agents = None
+    c.dist = None
+    c.walk = None
+    c.barrier = None
+    return c
+
+
+class AssistedEnsemble:
+    """Surrogate-assisted coupled ensemble with the finite-volume judge and
+    fallback (see the module docstring).  All scenarios share one grid size.
+
+    Per block of K steps and scenario: the network proposes the flood state
+    K steps on from (h, hu, hv, z, evacuee counts); the finite-volume method
+    re-runs the K steps on the judge region (the neighbourhoods of the judged
+    people, with the counts of the block start); the proposal is accepted
+    when every judged person's depth is within tol and hazard class is the
+    same, and when the fixed step dt_max is within the CFL limit of the block
+    start state.  Accepted: the flood takes the proposal and the people walk
+    K steps of dt_max on it (fps_set_flood_frozen).  Rejected: K coupled
+    finite-volume steps.  Judged people: every stride-th, plus everyone
+    whose cell at the block start is within h_margin of the dry threshold or
+    hr_margin of a Table 1 threshold."""
+
+    def __init__(self, scenarios, params, chunk: int, stride: int = 1, tol: float = 0.01, halo: int = K_STEPS,
+                 hr_margin: float = 0.1, h_margin: float = 0.01):
         import torch
         self.torch = torch
-        d0 = cases[0].sc.desc
-        self.sur = fps.Surrogate(chunk, d0.ny, d0.nx)
+        d = scenarios[0].desc
+        assert all(sc.desc.nx == d.nx and sc.desc.ny == d.ny for sc in scenarios)
+        self.d, self.S, self.chunk = d, len(scenarios), chunk
+        self.stride, self.tol, self.halo = stride, tol, halo
+        self.hr_margin, self.h_margin = hr_margin, h_margin
+        self.sur = fps.Surrogate(chunk, d.ny, d.nx)
         self.sur.set_params(params)
-        self.cases, self.chunk = cases, chunk
-        self.stride, self.tol = stride, tol
-        d = cases[0].sc.desc
-        assert all(c.sc.desc.nx == d.nx and c.sc.desc.ny == d.ny for c in cases)
-        self.d = d
         self.dt = float(np.float32(d.dt_max))
-        self.E, self.crowds = _flood_ensemble(cases)
-        self.J, _ = _flood_ensemble(cases)
-        self.masks = []
-        for m, cr in zip(self.J.members, self.crowds):
-            mk = fps.sur_judge_mask(cr.t["x"], cr.t["y"], cr.t["state"], d.nx, d.ny, d.dx, d.dy, halo,
-                                    JUDGE_BLOCK, stride=stride)
-            m.set_judge_region(mk, JUDGE_BLOCK)
-            self.masks.append(mk)
+        self.E = fps.Ensemble(scenarios)
+        self.J = fps.Ensemble([_flood_only(sc) for sc in scenarios])
         self.us = [tuple(torch.empty_like(a) for a in _state(m)) for m in self.E.members]
+        self.u0 = [tuple(torch.empty_like(a) for a in _state(m)) for m in self.E.members]
         self.x = torch.empty((chunk, d.ny, d.nx, 16), dtype=torch.bfloat16, device="cuda")
         self.y = torch.empty((chunk, d.ny, d.nx, 4), dtype=torch.float32, device="cuda")
-        self.jout = torch.empty((len(cases), 2), dtype=torch.int32, device="cuda")
-        self.t = [0.0] * len(cases)
-        self.stats = {"blocks": 0, "accepted": 0, "fallback": 0, "judged_fraction": self.judged_fraction()}
+        self.jout = torch.empty((self.S, 3), dtype=torch.int32, device="cuda")
+        nb = ((d.ny + JUDGE_BLOCK - 1) // JUDGE_BLOCK, (d.nx + JUDGE_BLOCK - 1) // JUDGE_BLOCK)
+        self.masks = [torch.empty(nb, dtype=torch.uint8, device="cuda") for _ in range(self.S)]
+        self.occ = [None] * self.S
+        self.stats = {"blocks": 0, "accepted": 0, "fallback": 0, "cfl_fallback": 0, "judged_people": 0,
+                      "judged_cells": 0.0}
 
-    def judged_fraction(self):
-        m = self.torch.stack([mk.float().mean() for mk in self.masks])
-        return float(m.mean())
+    def _pick(self, k):
+        a = _agents_of(self.E[k])
+        return dict(stride=self.stride, select=self.u0[k], h_dry=self.d.h_dry, hr_margin=self.hr_margin,
+                    h_margin=self.h_margin), a
 
     def block(self):
-        """Advance every case by K fixed steps; returns the accept flags."""
-        S = len(self.cases)
-        E, J = self.E.members, self.J.members
-        # 1. the network's proposal for every case, in chunks
+        """Advance every scenario by K steps; returns the accept flags."""
+        d, S, E, J = self.d, self.S, self.E.members, self.J.members
         span = K_STEPS * self.dt
+        times = [m.time() for m in E]
+        cfl_ok = np.array([dtn >= self.dt for _, dtn in times])
+        # 1. the network's proposal for every scenario, in chunks, from the
+        #    block start state and the evacuee counts of the block start
+        for k in range(S):
+            fps.sur_copy_state(_state(E[k]), self.u0[k])
+            self.occ[k] = E[k].counts()
         for c0 in range(0, S, self.chunk):
             cnt = min(self.chunk, S - c0)
             for k in range(c0, c0 + cnt):
                 m = E[k]
-                fps.sur_pack(m.h, m.qx, m.qy, m.z, self.crowds[k].occ,
-                             inflow=m.inflow_feature(self.t[k], self.t[k] + span), out=self.x[k - c0])
+                fps.sur_pack(m.h, m.qx, m.qy, m.z, self.occ[k],
+                             inflow=m.inflow_feature(times[k][0], times[k][0] + span), out=self.x[k - c0])
             self.sur.forward(self.x[:cnt], self.y[:cnt])
             for k in range(c0, c0 + cnt):
-                fps.sur_copy_state(_state(E[k]), self.us[k])
-                fps.sur_apply(self.y[k - c0], *self.us[k], h_dry=self.d.h_dry, h_snap=H_SNAP)
-        # 2. the finite-volume judge on the judge regions
+                fps.sur_copy_state(self.u0[k], self.us[k])
+                fps.sur_apply(self.y[k - c0], *self.us[k], h_dry=d.h_dry, h_snap=H_SNAP)
+        # 2. the finite-volume judge on the judge regions of the judged people
         for k in range(S):
-            fps.sur_copy_state(_state(E[k]), _state(J[k]))
+            pick, a = self._pick(k)
+            fps.sur_judge_mask(a["x"], a["y"], a["state"], d.nx, d.ny, d.dx, d.dy, self.halo, JUDGE_BLOCK,
+                               out=self.masks[k], **pick)
+            J[k].set_judge_region(self.masks[k], JUDGE_BLOCK)
+            fps.sur_copy_state(self.u0[k], _state(J[k]))
             J[k].rebind_fields()
+            J[k].set_time(times[k][0], 0)
+            J[k].set_occupancy(self.occ[k])
         self.J.step(K_STEPS)
         for k in range(S):
-            cr = self.crowds[k].t
-            fps.sur_judge(cr["x"], cr["y"], cr["state"], self.d.nx, self.d.ny, self.d.dx, self.d.dy,
-                          self.us[k], _state(J[k]), tol=self.tol, h_dry=self.d.h_dry, stride=self.stride,
-                          out=self.jout[k])
-        bad = self.jout[:, 0].cpu().numpy()
-        accept = bad == 0
-        # 3. commit the accepted proposals, fall back to the finite-volume
-        #    update for the others
-        t_acc = [self._acc_time(t) for t in self.t]
+            pick, a = self._pick(k)
+            fps.sur_judge(a["x"], a["y"], a["state"], d.nx, d.ny, d.dx, d.dy, self.us[k], _state(J[k]),
+                          tol=self.tol, out=self.jout[k], **pick)
+        res = self.jout.cpu().numpy()
+        accept = (res[:, 0] == 0) & cfl_ok
+        # 3. accepted: the proposal, and the people walk on it; rejected: the
+        #    coupled finite-volume steps
         for k in np.flatnonzero(accept):
             fps.sur_copy_state(self.us[k], _state(E[k]))
             E[k].rebind_fields()
-            E[k].set_time(t_acc[k], 0)
-        rejected = np.flatnonzero(~accept)
-        if len(rejected):
-            for k in np.flatnonzero(accept):
-                E[k].set_end_time(t_acc[k])                    # inactive while the others catch up
-            for k in rejected:
-                E[k].set_end_time(self.t[k] + (K_STEPS - 0.5) * self.dt)
-            self.E.step(K_STEPS)
-            while self.E.active() > 0:                         # a CFL-limited step made a block longer
-                self.E.step(1)
-            for k in range(S):
-                E[k].set_end_time(0.0)
-        for k in range(S):
-            self.t[k] = t_acc[k] if accept[k] else E[k].diag()["t"]
-            J[k].set_time(self.t[k], 0)
+            E[k].set_flood_frozen(1)
+        self.E.step(K_STEPS)
+        for k in np.flatnonzero(accept):
+            E[k].set_flood_frozen(0)
         self.stats["blocks"] += 1
         self.stats["accepted"] += int(accept.sum())
         self.stats["fallback"] += int((~accept).sum())
+        self.stats["cfl_fallback"] += int((~cfl_ok).sum())
+        self.stats["judged_people"] += int(res[:, 2].sum())
+        self.stats["judged_cells"] += float(self.torch.stack([mk.float().mean() for mk in self.masks]).mean())
         return accept
 
-    def _acc_time(self, t):
-        """The time the engine reaches after K fixed steps from t (the same
-        FP64 sums of the FP32 step)."""
-        for _ in range(K_STEPS):
-            t += self.dt
-        return t
+    def close(self):
+        self.E.close()
+        self.J.close()
+        self.sur.close()
+
+
+def _agents_of(m):
+    """The device agent arrays of a member (empty ones when it has no agents)."""
+    import torch
+    if getattr(m, "agents_t", None) is None:
+        z = torch.zeros(0, device=m.device)
+        m.agents_t = {"x": z, "y": z, "state": torch.zeros(0, dtype=torch.uint8, device=m.device)}
+    return m.agents_t
+
+
+def bar_check(plain, assisted: AssistedEnsemble, tol: float = 0.01):
+    """Every person of the plain finite-volume ensemble (its own positions)
+    against the assisted ensemble's flood: (people whose depth differs by
+    more than tol or whose hazard class differs, largest depth difference)."""
+    d = assisted.d
+    bad, worst = 0, 0.0
+    for k in range(assisted.S):
+        a = _agents_of(plain[k])
+        r = fps.judge_result(fps.sur_judge(a["x"], a["y"], a["state"], d.nx, d.ny, d.dx, d.dy,
+                                           _state(assisted.E[k]), _state(plain[k]), tol=tol, stride=1))
+        bad += r[0]
+        worst = max(worst, r[1])
+    return bad, worst
 
 
 def timed(fn, *a, **kw):

@@ -199,3 +199,23 @@ def test_hll_switch_changes_only_the_tangential_flux():
         assert np.array_equal(x, y)
     with pytest.raises(fps.FpsError):
         hll.set_flux(7)
+
+
+def test_vanishing_velocities_stay_finite(oracle):
+    """Still water carrying discharges from 1e-40 to 1e-6 m^2/s (velocities
+    down to the FP32 subnormal range): the friction of the update must leave
+    every cell finite and match the oracle (a subnormal squared speed once
+    gave an infinite reciprocal square root and a NaN discharge)."""
+    n = 150
+    rng = I.rng_of(77)
+    h = np.full((n, n), 0.02)
+    mag = 10.0 ** rng.uniform(-40.0, -6.0, (n, n))
+    qx = mag * rng.choice([-1.0, 1.0], (n, n))
+    qy = np.where(rng.random((n, n)) < 0.5, 0.0, -qx)
+    d = I.GridDesc(nx=n, ny=n, dx=0.25, dy=0.25, n_base=0.03)
+    sc = I.Scenario(desc=d, h=h, qx=qx.astype(np.float32).astype(np.float64),
+                    qy=qy.astype(np.float32).astype(np.float64), z=np.zeros((n, n)), name="vanishing")
+    sim = fps.Sim(sc)
+    check_window(oracle, sim, sc, 50, "vanishing velocities 150^2")
+    h1, qx1, qy1, _ = sim.fields()
+    assert np.isfinite(h1).all() and np.isfinite(qx1).all() and np.isfinite(qy1).all()

@@ -134,19 +134,20 @@ def test_surrogate_forward_sampled_pixels_at_training_size():
 
 
 def test_learned_update_full_size_fallback_and_judge():
-    cases = [SG.flood_case(500000 + k, n=2048, n_evac=50000, barrier_height=0.3 + 0.2 * k) for k in range(3)]
+    scs = SG.coupled_cases(3, n=2048, n_evac=50000)
     params = torch.tensor(SG.init_params(1)).cuda()
-    A = SG.AssistedEnsemble(cases, params, chunk=1, stride=250, tol=-1.0)   # every block rejected
-    plain, _ = SG._flood_ensemble(cases)
+    A = SG.AssistedEnsemble(scs, params, chunk=1, stride=250, tol=-1.0)   # every block rejected
+    plain = fps.Ensemble(scs)
     for _ in range(2):
         assert not A.block().any()
-    plain.step(2 * SG.K_STEPS)
-    for k in range(len(cases)):
+        plain.step(SG.K_STEPS)
+    for k in range(len(scs)):
         for a, b in zip(SG._state(A.E[k]), SG._state(plain[k])):
             assert torch.equal(a, b), k
+    assert SG.bar_check(plain, A) == (0, 0.0)
     # the judge at full size against the oracle judge on host copies
-    d = cases[0].sc.desc
-    cr = A.crowds[0].t
+    d = scs[0].desc
+    cr = A.E[0].agents_t
     us = tuple(t.clone() for t in SG._state(A.E[0]))
     us[0].add_(torch.where(us[0] > 0, 0.004, 0.0) * (torch.rand_like(us[0]) < 0.3))
     out = fps.judge_result(fps.sur_judge(cr["x"], cr["y"], cr["state"], d.nx, d.ny, d.dx, d.dy, us,

@@ -241,19 +241,29 @@ def test_judge_matches_oracle():
     st = rng.integers(0, 3, na).astype(np.uint8)
     dv = lambda arr: torch.tensor(arr).cuda()
     for stride in (1, 3):
-        want = S.judge(x[::stride], y[::stride], st[::stride], nx, ny, dx, dy, a, b, 0.01, 1e-5,
-                       (0.75, 1.5, 2.5))
+        want = S.judge(x, y, st, nx, ny, dx, dy, a, b, 0.01, 1e-5, (0.75, 1.5, 2.5), stride=stride)
         out = fps.sur_judge(dv(x), dv(y), dv(st), nx, ny, dx, dy, tuple(map(dv, a)), tuple(map(dv, b)),
                             stride=stride)
         got = fps.judge_result(out)
         say(f"judge stride {stride}: {got} oracle {want}")
-        assert got[0] == want[0] and got[1] == want[1] and want[0] > 0
-    # no agents -> (0, 0); identical states -> (0, 0)
+        assert got == want and want[0] > 0
+    # the sample plus the people near a class boundary of a selection state
+    sel = _planes(np.random.default_rng(14), ny, nx)
+    for stride, hrm, hm in ((50, 0.1, 0.01), (1000000, 0.05, 0.0), (7, 0.0, 0.02)):
+        want = S.judge(x, y, st, nx, ny, dx, dy, a, b, 0.01, 1e-5, (0.75, 1.5, 2.5), stride=stride, select=sel,
+                       hr_margin=hrm, h_margin=hm)
+        out = fps.sur_judge(dv(x), dv(y), dv(st), nx, ny, dx, dy, tuple(map(dv, a)), tuple(map(dv, b)),
+                            stride=stride, select=tuple(map(dv, sel)), hr_margin=hrm, h_margin=hm)
+        got = fps.judge_result(out)
+        plain = S.judge(x, y, st, nx, ny, dx, dy, a, b, 0.01, 1e-5, (0.75, 1.5, 2.5), stride=stride)
+        say(f"judge stride {stride} + margins {hrm}, {hm}: {got} oracle {want} (sample alone: {plain[2]} judged)")
+        assert got == want and want[2] > plain[2]
+    # no agents -> (0, 0, 0); identical states -> nothing off
     out0 = fps.sur_judge(dv(x[:0]), dv(y[:0]), dv(st[:0]), nx, ny, dx, dy, tuple(map(dv, a)),
                          tuple(map(dv, b)))
-    assert fps.judge_result(out0) == (0, 0.0)
+    assert fps.judge_result(out0) == (0, 0.0, 0)
     same = fps.sur_judge(dv(x), dv(y), dv(st), nx, ny, dx, dy, tuple(map(dv, b)), tuple(map(dv, b)))
-    assert fps.judge_result(same) == (0, 0.0)
+    assert fps.judge_result(same)[:2] == (0, 0.0)
 
 
 def _cells(x, y, nx, ny, dx, dy):
@@ -286,6 +296,26 @@ def test_occupancy_and_judge_mask():
         wm[max(j[a] - halo, 0) // block:min(j[a] + halo, ny - 1) // block + 1,
            max(i[a] - halo, 0) // block:min(i[a] + halo, nx - 1) // block + 1] = 1
     assert np.array_equal(m, wm)
+    # with a selection state: the region also covers the people near a class boundary
+    # (a sparse sample, so that the extra people add blocks)
+    stride = 1500
+    m = fps.sur_judge_mask(dv(x), dv(y), dv(st), nx, ny, dx, dy, halo, block, stride=stride).cpu().numpy()
+    sel = _planes(rng, ny, nx)
+    m2 = fps.sur_judge_mask(dv(x), dv(y), dv(st), nx, ny, dx, dy, halo, block, stride=stride,
+                            select=tuple(map(dv, sel)), hr_margin=0.1, h_margin=0.01).cpu().numpy()
+    hs, qxs, qys = (p[j, i] for p in sel)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        hr = ((np.maximum(np.abs(qxs / hs), np.abs(qys / hs)).astype(np.float32) + np.float32(0.5)) * hs)
+    near = ~(hs > np.float32(1e-5) + np.float32(0.01))
+    for t in (0.75, 1.5, 2.5):
+        near |= np.abs(hr.astype(np.float32) - np.float32(t)) < np.float32(0.1)
+    wm2 = np.zeros_like(wm)
+    for a in range(na):
+        if st[a] == 1 or not (a % stride == 0 or near[a]):
+            continue
+        wm2[max(j[a] - halo, 0) // block:min(j[a] + halo, ny - 1) // block + 1,
+            max(i[a] - halo, 0) // block:min(i[a] + halo, nx - 1) // block + 1] = 1
+    assert np.array_equal(m2, wm2) and m2.sum() > m.sum()
 
 
 def test_judge_region_is_exact_inside():

@@ -1,7 +1,13 @@
-"""GPU checks of the surrogate workflow: the finite-volume fallback of the
-assisted ensemble reproduces the plain finite-volume ensemble bit for bit,
-an accepted block is exactly the network's update, and training on pairs
-that the finite-volume engine generates lowers the loss."""
+"""GPU checks of the surrogate workflow on coupled scenarios (people walking
+in both arms): the finite-volume fallback of the assisted ensemble reproduces
+the plain coupled ensemble bit for bit, flood and people; an accepted block
+is exactly the network's update, with the people walking on it as a held
+flood lets them; training on pairs that the finite-volume engine generates
+lowers the loss; and the assisted ensemble against the plain finite-volume
+ensemble at the same accuracy bar, with its throughput ratio reported
+whatever it is."""
+import time
+
 import numpy as np
 import pytest
 import torch
@@ -16,6 +22,10 @@ def _cases(seeds, n=64, **kw):
     return [SG.flood_case(s, n=n, **kw) for s in seeds]
 
 
+def _coupled(S, n=128, people=400):
+    return [SG.coupled_case(k, n=n, n_evac=people, master=77) for k in range(S)]
+
+
 def _random_surrogate(batch, n, seed=0):
     sur = fps.Surrogate(batch, n, n)
     g = torch.Generator().manual_seed(seed)
@@ -24,42 +34,76 @@ def _random_surrogate(batch, n, seed=0):
     return sur
 
 
+def _agents_equal(a, b):
+    A, B = a.agents(), b.agents()
+    return all(np.array_equal(A[k], B[k]) for k in A)
+
+
 def test_fallback_equals_plain_fv():
-    cases = _cases([31, 32, 33])
-    sur = _random_surrogate(2, 64)
-    A = SG.AssistedEnsemble(cases, sur.get_params(), chunk=2, tol=-1.0)      # every block rejected
-    plain, _ = SG._flood_ensemble(cases)
+    scs = _coupled(3)
+    sur = _random_surrogate(2, 128)
+    A = SG.AssistedEnsemble(scs, sur.get_params(), chunk=2, tol=-1.0)      # every block rejected
+    plain = fps.Ensemble(scs)
     for _ in range(3):
         acc = A.block()
         assert not acc.any()
-    plain.step(3 * SG.K_STEPS)
-    for k in range(len(cases)):
+        plain.step(SG.K_STEPS)
+    for k in range(len(scs)):
         for a, b in zip(A.E[k].fields(), plain[k].fields()):
             assert np.array_equal(a, b), k
-        assert A.E[k].diag()["t"] == plain[k].diag()["t"] == A.t[k]
+        assert _agents_equal(A.E[k], plain[k]), k
+        assert A.E[k].time()[0] == plain[k].time()[0]
+    bad, worst = SG.bar_check(plain, A)
+    assert bad == 0 and worst == 0.0
     say(f"fallback: {A.stats}")
 
 
 def test_accepted_block_is_the_network_update():
-    cases = _cases([41, 42], n=64)
-    for c in cases:                                  # no crowd: nothing to judge, every block accepted
-        c.agents = {k: v[:0] for k, v in c.agents.items()}
-    sur = _random_surrogate(2, 64, seed=3)
-    A = SG.AssistedEnsemble(cases, sur.get_params(), chunk=2)
+    scs = _coupled(2, people=0)                       # no one to judge: every block accepted
+    sur = _random_surrogate(2, 128, seed=3)
+    A = SG.AssistedEnsemble(scs, sur.get_params(), chunk=2)
     u0 = [tuple(t.clone() for t in SG._state(A.E[k])) for k in range(2)]
-    feats = [A.E[k].inflow_feature(0.0, SG.K_STEPS * A.dt) for k in range(2)]
-    assert all(f[3] > 0 for f in feats)
+    t0 = [A.E[k].time()[0] for k in range(2)]
+    feats = [A.E[k].inflow_feature(t0[k], t0[k] + SG.K_STEPS * A.dt) for k in range(2)]
     acc = A.block()
     assert acc.all()
     for k in range(2):
-        x = torch.empty((1, 64, 64, 16), dtype=torch.bfloat16, device="cuda")
-        y = torch.empty((1, 64, 64, 4), dtype=torch.float32, device="cuda")
-        fps.sur_pack(*u0[k], A.E[k].z, A.crowds[k].occ, inflow=feats[k], out=x[0])
+        x = torch.empty((1, 128, 128, 16), dtype=torch.bfloat16, device="cuda")
+        y = torch.empty((1, 128, 128, 4), dtype=torch.float32, device="cuda")
+        occ = torch.zeros((128, 128), dtype=torch.int32, device="cuda")
+        fps.sur_pack(*u0[k], A.E[k].z, occ, inflow=feats[k], out=x[0])
         sur.forward(x, y)
-        fps.sur_apply(y[0], *u0[k], h_dry=cases[k].sc.desc.h_dry, h_snap=SG.H_SNAP)
+        fps.sur_apply(y[0], *u0[k], h_dry=scs[k].desc.h_dry, h_snap=SG.H_SNAP)
         for a, b in zip(SG._state(A.E[k]), u0[k]):
             assert torch.equal(a, b)
-        assert A.E[k].diag()["t"] == A.t[k] == A._acc_time(0.0)
+        t = t0[k]
+        for _ in range(SG.K_STEPS):
+            t += A.dt
+        assert A.E[k].time()[0] == t
+
+
+def test_held_flood_moves_only_the_people():
+    """fps_set_flood_frozen: K held steps of dt_max leave the flood state
+    untouched bit for bit while the people walk; resuming gives the CFL step
+    of the state again."""
+    sc = SG.coupled_case(5, n=128, n_evac=600, master=77)
+    a, b = fps.Sim(sc), fps.Sim(sc)
+    a.step(30)
+    b.step(30)
+    f0 = [t.clone() for t in SG._state(a)]
+    a.set_flood_frozen(1)
+    t0, _ = a.time()
+    a.step(SG.K_STEPS)
+    t1, dt1 = a.time()
+    assert all(torch.equal(x, y) for x, y in zip(SG._state(a), f0))
+    assert dt1 == np.float32(sc.desc.dt_max)
+    A0, A1 = b.agents(), a.agents()
+    moved = np.abs(A1["x"] - A0["x"]) + np.abs(A1["y"] - A0["y"])
+    assert moved.max() > 0.0
+    a.set_flood_frozen(0)
+    d = a.diag()
+    assert d["dt_next"] <= sc.desc.dt_max and d["t"] == t1
+    say(f"held flood: {SG.K_STEPS} steps, t {t0:.3f} -> {t1:.3f}, people moved up to {moved.max():.3f} m")
 
 
 def test_pairs_and_training():
@@ -79,22 +123,53 @@ def test_pairs_and_training():
     assert hist[-1][1] < 0.5 * hist[0][1]
 
 
-def test_trained_network_beats_no_update_on_held_out_pairs():
-    """What the learned part gains over the method without it: trained on
-    finite-volume pairs of 32 random layouts, the network's depth error on
-    pairs of 8 unseen layouts is well below that of keeping the state (the
-    update a block would make without the network)."""
+def test_assisted_against_plain_fv_at_equal_accuracy():
+    """What the trained network gains over the method without it, measured
+    against the plain coupled finite-volume ensemble: a network trained on
+    finite-volume pairs of 32 random layouts advances 4 unseen coupled
+    scenarios (every person judged, plus the margins) in lockstep with the
+    plain arm; the bar (1 cm and the same class at every person after every
+    block) is checked, and the wall-clock ratio of the two arms is reported
+    as it is, below 1 included."""
     n = 128
     train_cases = [SG.flood_case(7000 + k, n=n, barrier_height=0.5 if k % 2 else None) for k in range(32)]
-    ds = SG.Dataset(32 * 4, n)
-    SG.generate_pairs(train_cases, ds, warmup=60, pairs=4, every=24)
+    ds = SG.Dataset(32 * 8, n)
+    SG.generate_pairs(train_cases, ds, warmup=60, pairs=8, every=24)
     sur = fps.Surrogate(8, n, n)
     sur.set_params(torch.tensor(SG.init_params(0)).cuda())
     hist = SG.train(sur, ds, steps=600, batch=8, lr=1e-3, log_every=100)
-    held = [SG.flood_case(8000 + k, n=n) for k in range(8)]
-    kept = []
-    SG.generate_pairs(held, SG.Dataset(16, n), warmup=90, pairs=2, every=40, keep=kept)
-    ev = SG.evaluate(sur, held, kept)
-    say(f"loss {hist[0][1]:.4f} -> {hist[-1][1]:.4f}; held-out {ev}")
-    assert ev["sur_rmse_h"] < 0.5 * ev["persist_rmse_h"]
-    assert ev["sur_bad_people"] < ev["persist_bad_people"]
+    params = sur.get_params()
+    scs = _coupled(4, n=n, people=500)
+    blocks = 4
+    A, P = SG.AssistedEnsemble(scs, params, chunk=4, stride=1), fps.Ensemble(scs)
+    worst_bad, worst_dh = 0, 0.0
+    for _ in range(blocks):
+        A.block()
+        P.step(SG.K_STEPS)
+        bad, dh = SG.bar_check(P, A)
+        worst_bad, worst_dh = max(worst_bad, bad), max(worst_dh, dh)
+    stats = dict(A.stats)
+    A.close()
+    P.close()
+    # wall clock of each arm alone over the same blocks
+    P = fps.Ensemble(scs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(blocks):
+        P.step(SG.K_STEPS)
+    torch.cuda.synchronize()
+    t_fv = time.perf_counter() - t0
+    A = SG.AssistedEnsemble(scs, params, chunk=4, stride=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(blocks):
+        A.block()
+    torch.cuda.synchronize()
+    t_as = time.perf_counter() - t0
+    say(f"loss {hist[0][1]:.4f} -> {hist[-1][1]:.4f}; assisted {stats}; most people off at a check "
+        f"{worst_bad} (max |dh| {worst_dh:.4f} m), meets the bar: {worst_bad == 0}; "
+        f"assisted / plain FV throughput = {t_fv / t_as:.3f}")
+    # every person is judged each block (stride 1)
+    assert stats["judged_people"] >= blocks * 4 * 500 * 0.9
+    assert stats["accepted"] + stats["fallback"] == blocks * 4
+    assert t_fv > 0 and t_as > 0

@@ -89,14 +89,24 @@ def test_agent_sample_calls_reject_null_arrays_without_touching_the_device():
     thr = (C.c_double * 3)(0.75, 1.5, 2.5)
     flood = [buf] * 6
     # judge: NULL agent or flood arrays are rejected when there are agents to sample
-    assert L.fps_sur_judge(4, 1, None, buf, buf, 8, 8, 1.0, 1.0, *flood, 0.05, 1e-5, thr, buf,
+    nosel = (None, None, None, 0.0, 0.0)
+    assert L.fps_sur_judge(4, 1, None, buf, buf, 8, 8, 1.0, 1.0, *flood, 0.05, 1e-5, thr, *nosel, buf,
                            None) == fps.FPS_E_INVALID
-    assert L.fps_sur_judge(4, 1, buf, buf, buf, 8, 8, 1.0, 1.0, buf, None, *flood[2:], 0.05, 1e-5, thr, buf,
+    assert L.fps_sur_judge(4, 1, buf, buf, buf, 8, 8, 1.0, 1.0, buf, None, *flood[2:], 0.05, 1e-5, thr, *nosel,
+                           buf, None) == fps.FPS_E_INVALID
+    assert L.fps_sur_judge(4, 0, buf, buf, buf, 8, 8, 1.0, 1.0, *flood, 0.05, 1e-5, thr, *nosel, buf,
                            None) == fps.FPS_E_INVALID
-    assert L.fps_sur_judge(4, 0, buf, buf, buf, 8, 8, 1.0, 1.0, *flood, 0.05, 1e-5, thr, buf,
-                           None) == fps.FPS_E_INVALID
-    assert L.fps_sur_judge_mask(4, 1, buf, buf, None, 8, 8, 1.0, 1.0, 1, 4, buf, None) == fps.FPS_E_INVALID
-    assert L.fps_sur_judge_mask(4, 1, buf, buf, buf, 8, 8, 1.0, 1.0, 1, 0, buf, None) == fps.FPS_E_INVALID
+    # a selection state with a missing plane, or a negative margin
+    assert L.fps_sur_judge(4, 1, buf, buf, buf, 8, 8, 1.0, 1.0, *flood, 0.05, 1e-5, thr, buf, None, buf, 0.1,
+                           0.01, buf, None) == fps.FPS_E_INVALID
+    assert L.fps_sur_judge(4, 1, buf, buf, buf, 8, 8, 1.0, 1.0, *flood, 0.05, 1e-5, thr, buf, buf, buf, -0.1,
+                           0.01, buf, None) == fps.FPS_E_INVALID
+    assert L.fps_sur_judge_mask(4, 1, buf, buf, None, 8, 8, 1.0, 1.0, None, None, None, 1e-5, None, 0.0, 0.0,
+                                1, 4, buf, None) == fps.FPS_E_INVALID
+    assert L.fps_sur_judge_mask(4, 1, buf, buf, buf, 8, 8, 1.0, 1.0, None, None, None, 1e-5, None, 0.0, 0.0,
+                                1, 0, buf, None) == fps.FPS_E_INVALID
+    assert L.fps_sur_judge_mask(4, 1, buf, buf, buf, 8, 8, 1.0, 1.0, buf, buf, buf, 1e-5, None, 0.1, 0.0,
+                                1, 4, buf, None) == fps.FPS_E_INVALID
     assert L.fps_sur_occupancy(4, buf, buf, None, buf, 8, 8, 1.0, 1.0, buf, None) == fps.FPS_E_INVALID
     assert L.fps_sur_occupancy(-1, buf, buf, buf, buf, 8, 8, 1.0, 1.0, buf, None) == fps.FPS_E_INVALID
     assert b"fps_sur_occupancy" in L.fps_sur_last_error(None)

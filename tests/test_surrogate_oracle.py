@@ -118,12 +118,33 @@ def test_judge_counts_by_hand():
     x = np.array([1.0, 5.0, 7.9, 5.5, -3.0, 100.0], np.float32)
     y = np.array([1.0, 3.0, 5.0, 3.5, 1.0, 100.0], np.float32)
     st = np.array([0, 0, 0, 1, 0, 0], np.uint8)
-    n, dmax = S.judge(x, y, st, nx, ny, dx, dy, (ha, qa, qb), (hb, qb, qb), 0.01, 1e-5, thr)
+    n, dmax, judged = S.judge(x, y, st, nx, ny, dx, dy, (ha, qa, qb), (hb, qb, qb), 0.01, 1e-5, thr)
     # bad: agent 1 (cell (2,1)), agent 2 (cell (3,2)), agent 5 (clamped to (3,2))
-    assert n == 3
+    assert n == 3 and judged == 5
     assert dmax == np.float32(0.52) - np.float32(0.5)
     same = S.judge(x, y, st, nx, ny, dx, dy, (hb, qb, qb), (hb, qb, qb), 0.01, 1e-5, thr)
-    assert same == (0, 0.0)
+    assert same == (0, 0.0, 5)
+    # every third agent: agent 0 (fine) and agent 3 (exited)
+    assert S.judge(x, y, st, nx, ny, dx, dy, (ha, qa, qb), (hb, qb, qb), 0.01, 1e-5, thr, stride=3) == (
+        0, float(np.float32(0.505) - np.float32(0.5)), 1)
+    # the sample (agent 0) plus the people near a class boundary of a selection
+    # state: cell (2,1) at HR 0.5 x 1.45 = 0.725, 0.025 below the first
+    # threshold; cell (3,2) dry
+    hs = np.full((ny, nx), 0.5, np.float32)
+    hs[1, 2] = 1.45
+    hs[2, 3] = 0.0
+    sel = (hs, qb, qb)
+    r = S.judge(x, y, st, nx, ny, dx, dy, (ha, qa, qb), (hb, qb, qb), 0.01, 1e-5, thr, stride=1000, select=sel,
+                hr_margin=0.05)
+    assert r[0] == 3 and r[2] == 4            # agents 0, 1, 2, 5 judged; 1, 2, 5 off
+    r = S.judge(x, y, st, nx, ny, dx, dy, (ha, qa, qb), (hb, qb, qb), 0.01, 1e-5, thr, stride=1000, select=sel,
+                hr_margin=0.02)
+    assert r[0] == 2 and r[2] == 3            # 0.025 away is outside a 0.02 margin: agent 1 not judged
+    # a depth margin makes the 0.5 m cells "near dry" as well (agents 0, 4 and, dry,
+    # 2 and 5), but not the 1.45 m cell of agent 1
+    r = S.judge(x, y, st, nx, ny, dx, dy, (ha, qa, qb), (hb, qb, qb), 0.01, 1e-5, thr, stride=1000, select=sel,
+                h_margin=0.6)
+    assert r[0] == 2 and r[2] == 4
 
 
 def test_bf16_round_ties_to_even_and_matches_library():
