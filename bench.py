@@ -349,6 +349,9 @@ def headline_section(args, stream):
     ens.set_flux(fps.FPS_FLUX_HLL)
     fv_ms_hll = ens.time_flood(args.flood_reps)
     ens.set_flux(fps.FPS_FLUX_HLLC)
+    ens.set_order(2)
+    fv_ms_o2 = ens.time_flood(args.flood_reps)
+    ens.set_order(1)
     wet = sum(float((m.h > 1e-5).float().mean()) for m in ens.members) / len(ens.members)
     out = {
         "cells": cells, "agents": agents, "rows": rows, "ms": ms, "fv_ms": fv_ms,
@@ -364,6 +367,7 @@ def headline_section(args, stream):
             "scenario_steps_per_s": len(ens.members) * args.steps / (ms * 1e-3),
             "flood_update_ms_per_launch": fv_ms,
             "flood_update_ms_per_launch_hll_flux": fv_ms_hll,
+            "flood_update_ms_per_step_second_order": fv_ms_o2,
             "kernel_ms_per_launch_in_step": {"flood_update": kms[0], "ped_step": kms[1], "end_of_step": kms[2],
                                              "bin_place": kms[3], "bin_sort": kms[4]}},
     }
@@ -423,6 +427,9 @@ def probe_section(args, stream):
     bms = bsim.time_flood(args.probe_steps)
     bsim.set_flux(fps.FPS_FLUX_HLL)
     bms_hll = bsim.time_flood(args.probe_steps)
+    bsim.set_flux(fps.FPS_FLUX_HLLC)
+    bsim.set_order(2)
+    bms_o2 = bsim.time_flood(args.probe_steps)
     bcells = args.probe_n * args.probe_n
     bach = FV_BYTES_PER_CELL * bcells / (bms * 1e-3) / 1e9
     probe = {"workload": f"wet_probe_{args.probe_n} (fully wet dam break, {bcells} cells)",
@@ -430,6 +437,7 @@ def probe_section(args, stream):
              "ms_per_launch": bms, "cell_updates_per_s": bcells / (bms * 1e-3),
              "achieved_GBs": bach, "frac": bach / HBM_PEAK_GBS,
              "hll_flux_ms_per_launch": bms_hll,
+             "second_order_ms_per_step": bms_o2,
              "working_set_MB": (FV_BYTES_PER_CELL + 12) * bcells / 1e6}
     bsim.close()
     del bsim
