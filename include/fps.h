@@ -61,7 +61,9 @@ enum {
     FPS_ST_TO_STORAGE = 2,  /* responder walking to the sandbag storage */
     FPS_ST_PICKING = 3,     /* responder picking up a bag (timer running) */
     FPS_ST_TO_BARRIER = 4,  /* responder carrying a bag to the barrier */
-    FPS_ST_DROPPING = 5     /* responder dropping the bag (timer running) */
+    FPS_ST_DROPPING = 5,    /* responder dropping the bag (timer running) */
+    FPS_ST_SHOPPING = 6,    /* before the flood: walking to the door it will leave by (fps_set_doors) */
+    FPS_ST_OUTSIDE = 7      /* outside the building: a free slot a new pedestrian may enter by (fps_set_doors) */
 };
 enum { FPS_CLS_DRY = 0, FPS_CLS_LOW = 1, FPS_CLS_MEDIUM = 2, FPS_CLS_HIGH = 3, FPS_CLS_HIGHEST = 4 };
 
@@ -102,12 +104,15 @@ typedef struct {
     int32_t any_wet;         /* some cell has h > h_dry */
     int32_t n_agents;
     int32_t class_count[5];  /* non-exited agents per hazard class */
-    int32_t state_count[6];  /* agents per state */
+    int32_t state_count[8];  /* agents per state */
     int32_t barrier_layers_done, barrier_active_cell, barrier_bags, barrier_done;
     int32_t drops_total;     /* sandbags delivered */
     int32_t status;          /* FPS_OK or the latched fault */
     int32_t active;          /* 0 once the end time (fps_set_end_time) is reached */
     int32_t flood_steps;     /* steps whose flood update ran; the others were dry and skipped */
+    int32_t doors_closed;    /* the pre-flood door flow has stopped (fps_set_doors) */
+    int64_t door_entries;    /* pedestrians that entered by a door */
+    int64_t door_leaves;     /* pedestrians that left by a door before the flood */
 } fps_diag;
 
 typedef struct fps_sim fps_sim;
@@ -166,6 +171,35 @@ int fps_bind_agents(fps_sim* sim, int32_t n, float* x, float* y, float* vx, floa
 int fps_set_barrier(fps_sim* sim, const int32_t* cells, int32_t ncells, int32_t storage_dest,
                     int32_t barrier_dest, int32_t n_layers, float layer_thickness,
                     float last_thickness, int32_t bags_per);
+
+/* Pre-flood pedestrian flow (sec. 3 and sec. 3.2: people enter and leave the
+   open area by n_doors entrance doors, each with probability 1/n_doors, at a
+   constant rate per door, and no one enters once the flood has reached the
+   site).  Agents in state FPS_ST_OUTSIDE are free slots; each step, every
+   free slot draws a door with probability 1/n_doors, and at each door the
+   first per_step slots (in slot order) that drew it enter: placed at a
+   uniform point in the central half of the door's cell, standing, state
+   FPS_ST_SHOPPING, heading for a leaving door drawn uniformly from the other
+   doors (so each door is the leaving door with probability 1/n_doors).  A
+   walker that reaches its leaving door (within the arrival radius) goes back
+   to FPS_ST_OUTSIDE and its slot may enter again.  On the first step after
+   whose flood update some cell is wet, the doors close for good: no more
+   entries, and every walker inside becomes an evacuee heading for the
+   nearest exit (the doors are not exits).  The draws come from SplitMix64
+   (Steele, Lea & Flood 2014) seeded with seed: draw k of slot a in step n is
+   output ((n << 26) | (a << 2) | k) + 1 of the generator; a door index is
+   ((u >> 32) * m) >> 32 for m choices and an offset in the cell 0.25 + 0.5 *
+   (u >> 40) / 2^24.  Both the per-door rate and the slot count (the
+   agents bound, 1000 in the paper) bound the population inside.  The
+   walkers do not add roughness (only evacuees do, sec. 2.4).
+   cells: host int32 [n_doors], the door cells (j * nx + i, walkable);
+   dests: host int32 [n_doors], the distance field of each door, in
+   [n_exit, n_dest) of the navigation map; copied.  n_doors in [2, 16],
+   per_step >= 0.  n_doors = 0 switches the flow off.  Needs the navigation
+   map; at most 2^24 agents.  Opens the doors (a previous closing is
+   forgotten).  Synchronises. */
+int fps_set_doors(fps_sim* sim, int32_t n_doors, const int32_t* cells, const int32_t* dests,
+                  int32_t per_step, uint64_t seed);
 
 /* Set the simulated time and step counter (resume). */
 int fps_set_time(fps_sim* sim, double t, int64_t step);

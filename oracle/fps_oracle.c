@@ -18,6 +18,9 @@
  *   - responder cycle storage -> 30 s pick -> barrier -> 30 s drop; layer fill
  *     along the barrier line, N_L layers: sec. 2.4, sec. 3.3
  *   - triangular inflow hydrograph: sec. 3.1
+ *   - pre-flood flow: 7 entrance doors, entering and leaving by each with
+ *     probability 1/7, 10 per door, 1,000 walkers, a 5-minute spin-up with
+ *     no inflow, no entries once water is on the site: sec. 3, sec. 3.2, sec. 2.4
  * Readings where the paper is silent (each also listed in the design notes):
  *   R1 Riemann solver: HLLC (Toro) with dry-bed wave speeds.  HLL part written
  *      anchored at the left state, which is the same formula rearranged so that
@@ -66,6 +69,33 @@
  *      i = floor((float)x / (float)dx).
  *   R21 cleanup after the update: h := max(h, 0) (clipped volume recorded),
  *      q := 0 where h <= h_dry.
+ * Readings of the pre-flood door flow (or_doors; the paper gives the counts,
+ * not the mechanism):
+ *   D1 the agents are slots: the most people inside at once (1,000); a slot
+ *      outside (OR_ST_OUTSIDE) may enter, at most door_rate per door per step
+ *      (the 10 per door, per 1 s pedestrian step while dry).
+ *   D2 admission: every free slot draws a door, each with probability 1/n_door,
+ *      every step; at each door the first door_rate slots in slot order that
+ *      drew it enter, at a uniform point of the central half of the door cell,
+ *      standing, hazard class DRY.  Entries follow the step's pedestrian moves,
+ *      so a slot freed in a step may enter in the same step.
+ *   D3 an entrant heads for a leaving door drawn uniformly from the other doors
+ *      (so each door is the leaving door with probability 1/n_door overall);
+ *      arriving there (R16) it goes back outside.  Walkers move like evacuees
+ *      (R14, R15) at their own dry speed and add no roughness (R13 counts
+ *      evacuees only).
+ *   D4 trigger (R17): the first step after whose flood update a cell is wet
+ *      closes the doors for good; every walker inside becomes an evacuee
+ *      heading for the nearest exit in that step's move (the doors are not
+ *      exits: the emergency exit stays open).
+ *   D5 spin-up: the run starts 300 s before the hydrograph, which is zero
+ *      until then; the dry steps are the 1 s pedestrian step.
+ *   D6 random numbers: SplitMix64 (Steele, Lea & Flood 2014) in counter form:
+ *      draw k (0 entry door, 1 leaving door, 2 and 3 offsets in x and y) of
+ *      slot a in step n is output (n * 2^26 + a * 4 + k) + 1 of the generator
+ *      seeded with door_seed; a choice among m is floor((u >> 32) * m / 2^32),
+ *      an offset 0.25 + 0.5 * floor(u / 2^40) / 2^24, the position
+ *      ((float)i + offset) * (float)dx in FP32 (R19's precision).
  */
 #include "fps_oracle.h"
 
@@ -753,7 +783,7 @@ void or_build_bins(const or_params *P, int32_t na, const float *x, const float *
     int32_t *key = malloc(sizeof(int32_t) * (na > 0 ? na : 1));
     for (int32_t a = 0; a < na; ++a) {
         key[a] = -1;
-        if (state[a] == OR_ST_EXITED) continue;
+        if (state[a] == OR_ST_EXITED || state[a] == OR_ST_OUTSIDE) continue;
         int32_t ci = clampi(or_cell_index(x[a], P->dx, P->nx), 0, P->nx - 1);
         int32_t cj = clampi(or_cell_index(y[a], P->dy, P->ny), 0, P->ny - 1);
         key[a] = (cj / bsy) * nbx + ci / bsx;
@@ -846,15 +876,15 @@ void or_ped_step(or_sim *S, double dt)
     double *x1 = malloc(sizeof(double) * na), *y1 = malloc(sizeof(double) * na);
     double *vx1 = malloc(sizeof(double) * na), *vy1 = malloc(sizeof(double) * na);
     const int32_t Rx = (int32_t)ceil(P->r_cut / P->dx - 1e-9), Ry = (int32_t)ceil(P->r_cut / P->dy - 1e-9);
-    int32_t drops = 0;
+    int32_t drops = 0, leaves = 0;
 
     /* every agent reads the start-of-step state and writes only its own record */
-#pragma omp parallel for schedule(dynamic, 256) reduction(+ : drops)
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : drops, leaves)
     for (int32_t a = 0; a < na; ++a) {
         double x = S->x[a], y = S->y[a];
         x1[a] = x; y1[a] = y; vx1[a] = S->vx[a]; vy1[a] = S->vy[a];
         int32_t st = S->state[a];
-        if (st == OR_ST_EXITED) continue;
+        if (st == OR_ST_EXITED || st == OR_ST_OUTSIDE) continue;
         int32_t ci = clampi(or_cell_index(x, P->dx, nx), 0, nx - 1);
         int32_t cj = clampi(or_cell_index(y, P->dy, ny), 0, ny - 1);
         int64_t c = (int64_t)cj * nx + ci;
@@ -876,6 +906,11 @@ void or_ped_step(or_sim *S, double dt)
             st = OR_ST_EVAC;
             S->dest[a] = nearest_exit(S, ci, cj);
         }
+        /* water on the site: walkers of the door flow become evacuees (D4) */
+        if (st == OR_ST_SHOPPING && S->any_wet) {
+            st = OR_ST_EVAC;
+            S->dest[a] = nearest_exit(S, ci, cj);
+        }
         /* responder waits (sec. 2.4) */
         if (st == OR_ST_PICKING || st == OR_ST_DROPPING) {
             S->timer[a] -= dt;
@@ -894,7 +929,7 @@ void or_ped_step(or_sim *S, double dt)
             }
         }
         /* evacuation trigger (R17); an agent without a destination stands */
-        if ((S->role[a] == OR_ROLE_EVACUEE && !S->any_wet) || S->dest[a] < 0 ||
+        if ((S->role[a] == OR_ROLE_EVACUEE && st == OR_ST_EVAC && !S->any_wet) || S->dest[a] < 0 ||
             S->dest[a] >= S->n_dest) {
             vx1[a] = 0.0; vy1[a] = 0.0;
             S->state[a] = (uint8_t)st;
@@ -981,6 +1016,9 @@ void or_ped_step(or_sim *S, double dt)
                 st = OR_ST_DROPPING;
                 S->timer[a] = P->drop_s;
                 vx = 0.0; vy = 0.0;
+            } else if (st == OR_ST_SHOPPING) {
+                st = OR_ST_OUTSIDE;      /* left by its door (D3) */
+                leaves += 1;
             }
         }
         x1[a] = xn; y1[a] = yn; vx1[a] = vx; vy1[a] = vy;
@@ -989,6 +1027,8 @@ void or_ped_step(or_sim *S, double dt)
     for (int32_t a = 0; a < na; ++a) {
         S->x[a] = x1[a]; S->y[a] = y1[a]; S->vx[a] = vx1[a]; S->vy[a] = vy1[a];
     }
+    S->door_out += leaves;
+    or_doors(S);
     /* barrier fill (R18) */
     S->drops_total += drops;
     if (!S->done && S->nline > 0) {
@@ -1006,6 +1046,60 @@ void or_ped_step(or_sim *S, double dt)
         }
     }
     free(xf); free(yf); free(x1); free(y1); free(vx1); free(vy1);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Pre-flood door flow (sec. 3, sec. 3.2; D1-D6)                              */
+/* ------------------------------------------------------------------------ */
+uint64_t or_splitmix64(uint64_t seed, uint64_t c)
+{
+    /* the generator's state after c + 1 steps of the golden-ratio gamma, then
+       its output mix (D6) */
+    uint64_t z = seed + (c + 1) * 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+static uint64_t door_draw(const or_sim *S, int32_t a, int32_t k)
+{
+    uint64_t c = ((uint64_t)S->step << 26) | ((uint64_t)a << 2) | (uint64_t)k;
+    return or_splitmix64(S->door_seed, c);
+}
+
+static int32_t choice_of(uint64_t u, int32_t m) { return (int32_t)(((u >> 32) * (uint64_t)m) >> 32); }
+
+static float offset_of(uint64_t u) { return 0.25f + 0.5f * ((float)(u >> 40) * (1.0f / 16777216.0f)); }
+
+void or_doors(or_sim *S)
+{
+    const or_params *P = &S->P;
+    if (S->n_door <= 0 || S->doors_closed) return;
+    if (S->any_wet) {
+        S->doors_closed = 1;
+        return;
+    }
+    int32_t taken[OR_MAX_DOOR] = {0};
+    for (int32_t a = 0; a < S->na; ++a) {
+        if (S->state[a] != OR_ST_OUTSIDE) continue;
+        int32_t d = choice_of(door_draw(S, a, 0), S->n_door);
+        if (taken[d] >= S->door_rate) continue;
+        taken[d] += 1;
+        int32_t j = choice_of(door_draw(S, a, 1), S->n_door - 1);
+        int32_t leave = j < d ? j : j + 1;
+        int32_t ci = S->door_cell[d] % P->nx, cj = S->door_cell[d] / P->nx;
+        float xf = ((float)ci + offset_of(door_draw(S, a, 2))) * (float)P->dx;
+        float yf = ((float)cj + offset_of(door_draw(S, a, 3))) * (float)P->dy;
+        S->x[a] = xf;
+        S->y[a] = yf;
+        S->vx[a] = 0.0;
+        S->vy[a] = 0.0;
+        S->timer[a] = 0.0;
+        S->state[a] = OR_ST_SHOPPING;
+        S->cls[a] = OR_CLS_DRY;
+        S->dest[a] = S->door_dest[leave];
+        S->door_in += 1;
+    }
 }
 
 double or_coupled_step(or_sim *S, double dt)

@@ -31,6 +31,9 @@ extern "C" {
 #define OR_ST_PICKING 3
 #define OR_ST_TO_BARRIER 4
 #define OR_ST_DROPPING 5
+#define OR_ST_SHOPPING 6   /* before the flood: walking to the door it leaves by (D3) */
+#define OR_ST_OUTSIDE 7    /* outside the building: a free slot (D1) */
+#define OR_MAX_DOOR 16
 #define OR_CLS_DRY 0
 #define OR_CLS_LOW 1
 #define OR_CLS_MEDIUM 2
@@ -88,6 +91,12 @@ typedef struct {
     int32_t drops_total;
     /* scratch for the cell lists, sized by the caller: bin_start[nbins+1], perm[na] */
     int32_t *bin_start, *perm;
+    /* pre-flood door flow (sec. 3, sec. 3.2; D1-D6): n_door = 0 switches it off */
+    int32_t n_door, door_rate;
+    const int32_t *door_cell, *door_dest;  /* [n_door]: cell j*nx+i, destination index */
+    uint64_t door_seed;
+    int32_t doors_closed;
+    int64_t door_in, door_out;
 } or_sim;
 
 /* ---- single operations (exposed for the pins) ---- */
@@ -112,7 +121,9 @@ double or_compute_dt(const or_sim *S);
 void or_fv_step(or_sim *S, double dt);            /* flood update, no time advance */
 double or_minmod(double a, double b);             /* slope limiter of the second-order variant */
 void or_count_evacuees(or_sim *S);                /* recompute np from the agents */
-void or_ped_step(or_sim *S, double dt);           /* agents + barrier fill */
+void or_ped_step(or_sim *S, double dt);           /* agents + barrier fill + door entries */
+uint64_t or_splitmix64(uint64_t seed, uint64_t c); /* output c + 1 of SplitMix64 from seed (D6) */
+void or_doors(or_sim *S);                         /* the entries of one step (D2, D4) */
 /* one coupled step; dt <= 0 means "compute it", returns the dt used */
 double or_coupled_step(or_sim *S, double dt);
 /* n coupled steps; dts (may be NULL) replays a dt per step; dt_used (may be NULL) records */

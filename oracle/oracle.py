@@ -25,7 +25,7 @@ _up = C.POINTER(C.c_uint8)
 
 WALL, TRANSMISSIVE = 0, 1
 ROLE_EVACUEE, ROLE_RESPONDER = 0, 1
-ST_EVAC, ST_EXITED, ST_TO_STORAGE, ST_PICKING, ST_TO_BARRIER, ST_DROPPING = range(6)
+ST_EVAC, ST_EXITED, ST_TO_STORAGE, ST_PICKING, ST_TO_BARRIER, ST_DROPPING, ST_SHOPPING, ST_OUTSIDE = range(8)
 CLS_DRY, CLS_LOW, CLS_MEDIUM, CLS_HIGH, CLS_HIGHEST = range(5)
 FLUX_HLLC, FLUX_HLL = 0, 1
 
@@ -66,6 +66,11 @@ class OrSim(C.Structure):
         ("active", C.c_int32), ("layers_done", C.c_int32), ("bags", C.c_int32),
         ("done", C.c_int32), ("drops_total", C.c_int32),
         ("bin_start", _ip), ("perm", _ip),
+        ("n_door", C.c_int32), ("door_rate", C.c_int32),
+        ("door_cell", _ip), ("door_dest", _ip),
+        ("door_seed", C.c_uint64),
+        ("doors_closed", C.c_int32),
+        ("door_in", C.c_int64), ("door_out", C.c_int64),
     ]
 
 
@@ -117,6 +122,9 @@ def lib(omp: bool = False):
         L.or_run.argtypes = [C.POINTER(OrSim), C.c_int32, _dp, _dp, C.c_int32]
         L.or_mass.argtypes = [C.POINTER(OrSim)]
         L.or_mass.restype = C.c_double
+        L.or_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
+        L.or_splitmix64.restype = C.c_uint64
+        L.or_doors.argtypes = [C.POINTER(OrSim)]
     return _libs[omp]
 
 
@@ -215,6 +223,16 @@ class OracleSim:
         else:
             S.nline = 0
             S.storage_dest = S.barrier_dest = -1
+        # pre-flood door flow
+        dr = getattr(sc, "doors", None)
+        if dr is not None and na:
+            self.door_cell = np.ascontiguousarray(dr["cells"], dtype=np.int32).copy()
+            self.door_dest = np.ascontiguousarray(dr["dests"], dtype=np.int32).copy()
+            S.n_door, S.door_rate = len(self.door_cell), int(dr["per_step"])
+            S.door_cell, S.door_dest = _ptr(self.door_cell, _ip), _ptr(self.door_dest, _ip)
+            S.door_seed = int(dr["seed"])
+        else:
+            S.n_door = 0
         S.any_wet = int(np.any(self.h > d.h_dry))
         if na:
             L.or_count_evacuees(C.byref(S))
@@ -306,6 +324,11 @@ def friction(params, dt, h, n, qx, qy):
     a, b = C.c_double(qx), C.c_double(qy)
     lib().or_friction(C.byref(params), float(dt), float(h), float(n), C.byref(a), C.byref(b))
     return a.value, b.value
+
+
+def splitmix64(seed, c):
+    """Output c + 1 of SplitMix64 started from seed."""
+    return int(lib().or_splitmix64(int(seed), int(c)))
 
 
 def cell_index(x, d, n):

@@ -41,6 +41,7 @@ struct fps_sim {
     uint4* wmask;
     int32_t* line;
     int32_t* stats;
+    int32_t* doors;            // door cells, then their destinations (kMaxDoor each)
     int32_t line_cap;
     int H;
     int nbins, bsx, bsy, nbx, nby, Rx, Ry;
@@ -64,6 +65,8 @@ struct fps_sim {
     bool nav_bound;
     int32_t nline, storage_dest, barrier_dest, n_layers, bags_per;
     float t_bag, t_last;
+    int32_t n_door, door_rate;
+    uint64_t door_seed;
     bool numeric_fault;
 };
 
@@ -83,6 +86,7 @@ struct Engine {
     int64_t max_cells = 0;
     int fin_lds_bytes = 0;
     bool any_big = false;
+    bool any_doors = false;          // some scenario runs the pre-flood door flow
     bool dirty = true;
     int graph_chunk = 16;
     int hll = 0;                     // face flux of every scenario: HLL instead of HLLC
@@ -163,7 +167,7 @@ bool valid_desc(const fps_grid_desc* d, char* why)
 // Per-scenario part of the workspace (offsets from the member's base).
 struct Layout {
     size_t st, partials, wet, h2, qx2, qy2, h1, qx1, qy1, np, bin_count, bin_start, rank, key, perm_u, perm, xy, slot,
-        wmask, line, stats, total;
+        wmask, line, stats, doors, total;
     int64_t nbins_max;
     int32_t line_cap;
 };
@@ -202,6 +206,7 @@ Layout member_layout(const fps_grid_desc* d, int32_t max_agents)
     L.wmask = take(max_agents > 0 ? sizeof(uint4) * nc : 0);
     L.line = take(sizeof(int32_t) * L.line_cap);
     L.stats = take(sizeof(int32_t) * 16);
+    L.doors = take(sizeof(int32_t) * 2 * kMaxDoor);
     L.total = o;
     return L;
 }
@@ -247,6 +252,7 @@ fps_sim* new_member(Engine* e, int idx, const fps_grid_desc* d, const fps_ped_pa
     s->wmask = at<uint4>(base, L.wmask);
     s->line = at<int32_t>(base, L.line);
     s->stats = at<int32_t>(base, L.stats);
+    s->doors = at<int32_t>(base, L.doors);
     s->line_cap = L.line_cap;
     s->H = fv_rows_per_wave(d->nx, d->ny);
     s->bsx = std::max(1, (int)std::ceil(P.r_cut / d->dx - 1e-9));
@@ -338,6 +344,8 @@ void fill_scn(const fps_sim* s, Scn& c)
     for (int k = 0; k < 3; ++k) q.hr_t[k] = (float)s->P.hr_t[k];
     q.pick_s = (float)s->P.pick_s; q.drop_s = (float)s->P.drop_s;
     q.storage_dest = s->storage_dest; q.barrier_dest = s->barrier_dest;
+    q.doors = s->doors; q.n_door = s->na > 0 ? s->n_door : 0; q.door_rate = s->door_rate;
+    q.door_seed = s->door_seed;
 
     BinParams& b = c.bins;
     b.x = s->x; b.y = s->y; b.state = s->state; b.role = s->role;
@@ -374,6 +382,7 @@ int upload(Engine* e)
     e->scn_h.resize(e->S);
     e->max_cells = 0;
     e->any_big = false;
+    e->any_doors = false;
     e->fin_lds_bytes = 0;
     for (int k = 0; k < e->S; ++k) {
         fps_sim* s = e->m[k];
@@ -382,6 +391,7 @@ int upload(Engine* e)
         e->agent_off_h[k + 1] = e->agent_off_h[k] + (s->na + kPedBlock - 1) / kPedBlock * kPedBlock;
         e->max_cells = std::max(e->max_cells, (int64_t)s->G.nx * s->G.ny);
         e->any_big = e->any_big || s->na > kInlinePlace;
+        e->any_doors = e->any_doors || e->scn_h[k].ped.n_door > 0;
         if (e->scn_h[k].lds_bins)
             e->fin_lds_bytes = std::max(e->fin_lds_bytes, (int)(sizeof(int) * (s->nbins + 1 + s->na)));
     }
@@ -475,6 +485,7 @@ int step_launches(Engine* e, hipStream_t st, KernelEvents* K)
     if (e->total_agents > 0) {
         rec(1, 0);
         HIPCHK_E(e, launch_ped(b, st));
+        if (e->any_doors) HIPCHK_E(e, launch_doors(b, st));
         rec(1, 1);
     }
     rec(2, 0);
@@ -755,6 +766,16 @@ int write_state_i32(fps_sim* s, int32_t* field, int32_t v)
 {
     HIPCHK(s, hipMemcpyAsync(field, &v, sizeof(v), hipMemcpyHostToDevice, s->eng->stream));
     HIPCHK(s, hipStreamSynchronize(s->eng->stream));
+    return FPS_OK;
+}
+
+// the free slots of the door flow, counted from the bound agents' states
+int recount_outside(fps_sim* s)
+{
+    hipStream_t st = s->eng->stream;
+    HIPCHK(s, launch_fill_i32(&s->st->n_outside, 0, 1, st));
+    if (s->na > 0) HIPCHK(s, launch_count_state(s->state, s->na, FPS_ST_OUTSIDE, &s->st->n_outside, st));
+    HIPCHK(s, hipStreamSynchronize(st));
     return FPS_OK;
 }
 
@@ -1131,7 +1152,45 @@ int fps_bind_agents(fps_sim* s, int32_t n, float* x, float* y, float* vx, float*
     s->x = x; s->y = y; s->vx = vx; s->vy = vy; s->vbase = v_base;
     s->role = role; s->state = state; s->cls = hr_class; s->dest = dest; s->timer = timer;
     mark_dirty(s);
-    return rebuild_bins(s);
+    int rc = rebuild_bins(s);
+    return rc != FPS_OK ? rc : recount_outside(s);
+}
+
+int fps_set_doors(fps_sim* s, int32_t n_doors, const int32_t* cells, const int32_t* dests, int32_t per_step,
+                  uint64_t seed)
+{
+    if (!s) return fail(nullptr, FPS_E_INVALID, "fps_set_doors: sim is NULL");
+    if (n_doors != 0 && (n_doors < 2 || n_doors > kMaxDoor))
+        return fail(s, FPS_E_INVALID, "fps_set_doors: n_doors must be 0 or in [2, %d], got %d", kMaxDoor, n_doors);
+    int32_t tab[2 * kMaxDoor] = {};
+    if (n_doors > 0) {
+        if (!cells || !dests) return fail(s, FPS_E_INVALID, "fps_set_doors: NULL array");
+        if (per_step < 0) return fail(s, FPS_E_INVALID, "fps_set_doors: per_step must be >= 0, got %d", per_step);
+        if (!s->nav_bound) return fail(s, FPS_E_STATE, "fps_set_doors: set the navigation map first");
+        if (s->max_agents > (1 << 24))
+            return fail(s, FPS_E_CAPACITY, "fps_set_doors: at most 2^24 agents (capacity %d)", s->max_agents);
+        if (s->G.nx > (1 << 20) || s->G.ny > (1 << 20))
+            return fail(s, FPS_E_CAPACITY, "fps_set_doors: at most 2^20 cells along a side");
+        const int64_t nc = (int64_t)s->G.nx * s->G.ny;
+        for (int k = 0; k < n_doors; ++k) {
+            if (cells[k] < 0 || cells[k] >= nc)
+                return fail(s, FPS_E_INVALID, "fps_set_doors: door %d: cell %d outside the grid", k, cells[k]);
+            if (dests[k] < s->n_exit || dests[k] >= s->n_dest)
+                return fail(s, FPS_E_INVALID, "fps_set_doors: door %d: destination %d not in [%d, %d)", k,
+                            dests[k], s->n_exit, s->n_dest);
+            tab[k] = cells[k];
+            tab[kMaxDoor + k] = dests[k];
+        }
+    }
+    hipStream_t st = s->eng->stream;
+    HIPCHK(s, hipMemcpyAsync(s->doors, tab, sizeof(tab), hipMemcpyHostToDevice, st));
+    int rc = write_state_i32(s, &s->st->doors_closed, 0);
+    if (rc != FPS_OK) return rc;
+    s->n_door = n_doors;
+    s->door_rate = per_step;
+    s->door_seed = seed;
+    mark_dirty(s);
+    return recount_outside(s);
 }
 
 int fps_set_barrier(fps_sim* s, const int32_t* cells, int32_t ncells, int32_t storage_dest,
@@ -1344,7 +1403,7 @@ int fps_get_diag(fps_sim* s, fps_diag* out)
     out->any_wet = d.any_wet;
     out->n_agents = s->na;
     for (int k = 0; k < 5; ++k) out->class_count[k] = stats[k];
-    for (int k = 0; k < 6; ++k) out->state_count[k] = stats[5 + k];
+    for (int k = 0; k <= FPS_ST_OUTSIDE; ++k) out->state_count[k] = stats[5 + k];
     out->barrier_layers_done = d.layers_done;
     out->barrier_active_cell = d.active_cell;
     out->barrier_bags = d.bags;
@@ -1353,6 +1412,9 @@ int fps_get_diag(fps_sim* s, fps_diag* out)
     out->status = d.status;
     out->active = d.active;
     out->flood_steps = d.flood_steps;
+    out->doors_closed = d.doors_closed;
+    out->door_entries = d.door_in;
+    out->door_leaves = d.door_out;
     if (d.status != FPS_OK) {
         s->numeric_fault = true;
         return fail(s, FPS_E_NUMERIC, "non-finite state or time step detected on the device");

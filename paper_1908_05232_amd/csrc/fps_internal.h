@@ -31,6 +31,7 @@ constexpr int kLdsBinWords = 30 * 1024;  // LDS words for bin starts + placement
 constexpr int kLdsScanBins = 16 * kScanThreads;   // bins the LDS binning scans in one pass
 constexpr int kWetSlots = 64;          // wetness flags of a flood update, one per group of blocks
 constexpr int kWetStride = 32;         // ints between flags (one 128-byte line each)
+constexpr int kMaxDoor = 16;           // entrance doors of the pre-flood flow
 
 // Scalars that live in device memory so that n steps run without the host.
 struct DevState {
@@ -54,6 +55,10 @@ struct DevState {
     int32_t layers_done, active_cell, bags, done, drops, drops_total;
     int32_t settled;       // the state came out of a flood update (dry cells carry no discharge)
     int32_t frozen;        // the flood update is held: steps of dt_max move only the pedestrians
+    // pre-flood door flow (sec. 3.2)
+    int32_t doors_closed;  // some cell has been wet: no more entries
+    int32_t n_outside;     // agents in state OUTSIDE (free slots)
+    int64_t door_in, door_out;   // entries and leaves so far
 };
 
 struct FvParams {
@@ -110,6 +115,10 @@ struct PedParams {
     float v_class[5], hr_t[3], pick_s, drop_s;
     int storage_dest, barrier_dest;
     int need_rank;              // histogram + each agent's rank in its bin (the global binning needs them)
+    // pre-flood door flow: door cells [0, kMaxDoor) then their destinations [kMaxDoor, 2 kMaxDoor)
+    const int32_t* doors;
+    int n_door, door_rate;
+    uint64_t door_seed;
 };
 
 // Sandbag barrier of sec. 2.4: the fill order and layer rules.
@@ -178,6 +187,8 @@ hipError_t launch_ped(const Batch& b, hipStream_t s);
 hipError_t launch_stream_probe(float* buf, int64_t n, int64_t stride, int n_in, int n_out, int blocks,
                                hipStream_t s);
 int ped_lanes(int64_t total_agents);     // lanes per agent of the pedestrian step
+hipError_t launch_doors(const Batch& b, hipStream_t s);    // entries of the pre-flood flow, one block per scenario
+hipError_t launch_count_state(const uint8_t* state, int na, int value, int32_t* out, hipStream_t s);
 hipError_t launch_bin_place_all(const Batch& b, hipStream_t s);
 hipError_t launch_bin_sort_all(const Batch& b, hipStream_t s);
 hipError_t launch_bin_keys(const BinParams& b, hipStream_t s);   // keys + ranks from positions
@@ -188,7 +199,7 @@ hipError_t launch_count(const BinParams& b, hipStream_t s);      // per-cell eva
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_hazard(const float* h, const float* qx, const float* qy, float* hr, int64_t n,
                          float eps, hipStream_t s);
-hipError_t launch_agent_stats(const uint8_t* state, const uint8_t* cls, int na, int32_t* out11,
+hipError_t launch_agent_stats(const uint8_t* state, const uint8_t* cls, int na, int32_t* out13,
                               hipStream_t s);
 hipError_t launch_wall_mask(const uint8_t* walk, uint4* mask, int nx, int ny, int Rx, int Ry,
                             hipStream_t s);

@@ -17,6 +17,8 @@
 // axis-wise rejection of moves into obstacles or out of the domain; arrival
 // when the destination distance at the new cell is <= r_arrive; evacuees stand
 // until some cell is wet; dry cells: hazard class DRY at the agent's own speed.
+// Before the flood, walkers of the door flow (sec. 3.2) walk at their own
+// speed to the door they leave by; the door kernel below lets free slots in.
 //
 // Binning is a stable counting sort by (bin, agent id): integer histogram with
 // atomic ranks, one-block exclusive scan, placement by rank, then each agent
@@ -163,7 +165,7 @@ __device__ __forceinline__ AgentRec load_agent(const PedParams& p, int a)
 template <int L>
 __device__ void agent_step(const PedParams& p, const AgentRec& rec, const float* __restrict__ fh,
                            const float* __restrict__ fqx, const float* __restrict__ fqy, int a, int q,
-                           float dt, int any_wet, int done, int& drop)
+                           float dt, int any_wet, int done, int& drop, int& left)
 {
     const bool lead = q == 0;
     const int st0 = rec.state;
@@ -173,7 +175,7 @@ __device__ void agent_step(const PedParams& p, const AgentRec& rec, const float*
     int dest = rec.dest;
     const float vbase = rec.vbase;
     const int self = rec.slot;
-    if (st0 == FPS_ST_EXITED) {
+    if (st0 == FPS_ST_EXITED || st0 == FPS_ST_OUTSIDE) {
         if (lead) p.key[a] = -1;
         return;
     }
@@ -198,6 +200,12 @@ __device__ void agent_step(const PedParams& p, const AgentRec& rec, const float*
         st = FPS_ST_EVAC;
         dest = nearest_exit(p, ci, cj);
     }
+    // the flood has reached the site: walkers of the pre-flood flow become
+    // evacuees heading for the nearest exit
+    if (st == FPS_ST_SHOPPING && any_wet) {
+        st = FPS_ST_EVAC;
+        dest = nearest_exit(p, ci, cj);
+    }
     bool moving = true;
     if (st == FPS_ST_PICKING || st == FPS_ST_DROPPING) {
         float tm = rec.timer - dt;
@@ -213,7 +221,7 @@ __device__ void agent_step(const PedParams& p, const AgentRec& rec, const float*
             dest = p.storage_dest;
         }
     }
-    if (moving && role == FPS_ROLE_EVACUEE && !any_wet) moving = false;
+    if (moving && role == FPS_ROLE_EVACUEE && st == FPS_ST_EVAC && !any_wet) moving = false;
     // an agent without a valid destination (e.g. a responder with no barrier set) stands
     if (dest < 0 || dest >= p.n_dest) moving = false;
     // second load round: everything addressed by the cell
@@ -429,6 +437,9 @@ __device__ void agent_step(const PedParams& p, const AgentRec& rec, const float*
                 if (lead) p.timer[a] = p.drop_s;
                 vx = 0.0f;
                 vy = 0.0f;
+            } else if (st == FPS_ST_SHOPPING) {
+                st = FPS_ST_OUTSIDE;      // left by its door: the slot is free again
+                left = 1;
             }
         }
     }
@@ -448,7 +459,7 @@ __device__ void agent_step(const PedParams& p, const AgentRec& rec, const float*
     // bin key of the new position; the global binning also needs the
     // histogram and each agent's rank in its bin (the LDS binning counts the
     // keys itself)
-    if (st != FPS_ST_EXITED) {
+    if (st != FPS_ST_EXITED && st != FPS_ST_OUTSIDE) {
         int b = (nj / p.bsy) * p.nbx + ni / p.bsx;
         p.key[a] = b;
         if (p.need_rank) p.rank[a] = atomicAdd(&p.bin_count[b], 1);
@@ -485,20 +496,146 @@ __global__ __launch_bounds__(kWave) void ped_step_kernel(Batch B)
     // one wetness flag per lane (the flood update sets them per group of blocks)
     // (a skipped update left the state, and its wetness, as they were)
     const int wet = skipped ? st->any_wet : (__ballot(S.fv.wet[kWetStride * threadIdx.x] != 0) != 0ull);
-    int drop = 0;
+    int drop = 0, left = 0;
     if (a < S.na)
         agent_step<L>(P, rec, fb ? S.fv.h[1] : S.fv.h[0], fb ? S.fv.qx[1] : S.fv.qx[0], fb ? S.fv.qy[1] : S.fv.qy[0],
-                   a, q, dt, wet, done, drop);
+                   a, q, dt, wet, done, drop, left);
     // one wave per block: the sandbag drops of the wave (lane 0 of each
     // group), one atomic; the agent-steps of the step are the agents that
     // start it outside the exits, which the bins hold: one add per scenario,
     // by its first block, instead of a same-address atomic from every block
     const unsigned long long drops = __popcll(__ballot(drop && q == 0));
+    const unsigned long long leaves = __popcll(__ballot(left && q == 0));
     if (threadIdx.x == 0) {
         DevState* stw = S.fv.st;
         if (drops) atomicAdd(&stw->drops, (int)drops);
+        if (leaves) {
+            atomicAdd(&stw->n_outside, (int)leaves);
+            atomicAdd(reinterpret_cast<unsigned long long*>(&stw->door_out), leaves);
+        }
         if (a == 0) atomicAdd(&stw->ped_steps, (unsigned long long)P.bin_start[P.nbx * P.nby]);
     }
+}
+
+// --- pre-flood door flow (sec. 3, sec. 3.2) ---------------------------------
+// SplitMix64 (Steele, Lea & Flood 2014): output number c + 1 of the generator
+// started from seed, i.e. its output mix applied to seed + (c + 1) * gamma.
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t c)
+{
+    uint64_t z = seed + (c + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// draw k of slot a in step n (k = 0: entry door, 1: leaving door, 2, 3: offsets in the cell)
+__device__ __forceinline__ uint64_t door_draw(uint64_t seed, int64_t n, int a, int k)
+{
+    return splitmix64_at(seed, ((uint64_t)n << 26) | ((uint64_t)(uint32_t)a << 2) | (uint64_t)k);
+}
+
+// an integer uniform in [0, m) from the upper 32 bits (multiply-shift)
+__device__ __forceinline__ int draw_below(uint64_t u, int m)
+{
+    return (int)(((u >> 32) * (uint64_t)(uint32_t)m) >> 32);
+}
+
+// a point of the central half of a cell: 0.25 + 0.5 * (upper 24 bits) / 2^24
+__device__ __forceinline__ float draw_mid(uint64_t u)
+{
+    return 0.25f + 0.5f * ((float)(uint32_t)(u >> 40) * 0x1p-24f);
+}
+
+// The entries of one step, one block per scenario, after the pedestrian step
+// (so slots freed by walkers who left this step may enter at once) and before
+// the end-of-step binning (which takes the entrants in through their keys).
+// Every free slot draws a door; at each door the first door_rate slots in
+// slot order that drew it enter.  The slots are scanned in chunks of the
+// block: per door, a ballot gives each slot its rank in its wave, the wave
+// counts in LDS its rank in the chunk, and the running count per door its
+// rank in the step.  The scan stops once every door is full.
+template <bool kOne>
+__global__ __launch_bounds__(kScanThreads) void door_kernel(Batch B)
+{
+    constexpr int kW = kScanThreads / kWave;
+    __shared__ int taken[kMaxDoor];
+    __shared__ int wcnt[kW][kMaxDoor];
+    const Scn& S = scn_at<kOne>(B, kOne ? 0 : (int)blockIdx.x);
+    const PedParams& P = S.ped;
+    const int nd = P.n_door;
+    DevState* st = S.fv.st;
+    if (nd == 0 || !st->active || st->doors_closed) return;
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
+    // the same wetness as the pedestrian step of this step
+    const bool skipped = flood_skipped(st);
+    const bool wet = skipped ? st->any_wet != 0 : __ballot(S.fv.wet[kWetStride * lane] != 0) != 0ull;
+    if (wet) {
+        if (threadIdx.x == 0) st->doors_closed = 1;
+        return;
+    }
+    if (st->n_outside <= 0) return;
+    const int64_t n = st->step;
+    const uint64_t seed = P.door_seed;
+    const int rate = P.door_rate, na = P.na;
+    if (threadIdx.x < kMaxDoor) taken[threadIdx.x] = 0;
+    for (int base = 0; base < na; base += kScanThreads) {
+        __syncthreads();
+        bool full = true;
+        for (int k = 0; k < nd; ++k) full = full && taken[k] >= rate;
+        if (full) break;
+        const int a = base + (int)threadIdx.x;
+        const bool out = a < na && P.state[a] == FPS_ST_OUTSIDE;
+        const int d = out ? draw_below(door_draw(seed, n, a, 0), nd) : -1;
+        int below = 0;
+        for (int k = 0; k < nd; ++k) {
+            const uint64_t m = __ballot(d == k);
+            if (lane == 0) wcnt[w][k] = __popcll(m);
+            if (d == k) below = __popcll(m & ((1ull << lane) - 1ull));
+        }
+        __syncthreads();
+        if (d >= 0) {
+            int r = taken[d] + below;
+            for (int v = 0; v < w; ++v) r += wcnt[v][d];
+            if (r < rate) {
+                const int dc = P.doors[d];
+                const int ci = dc % P.nx, cj = dc / P.nx;
+                const int j = draw_below(door_draw(seed, n, a, 1), nd - 1);
+                const int leave = j < d ? j : j + 1;
+                P.x[a] = ((float)ci + draw_mid(door_draw(seed, n, a, 2))) * P.dx;
+                P.y[a] = ((float)cj + draw_mid(door_draw(seed, n, a, 3))) * P.dy;
+                P.vx[a] = 0.0f;
+                P.vy[a] = 0.0f;
+                P.timer[a] = 0.0f;
+                P.state[a] = FPS_ST_SHOPPING;
+                P.cls[a] = FPS_CLS_DRY;
+                P.dest[a] = P.doors[kMaxDoor + leave];
+                const int b = (cj / P.bsy) * P.nbx + ci / P.bsx;
+                P.key[a] = b;
+                if (P.need_rank) P.rank[a] = atomicAdd(&P.bin_count[b], 1);
+            }
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < nd) {
+            int t = 0;
+            for (int v = 0; v < kW; ++v) t += wcnt[v][threadIdx.x];
+            taken[threadIdx.x] += t;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int e = 0;
+        for (int k = 0; k < nd; ++k) e += min(taken[k], rate);
+        st->n_outside -= e;
+        st->door_in += e;
+    }
+}
+
+// agents in one state (ballot counts, one atomic per wave)
+__global__ void count_state_kernel(const uint8_t* state, int na, int value, int32_t* out)
+{
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = __popcll(__ballot(a < na && state[a] == value));
+    if ((threadIdx.x & (kWave - 1)) == 0 && n) atomicAdd(out, n);
 }
 
 // --- binning ---------------------------------------------------------------
@@ -506,7 +643,7 @@ __global__ void bin_keys_kernel(BinParams b)
 {
     int a = blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= b.na) return;
-    if (b.state[a] == FPS_ST_EXITED) {
+    if (b.state[a] == FPS_ST_EXITED || b.state[a] == FPS_ST_OUTSIDE) {
         b.key[a] = -1;
         return;
     }
@@ -588,18 +725,18 @@ __global__ void hazard_kernel(const float* h, const float* qx, const float* qy, 
     }
 }
 
-// Counts per hazard class (non-exited agents) and per state: each wave counts
+// Counts per hazard class (agents inside: neither exited nor outside) and per state: each wave counts
 // its agents by ballots, one lane adds the wave's counts (integer sums, so
 // the order does not matter).
 __global__ void agent_stats_kernel(const uint8_t* state, const uint8_t* cls, int na, int32_t* out)
 {
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     const bool in = a < na;
-    const int s = in ? min((int)state[a], 5) : -1;
-    const int c = in && s != FPS_ST_EXITED ? min((int)cls[a], 4) : -1;
+    const int s = in ? min((int)state[a], (int)FPS_ST_OUTSIDE) : -1;
+    const int c = in && s != FPS_ST_EXITED && s != FPS_ST_OUTSIDE ? min((int)cls[a], 4) : -1;
     const bool first = (threadIdx.x & (kWave - 1)) == 0;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
+    for (int k = 0; k <= FPS_ST_OUTSIDE; ++k) {
         const int n = __popcll(__ballot(s == k));
         if (first && n) atomicAdd(&out[5 + k], n);
     }
@@ -636,7 +773,9 @@ __global__ void check_agents_kernel(const float* x, const float* y, const uint8_
     if (a >= na) return;
     float xa = x[a], ya = y[a];
     if (!(xa >= 0.0f && xa < lx && ya >= 0.0f && ya < ly)) atomicAdd(&bad[0], 1);
-    if (role[a] > FPS_ROLE_RESPONDER || state[a] > FPS_ST_DROPPING || dest[a] < -1 || dest[a] >= n_dest)
+    const bool door_flow = state[a] == FPS_ST_SHOPPING || state[a] == FPS_ST_OUTSIDE;
+    if (role[a] > FPS_ROLE_RESPONDER || state[a] > FPS_ST_OUTSIDE || dest[a] < -1 || dest[a] >= n_dest ||
+        (door_flow && role[a] != FPS_ROLE_EVACUEE))
         atomicAdd(&bad[1], 1);
 }
 
@@ -670,6 +809,17 @@ hipError_t launch_ped(const Batch& b, hipStream_t s)
         default: launch_ped_lanes<1>(b, s); break;
         }
     }
+    return hipGetLastError();
+}
+hipError_t launch_doors(const Batch& b, hipStream_t s)
+{
+    if (b.S == 1) hipLaunchKernelGGL((door_kernel<true>), dim3(1), dim3(kScanThreads), 0, s, b);
+    else hipLaunchKernelGGL((door_kernel<false>), dim3(b.S), dim3(kScanThreads), 0, s, b);
+    return hipGetLastError();
+}
+hipError_t launch_count_state(const uint8_t* state, int na, int value, int32_t* out, hipStream_t s)
+{
+    if (na > 0) hipLaunchKernelGGL(count_state_kernel, dim3(blocks_for(na, 256)), dim3(256), 0, s, state, na, value, out);
     return hipGetLastError();
 }
 hipError_t launch_bin_place_all(const Batch& b, hipStream_t s)
@@ -724,12 +874,12 @@ hipError_t launch_hazard(const float* h, const float* qx, const float* qy, float
     hipLaunchKernelGGL(hazard_kernel, dim3(g), dim3(256), 0, s, h, qx, qy, hr, n, eps);
     return hipGetLastError();
 }
-hipError_t launch_agent_stats(const uint8_t* state, const uint8_t* cls, int na, int32_t* out11,
+hipError_t launch_agent_stats(const uint8_t* state, const uint8_t* cls, int na, int32_t* out13,
                               hipStream_t s)
 {
     if (na > 0)
         hipLaunchKernelGGL(agent_stats_kernel, dim3(blocks_for(na, 256)), dim3(256), 0, s, state,
-                           cls, na, out11);
+                           cls, na, out13);
     return hipGetLastError();
 }
 hipError_t launch_wall_mask(const uint8_t* walk, uint4* mask, int nx, int ny, int Rx, int Ry,

@@ -553,7 +553,7 @@ __global__ void judge_kernel(int na, JudgePick q, const float* __restrict__ x, c
     // every agent when a selection state is given, else only the sample
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t a = q.hs ? t : t * q.stride;
-    if (a >= na || state[a] == FPS_ST_EXITED) return;
+    if (a >= na || state[a] == FPS_ST_EXITED || state[a] == FPS_ST_OUTSIDE) return;
     const size_t c = (size_t)cell_index(y[a], dy, ny) * nx + cell_index(x[a], dx, nx);
     if (!judged(q, a, c)) return;
     const float thr[3] = {q.t1, q.t2, q.t3};
@@ -579,7 +579,7 @@ __global__ void judge_mask_kernel(int na, JudgePick q, const float* __restrict__
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t a = q.hs ? t : t * q.stride;
-    if (a >= na || state[a] == FPS_ST_EXITED) return;
+    if (a >= na || state[a] == FPS_ST_EXITED || state[a] == FPS_ST_OUTSIDE) return;
     const int i = cell_index(x[a], dx, nx), j = cell_index(y[a], dy, ny);
     if (!judged(q, a, (size_t)j * nx + i)) return;
     const int mbx = (nx + block - 1) / block;

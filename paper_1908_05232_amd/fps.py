@@ -46,11 +46,12 @@ class DiagC(C.Structure):
         ("dt_last", C.c_double), ("dt_next", C.c_double),
         ("mass", C.c_double), ("v_in", C.c_double), ("v_out", C.c_double), ("v_clip", C.c_double),
         ("any_wet", C.c_int32), ("n_agents", C.c_int32),
-        ("class_count", C.c_int32 * 5), ("state_count", C.c_int32 * 6),
+        ("class_count", C.c_int32 * 5), ("state_count", C.c_int32 * 8),
         ("barrier_layers_done", C.c_int32), ("barrier_active_cell", C.c_int32),
         ("barrier_bags", C.c_int32), ("barrier_done", C.c_int32),
         ("drops_total", C.c_int32), ("status", C.c_int32),
         ("active", C.c_int32), ("flood_steps", C.c_int32),
+        ("doors_closed", C.c_int32), ("door_entries", C.c_int64), ("door_leaves", C.c_int64),
     ]
 
 
@@ -67,6 +68,8 @@ EXPORTS = {
     "fps_set_barrier": (C.c_int, [_vp, C.POINTER(C.c_int32), C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                   C.c_float, C.c_float, C.c_int32]),
     "fps_set_time": (C.c_int, [_vp, C.c_double, C.c_int64]),
+    "fps_set_doors": (C.c_int, [_vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int32,
+                                C.c_uint64]),
     "fps_step": (C.c_int, [_vp, C.c_int32]),
     "fps_get_diag": (C.c_int, [_vp, C.POINTER(DiagC)]),
     "fps_get_time": (C.c_int, [_vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
@@ -217,6 +220,8 @@ class Member:
             self._check(L.fps_set_barrier(h, cells.ctypes.data_as(C.POINTER(C.c_int32)), len(cells),
                                           b["storage_dest"], b["barrier_dest"], b["n_layers"],
                                           float(b["t_bag"]), float(b["t_last"]), b["bags_per"]))
+        if getattr(sc, "doors", None) is not None:
+            self.set_doors(sc.doors)
         self.na = 0 if sc.agents is None else len(sc.agents["x"])
         if self.na:
             A = sc.agents
@@ -237,6 +242,16 @@ class Member:
 
     def set_time(self, t, step=0):
         return self._check(self._lib.fps_set_time(self.h_, float(t), int(step)))
+
+    def set_doors(self, doors):
+        """Pre-flood door flow: doors = dict(cells, dests, per_step, seed) or None (off)."""
+        if doors is None:
+            return self._check(self._lib.fps_set_doors(self.h_, 0, None, None, 0, 0))
+        cells = np.ascontiguousarray(doors["cells"], np.int32)
+        dests = np.ascontiguousarray(doors["dests"], np.int32)
+        return self._check(self._lib.fps_set_doors(
+            self.h_, len(cells), cells.ctypes.data_as(C.POINTER(C.c_int32)),
+            dests.ctypes.data_as(C.POINTER(C.c_int32)), int(doors["per_step"]), int(doors["seed"])))
 
     def set_end_time(self, t_end):
         return self._check(self._lib.fps_set_end_time(self.h_, float(t_end)))

@@ -25,6 +25,7 @@ import numpy as np
 WALL, TRANSMISSIVE = 0, 1
 SIDE_W, SIDE_E, SIDE_S, SIDE_N = 0, 1, 2, 3
 ROLE_EVACUEE, ROLE_RESPONDER = 0, 1
+ST_EVAC, ST_EXITED, ST_SHOPPING, ST_OUTSIDE = 0, 1, 6, 7
 
 
 @dataclasses.dataclass
@@ -82,6 +83,7 @@ class Scenario:
     walk: Optional[np.ndarray] = None      # [ny, nx] uint8, 1 = walkable
     agents: Optional[dict] = None
     barrier: Optional[dict] = None
+    doors: Optional[dict] = None           # pre-flood door flow: cells, dests, per_step, seed
     name: str = ""
 
 
@@ -356,6 +358,58 @@ def add_barrier(sc: Scenario, seed: int, n_resp: int, height: float, t_bag: floa
     R["x"], R["y"] = place_uniform(rng, walk, n_resp, d.dx, d.dy)
     R["role"][:] = ROLE_RESPONDER
     sc.agents = concat_agents(sc.agents, R) if sc.agents is not None else R
+    return sc
+
+
+def door_cells(walk: np.ndarray, n_doors: int = 7):
+    """Entrance doors on the site's outer walls (stores east and west, doors
+    at the ends of the corridors, sec. 3): alternately on the west and east
+    walls at even spacing, and one on the south wall at a sixth of the width
+    (clear of the breach) when the count is odd; the north wall holds the
+    emergency exit.  Each door is the walkable wall cell nearest to its
+    target point.  Returns a list of (i, j)."""
+    ny, nx = walk.shape
+    n_side = n_doors // 2
+    targets = []
+    for m in range(n_side):
+        jt = int(round((m + 1) * ny / (n_side + 1)))
+        targets += [("W", jt), ("E", jt)]
+    if n_doors % 2:
+        targets.append(("S", int(round(nx / 6))))
+    out = []
+    for side, c in targets[:n_doors]:
+        line = ([(0, j) for j in range(ny)] if side == "W" else
+                [(nx - 1, j) for j in range(ny)] if side == "E" else [(i, 0) for i in range(nx)])
+        free = [p for p in line if walk[p[1], p[0]] and p not in out]
+        if not free:
+            raise ValueError(f"no walkable cell on the {side} wall for a door")
+        out.append(min(free, key=lambda p: abs((p[1] if side in "WE" else p[0]) - c)))
+    return out
+
+
+def add_doors(sc: Scenario, n_doors: int = 7, per_step: int = 10, seed: int = 1908,
+              spin_up: float = 300.0) -> Scenario:
+    """The pre-flood pedestrian flow of sec. 3.2: ``n_doors`` entrance doors
+    (``door_cells``) with a distance field each, appended to the navigation
+    map; every agent becomes a free slot outside the building (state OUTSIDE,
+    evacuee role), so the agent count is the most people inside at once (1,000
+    in the paper); ``per_step`` entries per door and step; the run starts
+    ``spin_up`` seconds before the flood (t0 = -300 s: the paper's -5 min, the
+    hydrograph still starting at its own t_flood)."""
+    d = sc.desc
+    cells = door_cells(sc.walk, n_doors)
+    base = sc.dist.shape[0]
+    fields = [distance_field(sc.walk, [c], d.dx, d.dy) for c in cells]
+    sc.dist = np.concatenate([sc.dist, np.stack(fields).astype(sc.dist.dtype)])
+    sc.doors = dict(cells=np.array([j * d.nx + i for (i, j) in cells], np.int32),
+                    dests=np.arange(base, base + n_doors, dtype=np.int32), per_step=per_step, seed=seed)
+    A = sc.agents
+    A["state"][:] = ST_OUTSIDE
+    A["role"][:] = ROLE_EVACUEE
+    A["dest"][:] = -1
+    A["vx"][:] = 0.0
+    A["vy"][:] = 0.0
+    sc.t0 = -float(spin_up)
     return sc
 
 
