@@ -3,7 +3,11 @@
 Scenario 1 (sec. 3.2): the evacuation run twice, with and without the
 people's effect on the flood (the roughness rule of sec. 2.4 switched off by a
 zero evacuee cap), at several breach discharges, since on this layout the
-crowd only meets the water once the breach carries more than a few m^2/s.  Scenario 2 (sec. 3.3): the pre-flood deployment sweep, six
+crowd only meets the water once the breach carries more than a few m^2/s.
+As in the paper the run starts 5 minutes before the breach with the
+pre-flood flow of walkers entering and leaving by 7 doors (10 per door and
+step, up to 1,000 inside); the first wet step closes the doors and makes the
+walkers inside evacuees.  Scenario 2 (sec. 3.3): the pre-flood deployment sweep, six
 responder group sizes (5 % to 50 % of the population) times one to six sandbag
 layers, each run until its barrier is complete or 12 hours have passed, then
 the flood over each finished barrier height.
@@ -35,16 +39,20 @@ LAYER_M = 0.25                 # sandbag thickness per layer (sec. 3.3: three la
 DEPLOY_WINDOW_S = 12 * 3600.0  # the 12-hour deployment window (sec. 3.3)
 BREACH_Q = (2.0, 5.0, 10.0, 20.0)  # peak unit discharges of the evacuation runs (m^2/s)
 NO_FLOOD = 1.0e9               # hydrograph start of the dry deployment runs
-ST_EXITED = 1                  # agent state: left through an exit (include/fps.h)
+ST_EVAC, ST_EXITED, ST_SHOPPING = 0, 1, 6     # agent states (include/fps.h)
 
 
 def _site(population, seed, n, dx, **kw):
     return I.shopping_centre(n=n, dx=dx, seed=seed, n_evac=population, n_exits=1, **kw)
 
 
-def evacuation_pair(population=1000, seed=5232, n=SITE_N, dx=SITE_DX, q_peak=2.0, duration=1800.0):
-    """Scenario 1 with and without the people's effect on the flood."""
+def evacuation_pair(population=1000, seed=5232, n=SITE_N, dx=SITE_DX, q_peak=2.0, duration=1800.0, doors=True):
+    """Scenario 1 with and without the people's effect on the flood.  doors:
+    the pre-flood flow (sec. 3.2) fills the site from 7 doors during a
+    5-minute spin-up; else the population starts spread uniformly, standing."""
     with_people = _site(population, seed, n, dx, q_peak=q_peak, duration=duration)
+    if doors:
+        with_people = I.add_doors(with_people, seed=seed)
     with_people.name = "evacuation_coupled"
     without = copy.deepcopy(with_people)
     without.desc.np_cap = 0
@@ -54,23 +62,28 @@ def evacuation_pair(population=1000, seed=5232, n=SITE_N, dx=SITE_DX, q_peak=2.0
 
 def run_evacuation(scs, t_max=3600.0, poll_steps=10):
     """Step an ensemble until every evacuee has left or ``t_max``; per member the
-    evacuation time and the largest number of people seen at once in each
-    hazard class (Table 1), polled every ``poll_steps`` steps."""
+    evacuation time, the people inside when the flood reached the site (the
+    evacuees), and the largest number of people seen at once in each hazard
+    class (Table 1), polled every ``poll_steps`` steps."""
     ens = fps.Ensemble(scs)
     ens.autotune()
-    n = [len(sc.agents["x"]) for sc in scs]
     q = [float(np.max(sc.hydro_q)) if sc.hydro_q is not None and len(sc.hydro_q) else 0.0 for sc in scs]
-    out = [dict(name=sc.name, evacuees=k, q_peak=qp, t_evacuated=None, peak_class_count=[0] * 5)
-           for sc, k, qp in zip(scs, n, q)]
-    t = 0.0
+    out = [dict(name=sc.name, evacuees=None, q_peak=qp, t_evacuated=None, peak_class_count=[0] * 5,
+                door_entries=0, door_leaves=0) for sc, qp in zip(scs, q)]
+    t = -np.inf
     while t < t_max and any(o["t_evacuated"] is None for o in out):
         ens.step(poll_steps)
         for k, m in enumerate(ens.members):
             d = m.diag()
             t = d["t"]
             o = out[k]
-            o["peak_class_count"] = [max(a, b) for a, b in zip(o["peak_class_count"], d["class_count"])]
-            if o["t_evacuated"] is None and d["state_count"][ST_EXITED] == o["evacuees"]:
+            sc_ = d["state_count"]
+            if d["any_wet"] or d["doors_closed"]:
+                o["peak_class_count"] = [max(a, b) for a, b in zip(o["peak_class_count"], d["class_count"])]
+            if o["evacuees"] is None and (d["doors_closed"] or (d["any_wet"] and sc_[ST_SHOPPING] == 0)):
+                o["evacuees"] = sc_[ST_EVAC] + sc_[ST_EXITED]
+                o["door_entries"], o["door_leaves"] = d["door_entries"], d["door_leaves"]
+            if o["t_evacuated"] is None and o["evacuees"] is not None and sc_[ST_EVAC] + sc_[ST_SHOPPING] == 0:
                 o["t_evacuated"] = d["t"]
     for k, m in enumerate(ens.members):
         d = m.diag()
