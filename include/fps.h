@@ -357,8 +357,10 @@ int fps_ens_set_order(fps_ens* ens, int32_t order);
    duration of the ensemble's whole flood launch on the bound states: one value
    for all scenarios, then each distinct grid size moved by factors of two
    while the launch gets shorter.  The states are not advanced; results do not
-   depend on the choice.  cache_path is accepted and not used (the best values
-   depend on the whole mix of grids).  Synchronises. */
+   depend on the choice.  cache_path (may be NULL): a text file of tuning
+   results shared with fps_autotune; a line for this device's architecture
+   and this mix of grids (the members' sizes in member order) is used instead
+   of timing, and a new result is appended.  Synchronises. */
 int fps_ens_autotune(fps_ens* ens, const char* cache_path);
 /* Average duration of the ensemble's flood-update launch (one launch over
    the tiles of every member) in the current tile shapes: reps back-to-back

@@ -13,6 +13,8 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <sstream>
+#include <string>
 #include <vector>
 
 #include "fps_internal.h"
@@ -42,6 +44,7 @@ struct fps_sim {
     int32_t* line;
     int32_t* stats;
     int32_t* doors;            // door cells, then their destinations (kMaxDoor each)
+    int32_t* csum;             // chunk counts / offsets of the multi-block bin scan
     int32_t line_cap;
     int H;
     int nbins, bsx, bsy, nbx, nby, Rx, Ry;
@@ -80,9 +83,10 @@ struct Engine {
     Scn* scn_d = nullptr;
     int* tile_off_d = nullptr;
     int* agent_off_d = nullptr;
+    int* chunk_off_d = nullptr;
     std::vector<Scn> scn_h;
-    std::vector<int> tile_off_h, agent_off_h;
-    int total_tiles = 0, total_agents = 0, fv_blocks = 0;
+    std::vector<int> tile_off_h, agent_off_h, chunk_off_h;
+    int total_tiles = 0, total_agents = 0, total_chunks = 0, fv_blocks = 0;
     int64_t max_cells = 0;
     int fin_lds_bytes = 0;
     bool any_big = false;
@@ -167,7 +171,7 @@ bool valid_desc(const fps_grid_desc* d, char* why)
 // Per-scenario part of the workspace (offsets from the member's base).
 struct Layout {
     size_t st, partials, wet, h2, qx2, qy2, h1, qx1, qy1, np, bin_count, bin_start, rank, key, perm_u, perm, xy, slot,
-        wmask, line, stats, doors, total;
+        wmask, line, stats, doors, csum, total;
     int64_t nbins_max;
     int32_t line_cap;
 };
@@ -207,13 +211,14 @@ Layout member_layout(const fps_grid_desc* d, int32_t max_agents)
     L.line = take(sizeof(int32_t) * L.line_cap);
     L.stats = take(sizeof(int32_t) * 16);
     L.doors = take(sizeof(int32_t) * 2 * kMaxDoor);
+    L.csum = take(max_agents > 0 ? sizeof(int32_t) * (size_t)(L.nbins_max / kChunkBins + 2) : 0);
     L.total = o;
     return L;
 }
 
 size_t engine_header_bytes(int S)
 {
-    return align256(sizeof(Scn) * S) + align256(sizeof(int) * (S + 1)) * 2;
+    return align256(sizeof(Scn) * S) + align256(sizeof(int) * (S + 1)) * 3;
 }
 
 template <class T>
@@ -253,6 +258,7 @@ fps_sim* new_member(Engine* e, int idx, const fps_grid_desc* d, const fps_ped_pa
     s->line = at<int32_t>(base, L.line);
     s->stats = at<int32_t>(base, L.stats);
     s->doors = at<int32_t>(base, L.doors);
+    s->csum = at<int32_t>(base, L.csum);
     s->line_cap = L.line_cap;
     s->H = fv_rows_per_wave(d->nx, d->ny);
     s->bsx = std::max(1, (int)std::ceil(P.r_cut / d->dx - 1e-9));
@@ -350,7 +356,7 @@ void fill_scn(const fps_sim* s, Scn& c)
     BinParams& b = c.bins;
     b.x = s->x; b.y = s->y; b.state = s->state; b.role = s->role;
     b.bin_count = s->bin_count; b.bin_start = s->bin_start; b.rank = s->rank; b.key = s->key;
-    b.perm_u = s->perm_u; b.perm = s->perm; b.xy = s->xy; b.slot = s->slot; b.np = s->np;
+    b.perm_u = s->perm_u; b.perm = s->perm; b.xy = s->xy; b.slot = s->slot; b.np = s->np; b.csum = s->csum;
     b.na = s->na; b.nbins = s->nbins; b.nx = s->G.nx; b.ny = s->G.ny;
     b.bsx = s->bsx; b.bsy = s->bsy; b.nbx = s->nbx;
     b.dx = (float)s->G.dx; b.dy = (float)s->G.dy;
@@ -360,7 +366,10 @@ void fill_scn(const fps_sim* s, Scn& c)
     r.bags_per = s->bags_per; r.t_bag = s->t_bag; r.t_last = s->t_last;
 
     c.na = s->na;
-    c.inline_place = s->na <= kInlinePlace;
+    // many bins: scanned by many blocks, and the agents placed by the placement kernels
+    const bool mb = s->na > 0 && s->nbins > kMbScanBins;
+    b.nchunk = mb ? (s->nbins + kChunkBins - 1) / kChunkBins : 0;
+    c.inline_place = s->na <= kInlinePlace && !mb;
     c.lds_bins = c.inline_place && s->na > 0 && s->nbins <= kLdsScanBins &&
                  (int64_t)s->nbins + 1 + s->na <= kLdsBinWords;
     c.ped.need_rank = !c.lds_bins;       // the LDS binning counts the keys itself
@@ -379,6 +388,7 @@ int upload(Engine* e)
     if (!e->dirty) return FPS_OK;
     e->tile_off_h.assign(e->S + 1, 0);
     e->agent_off_h.assign(e->S + 1, 0);
+    e->chunk_off_h.assign(e->S + 1, 0);
     e->scn_h.resize(e->S);
     e->max_cells = 0;
     e->any_big = false;
@@ -390,7 +400,8 @@ int upload(Engine* e)
         e->tile_off_h[k + 1] = e->tile_off_h[k] + e->scn_h[k].fv.ntiles;
         e->agent_off_h[k + 1] = e->agent_off_h[k] + (s->na + kPedBlock - 1) / kPedBlock * kPedBlock;
         e->max_cells = std::max(e->max_cells, (int64_t)s->G.nx * s->G.ny);
-        e->any_big = e->any_big || s->na > kInlinePlace;
+        e->chunk_off_h[k + 1] = e->chunk_off_h[k] + e->scn_h[k].bins.nchunk;
+        e->any_big = e->any_big || (s->na > 0 && !e->scn_h[k].inline_place);
         e->any_doors = e->any_doors || e->scn_h[k].ped.n_door > 0;
         if (e->scn_h[k].lds_bins)
             e->fin_lds_bytes = std::max(e->fin_lds_bytes, (int)(sizeof(int) * (s->nbins + 1 + s->na)));
@@ -398,11 +409,14 @@ int upload(Engine* e)
     HIPCHK_E(e, prepare_finalize(e->fin_lds_bytes));
     e->total_tiles = e->tile_off_h[e->S];
     e->total_agents = e->agent_off_h[e->S];
+    e->total_chunks = e->chunk_off_h[e->S];
     e->fv_blocks = fv_blocks_for_tiles(e->total_tiles);
     HIPCHK_E(e, hipMemcpyAsync(e->scn_d, e->scn_h.data(), sizeof(Scn) * e->S, hipMemcpyHostToDevice, e->stream));
     HIPCHK_E(e, hipMemcpyAsync(e->tile_off_d, e->tile_off_h.data(), sizeof(int) * (e->S + 1),
                                hipMemcpyHostToDevice, e->stream));
     HIPCHK_E(e, hipMemcpyAsync(e->agent_off_d, e->agent_off_h.data(), sizeof(int) * (e->S + 1),
+                               hipMemcpyHostToDevice, e->stream));
+    HIPCHK_E(e, hipMemcpyAsync(e->chunk_off_d, e->chunk_off_h.data(), sizeof(int) * (e->S + 1),
                                hipMemcpyHostToDevice, e->stream));
     HIPCHK_E(e, hipStreamSynchronize(e->stream));
     e->dirty = false;
@@ -416,6 +430,8 @@ Batch batch_of(const Engine* e, int s_only = -1)
     b.scn = e->scn_d;
     b.tile_off = e->tile_off_d;
     b.agent_off = e->agent_off_d;
+    b.chunk_off = e->chunk_off_d;
+    b.total_chunks = e->total_chunks;
     b.S = e->S;
     b.total_tiles = e->total_tiles;
     b.total_agents = e->total_agents;
@@ -489,7 +505,9 @@ int step_launches(Engine* e, hipStream_t st, KernelEvents* K)
         rec(1, 1);
     }
     rec(2, 0);
+    if (e->total_chunks > 0) HIPCHK_E(e, launch_bin_chunk_sum(b, st));
     HIPCHK_E(e, launch_finalize(b, 0, 0, e->S, st));
+    if (e->total_chunks > 0) HIPCHK_E(e, launch_bin_chunk_scan(b, st));
     rec(2, 1);
     if (e->any_big) {
         rec(3, 0);
@@ -632,21 +650,87 @@ int current_arch(char* arch, size_t n)
     return 0;
 }
 
+// one line of a tuning cache file (false at the end of the file)
+bool read_line(FILE* f, std::string& line)
+{
+    line.clear();
+    int c;
+    while ((c = fgetc(f)) != EOF && c != '\n') line.push_back((char)c);
+    return c != EOF || !line.empty();
+}
+
+bool valid_rows(int H) { return H >= 1 && H <= 64 && !(H & (H - 1)); }
+
+// a grid size as one key: nx in the upper 32 bits, ny in the lower
+int64_t size_key(int nx, int ny) { return (int64_t)nx << 32 | (uint32_t)ny; }
+
+// Cache lines of one grid: "<arch> <nx> <ny> <rows> <ms>"; the last match wins.
 bool cache_lookup(const char* path, const char* arch, int nx, int ny, int* H, double* ms)
 {
     if (!path) return false;
     FILE* f = fopen(path, "r");
     if (!f) return false;
-    char a[64];
-    int cx, cy, ch;
-    double cm;
+    std::string line;
     bool found = false;
-    while (fscanf(f, "%63s %d %d %d %lf", a, &cx, &cy, &ch, &cm) == 5)
-        if (!strcmp(a, arch) && cx == nx && cy == ny && ch >= 1 && ch <= 64 && !(ch & (ch - 1))) {
+    while (read_line(f, line)) {
+        std::istringstream in(line);
+        std::string a;
+        int cx, cy, ch;
+        double cm;
+        if ((in >> a >> cx >> cy >> ch >> cm) && a == arch && cx == nx && cy == ny && valid_rows(ch)) {
             *H = ch;
             *ms = cm;
             found = true;
         }
+    }
+    fclose(f);
+    return found;
+}
+
+// An ensemble's mix of grids: FNV-1a over the members' (nx, ny) in member order.
+uint64_t mix_key(const Engine* e)
+{
+    uint64_t h = 1469598103934665603ull;
+    for (const fps_sim* s : e->m)
+        for (int v : {s->G.nx, s->G.ny})
+            for (int b = 0; b < 4; ++b) {
+                h ^= (uint64_t)((uint32_t)v >> (8 * b) & 0xffu);
+                h *= 1099511628211ull;
+            }
+    return h;
+}
+
+// Cache lines of an ensemble: "<arch> ens <mix key, hex> <n sizes> (<nx> <ny> <rows>)... <ms>".
+bool ens_cache_lookup(const char* path, const char* arch, uint64_t key, std::vector<int64_t>& sizes,
+                      std::vector<int>& rows)
+{
+    if (!path) return false;
+    FILE* f = fopen(path, "r");
+    if (!f) return false;
+    std::string line;
+    bool found = false;
+    while (read_line(f, line)) {
+        std::istringstream in(line);
+        std::string a, tag;
+        uint64_t k = 0;
+        int n = 0;
+        if (!(in >> a >> tag >> std::hex >> k >> std::dec >> n) || a != arch || tag != "ens" || k != key || n < 1)
+            continue;
+        std::vector<int64_t> sz;
+        std::vector<int> hs;
+        bool ok = true;
+        for (int i = 0; i < n && ok; ++i) {
+            int cx, cy, ch;
+            ok = (in >> cx >> cy >> ch) && valid_rows(ch);
+            sz.push_back(size_key(cx, cy));
+            hs.push_back(ch);
+        }
+        if (ok) {
+            sizes = sz;
+            rows = hs;
+            found = true;
+        }
+    }
     fclose(f);
     return found;
 }
@@ -746,6 +830,8 @@ int build_engine(Engine* e, int32_t S, const fps_grid_desc* descs, const fps_ped
     e->tile_off_d = at<int>(ws, o);
     o += align256(sizeof(int) * (S + 1));
     e->agent_off_d = at<int>(ws, o);
+    o += align256(sizeof(int) * (S + 1));
+    e->chunk_off_d = at<int>(ws, o);
     o += align256(sizeof(int) * (S + 1));
     for (int k = 0; k < S; ++k) {
         fps_ped_params P;
@@ -934,11 +1020,25 @@ int fps_ens_set_flux(fps_ens* e, int32_t flux)
 
 int fps_ens_autotune(fps_ens* e, const char* cache_path)
 {
-    (void)cache_path;    // the best heights depend on the whole mix of grids, not on one size
     if (!e) return fail(nullptr, FPS_E_INVALID, "fps_ens_autotune: ens is NULL");
     for (fps_sim* s : e->m)
         if (!s->fields_bound) return efail(e, FPS_E_STATE, "fps_ens_autotune: scenario %d: fields not bound", s->idx);
     HIPCHK_E(e, hipStreamSynchronize(e->stream));
+    // the best heights depend on the whole mix of grids: the cache is keyed by it
+    char arch[64] = "unknown";
+    if (current_arch(arch, sizeof(arch)) != 0) return efail(e, FPS_E_DEVICE, "no HIP device");
+    const uint64_t key = mix_key(e);
+    std::vector<int64_t> c_sizes;
+    std::vector<int> c_rows;
+    if (ens_cache_lookup(cache_path, arch, key, c_sizes, c_rows)) {
+        for (fps_sim* s : e->m) {
+            const int64_t k = size_key(s->G.nx, s->G.ny);
+            for (size_t i = 0; i < c_sizes.size(); ++i)
+                if (c_sizes[i] == k) s->H = c_rows[i];
+            mark_dirty(s);
+        }
+        return FPS_OK;
+    }
     // The flood update of an ensemble is one launch over the tiles of every
     // member, which fills the chip: tune the rows per wave for that launch's
     // duration, not for each member alone (alone, a small grid is latency
@@ -967,22 +1067,22 @@ int fps_ens_autotune(fps_ens* e, const char* cache_path)
         }
     }
     set_all(best_h);
-    std::vector<int> sizes;      // distinct grid sizes, as nx * 65536 + ny
+    std::vector<int64_t> sizes;      // distinct grid sizes (size_key)
     for (fps_sim* s : e->m) {
-        const int key = s->G.nx * 65536 + s->G.ny;
+        const int64_t key = size_key(s->G.nx, s->G.ny);
         if (std::find(sizes.begin(), sizes.end(), key) == sizes.end()) sizes.push_back(key);
     }
     if (sizes.size() > 1) {
         for (int pass = 0; pass < 2; ++pass) {
             bool moved = false;
-            for (int key : sizes) {
+            for (int64_t key : sizes) {
                 int cur_h = 0;
                 for (fps_sim* s : e->m)
-                    if (s->G.nx * 65536 + s->G.ny == key) cur_h = s->H;
+                    if (size_key(s->G.nx, s->G.ny) == key) cur_h = s->H;
                 for (int H : {cur_h * 2, cur_h / 2}) {
                     if (H < 1 || H > 64) continue;
                     for (fps_sim* s : e->m)
-                        if (s->G.nx * 65536 + s->G.ny == key) {
+                        if (size_key(s->G.nx, s->G.ny) == key) {
                             s->H = H;
                             mark_dirty(s);
                         }
@@ -995,13 +1095,27 @@ int fps_ens_autotune(fps_ens* e, const char* cache_path)
                         moved = true;
                     }
                     for (fps_sim* s : e->m)
-                        if (s->G.nx * 65536 + s->G.ny == key) {
+                        if (size_key(s->G.nx, s->G.ny) == key) {
                             s->H = cur_h;
                             mark_dirty(s);
                         }
                 }
             }
             if (!moved) break;
+        }
+    }
+    if (cache_path) {
+        FILE* f = fopen(cache_path, "a");
+        if (f) {
+            fprintf(f, "%s ens %llx %d", arch, (unsigned long long)key, (int)sizes.size());
+            for (int64_t k : sizes) {
+                int h = 1;
+                for (fps_sim* s : e->m)
+                    if (size_key(s->G.nx, s->G.ny) == k) h = s->H;
+                fprintf(f, " %d %d %d", (int)(k >> 32), (int)(uint32_t)k, h);
+            }
+            fprintf(f, " %.6f\n", (double)best);
+            fclose(f);
         }
     }
     // the timing launches wrote scratch partials and the wetness flags

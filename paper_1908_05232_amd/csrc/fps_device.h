@@ -177,6 +177,35 @@ __device__ inline void block_scan_bins(const BinParams& b)
     __syncthreads();
 }
 
+// The middle step of the multi-block bin scan, by the scenario's end-of-step
+// block: the chunk counts (written by the chunk-count launch) become their
+// exclusive offsets in place, one value per thread per round, and the total
+// closes the bin starts.
+__device__ inline void block_scan_chunks(const BinParams& b)
+{
+    __shared__ int wtot[kScanThreads / kWave];
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x >> 6;
+    int carry = 0;
+    for (int base = 0; base < b.nchunk; base += kScanThreads) {
+        const int i = base + (int)threadIdx.x;
+        const int v = i < b.nchunk ? b.csum[i] : 0;
+        const int incl = wave_inclusive_scan(v);
+        if (lane == kWave - 1) wtot[wid] = incl;
+        __syncthreads();
+        int wbase = 0, total = 0;
+        for (int w = 0; w < kScanThreads / kWave; ++w) {
+            const int x = wtot[w];
+            wbase += w < wid ? x : 0;
+            total += x;
+        }
+        if (i < b.nchunk) b.csum[i] = carry + wbase + incl - v;
+        carry += total;
+        __syncthreads();      // wtot is rewritten by the next round
+    }
+    if (threadIdx.x == 0) b.bin_start[b.nbins] = carry;
+    __syncthreads();
+}
+
 // Placement of the agents into their bins by rank, then the stable order: an
 // agent's final slot counts the smaller ids of its own bin.  Whole-grid
 // version, in two kernels (one thread per agent).

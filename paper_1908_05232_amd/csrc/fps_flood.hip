@@ -760,7 +760,8 @@ __device__ double wave_hydro_integral(int nh, double tk, double qk, double a, do
 // inflow depth, applies the sandbag drops of the step to the barrier line
 // (sec. 2.4) and, for scenarios binned in global memory, scans the histogram
 // of the new agent bins (and, for small agent counts, places the agents in bin
-// order).  Mode 1 only recomputes the time step and mass of the current state.
+// order), or, for scenarios with many bins, the chunk counts of the
+// multi-block scan.  Mode 1 only recomputes the time step and mass of the current state.
 template <bool kOne>
 __global__ __launch_bounds__(kScanThreads) void finalize_kernel(Batch B, int mode, int s_first)
 {
@@ -948,8 +949,12 @@ __global__ __launch_bounds__(kScanThreads) void finalize_kernel(Batch B, int mod
         reinterpret_cast<uint32_t*>(gst)[cw] = reinterpret_cast<const uint32_t*>(&sst)[cw];
     if (mode == 0 && na > 0 && !lds_bins) {
         const BinParams bp = S.bins;
-        block_scan_bins(bp);
-        if (inline_place) inline_bins_place(bp);
+        if (bp.nchunk > 0) {
+            block_scan_chunks(bp);      // the chunk scans follow in a launch of their own
+        } else {
+            block_scan_bins(bp);
+            if (inline_place) inline_bins_place(bp);
+        }
     }
 }
 

@@ -32,6 +32,8 @@ constexpr int kLdsScanBins = 16 * kScanThreads;   // bins the LDS binning scans 
 constexpr int kWetSlots = 64;          // wetness flags of a flood update, one per group of blocks
 constexpr int kWetStride = 32;         // ints between flags (one 128-byte line each)
 constexpr int kMaxDoor = 16;           // entrance doors of the pre-flood flow
+constexpr int kChunkBins = 4096;       // bins per block of the multi-block bin scan (256 threads x 16)
+constexpr int kMbScanBins = 32768;     // scenarios with more bins scan them with many blocks
 
 // Scalars that live in device memory so that n steps run without the host.
 struct DevState {
@@ -143,7 +145,9 @@ struct BinParams {
     float2* xy;
     int32_t* slot;
     int32_t* np;
+    int32_t* csum;     // multi-block scan: per chunk of kChunkBins bins its count, then its offset; [nchunk]: active flag
     int na, nbins, nx, ny, bsx, bsy, nbx;
+    int nchunk;        // chunks of the multi-block scan (0: the bins are scanned by one block)
     float dx, dy;
 };
 
@@ -163,8 +167,9 @@ struct Batch {
     const Scn* scn;
     const int* tile_off;   // [S+1] prefix of flood tiles (waves) per scenario
     const int* agent_off;  // [S+1] prefix of agents per scenario
+    const int* chunk_off;  // [S+1] prefix of multi-block bin-scan chunks per scenario
     int S;
-    int total_tiles, total_agents;
+    int total_tiles, total_agents, total_chunks;
     int fv_blocks;         // launched flood blocks: a multiple of 8 covering total_tiles
     int fin_lds_bytes;     // dynamic LDS of the finalize launch (LDS binning)
     int s_only;            // >= 0: restrict the flood launch to one scenario (tuning)
@@ -190,6 +195,8 @@ int ped_lanes(int64_t total_agents);     // lanes per agent of the pedestrian st
 hipError_t launch_doors(const Batch& b, hipStream_t s);    // entries of the pre-flood flow, one block per scenario
 hipError_t launch_count_state(const uint8_t* state, int na, int value, int32_t* out, hipStream_t s);
 hipError_t launch_bin_place_all(const Batch& b, hipStream_t s);
+hipError_t launch_bin_chunk_sum(const Batch& b, hipStream_t s);    // multi-block scan: chunk counts
+hipError_t launch_bin_chunk_scan(const Batch& b, hipStream_t s);   // multi-block scan: bin starts
 hipError_t launch_bin_sort_all(const Batch& b, hipStream_t s);
 hipError_t launch_bin_keys(const BinParams& b, hipStream_t s);   // keys + ranks from positions
 hipError_t launch_bin_scan(const BinParams& b, hipStream_t s);

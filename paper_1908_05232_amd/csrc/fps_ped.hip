@@ -697,6 +697,104 @@ __global__ __launch_bounds__(kPedBlock) void bin_sort_all_kernel(Batch B)
     }
 }
 
+// --- multi-block bin scan (scenarios with more than kMbScanBins bins) --------
+// Instead of one block per scenario walking all its bins: the count of every
+// chunk of kChunkBins bins (one block each), the exclusive scan of the chunk
+// counts (the scenario's end-of-step block, which also writes the total), and
+// the scan of every chunk from its offset (one block each), which clears the
+// histogram behind it.  Integer sums: the bin starts are those of the
+// one-block scan.  A scenario that does not step (past its end time) keeps
+// its bins: the chunk-count launch records whether it stepped, since the end
+// of the step may mark it inactive before the chunk scan runs.
+constexpr int kChunkThreads = kChunkBins / 16;
+
+__device__ __forceinline__ void chunk_counts(const BinParams& b, int k0, int (&v)[16])
+{
+    if (k0 + 16 <= b.nbins) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int4 w = *reinterpret_cast<const int4*>(b.bin_count + k0 + 4 * q);
+            v[4 * q] = w.x; v[4 * q + 1] = w.y; v[4 * q + 2] = w.z; v[4 * q + 3] = w.w;
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) v[e] = k0 + e < b.nbins ? b.bin_count[k0 + e] : 0;
+    }
+}
+
+__global__ __launch_bounds__(kChunkThreads) void bin_chunk_sum_kernel(Batch B)
+{
+    __shared__ int wt[kChunkThreads / kWave];
+    const int g = blockIdx.x;
+    const int sc = find_scenario(B.chunk_off, B.S, g);
+    const Scn& S = B.scn[sc];
+    const BinParams b = S.bins;
+    const int c = g - B.chunk_off[sc];
+    const int active = S.fv.st->active != 0;
+    if (c == 0 && threadIdx.x == 0) b.csum[b.nchunk] = active;
+    if (!active) return;
+    int v[16];
+    chunk_counts(b, c * kChunkBins + 16 * (int)threadIdx.x, v);
+    int t = 0;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) t += v[e];
+    const int incl = wave_inclusive_scan(t);
+    if ((threadIdx.x & (kWave - 1)) == kWave - 1) wt[threadIdx.x >> 6] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int sum = 0;
+        for (int w = 0; w < kChunkThreads / kWave; ++w) sum += wt[w];
+        b.csum[c] = sum;
+    }
+}
+
+__global__ __launch_bounds__(kChunkThreads) void bin_chunk_scan_kernel(Batch B)
+{
+    __shared__ int wt[kChunkThreads / kWave];
+    const int g = blockIdx.x;
+    const int sc = find_scenario(B.chunk_off, B.S, g);
+    const Scn& S = B.scn[sc];
+    const BinParams b = S.bins;
+    const int c = g - B.chunk_off[sc];
+    if (!b.csum[b.nchunk]) return;
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x >> 6;
+    const int k0 = c * kChunkBins + 16 * (int)threadIdx.x;
+    int v[16];
+    chunk_counts(b, k0, v);
+    const bool full = k0 + 16 <= b.nbins;
+    if (full) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) *reinterpret_cast<int4*>(b.bin_count + k0 + 4 * q) = make_int4(0, 0, 0, 0);
+    } else {
+        for (int e = 0; e < 16; ++e)
+            if (k0 + e < b.nbins) b.bin_count[k0 + e] = 0;
+    }
+    int t = 0;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) t += v[e];
+    const int incl = wave_inclusive_scan(t);
+    if (lane == kWave - 1) wt[wid] = incl;
+    __syncthreads();
+    int run = b.csum[c] + incl - t;
+    for (int w = 0; w < wid; ++w) run += wt[w];
+    if (full) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int4 w;
+            w.x = run; run += v[4 * q];
+            w.y = run; run += v[4 * q + 1];
+            w.z = run; run += v[4 * q + 2];
+            w.w = run; run += v[4 * q + 3];
+            *reinterpret_cast<int4*>(b.bin_start + k0 + 4 * q) = w;
+        }
+    } else {
+        for (int e = 0; e < 16; ++e) {
+            if (k0 + e < b.nbins) b.bin_start[k0 + e] = run;
+            run += v[e];
+        }
+    }
+}
+
 __global__ void count_kernel(BinParams b)
 {
     int a = blockIdx.x * blockDim.x + threadIdx.x;
@@ -826,6 +924,18 @@ hipError_t launch_bin_place_all(const Batch& b, hipStream_t s)
 {
     if (b.total_agents > 0)
         hipLaunchKernelGGL(bin_place_all_kernel, dim3(b.total_agents / kPedBlock), dim3(kPedBlock), 0, s, b);
+    return hipGetLastError();
+}
+hipError_t launch_bin_chunk_sum(const Batch& b, hipStream_t s)
+{
+    if (b.total_chunks > 0)
+        hipLaunchKernelGGL(bin_chunk_sum_kernel, dim3(b.total_chunks), dim3(kChunkThreads), 0, s, b);
+    return hipGetLastError();
+}
+hipError_t launch_bin_chunk_scan(const Batch& b, hipStream_t s)
+{
+    if (b.total_chunks > 0)
+        hipLaunchKernelGGL(bin_chunk_scan_kernel, dim3(b.total_chunks), dim3(kChunkThreads), 0, s, b);
     return hipGetLastError();
 }
 hipError_t launch_bin_sort_all(const Batch& b, hipStream_t s)

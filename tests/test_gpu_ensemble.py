@@ -100,6 +100,30 @@ def test_end_times_stop_scenarios():
     assert all(np.array_equal(x, y) for x, y in zip(f0, ens[0].fields()))
 
 
+def test_stopped_member_keeps_its_chunk_scanned_bins(oracle):
+    """A member with more bins than one block scans (1024^2 cells: the
+    multi-block scan) stops at its end time while the others step on: its
+    bins, taken in its last step, stay those of its agents (the oracle's
+    stable sort), step after step."""
+    big = I.shopping_centre(n=1024, dx=0.25, seed=23, n_evac=3000, q_peak=2.0)
+    scs = [big] + mixed_scenarios()[:2]
+    ens = fps.Ensemble(scs)
+    ens[0].set_end_time(1.0)
+    ens.step(200)
+    d0 = ens[0].diag()
+    assert d0["active"] == 0 and ens.active() == 2
+    P = oracle.make_params(big.desc, big.ped)
+    bs0, perm0 = ens[0].bins()
+    A = ens[0].agents()
+    bs_ref, perm_ref = oracle.build_bins(P, A["x"], A["y"], A["state"])
+    assert np.array_equal(bs0, bs_ref) and np.array_equal(perm0, perm_ref)
+    ens.step(30)
+    bs1, perm1 = ens[0].bins()
+    assert np.array_equal(bs0, bs1) and np.array_equal(perm0, perm1)
+    assert all(np.array_equal(A[k], v) for k, v in ens[0].agents().items())
+    say(f"stopped member: t = {d0['t']:.3f}, {len(perm0)} agents binned, bins unchanged over 30 more steps")
+
+
 def test_dry_steps_skip_the_flood_update(oracle):
     sc = I.shopping_centre(n=128, dx=0.5, seed=21, n_evac=50, t_flood=30.0, q_peak=1.0,
                            duration=60.0)
@@ -136,3 +160,34 @@ def test_ensemble_hll_equals_solo_runs():
             assert np.array_equal(x, y), (k, sc.name)
     with pytest.raises(fps.FpsError):
         ens[0].set_flux(fps.FPS_FLUX_HLLC)
+
+
+def test_ensemble_autotune_cache(tmp_path):
+    """fps_ens_autotune keys its cache by the mix of grids: the first call
+    times and appends one line, a second ensemble of the same mix reads the
+    same rows per wave back without timing, a single-grid line in the same
+    file is still read by fps_autotune, and another mix does not match."""
+    cache = tmp_path / "tiles.txt"
+    scs = mixed_scenarios()
+    sim = fps.Sim(scs[0])
+    rows0, _ = sim.autotune(cache)
+    ens = fps.Ensemble(scs)
+    ens.autotune(cache)
+    rows = [m.rows_per_wave() for m in ens.members]
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 2 and lines[1].split()[1] == "ens"
+    again = fps.Ensemble(scs)
+    again.autotune(cache)
+    assert [m.rows_per_wave() for m in again.members] == rows
+    assert len(cache.read_text().splitlines()) == 2
+    assert fps.Sim(scs[0]).autotune(cache)[0] == rows0
+    other = fps.Ensemble(scs[:2])
+    other.autotune(cache)
+    assert len(cache.read_text().splitlines()) == 3
+    again.step(40)
+    ref = fps.Ensemble(scs)
+    ref.step(40)
+    for a, b in zip(again.members, ref.members):
+        for x, y in zip(a.fields(), b.fields()):
+            assert np.array_equal(x, y)
+    say(f"ensemble rows per wave {rows}, cached")

@@ -22,14 +22,15 @@ def recount(sc, A):
     return cnt.reshape(d.ny, d.nx)
 
 
-@pytest.mark.parametrize("which", ["cfg1", "one", "centre", "wide", "big"])
+@pytest.mark.parametrize("which", ["cfg1", "one", "centre", "wide", "big", "chunks", "chunks_big"])
 def test_bins_and_counts_bit_exact(oracle, which):
     """The bins after the step against the oracle's stable counting sort:
     the one-block LDS binning (cfg1, one agent, centre), the global histogram
     scanned by the end-of-step block which also places the agents (wide:
-    22,500 bins, more than the LDS binning takes, and 3,000 agents), and the
+    22,500 bins, more than the LDS binning takes, and 3,000 agents), the
     global scan with the placement kernels (big: 9,000 agents, more than the
-    end-of-step block places itself)."""
+    end-of-step block places itself), and the multi-block scan (1024^2 cells:
+    65,536 bins in 16 chunks, with 3,000 and 12,000 agents)."""
     if which == "cfg1":
         sc = I.cfg1_dam_break(n_ped=400)
         checkpoints = (0, 5, 60)
@@ -42,9 +43,15 @@ def test_bins_and_counts_bit_exact(oracle, which):
     elif which == "wide":
         sc = I.shopping_centre(n=600, dx=0.25, seed=19, n_evac=3000)
         checkpoints = (0, 10, 100)
-    else:
+    elif which == "big":
         sc = I.shopping_centre(n=600, dx=0.25, seed=19, n_evac=9000)
         checkpoints = (0, 10, 100)
+    elif which == "chunks":
+        sc = I.shopping_centre(n=1024, dx=0.25, seed=23, n_evac=3000)
+        checkpoints = (0, 1, 10, 100)
+    else:
+        sc = I.shopping_centre(n=1024, dx=0.25, seed=23, n_evac=12000)
+        checkpoints = (0, 1, 10, 100)
     sim = fps.Sim(sc)
     P = oracle.make_params(sc.desc, sc.ped)
     done = 0
