@@ -148,7 +148,13 @@ int fps_set_hydrograph(fps_sim* sim, const double* t, const double* q, int32_t n
 /* Navigation map (sec. 2.1): n_dest distance fields (device, float32
    [n_dest][ny][nx], metres to the nearest cell of that destination, +inf where
    unreachable); destinations [0, n_exit) are exits.  walkable: device uint8
-   [ny][nx], 1 where pedestrians may stand.  Caller-owned, read-only. */
+   [ny][nx], 1 where pedestrians may stand.  Caller-owned, read-only.  The
+   per-cell decisions the step takes from them are derived here, once: the
+   heading of each cell for the first 16 destinations (the neighbour of
+   steepest descent) and whether it lies within the arrival radius, by the
+   same FP32 comparisons the step would make (further destinations are read
+   from the fields at every step), and the obstacles around each cell; call
+   again after changing the contents. */
 int fps_set_navigation(fps_sim* sim, int32_t n_dest, int32_t n_exit, const float* dist,
                        const uint8_t* walkable);
 

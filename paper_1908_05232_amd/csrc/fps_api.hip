@@ -41,6 +41,7 @@ struct fps_sim {
     float2* xy;
     int32_t* slot;
     uint4* wmask;
+    uint8_t* codes;            // heading / arrival codes of up to kCodeDest destinations
     int32_t* line;
     int32_t* stats;
     int32_t* doors;            // door cells, then their destinations (kMaxDoor each)
@@ -50,6 +51,7 @@ struct fps_sim {
     int nbins, bsx, bsy, nbx, nby, Rx, Ry;
     int n_inflow;
     bool use_wmask;
+    bool use_codes;
     double t_end;
     double hyd_t[kMaxHydro], hyd_q[kMaxHydro];   // host copy of the hydrograph
     int hyd_n;
@@ -171,7 +173,7 @@ bool valid_desc(const fps_grid_desc* d, char* why)
 // Per-scenario part of the workspace (offsets from the member's base).
 struct Layout {
     size_t st, partials, wet, h2, qx2, qy2, h1, qx1, qy1, np, bin_count, bin_start, rank, key, perm_u, perm, xy, slot,
-        wmask, line, stats, doors, csum, total;
+        wmask, codes, line, stats, doors, csum, total;
     int64_t nbins_max;
     int32_t line_cap;
 };
@@ -208,6 +210,7 @@ Layout member_layout(const fps_grid_desc* d, int32_t max_agents)
     L.xy = take(sizeof(float2) * na);
     L.slot = take(sizeof(int32_t) * na);
     L.wmask = take(max_agents > 0 ? sizeof(uint4) * nc : 0);
+    L.codes = take(max_agents > 0 ? (size_t)kCodeDest * nc : 0);
     L.line = take(sizeof(int32_t) * L.line_cap);
     L.stats = take(sizeof(int32_t) * 16);
     L.doors = take(sizeof(int32_t) * 2 * kMaxDoor);
@@ -255,6 +258,7 @@ fps_sim* new_member(Engine* e, int idx, const fps_grid_desc* d, const fps_ped_pa
     s->xy = at<float2>(base, L.xy);
     s->slot = at<int32_t>(base, L.slot);
     s->wmask = at<uint4>(base, L.wmask);
+    s->codes = at<uint8_t>(base, L.codes);
     s->line = at<int32_t>(base, L.line);
     s->stats = at<int32_t>(base, L.stats);
     s->doors = at<int32_t>(base, L.doors);
@@ -342,6 +346,7 @@ void fill_scn(const fps_sim* s, Scn& c)
     q.nx = s->G.nx; q.ny = s->G.ny;
     q.bsx = s->bsx; q.bsy = s->bsy; q.nbx = s->nbx; q.nby = s->nby; q.Rx = s->Rx; q.Ry = s->Ry;
     q.use_wmask = s->use_wmask;
+    q.codes = s->codes; q.use_codes = s->use_codes;
     q.dx = (float)s->G.dx; q.dy = (float)s->G.dy; q.eps = (float)s->G.h_dry;
     q.tau = (float)s->P.tau; q.a_over_m = (float)s->P.a_over_m; q.inv_b = (float)(1.0 / s->P.b_range);
     q.two_r = (float)(2.0 * s->P.radius); q.radius = (float)s->P.radius;
@@ -1237,6 +1242,9 @@ int fps_set_navigation(fps_sim* s, int32_t n_dest, int32_t n_exit, const float* 
     s->use_wmask = s->max_agents > 0 && (2 * s->Rx + 1) * (2 * s->Ry + 1) <= kMaskBits;
     if (s->use_wmask)
         HIPCHK(s, launch_wall_mask(walkable, s->wmask, s->G.nx, s->G.ny, s->Rx, s->Ry, s->eng->stream));
+    s->use_codes = s->max_agents > 0 && n_dest <= kCodeDest;
+    if (s->use_codes)
+        HIPCHK(s, launch_nav_codes(dist, n_dest, s->G.nx, s->G.ny, (float)s->P.r_arrive, s->codes, s->eng->stream));
     mark_dirty(s);
     return FPS_OK;
 }

@@ -32,6 +32,7 @@ constexpr int kLdsScanBins = 16 * kScanThreads;   // bins the LDS binning scans 
 constexpr int kWetSlots = 64;          // wetness flags of a flood update, one per group of blocks
 constexpr int kWetStride = 32;         // ints between flags (one 128-byte line each)
 constexpr int kMaxDoor = 16;           // entrance doors of the pre-flood flow
+constexpr int kCodeDest = 16;          // destinations whose direction codes are kept (more: read the distances)
 constexpr int kChunkBins = 4096;       // bins per block of the multi-block bin scan (256 threads x 16)
 constexpr int kMbScanBins = 32768;     // scenarios with more bins scan them with many blocks
 
@@ -108,6 +109,8 @@ struct PedParams {
     const float2* xy;           // positions in bin order
     const int32_t* slot;        // each agent's place in that order
     const uint4* wmask;         // per cell: obstacle cells within r_cut (bit per offset)
+    const uint8_t* codes;       // [n_dest][ny][nx]: heading (bits 0-3) and arrival (bit 4) per destination and cell
+    int use_codes;              // codes valid (n_dest <= kCodeDest); else the step reads the distances
     int32_t* bin_count;         // histogram of the new positions
     int32_t* rank;
     int32_t* key;
@@ -209,6 +212,8 @@ hipError_t launch_hazard(const float* h, const float* qx, const float* qy, float
 hipError_t launch_agent_stats(const uint8_t* state, const uint8_t* cls, int na, int32_t* out13,
                               hipStream_t s);
 hipError_t launch_wall_mask(const uint8_t* walk, uint4* mask, int nx, int ny, int Rx, int Ry,
+                            hipStream_t s);
+hipError_t launch_nav_codes(const float* dist, int n_dest, int nx, int ny, float r_arrive, uint8_t* codes,
                             hipStream_t s);
 // bad2[0]: agents outside the domain; bad2[1]: invalid role / state / destination
 hipError_t launch_check_agents(const float* x, const float* y, const uint8_t* role,

@@ -69,6 +69,30 @@ __device__ __forceinline__ int nearest_exit(const PedParams& p, int ci, int cj)
 
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// The eight neighbour offsets in the tie order of the heading rule (E, N, W, S, NE, NW, SW, SE),
+// packed two bits an offset (offset + 1) so that a run-time index selects one
+// without a table in memory.
+constexpr int kOffX[8] = {1, 0, -1, 0, 1, -1, -1, 1};
+constexpr int kOffY[8] = {0, 1, 0, -1, 1, 1, -1, -1};
+constexpr uint32_t pack_offsets(const int (&o)[8])
+{
+    uint32_t v = 0;
+    for (int k = 0; k < 8; ++k) v |= (uint32_t)(o[k] + 1) << (2 * k);
+    return v;
+}
+constexpr uint32_t kOffXPacked = pack_offsets(kOffX), kOffYPacked = pack_offsets(kOffY);
+__device__ __forceinline__ int off_of(uint32_t packed, int k) { return (int)((packed >> (2 * k)) & 3u) - 1; }
+
+// Heading and arrival codes of a destination's distance field (sec. 2.1 navigation):
+// the decisions the pedestrian step takes from the field at a cell, taken
+// once per cell when the navigation map is set.  Bits 0-3: the neighbour to
+// head for (0-7 in the order above: the first of the smallest distances
+// below the cell's own), 8 for the cell's own centre (the destination, at
+// distance 0), 15 for none; bit 4: the distance is within the arrival
+// radius.  The FP32 comparisons are those the step would make, in the same
+// order, so the decisions are the same.
+constexpr int kCodeNone = 15, kCodeHere = 8, kCodeArrive = 16;
+
 // Repulsion of one neighbour or obstacle point at offset (rx, ry) from the
 // agent: A/m exp((r0 - d)/B) along the unit offset, zero outside (0, r_cut).
 __device__ __forceinline__ void repel(const PedParams& p, float rx, float ry, float r0, float& fx, float& fy)
@@ -244,45 +268,58 @@ __device__ void agent_step(const PedParams& p, const AgentRec& rec, const float*
         seg0[r] = s0;
         seg1[r] = ok ? s1 : s0;
     }
-    // the direction from the nine distances of the destination field: their
-    // loads go out before the wait for the cell's flood state (the hazard
-    // class below), so that they travel in the same round as the cell's
-    const int offx[8] = {1, 0, -1, 0, 1, -1, -1, 1};
-    const int offy[8] = {0, 1, 0, -1, 1, 1, -1, -1};
-    // a 32 x 32 -> 64-bit product: the 64 x 64 one leaves its upper addend
+    // the direction: from the cell's heading code of the destination (one
+    // byte), or, for destinations beyond the coded ones, from the nine
+    // distances of its field; the loads go out before the wait for the cell's
+    // flood state (the hazard class below), so that they travel in the same
+    // round as the cell's.
+    // A 32 x 32 -> 64-bit product: the 64 x 64 one leaves its upper addend
     // undefined, and the register chosen for it can be a load still in flight
-    const float* D = p.dist + (uint64_t)(uint32_t)(moving ? dest : 0) * (uint64_t)(uint32_t)nc;
+    const uint64_t doff = (uint64_t)(uint32_t)(moving ? dest : 0) * (uint64_t)(uint32_t)nc;
+    const float* D = p.dist + doff;
+    const uint8_t* K = p.codes + doff;
     float ex = 0.0f, ey = 0.0f;    // desired direction
     if (moving) {
-        float dk[8];
+        bool has_target;
+        int ti, tj;
+        if (p.use_codes) {
+            const int code = K[c] & 15;
+            has_target = code <= kCodeHere;
+            const bool here_c = code == kCodeHere;
+            ti = here_c ? ci : ci + off_of(kOffXPacked, code & 7);
+            tj = here_c ? cj : cj + off_of(kOffYPacked, code & 7);
+        } else {
+            float dk[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int qi = ci + offx[k], qj = cj + offy[k];
-            const bool in = qi >= 0 && qj >= 0 && qi < p.nx && qj < p.ny;
-            const float val = D[(size_t)clampi(qj, 0, p.ny - 1) * p.nx + clampi(qi, 0, p.nx - 1)];
-            dk[k] = in ? val : __builtin_inff();
-        }
-        const float here = D[c];
-        // steepest descent: the first of the smallest neighbour distances
-        // below the agent's own; on the destination (distance 0) the target
-        // is the agent's cell.  Selected without a branch on the agent's own
-        // distance (which would hold the other eight loads back until it
-        // arrives) and with the offsets as constants (no offset table read).
-        float best = here;
-        int box = 0, boy = 0;
-        bool found = false;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            if (dk[k] < best) {
-                best = dk[k];
-                box = offx[k];
-                boy = offy[k];
-                found = true;
+            for (int k = 0; k < 8; ++k) {
+                const int qi = ci + kOffX[k], qj = cj + kOffY[k];
+                const bool in = qi >= 0 && qj >= 0 && qi < p.nx && qj < p.ny;
+                const float val = D[(size_t)clampi(qj, 0, p.ny - 1) * p.nx + clampi(qi, 0, p.nx - 1)];
+                dk[k] = in ? val : __builtin_inff();
             }
+            const float here = D[c];
+            // steepest descent: the first of the smallest neighbour distances
+            // below the agent's own; on the destination (distance 0) the target
+            // is the agent's cell.  Selected without a branch on the agent's own
+            // distance (which would hold the other eight loads back until it
+            // arrives) and with the offsets as constants (no offset table read).
+            float best = here;
+            int box = 0, boy = 0;
+            bool found = false;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                if (dk[k] < best) {
+                    best = dk[k];
+                    box = kOffX[k];
+                    boy = kOffY[k];
+                    found = true;
+                }
+            }
+            const bool at_goal = here == 0.0f;
+            has_target = at_goal || found;
+            ti = at_goal ? ci : ci + box;
+            tj = at_goal ? cj : cj + boy;
         }
-        const bool at_goal = here == 0.0f;
-        const bool has_target = at_goal || found;
-        const int ti = at_goal ? ci : ci + box, tj = at_goal ? cj : cj + boy;
         if (has_target) {
             float tx = ((float)ti + 0.5f) * p.dx - x, ty = ((float)tj + 0.5f) * p.dy - y;
             float len2 = tx * tx + ty * ty;
@@ -408,8 +445,18 @@ __device__ void agent_step(const PedParams& p, const AgentRec& rec, const float*
         const uint8_t w_x = p.walk[(size_t)cj * nxs + ix];      // (ni_try, cj)
         const uint8_t w_xy = p.walk[iy * nxs + ix];             // (ni_try, ny_try)
         const uint8_t w_y = p.walk[iy * nxs + ci];              // (ci, ny_try)
-        const float d_xy = D[iy * nxs + ix], d_x = D[(size_t)cj * nxs + ix];
-        const float d_y = D[iy * nxs + ci], d_0 = D[(size_t)cj * nxs + ci];
+        bool arr_xy, arr_x, arr_y, arr_0;       // arrival at each cell the move may end in
+        if (p.use_codes) {
+            arr_xy = K[iy * nxs + ix] & kCodeArrive;
+            arr_x = K[(size_t)cj * nxs + ix] & kCodeArrive;
+            arr_y = K[iy * nxs + ci] & kCodeArrive;
+            arr_0 = K[(size_t)cj * nxs + ci] & kCodeArrive;
+        } else {
+            arr_xy = D[iy * nxs + ix] <= p.r_arrive;
+            arr_x = D[(size_t)cj * nxs + ix] <= p.r_arrive;
+            arr_y = D[iy * nxs + ci] <= p.r_arrive;
+            arr_0 = D[(size_t)cj * nxs + ci] <= p.r_arrive;
+        }
         const bool okx = in_x && w_x;
         ni = okx ? ni_try : ci;
         if (!okx) {
@@ -423,8 +470,8 @@ __device__ void agent_step(const PedParams& p, const AgentRec& rec, const float*
             yn = y;
             vy = 0.0f;
         }
-        const float d_new = okx ? (oky ? d_xy : d_x) : (oky ? d_y : d_0);
-        if (d_new <= p.r_arrive) {
+        const bool arrive = okx ? (oky ? arr_xy : arr_x) : (oky ? arr_y : arr_0);
+        if (arrive) {
             if (st == FPS_ST_EVAC) {
                 st = FPS_ST_EXITED;
             } else if (st == FPS_ST_TO_STORAGE) {
@@ -863,6 +910,33 @@ __global__ void wall_mask_kernel(const uint8_t* walk, uint4* mask, int nx, int n
     mask[c] = make_uint4(m[0], m[1], m[2], m[3]);
 }
 
+__global__ void nav_code_kernel(const float* __restrict__ dist, int n_dest, int nx, int ny, float r_arrive,
+                                uint8_t* __restrict__ codes)
+{
+    const int64_t nc = (int64_t)nx * ny;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nc * n_dest) return;
+    const int64_t d = g / nc, c = g - d * nc;
+    const int ci = (int)(c % nx), cj = (int)(c / nx);
+    const float* D = dist + d * nc;
+    const float here = D[c];
+    float best = here;
+    int kb = -1;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int qi = ci + kOffX[k], qj = cj + kOffY[k];
+        if (qi < 0 || qj < 0 || qi >= nx || qj >= ny) continue;
+        const float v = D[(int64_t)qj * nx + qi];
+        if (v < best) {
+            best = v;
+            kb = k;
+        }
+    }
+    int code = here == 0.0f ? kCodeHere : kb >= 0 ? kb : kCodeNone;
+    if (here <= r_arrive) code |= kCodeArrive;
+    codes[g] = (uint8_t)code;
+}
+
 __global__ void check_agents_kernel(const float* x, const float* y, const uint8_t* role,
                                     const uint8_t* state, const int32_t* dest, int na, float lx,
                                     float ly, int n_dest, int32_t* bad)
@@ -918,6 +992,15 @@ hipError_t launch_doors(const Batch& b, hipStream_t s)
 hipError_t launch_count_state(const uint8_t* state, int na, int value, int32_t* out, hipStream_t s)
 {
     if (na > 0) hipLaunchKernelGGL(count_state_kernel, dim3(blocks_for(na, 256)), dim3(256), 0, s, state, na, value, out);
+    return hipGetLastError();
+}
+hipError_t launch_nav_codes(const float* dist, int n_dest, int nx, int ny, float r_arrive, uint8_t* codes,
+                            hipStream_t s)
+{
+    const int64_t n = (int64_t)nx * ny * n_dest;
+    if (n > 0)
+        hipLaunchKernelGGL(nav_code_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dist, n_dest, nx,
+                           ny, r_arrive, codes);
     return hipGetLastError();
 }
 hipError_t launch_bin_place_all(const Batch& b, hipStream_t s)

@@ -1,4 +1,5 @@
 """GPU parity of the pedestrian step, binning, counts and barrier write-back."""
+import copy
 import json
 import os
 
@@ -248,3 +249,35 @@ def test_ped_steps_count_agents_outside_the_exits():
         "exited", d1["state_count"][1])
     assert d1["ped_steps"] == expect
     assert d2["ped_steps"] == expect
+
+
+@pytest.mark.parametrize("which", ["centre", "barrier", "doors"])
+def test_heading_codes_equal_distance_reads(which):
+    """The heading and arrival codes derived once per cell (up to 16
+    destinations) take the decisions the step takes from the distance fields
+    themselves: the same scenario with its navigation map padded to 17
+    destinations (beyond the coded ones, so the step reads the fields) walks
+    the same agents bit for bit."""
+    if which == "centre":
+        sc = I.shopping_centre(n=256, dx=0.25, seed=9, n_evac=3000)
+        n = 400
+    elif which == "barrier":
+        sc = I.add_barrier(I.shopping_centre(n=256, dx=0.25, seed=9, n_evac=500, t_flood=1e9),
+                           seed=9, n_resp=150, height=0.4)
+        n = 600
+    else:
+        sc = I.add_doors(I.shopping_centre(n=128, dx=332.0 / 128, seed=5232, n_evac=1000, n_exits=1,
+                                           q_peak=20.0, duration=1800.0))
+        n = 420
+    padded = copy.deepcopy(sc)
+    pad = np.full((17 - sc.dist.shape[0],) + sc.dist.shape[1:], np.inf, np.float32)
+    padded.dist = np.concatenate([sc.dist, pad])
+    a, b = fps.Sim(sc), fps.Sim(padded)
+    a.step(n)
+    b.step(n)
+    A, B = a.agents(), b.agents()
+    for k in A:
+        assert np.array_equal(A[k], B[k]), k
+    for x, y in zip(a.fields(), b.fields()):
+        assert np.array_equal(x, y)
+    say(f"[{which}] {n} steps: coded and field-read headings give the same agents; states {a.diag()['state_count']}")
