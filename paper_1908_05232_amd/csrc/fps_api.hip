@@ -192,7 +192,7 @@ Layout member_layout(const fps_grid_desc* d, int32_t max_agents)
     };
     const size_t na = (size_t)std::max(max_agents, 0);
     L.st = take(sizeof(DevState));
-    L.partials = take(sizeof(double) * 4 * (size_t)fv_tiles(d->nx, d->ny, 1));
+    L.partials = take(sizeof(double) * 4 * (size_t)std::max(fv_tiles(d->nx, d->ny, 1), fv_tiles2(d->nx, d->ny, 1)));
     L.wet = take(sizeof(int32_t) * kWetSlots * kWetStride);
     L.h2 = take(sizeof(float) * nc);
     L.qx2 = take(sizeof(float) * nc);
@@ -316,8 +316,9 @@ void fill_scn(const fps_sim* s, Scn& c)
     p.partials = s->partials;
     p.wet = s->wet;
     p.nx = s->G.nx; p.ny = s->G.ny; p.H = s->H;
-    p.nsx = (s->G.nx + kStrip - 1) / kStrip;
-    p.ntiles = fv_tiles(s->G.nx, s->G.ny, s->H);
+    const bool order2 = s->eng->order2;
+    p.nsx = (s->G.nx + fv_strip(order2) - 1) / fv_strip(order2);
+    p.ntiles = order2 ? fv_tiles2(s->G.nx, s->G.ny, s->H) : fv_tiles(s->G.nx, s->G.ny, s->H);
     for (int k = 0; k < 4; ++k) p.bc[k] = s->G.bc[k];
     p.inflow_side = s->G.inflow_side;
     p.c0 = s->G.inflow_c0;
@@ -1059,18 +1060,26 @@ int fps_ens_autotune(fps_ens* e, const char* cache_path)
             mark_dirty(s);
         }
     };
-    int best_h = 1;
-    float best = 0.0f;
-    for (int H = 1; H <= 64; H <<= 1) {
-        set_all(H);
-        float ms = 0.0f;
-        int rc = time_ensemble_flood(e, reps, &ms);
-        if (rc != FPS_OK) return rc;
-        if (H == 1 || ms < best) {
-            best = ms;
-            best_h = H;
+    // the common height: three interleaved passes over the heights, each
+    // keeping its fastest (neighbouring heights differ by a few per cent,
+    // about as much as one pass drifts with the clock)
+    constexpr int kPasses = 3;
+    float tmin[7] = {};
+    for (int pass = 0; pass < kPasses; ++pass)
+        for (int i = 0; i < 7; ++i) {
+            set_all(1 << i);
+            float ms = 0.0f;
+            int rc = time_ensemble_flood(e, reps, &ms);
+            if (rc != FPS_OK) return rc;
+            if (pass == 0 || ms < tmin[i]) tmin[i] = ms;
         }
-    }
+    int best_h = 1;
+    float best = tmin[0];
+    for (int i = 1; i < 7; ++i)
+        if (tmin[i] < best) {
+            best = tmin[i];
+            best_h = 1 << i;
+        }
     set_all(best_h);
     std::vector<int64_t> sizes;      // distinct grid sizes (size_key)
     for (fps_sim* s : e->m) {
@@ -1446,6 +1455,7 @@ static int set_order(Engine* e, int32_t order, char* err)
                 return (snprintf(err, 512, "scenario %d has a judge region (first order only)", s->idx),
                         FPS_E_STATE);
     e->order2 = order == 2;
+    for (fps_sim* s : e->m) mark_dirty(s);     // the tiles of the march depend on the order
     drop_graph(e);      // the captured launches name the kernels of the old order
     return FPS_OK;
 }

@@ -440,10 +440,19 @@ __global__ __launch_bounds__(kFvBlock) void fv_step_kernel(Batch B)
 // each cell the centred -g/2 (h_w + h_e)(z_e - z_w)), and Heun's two-stage
 // Runge-Kutta step: U1 = U + dt L(U), U' = (U + U1 + dt L(U1)) / 2, with the
 // depth cleanup after each stage and the inflow and friction once after both.
-// A lane updates one cell from its plus-shaped stencil of radius 2 (faces
-// shared with the neighbours are evaluated again by them); the tiles are
-// those of the first-order march, so partials and wetness flags are the same.
+//
+// The march of the first-order update widened to the stencil of radius 2: a
+// wave holds 64 adjacent columns and owns the middle kStrip2 (two halo lanes
+// a side), marching down its rows with a window of three rows in registers.
+// Each row is reconstructed once per direction: in x from the neighbour
+// lanes' cells (DPP moves), in y from the window.  Each face is evaluated
+// once: a lane forms its west face (the east state of the lane below against
+// its own west state) and takes its east face from the lane above; the face
+// below row r is formed when row r is reconstructed and, carried, is the
+// face above row r - 1, which is then complete and updated (one row behind).
 // ---------------------------------------------------------------------------
+constexpr int kStrip2 = kWave - 4;      // output columns of one wave in the second-order march
+
 struct V4 {
     float h, eta, u, v;     // depth, surface elevation, velocities (0 where h <= h_dry)
 };
@@ -453,106 +462,67 @@ __device__ __forceinline__ float minmod(float a, float b)
     return a * b > 0.0f ? (fabsf(a) <= fabsf(b) ? a : b) : 0.0f;
 }
 
-// cell (i, j) with one ghost layer (not both outside); *ghost for ghosts
-__device__ __forceinline__ V4 cell_v4(const Src& s, const FvParams& p, int i, int j, bool& ghost)
+// the velocities and surface of a raw cell (a ghost mirrors the adjacent
+// interior cell: the normal velocity negated at a wall)
+__device__ __forceinline__ V4 v4_of(const FvParams& p, const Cell& c, bool mirror_x, int j)
 {
-    const int ii = min(max(i, 0), p.nx - 1), jj = min(max(j, 0), p.ny - 1);
-    const uint32_t k = (uint32_t)jj * (uint32_t)p.nx + (uint32_t)ii;
     V4 v;
-    v.h = ld(s.h, k);
-    v.eta = v.h + ld(s.z, k);
-    const float r = v.h > p.eps ? rcp(v.h) : 0.0f;
-    v.u = ld(s.qx, k) * r;
-    v.v = ld(s.qy, k) * r;
-    ghost = i != ii || j != jj;
-    if ((i < 0 && p.bc[0] == FPS_BC_WALL) || (i >= p.nx && p.bc[1] == FPS_BC_WALL)) v.u = -v.u;
+    v.h = c.h;
+    v.eta = c.h + c.z;
+    const float r = c.h > p.eps ? rcp(c.h) : 0.0f;
+    v.u = c.qx * r;
+    v.v = c.qy * r;
+    if (mirror_x) v.u = -v.u;
     if ((j < 0 && p.bc[2] == FPS_BC_WALL) || (j >= p.ny && p.bc[3] == FPS_BC_WALL)) v.v = -v.v;
     return v;
 }
 
-// the state of cell (i, j) reconstructed at its face on side sgn (+1 east /
-// north, -1 west / south) of direction dir (0: x, 1: y); b is the cell itself
-__device__ __forceinline__ V4 face_state(const Src& s, const FvParams& p, int i, int j, int dir, float sgn)
+// cell b reconstructed at its two faces in one direction, from its
+// neighbours a (before) and c (after): lo at the face towards a, hi at the
+// face towards c; no slope for a ghost or next to a dry cell
+__device__ __forceinline__ void recon(const FvParams& p, const V4& a, const V4& b, const V4& c, bool ghost,
+                                      V4& lo, V4& hi)
 {
-    bool gb, ga, gc;
-    V4 b = cell_v4(s, p, i, j, gb);
-    if (gb) return b;
-    const V4 a = dir == 0 ? cell_v4(s, p, i - 1, j, ga) : cell_v4(s, p, i, j - 1, ga);
-    const V4 c = dir == 0 ? cell_v4(s, p, i + 1, j, gc) : cell_v4(s, p, i, j + 1, gc);
-    if (!(a.h > p.eps) || !(b.h > p.eps) || !(c.h > p.eps)) return b;
-    const float hf = 0.5f * sgn;
-    b.h += hf * minmod(c.h - b.h, b.h - a.h);
-    b.eta += hf * minmod(c.eta - b.eta, b.eta - a.eta);
-    b.u += hf * minmod(c.u - b.u, b.u - a.u);
-    b.v += hf * minmod(c.v - b.v, b.v - a.v);
-    return b;
+    lo = b;
+    hi = b;
+    if (ghost || !(a.h > p.eps) || !(b.h > p.eps) || !(c.h > p.eps)) return;
+    const float mh = minmod(c.h - b.h, b.h - a.h), me = minmod(c.eta - b.eta, b.eta - a.eta);
+    const float mu = minmod(c.u - b.u, b.u - a.u), mv = minmod(c.v - b.v, b.v - a.v);
+    hi.h += 0.5f * mh;
+    hi.eta += 0.5f * me;
+    hi.u += 0.5f * mu;
+    hi.v += 0.5f * mv;
+    lo.h += -0.5f * mh;
+    lo.eta += -0.5f * me;
+    lo.u += -0.5f * mu;
+    lo.v += -0.5f * mv;
 }
 
 // one face between reconstructed states L and R in the face's normal
-// direction (un, ut: normal and tangential velocity, limited between the
-// neighbours' velocities): flux and, per side, the reconstructed depth, the
-// hydrostatic depth and the face bed
+// direction (un, ut: normal and tangential velocity): flux and, per side, the
+// hydrostatic depth
 template <bool kHll>
 __device__ __forceinline__ void face2(const FvParams& p, float hL, float etaL, float unL, float utL, float hR,
                                       float etaR, float unR, float utR, bool wall, float& F0, float& F1,
-                                      float& F2, float& hsL, float& hsR, float& zL, float& zR)
+                                      float& F2, float& hsL, float& hsR)
 {
-    zL = etaL - hL;
-    zR = etaR - hR;
+    const float zL = etaL - hL, zR = etaR - hR;
     const bool wL = hL > p.eps, wR = hR > p.eps;
     float pL, pR;
     face_flux<kHll>(p, hL, wL ? unL : 0.0f, wL ? utL : 0.0f, zL, hR, wR ? unR : 0.0f, wR ? utR : 0.0f, zR, wall,
                     F0, F1, F2, pL, pR);
-    // the hydrostatic depths back from their pressures is not exact: recompute
+    // the hydrostatic depths themselves (the pressures are their squares)
     const float zf = zL > zR ? zL : zR;
-    float hl = hL - (zf - zL), hr = hR - (zf - zR);
+    const float hl = hL - (zf - zL), hr = hR - (zf - zR);
     hsL = hl > p.eps ? hl : 0.0f;
     hsR = hr > p.eps ? hr : 0.0f;
 }
 
-// dt L(U) at cell (i, j) of state s, and the outflow rate through the
-// transmissive sides of that cell's boundary faces
-template <bool kHll>
-__device__ __forceinline__ void residual2(const Src& s, const FvParams& p, int i, int j, float lx, float ly,
-                                          float& dh, float& dqx, float& dqy, double& vout_rate)
-{
-    float FW0, FW1, FW2, FE0, FE1, FE2, FS0, FS1, FS2, FN0, FN1, FN2;
-    float hsW, hsE, hsS, hsN, zW, zE, zS, zN, d0, d1, d2, d3;
-    // west face: (i-1 east side, i west side)
-    const V4 wl = face_state(s, p, i - 1, j, 0, 1.0f), wr = face_state(s, p, i, j, 0, -1.0f);
-    face2<kHll>(p, wl.h, wl.eta, wl.u, wl.v, wr.h, wr.eta, wr.u, wr.v, i == 0 && p.bc[0] == FPS_BC_WALL,
-                FW0, FW1, FW2, d0, hsW, d1, zW);
-    const V4 er = face_state(s, p, i + 1, j, 0, -1.0f), el = face_state(s, p, i, j, 0, 1.0f);
-    face2<kHll>(p, el.h, el.eta, el.u, el.v, er.h, er.eta, er.u, er.v,
-                i == p.nx - 1 && p.bc[1] == FPS_BC_WALL, FE0, FE1, FE2, hsE, d2, zE, d3);
-    // south and north faces: y is normal
-    const V4 sl = face_state(s, p, i, j - 1, 1, 1.0f), sr = face_state(s, p, i, j, 1, -1.0f);
-    face2<kHll>(p, sl.h, sl.eta, sl.v, sl.u, sr.h, sr.eta, sr.v, sr.u, j == 0 && p.bc[2] == FPS_BC_WALL,
-                FS0, FS1, FS2, d0, hsS, d1, zS);
-    const V4 nr = face_state(s, p, i, j + 1, 1, -1.0f), nl = face_state(s, p, i, j, 1, 1.0f);
-    face2<kHll>(p, nl.h, nl.eta, nl.v, nl.u, nr.h, nr.eta, nr.v, nr.u,
-                j == p.ny - 1 && p.bc[3] == FPS_BC_WALL, FN0, FN1, FN2, hsN, d2, zN, d3);
-    const float hw = wr.h, he = el.h, hS = sr.h, hN = nl.h;
-    const float cx = p.half_g * (he * he - hsE * hsE) - p.half_g * (hw * hw - hsW * hsW) +
-                     p.half_g * (hw + he) * (zE - zW);
-    const float cy = p.half_g * (hN * hN - hsN * hsN) - p.half_g * (hS * hS - hsS * hsS) +
-                     p.half_g * (hS + hN) * (zN - zS);
-    dh = -(lx * (FE0 - FW0) + ly * (FN0 - FS0));
-    dqx = -(lx * ((FE1 - FW1) + cx) + ly * (FN2 - FS2));
-    dqy = -(ly * ((FN1 - FS1) + cy) + lx * (FE2 - FW2));
-    vout_rate = 0.0;
-    if (i == 0 && p.bc[0] == FPS_BC_TRANSMISSIVE) vout_rate -= (double)FW0 * p.dy;
-    if (i == p.nx - 1 && p.bc[1] == FPS_BC_TRANSMISSIVE) vout_rate += (double)FE0 * p.dy;
-    if (j == 0 && p.bc[2] == FPS_BC_TRANSMISSIVE) vout_rate -= (double)FS0 * p.dx;
-    if (j == p.ny - 1 && p.bc[3] == FPS_BC_TRANSMISSIVE) vout_rate += (double)FN0 * p.dx;
-}
-
-// One Runge-Kutta stage of the second-order variant over one tile of the
-// march (lanes 1..kStrip of a wave own a column each; kStage 1: U1 = U + dt
-// L(U) into the stage buffer; kStage 2: U' = (U + U1 + dt L(U1)) / 2 into the
-// other ping-pong buffer, then inflow, friction, volumes and the wave speed).
-// The outflow and clipped volumes of stage 1 are left in the tile's partial
-// slots for stage 2 to add to (each stage counts half).
+// One Runge-Kutta stage of the second-order variant over one tile (kStage 1:
+// U1 = U + dt L(U) into the stage buffer; kStage 2: U' = (U + U1 + dt L(U1))
+// / 2 into the other ping-pong buffer, then inflow, friction, volumes and the
+// wave speed).  The outflow and clipped volumes of stage 1 are left in the
+// tile's partial slots for stage 2 to add to (each stage counts half).
 template <bool kOne, bool kHll, int kStage>
 __global__ __launch_bounds__(kFvBlock) void fv2_stage_kernel(Batch B)
 {
@@ -579,81 +549,158 @@ __global__ __launch_bounds__(kFvBlock) void fv2_stage_kernel(Batch B)
     const Src s0{gmem<const float>(cur ? p.h[1] : p.h[0]), gmem<const float>(cur ? p.qx[1] : p.qx[0]),
                  gmem<const float>(cur ? p.qy[1] : p.qy[0]), gmem(p.z)};
     const Src s1{gmem<const float>(p.h1), gmem<const float>(p.qx1), gmem<const float>(p.qy1), gmem(p.z)};
+    const Src& src = kStage == 1 ? s0 : s1;        // the state the residual is taken of
     const float dt = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, st->dt)));
     const float inc = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, st->inc)));
     const float lx = dt * p.inv_dx, ly = dt * p.inv_dy;
     const int sx = tile % p.nsx, sy = tile / p.nsx;
-    const int i = sx * kStrip - 1 + lane;
+    const int i = sx * kStrip2 - 2 + lane;
+    const int ii = min(max(i, 0), p.nx - 1);
     const int j0 = sy * p.H, j1 = min(j0 + p.H, p.ny);
-    const bool out_lane = lane >= 1 && lane <= kStrip && i < p.nx;
+    const bool out_lane = lane >= 2 && lane < 2 + kStrip2 && i < p.nx;
+    const bool gx = i < 0 || i >= p.nx;       // ghost column (no x slope)
+    const bool mirror_x = (i < 0 && p.bc[0] == FPS_BC_WALL) || (i >= p.nx && p.bc[1] == FPS_BC_WALL);
+    // the west face of this lane's column is a wall face
+    const bool xwall = (i == 0 && p.bc[0] == FPS_BC_WALL) || (i == p.nx && p.bc[1] == FPS_BC_WALL);
     double m_acc = 0.0, vout_acc = 0.0, vclip_acc = 0.0;
     float smax = 0.0f;
     FPS_GLOBAL double* part = gmem(&p.partials[4 * tile]);
-    if (out_lane) {
-        for (int j = j0; j < j1; ++j) {
-            const uint32_t k = (uint32_t)j * (uint32_t)p.nx + (uint32_t)i;
-            float dh, dqx, dqy;
-            double rate;
-            residual2<kHll>(kStage == 1 ? s0 : s1, p, i, j, lx, ly, dh, dqx, dqy, rate);
-            vout_acc += 0.5 * rate * (double)dt;
-            const Src& base = kStage == 1 ? s0 : s1;
-            float h = ld(base.h, k) + dh, qx = ld(base.qx, k) + dqx, qy = ld(base.qy, k) + dqy;
-            if (h < 0.0f) {
-                vclip_acc += 0.5 * (double)(-h);
-                h = 0.0f;
-            }
-            if (!(h > p.eps)) {
-                qx = 0.0f;
-                qy = 0.0f;
-            }
-            if (kStage == 1) {
-                st_at(gmem(p.h1), k, h);
-                st_at(gmem(p.qx1), k, qx);
-                st_at(gmem(p.qy1), k, qy);
-                continue;
-            }
-            float hn = 0.5f * (ld(s0.h, k) + h), qxn = 0.5f * (ld(s0.qx, k) + qx), qyn = 0.5f * (ld(s0.qy, k) + qy);
-            bool inflow = false;
-            if (p.inflow_side == FPS_SIDE_S) inflow = j == 0 && i >= p.c0 && i < p.c1;
-            else if (p.inflow_side == FPS_SIDE_N) inflow = j == p.ny - 1 && i >= p.c0 && i < p.c1;
-            else if (p.inflow_side == FPS_SIDE_W) inflow = i == 0 && j >= p.c0 && j < p.c1;
-            else if (p.inflow_side == FPS_SIDE_E) inflow = i == p.nx - 1 && j >= p.c0 && j < p.c1;
-            if (inflow) hn += inc;
-            if (!(hn > p.eps)) {
-                qxn = 0.0f;
-                qyn = 0.0f;
-            }
-            if (hn > p.eps) {
-                const float r = rcp(hn);
-                float u = qxn * r, v = qyn * r;
-                const float V2 = u * u + v * v;
-                if (V2 > 0.0f) {
-                    // Manning friction, splitting point-implicit (as in the first-order update)
-                    const int npc = ld(gmem<const int32_t>(p.np), k);
-                    const float n = p.n_base + (float)min(npc, p.np_cap) * p.n_base;
-                    const float speed = sqrt_fast(V2);
-                    const float hm13 = __builtin_amdgcn_exp2f(-__builtin_amdgcn_logf(hn) * (1.0f / 3.0f));
-                    const float Cf = p.g * n * n * hm13;
-                    const float Sx = -Cf * u * speed, Sy = -Cf * v * speed;
-                    const float a = dt * Cf * r * rcp(speed);
-                    const float Dx = 1.0f + a * (2.0f * u * u + v * v);
-                    const float Dy = 1.0f + a * (2.0f * v * v + u * u);
-                    float dfx = dt * Sx * rcp(Dx), dfy = dt * Sy * rcp(Dy);
-                    if (fabsf(dfx) > fabsf(qxn)) dfx = -qxn;
-                    if (fabsf(dfy) > fabsf(qyn)) dfy = -qyn;
-                    qxn += dfx;
-                    qyn += dfy;
-                    u = qxn * r;
-                    v = qyn * r;
+
+    // window: rows r - 1, r, r + 1 (raw and derived), two rows in flight
+    Cell cm = load_raw(src, p, ii, j0 - 2), c0 = load_raw(src, p, ii, j0 - 1), cp = load_raw(src, p, ii, j0);
+    Cell pf0 = load_raw(src, p, ii, j0 + 1), pf1 = load_raw(src, p, ii, j0 + 2);
+    V4 vm = v4_of(p, cm, mirror_x, j0 - 2), v0 = v4_of(p, c0, mirror_x, j0 - 1), vp = v4_of(p, cp, mirror_x, j0);
+    // carried from row r - 1: its north state, and its residual but the north face
+    V4 nprev = {};
+    Cell crow = {};                                // raw values of row r - 1 (the stage's base)
+    float Fs0 = 0.0f, Fs1 = 0.0f, Fs2 = 0.0f, hsS = 0.0f, hS = 0.0f, zS = 0.0f, hN = 0.0f, zN = 0.0f;
+    float ex0 = 0.0f, ex1 = 0.0f, ex2 = 0.0f, cx = 0.0f;
+    double rate_x = 0.0;                           // outflow rate through the row's x boundary faces
+    for (int r = j0 - 1; r <= j1; ++r) {
+        // y reconstruction of row r from the window (rows r - 1, r, r + 1)
+        V4 sr, nr;
+        recon(p, vm, v0, vp, r < 0 || r >= p.ny, sr, nr);
+        if (r >= j0) {
+            // the face below row r: north state of row r - 1 against the south state of row r
+            float F0, F1, F2, hsl, hsr;
+            face2<kHll>(p, nprev.h, nprev.eta, nprev.v, nprev.u, sr.h, sr.eta, sr.v, sr.u,
+                        (r == 0 && p.bc[2] == FPS_BC_WALL) || (r == p.ny && p.bc[3] == FPS_BC_WALL), F0, F1,
+                        F2, hsl, hsr);
+            if (r > j0) {
+                // row r - 1 is complete: its north face is this one
+                const int jr = r - 1;
+                const float cy = p.half_g * (hN * hN - hsl * hsl) - p.half_g * (hS * hS - hsS * hsS) +
+                                 p.half_g * (hS + hN) * (zN - zS);
+                const float dh = -(lx * ex0 + ly * (F0 - Fs0));
+                const float dqx = -(lx * (ex1 + cx) + ly * (F2 - Fs2));
+                const float dqy = -(ly * ((F1 - Fs1) + cy) + lx * ex2);
+                if (out_lane) {
+                    const uint32_t k = (uint32_t)jr * (uint32_t)p.nx + (uint32_t)i;
+                    double rate = rate_x;
+                    if (jr == 0 && p.bc[2] == FPS_BC_TRANSMISSIVE) rate -= (double)Fs0 * p.dx;
+                    if (jr == p.ny - 1 && p.bc[3] == FPS_BC_TRANSMISSIVE) rate += (double)F0 * p.dx;
+                    vout_acc += 0.5 * rate * (double)dt;
+                    float h = crow.h + dh, qx = crow.qx + dqx, qy = crow.qy + dqy;
+                    if (h < 0.0f) {
+                        vclip_acc += 0.5 * (double)(-h);
+                        h = 0.0f;
+                    }
+                    if (!(h > p.eps)) {
+                        qx = 0.0f;
+                        qy = 0.0f;
+                    }
+                    if (kStage == 1) {
+                        st_at(gmem(p.h1), k, h);
+                        st_at(gmem(p.qx1), k, qx);
+                        st_at(gmem(p.qy1), k, qy);
+                    } else {
+                        float hn = 0.5f * (ld(s0.h, k) + h), qxn = 0.5f * (ld(s0.qx, k) + qx),
+                              qyn = 0.5f * (ld(s0.qy, k) + qy);
+                        bool inflow = false;
+                        if (p.inflow_side == FPS_SIDE_S) inflow = jr == 0 && i >= p.c0 && i < p.c1;
+                        else if (p.inflow_side == FPS_SIDE_N) inflow = jr == p.ny - 1 && i >= p.c0 && i < p.c1;
+                        else if (p.inflow_side == FPS_SIDE_W) inflow = i == 0 && jr >= p.c0 && jr < p.c1;
+                        else if (p.inflow_side == FPS_SIDE_E) inflow = i == p.nx - 1 && jr >= p.c0 && jr < p.c1;
+                        if (inflow) hn += inc;
+                        if (!(hn > p.eps)) {
+                            qxn = 0.0f;
+                            qyn = 0.0f;
+                        }
+                        if (hn > p.eps) {
+                            const float rr = rcp(hn);
+                            float u = qxn * rr, v = qyn * rr;
+                            const float V2 = u * u + v * v;
+                            if (V2 > 0.0f) {
+                                // Manning friction, splitting point-implicit (as in the first-order update)
+                                const int npc = ld(gmem<const int32_t>(p.np), k);
+                                const float n = p.n_base + (float)min(npc, p.np_cap) * p.n_base;
+                                const float speed = sqrt_fast(V2);
+                                const float hm13 = __builtin_amdgcn_exp2f(-__builtin_amdgcn_logf(hn) * (1.0f / 3.0f));
+                                const float Cf = p.g * n * n * hm13;
+                                const float Sx = -Cf * u * speed, Sy = -Cf * v * speed;
+                                const float a = dt * Cf * rr * rcp(speed);
+                                const float Dx = 1.0f + a * (2.0f * u * u + v * v);
+                                const float Dy = 1.0f + a * (2.0f * v * v + u * u);
+                                float dfx = dt * Sx * rcp(Dx), dfy = dt * Sy * rcp(Dy);
+                                if (fabsf(dfx) > fabsf(qxn)) dfx = -qxn;
+                                if (fabsf(dfy) > fabsf(qyn)) dfy = -qyn;
+                                qxn += dfx;
+                                qyn += dfy;
+                                u = qxn * rr;
+                                v = qyn * rr;
+                            }
+                            const float cel = sqrt_fast(p.g * hn);
+                            smax = fmaxf(smax, fmaxf((fabsf(u) + cel) * p.inv_dx, (fabsf(v) + cel) * p.inv_dy));
+                        }
+                        m_acc += (double)hn;
+                        st_at(gmem(cur ? p.h[0] : p.h[1]), k, hn);
+                        st_at(gmem(cur ? p.qx[0] : p.qx[1]), k, qxn);
+                        st_at(gmem(cur ? p.qy[0] : p.qy[1]), k, qyn);
+                    }
                 }
-                const float cel = sqrt_fast(p.g * hn);
-                smax = fmaxf(smax, fmaxf((fabsf(u) + cel) * p.inv_dx, (fabsf(v) + cel) * p.inv_dy));
             }
-            m_acc += (double)hn;
-            st_at(gmem(cur ? p.h[0] : p.h[1]), k, hn);
-            st_at(gmem(cur ? p.qx[0] : p.qx[1]), k, qxn);
-            st_at(gmem(cur ? p.qy[0] : p.qy[1]), k, qyn);
+            Fs0 = F0;
+            Fs1 = F1;
+            Fs2 = F2;
+            hsS = hsr;
         }
+        if (r >= j0 && r < j1) {
+            // x reconstruction of row r from the neighbour lanes, its west face,
+            // and its east face from the lane above
+            const V4 w{lane_from_below(v0.h), lane_from_below(v0.eta), lane_from_below(v0.u), lane_from_below(v0.v)};
+            const V4 e{lane_from_above(v0.h), lane_from_above(v0.eta), lane_from_above(v0.u), lane_from_above(v0.v)};
+            V4 wr, er;
+            recon(p, w, v0, e, gx, wr, er);
+            const V4 el{lane_from_below(er.h), lane_from_below(er.eta), lane_from_below(er.u), lane_from_below(er.v)};
+            float Fw0, Fw1, Fw2, hsw_l, hsw_r;
+            face2<kHll>(p, el.h, el.eta, el.u, el.v, wr.h, wr.eta, wr.u, wr.v, xwall, Fw0, Fw1, Fw2, hsw_l, hsw_r);
+            const float Fe0 = lane_from_above(Fw0), Fe1 = lane_from_above(Fw1), Fe2 = lane_from_above(Fw2);
+            const float hsE = lane_from_above(hsw_l);
+            const float zW = wr.eta - wr.h, zE = er.eta - er.h;
+            cx = p.half_g * (er.h * er.h - hsE * hsE) - p.half_g * (wr.h * wr.h - hsw_r * hsw_r) +
+                 p.half_g * (wr.h + er.h) * (zE - zW);
+            ex0 = Fe0 - Fw0;
+            ex1 = Fe1 - Fw1;
+            ex2 = Fe2 - Fw2;
+            rate_x = 0.0;
+            if (i == 0 && p.bc[0] == FPS_BC_TRANSMISSIVE) rate_x -= (double)Fw0 * p.dy;
+            if (i == p.nx - 1 && p.bc[1] == FPS_BC_TRANSMISSIVE) rate_x += (double)Fe0 * p.dy;
+            hS = sr.h;
+            zS = sr.eta - sr.h;
+            hN = nr.h;
+            zN = nr.eta - nr.h;
+            crow = c0;
+        }
+        nprev = nr;
+        // advance the window
+        cm = c0;
+        c0 = cp;
+        cp = pf0;
+        pf0 = pf1;
+        if (r + 4 <= j1 + 1) pf1 = load_raw(src, p, ii, r + 4);     // rows past the last one needed stay unread
+        vm = v0;
+        v0 = vp;
+        vp = v4_of(p, cp, mirror_x, r + 2);
     }
     // the two stages' volumes in the tile's partials (stage 1 leaves its
     // outflow and clipped volumes there for stage 2)
@@ -1020,6 +1067,14 @@ int fv_rows_per_wave(int nx, int ny)
     while (H > 4 && nsx * ((ny + H - 1) / H) < 4096) H >>= 1;
     return H;
 }
+
+int fv_tiles2(int nx, int ny, int H)
+{
+    const int64_t nsx = (nx + kStrip2 - 1) / kStrip2;
+    return (int)(nsx * ((ny + H - 1) / H));
+}
+
+int fv_strip(bool order2) { return order2 ? kStrip2 : kStrip; }
 
 int fv_tiles(int nx, int ny, int H)
 {

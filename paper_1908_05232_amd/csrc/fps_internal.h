@@ -184,6 +184,8 @@ struct Batch {
 // launchers (stream-ordered, no synchronisation)
 int fv_blocks_for_tiles(int64_t tiles);
 int fv_tiles(int nx, int ny, int H);
+int fv_tiles2(int nx, int ny, int H);    // tiles of the second-order march (narrower strips)
+int fv_strip(bool order2);               // output columns of one wave of the march
 int fv_rows_per_wave(int nx, int ny);
 hipError_t launch_fv(const Batch& b, hipStream_t s);
 hipError_t launch_fv_scan(const Batch& b, int scenario, int ntiles, hipStream_t s);
