@@ -377,6 +377,27 @@ def headline_section(args, stream):
     return out, sample
 
 
+def stability_section(args, stream):
+    """The pedestrian step with and without the stability rule (varied bodies
+    standing in the flow): 8 scenarios of 1024^2 cells, wet everywhere, with
+    50,000 evacuees each."""
+    import copy
+    import torch
+    from paper_1908_05232_amd import fps, inputs as I
+    scs = I.large_sweep(8, n=1024, n_evac=50000, seed=7)
+    out = {"workload": "large_sweep_8x1024 with 50,000 evacuees each", "agents": 8 * 50000}
+    for tag, members in (("off", scs), ("on", [I.add_bodies(copy.deepcopy(sc), seed=k) for k, sc in enumerate(scs)])):
+        ens = fps.Ensemble(members, stream=stream)
+        ens.step(50)
+        kms = ens.step_profiled(args.profile_steps)
+        out[f"ped_step_ms_rule_{tag}"] = kms[1]
+        out[f"unstable_people_rule_{tag}"] = sum(m.diag()["class_count"][5] for m in ens.members)
+        ens.close()
+        del ens
+        torch.cuda.empty_cache()
+    return out
+
+
 def cache_resident_section(args, stream):
     """The 512^2 shopping centre with 2,000 evacuees: a 12.6 MB working set that
     stays in the caches, so its rate is set by launch and dependency latency."""
@@ -568,6 +589,8 @@ def main():
             log("probe done")
         if not args.no_ensemble:
             out["secondary"]["ensemble"] = ensemble_section(args, stream)
+            out["secondary"]["stability_rule"] = stability_section(args, stream)
+            log("stability rule done")
         if not args.no_surrogate:
             out["secondary"]["surrogate"] = surrogate_section(args)
     if not args.no_cpu:

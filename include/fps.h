@@ -65,7 +65,8 @@ enum {
     FPS_ST_SHOPPING = 6,    /* before the flood: walking to the door it will leave by (fps_set_doors) */
     FPS_ST_OUTSIDE = 7      /* outside the building: a free slot a new pedestrian may enter by (fps_set_doors) */
 };
-enum { FPS_CLS_DRY = 0, FPS_CLS_LOW = 1, FPS_CLS_MEDIUM = 2, FPS_CLS_HIGH = 3, FPS_CLS_HIGHEST = 4 };
+enum { FPS_CLS_DRY = 0, FPS_CLS_LOW = 1, FPS_CLS_MEDIUM = 2, FPS_CLS_HIGH = 3, FPS_CLS_HIGHEST = 4,
+       FPS_CLS_UNSTABLE = 5 /* the stability rule: cannot stand in the flow (speed 0) */ };
 
 /* Grid and flood constants.  Eq. (1)-(2), sec. 2.2; time step rule, sec. 3. */
 typedef struct {
@@ -91,6 +92,21 @@ typedef struct {
     double v_class[5];       /* walking speed per class; [0] unused (dry: agent's base speed) */
     double hr_t[3];          /* class thresholds (0.75, 1.5, 2.5) */
     double pick_s, drop_s;   /* responder waits (s) */
+    /* Stability rule (the paper names richer walking-speed and stability rules
+       and variable bodies as further work, sec. 2.4 note 1 and sec. 4; this is
+       a mechanics reading of them).  stability = 0 (the default): Table 1
+       alone.  stability = 1: a person in a wet cell is an upright cylinder of
+       its height H and its volume M / rho_body (cross-section A = M /
+       (rho_body H), diameter b = 2 sqrt(A / pi)); the water of depth h takes
+       rho_w g A h of its weight W = M g by buoyancy and pushes it with the
+       drag D = 1/2 rho_w c_drag b h u^2 of the flow speed u = |(hu, hv)| / h
+       at the cell, acting at h / 2.  It cannot stand (class FPS_CLS_UNSTABLE,
+       speed 0) when D > mu_f (W - buoyancy) (sliding), when D h / 2 > (W -
+       buoyancy) b / 2 (toppling about the cylinder's edge), or when h >= H.
+       Defaults 1.1, 0.45, 1000, 1000 kg/m^3; bodies from fps_set_bodies, else
+       body_h0 = 1.71 m and body_m0 = 70 kg for everyone.  Evaluated in FP32. */
+    int32_t stability;
+    double c_drag, mu_f, rho_w, rho_body, body_h0, body_m0;
 } fps_ped_params;
 
 typedef struct {
@@ -103,7 +119,7 @@ typedef struct {
     double v_in, v_out, v_clip;  /* accumulated inflow, transmissive outflow, clipped volume (m^3) */
     int32_t any_wet;         /* some cell has h > h_dry */
     int32_t n_agents;
-    int32_t class_count[5];  /* non-exited agents per hazard class */
+    int32_t class_count[6];  /* agents inside per hazard class (FPS_CLS_*) */
     int32_t state_count[8];  /* agents per state */
     int32_t barrier_layers_done, barrier_active_cell, barrier_bags, barrier_done;
     int32_t drops_total;     /* sandbags delivered */
@@ -168,6 +184,13 @@ int fps_set_navigation(fps_sim* sim, int32_t n_dest, int32_t n_exit, const float
 int fps_bind_agents(fps_sim* sim, int32_t n, float* x, float* y, float* vx, float* vy,
                     float* v_base, uint8_t* role, uint8_t* state, uint8_t* hr_class,
                     int32_t* dest, float* timer);
+
+/* Bodies of the agents for the stability rule (fps_ped_params.stability):
+   height (m) and mass (kg), device float32 [n_agents] each, caller-owned,
+   read at every step; both NULL: the default body for everyone.  Call after
+   fps_bind_agents (the arrays follow its agent count); FPS_E_INVALID for one
+   array without the other. */
+int fps_set_bodies(fps_sim* sim, const float* height, const float* mass);
 
 /* Sandbag barrier (sec. 2.4, sec. 3.3): cells (host, copied) in fill order
    starting at the first barrier cell; responders shuttle between destination

@@ -18,6 +18,9 @@
  *   - responder cycle storage -> 30 s pick -> barrier -> 30 s drop; layer fill
  *     along the barrier line, N_L layers: sec. 2.4, sec. 3.3
  *   - triangular inflow hydrograph: sec. 3.1
+ *   - richer walking-speed and stability rules and variable body shapes are
+ *     named as further work (sec. 2.4 note 1, sec. 4): the stability rule
+ *     below (S1-S4) is this oracle's reading of them
  *   - pre-flood flow: 7 entrance doors, entering and leaving by each with
  *     probability 1/7, 10 per door, 1,000 walkers, a 5-minute spin-up with
  *     no inflow, no entries once water is on the site: sec. 3, sec. 3.2, sec. 2.4
@@ -96,6 +99,22 @@
  *      seeded with door_seed; a choice among m is floor((u >> 32) * m / 2^32),
  *      an offset 0.25 + 0.5 * floor(u / 2^40) / 2^24, the position
  *      ((float)i + offset) * (float)dx in FP32 (R19's precision).
+ * Readings of the stability rule (or_unstable; the paper names richer
+ * walking-speed and stability rules and variable bodies as further work):
+ *   S1 every person has a body: height and mass (a default body for those
+ *      without one).
+ *   S2 the body is an upright cylinder of its own volume (mass over the body
+ *      density); standing in water of depth h it loses the weight of the
+ *      water it displaces and meets the drag of the flow speed (the magnitude
+ *      of the cell's velocity, not the max of its components) on its wetted
+ *      frontal area, acting half way up the water.
+ *   S3 it cannot stand when the drag exceeds the foot friction on its
+ *      effective weight (sliding), when the drag's moment exceeds that
+ *      weight's moment about the cylinder's edge (toppling), or when the
+ *      water reaches its height.
+ *   S4 a person who cannot stand does not walk (speed 0) and takes a sixth
+ *      state in floodwater, UNSTABLE, in place of its Table 1 class; on dry
+ *      cells and with the rule off the paper's Table 1 alone applies.
  */
 #include "fps_oracle.h"
 
@@ -257,6 +276,39 @@ int32_t or_hr_class(const or_params *P, double h, double qx, double qy, double *
     if (hr < P->hr_t[1]) return OR_CLS_MEDIUM;
     if (hr < P->hr_t[2]) return OR_CLS_HIGH;
     return OR_CLS_HIGHEST;
+}
+
+/* Stability of a person standing in flowing water (S1-S4; the paper leaves
+   richer rules than Table 1 to later work and names mechanics-based criteria):
+   the body an upright cylinder of height H and volume M / rho_body, so of
+   cross-section A = M / (rho_body H) and diameter b = 2 sqrt(A / pi); in water
+   of depth h it loses rho_w g A h of its weight to buoyancy and meets the drag
+   D = 1/2 rho_w c_drag b h u^2 of the flow speed u, acting at h / 2.  It
+   slides when D exceeds mu_f times its effective weight W' and topples when
+   the moment D h / 2 exceeds W' b / 2 (the cylinder tipping about its edge);
+   it cannot stand once h >= H. */
+int32_t or_unstable(const or_params *P, double h, double qx, double qy, double height, double mass,
+                    double *margin)
+{
+    if (margin) *margin = 1.0;
+    if (!(h > P->h_dry)) return 0;
+    if (h >= height) {
+        if (margin) *margin = -1.0;
+        return 1;
+    }
+    const double pi = 3.14159265358979323846;
+    double u = sqrt(qx * qx + qy * qy) / h;
+    double area = mass / (P->rho_body * height);
+    double b = 2.0 * sqrt(area / pi);
+    double w_eff = P->g * (mass - P->rho_w * area * h);
+    double drag = 0.5 * P->rho_w * P->c_drag * b * h * u * u;
+    double hold_slide = P->mu_f * w_eff, hold_topple = w_eff * 0.5 * b;
+    double push_topple = drag * 0.5 * h;
+    if (margin) {
+        double m1 = (hold_slide - drag) / hold_slide, m2 = (hold_topple - push_topple) / hold_topple;
+        *margin = m1 < m2 ? m1 : m2;
+    }
+    return drag > hold_slide || push_topple > hold_topple;
 }
 
 /* roughness write-back (sec. 2.4; R13) */
@@ -890,8 +942,16 @@ void or_ped_step(or_sim *S, double dt)
         int64_t c = (int64_t)cj * nx + ci;
         /* hazard from the containing cell (Table 1) */
         int32_t cls = or_hr_class(P, S->h[c], S->qx[c], S->qy[c], NULL);
-        S->cls[a] = (uint8_t)cls;
         double v0 = cls == OR_CLS_DRY ? S->vbase[a] : P->v_class[cls];
+        /* the stability rule overrides Table 1 where a person cannot stand (S4) */
+        if (P->stability && cls != OR_CLS_DRY) {
+            double hb = S->body_h ? S->body_h[a] : P->body_h0, mb = S->body_m ? S->body_m[a] : P->body_m0;
+            if (or_unstable(P, S->h[c], S->qx[c], S->qy[c], hb, mb, NULL)) {
+                cls = OR_CLS_UNSTABLE;
+                v0 = 0.0;
+            }
+        }
+        S->cls[a] = (uint8_t)cls;
         /* destinations */
         if (S->dest[a] < 0) {
             if (S->role[a] == OR_ROLE_EVACUEE) {

@@ -39,6 +39,7 @@ extern "C" {
 #define OR_CLS_MEDIUM 2
 #define OR_CLS_HIGH 3
 #define OR_CLS_HIGHEST 4
+#define OR_CLS_UNSTABLE 5  /* the stability rule (S1-S4): swept off the feet, speed 0 */
 #define OR_FLUX_HLLC 0
 #define OR_FLUX_HLL 1
 
@@ -58,6 +59,10 @@ typedef struct {
     double pick_s, drop_s;
     int32_t flux;                        /* OR_FLUX_HLLC (R1) or OR_FLUX_HLL (variant) */
     int32_t order;                       /* 1: the paper's first-order scheme; 2: the MUSCL variant */
+    /* stability rule of a person standing in flowing water (S1-S4); 0 = Table 1 only */
+    int32_t stability;
+    double c_drag, mu_f, rho_w, rho_body; /* drag coefficient, foot friction, water and body densities */
+    double body_h0, body_m0;             /* the body of people without one of their own (m, kg) */
 } or_params;
 
 typedef struct {
@@ -97,6 +102,8 @@ typedef struct {
     uint64_t door_seed;
     int32_t doors_closed;
     int64_t door_in, door_out;
+    /* bodies of the people (S1): height (m), mass (kg) per agent, or NULL */
+    const double *body_h, *body_m;
 } or_sim;
 
 /* ---- single operations (exposed for the pins) ---- */
@@ -109,6 +116,10 @@ void or_face(const or_params *P, double hL, double qnL, double qtL, double zL,
              double *hsL, double *hsR);
 double or_hydro_integral(int32_t nh, const double *ht, const double *hq, double a, double b);
 int32_t or_hr_class(const or_params *P, double h, double qx, double qy, double *hr_out);
+/* 1 if a person of the given height and mass cannot stand in the cell (S2, S3);
+   *margin (may be NULL): the smaller relative excess of holding over pushing */
+int32_t or_unstable(const or_params *P, double h, double qx, double qy, double height, double mass,
+                    double *margin);
 double or_n_eff(const or_params *P, int32_t np);
 void or_friction(const or_params *P, double dt, double h, double n, double *qx, double *qy);
 int32_t or_cell_index(double x, double d, int32_t n);

@@ -26,7 +26,7 @@ _up = C.POINTER(C.c_uint8)
 WALL, TRANSMISSIVE = 0, 1
 ROLE_EVACUEE, ROLE_RESPONDER = 0, 1
 ST_EVAC, ST_EXITED, ST_TO_STORAGE, ST_PICKING, ST_TO_BARRIER, ST_DROPPING, ST_SHOPPING, ST_OUTSIDE = range(8)
-CLS_DRY, CLS_LOW, CLS_MEDIUM, CLS_HIGH, CLS_HIGHEST = range(5)
+CLS_DRY, CLS_LOW, CLS_MEDIUM, CLS_HIGH, CLS_HIGHEST, CLS_UNSTABLE = range(6)
 FLUX_HLLC, FLUX_HLL = 0, 1
 
 
@@ -44,6 +44,9 @@ class OrParams(C.Structure):
         ("pick_s", C.c_double), ("drop_s", C.c_double),
         ("flux", C.c_int32),
         ("order", C.c_int32),
+        ("stability", C.c_int32),
+        ("c_drag", C.c_double), ("mu_f", C.c_double), ("rho_w", C.c_double), ("rho_body", C.c_double),
+        ("body_h0", C.c_double), ("body_m0", C.c_double),
     ]
 
 
@@ -71,6 +74,7 @@ class OrSim(C.Structure):
         ("door_seed", C.c_uint64),
         ("doors_closed", C.c_int32),
         ("door_in", C.c_int64), ("door_out", C.c_int64),
+        ("body_h", _dp), ("body_m", _dp),
     ]
 
 
@@ -105,6 +109,8 @@ def lib(omp: bool = False):
         L.or_hydro_integral.restype = C.c_double
         L.or_hr_class.argtypes = [C.POINTER(OrParams), C.c_double, C.c_double, C.c_double, _dp]
         L.or_hr_class.restype = C.c_int32
+        L.or_unstable.argtypes = [C.POINTER(OrParams)] + [C.c_double] * 5 + [_dp]
+        L.or_unstable.restype = C.c_int32
         L.or_n_eff.argtypes = [C.POINTER(OrParams), C.c_int32]
         L.or_n_eff.restype = C.c_double
         L.or_friction.argtypes = [C.POINTER(OrParams), C.c_double, C.c_double, C.c_double, _dp, _dp]
@@ -152,6 +158,10 @@ def make_params(desc, ped=None) -> OrParams:
     P.pick_s, P.drop_s = ped.pick_s, ped.drop_s
     P.flux = getattr(desc, "flux", FLUX_HLLC)
     P.order = getattr(desc, "order", 1)
+    P.stability = int(getattr(ped, "stability", 0))
+    P.c_drag, P.mu_f = getattr(ped, "c_drag", 1.1), getattr(ped, "mu_f", 0.45)
+    P.rho_w, P.rho_body = getattr(ped, "rho_w", 1000.0), getattr(ped, "rho_body", 1000.0)
+    P.body_h0, P.body_m0 = getattr(ped, "body_h0", 1.71), getattr(ped, "body_m0", 70.0)
     return P
 
 
@@ -208,6 +218,10 @@ class OracleSim:
             for nm in ("role", "state", "cls"):
                 setattr(S, nm, _ptr(getattr(self, nm), _up))
             S.dest = _ptr(self.dest, _ip)
+            if "height" in A and "mass" in A:
+                self.body_h = np.asarray(A["height"], dtype=np.float64).copy()
+                self.body_m = np.asarray(A["mass"], dtype=np.float64).copy()
+                S.body_h, S.body_m = _ptr(self.body_h, _dp), _ptr(self.body_m, _dp)
             bsx, bsy, nbx, nby = self.bins_dims()
             self.bin_start = np.zeros(nbx * nby + 1, dtype=np.int32)
             self.perm = np.zeros(na, dtype=np.int32)
@@ -314,6 +328,13 @@ def hr_class(params, h, qx, qy):
     hr = C.c_double()
     c = lib().or_hr_class(C.byref(params), float(h), float(qx), float(qy), C.byref(hr))
     return c, hr.value
+
+
+def unstable(params, h, qx, qy, height, mass):
+    """(1 if a person of that body cannot stand in the cell, relative margin)."""
+    m = C.c_double()
+    r = lib().or_unstable(C.byref(params), float(h), float(qx), float(qy), float(height), float(mass), C.byref(m))
+    return r, m.value
 
 
 def n_eff(params, np_count):

@@ -70,6 +70,7 @@ struct fps_sim {
     bool nav_bound;
     int32_t nline, storage_dest, barrier_dest, n_layers, bags_per;
     float t_bag, t_last;
+    const float *body_h, *body_m;   // bodies of the stability rule (NULL: the default body)
     int32_t n_door, door_rate;
     uint64_t door_seed;
     bool numeric_fault;
@@ -357,6 +358,11 @@ void fill_scn(const fps_sim* s, Scn& c)
     q.pick_s = (float)s->P.pick_s; q.drop_s = (float)s->P.drop_s;
     q.storage_dest = s->storage_dest; q.barrier_dest = s->barrier_dest;
     q.doors = s->doors; q.n_door = s->na > 0 ? s->n_door : 0; q.door_rate = s->door_rate;
+    q.stab = s->P.stability;
+    q.body_h = s->body_h; q.body_m = s->body_m;
+    q.stab_kd = (float)(0.5 * s->P.rho_w * s->P.c_drag);
+    q.stab_mu = (float)s->P.mu_f; q.stab_rw = (float)s->P.rho_w; q.stab_rb = (float)s->P.rho_body;
+    q.stab_g = (float)s->G.g; q.body_h0 = (float)s->P.body_h0; q.body_m0 = (float)s->P.body_m0;
     q.door_seed = s->door_seed;
 
     BinParams& b = c.bins;
@@ -821,6 +827,9 @@ int build_engine(Engine* e, int32_t S, const fps_grid_desc* descs, const fps_ped
             const fps_ped_params& P = peds[k];
             if (!(P.tau > 0) || !(P.b_range > 0) || !(P.r_cut > 0) || !(P.radius >= 0) || !(P.r_arrive >= 0))
                 return efail(e, FPS_E_INVALID, "scenario %d: pedestrian constants out of range", k);
+            if ((P.stability != 0 && P.stability != 1) || !(P.c_drag >= 0) || !(P.mu_f > 0) || !(P.rho_w > 0) ||
+                !(P.rho_body > 0) || !(P.body_h0 > 0) || !(P.body_m0 > 0))
+                return efail(e, FPS_E_INVALID, "scenario %d: stability constants out of range", k);
         }
     }
     if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255))
@@ -913,6 +922,13 @@ void fps_ped_params_default(fps_ped_params* o)
     o->hr_t[2] = 2.5;
     o->pick_s = 30.0;
     o->drop_s = 30.0;
+    o->stability = 0;
+    o->c_drag = 1.1;
+    o->mu_f = 0.45;
+    o->rho_w = 1000.0;
+    o->rho_body = 1000.0;
+    o->body_h0 = 1.71;
+    o->body_m0 = 70.0;
 }
 
 size_t fps_workspace_bytes(const fps_grid_desc* desc, int32_t max_agents)
@@ -1280,11 +1296,23 @@ int fps_bind_agents(fps_sim* s, int32_t n, float* x, float* y, float* vx, float*
             return fail(s, FPS_E_INVALID, "fps_bind_agents: %d agents with invalid role/state/dest", bad[1]);
     }
     s->na = n;
+    s->body_h = s->body_m = nullptr;      // bodies follow the agents: set them again
     s->x = x; s->y = y; s->vx = vx; s->vy = vy; s->vbase = v_base;
     s->role = role; s->state = state; s->cls = hr_class; s->dest = dest; s->timer = timer;
     mark_dirty(s);
     int rc = rebuild_bins(s);
     return rc != FPS_OK ? rc : recount_outside(s);
+}
+
+int fps_set_bodies(fps_sim* s, const float* height, const float* mass)
+{
+    if (!s) return fail(nullptr, FPS_E_INVALID, "fps_set_bodies: sim is NULL");
+    if (!height != !mass) return fail(s, FPS_E_INVALID, "fps_set_bodies: give both arrays or neither");
+    HIPCHK(s, hipStreamSynchronize(s->eng->stream));
+    s->body_h = height;
+    s->body_m = mass;
+    mark_dirty(s);
+    return FPS_OK;
 }
 
 int fps_set_doors(fps_sim* s, int32_t n_doors, const int32_t* cells, const int32_t* dests, int32_t per_step,
@@ -1534,8 +1562,8 @@ int fps_get_diag(fps_sim* s, fps_diag* out)
     out->v_clip = d.v_clip;
     out->any_wet = d.any_wet;
     out->n_agents = s->na;
-    for (int k = 0; k < 5; ++k) out->class_count[k] = stats[k];
-    for (int k = 0; k <= FPS_ST_OUTSIDE; ++k) out->state_count[k] = stats[5 + k];
+    for (int k = 0; k <= FPS_CLS_UNSTABLE; ++k) out->class_count[k] = stats[k];
+    for (int k = 0; k <= FPS_ST_OUTSIDE; ++k) out->state_count[k] = stats[6 + k];
     out->barrier_layers_done = d.layers_done;
     out->barrier_active_cell = d.active_cell;
     out->barrier_bags = d.bags;

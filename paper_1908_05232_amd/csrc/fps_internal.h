@@ -124,6 +124,11 @@ struct PedParams {
     const int32_t* doors;
     int n_door, door_rate;
     uint64_t door_seed;
+    // stability rule: bodies (NULL: body_h0 / body_m0 for everyone) and constants
+    const float* body_h;
+    const float* body_m;
+    int stab;
+    float stab_kd, stab_mu, stab_rw, stab_rb, stab_g, body_h0, body_m0;   // kd = rho_w c_drag / 2
 };
 
 // Sandbag barrier of sec. 2.4: the fill order and layer rules.
@@ -211,7 +216,7 @@ hipError_t launch_count(const BinParams& b, hipStream_t s);      // per-cell eva
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_hazard(const float* h, const float* qx, const float* qy, float* hr, int64_t n,
                          float eps, hipStream_t s);
-hipError_t launch_agent_stats(const uint8_t* state, const uint8_t* cls, int na, int32_t* out13,
+hipError_t launch_agent_stats(const uint8_t* state, const uint8_t* cls, int na, int32_t* out14,
                               hipStream_t s);
 hipError_t launch_wall_mask(const uint8_t* walk, uint4* mask, int nx, int ny, int Rx, int Ry,
                             hipStream_t s);

@@ -158,7 +158,7 @@ __device__ __forceinline__ int window_row(int b, int wdth, int wcells, uint32_t 
 
 // The agent's record, read before anything else of the step.
 struct AgentRec {
-    float x, y, vx, vy, vbase, timer;
+    float x, y, vx, vy, vbase, timer, body_h, body_m;
     int state, role, dest, slot;
 };
 
@@ -175,6 +175,12 @@ __device__ __forceinline__ AgentRec load_agent(const PedParams& p, int a)
     r.vbase = p.vbase[a];
     r.slot = p.slot[a];
     r.timer = p.timer[a];
+    r.body_h = p.body_h0;
+    r.body_m = p.body_m0;
+    if (p.stab && p.body_h) {
+        r.body_h = p.body_h[a];
+        r.body_m = p.body_m[a];
+    }
     return r;
 }
 
@@ -346,6 +352,21 @@ __device__ void agent_step(const PedParams& p, const AgentRec& rec, const float*
         v0 = cls == FPS_CLS_LOW ? p.v_class[FPS_CLS_LOW]
            : cls == FPS_CLS_MEDIUM ? p.v_class[FPS_CLS_MEDIUM]
            : cls == FPS_CLS_HIGH ? p.v_class[FPS_CLS_HIGH] : p.v_class[FPS_CLS_HIGHEST];
+        if (p.stab) {
+            // stability rule: an upright cylinder of the body's volume in the
+            // flow; sliding, toppling about its edge, or water to its height
+            const float bh = rec.body_h, bm = rec.body_m;
+            const float u = sqrtf(qxc * qxc + qyc * qyc) / h;
+            const float area = bm / (p.stab_rb * bh);
+            const float b = 2.0f * sqrtf(area * 0.318309886f);
+            const float w_eff = p.stab_g * (bm - p.stab_rw * area * h);
+            const float drag = p.stab_kd * b * h * u * u;
+            const bool unstable = h >= bh || drag > p.stab_mu * w_eff || drag * (0.5f * h) > w_eff * (0.5f * b);
+            if (unstable) {
+                cls = FPS_CLS_UNSTABLE;
+                v0 = 0.0f;
+            }
+        }
     }
     if (lead) p.cls[a] = (uint8_t)cls;
     // the direction is needed here: this keeps the compiler from moving its
@@ -875,18 +896,19 @@ __global__ void hazard_kernel(const float* h, const float* qx, const float* qy, 
 // the order does not matter).
 __global__ void agent_stats_kernel(const uint8_t* state, const uint8_t* cls, int na, int32_t* out)
 {
+    constexpr int kCls = FPS_CLS_UNSTABLE + 1;
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     const bool in = a < na;
     const int s = in ? min((int)state[a], (int)FPS_ST_OUTSIDE) : -1;
-    const int c = in && s != FPS_ST_EXITED && s != FPS_ST_OUTSIDE ? min((int)cls[a], 4) : -1;
+    const int c = in && s != FPS_ST_EXITED && s != FPS_ST_OUTSIDE ? min((int)cls[a], kCls - 1) : -1;
     const bool first = (threadIdx.x & (kWave - 1)) == 0;
 #pragma unroll
     for (int k = 0; k <= FPS_ST_OUTSIDE; ++k) {
         const int n = __popcll(__ballot(s == k));
-        if (first && n) atomicAdd(&out[5 + k], n);
+        if (first && n) atomicAdd(&out[kCls + k], n);
     }
 #pragma unroll
-    for (int k = 0; k < 5; ++k) {
+    for (int k = 0; k < kCls; ++k) {
         const int n = __popcll(__ballot(c == k));
         if (first && n) atomicAdd(&out[k], n);
     }
@@ -1067,12 +1089,12 @@ hipError_t launch_hazard(const float* h, const float* qx, const float* qy, float
     hipLaunchKernelGGL(hazard_kernel, dim3(g), dim3(256), 0, s, h, qx, qy, hr, n, eps);
     return hipGetLastError();
 }
-hipError_t launch_agent_stats(const uint8_t* state, const uint8_t* cls, int na, int32_t* out13,
+hipError_t launch_agent_stats(const uint8_t* state, const uint8_t* cls, int na, int32_t* out14,
                               hipStream_t s)
 {
     if (na > 0)
         hipLaunchKernelGGL(agent_stats_kernel, dim3(blocks_for(na, 256)), dim3(256), 0, s, state,
-                           cls, na, out13);
+                           cls, na, out14);
     return hipGetLastError();
 }
 hipError_t launch_wall_mask(const uint8_t* walk, uint4* mask, int nx, int ny, int Rx, int Ry,

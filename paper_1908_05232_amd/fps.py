@@ -37,6 +37,9 @@ class PedParamsC(C.Structure):
         ("radius", C.c_double), ("r_cut", C.c_double), ("r_arrive", C.c_double),
         ("v_class", C.c_double * 5), ("hr_t", C.c_double * 3),
         ("pick_s", C.c_double), ("drop_s", C.c_double),
+        ("stability", C.c_int32),
+        ("c_drag", C.c_double), ("mu_f", C.c_double), ("rho_w", C.c_double), ("rho_body", C.c_double),
+        ("body_h0", C.c_double), ("body_m0", C.c_double),
     ]
 
 
@@ -46,7 +49,7 @@ class DiagC(C.Structure):
         ("dt_last", C.c_double), ("dt_next", C.c_double),
         ("mass", C.c_double), ("v_in", C.c_double), ("v_out", C.c_double), ("v_clip", C.c_double),
         ("any_wet", C.c_int32), ("n_agents", C.c_int32),
-        ("class_count", C.c_int32 * 5), ("state_count", C.c_int32 * 8),
+        ("class_count", C.c_int32 * 6), ("state_count", C.c_int32 * 8),
         ("barrier_layers_done", C.c_int32), ("barrier_active_cell", C.c_int32),
         ("barrier_bags", C.c_int32), ("barrier_done", C.c_int32),
         ("drops_total", C.c_int32), ("status", C.c_int32),
@@ -68,6 +71,7 @@ EXPORTS = {
     "fps_set_barrier": (C.c_int, [_vp, C.POINTER(C.c_int32), C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                   C.c_float, C.c_float, C.c_int32]),
     "fps_set_time": (C.c_int, [_vp, C.c_double, C.c_int64]),
+    "fps_set_bodies": (C.c_int, [_vp, _vp, _vp]),
     "fps_set_doors": (C.c_int, [_vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int32,
                                 C.c_uint64]),
     "fps_step": (C.c_int, [_vp, C.c_int32]),
@@ -179,6 +183,10 @@ def ped_params_c(p) -> PedParamsC:
     for k in range(3):
         c.hr_t[k] = p.hr_t[k]
     c.pick_s, c.drop_s = p.pick_s, p.drop_s
+    c.stability = int(getattr(p, "stability", 0))
+    c.c_drag, c.mu_f = getattr(p, "c_drag", 1.1), getattr(p, "mu_f", 0.45)
+    c.rho_w, c.rho_body = getattr(p, "rho_w", 1000.0), getattr(p, "rho_body", 1000.0)
+    c.body_h0, c.body_m0 = getattr(p, "body_h0", 1.71), getattr(p, "body_m0", 70.0)
     return c
 
 
@@ -231,6 +239,10 @@ class Member:
             a = self.agents_t
             self._check(L.fps_bind_agents(h, self.na, *[_ptr(a[k]) for k in (
                 "x", "y", "vx", "vy", "v_base", "role", "state", "hr_class", "dest", "timer")]))
+            if "height" in A and "mass" in A:
+                self.body_t = {k: torch.tensor(np.asarray(A[k], np.float32), device=self.device).contiguous()
+                               for k in ("height", "mass")}
+                self._check(L.fps_set_bodies(h, _ptr(self.body_t["height"]), _ptr(self.body_t["mass"])))
         if sc.t0:
             self.set_time(sc.t0, 0)
 

@@ -65,6 +65,14 @@ class PedParams:
     hr_t: tuple = (0.75, 1.5, 2.5)
     pick_s: float = 30.0
     drop_s: float = 30.0
+    # stability of a person standing in flowing water (off: the paper's Table 1 alone)
+    stability: int = 0
+    c_drag: float = 1.1           # drag coefficient of an upright cylinder
+    mu_f: float = 0.45            # friction of feet on a wet floor
+    rho_w: float = 1000.0         # water density (kg/m^3)
+    rho_body: float = 1000.0      # body density (kg/m^3)
+    body_h0: float = 1.71         # body of people without one of their own: height (m)
+    body_m0: float = 70.0         # ... and mass (kg)
 
 
 @dataclasses.dataclass
@@ -149,6 +157,21 @@ def empty_agents(n: int) -> dict:
         role=np.zeros(n, np.uint8), state=np.zeros(n, np.uint8),
         hr_class=np.zeros(n, np.uint8), dest=np.full(n, -1, np.int32),
         timer=np.zeros(n, np.float32))
+
+
+def add_bodies(sc: Scenario, seed: int, stability: int = 1) -> Scenario:
+    """Variable bodies for every agent: heights N(1.71, 0.09) m clipped to
+    [1.45, 1.95] m and body-mass indices N(25, 3.5) clipped to [17, 35] kg/m^2
+    (mass = index x height^2), a seeded adult population; switches the
+    stability rule on."""
+    rng = rng_of(seed + 31337)
+    n = len(sc.agents["x"])
+    height = np.clip(rng.normal(1.71, 0.09, n), 1.45, 1.95)
+    bmi = np.clip(rng.normal(25.0, 3.5, n), 17.0, 35.0)
+    sc.agents["height"] = height.astype(np.float32)
+    sc.agents["mass"] = (bmi * height ** 2).astype(np.float32)
+    sc.ped = dataclasses.replace(sc.ped, stability=stability)
+    return sc
 
 
 def place_uniform(rng, walk: np.ndarray, n: int, dx: float, dy: float):

@@ -68,7 +68,7 @@ def run_evacuation(scs, t_max=3600.0, poll_steps=10):
     ens = fps.Ensemble(scs)
     ens.autotune()
     q = [float(np.max(sc.hydro_q)) if sc.hydro_q is not None and len(sc.hydro_q) else 0.0 for sc in scs]
-    out = [dict(name=sc.name, evacuees=None, q_peak=qp, t_evacuated=None, peak_class_count=[0] * 5,
+    out = [dict(name=sc.name, evacuees=None, q_peak=qp, t_evacuated=None, peak_class_count=[0] * 6,
                 door_entries=0, door_leaves=0) for sc, qp in zip(scs, q)]
     t = -np.inf
     while t < t_max and any(o["t_evacuated"] is None for o in out):

@@ -23,6 +23,9 @@ def snapshot(sim, sc):
     if sim.na:
         A = sim.agents()
         s2.agents = {k: v.copy() for k, v in A.items()}
+        for k in ("height", "mass"):          # bodies do not change: the scenario's own
+            if k in sc.agents:
+                s2.agents[k] = np.asarray(sc.agents[k]).copy()
     return s2, d
 
 
