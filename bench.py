@@ -39,8 +39,20 @@ def log(*a):
 
 
 def kernel_source_hash():
-    src = os.path.join(ROOT, "paper_1908_05232_amd", "csrc", "fps_flood.hip")
-    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    """Hash of the first-order flood update's own source: fps_flood.hip from
+    its cell record to the start of the second-order variant (its helpers and
+    fv_step_kernel), and the parameter and state records it reads; edits to the
+    other kernels leave it, and the counters taken on it, valid."""
+    csrc = os.path.join(ROOT, "paper_1908_05232_amd", "csrc")
+    text = open(os.path.join(csrc, "fps_flood.hip")).read()
+    a = text.index("struct Cell {")
+    b = text.index("// Second-order variant")
+    h = hashlib.sha256(text[a:b].encode())
+    inner = open(os.path.join(csrc, "fps_internal.h")).read()
+    for rec in ("struct DevState {", "struct FvParams {"):
+        i = inner.index(rec)
+        h.update(inner[i:inner.index("};", i)].encode())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(workload, rows):
