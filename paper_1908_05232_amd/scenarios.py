@@ -46,17 +46,22 @@ def _site(population, seed, n, dx, **kw):
     return I.shopping_centre(n=n, dx=dx, seed=seed, n_evac=population, n_exits=1, **kw)
 
 
-def evacuation_pair(population=1000, seed=5232, n=SITE_N, dx=SITE_DX, q_peak=2.0, duration=1800.0, doors=True):
+def evacuation_pair(population=1000, seed=5232, n=SITE_N, dx=SITE_DX, q_peak=2.0, duration=1800.0, doors=True,
+                    bodies=False):
     """Scenario 1 with and without the people's effect on the flood.  doors:
     the pre-flood flow (sec. 3.2) fills the site from 7 doors during a
-    5-minute spin-up; else the population starts spread uniformly, standing."""
+    5-minute spin-up; else the population starts spread uniformly, standing.
+    bodies: varied heights and masses and the stability rule (people who
+    cannot stand in the flow stop)."""
     with_people = _site(population, seed, n, dx, q_peak=q_peak, duration=duration)
     if doors:
         with_people = I.add_doors(with_people, seed=seed)
-    with_people.name = "evacuation_coupled"
+    if bodies:
+        with_people = I.add_bodies(with_people, seed=seed)
+    with_people.name = "evacuation_coupled" + ("_bodies" if bodies else "")
     without = copy.deepcopy(with_people)
     without.desc.np_cap = 0
-    without.name = "evacuation_uncoupled"
+    without.name = "evacuation_uncoupled" + ("_bodies" if bodies else "")
     return [with_people, without]
 
 
@@ -190,6 +195,7 @@ def main(argv=None):
                    barrier_floods=barrier_floods(layers=(0, 1, 2), t_run=900.0))
     else:
         res = dict(evacuation=[run_evacuation(evacuation_pair(q_peak=q)) for q in BREACH_Q],
+                   evacuation_stability=[run_evacuation(evacuation_pair(q_peak=q, bodies=True)) for q in BREACH_Q[2:]],
                    deployment=run_deployment(deployment_sweep()),
                    barrier_floods=barrier_floods())
     res["wall_s"] = time.perf_counter() - t0

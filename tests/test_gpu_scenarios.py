@@ -57,3 +57,58 @@ def test_deployment_sweep_and_barrier_floods():
           f["wet_cells_downstream"], f["t_water_behind_line"]) for f in fl])
     a0, a6 = fl[0]["t_water_behind_line"], fl[-1]["t_water_behind_line"]
     assert a0 is not None and (a6 is None or a6 > a0)
+
+
+@pytest.mark.parametrize("q_peak", [2.0, 10.0])
+def test_evacuation_matches_the_oracle(oracle, q_peak):
+    """Scenario 1 on the paper's site (128^2 cells over 332 m, the door flow
+    from t = -5 min, 1,000 people, the breach at t = 0), run to the end on
+    the GPU and on the FP64 oracle, both polled every step: the same number
+    of evacuees, the evacuation time within 3 % (FP32 and FP64 walks part
+    after a few hundred steps, so arrival times differ by a few steps), the
+    door entries within 2 % and the largest number of people seen at once in
+    the wet hazard classes, a statistic of the crowd, within 25 % or, for the
+    few people of a small flood, within the counting noise 3 sqrt(N) + 3."""
+    sc, _ = S.evacuation_pair(population=1000, q_peak=q_peak)
+
+    def run_gpu():
+        sim = fps.Sim(sc)
+        peak, n_evac, t_evac = np.zeros(6, int), None, None
+        while t_evac is None:
+            sim.step(1)
+            d = sim.diag()
+            sc_ = d["state_count"]
+            if d["any_wet"] or d["doors_closed"]:
+                peak = np.maximum(peak, d["class_count"])
+            if n_evac is None and d["doors_closed"]:
+                n_evac = sc_[0] + sc_[1]
+            if n_evac is not None and sc_[0] + sc_[6] == 0:
+                t_evac = d["t"]
+            assert d["t"] < 4000.0
+        return t_evac, n_evac, peak, d["door_entries"]
+
+    def run_oracle():
+        ref = oracle.OracleSim(sc)
+        peak, n_evac, t_evac = np.zeros(6, int), None, None
+        while t_evac is None:
+            ref.coupled_step(0.0)
+            st = ref.state
+            inside = (st == 0) | (st == 6)
+            if ref.S.any_wet or ref.S.doors_closed:
+                peak = np.maximum(peak, np.bincount(ref.cls[inside], minlength=6))
+            if n_evac is None and ref.S.doors_closed:
+                n_evac = int((st == 0).sum() + (st == 1).sum())
+            if n_evac is not None and inside.sum() == 0:
+                t_evac = ref.t
+            assert ref.t < 4000.0
+        return t_evac, n_evac, peak, ref.S.door_in
+
+    tg, ng, pg, eg = run_gpu()
+    to, no, po, eo = run_oracle()
+    say(f"breach {q_peak} m^2/s: evacuated gpu {tg:.1f} s oracle {to:.1f} s, evacuees {ng} / {no}, "
+        f"entries {eg} / {eo}, wet-class peaks gpu {pg[1:5]} oracle {po[1:5]}")
+    assert ng == no == 1000
+    assert abs(tg - to) <= 0.03 * to
+    assert abs(eg - eo) <= 0.02 * eo
+    n_o = int(po[1:5].sum())
+    assert abs(int(pg[1:5].sum()) - n_o) <= max(0.25 * n_o, 3.0 * np.sqrt(n_o) + 3.0)
