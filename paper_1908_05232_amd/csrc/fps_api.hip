@@ -1269,7 +1269,8 @@ int fps_set_navigation(fps_sim* s, int32_t n_dest, int32_t n_exit, const float* 
         HIPCHK(s, launch_wall_mask(walkable, s->wmask, s->G.nx, s->G.ny, s->Rx, s->Ry, s->eng->stream));
     s->use_codes = s->max_agents > 0 && n_dest <= kCodeDest;
     if (s->use_codes)
-        HIPCHK(s, launch_nav_codes(dist, n_dest, s->G.nx, s->G.ny, (float)s->P.r_arrive, s->codes, s->eng->stream));
+        HIPCHK(s, launch_nav_codes(dist, walkable, n_dest, s->G.nx, s->G.ny, (float)s->P.r_arrive, s->Rx, s->Ry,
+                                   s->codes, s->eng->stream));
     mark_dirty(s);
     return FPS_OK;
 }

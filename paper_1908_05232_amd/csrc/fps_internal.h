@@ -220,8 +220,8 @@ hipError_t launch_agent_stats(const uint8_t* state, const uint8_t* cls, int na, 
                               hipStream_t s);
 hipError_t launch_wall_mask(const uint8_t* walk, uint4* mask, int nx, int ny, int Rx, int Ry,
                             hipStream_t s);
-hipError_t launch_nav_codes(const float* dist, int n_dest, int nx, int ny, float r_arrive, uint8_t* codes,
-                            hipStream_t s);
+hipError_t launch_nav_codes(const float* dist, const uint8_t* walk, int n_dest, int nx, int ny, float r_arrive,
+                            int Rx, int Ry, uint8_t* codes, hipStream_t s);
 // bad2[0]: agents outside the domain; bad2[1]: invalid role / state / destination
 hipError_t launch_check_agents(const float* x, const float* y, const uint8_t* role,
                                const uint8_t* state, const int32_t* dest, int na, float lx,

@@ -89,9 +89,11 @@ __device__ __forceinline__ int off_of(uint32_t packed, int k) { return (int)((pa
 // head for (0-7 in the order above: the first of the smallest distances
 // below the cell's own), 8 for the cell's own centre (the destination, at
 // distance 0), 15 for none; bit 4: the distance is within the arrival
-// radius.  The FP32 comparisons are those the step would make, in the same
-// order, so the decisions are the same.
-constexpr int kCodeNone = 15, kCodeHere = 8, kCodeArrive = 16;
+// radius; bit 5: no obstacle cell within the repulsion window around the
+// cell; bit 6: the cell is walkable (the last two the same for every
+// destination).  The FP32 comparisons are those the step would make, in the
+// same order, so the decisions are the same.
+constexpr int kCodeNone = 15, kCodeHere = 8, kCodeArrive = 16, kCodeClear = 32, kCodeWalk = 64;
 
 // Repulsion of one neighbour or obstacle point at offset (rx, ry) from the
 // agent: A/m exp((r0 - d)/B) along the unit offset, zero outside (0, r_cut).
@@ -254,10 +256,26 @@ __device__ void agent_step(const PedParams& p, const AgentRec& rec, const float*
     if (moving && role == FPS_ROLE_EVACUEE && st == FPS_ST_EVAC && !any_wet) moving = false;
     // an agent without a valid destination (e.g. a responder with no barrier set) stands
     if (dest < 0 || dest >= p.n_dest) moving = false;
-    // second load round: everything addressed by the cell
+    // second load round: everything addressed by the cell.
+    // A 32 x 32 -> 64-bit product: the 64 x 64 one leaves its upper addend
+    // undefined, and the register chosen for it can be a load still in flight
+    const uint64_t doff = (uint64_t)(uint32_t)(moving ? dest : 0) * (uint64_t)(uint32_t)nc;
+    const float* D = p.dist + doff;
+    const uint8_t* K = p.codes + doff;
     const float h = fh[c], qxc = fqx[c], qyc = fqy[c];
+    const int kc = moving && p.use_codes ? (int)K[c] : 0;       // the cell's code of the destination
     uint4 m4 = make_uint4(0, 0, 0, 0);
-    if (p.use_wmask) m4 = p.wmask[c];
+    if (p.use_wmask) {
+        // with one lane per agent (many agents: the step is bound by memory
+        // traffic) the obstacle mask is read only where the code says an
+        // obstacle is near, a round later; with several lanes (few agents:
+        // bound by latency) it goes out with this round
+        if constexpr (L == 1) {
+            if (!(kc & kCodeClear)) m4 = p.wmask[c];
+        } else {
+            m4 = p.wmask[c];
+        }
+    }
     const int bi = ci / p.bsx, bj = cj / p.bsy;
     const int qi0 = max(bi - 1, 0), qi1 = min(bi + 1, p.nbx - 1);
     // both bounds of every bin row are loaded (a row outside the grid reads
@@ -279,17 +297,12 @@ __device__ void agent_step(const PedParams& p, const AgentRec& rec, const float*
     // distances of its field; the loads go out before the wait for the cell's
     // flood state (the hazard class below), so that they travel in the same
     // round as the cell's.
-    // A 32 x 32 -> 64-bit product: the 64 x 64 one leaves its upper addend
-    // undefined, and the register chosen for it can be a load still in flight
-    const uint64_t doff = (uint64_t)(uint32_t)(moving ? dest : 0) * (uint64_t)(uint32_t)nc;
-    const float* D = p.dist + doff;
-    const uint8_t* K = p.codes + doff;
     float ex = 0.0f, ey = 0.0f;    // desired direction
     if (moving) {
         bool has_target;
         int ti, tj;
         if (p.use_codes) {
-            const int code = K[c] & 15;
+            const int code = kc & 15;
             has_target = code <= kCodeHere;
             const bool here_c = code == kCodeHere;
             ti = here_c ? ci : ci + off_of(kOffXPacked, code & 7);
@@ -417,7 +430,7 @@ __device__ void agent_step(const PedParams& p, const AgentRec& rec, const float*
                 for (int j = 0; j < J; ++j)
                     if (sl[u][j] != self) repel(p, x - o[u][j].x, y - o[u][j].y, p.two_r, fx[j], fy[j]);
         }
-        const int wdth = 2 * p.Rx + 1, wcells = wdth * (2 * p.Ry + 1);
+        const int wdth = 2 * p.Rx + 1, wcells = (kc & kCodeClear) ? 0 : wdth * (2 * p.Ry + 1);
         const uint32_t wmagic = ((1u << 20) + (uint32_t)wdth - 1u) / (uint32_t)wdth;
         for (int b0 = 0; b0 < wcells; b0 += kSlots) {
 #pragma unroll
@@ -463,16 +476,21 @@ __device__ void agent_step(const PedParams& p, const AgentRec& rec, const float*
         const bool in_x = ni_try >= 0 && ni_try < p.nx, in_y = ny_try >= 0 && ny_try < p.ny;
         const size_t ix = (size_t)clampi(ni_try, 0, p.nx - 1), iy = (size_t)clampi(ny_try, 0, p.ny - 1);
         const size_t nxs = (size_t)p.nx;
-        const uint8_t w_x = p.walk[(size_t)cj * nxs + ix];      // (ni_try, cj)
-        const uint8_t w_xy = p.walk[iy * nxs + ix];             // (ni_try, ny_try)
-        const uint8_t w_y = p.walk[iy * nxs + ci];              // (ci, ny_try)
+        bool w_x, w_xy, w_y;                    // walkable: (ni_try, cj), (ni_try, ny_try), (ci, ny_try)
         bool arr_xy, arr_x, arr_y, arr_0;       // arrival at each cell the move may end in
         if (p.use_codes) {
-            arr_xy = K[iy * nxs + ix] & kCodeArrive;
-            arr_x = K[(size_t)cj * nxs + ix] & kCodeArrive;
-            arr_y = K[iy * nxs + ci] & kCodeArrive;
-            arr_0 = K[(size_t)cj * nxs + ci] & kCodeArrive;
+            const int k_xy = K[iy * nxs + ix], k_x = K[(size_t)cj * nxs + ix], k_y = K[iy * nxs + ci];
+            w_x = k_x & kCodeWalk;
+            w_xy = k_xy & kCodeWalk;
+            w_y = k_y & kCodeWalk;
+            arr_xy = k_xy & kCodeArrive;
+            arr_x = k_x & kCodeArrive;
+            arr_y = k_y & kCodeArrive;
+            arr_0 = kc & kCodeArrive;
         } else {
+            w_x = p.walk[(size_t)cj * nxs + ix];
+            w_xy = p.walk[iy * nxs + ix];
+            w_y = p.walk[iy * nxs + ci];
             arr_xy = D[iy * nxs + ix] <= p.r_arrive;
             arr_x = D[(size_t)cj * nxs + ix] <= p.r_arrive;
             arr_y = D[iy * nxs + ci] <= p.r_arrive;
@@ -932,8 +950,8 @@ __global__ void wall_mask_kernel(const uint8_t* walk, uint4* mask, int nx, int n
     mask[c] = make_uint4(m[0], m[1], m[2], m[3]);
 }
 
-__global__ void nav_code_kernel(const float* __restrict__ dist, int n_dest, int nx, int ny, float r_arrive,
-                                uint8_t* __restrict__ codes)
+__global__ void nav_code_kernel(const float* __restrict__ dist, const uint8_t* __restrict__ walk, int n_dest, int nx,
+                                int ny, float r_arrive, int Rx, int Ry, uint8_t* __restrict__ codes)
 {
     const int64_t nc = (int64_t)nx * ny;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -956,6 +974,12 @@ __global__ void nav_code_kernel(const float* __restrict__ dist, int n_dest, int 
     }
     int code = here == 0.0f ? kCodeHere : kb >= 0 ? kb : kCodeNone;
     if (here <= r_arrive) code |= kCodeArrive;
+    if (walk[c]) code |= kCodeWalk;
+    bool clear = true;        // no obstacle cell in the window (cells outside the grid are none)
+    for (int wj = max(cj - Ry, 0); wj <= min(cj + Ry, ny - 1) && clear; ++wj)
+        for (int wi = max(ci - Rx, 0); wi <= min(ci + Rx, nx - 1); ++wi)
+            clear = clear && walk[(int64_t)wj * nx + wi];
+    if (clear) code |= kCodeClear;
     codes[g] = (uint8_t)code;
 }
 
@@ -1016,13 +1040,13 @@ hipError_t launch_count_state(const uint8_t* state, int na, int value, int32_t* 
     if (na > 0) hipLaunchKernelGGL(count_state_kernel, dim3(blocks_for(na, 256)), dim3(256), 0, s, state, na, value, out);
     return hipGetLastError();
 }
-hipError_t launch_nav_codes(const float* dist, int n_dest, int nx, int ny, float r_arrive, uint8_t* codes,
-                            hipStream_t s)
+hipError_t launch_nav_codes(const float* dist, const uint8_t* walk, int n_dest, int nx, int ny, float r_arrive,
+                            int Rx, int Ry, uint8_t* codes, hipStream_t s)
 {
     const int64_t n = (int64_t)nx * ny * n_dest;
     if (n > 0)
-        hipLaunchKernelGGL(nav_code_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dist, n_dest, nx,
-                           ny, r_arrive, codes);
+        hipLaunchKernelGGL(nav_code_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dist, walk, n_dest,
+                           nx, ny, r_arrive, Rx, Ry, codes);
     return hipGetLastError();
 }
 hipError_t launch_bin_place_all(const Batch& b, hipStream_t s)
