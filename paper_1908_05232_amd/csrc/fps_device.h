@@ -208,11 +208,15 @@ __device__ inline void block_scan_chunks(const BinParams& b)
 
 // Placement of the agents into their bins by rank, then the stable order: an
 // agent's final slot counts the smaller ids of its own bin.  Whole-grid
-// version, in two kernels (one thread per agent).
+// version, in two kernels (one thread per agent).  An agent alone in its bin
+// (most of them in a sparse crowd) takes the bin's first slot directly: it
+// is neither placed nor compared.
 __device__ inline void place_agent(const BinParams& b, int a)
 {
     int k = b.key[a];
-    if (k >= 0) b.perm_u[b.bin_start[k] + b.rank[a]] = a;
+    if (k < 0) return;
+    const int s0 = b.bin_start[k], s1 = b.bin_start[k + 1];
+    if (s1 - s0 > 1) b.perm_u[s0 + b.rank[a]] = a;
 }
 __device__ inline void sort_agent(const BinParams& b, int a)
 {
@@ -220,7 +224,8 @@ __device__ inline void sort_agent(const BinParams& b, int a)
     if (k < 0) return;
     int s0 = b.bin_start[k], s1 = b.bin_start[k + 1];
     int below = 0;
-    for (int s = s0; s < s1; ++s) below += b.perm_u[s] < a;
+    if (s1 - s0 > 1)
+        for (int s = s0; s < s1; ++s) below += b.perm_u[s] < a;
     int f = s0 + below;
     b.perm[f] = a;
     b.slot[a] = f;
