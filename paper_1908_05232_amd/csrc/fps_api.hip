@@ -37,7 +37,7 @@ struct fps_sim {
     float *h2, *qx2, *qy2;
     float *h1, *qx1, *qy1;     // first stage of the second-order variant
     int32_t* np;
-    int32_t *bin_count, *bin_start, *rank, *key, *perm_u, *perm;
+    int32_t *bin_count, *bin_start, *rank, *key, *perm_u;
     float2* xy;
     int32_t* slot;
     uint4* wmask;
@@ -173,7 +173,7 @@ bool valid_desc(const fps_grid_desc* d, char* why)
 
 // Per-scenario part of the workspace (offsets from the member's base).
 struct Layout {
-    size_t st, partials, wet, h2, qx2, qy2, h1, qx1, qy1, np, bin_count, bin_start, rank, key, perm_u, perm, xy, slot,
+    size_t st, partials, wet, h2, qx2, qy2, h1, qx1, qy1, np, bin_count, bin_start, rank, key, perm_u, xy, slot,
         wmask, codes, line, stats, doors, csum, total;
     int64_t nbins_max;
     int32_t line_cap;
@@ -207,7 +207,6 @@ Layout member_layout(const fps_grid_desc* d, int32_t max_agents)
     L.rank = take(sizeof(int32_t) * na);
     L.key = take(sizeof(int32_t) * na);
     L.perm_u = take(sizeof(int32_t) * na);
-    L.perm = take(sizeof(int32_t) * na);
     L.xy = take(sizeof(float2) * na);
     L.slot = take(sizeof(int32_t) * na);
     L.wmask = take(max_agents > 0 ? sizeof(uint4) * nc : 0);
@@ -255,7 +254,6 @@ fps_sim* new_member(Engine* e, int idx, const fps_grid_desc* d, const fps_ped_pa
     s->rank = at<int32_t>(base, L.rank);
     s->key = at<int32_t>(base, L.key);
     s->perm_u = at<int32_t>(base, L.perm_u);
-    s->perm = at<int32_t>(base, L.perm);
     s->xy = at<float2>(base, L.xy);
     s->slot = at<int32_t>(base, L.slot);
     s->wmask = at<uint4>(base, L.wmask);
@@ -368,7 +366,7 @@ void fill_scn(const fps_sim* s, Scn& c)
     BinParams& b = c.bins;
     b.x = s->x; b.y = s->y; b.state = s->state; b.role = s->role;
     b.bin_count = s->bin_count; b.bin_start = s->bin_start; b.rank = s->rank; b.key = s->key;
-    b.perm_u = s->perm_u; b.perm = s->perm; b.xy = s->xy; b.slot = s->slot; b.np = s->np; b.csum = s->csum;
+    b.perm_u = s->perm_u; b.xy = s->xy; b.slot = s->slot; b.np = s->np; b.csum = s->csum;
     b.na = s->na; b.nbins = s->nbins; b.nx = s->G.nx; b.ny = s->G.ny;
     b.bsx = s->bsx; b.bsy = s->bsy; b.nbx = s->nbx;
     b.dx = (float)s->G.dx; b.dy = (float)s->G.dy;
@@ -1622,9 +1620,7 @@ int fps_get_bins(fps_sim* s, int32_t* bin_start, int32_t* perm, int32_t* nbins_o
     if (bin_start)
         HIPCHK(s, hipMemcpyAsync(bin_start, s->bin_start, sizeof(int32_t) * (s->nbins + 1),
                                  hipMemcpyDeviceToDevice, s->eng->stream));
-    if (perm)
-        HIPCHK(s, hipMemcpyAsync(perm, s->perm, sizeof(int32_t) * s->na, hipMemcpyDeviceToDevice,
-                                 s->eng->stream));
+    if (perm) HIPCHK(s, launch_perm_from_slots(s->key, s->slot, s->na, perm, s->eng->stream));
     return FPS_OK;
 }
 

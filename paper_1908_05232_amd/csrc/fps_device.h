@@ -227,7 +227,6 @@ __device__ inline void sort_agent(const BinParams& b, int a)
     if (s1 - s0 > 1)
         for (int s = s0; s < s1; ++s) below += b.perm_u[s] < a;
     int f = s0 + below;
-    b.perm[f] = a;
     b.slot[a] = f;
     b.xy[f] = make_float2(b.x[a], b.y[a]);
 }
@@ -270,7 +269,6 @@ __device__ inline void inline_bins_place(const BinParams& b)
         int below = 0;
         for (int s = s0[q]; s < s1[q]; ++s) below += lp[s] < a;
         const int f = s0[q] + below;
-        b.perm[f] = a;
         b.slot[a] = f;
         b.xy[f] = make_float2(ax[q], ay[q]);
     }
@@ -379,7 +377,6 @@ __device__ inline void lds_bins_build(const BinParams& b)
         int below = 0;
         for (int s = s0; s < s1; ++s) below += lp[s] < a;
         const int f = s0 + below;
-        b.perm[f] = a;
         b.slot[a] = f;
         b.xy[f] = make_float2(ax[q], ay[q]);
     }

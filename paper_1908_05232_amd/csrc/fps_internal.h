@@ -149,7 +149,6 @@ struct BinParams {
     int32_t* rank;
     int32_t* key;
     int32_t* perm_u;
-    int32_t* perm;
     float2* xy;
     int32_t* slot;
     int32_t* np;
@@ -205,6 +204,7 @@ int ped_lanes(int64_t total_agents);     // lanes per agent of the pedestrian st
 hipError_t launch_doors(const Batch& b, hipStream_t s);    // entries of the pre-flood flow, one block per scenario
 hipError_t launch_count_state(const uint8_t* state, int na, int value, int32_t* out, hipStream_t s);
 hipError_t launch_bin_place_all(const Batch& b, hipStream_t s);
+hipError_t launch_perm_from_slots(const int32_t* key, const int32_t* slot, int na, int32_t* perm, hipStream_t s);
 hipError_t launch_bin_chunk_sum(const Batch& b, hipStream_t s);    // multi-block scan: chunk counts
 hipError_t launch_bin_chunk_scan(const Batch& b, hipStream_t s);   // multi-block scan: bin starts
 hipError_t launch_bin_sort_all(const Batch& b, hipStream_t s);

@@ -881,6 +881,14 @@ __global__ __launch_bounds__(kChunkThreads) void bin_chunk_scan_kernel(Batch B)
     }
 }
 
+// the agents in bin order from each binned agent's slot (the step keeps only
+// the slots; this list is for reading the bins out)
+__global__ void perm_from_slots_kernel(const int32_t* key, const int32_t* slot, int na, int32_t* perm)
+{
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a < na && key[a] >= 0) perm[slot[a]] = a;
+}
+
 __global__ void count_kernel(BinParams b)
 {
     int a = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1047,6 +1055,12 @@ hipError_t launch_nav_codes(const float* dist, const uint8_t* walk, int n_dest, 
     if (n > 0)
         hipLaunchKernelGGL(nav_code_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dist, walk, n_dest,
                            nx, ny, r_arrive, Rx, Ry, codes);
+    return hipGetLastError();
+}
+hipError_t launch_perm_from_slots(const int32_t* key, const int32_t* slot, int na, int32_t* perm, hipStream_t s)
+{
+    if (na > 0)
+        hipLaunchKernelGGL(perm_from_slots_kernel, dim3(blocks_for(na, 256)), dim3(256), 0, s, key, slot, na, perm);
     return hipGetLastError();
 }
 hipError_t launch_bin_place_all(const Batch& b, hipStream_t s)
