@@ -414,8 +414,7 @@ typedef struct fps_sur fps_sur;
 int32_t fps_sur_param_count(void);
 size_t fps_sur_workspace_bytes(int32_t max_batch, int32_t H, int32_t W);
 /* Caps on the blocks the convolution and weight-gradient kernels launch
-   (0 = the defaults: one block per compute unit, and up to 512 blocks of
-   weight-gradient partials).  Both kernels walk their tiles with a stride of
+   (0 = the defaults: one block per compute unit for both).  Both kernels walk their tiles with a stride of
    the grid, so a cap makes every block take several tiles at any size (used to
    test that path on small images); the forward pass and input gradients are
    unchanged bit for bit, the weight gradients change only in the grouping of

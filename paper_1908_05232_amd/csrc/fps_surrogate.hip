@@ -16,9 +16,10 @@
 //     channels, issuing v_mfma_f32_16x16x32_bf16.  Forward and input-gradient
 //     passes use the same kernel (the latter with flipped, transposed weights).
 //   wgrad_kernel<CIN, COUT>: dW[co][tap][ci] = sum_p dz[p][co] x[p + tap][ci],
-//     M = COUT, N = 9 * CIN, K = pixels; dz and x are staged transposed in LDS
-//     (pixel-contiguous), one k-slab is one 32-pixel row of the tile; per-block
-//     FP32 partials are summed in a fixed order by reduce_kernel.
+//     M = COUT, N = 9 * CIN, K = pixels; dz and x are staged in LDS as one
+//     8-image vector per position and channel (a k-slab is 4 positions x 8
+//     images); per-block FP32 partials are summed in a fixed order by
+//     reduce_kernel.
 //   loss / mask / Adam / weight-prep / pack / apply: elementwise.
 #include <hip/hip_runtime.h>
 
@@ -38,12 +39,13 @@ typedef __bf16 bf16;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int TH = 8, TW = 32;     // pixel tile of one weight-gradient block
+constexpr int TW = 32;            // columns of the output tile of one convolution block
 constexpr int CTH = 16;            // rows of the output tile of one convolution block (x TW columns)
 constexpr int kMtPerWave = 4;      // 16-pixel M tiles per wave in the convolution (2 rows x 2)
 constexpr int kConvThreads = 512;  // 8 waves, two per SIMD: one computes while the other waits
-constexpr int kWgThreads = 512;    // weight gradient: 8 waves as well
-constexpr int kWgWaves = kWgThreads / 64;
+constexpr int kWgWaves = 4;        // weight gradient: 4 compute waves, one per SIMD (36 MFMA tiles each) ...
+constexpr int kWgLoaders = 256;    // ... and 4 loader waves that stage the next tile
+constexpr int kWgThreads = kWgWaves * 64 + kWgLoaders;
 constexpr int kThreads = 256;
 constexpr int kLayers = 5;
 constexpr int kCin[kLayers] = {16, 64, 64, 64, 64};
@@ -199,146 +201,237 @@ __global__ __launch_bounds__(kConvThreads) void conv_kernel(const bf16* __restri
 
 // ----------------------------------------------------------------------------
 // weight gradient: per-block partials of dW[co][tap][ci] over pixel tiles
+//
+// The reduction runs over pixels, so each MFMA's k index needs runs of
+// consecutive pixels per channel in LDS, and the nine taps shift those runs.
+// Here the eight k values a lane supplies are the same pixel of eight images
+// (images past the batch are zero): the LDS tiles hold, per pixel position
+// and channel, one 16-byte vector of the eight images, so a tap's shift moves
+// whole vectors and one copy of the input tile serves all nine taps.  A k-slab
+// of 32 is four positions (the four rows of the tile in one column) times
+// eight images.
+//
+// Tile: 4 rows x 8 columns of positions x 8 images (256 pixels).  LDS:
+//   dzL[pos][swz(co)][8 images], pos = row * 8 + col           (32 positions)
+//   xL[pos][swz(ci)][8 images],  pos = row * 10 + col, halo of one (60 positions)
+// with swz(c) = c ^ ((c >> 3) & 7) and a padded position stride, so that the
+// 16-byte stores of the staging (a lane per channel group) and the 16-byte
+// operand reads (a lane per channel) fall in distinct banks.
+// A compute wave owns one 16-channel input tile, every 16-channel output tile
+// and all nine taps, and walks the columns of its share of the tile with a
+// window of three input columns in registers: per column 3 new B operands and
+// COUT / 16 A operands feed 9 * COUT / 16 MFMAs.  Layers with fewer input
+// tiles than compute waves split the columns between waves, each writing a
+// partial of its own.  Four more waves only load: while the compute waves
+// work on a tile they fetch the next one, transpose it in registers and add
+// up its bias gradient, and between two barriers they store it to LDS.
 // ----------------------------------------------------------------------------
+constexpr int WTH = 4, WTW = 8, WNG = 8;      // weight-gradient tile: rows, columns, images
+__host__ __device__ constexpr int wg_pad(int c) { return c == 64 ? 8 : 2; }
+__host__ __device__ constexpr int wg_co_per(int cout) { return cout / 16; }
+__host__ __device__ constexpr int wg_groups(int cin, int cout) { return (cin / 16) * (cout / 16 / wg_co_per(cout)); }
+__host__ __device__ constexpr int wg_ksplit(int cin, int cout) { return kWgWaves / wg_groups(cin, cout); }
+__host__ __device__ constexpr size_t wg_lds(int cin, int cout)
+{
+    return (size_t)16 * (WTH * WTW * (cout + wg_pad(cout)) + (WTH + 2) * (WTW + 2) * (cin + wg_pad(cin)));
+}
+
+__device__ __forceinline__ int wg_swz(int c) { return c ^ ((c >> 3) & 7); }
+
 template <int CIN, int COUT>
 __global__ __launch_bounds__(kWgThreads) void wgrad_kernel(const bf16* __restrict__ X,
                                                          const bf16* __restrict__ DZ,
                                                          float* __restrict__ part, float* __restrict__ bpart,
                                                          int N, int H, int W)
 {
-    constexpr int MT = COUT / 16, NTAP = CIN / 16;     // N tiles per tap
-    constexpr int TILES = MT * 9 * NTAP;               // 16x16 output tiles
-    constexpr int PER_WAVE = (TILES + kWgWaves - 1) / kWgWaves;
-    constexpr int XROW = TW;                           // transposed x tile row length
+    static_assert(CIN == 16 || CIN == 64, "input channels");
+    static_assert(COUT == 16 || COUT == 64, "output channels");
+    constexpr int PSD = COUT + wg_pad(COUT), PSX = CIN + wg_pad(CIN);   // position strides, 16-byte units
+    constexpr int XW = WTW + 2, XPOS = (WTH + 2) * XW;
+    constexpr int NCO8 = COUT / 8, NCI8 = CIN / 8;
+    constexpr int DZU = WTH * WTW * NCO8, XU = XPOS * NCI8, UNITS = DZU + XU;   // staging units
+    constexpr int XPT = (UNITS + kWgLoaders - 1) / kWgLoaders;
+    constexpr int CO_PER = wg_co_per(COUT), NCIT = CIN / 16;
+    constexpr int G = wg_groups(CIN, COUT), KS = wg_ksplit(CIN, COUT), CPW = WTW / KS;
+    static_assert(G * KS == kWgWaves && WTW % KS == 0, "wave split");
+    static_assert(DZU <= kWgLoaders, "every dz unit in the first round of a fixed loader thread");
+    static_assert(kWgLoaders % NCO8 == 0, "fixed channel group per loader thread");
     extern __shared__ __align__(16) unsigned char smem[];
-    bf16* dzT = reinterpret_cast<bf16*>(smem);          // [COUT][TH*TW]
-    bf16* xT = dzT + COUT * TH * TW;                    // [CIN][(TH+2)][XROW] for one dx
+    bf16x8* dzL = reinterpret_cast<bf16x8*>(smem);
+    bf16x8* xL = dzL + WTH * WTW * PSD;
 
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int row16 = lane & 15, kgrp = lane >> 4;
-    f32x4 acc[PER_WAVE];
-#pragma unroll
-    for (int k = 0; k < PER_WAVE; ++k) acc[k] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    // bias gradient: a thread always stages the same 8 channels (channel group
-    // threadIdx.x % (COUT / 8)), so it sums them as it goes
-    static_assert(kWgThreads % (COUT / 8) == 0, "fixed channel group per thread");
+    const int wave = threadIdx.x >> 6;
+    const int tiles_x = W / WTW, tiles_y = H / WTH, per_grp = tiles_x * tiles_y;
+    const int ntiles = ((N + WNG - 1) / WNG) * per_grp;
     float bsum[8] = {};
 
-    const int tiles_x = W / TW, tiles_y = H / TH, per_img = tiles_x * tiles_y;
-    for (int tile = blockIdx.x; tile < N * per_img; tile += gridDim.x) {
-        const int n = tile / per_img, t = tile % per_img;
-        const int y0 = (t / tiles_x) * TH, x0 = (t % tiles_x) * TW;
-        __syncthreads();
-        // dz tile transposed: dzT[co][p], p = row * TW + col.  A thread takes
-        // an 8-pixel x 8-channel block: eight 16-byte loads, an 8 x 8
-        // transpose in registers, eight 16-byte LDS stores.  Pixel blocks are
-        // XOR-swizzled by the channel group (the MFMA reads use the same map)
-        // so that the stores of neighbouring channel groups hit other banks.
-        constexpr int NCG = COUT / 8, NPG = TH * TW / 8;
-        static_assert(NCG * NPG <= kWgThreads, "one dz block per thread");
-        if (threadIdx.x < NCG * NPG) {
-            const int cg = threadIdx.x % NCG, pg = threadIdx.x / NCG;
-            const int gy = y0 + (8 * pg) / TW, gx = x0 + (8 * pg) % TW;
-            const bf16* src = DZ + (((size_t)n * H + gy) * W + gx) * COUT + 8 * cg;
-            bf16x8 v[8];
+    if (wave >= kWgWaves) {
+        // ---- loader waves: fetch the next tile, transpose it in registers
+        // while the compute waves work, store it to LDS between the barriers
+        const int lt = threadIdx.x - kWgWaves * 64;
+        typedef bf16x8 Set[XPT][8];
+        Set s0;
+        // unit u: 8 images x 8 channels of one position; addresses clamped
+        // into the arrays, values outside the image or the batch zeroed
+        auto fetch = [&](Set& v, int t) {
+            const int n0 = (t / per_grp) * WNG, r = t % per_grp;
+            const int y0 = (r / tiles_x) * WTH, x0 = (r % tiles_x) * WTW;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) v[q] = *reinterpret_cast<const bf16x8*>(src + (size_t)q * COUT);
+            for (int u = 0; u < XPT; ++u) {
+                const int q = lt + u * kWgLoaders;
+                const bool isdz = q < DZU;
+                const int qq = isdz ? q : q - DZU;
+                const int nc8 = isdz ? NCO8 : NCI8, C = isdz ? COUT : CIN;
+                const int pos = qq / nc8, cg = qq % nc8;
+                const int gy = isdz ? y0 + pos / WTW : y0 + pos / XW - 1;
+                const int gx = isdz ? x0 + pos % WTW : x0 + pos % XW - 1;
+                const bool in = q < UNITS && gy >= 0 && gy < H && gx >= 0 && gx < W;
+                const bf16* src = (isdz ? DZ : X) +
+                                  ((size_t)min(max(gy, 0), H - 1) * W + min(max(gx, 0), W - 1)) * C + 8 * cg;
+                const size_t img = (size_t)H * W * C;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                bf16x8 t;
-#pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    t[q] = v[q][e];
-                    bsum[e] += to_f32(v[q][e]);
+                for (int j = 0; j < 8; ++j) {
+                    const bf16x8 l = *reinterpret_cast<const bf16x8*>(src + (size_t)min(n0 + j, N - 1) * img);
+                    v[u][j] = in && n0 + j < N ? l : bf16x8{};
                 }
-                *reinterpret_cast<bf16x8*>(dzT + (8 * cg + e) * (TH * TW) + 8 * (pg ^ (cg & 7))) = t;
             }
+        };
+        // v[u][j][e] (image j, channel e) -> v[u][e][j]; dz units add to the bias sums
+        auto transpose = [&](Set& v) {
+#pragma unroll
+            for (int u = 0; u < XPT; ++u) {
+                const int q = lt + u * kWgLoaders;
+                if (u == 0 && q < DZU) {
+#pragma unroll
+                    for (int j = 0; j < 8; ++j)
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) bsum[e] += to_f32(v[u][j][e]);
+                }
+                bf16x8 tv[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) tv[e][j] = v[u][j][e];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) v[u][e] = tv[e];
+            }
+        };
+        auto store = [&](Set& v) {
+#pragma unroll
+            for (int u = 0; u < XPT; ++u) {
+                const int q = lt + u * kWgLoaders;
+                if (q >= UNITS) continue;
+                const bool isdz = q < DZU;
+                const int pos = isdz ? q / NCO8 : (q - DZU) / NCI8;
+                const int cg = isdz ? q % NCO8 : (q - DZU) % NCI8;
+                bf16x8* dst = isdz ? dzL + pos * PSD : xL + pos * PSX;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) dst[wg_swz(8 * cg + e)] = v[u][e];
+            }
+        };
+        // the next tile's loads are issued at barrier A and land during the
+        // compute of this one
+        fetch(s0, blockIdx.x);
+        transpose(s0);
+        store(s0);
+        for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+            __syncthreads();                  // A: tile t is in LDS
+            const int t1 = t + gridDim.x;
+            if (t1 < ntiles) {
+                fetch(s0, t1);
+                transpose(s0);
+            }
+            __syncthreads();                  // B: the compute waves are done with tile t
+            if (t1 < ntiles) store(s0);
         }
-        for (int dx = 0; dx < 3; ++dx) {
-            __syncthreads();
-            // x tile for this column offset, transposed: xT[ci][ly][col] = x[y0+ly-1][x0+col+dx-1][ci],
-            // in 8-column x 8-channel blocks as above (column blocks swizzled by the channel group)
-            constexpr int NCI = CIN / 8, NXB = (TH + 2) * (XROW / 8);
-            static_assert(NCI * NXB <= kWgThreads, "one x block per thread");
-            if (threadIdx.x < NCI * NXB) {
-                const int cg = threadIdx.x % NCI, xb = threadIdx.x / NCI;
-                const int ly = xb / (XROW / 8), cb = xb % (XROW / 8);
-                const int gy = y0 + ly - 1, gx0 = x0 + 8 * cb + dx - 1;
-                bf16x8 v[8];
+    } else {
+        // ---- compute waves
+        const int lane = threadIdx.x & 63;
+        const int row16 = lane & 15, kgrp = lane >> 4;
+        const int grp = wave % G, ks = wave / G;
+        const int ct = grp % NCIT, cp = grp / NCIT;
+        f32x4 acc[CO_PER][9];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const int gx = gx0 + q;
-                    v[q] = bf16x8{};
-                    if (gy >= 0 && gy < H && gx >= 0 && gx < W)
-                        v[q] = *reinterpret_cast<const bf16x8*>(X + (((size_t)n * H + gy) * W + gx) * CIN + 8 * cg);
-                }
+        for (int j = 0; j < CO_PER; ++j)
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    bf16x8 t;
+            for (int k = 0; k < 9; ++k) acc[j][k] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        const int ci_sw = wg_swz(16 * ct + row16);
+        int co_sw[CO_PER];
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) t[q] = v[q][e];
-                    *reinterpret_cast<bf16x8*>(xT + (8 * cg + e) * ((TH + 2) * XROW) + ly * XROW +
-                                               8 * (cb ^ (cg & (XROW / 8 - 1)))) = t;
-                }
+        for (int j = 0; j < CO_PER; ++j) co_sw[j] = wg_swz(16 * (cp * CO_PER + j) + row16);
+        const int c0 = ks * CPW;
+        for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+            __syncthreads();                  // A
+            // window of input columns: win[dy][k % 3] holds halo column c0 + k, rows kgrp + dy
+            bf16x8 win[3][3];
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                for (int k = 0; k < 2; ++k) win[dy][k] = xL[((kgrp + dy) * XW + c0 + k) * PSX + ci_sw];
+#pragma unroll
+            for (int cc = 0; cc < CPW; ++cc) {
+                const int c = c0 + cc;
+#pragma unroll
+                for (int dy = 0; dy < 3; ++dy) win[dy][(cc + 2) % 3] = xL[((kgrp + dy) * XW + c + 2) * PSX + ci_sw];
+                bf16x8 a[CO_PER];
+#pragma unroll
+                for (int j = 0; j < CO_PER; ++j) a[j] = dzL[(kgrp * WTW + c) * PSD + co_sw[j]];
+#pragma unroll
+                for (int j = 0; j < CO_PER; ++j)
+#pragma unroll
+                    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                        for (int dx = 0; dx < 3; ++dx)
+                            acc[j][dy * 3 + dx] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                a[j], win[dy][(cc + dx) % 3], acc[j][dy * 3 + dx], 0, 0, 0);
             }
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < PER_WAVE; ++k) {
-                const int tl = wave + kWgWaves * k;
-                if (tl >= TILES) break;
-                const int mt = tl / (9 * NTAP), rest = tl % (9 * NTAP);
-                const int tap = rest / NTAP, ci0 = (rest % NTAP) * 16;
-                if (tap % 3 != dx) continue;
-                const int dy = tap / 3;
-                const int co = 16 * mt + row16, ci = ci0 + row16;
-                for (int r = 0; r < TH; ++r) {
-                    // k-slab: pixels of tile row r, the lane's 8 columns 8*kgrp.. (swizzled blocks)
-                    const bf16x8 a = *reinterpret_cast<const bf16x8*>(
-                        dzT + co * (TH * TW) + 8 * ((r * (TW / 8) + kgrp) ^ ((co / 8) & 7)));
-                    const bf16x8 b = *reinterpret_cast<const bf16x8*>(
-                        xT + ci * ((TH + 2) * XROW) + (r + dy) * XROW + 8 * (kgrp ^ ((ci / 8) & (XROW / 8 - 1))));
-                    acc[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[k], 0, 0, 0);
-                }
-            }
+            __syncthreads();                  // B
         }
+        // partial [block * KS + ks][co][tap][ci]; D tile lane holds rows (co) 4*kgrp + r, column (ci) row16
+        float* pb = part + ((size_t)blockIdx.x * KS + ks) * COUT * 9 * CIN;
+        const int ci = 16 * ct + row16;
+#pragma unroll
+        for (int j = 0; j < CO_PER; ++j)
+#pragma unroll
+            for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int co = 16 * (cp * CO_PER + j) + 4 * kgrp + r;
+                    pb[((size_t)co * 9 + tap) * CIN + ci] = acc[j][tap][r];
+                }
     }
-    // bias partial of the block: the threads of each channel group in thread order
+    // bias partial of the block: the loader threads of each channel group in thread order
     __syncthreads();
     float* bs = reinterpret_cast<float*>(smem);
+    if (wave >= kWgWaves) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) bs[threadIdx.x * 8 + e] = bsum[e];
+        for (int e = 0; e < 8; ++e) bs[(threadIdx.x - kWgWaves * 64) * 8 + e] = bsum[e];
+    }
     __syncthreads();
     if (threadIdx.x < COUT) {
         const int g = threadIdx.x / 8, e = threadIdx.x % 8;
-        float t = 0.0f;
-        for (int th = g; th < kWgThreads; th += COUT / 8) t += bs[th * 8 + e];
-        bpart[(size_t)blockIdx.x * COUT + threadIdx.x] = t;
-    }
-    // partial [block][co][tap][ci]; D tile lane holds rows (co) 4*kgrp + r, column (ci) row16
-    float* pb = part + (size_t)blockIdx.x * COUT * 9 * CIN;
-#pragma unroll
-    for (int k = 0; k < PER_WAVE; ++k) {
-        const int tl = wave + kWgWaves * k;
-        if (tl >= TILES) break;
-        const int mt = tl / (9 * NTAP), rest = tl % (9 * NTAP);
-        const int tap = rest / NTAP, ci0 = (rest % NTAP) * 16;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int co = 16 * mt + 4 * kgrp + r;
-            pb[((size_t)co * 9 + tap) * CIN + ci0 + row16] = acc[k][r];
-        }
+        float s = 0.0f;
+        for (int th = g; th < kWgLoaders; th += NCO8) s += bs[th * 8 + e];
+        bpart[(size_t)blockIdx.x * COUT + threadIdx.x] = s;
     }
 }
 
 // Sum of the per-block partials of every output element in a fixed order:
 // 16 threads per element each sum every 16th block, then the 16 sums are
-// added in thread order.  Block: 64 elements x 16 groups.
-__global__ __launch_bounds__(1024) void reduce_kernel(const float* __restrict__ part, int nblocks, int count,
-                                                      float* __restrict__ out)
+// added in thread order.  Block: 64 elements x 16 groups.  The blocks past
+// the weights' (count / 64 rounded up) do the same for the bias partials.
+__global__ __launch_bounds__(1024) void reduce_kernel(const float* __restrict__ wpart, int nwparts, int wcount,
+                                                      float* __restrict__ wout, const float* __restrict__ bpart,
+                                                      int nbparts, int bcount, float* __restrict__ bout)
 {
     __shared__ float red[16][64];
+    const int wblocks = (wcount + 63) / 64;
+    const bool bias = (int)blockIdx.x >= wblocks;
+    const float* part = bias ? bpart : wpart;
+    const int nblocks = bias ? nbparts : nwparts, count = bias ? bcount : wcount;
+    float* out = bias ? bout : wout;
     const int o = threadIdx.x & 63, g = threadIdx.x >> 6;
-    const int i = blockIdx.x * 64 + o;
+    const int i = (blockIdx.x - (bias ? wblocks : 0)) * 64 + o;
     float s = 0.0f;
     if (i < count) {
         int b = g;
@@ -391,19 +484,37 @@ __global__ void loss_kernel(const float* __restrict__ pred, const float* __restr
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
+// sum of the loss partials in a fixed order: thread t adds partials t,
+// t + 256, ...; then a tree over the 256 thread sums.  One block of kThreads.
 __global__ void sum_kernel(const float* __restrict__ part, int n, float scale, float* __restrict__ out)
 {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        float s = 0.0f;
-        for (int i = 0; i < n; ++i) s += part[i];
-        *out = s * scale;
+    __shared__ float red[kThreads];
+    float s = 0.0f;
+    for (int i = threadIdx.x; i < n; i += kThreads) s += part[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = kThreads / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
     }
+    if (threadIdx.x == 0) *out = red[0] * scale;
 }
 
-// Adam on FP32 master parameters (bias-corrected)
+// Adam on FP32 master parameters (bias-corrected).
+// BF16 copies of the weights a layer's passes read (see prep_weights_kernel)
+struct WeightCopies {
+    bf16* wf[kLayers];
+    bf16* wd[kLayers];       // nullptr for the first layer (no input gradient)
+    int off[kLayers + 1];    // parameter offset of each layer
+    int cin[kLayers], cout[kLayers];
+};
+
+// Adam step of every parameter; the new weights go straight into the BF16
+// copies of the forward and input-gradient passes (their zero padding is
+// written once, by prep_weights_kernel)
 __global__ void adam_kernel(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
                             const float* __restrict__ g, int n, float lr, float b1, float b2, float eps,
-                            float c1, float c2)
+                            float c1, float c2, WeightCopies wc)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -412,7 +523,17 @@ __global__ void adam_kernel(float* __restrict__ w, float* __restrict__ m, float*
     const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
     m[i] = mi;
     v[i] = vi;
-    w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    w[i] = wi;
+    int l = 0;
+#pragma unroll
+    for (int k = 1; k < kLayers; ++k) l += i >= wc.off[k];
+    const int j = i - wc.off[l], cin = wc.cin[l], cout = wc.cout[l];
+    if (j < cout * 9 * cin) {
+        const int co = j / (9 * cin), tap = (j / cin) % 9, ci = j % cin;
+        wc.wf[l][co * kp_of(cin) + tap * cin + ci] = to_bf16(wi);
+        if (wc.wd[l]) wc.wd[l][ci * kp_of(cout) + (8 - tap) * cout + co] = to_bf16(wi);
+    }
 }
 
 // bf16 weights for the forward pass [COUT][KP] (k = tap*CIN + ci) and for the
@@ -727,20 +848,21 @@ int conv(fps_sur* s, int n, const bf16* x, const bf16* w, const float* b, void* 
 template <int CIN, int COUT>
 int wgrad(fps_sur* s, int n, const bf16* x, const bf16* dz, int layer)
 {
-    const size_t lds = (size_t)COUT * TH * TW * 2 + (size_t)CIN * (TH + 2) * TW * 2;
+    const size_t lds = wg_lds(CIN, COUT);
     auto k = wgrad_kernel<CIN, COUT>;
     SCHK(s, hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    const int tiles = n * (s->H / TH) * (s->W / TW);
-    const int blocks = std::min(tiles, s->wgrad_cap > 0 ? std::min(s->wgrad_cap, kWgradBlocks) : kWgradBlocks);
+    const int tiles = (n + WNG - 1) / WNG * (s->H / WTH) * (s->W / WTW);
+    // persistent: one block per compute unit (or fewer, when capped)
+    const int cap = std::min(s->cus, kWgradBlocks);
+    const int blocks = std::min(tiles, s->wgrad_cap > 0 ? std::min(s->wgrad_cap, cap) : cap);
+    const int nparts = blocks * wg_ksplit(CIN, COUT);
     hipLaunchKernelGGL(k, dim3(blocks), dim3(kWgThreads), lds, s->stream, x, dz, s->wpart, s->bpart, n, s->H,
                        s->W);
     SCHK(s, hipGetLastError());
     const int count = COUT * 9 * CIN;
     float* dw = s->grads + param_offset(layer);
-    hipLaunchKernelGGL(reduce_kernel, dim3((count + 63) / 64), dim3(1024), 0, s->stream, s->wpart, blocks, count,
-                       dw);
-    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, s->stream, s->bpart, blocks, COUT,
-                       dw + w_count(layer));
+    hipLaunchKernelGGL(reduce_kernel, dim3((count + 63) / 64 + (COUT + 63) / 64), dim3(1024), 0, s->stream,
+                       s->wpart, nparts, count, dw, s->bpart, blocks, COUT, dw + w_count(layer));
     SCHK(s, hipGetLastError());
     return FPS_OK;
 }
@@ -977,7 +1099,7 @@ int fps_sur_gradients(fps_sur* s, int32_t n, const void* xv, const float* target
     const float scale = 1.0f / (float)(npix * kOutUsed);
     hipLaunchKernelGGL(loss_kernel, dim3(kLossBlocks), dim3(kThreads), 0, s->stream, s->y, target, npix, scale,
                        s->dz5, s->lpart);
-    hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(64), 0, s->stream, s->lpart, kLossBlocks, scale, loss);
+    hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(kThreads), 0, s->stream, s->lpart, kLossBlocks, scale, loss);
     SCHK(s, hipGetLastError());
     // layer 5 (no ReLU): dz5 -> dW5; its input gradient masked by the ReLU of
     // layer 4 is dz of layer 4.  Then down the layers, dz ping-ponging
@@ -1011,10 +1133,19 @@ int fps_sur_adam(fps_sur* s, float lr)
     const float b1 = 0.9f, b2 = 0.999f;
     const float c1 = 1.0f - std::pow(b1, (float)s->adam_step), c2 = 1.0f - std::pow(b2, (float)s->adam_step);
     const int n = (int)total_params();
+    WeightCopies wc{};
+    for (int l = 0; l < kLayers; ++l) {
+        wc.wf[l] = s->wf[l];
+        wc.wd[l] = l > 0 ? s->wd[l] : nullptr;
+        wc.off[l] = (int)param_offset(l);
+        wc.cin[l] = kCin[l];
+        wc.cout[l] = kCout[l];
+    }
+    wc.off[kLayers] = n;
     hipLaunchKernelGGL(adam_kernel, dim3((n + 255) / 256), dim3(256), 0, s->stream, s->params, s->m, s->v,
-                       s->grads, n, lr, b1, b2, 1e-8f, c1, c2);
+                       s->grads, n, lr, b1, b2, 1e-8f, c1, c2, wc);
     SCHK(s, hipGetLastError());
-    return prep_weights(s);
+    return FPS_OK;
 }
 
 int fps_sur_train_step(fps_sur* s, int32_t n, const void* x, const float* target, float lr, float* loss)

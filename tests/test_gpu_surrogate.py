@@ -122,9 +122,10 @@ def test_multi_tile_gradients_match_oracle():
     """Every block walks several tiles: the kernels' grid-stride paths (next
     tile prefetched during the matrix work, LDS re-deposit, partial weight
     gradients accumulated over tiles) against the oracle, element by element.
-    3 images of 48 x 96 make 27 convolution tiles and 54 weight-gradient
-    tiles; caps of 5 and 7 blocks give each block 5-6 and 7-8 of them, the
-    last block fewer (ragged).  The forward pass must not change at all under
+    3 images of 48 x 96 make 27 convolution tiles (16 x 32 pixels) and 144
+    weight-gradient tiles (4 x 8 positions of the 8-image group, 5 of the 8
+    images past the batch); caps of 5 and 7 blocks give each block 5-6 and
+    20-21 of them, the last block fewer (ragged).  The forward pass must not change at all under
     the caps, the gradients only by the grouping of their FP32 partial sums."""
     params, x, target = make_case(9, 3, 48, 96)
     sur = fps.Surrogate(3, 48, 96)
