@@ -10,11 +10,16 @@
 //
 // Kernels
 //   conv_kernel<CIN, COUT, MODE>: implicit GEMM, M = pixels, N = COUT,
-//     K = 9 * CIN.  A block computes an 8 x 32 pixel tile; the input tile with
-//     its one-pixel halo and the whole weight matrix are staged in LDS; each of
-//     the 4 waves owns two image rows (four 16-pixel M tiles) and all COUT
-//     channels, issuing v_mfma_f32_16x16x32_bf16.  Forward and input-gradient
-//     passes use the same kernel (the latter with flipped, transposed weights).
+//     K = 9 * CIN, for the 16-channel input of the first layer (and the input
+//     gradient through the last).  A persistent block computes 16 x 32 pixel
+//     tiles; the input tile with its one-pixel halo and the whole weight
+//     matrix are staged in LDS; each of the 8 waves owns two image rows (four
+//     16-pixel M tiles) and all COUT channels, issuing
+//     v_mfma_f32_16x16x32_bf16.  Forward and input-gradient passes use the
+//     same kernel (the latter with flipped, transposed weights).
+//   conv64_kernel<COUT, MODE>: the same for 64 input channels, with compute
+//     waves of 4 rows each that reuse every loaded operand for several MFMAs
+//     and loader waves that stage the next tile.
 //   wgrad_kernel<CIN, COUT>: dW[co][tap][ci] = sum_p dz[p][co] x[p + tap][ci],
 //     M = COUT, N = 9 * CIN, K = pixels; dz and x are staged in LDS as one
 //     8-image vector per position and channel (a k-slab is 4 positions x 8
@@ -132,6 +137,9 @@ __global__ __launch_bounds__(kConvThreads) void conv_kernel(const bf16* __restri
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int row16 = lane & 15, kgrp = lane >> 4;
+    float bb[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) bb[nt] = bias ? bias[16 * nt + row16] : 0.0f;
     for (; t < ntiles; t += gridDim.x) {
         const int n = t / per_img, r = t % per_img;
         const int y0 = (r / tiles_x) * CTH, x0 = (r % tiles_x) * TW;
@@ -167,24 +175,31 @@ __global__ __launch_bounds__(kConvThreads) void conv_kernel(const bf16* __restri
                     acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], b[nt], acc[mt][nt], 0, 0, 0);
         }
 
-        // D tile: lane holds rows (pixels) 4*kgrp + r, column (channel) row16
+        // D tile: lane holds rows (pixels) 4*kgrp + r, column (channel) row16.
+        // One M tile at a time: its mask values (MODE 3) loaded together, then the stores.
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
             const int gy = y0 + 2 * wave + (mt >> 1);
+            const size_t p0 = ((size_t)n * H + gy) * W + x0 + 16 * (mt & 1) + 4 * kgrp;
+            bf16 mk[NT][4];
+            if (MODE == 3) {
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                    for (int rr = 0; rr < 4; ++rr) mk[nt][rr] = mask[(p0 + rr) * COUT + 16 * nt + row16];
+            }
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
                 const int co = 16 * nt + row16;
-                const float bb = bias ? bias[co] : 0.0f;
 #pragma unroll
                 for (int rr = 0; rr < 4; ++rr) {
-                    const int gx = x0 + 16 * (mt & 1) + 4 * kgrp + rr;
-                    float v = acc[mt][nt][rr] + bb;
-                    const size_t p = ((size_t)n * H + gy) * W + gx;
+                    float v = acc[mt][nt][rr] + bb[nt];
+                    const size_t p = p0 + rr;
                     if (MODE == 0) {
                         reinterpret_cast<bf16*>(Y)[p * COUT + co] = to_bf16(fmaxf(v, 0.0f));
                     } else if (MODE == 3) {
                         reinterpret_cast<bf16*>(Y)[p * COUT + co] =
-                            to_f32(mask[p * COUT + co]) > 0.0f ? to_bf16(v) : to_bf16(0.0f);
+                            to_f32(mk[nt][rr]) > 0.0f ? to_bf16(v) : to_bf16(0.0f);
                     } else {
                         if (co < 4) reinterpret_cast<float*>(Y)[p * 4 + co] = co < kOutUsed ? v : 0.0f;
                     }
@@ -195,6 +210,181 @@ __global__ __launch_bounds__(kConvThreads) void conv_kernel(const bf16* __restri
             __syncthreads();          // every wave is done with this tile's input
             deposit();
             __syncthreads();
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// convolution with 64 input channels (the four layers after the first, and the
+// input gradients through them): the same implicit GEMM and modes as
+// conv_kernel, organised so that each operand loaded from LDS feeds more
+// matrix work.  A compute wave owns 4 output rows x 32 columns x all COUT
+// channels (4 x 2 x COUT/16 accumulator tiles).  The reduction runs over
+// (dx, channel half, dy): for a fixed dx and half of the input channels the
+// wave loads the 3 x COUT/16 weight operands of the three dy taps once, then
+// streams the 6 input rows its output rows need, and each input row's two
+// operands feed every (output row, dy) pair that reads that row: 12 A and 12 B
+// loads per 96 MFMAs for COUT = 64.  Four loader waves fetch the next tile's
+// input into registers during the matrix work and store it to LDS between
+// two barriers.
+// ----------------------------------------------------------------------------
+constexpr int kC64Waves = 4, kC64Loaders = 256, kC64Threads = kC64Waves * 64 + kC64Loaders;
+constexpr int kC64Rows = CTH / kC64Waves;     // output rows per compute wave
+
+template <int COUT, int MODE>
+__global__ __launch_bounds__(kC64Threads) void conv64_kernel(const bf16* __restrict__ X,
+                                                           const bf16* __restrict__ Wt,
+                                                           const float* __restrict__ bias,
+                                                           void* __restrict__ Y, int N, int H, int W,
+                                                           const bf16* __restrict__ mask)
+{
+    constexpr int CIN = 64, KP = kp_of(CIN);
+    constexpr int PIX = CIN + 8;        // padded pixel stride in LDS (bank spread, 16-byte rows)
+    constexpr int WST = KP + 8;         // padded weight row stride in LDS
+    constexpr int NT = COUT / 16, R = kC64Rows;
+    constexpr int CHUNKS = (CTH + 2) * (TW + 2) * (CIN / 8);
+    constexpr int XPT = (CHUNKS + kC64Loaders - 1) / kC64Loaders;
+    constexpr int WCH = COUT * (KP / 8);
+    static_assert(KP == 9 * CIN, "no padding of the reduction");
+    extern __shared__ __align__(16) unsigned char smem[];
+    bf16* xin = reinterpret_cast<bf16*>(smem);                        // [(CTH+2)(TW+2)][PIX]
+    bf16* wl = xin + (CTH + 2) * (TW + 2) * PIX;                       // [COUT][WST]
+
+    const int tiles_x = W / TW, tiles_y = H / CTH, per_img = tiles_x * tiles_y;
+    const int ntiles = N * per_img;
+    const int wave = threadIdx.x >> 6;
+    if ((int)blockIdx.x >= ntiles) return;
+    // the weights [COUT][KP], once per block
+    for (int q = threadIdx.x; q < WCH; q += kC64Threads) {
+        const int co = q / (KP / 8), k8 = (q % (KP / 8)) * 8;
+        *reinterpret_cast<bf16x8*>(wl + co * WST + k8) = *reinterpret_cast<const bf16x8*>(Wt + (size_t)co * KP + k8);
+    }
+
+    if (wave >= kC64Waves) {
+        // ---- loader waves
+        const int lt = threadIdx.x - kC64Waves * 64;
+        bf16x8 xb[XPT];
+        // input tile (with halo, zeros outside the image) of tile t into registers
+        auto fetch = [&](int t) {
+            const int n = t / per_img, r = t % per_img;
+            const int y0 = (r / tiles_x) * CTH, x0 = (r % tiles_x) * TW;
+            const bf16* Xn = X + (size_t)n * H * W * CIN;
+#pragma unroll
+            for (int u = 0; u < XPT; ++u) {
+                const int q = lt + u * kC64Loaders;
+                const int px = q / (CIN / 8), c8 = (q % (CIN / 8)) * 8;
+                const int gy = y0 + px / (TW + 2) - 1, gx = x0 + px % (TW + 2) - 1;
+                const bool in = q < CHUNKS && gy >= 0 && gy < H && gx >= 0 && gx < W;
+                const bf16x8 l = *reinterpret_cast<const bf16x8*>(
+                    Xn + ((size_t)min(max(gy, 0), H - 1) * W + min(max(gx, 0), W - 1)) * CIN + c8);
+                xb[u] = in ? l : bf16x8{};
+            }
+        };
+        auto deposit = [&]() {
+#pragma unroll
+            for (int u = 0; u < XPT; ++u) {
+                const int q = lt + u * kC64Loaders;
+                if (q < CHUNKS) {
+                    const int px = q / (CIN / 8), c8 = (q % (CIN / 8)) * 8;
+                    *reinterpret_cast<bf16x8*>(xin + px * PIX + c8) = xb[u];
+                }
+            }
+        };
+        fetch(blockIdx.x);
+        deposit();
+        for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+            __syncthreads();                  // A: tile t (and the weights) in LDS
+            const int tn = t + gridDim.x;
+            if (tn < ntiles) fetch(tn);
+            __syncthreads();                  // B: the compute waves are done with tile t
+            if (tn < ntiles) deposit();
+        }
+        return;
+    }
+
+    // ---- compute waves
+    const int lane = threadIdx.x & 63;
+    const int row16 = lane & 15, kgrp = lane >> 4;
+    float bb[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) bb[nt] = bias ? bias[16 * nt + row16] : 0.0f;
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int n = t / per_img, r = t % per_img;
+        const int y0 = (r / tiles_x) * CTH, x0 = (r % tiles_x) * TW;
+        __syncthreads();                      // A
+        f32x4 acc[R][2][NT];
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+#pragma unroll
+            for (int hf = 0; hf < 2; ++hf)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) acc[i][hf][nt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 1
+        for (int s = 0; s < 6; ++s) {
+            const int dx = s >> 1, c = 32 * (s & 1) + 8 * kgrp;
+            bf16x8 b[3][NT];
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+                    b[dy][nt] = *reinterpret_cast<const bf16x8*>(wl + (16 * nt + row16) * WST + (dy * 3 + dx) * CIN + c);
+            // input row xr of the wave's window is tile row R * wave + xr (one halo row above)
+#pragma unroll
+            for (int xr = 0; xr < R + 2; ++xr) {
+                bf16x8 a[2];
+#pragma unroll
+                for (int hf = 0; hf < 2; ++hf)
+                    a[hf] = *reinterpret_cast<const bf16x8*>(
+                        xin + ((R * wave + xr) * (TW + 2) + 16 * hf + row16 + dx) * PIX + c);
+#pragma unroll
+                for (int dy = 0; dy < 3; ++dy) {
+                    const int i = xr - dy;
+                    if (i < 0 || i >= R) continue;
+#pragma unroll
+                    for (int hf = 0; hf < 2; ++hf)
+#pragma unroll
+                        for (int nt = 0; nt < NT; ++nt)
+                            acc[i][hf][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[hf], b[dy][nt], acc[i][hf][nt], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();                      // B: the loaders may overwrite the input tile
+
+        // D tile: lane holds rows (pixels) 4*kgrp + r, column (channel) row16.
+        // One output row at a time: its mask values (MODE 3) loaded together, then the stores.
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const int gy = y0 + R * wave + i;
+            const size_t p0 = ((size_t)n * H + gy) * W + x0 + 4 * kgrp;
+            bf16 mk[2][NT][4];
+            if (MODE == 3) {
+#pragma unroll
+                for (int hf = 0; hf < 2; ++hf)
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                        for (int rr = 0; rr < 4; ++rr)
+                            mk[hf][nt][rr] = mask[(p0 + 16 * hf + rr) * COUT + 16 * nt + row16];
+            }
+#pragma unroll
+            for (int hf = 0; hf < 2; ++hf)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) {
+                    const int co = 16 * nt + row16;
+#pragma unroll
+                    for (int rr = 0; rr < 4; ++rr) {
+                        const float v = acc[i][hf][nt][rr] + bb[nt];
+                        const size_t p = p0 + 16 * hf + rr;
+                        if (MODE == 0) {
+                            reinterpret_cast<bf16*>(Y)[p * COUT + co] = to_bf16(fmaxf(v, 0.0f));
+                        } else if (MODE == 3) {
+                            reinterpret_cast<bf16*>(Y)[p * COUT + co] =
+                                to_f32(mk[hf][nt][rr]) > 0.0f ? to_bf16(v) : to_bf16(0.0f);
+                        } else {
+                            if (co < 4) reinterpret_cast<float*>(Y)[p * 4 + co] = co < kOutUsed ? v : 0.0f;
+                        }
+                    }
+                }
         }
     }
 }
@@ -834,12 +1024,20 @@ int conv(fps_sur* s, int n, const bf16* x, const bf16* w, const float* b, void* 
 {
     constexpr int KP = kp_of(CIN);
     const size_t lds = (size_t)(CTH + 2) * (TW + 2) * (CIN + 8) * 2 + (size_t)COUT * (KP + 8) * 2;
-    auto k = conv_kernel<CIN, COUT, MODE>;
+    void (*k)(const bf16*, const bf16*, const float*, void*, int, int, int, const bf16*);
+    int threads;
+    if constexpr (CIN == 64) {
+        k = conv64_kernel<COUT, MODE>;
+        threads = kC64Threads;
+    } else {
+        k = conv_kernel<CIN, COUT, MODE>;
+        threads = kConvThreads;
+    }
     SCHK(s, hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     const int tiles = n * (s->H / CTH) * (s->W / TW);
     // persistent: one block per compute unit (or fewer, when capped)
     const int blocks = std::min(tiles, s->conv_cap > 0 ? std::min(s->conv_cap, s->cus) : s->cus);
-    hipLaunchKernelGGL(k, dim3(blocks), dim3(kConvThreads), lds, s->stream, x, w, b, y, n, s->H, s->W, mask);
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(threads), lds, s->stream, x, w, b, y, n, s->H, s->W, mask);
     SCHK(s, hipGetLastError());
     return FPS_OK;
 }
