@@ -395,15 +395,21 @@ def headline_section(args, stream):
 
 
 def stability_section(args, stream):
-    """The pedestrian step with and without the stability rule (varied bodies
-    standing in the flow): 8 scenarios of 1024^2 cells, wet everywhere, with
-    50,000 evacuees each."""
+    """The pedestrian step without the body rules, with the stability rule
+    (varied bodies standing in the flow) and with the stability and wading
+    rules: 8 scenarios of 1024^2 cells, wet everywhere, with 50,000 evacuees
+    each."""
     import copy
+    import dataclasses
     import torch
     from paper_1908_05232_amd import fps, inputs as I
     scs = I.large_sweep(8, n=1024, n_evac=50000, seed=7)
     out = {"workload": "large_sweep_8x1024 with 50,000 evacuees each", "agents": 8 * 50000}
-    for tag, members in (("off", scs), ("on", [I.add_bodies(copy.deepcopy(sc), seed=k) for k, sc in enumerate(scs)])):
+    bodies = [I.add_bodies(copy.deepcopy(sc), seed=k) for k, sc in enumerate(scs)]
+    wading = [copy.deepcopy(sc) for sc in bodies]
+    for sc in wading:
+        sc.ped = dataclasses.replace(sc.ped, wading=1)
+    for tag, members in (("off", scs), ("on", bodies), ("on_wading", wading)):
         ens = fps.Ensemble(members, stream=stream)
         ens.step(50)
         kms = ens.step_profiled(args.profile_steps)

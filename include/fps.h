@@ -107,6 +107,18 @@ typedef struct {
        body_h0 = 1.71 m and body_m0 = 70 kg for everyone.  Evaluated in FP32. */
     int32_t stability;
     double c_drag, mu_f, rho_w, rho_body, body_h0, body_m0;
+    /* Wading rule (the walking-speed half of the same further work; a
+       mechanics reading).  wading = 0 (the default): Table 1's speeds.
+       wading = 1: in a wet cell where the person stands, the walking speed is
+       the smaller of Table 1's and v_w = sqrt(2 wade_k W' / (rho_w c_drag b
+       h)), the speed at which the drag of wading through still water of depth
+       h on the body's frontal width b (the cylinder above) equals the push
+       wade_k W' its feet keep up, W' = g M - rho_w g A h the weight less
+       buoyancy; v_w = 0 where W' <= 0.  The class stays Table 1's.  Default
+       wade_k 0.1 (an adult of 1.71 m and 70 kg wades at 1.55, 0.88 and
+       0.48 m/s in 0.2, 0.5 and 1 m of water).  Evaluated in FP32. */
+    int32_t wading;
+    double wade_k;
 } fps_ped_params;
 
 typedef struct {
@@ -185,7 +197,7 @@ int fps_bind_agents(fps_sim* sim, int32_t n, float* x, float* y, float* vx, floa
                     float* v_base, uint8_t* role, uint8_t* state, uint8_t* hr_class,
                     int32_t* dest, float* timer);
 
-/* Bodies of the agents for the stability rule (fps_ped_params.stability):
+/* Bodies of the agents for the stability and wading rules (fps_ped_params.stability, .wading):
    height (m) and mass (kg), device float32 [n_agents] each, caller-owned,
    read at every step; both NULL: the default body for everyone.  Call after
    fps_bind_agents (the arrays follow its agent count); FPS_E_INVALID for one

@@ -20,7 +20,8 @@
  *   - triangular inflow hydrograph: sec. 3.1
  *   - richer walking-speed and stability rules and variable body shapes are
  *     named as further work (sec. 2.4 note 1, sec. 4): the stability rule
- *     below (S1-S4) is this oracle's reading of them
+ *     (S1-S4) and the wading rule (W1-W3) below are this oracle's reading
+ *     of them
  *   - pre-flood flow: 7 entrance doors, entering and leaving by each with
  *     probability 1/7, 10 per door, 1,000 walkers, a 5-minute spin-up with
  *     no inflow, no entries once water is on the site: sec. 3, sec. 3.2, sec. 2.4
@@ -115,6 +116,18 @@
  *   S4 a person who cannot stand does not walk (speed 0) and takes a sixth
  *      state in floodwater, UNSTABLE, in place of its Table 1 class; on dry
  *      cells and with the rule off the paper's Table 1 alone applies.
+ * Readings of the wading rule (or_wade_speed; the walking-speed half of the
+ * same further work):
+ *   W1 wading through still water of depth h at speed v, the body of S2 meets
+ *      the drag 1/2 rho_w c_drag b h v^2 on its wetted frontal width b.
+ *   W2 its feet keep up a horizontal push of at most wade_k times its weight
+ *      less buoyancy, W' = g (M - rho_w A h); the fastest it can wade is the
+ *      speed at which the two balance, sqrt(2 wade_k W' / (rho_w c_drag b
+ *      h)), and 0 once buoyancy takes the whole weight.
+ *   W3 in a wet cell where the person stands, the walking speed is the
+ *      smaller of Table 1's speed for its class and that cap; the class stays
+ *      Table 1's (or UNSTABLE by S4, speed 0); on dry cells and with the rule
+ *      off Table 1 alone applies.
  */
 #include "fps_oracle.h"
 
@@ -309,6 +322,21 @@ int32_t or_unstable(const or_params *P, double h, double qx, double qy, double h
         *margin = m1 < m2 ? m1 : m2;
     }
     return drag > hold_slide || push_topple > hold_topple;
+}
+
+/* Wading speed cap (W1, W2): the body of S2 (cross-section A = M / (rho_body
+   H), frontal width b = 2 sqrt(A / pi)) wading through still water of depth
+   h at speed v meets the drag 1/2 rho_w c_drag b h v^2; its feet keep up a
+   push of wade_k W' with W' = g (M - rho_w A h); the cap is the speed at which
+   the two are equal, 0 where W' <= 0. */
+double or_wade_speed(const or_params *P, double h, double height, double mass)
+{
+    const double pi = 3.14159265358979323846;
+    double area = mass / (P->rho_body * height);
+    double b = 2.0 * sqrt(area / pi);
+    double w_eff = P->g * (mass - P->rho_w * area * h);
+    if (!(w_eff > 0.0)) return 0.0;
+    return sqrt(2.0 * P->wade_k * w_eff / (P->rho_w * P->c_drag * b * h));
 }
 
 /* roughness write-back (sec. 2.4; R13) */
@@ -950,6 +978,12 @@ void or_ped_step(or_sim *S, double dt)
                 cls = OR_CLS_UNSTABLE;
                 v0 = 0.0;
             }
+        }
+        /* the wading rule caps the speed of a person standing in water (W3) */
+        if (P->wading && cls != OR_CLS_DRY && cls != OR_CLS_UNSTABLE) {
+            double hb = S->body_h ? S->body_h[a] : P->body_h0, mb = S->body_m ? S->body_m[a] : P->body_m0;
+            double vw = or_wade_speed(P, S->h[c], hb, mb);
+            if (vw < v0) v0 = vw;
         }
         S->cls[a] = (uint8_t)cls;
         /* destinations */

@@ -63,6 +63,9 @@ typedef struct {
     int32_t stability;
     double c_drag, mu_f, rho_w, rho_body; /* drag coefficient, foot friction, water and body densities */
     double body_h0, body_m0;             /* the body of people without one of their own (m, kg) */
+    /* wading rule: walking speed capped by the drag of wading (W1-W3); 0 = Table 1 only */
+    int32_t wading;
+    double wade_k;                       /* sustained push as a fraction of the weight less buoyancy */
 } or_params;
 
 typedef struct {
@@ -120,6 +123,8 @@ int32_t or_hr_class(const or_params *P, double h, double qx, double qy, double *
    *margin (may be NULL): the smaller relative excess of holding over pushing */
 int32_t or_unstable(const or_params *P, double h, double qx, double qy, double height, double mass,
                     double *margin);
+/* the wading speed cap of a person of that body in still water of depth h (W1, W2) */
+double or_wade_speed(const or_params *P, double h, double height, double mass);
 double or_n_eff(const or_params *P, int32_t np);
 void or_friction(const or_params *P, double dt, double h, double n, double *qx, double *qy);
 int32_t or_cell_index(double x, double d, int32_t n);

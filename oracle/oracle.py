@@ -47,6 +47,7 @@ class OrParams(C.Structure):
         ("stability", C.c_int32),
         ("c_drag", C.c_double), ("mu_f", C.c_double), ("rho_w", C.c_double), ("rho_body", C.c_double),
         ("body_h0", C.c_double), ("body_m0", C.c_double),
+        ("wading", C.c_int32), ("wade_k", C.c_double),
     ]
 
 
@@ -111,6 +112,8 @@ def lib(omp: bool = False):
         L.or_hr_class.restype = C.c_int32
         L.or_unstable.argtypes = [C.POINTER(OrParams)] + [C.c_double] * 5 + [_dp]
         L.or_unstable.restype = C.c_int32
+        L.or_wade_speed.argtypes = [C.POINTER(OrParams)] + [C.c_double] * 3
+        L.or_wade_speed.restype = C.c_double
         L.or_n_eff.argtypes = [C.POINTER(OrParams), C.c_int32]
         L.or_n_eff.restype = C.c_double
         L.or_friction.argtypes = [C.POINTER(OrParams), C.c_double, C.c_double, C.c_double, _dp, _dp]
@@ -162,6 +165,7 @@ def make_params(desc, ped=None) -> OrParams:
     P.c_drag, P.mu_f = getattr(ped, "c_drag", 1.1), getattr(ped, "mu_f", 0.45)
     P.rho_w, P.rho_body = getattr(ped, "rho_w", 1000.0), getattr(ped, "rho_body", 1000.0)
     P.body_h0, P.body_m0 = getattr(ped, "body_h0", 1.71), getattr(ped, "body_m0", 70.0)
+    P.wading, P.wade_k = int(getattr(ped, "wading", 0)), getattr(ped, "wade_k", 0.1)
     return P
 
 
@@ -335,6 +339,11 @@ def unstable(params, h, qx, qy, height, mass):
     m = C.c_double()
     r = lib().or_unstable(C.byref(params), float(h), float(qx), float(qy), float(height), float(mass), C.byref(m))
     return r, m.value
+
+
+def wade_speed(params, h, height, mass):
+    """The wading speed cap of a person of that body in still water of depth h (W1, W2)."""
+    return lib().or_wade_speed(C.byref(params), float(h), float(height), float(mass))
 
 
 def n_eff(params, np_count):

@@ -361,6 +361,7 @@ void fill_scn(const fps_sim* s, Scn& c)
     q.stab_kd = (float)(0.5 * s->P.rho_w * s->P.c_drag);
     q.stab_mu = (float)s->P.mu_f; q.stab_rw = (float)s->P.rho_w; q.stab_rb = (float)s->P.rho_body;
     q.stab_g = (float)s->G.g; q.body_h0 = (float)s->P.body_h0; q.body_m0 = (float)s->P.body_m0;
+    q.wade = s->P.wading; q.wade_k = (float)s->P.wade_k;
     q.door_seed = s->door_seed;
 
     BinParams& b = c.bins;
@@ -828,6 +829,8 @@ int build_engine(Engine* e, int32_t S, const fps_grid_desc* descs, const fps_ped
             if ((P.stability != 0 && P.stability != 1) || !(P.c_drag >= 0) || !(P.mu_f > 0) || !(P.rho_w > 0) ||
                 !(P.rho_body > 0) || !(P.body_h0 > 0) || !(P.body_m0 > 0))
                 return efail(e, FPS_E_INVALID, "scenario %d: stability constants out of range", k);
+            if ((P.wading != 0 && P.wading != 1) || !(P.wade_k > 0) || (P.wading && !(P.c_drag > 0)))
+                return efail(e, FPS_E_INVALID, "scenario %d: wading constants out of range", k);
         }
     }
     if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255))
@@ -927,6 +930,8 @@ void fps_ped_params_default(fps_ped_params* o)
     o->rho_body = 1000.0;
     o->body_h0 = 1.71;
     o->body_m0 = 70.0;
+    o->wading = 0;
+    o->wade_k = 0.1;
 }
 
 size_t fps_workspace_bytes(const fps_grid_desc* desc, int32_t max_agents)

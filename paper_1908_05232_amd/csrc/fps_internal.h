@@ -129,6 +129,9 @@ struct PedParams {
     const float* body_m;
     int stab;
     float stab_kd, stab_mu, stab_rw, stab_rb, stab_g, body_h0, body_m0;   // kd = rho_w c_drag / 2
+    // wading rule: the speed cap sqrt(wade_k W' / (kd b h))
+    int wade;
+    float wade_k;
 };
 
 // Sandbag barrier of sec. 2.4: the fill order and layer rules.

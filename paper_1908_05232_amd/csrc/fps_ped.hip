@@ -179,7 +179,7 @@ __device__ __forceinline__ AgentRec load_agent(const PedParams& p, int a)
     r.timer = p.timer[a];
     r.body_h = p.body_h0;
     r.body_m = p.body_m0;
-    if (p.stab && p.body_h) {
+    if ((p.stab || p.wade) && p.body_h) {
         r.body_h = p.body_h[a];
         r.body_m = p.body_m[a];
     }
@@ -365,19 +365,26 @@ __device__ void agent_step(const PedParams& p, const AgentRec& rec, const float*
         v0 = cls == FPS_CLS_LOW ? p.v_class[FPS_CLS_LOW]
            : cls == FPS_CLS_MEDIUM ? p.v_class[FPS_CLS_MEDIUM]
            : cls == FPS_CLS_HIGH ? p.v_class[FPS_CLS_HIGH] : p.v_class[FPS_CLS_HIGHEST];
-        if (p.stab) {
-            // stability rule: an upright cylinder of the body's volume in the
-            // flow; sliding, toppling about its edge, or water to its height
+        if (p.stab || p.wade) {
+            // the body: an upright cylinder of its volume, its weight less buoyancy
             const float bh = rec.body_h, bm = rec.body_m;
-            const float u = sqrtf(qxc * qxc + qyc * qyc) / h;
             const float area = bm / (p.stab_rb * bh);
             const float b = 2.0f * sqrtf(area * 0.318309886f);
             const float w_eff = p.stab_g * (bm - p.stab_rw * area * h);
-            const float drag = p.stab_kd * b * h * u * u;
-            const bool unstable = h >= bh || drag > p.stab_mu * w_eff || drag * (0.5f * h) > w_eff * (0.5f * b);
-            if (unstable) {
-                cls = FPS_CLS_UNSTABLE;
-                v0 = 0.0f;
+            if (p.stab) {
+                // stability rule: sliding, toppling about its edge, or water to its height
+                const float u = sqrtf(qxc * qxc + qyc * qyc) / h;
+                const float drag = p.stab_kd * b * h * u * u;
+                const bool unstable = h >= bh || drag > p.stab_mu * w_eff || drag * (0.5f * h) > w_eff * (0.5f * b);
+                if (unstable) {
+                    cls = FPS_CLS_UNSTABLE;
+                    v0 = 0.0f;
+                }
+            }
+            if (p.wade) {
+                // wading rule: no faster than the drag of wading lets the feet push
+                const float vw = w_eff > 0.0f ? sqrtf(p.wade_k * w_eff / (p.stab_kd * b * h)) : 0.0f;
+                v0 = fminf(v0, vw);
             }
         }
     }

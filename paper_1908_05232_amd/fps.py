@@ -40,6 +40,7 @@ class PedParamsC(C.Structure):
         ("stability", C.c_int32),
         ("c_drag", C.c_double), ("mu_f", C.c_double), ("rho_w", C.c_double), ("rho_body", C.c_double),
         ("body_h0", C.c_double), ("body_m0", C.c_double),
+        ("wading", C.c_int32), ("wade_k", C.c_double),
     ]
 
 
@@ -187,6 +188,7 @@ def ped_params_c(p) -> PedParamsC:
     c.c_drag, c.mu_f = getattr(p, "c_drag", 1.1), getattr(p, "mu_f", 0.45)
     c.rho_w, c.rho_body = getattr(p, "rho_w", 1000.0), getattr(p, "rho_body", 1000.0)
     c.body_h0, c.body_m0 = getattr(p, "body_h0", 1.71), getattr(p, "body_m0", 70.0)
+    c.wading, c.wade_k = int(getattr(p, "wading", 0)), getattr(p, "wade_k", 0.1)
     return c
 
 

@@ -73,6 +73,9 @@ class PedParams:
     rho_body: float = 1000.0      # body density (kg/m^3)
     body_h0: float = 1.71         # body of people without one of their own: height (m)
     body_m0: float = 70.0         # ... and mass (kg)
+    # walking speed capped by the drag of wading (off: the paper's Table 1 alone)
+    wading: int = 0
+    wade_k: float = 0.1           # sustained push of the feet over the weight less buoyancy
 
 
 @dataclasses.dataclass

@@ -24,6 +24,7 @@ from __future__ import annotations
 
 import argparse
 import copy
+import dataclasses
 import json
 import time
 
@@ -47,21 +48,27 @@ def _site(population, seed, n, dx, **kw):
 
 
 def evacuation_pair(population=1000, seed=5232, n=SITE_N, dx=SITE_DX, q_peak=2.0, duration=1800.0, doors=True,
-                    bodies=False):
+                    bodies=False, wading=False):
     """Scenario 1 with and without the people's effect on the flood.  doors:
     the pre-flood flow (sec. 3.2) fills the site from 7 doors during a
     5-minute spin-up; else the population starts spread uniformly, standing.
     bodies: varied heights and masses and the stability rule (people who
-    cannot stand in the flow stop)."""
+    cannot stand in the flow stop); wading: with bodies, also the wading rule
+    (walking speed capped by the drag of wading)."""
     with_people = _site(population, seed, n, dx, q_peak=q_peak, duration=duration)
     if doors:
         with_people = I.add_doors(with_people, seed=seed)
+    tag = ""
     if bodies:
         with_people = I.add_bodies(with_people, seed=seed)
-    with_people.name = "evacuation_coupled" + ("_bodies" if bodies else "")
+        tag = "_bodies"
+        if wading:
+            with_people.ped = dataclasses.replace(with_people.ped, wading=1)
+            tag = "_bodies_wading"
+    with_people.name = "evacuation_coupled" + tag
     without = copy.deepcopy(with_people)
     without.desc.np_cap = 0
-    without.name = "evacuation_uncoupled" + ("_bodies" if bodies else "")
+    without.name = "evacuation_uncoupled" + tag
     return [with_people, without]
 
 
@@ -196,6 +203,8 @@ def main(argv=None):
     else:
         res = dict(evacuation=[run_evacuation(evacuation_pair(q_peak=q)) for q in BREACH_Q],
                    evacuation_stability=[run_evacuation(evacuation_pair(q_peak=q, bodies=True)) for q in BREACH_Q[2:]],
+                   evacuation_wading=[run_evacuation(evacuation_pair(q_peak=q, bodies=True, wading=True))
+                                      for q in BREACH_Q[2:]],
                    deployment=run_deployment(deployment_sweep()),
                    barrier_floods=barrier_floods())
     res["wall_s"] = time.perf_counter() - t0
