@@ -142,26 +142,30 @@ __device__ __forceinline__ void face_flux(const FvParams& p, float hL, float unL
     float qL = hl * unL, qR = hr * unR;
     float FL0 = qL, FL1 = qL * unL + pL, FL2 = qL * utL;
     float FR0 = qR, FR1 = qR * unR + pR, FR2 = qR * utR;
-    // HLL written from the left flux: identical states give F exactly
-    float inv = rcp(sR - sL);
-    float H0 = FL0 + sL * ((FL0 - FR0) + sR * (hr - hl)) * inv;
-    float H1 = FL1 + sL * ((FL1 - FR1) + sR * (qR - qL)) * inv;
+    // HLL written from the left flux with the wave speeds clamped to either
+    // side of zero: the one formula is the left flux exactly when sL >= 0
+    // (the clamped sL is 0), the right flux up to rounding when sR <= 0, and
+    // the star-region flux between, with no selection of the case; identical
+    // states give F exactly.  Only a face dry on both sides has a zero
+    // denominator, and its flux is set to zero below.
+    const float sLc = fminf(sL, 0.0f), sRc = fmaxf(sR, 0.0f);
+    float inv = rcp(sRc - sLc);
+    float H0 = FL0 + sLc * ((FL0 - FR0) + sRc * (hr - hl)) * inv;
+    float H1 = FL1 + sLc * ((FL1 - FR1) + sRc * (qR - qL)) * inv;
     float H2;
     if (kHll) {
-        H2 = FL2 + sL * ((FL2 - FR2) + sR * (hr * utR - hl * utL)) * inv;
+        H2 = FL2 + sLc * ((FL2 - FR2) + sRc * (hr * utR - hl * utL)) * inv;
     } else {
-        // contact speed s_M = num / den with den < 0 here, so s_M >= 0 iff num <= 0
+        // tangential momentum from the side of the contact wave: s_M = num /
+        // den with den < 0 here, so s_M >= 0 iff num <= 0 (the left state for
+        // sL >= 0, the right one for sR <= 0)
         float num = sL * hr * (unR - sR) - sR * hl * (unL - sL);
         H2 = H0 * (num <= 0.0f ? utL : utR);
     }
-    const bool left = sL >= 0.0f, right = sR <= 0.0f;
-    F0 = left ? FL0 : (right ? FR0 : H0);
-    F1 = left ? FL1 : (right ? FR1 : H1);
-    F2 = left ? FL2 : (right ? FR2 : H2);
     const bool none = !(wetL || wetR);
-    F0 = (none || wall) ? 0.0f : F0;
-    F1 = none ? 0.0f : F1;
-    F2 = (none || wall) ? 0.0f : F2;
+    F0 = (none || wall) ? 0.0f : H0;
+    F1 = none ? 0.0f : H1;
+    F2 = (none || wall) ? 0.0f : H2;
 }
 
 // Wave reductions by DPP lane moves (VALU only, no LDS round trips): pairs,
