@@ -162,6 +162,31 @@ def test_multi_tile_gradients_match_oracle():
         assert c >= 0.9999 and e <= 1e-2
 
 
+def test_gradients_over_two_image_groups_match_oracle():
+    """The weight gradient takes the batch eight images at a time (the k
+    index of its matrix products runs over the images of one position): 9
+    images make one full group and one with a single image and seven empty
+    slots.  Element by element against the oracle with the same BF16
+    rounding points, as the multi-tile test."""
+    params, x, target = make_case(13, 9, 16, 64)
+    sur = fps.Surrogate(9, 16, 64)
+    p, xt, tt = to_dev(params, x, target)
+    sur.set_params(p)
+    loss, g = sur.gradients(xt, tt)
+    lb, gb = S.loss_and_grads(params, x, target, bf16=True)
+    assert float(loss.item()) == pytest.approx(lb, rel=5e-3)
+    gg = unpack(g.cpu().numpy().astype(np.float64), params)
+    for li in range(len(gg)):
+        (dw, db), (dwb, dbb) = gg[li], gb[li]
+        if li == 0:
+            dw, dwb = dw[..., :5], dwb[..., :5]       # zero input channels carry no gradient
+        ew = float(np.abs(dw - dwb).max() / np.abs(dwb).max())
+        eb = float(np.abs(db - dbb).max() / np.abs(dbb).max())
+        say(f"9 images, layer {li + 1}: dW max|d| / max|ref| {ew:.2e}, db {eb:.2e}")
+        assert ew <= ELEM_TOL and eb <= ELEM_TOL
+        assert cosine(dw, dwb) >= 0.9999 and rel_l2(dw, dwb) <= 1e-2
+
+
 def test_training_reduces_loss_and_matches_adam():
     params, x, target = make_case(3, 2, 16, 64)
     sur = fps.Surrogate(2, 16, 64)
