@@ -209,24 +209,32 @@ __device__ inline void block_scan_chunks(const BinParams& b)
 // Placement of the agents into their bins by rank, then the stable order: an
 // agent's final slot counts the smaller ids of its own bin.  Whole-grid
 // version, in two kernels (one thread per agent).  An agent alone in its bin
-// (most of them in a sparse crowd) takes the bin's first slot directly: it
-// is neither placed nor compared.
+// (most of them in a sparse crowd) takes the bin's first slot in the
+// placement pass; the others are marked (slot -1) for the order pass, which
+// passes over everyone else after reading their slot and key (both read in
+// agent order, no bin bounds).
 __device__ inline void place_agent(const BinParams& b, int a)
 {
-    int k = b.key[a];
+    const int k = b.key[a], r = b.rank[a];
+    const float x = b.x[a], y = b.y[a];
     if (k < 0) return;
     const int s0 = b.bin_start[k], s1 = b.bin_start[k + 1];
-    if (s1 - s0 > 1) b.perm_u[s0 + b.rank[a]] = a;
+    if (s1 - s0 > 1) {
+        b.perm_u[s0 + r] = a;
+        b.slot[a] = -1;
+    } else {
+        b.slot[a] = s0;
+        b.xy[s0] = make_float2(x, y);
+    }
 }
 __device__ inline void sort_agent(const BinParams& b, int a)
 {
-    int k = b.key[a];
-    if (k < 0) return;
-    int s0 = b.bin_start[k], s1 = b.bin_start[k + 1];
+    const int k = b.key[a], sl = b.slot[a];
+    if (k < 0 || sl >= 0) return;
+    const int s0 = b.bin_start[k], s1 = b.bin_start[k + 1];
     int below = 0;
-    if (s1 - s0 > 1)
-        for (int s = s0; s < s1; ++s) below += b.perm_u[s] < a;
-    int f = s0 + below;
+    for (int s = s0; s < s1; ++s) below += b.perm_u[s] < a;
+    const int f = s0 + below;
     b.slot[a] = f;
     b.xy[f] = make_float2(b.x[a], b.y[a]);
 }

@@ -192,7 +192,8 @@ __device__ __forceinline__ AgentRec load_agent(const PedParams& p, int a)
 // The loads come in four dependent rounds: the agent record; everything
 // addressed by its cell (flood state, the nine distances of its destination
 // field, the obstacle mask, the bin bounds of the three bin rows); the
-// neighbours' positions; the cells of the move.  Cell and bin indices use IEEE
+// neighbours' positions (with one lane per agent, also the discharge of a wet
+// cell); the cells of the move.  Cell and bin indices use IEEE
 // division so they match the FP32 decisions of the oracle exactly.
 template <int L>
 __device__ void agent_step(const PedParams& p, const AgentRec& rec, const float* __restrict__ fh,
@@ -262,7 +263,12 @@ __device__ void agent_step(const PedParams& p, const AgentRec& rec, const float*
     const uint64_t doff = (uint64_t)(uint32_t)(moving ? dest : 0) * (uint64_t)(uint32_t)nc;
     const float* D = p.dist + doff;
     const uint8_t* K = p.codes + doff;
-    const float h = fh[c], qxc = fqx[c], qyc = fqy[c];
+    const float h = fh[c];
+    float qxc = 0.0f, qyc = 0.0f;     // the cell's discharge: this round with several lanes per agent
+    if constexpr (L > 1) {
+        qxc = fqx[c];
+        qyc = fqy[c];
+    }
     const int kc = moving && p.use_codes ? (int)K[c] : 0;       // the cell's code of the destination
     uint4 m4 = make_uint4(0, 0, 0, 0);
     if (p.use_wmask) {
@@ -349,59 +355,22 @@ __device__ void agent_step(const PedParams& p, const AgentRec& rec, const float*
             }
         }
     }
-    // hazard of the containing cell (Table 1)
-    int cls;
-    float v0;
-    if (!(h > p.eps)) {
-        cls = FPS_CLS_DRY;
-        v0 = vbase;
-    } else {
-        float u = qxc / h, v = qyc / h;
-        float hr = (fmaxf(fabsf(u), fabsf(v)) + 0.5f) * h;
-        cls = hr < p.hr_t[0] ? FPS_CLS_LOW
-            : hr < p.hr_t[1] ? FPS_CLS_MEDIUM
-            : hr < p.hr_t[2] ? FPS_CLS_HIGH : FPS_CLS_HIGHEST;
-        // constant indices keep the parameter copy in registers
-        v0 = cls == FPS_CLS_LOW ? p.v_class[FPS_CLS_LOW]
-           : cls == FPS_CLS_MEDIUM ? p.v_class[FPS_CLS_MEDIUM]
-           : cls == FPS_CLS_HIGH ? p.v_class[FPS_CLS_HIGH] : p.v_class[FPS_CLS_HIGHEST];
-        if (p.stab || p.wade) {
-            // the body: an upright cylinder of its volume, its weight less buoyancy
-            const float bh = rec.body_h, bm = rec.body_m;
-            const float area = bm / (p.stab_rb * bh);
-            const float b = 2.0f * sqrtf(area * 0.318309886f);
-            const float w_eff = p.stab_g * (bm - p.stab_rw * area * h);
-            if (p.stab) {
-                // stability rule: sliding, toppling about its edge, or water to its height
-                const float u = sqrtf(qxc * qxc + qyc * qyc) / h;
-                const float drag = p.stab_kd * b * h * u * u;
-                const bool unstable = h >= bh || drag > p.stab_mu * w_eff || drag * (0.5f * h) > w_eff * (0.5f * b);
-                if (unstable) {
-                    cls = FPS_CLS_UNSTABLE;
-                    v0 = 0.0f;
-                }
-            }
-            if (p.wade) {
-                // wading rule: no faster than the drag of wading lets the feet push
-                const float vw = w_eff > 0.0f ? sqrtf(p.wade_k * w_eff / (p.stab_kd * b * h)) : 0.0f;
-                v0 = fminf(v0, vw);
-            }
-        }
-    }
-    if (lead) p.cls[a] = (uint8_t)cls;
     // the direction is needed here: this keeps the compiler from moving its
     // loads below the neighbour loop, where they would form a round of their own
     asm volatile("" : "+v"(ex), "+v"(ey));
-    float xn = x, yn = y;
-    int ni = ci, nj = cj;
-    if (!moving) {
-        vx = 0.0f;
-        vy = 0.0f;
-    } else {
-        // relaxation toward the desired velocity
-        float k = __expf(-dt / p.tau);
-        vx = v0 * ex + (vx - v0 * ex) * k;
-        vy = v0 * ey + (vy - v0 * ey) * k;
+    // with one lane per agent (many agents: the step is bound by memory
+    // traffic) the cell's discharge is read only where the cell is wet, in
+    // the round of the neighbours' positions
+    if constexpr (L == 1) {
+        if (h > p.eps) {
+            qxc = fqx[c];
+            qyc = fqy[c];
+        }
+    }
+    // the forces first (they do not depend on the hazard class), so that
+    // the discharge loads travel with the neighbour loads
+    float fsx = 0.0f, fsy = 0.0f;
+    if (moving) {
         // repulsion from the neighbours in the 3x3 bins (the three bins of one
         // bin row are one contiguous run of the sorted positions; the runs of
         // the three rows are numbered one after the other), then from the
@@ -460,7 +429,59 @@ __device__ void agent_step(const PedParams& p, const AgentRec& rec, const float*
                 }
             }
         }
-        const float fsx = slot_sum<L>(fx), fsy = slot_sum<L>(fy);
+        fsx = slot_sum<L>(fx);
+        fsy = slot_sum<L>(fy);
+    }
+    // hazard of the containing cell (Table 1)
+    int cls;
+    float v0;
+    if (!(h > p.eps)) {
+        cls = FPS_CLS_DRY;
+        v0 = vbase;
+    } else {
+        float u = qxc / h, v = qyc / h;
+        float hr = (fmaxf(fabsf(u), fabsf(v)) + 0.5f) * h;
+        cls = hr < p.hr_t[0] ? FPS_CLS_LOW
+            : hr < p.hr_t[1] ? FPS_CLS_MEDIUM
+            : hr < p.hr_t[2] ? FPS_CLS_HIGH : FPS_CLS_HIGHEST;
+        // constant indices keep the parameter copy in registers
+        v0 = cls == FPS_CLS_LOW ? p.v_class[FPS_CLS_LOW]
+           : cls == FPS_CLS_MEDIUM ? p.v_class[FPS_CLS_MEDIUM]
+           : cls == FPS_CLS_HIGH ? p.v_class[FPS_CLS_HIGH] : p.v_class[FPS_CLS_HIGHEST];
+        if (p.stab || p.wade) {
+            // the body: an upright cylinder of its volume, its weight less buoyancy
+            const float bh = rec.body_h, bm = rec.body_m;
+            const float area = bm / (p.stab_rb * bh);
+            const float b = 2.0f * sqrtf(area * 0.318309886f);
+            const float w_eff = p.stab_g * (bm - p.stab_rw * area * h);
+            if (p.stab) {
+                // stability rule: sliding, toppling about its edge, or water to its height
+                const float u = sqrtf(qxc * qxc + qyc * qyc) / h;
+                const float drag = p.stab_kd * b * h * u * u;
+                const bool unstable = h >= bh || drag > p.stab_mu * w_eff || drag * (0.5f * h) > w_eff * (0.5f * b);
+                if (unstable) {
+                    cls = FPS_CLS_UNSTABLE;
+                    v0 = 0.0f;
+                }
+            }
+            if (p.wade) {
+                // wading rule: no faster than the drag of wading lets the feet push
+                const float vw = w_eff > 0.0f ? sqrtf(p.wade_k * w_eff / (p.stab_kd * b * h)) : 0.0f;
+                v0 = fminf(v0, vw);
+            }
+        }
+    }
+    if (lead) p.cls[a] = (uint8_t)cls;
+    float xn = x, yn = y;
+    int ni = ci, nj = cj;
+    if (!moving) {
+        vx = 0.0f;
+        vy = 0.0f;
+    } else {
+        // relaxation toward the desired velocity, then the forces
+        float k = __expf(-dt / p.tau);
+        vx = v0 * ex + (vx - v0 * ex) * k;
+        vy = v0 * ey + (vy - v0 * ey) * k;
         vx += dt * fsx;
         vy += dt * fsy;
         float sp2 = vx * vx + vy * vy;
