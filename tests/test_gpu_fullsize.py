@@ -8,6 +8,11 @@ hold at any size.
   per-cell counts are bit-exact; the volume budget closes.
 * the 64-scenario intervention sweep: three members (one of each grid size)
   equal their solo runs bit for bit; every member closes its volume budget.
+* the large sweep, 32 shopping centres of 2048^2 cells with 50,000 evacuees
+  each, as one ensemble with tuned tiles and graph-captured steps: after the
+  warm-up every member closes its volume budget; for three members the bins
+  and per-cell counts are bit-exact, and one more coupled step matches the
+  FP64 oracle from the GPU's state (depth, discharge, positions, classes).
 * the surrogate at 8 x 256^2: sampled output pixels equal the oracle network
   evaluated on the 11 x 11 receptive field of each pixel.
 * the learned update on 2048^2 grids with 50,000 people: the assisted
@@ -72,6 +77,63 @@ def test_intervention_sweep_members_equal_solo_runs():
         for key in A:
             assert np.array_equal(A[key], B[key]), (k, key)
         say(f"sweep member {k} ({n}^2, {len(A['x'])} agents): identical to its solo run")
+
+
+def test_large_sweep_headline_configuration(oracle):
+    """32 x 2048^2 (134 M cells, 1.6 M evacuees) in one launch per kernel, as
+    the benchmark times it: 4 eager steps, the tile shape tuned, then a chunk
+    of 16 steps replayed from a graph."""
+    scs = I.large_sweep(32, n=2048, n_evac=50000, seed=5, workers=8)
+    ens = fps.Ensemble(scs)
+    m0 = [m.diag()["mass"] for m in ens.members]       # the site starts wet
+    ens.set_graph(16)
+    ens.step(4)
+    ens.autotune()
+    ens.step(16)
+    for k, m in enumerate(ens.members):
+        d = m.diag()
+        budget = m0[k] + d["v_in"] - d["v_out"] + d["v_clip"]
+        assert abs(d["mass"] - budget) <= 1e-5 * (m0[k] + d["v_in"]), (k, d["mass"], budget)
+    picked = (0, 17, 31)
+    refs = {}
+    for k in picked:
+        sc = scs[k]
+        start, d0 = snapshot(ens[k], sc)
+        ref = oracle.OracleSim(start)
+        ref.S.t = d0["t"]
+        assert np.array_equal(ens[k].counts().cpu().numpy().reshape(-1), ref.np_), k
+        A = ens[k].agents()
+        bs, perm = ens[k].bins()
+        bs_ref, perm_ref = oracle.build_bins(oracle.make_params(sc.desc, sc.ped), A["x"], A["y"], A["state"])
+        assert np.array_equal(bs, bs_ref) and np.array_equal(perm, perm_ref), k
+        refs[k] = (start, ref)
+    ens.step(1)
+    for k in picked:
+        sc = scs[k]
+        start, ref = refs[k]
+        dt = ens[k].diag()["dt_last"]
+        ref.coupled_step(dt)
+        h, qx, qy, _ = ens[k].fields()
+        hr, qxr, qyr, _ = ref.fields()
+        dh = float(np.abs(h - hr).max())
+        dq = float(max(np.abs(qx - qxr).max(), np.abs(qy - qyr).max()))
+        A = ens[k].agents()
+        act = start.agents["state"] != 1
+        dpos = max(np.abs(A["x"] - ref.x)[act].max(), np.abs(A["y"] - ref.y)[act].max())
+        near = 0
+        for a in np.flatnonzero((A["hr_class"] != ref.cls) & act):
+            ci = min(int(np.floor(np.float32(start.agents["x"][a]) / np.float32(sc.desc.dx))), sc.desc.nx - 1)
+            cj = min(int(np.floor(np.float32(start.agents["y"][a]) / np.float32(sc.desc.dy))), sc.desc.ny - 1)
+            c = cj * sc.desc.nx + ci
+            _, hrv = oracle.hr_class(ref.S.P, start.h.reshape(-1)[c], start.qx.reshape(-1)[c],
+                                     start.qy.reshape(-1)[c])
+            assert min(abs(hrv - t) for t in sc.ped.hr_t) < 1e-5, (k, a, hrv)
+            near += 1
+        st_mism = int((A["state"] != ref.state).sum())
+        say(f"large sweep member {k}: t {start.t0:.2f} s, dt {dt:.3g}, max|dh| {dh:.2e}, max|dq| {dq:.2e}, "
+            f"max|dpos| {dpos:.2e}, class mismatches {near} (all near a threshold), state mismatches {st_mism}")
+        assert dh <= 1e-4 and dq <= 5e-4 and dpos <= 1e-4
+        assert st_mism <= max(1, 0.005 * len(A["x"]))
 
 
 def _receptive_forward(params, x_img, i, j):
