@@ -13,6 +13,10 @@ hold at any size.
   warm-up every member closes its volume budget; for three members the bins
   and per-cell counts are bit-exact, and one more coupled step matches the
   FP64 oracle from the GPU's state (depth, discharge, positions, classes).
+* the largest grid the library takes, 32768 x 32768 = 2^30 cells: after one
+  step the first and last rows and columns and those beside tile and strip
+  seams equal the oracle on the three rows or columns around them; the
+  volume is conserved.
 * the surrogate at 8 x 256^2: sampled output pixels equal the oracle network
   evaluated on the 11 x 11 receptive field of each pixel.
 * the learned update on 2048^2 grids with 50,000 people: the assisted
@@ -134,6 +138,95 @@ def test_large_sweep_headline_configuration(oracle):
             f"max|dpos| {dpos:.2e}, class mismatches {near} (all near a threshold), state mismatches {st_mism}")
         assert dh <= 1e-4 and dq <= 5e-4 and dpos <= 1e-4
         assert st_mism <= max(1, 0.005 * len(A["x"]))
+
+
+def _band_step(oracle, h, qx, qy, z, d, sides, dt):
+    """The oracle's step on a band of rows or columns of the GPU's state.
+    sides: which of W, E, S, N of the band are sides of the grid (they keep
+    the grid's walls; the band's other sides are open, which the cells in its
+    middle do not see)."""
+    bc = tuple(I.WALL if real else I.TRANSMISSIVE for real in sides)
+    ny, nx = h.shape
+    bd = I.GridDesc(nx=nx, ny=ny, dx=d.dx, dy=d.dy, bc=bc, n_base=d.n_base)
+    ref = oracle.OracleSim(I.Scenario(desc=bd, h=h, qx=qx, qy=qy, z=z))
+    ref.fv_step(dt)
+    return ref.fields()[:3]
+
+
+def test_largest_grid_rows_and_columns_match_oracle(oracle):
+    """32768 x 32768 = 2^30 cells, the largest grid the library takes (the
+    flood kernels address a grid by 32-bit byte offsets from its base, so the
+    last cell sits at 2^32 - 4): moving water over a rough bed, a step in
+    depth, dry bands and walls.  After one step each checked row and column
+    (the first and last, and the two sides of a tile seam, of the middle row
+    seam, of the first strip seam and of the last, ragged, strip) equals the
+    FP64 oracle stepped on the three rows or columns around it from the GPU's
+    state (a cell's update reads only its four neighbours); the volume is
+    conserved to 1e-9 (a tile skipped or written twice would move it by
+    about 1e-6)."""
+    import torch
+    n, dx = 32768, 0.25
+    c = (np.arange(n, dtype=np.float32) + np.float32(0.5)) * np.float32(dx)
+    say("largest grid: building 2^30 cells")
+    z = (np.float32(0.05) * np.sin(c / np.float32(7.0)))[None, :] + \
+        (np.float32(0.05) * np.cos(c / np.float32(5.0)))[:, None]
+    h = (np.float32(0.3) * np.sin(c / np.float32(13.0)))[None, :] * np.cos(c / np.float32(11.0))[:, None]
+    h += np.float32(0.6)
+    h -= z
+    h[:, : n // 2] += np.float32(0.4)
+    h[:, n - 300: n - 200] = 0.0
+    h[n // 3: n // 3 + 50, :] = 0.0
+    np.maximum(h, np.float32(0.0), out=h)
+    qx = h * (np.float32(0.2) * np.cos(c / np.float32(9.0)))[:, None]
+    qy = h * (np.float32(-0.1) * np.sin(c / np.float32(17.0)))[None, :]
+    d = I.GridDesc(nx=n, ny=n, dx=dx, dy=dx, n_base=0.02)
+    sim = fps.Sim(I.Scenario(desc=d, h=h, qx=qx, qy=qy, z=z, name="largest"))
+    del h, qx, qy, z
+    H = sim.rows_per_wave()
+    strip = 62                                   # output columns of one wave of the march
+    last_strip = (n - 1) // strip * strip
+    rows = sorted({0, H - 1, H, n // 2 - 1, n // 2, n - 1})
+    cols = sorted({0, strip - 1, strip, last_strip - 1, last_strip, n - 1})
+    torch.cuda.synchronize()
+
+    def bands(t):
+        out = {}
+        for r in rows:
+            r0, r1 = max(r - 1, 0), min(r + 1, n - 1)
+            out[("row", r)] = (r0, t[r0:r1 + 1, :].double().cpu().numpy())
+        for k in cols:
+            k0, k1 = max(k - 1, 0), min(k + 1, n - 1)
+            out[("col", k)] = (k0, t[:, k0:k1 + 1].double().cpu().numpy())
+        return out
+
+    pre = [bands(t) for t in (sim.h, sim.qx, sim.qy, sim.z)]
+    d0 = sim.diag()
+    sim.step(1)
+    torch.cuda.synchronize()
+    d1 = sim.diag()
+    dt = d1["dt_last"]
+    post = [bands(t) for t in (sim.h, sim.qx, sim.qy)]
+    worst = [0.0, 0.0]
+    for key in pre[0]:
+        kind, idx = key
+        lo, hb = pre[0][key]
+        qxb, qyb, zb = pre[1][key][1], pre[2][key][1], pre[3][key][1]
+        if kind == "row":
+            sides = (True, True, lo == 0, lo + hb.shape[0] == n)
+        else:
+            sides = (lo == 0, lo + hb.shape[1] == n, True, True)
+        hr, qxr, qyr = _band_step(oracle, hb, qxb, qyb, zb, d, sides, dt)
+        sel = (lambda a: a[idx - lo, :]) if kind == "row" else (lambda a: a[:, idx - lo])
+        g = [sel(post[f][key][1]) for f in range(3)]
+        dh = float(np.abs(g[0] - sel(hr)).max())
+        dq = float(max(np.abs(g[1] - sel(qxr)).max(), np.abs(g[2] - sel(qyr)).max()))
+        worst = [max(worst[0], dh), max(worst[1], dq)]
+        assert dh <= 1e-4 and dq <= 5e-4, (key, dh, dq)
+    budget = d0["mass"] + d1["v_clip"] - d0["v_clip"]
+    rel = abs(d1["mass"] - budget) / d0["mass"]
+    say(f"largest grid (H = {H}, dt {dt:.4g} s): rows {rows}, columns {cols}: max|dh| {worst[0]:.2e}, "
+        f"max|dq| {worst[1]:.2e}; volume {d1['mass']:.6e} m^3, budget error {rel:.1e}")
+    assert rel <= 1e-9
 
 
 def _receptive_forward(params, x_img, i, j):
