@@ -70,7 +70,7 @@ enum { FPS_CLS_DRY = 0, FPS_CLS_LOW = 1, FPS_CLS_MEDIUM = 2, FPS_CLS_HIGH = 3, F
 
 /* Grid and flood constants.  Eq. (1)-(2), sec. 2.2; time step rule, sec. 3. */
 typedef struct {
-    int32_t nx, ny;          /* cells, >= 1 each */
+    int32_t nx, ny;          /* cells, >= 1 each, nx * ny <= 2^30 (32-bit byte offsets) */
     double dx, dy;           /* cell size (m), > 0 */
     double g;                /* gravity (m/s^2), e.g. 9.81 */
     double cfl;              /* Courant number in (0, 1], e.g. 0.5 */

@@ -63,6 +63,12 @@ def test_workspace_query_validates():
     bad = fps.grid_desc_c(I.GridDesc(nx=4, ny=4, dx=0.5, dy=0.5, cfl=1.5))
     assert L.fps_workspace_bytes(C.byref(bad), 0) == 0
     assert L.fps_workspace_bytes(C.byref(d), -1) == 0
+    # the flood kernels address a grid by 32-bit byte offsets: 2^30 cells is the
+    # largest grid taken, one row more is refused
+    big = fps.grid_desc_c(I.GridDesc(nx=32768, ny=32768, dx=0.25, dy=0.25))
+    assert L.fps_workspace_bytes(C.byref(big), 0) >= 32768 * 32768 * 16
+    over = fps.grid_desc_c(I.GridDesc(nx=32768, ny=32769, dx=0.25, dy=0.25))
+    assert L.fps_workspace_bytes(C.byref(over), 0) == 0
 
 
 def test_create_rejects_bad_arguments_without_touching_the_device():
