@@ -13,10 +13,10 @@ hold at any size.
   warm-up every member closes its volume budget; for three members the bins
   and per-cell counts are bit-exact, and one more coupled step matches the
   FP64 oracle from the GPU's state (depth, discharge, positions, classes).
-* the largest grid the library takes, 32768 x 32768 = 2^30 cells: after one
-  step the first and last rows and columns and those beside tile and strip
-  seams equal the oracle on the three rows or columns around them; the
-  volume is conserved.
+* the largest grid the library takes, 32768 x 32768 = 2^30 cells, first and
+  second order: after one step the first and last rows and columns and
+  those beside tile and strip seams equal the oracle on bands around them;
+  the volume is conserved.
 * the surrogate at 8 x 256^2: sampled output pixels equal the oracle network
   evaluated on the 11 x 11 receptive field of each pixel.
 * the learned update on 2048^2 grids with 50,000 people: the assisted
@@ -141,19 +141,23 @@ def test_large_sweep_headline_configuration(oracle):
 
 
 def _band_step(oracle, h, qx, qy, z, d, sides, dt):
-    """The oracle's step on a band of rows or columns of the GPU's state.
+    """The oracle's step on a band of rows or columns of the GPU's state
+    (wide enough that the checked row or column in its middle does not see
+    the band's open sides: one cell of the first-order stencil, four of the
+    two radius-2 stages of the second order).
     sides: which of W, E, S, N of the band are sides of the grid (they keep
     the grid's walls; the band's other sides are open, which the cells in its
     middle do not see)."""
     bc = tuple(I.WALL if real else I.TRANSMISSIVE for real in sides)
     ny, nx = h.shape
-    bd = I.GridDesc(nx=nx, ny=ny, dx=d.dx, dy=d.dy, bc=bc, n_base=d.n_base)
+    bd = I.GridDesc(nx=nx, ny=ny, dx=d.dx, dy=d.dy, bc=bc, n_base=d.n_base, order=d.order)
     ref = oracle.OracleSim(I.Scenario(desc=bd, h=h, qx=qx, qy=qy, z=z))
     ref.fv_step(dt)
     return ref.fields()[:3]
 
 
-def test_largest_grid_rows_and_columns_match_oracle(oracle):
+@pytest.mark.parametrize("order", [1, 2])
+def test_largest_grid_rows_and_columns_match_oracle(oracle, order):
     """32768 x 32768 = 2^30 cells, the largest grid the library takes (the
     flood kernels address a grid by 32-bit byte offsets from its base, so the
     last cell sits at 2^32 - 4): moving water over a rough bed, a step in
@@ -163,7 +167,7 @@ def test_largest_grid_rows_and_columns_match_oracle(oracle):
     FP64 oracle stepped on the three rows or columns around it from the GPU's
     state (a cell's update reads only its four neighbours); the volume is
     conserved to 1e-9 (a tile skipped or written twice would move it by
-    about 1e-6)."""
+    about 1e-6).  Both the first-order update and the second-order one."""
     import torch
     n, dx = 32768, 0.25
     c = (np.arange(n, dtype=np.float32) + np.float32(0.5)) * np.float32(dx)
@@ -179,11 +183,12 @@ def test_largest_grid_rows_and_columns_match_oracle(oracle):
     np.maximum(h, np.float32(0.0), out=h)
     qx = h * (np.float32(0.2) * np.cos(c / np.float32(9.0)))[:, None]
     qy = h * (np.float32(-0.1) * np.sin(c / np.float32(17.0)))[None, :]
-    d = I.GridDesc(nx=n, ny=n, dx=dx, dy=dx, n_base=0.02)
+    d = I.GridDesc(nx=n, ny=n, dx=dx, dy=dx, n_base=0.02, order=order)
     sim = fps.Sim(I.Scenario(desc=d, h=h, qx=qx, qy=qy, z=z, name="largest"))
     del h, qx, qy, z
     H = sim.rows_per_wave()
-    strip = 62                                   # output columns of one wave of the march
+    strip = 62 if order == 1 else 60             # output columns of one wave of the march
+    w = 1 if order == 1 else 4                   # half-width of the oracle's bands
     last_strip = (n - 1) // strip * strip
     rows = sorted({0, H - 1, H, n // 2 - 1, n // 2, n - 1})
     cols = sorted({0, strip - 1, strip, last_strip - 1, last_strip, n - 1})
@@ -192,10 +197,10 @@ def test_largest_grid_rows_and_columns_match_oracle(oracle):
     def bands(t):
         out = {}
         for r in rows:
-            r0, r1 = max(r - 1, 0), min(r + 1, n - 1)
+            r0, r1 = max(r - w, 0), min(r + w, n - 1)
             out[("row", r)] = (r0, t[r0:r1 + 1, :].double().cpu().numpy())
         for k in cols:
-            k0, k1 = max(k - 1, 0), min(k + 1, n - 1)
+            k0, k1 = max(k - w, 0), min(k + w, n - 1)
             out[("col", k)] = (k0, t[:, k0:k1 + 1].double().cpu().numpy())
         return out
 
@@ -224,7 +229,7 @@ def test_largest_grid_rows_and_columns_match_oracle(oracle):
         assert dh <= 1e-4 and dq <= 5e-4, (key, dh, dq)
     budget = d0["mass"] + d1["v_clip"] - d0["v_clip"]
     rel = abs(d1["mass"] - budget) / d0["mass"]
-    say(f"largest grid (H = {H}, dt {dt:.4g} s): rows {rows}, columns {cols}: max|dh| {worst[0]:.2e}, "
+    say(f"largest grid, order {order} (H = {H}, dt {dt:.4g} s): rows {rows}, columns {cols}: max|dh| {worst[0]:.2e}, "
         f"max|dq| {worst[1]:.2e}; volume {d1['mass']:.6e} m^3, budget error {rel:.1e}")
     assert rel <= 1e-9
 
