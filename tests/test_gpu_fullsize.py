@@ -13,6 +13,9 @@ hold at any size.
   warm-up every member closes its volume budget; for three members the bins
   and per-cell counts are bit-exact, and one more coupled step matches the
   FP64 oracle from the GPU's state (depth, discharge, positions, classes).
+* the body-rules workload, 8 x 1024^2 with 50,000 evacuees of varied bodies
+  each and both rules on, as one ensemble: one coupled step of two members
+  against the oracle (classes decided alike away from the thresholds).
 * the largest grid the library takes, 32768 x 32768 = 2^30 cells, first and
   second order: after one step the first and last rows and columns and
   those beside tile and strip seams equal the oracle on bands around them;
@@ -22,6 +25,8 @@ hold at any size.
 * the learned update on 2048^2 grids with 50,000 people: the assisted
   ensemble with every block rejected equals the plain finite-volume
   ensemble; the judge's count at full size equals the oracle judge."""
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -138,6 +143,58 @@ def test_large_sweep_headline_configuration(oracle):
             f"max|dpos| {dpos:.2e}, class mismatches {near} (all near a threshold), state mismatches {st_mism}")
         assert dh <= 1e-4 and dq <= 5e-4 and dpos <= 1e-4
         assert st_mism <= max(1, 0.005 * len(A["x"]))
+
+
+def test_body_rules_workload_one_step_matches_oracle(oracle):
+    """The workload the pedestrian step with the body rules is timed on: 8
+    shopping centres of 1024^2 cells, wet everywhere, 50,000 evacuees of
+    varied bodies each, stability and wading rules on, one ensemble.  After
+    50 steps, one coupled step of two members against the oracle from the
+    GPU's state: depth and discharge within the flood bars, positions within
+    1e-4 m where the class agrees, and a class that differs only where the
+    oracle's hazard rate is within 1e-5 of a Table 1 threshold or its force
+    balance within 1e-4 of tipping."""
+    scs = I.large_sweep(8, n=1024, n_evac=50000, seed=7)
+    for k, sc in enumerate(scs):
+        I.add_bodies(sc, seed=k)
+        sc.ped = dataclasses.replace(sc.ped, wading=1)
+    ens = fps.Ensemble(scs)
+    ens.step(50)
+    picked = (0, 7)
+    refs = {}
+    for k in picked:
+        start, d0 = snapshot(ens[k], scs[k])
+        ref = oracle.OracleSim(start)
+        ref.S.t = d0["t"]
+        refs[k] = (start, ref)
+    ens.step(1)
+    for k in picked:
+        sc = scs[k]
+        start, ref = refs[k]
+        ref.coupled_step(ens[k].diag()["dt_last"])
+        h, qx, qy, _ = ens[k].fields()
+        hr, qxr, qyr, _ = ref.fields()
+        dh = float(np.abs(h - hr).max())
+        dq = float(max(np.abs(qx - qxr).max(), np.abs(qy - qyr).max()))
+        A = ens[k].agents()
+        act = start.agents["state"] != 1
+        same = act & (A["hr_class"] == ref.cls)
+        dpos = max(np.abs(A["x"] - ref.x)[same].max(), np.abs(A["y"] - ref.y)[same].max())
+        d = sc.desc
+        mism = np.flatnonzero((A["hr_class"] != ref.cls) & act)
+        for a in mism:
+            ci = min(int(np.floor(np.float32(start.agents["x"][a]) / np.float32(d.dx))), d.nx - 1)
+            cj = min(int(np.floor(np.float32(start.agents["y"][a]) / np.float32(d.dy))), d.ny - 1)
+            c = cj * d.nx + ci
+            hc, qxc, qyc = start.h.reshape(-1)[c], start.qx.reshape(-1)[c], start.qy.reshape(-1)[c]
+            _, hrv = oracle.hr_class(ref.S.P, hc, qxc, qyc)
+            _, margin = oracle.unstable(ref.S.P, hc, qxc, qyc, start.agents["height"][a], start.agents["mass"][a])
+            assert min(abs(hrv - t) for t in sc.ped.hr_t) < 1e-5 or abs(margin) < 1e-4, (k, a, hrv, margin)
+        n_unst = int((A["hr_class"] == 5).sum())
+        say(f"body rules, member {k}: t {start.t0:.2f} s, max|dh| {dh:.2e}, max|dq| {dq:.2e}, max|dpos| {dpos:.2e}, "
+            f"{n_unst} unstable (oracle {int((ref.cls == 5).sum())}), class mismatches {len(mism)} (all near a threshold)")
+        assert dh <= 1e-4 and dq <= 5e-4 and dpos <= 1e-4
+        assert n_unst > 0                          # the stability rule is at work in this flow
 
 
 def _band_step(oracle, h, qx, qy, z, d, sides, dt):
