@@ -7,7 +7,8 @@ hold at any size.
   one coupled step matches the FP64 oracle from the GPU's state; bins and
   per-cell counts are bit-exact; the volume budget closes.
 * the 64-scenario intervention sweep: three members (one of each grid size)
-  equal their solo runs bit for bit; every member closes its volume budget.
+  equal their solo runs bit for bit; every member closes its volume budget;
+  one coupled step of a 1024^2 and a 256^2 member matches the oracle.
 * the large sweep, 32 shopping centres of 2048^2 cells with 50,000 evacuees
   each, as one ensemble with tuned tiles and graph-captured steps: after the
   warm-up every member closes its volume budget; for three members the bins
@@ -289,6 +290,57 @@ def test_largest_grid_rows_and_columns_match_oracle(oracle, order):
     say(f"largest grid, order {order} (H = {H}, dt {dt:.4g} s): rows {rows}, columns {cols}: max|dh| {worst[0]:.2e}, "
         f"max|dq| {worst[1]:.2e}; volume {d1['mass']:.6e} m^3, budget error {rel:.1e}")
     assert rel <= 1e-9
+
+
+def test_intervention_sweep_members_one_step_match_oracle(oracle):
+    """The 64-scenario sweep in the benchmark's launch configuration (tuned
+    tiles, graph-replayed steps): after 120 steps, one coupled step of the
+    first 1024^2 and the first 256^2 member against the oracle from the GPU's
+    state: depth and discharge within the flood bars, positions within 1e-4 m
+    where the class agrees, classes apart only next to a Table 1 threshold,
+    states (arrivals, pick-up and drop timers) apart for at most 0.5 % of the
+    people.  The bed is not compared: the oracle restarts the sandbag fill
+    from its first cell, the GPU continues its own."""
+    scs = I.intervention_sweep(64, workers=8)
+    ens = fps.Ensemble(scs)
+    ens.autotune()
+    ens.step(120)
+    picked = []
+    for n in (1024, 256):
+        picked.append(next(k for k, sc in enumerate(scs) if sc.desc.nx == n))
+    refs = {}
+    for k in picked:
+        start, d0 = snapshot(ens[k], scs[k])
+        ref = oracle.OracleSim(start)
+        ref.S.t = d0["t"]
+        refs[k] = (start, ref)
+    ens.step(1)
+    for k in picked:
+        sc = scs[k]
+        start, ref = refs[k]
+        ref.coupled_step(ens[k].diag()["dt_last"])
+        h, qx, qy, _ = ens[k].fields()
+        hr, qxr, qyr, _ = ref.fields()
+        dh = float(np.abs(h - hr).max())
+        dq = float(max(np.abs(qx - qxr).max(), np.abs(qy - qyr).max()))
+        A = ens[k].agents()
+        act = start.agents["state"] != 1
+        same = act & (A["hr_class"] == ref.cls)
+        dpos = max(np.abs(A["x"] - ref.x)[same].max(), np.abs(A["y"] - ref.y)[same].max())
+        d = sc.desc
+        mism = np.flatnonzero((A["hr_class"] != ref.cls) & act)
+        for a in mism:
+            ci = min(int(np.floor(np.float32(start.agents["x"][a]) / np.float32(d.dx))), d.nx - 1)
+            cj = min(int(np.floor(np.float32(start.agents["y"][a]) / np.float32(d.dy))), d.ny - 1)
+            c = cj * d.nx + ci
+            _, hrv = oracle.hr_class(ref.S.P, start.h.reshape(-1)[c], start.qx.reshape(-1)[c],
+                                     start.qy.reshape(-1)[c])
+            assert min(abs(hrv - t) for t in sc.ped.hr_t) < 1e-5, (k, a, hrv)
+        st_mism = int((A["state"] != ref.state).sum())
+        say(f"sweep member {k} ({d.nx}^2, {len(A['x'])} people): t {start.t0:.1f} s, max|dh| {dh:.2e}, "
+            f"max|dq| {dq:.2e}, max|dpos| {dpos:.2e}, class mismatches {len(mism)}, state mismatches {st_mism}")
+        assert dh <= 1e-4 and dq <= 5e-4 and dpos <= 1e-4
+        assert st_mism <= max(1, 0.005 * len(A["x"]))
 
 
 def _receptive_forward(params, x_img, i, j):
